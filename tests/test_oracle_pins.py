@@ -1,0 +1,433 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by Stokes
+theory, independent of the oracle's own code.
+
+Each pin targets a plausible mistake:
+  * worked pair values (golden file)     -> dropped term, wrong power, prefactor
+  * sphere interior / exterior closed form -> single-layer normalisation, 1/mu
+  * Gauss identity and rigid motions       -> double-layer sign and tensor shape
+  * S[n] = 0 off the surface               -> single-layer tensor structure
+  * symmetry, rotation, translation        -> transposed operands, SoA indexing
+  * exclusion == restriction, rho = 0      -> the same-group / zero-distance rule
+  * P2P with full lists == direct          -> leaf indexing
+  * central differences, dot tests, zero divergence, translation invariance of
+    the loss                               -> the vector-Jacobian products
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import ref_numpy as RN
+from paper_1909_11085_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "pair_values.txt")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _frac(s):
+    return float(Fraction(s))
+
+
+# ---------------------------------------------------------------- worked values
+def _golden_rows():
+    rows = []
+    with open(GOLDEN) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            t = line.split()
+            rows.append((t[0], [_frac(v) for v in t[1:4]], [_frac(v) for v in t[4:7]],
+                         [_frac(v) for v in t[7:10]], _frac(t[10]), [_frac(v) for v in t[11:14]]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_rows())
+def test_worked_pair_values(row):
+    kind, r, d, n, mu, expect = row
+    y = np.array([[0.5], [-1.0], [2.0]])
+    x = y + np.array(r)[:, None]
+    dens = np.array(d)[:, None]
+    w = np.ones(1)
+    if kind == "SL":
+        u = O.sl(y, dens, w, x, mu=mu)
+    else:
+        u = O.dl(y, dens, w, np.array(n)[:, None], x)
+    got = 8.0 * math.pi * u[:, 0]
+    np.testing.assert_allclose(got, expect, rtol=1e-15, atol=1e-16)
+
+
+# ---------------------------------------------------------------- sphere closed forms
+def _ball_points(rng, n, rmin, rmax, centre):
+    v = rng.standard_normal((3, n))
+    v /= np.linalg.norm(v, axis=0)
+    rad = rmin + (rmax - rmin) * rng.random(n)
+    return centre[:, None] + v * rad
+
+
+def test_sphere_interior_rigid_velocity():
+    """Uniform traction f on a sphere of radius a: u = 2 a f / (3 mu) inside."""
+    rng = np.random.default_rng(11)
+    a, mu = 1.7, 0.8
+    c = np.array([0.3, -0.2, 0.5])
+    p, w, _ = W.sphere_surface(a, order=32)
+    p = p + c[:, None]
+    fvec = np.array([0.3, -1.1, 0.6])
+    f = np.repeat(fvec[:, None], p.shape[1], axis=1)
+    x = _ball_points(rng, 40, 0.0, 0.5 * a, c)
+    u = O.sl(p, f, w, x, mu=mu)
+    expect = np.repeat((2 * a * fvec / (3 * mu))[:, None], x.shape[1], axis=1)
+    assert rel(u, expect) < 1e-13
+
+
+def test_sphere_exterior_translating_sphere_flow():
+    """Outside, the same single layer is the flow of a sphere translating with
+    U = 2 a f/(3 mu): (3a/4)(U/rho + x(x.U)/rho^3) + (a^3/4)(U/rho^3 - 3x(x.U)/rho^5)."""
+    rng = np.random.default_rng(12)
+    a, mu = 1.3, 1.9
+    c = np.array([-1.0, 2.0, 0.25])
+    p, w, _ = W.sphere_surface(a, order=32)
+    p = p + c[:, None]
+    fvec = np.array([-0.4, 0.9, 1.2])
+    f = np.repeat(fvec[:, None], p.shape[1], axis=1)
+    x = _ball_points(rng, 40, 2.0 * a, 6.0 * a, c)
+    u = O.sl(p, f, w, x, mu=mu)
+    U = 2 * a * fvec / (3 * mu)
+    d = x - c[:, None]
+    rho = np.linalg.norm(d, axis=0)
+    xU = (d * U[:, None]).sum(0)
+    expect = (0.75 * a) * (U[:, None] / rho + d * xU / rho ** 3) \
+        + (a ** 3 / 4) * (U[:, None] / rho ** 3 - 3 * d * xU / rho ** 5)
+    assert rel(u, expect) < 1e-13
+
+
+def test_double_layer_gauss_identity_sphere():
+    """Constant density: D phi = -phi inside, 0 outside (outward source normals)."""
+    rng = np.random.default_rng(13)
+    a = 2.1
+    c = np.array([0.1, 0.2, -0.3])
+    p, w, n = W.sphere_surface(a, order=32)
+    p = p + c[:, None]
+    phi0 = np.array([0.7, -0.3, 1.1])
+    phi = np.repeat(phi0[:, None], p.shape[1], axis=1)
+    xin = _ball_points(rng, 30, 0.0, 0.5 * a, c)
+    xout = _ball_points(rng, 30, 2.0 * a, 5.0 * a, c)
+    uin = O.dl(p, phi, w, n, xin)
+    uout = O.dl(p, phi, w, n, xout)
+    assert rel(uin, -np.repeat(phi0[:, None], 30, axis=1)) < 1e-12
+    assert np.abs(uout).max() < 1e-12 * np.linalg.norm(phi0)
+
+
+def test_double_layer_gauss_identity_rbc_far():
+    """Same identity on the Evans-Fung cell, far exterior targets (|x| >= 12)."""
+    rng = np.random.default_rng(14)
+    p, w, n = W.evans_fung_surface()
+    phi0 = np.array([1.0, 2.0, -0.5])
+    phi = np.repeat(phi0[:, None], p.shape[1], axis=1)
+    x = _ball_points(rng, 30, 12.0, 20.0, np.zeros(3))
+    u = O.dl(p, phi, w, n, x)
+    assert np.abs(u).max() < 1e-10 * np.linalg.norm(phi0)
+
+
+def test_double_layer_rigid_motion():
+    """phi = U + omega x y gives -(U + omega x x) inside and 0 outside."""
+    rng = np.random.default_rng(15)
+    a = 1.5
+    p, w, n = W.sphere_surface(a, order=32)
+    U = np.array([0.2, -0.7, 0.4])
+    om = np.array([1.1, 0.3, -0.6])
+    phi = U[:, None] + np.cross(om[:, None], p, axis=0)
+    xin = _ball_points(rng, 30, 0.0, 0.5 * a, np.zeros(3))
+    xout = _ball_points(rng, 30, 2.0 * a, 5.0 * a, np.zeros(3))
+    uin = O.dl(p, phi, w, n, xin)
+    expect = -(U[:, None] + np.cross(om[:, None], xin, axis=0))
+    assert rel(uin, expect) < 1e-12
+    assert np.abs(O.dl(p, phi, w, n, xout)).max() < 1e-12
+
+
+@pytest.mark.parametrize("shape", ["sphere", "rbc"])
+def test_single_layer_of_normal_vanishes(shape):
+    """The Stokeslet is divergence-free in y, so S[n] = 0 off any closed surface."""
+    rng = np.random.default_rng(16)
+    if shape == "sphere":
+        p, w, n = W.sphere_surface(1.0, order=32)
+        x = np.concatenate([_ball_points(rng, 20, 0, 0.5, np.zeros(3)),
+                            _ball_points(rng, 20, 2.0, 5.0, np.zeros(3))], axis=1)
+        tol = 1e-13
+    else:
+        p, w, n = W.evans_fung_surface()
+        x = _ball_points(rng, 20, 8.0, 15.0, np.zeros(3))
+        tol = 1e-9
+    u = O.sl(p, n, w, x)
+    scale = np.abs(O.sl(p, np.repeat(np.array([[1.0], [0], [0]]), p.shape[1], 1), w, x)).max()
+    assert np.abs(u).max() < tol * scale
+
+
+# ---------------------------------------------------------------- structure
+def _small_cells(seed=3, n_cells=3, order=8, side=12.0):
+    rng = np.random.default_rng(seed)
+    cells = W.place_cells(rng, n_cells, ("box", side), order=order)
+    f = rng.standard_normal((3, cells.n))
+    return rng, cells, f
+
+
+def test_symmetry_of_weighted_single_layer():
+    """S(x,y) = S(y,x) = S^T: <W g, S W f> = <W f, S W g> on a shared point set."""
+    rng, c, f = _small_cells()
+    g = rng.standard_normal((3, c.n))
+    kw = dict(src_group=c.group, trg_group=c.group, exclude_same_group=True)
+    Af = O.sl(c.pos, f, c.weight, c.pos, **kw)
+    Ag = O.sl(c.pos, g, c.weight, c.pos, **kw)
+    lhs = (c.weight * (g * Af).sum(0)).sum()
+    rhs = (c.weight * (f * Ag).sum(0)).sum()
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + abs(rhs))
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_rotation_and_translation(kernel):
+    rng, c, f = _small_cells(seed=5)
+    x = c.pos[:, ::3] + 0.05 * rng.standard_normal((3, c.pos[:, ::3].shape[1]))
+    Q = W.random_rotations(rng, 1)[0]
+    shift = np.array([1e3, -2e3, 5e2])[:, None]
+
+    def run(y, dens, nrm, xt):
+        if kernel == "sl":
+            return O.sl(y, dens, c.weight, xt, mu=1.3)
+        return O.dl(y, dens, c.weight, nrm, xt)
+
+    # Rounding of the inputs moves r by ~|x| eps; the kernels (up to 1/rho^2 of
+    # relative sensitivity) amplify that by ~5 |x| / rho_min.  An indexing or
+    # transposed-operand mistake gives O(1) errors instead.
+    rho_min = np.sqrt(((x.T[:, None, :] - c.pos.T[None, :, :]) ** 2).sum(-1).min())
+    eps = np.finfo(float).eps
+
+    u = run(c.pos, f, c.normal, x)
+    ur = run(Q @ c.pos, Q @ f, Q @ c.normal, Q @ x)
+    tol_rot = 50 * eps * np.abs(x).max() / rho_min
+    assert rel(ur, Q @ u) < tol_rot
+    ut = run(c.pos + shift, f, c.normal, x + shift)
+    tol_shift = 50 * eps * np.abs(x + shift).max() / rho_min
+    assert rel(ut, u) < tol_shift
+
+
+def test_linearity_and_viscosity():
+    rng, c, f = _small_cells(seed=6)
+    x = c.pos[:, ::5] + 0.1
+    u1 = O.sl(c.pos, f, c.weight, x, mu=1.0)
+    assert rel(O.sl(c.pos, -2.5 * f, c.weight, x, mu=1.0), -2.5 * u1) < 1e-15
+    assert rel(O.sl(c.pos, f, c.weight, x, mu=4.0), u1 / 4.0) < 1e-15
+
+
+def test_exclusion_equals_restriction():
+    """Same-group exclusion is the sum over the other groups' sources only."""
+    rng, c, f = _small_cells(seed=7, n_cells=4)
+    u = O.sl(c.pos, f, c.weight, c.pos, src_group=c.group, trg_group=c.group,
+             exclude_same_group=True)
+    for gid in range(4):
+        t = c.group == gid
+        s = c.group != gid
+        ug = O.sl(c.pos[:, s], f[:, s], c.weight[s], c.pos[:, t])
+        assert rel(u[:, t], ug) < 1e-14
+    ud = O.dl(c.pos, f, c.weight, c.normal, c.pos, src_group=c.group, trg_group=c.group,
+              exclude_same_group=True)
+    t, s = c.group == 1, c.group != 1
+    assert rel(ud[:, t], O.dl(c.pos[:, s], f[:, s], c.weight[s], c.normal[:, s], c.pos[:, t])) < 1e-14
+
+
+def test_zero_distance_pairs_contribute_nothing():
+    rng, c, f = _small_cells(seed=8, n_cells=2)
+    x = c.pos[:, :10].copy()
+    base = O.sl(c.pos[:, 10:], f[:, 10:], c.weight[10:], x)
+    # the full source set contains each target itself (rho = 0) and nothing else new
+    full = O.sl(c.pos, f, c.weight, x)
+    extra = O.sl(c.pos[:, :10], f[:, :10], c.weight[:10], x)   # rho = 0 on the diagonal only
+    assert rel(full, base + extra) < 1e-13
+    assert np.all(np.isfinite(full))
+    d = O.dl(c.pos[:, :1], f[:, :1], c.weight[:1], c.normal[:, :1], c.pos[:, :1])
+    assert np.all(d == 0.0)
+
+
+def test_numpy_cross_check_tiny():
+    """Layout cross-check against the dense NumPy transcription (not a pin alone)."""
+    rng = np.random.default_rng(9)
+    ns, nt = 150, 90
+    y = rng.standard_normal((3, ns)) * 3
+    x = np.concatenate([rng.standard_normal((3, nt - 5)) * 3, y[:, :5]], axis=1)  # some rho = 0
+    f = rng.standard_normal((3, ns))
+    w = rng.random(ns) + 0.5
+    nv = rng.standard_normal((3, ns))
+    nv /= np.linalg.norm(nv, axis=0)
+    gs = rng.integers(0, 4, ns).astype(np.int32)
+    gt = rng.integers(0, 4, nt).astype(np.int32)
+    for ex in (False, True):
+        kw = dict(src_group=gs, trg_group=gt, exclude_same_group=ex)
+        assert rel(O.sl(y, f, w, x, mu=0.7, **kw), RN.sl(y, f, w, x, mu=0.7, **kw)) < 1e-13
+        assert rel(O.dl(y, f, w, nv, x, **kw), RN.dl(y, f, w, nv, x, **kw)) < 1e-13
+
+
+# ---------------------------------------------------------------- P2P
+def _small_tree(seed=21):
+    rng, c, f = _small_cells(seed=seed, n_cells=6, order=8, side=14.0)
+    lo = c.pos.min(1) - 1e-3
+    side = float((c.pos.max(1) - lo).max()) + 1e-3
+    tree = W.build_octree(c.pos, lo, side, max_leaf=32)
+    p = tree.perm
+    pos, f, w, g, nrm = c.pos[:, p], f[:, p], c.weight[p], c.group[p], c.normal[:, p]
+    return rng, tree, pos, f, w, g, nrm
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_p2p_full_lists_equal_direct(kernel):
+    rng, tree, pos, f, w, g, nrm = _small_tree()
+    nl = len(tree.leaf_ofs) - 1
+    assert nl > 8
+    uofs = np.arange(nl + 1, dtype=np.int64) * nl
+    ul = np.tile(np.arange(nl, dtype=np.int32), nl)
+    kw = dict(src_group=g, trg_group=g, exclude_same_group=True)
+    up = O.p2p(kernel, pos, f, w, pos, tree.leaf_ofs, tree.leaf_ofs, uofs, ul, nrm=nrm, mu=1.7, **kw)
+    if kernel == 0:
+        ud = O.sl(pos, f, w, pos, mu=1.7, **kw)
+    else:
+        ud = O.dl(pos, f, w, nrm, pos, **kw)
+    assert rel(up, ud) < 1e-14
+
+
+def test_p2p_lists_restrict_sources():
+    rng, tree, pos, f, w, g, nrm = _small_tree(seed=22)
+    ofs, ul = W.nearest_leaf_lists(rng, tree, kmin=2, kmax=5)
+    kw = dict(src_group=g, trg_group=g, exclude_same_group=True)
+    up = O.p2p(0, pos, f, w, pos, tree.leaf_ofs, tree.leaf_ofs, ofs, ul, **kw)
+    for L in range(0, len(tree.leaf_ofs) - 1, 3):
+        t = slice(tree.leaf_ofs[L], tree.leaf_ofs[L + 1])
+        src = np.concatenate([np.arange(tree.leaf_ofs[k], tree.leaf_ofs[k + 1]) for k in ul[ofs[L]:ofs[L + 1]]])
+        ud = O.sl(pos[:, src], f[:, src], w[src], pos[:, t], src_group=g[src], trg_group=g[t],
+                  exclude_same_group=True)
+        assert rel(up[:, t], ud) < 1e-13
+
+
+# ---------------------------------------------------------------- adjoints
+def _loss_delta(u_plus, u_minus, u_ref):
+    # L = 0.5 |u - u_ref|^2;  L+ - L- = sum (u+ - u-) . (0.5 (u+ + u-) - u_ref), termwise
+    return float(((u_plus - u_minus) * (0.5 * (u_plus + u_minus) - u_ref)).sum())
+
+
+def _vjp_case(seed=31):
+    rng, c, f = _small_cells(seed=seed, n_cells=3, order=6, side=10.0)
+    u_ref = rng.standard_normal((3, c.n))
+    return rng, c, f, u_ref
+
+
+def test_sl_vjp_central_differences():
+    rng, c, f, u_ref = _vjp_case()
+    mu = 1.2
+    kw = dict(src_group=c.group, trg_group=c.group, exclude_same_group=True)
+    x = c.pos[:, ::2].copy()                                     # distinct target set
+    xg = c.group[::2]
+    kwt = dict(src_group=c.group, trg_group=xg, exclude_same_group=True)
+    uref = u_ref[:, ::2]
+
+    def fwd(y, ff, xt):
+        return O.sl(y, ff, c.weight, xt, mu=mu, **kwt)
+
+    u = fwd(c.pos, f, x)
+    gf, gy, gx = O.sl_vjp(c.pos, f, c.weight, x, u - uref, mu=mu, **kwt)
+    h = 1e-6
+    for (arr, grad, name) in ((f, gf, "f"), (c.pos, gy, "src"), (x, gx, "trg")):
+        for _ in range(6):
+            i, j = rng.integers(0, 3), rng.integers(0, arr.shape[1])
+            ap, am = arr.copy(), arr.copy()
+            ap[i, j] += h
+            am[i, j] -= h
+            if name == "f":
+                up, um = fwd(c.pos, ap, x), fwd(c.pos, am, x)
+            elif name == "src":
+                up, um = fwd(ap, f, x), fwd(am, f, x)
+            else:
+                up, um = fwd(c.pos, f, ap), fwd(c.pos, f, am)
+            fd = _loss_delta(up, um, uref) / (2 * h)
+            assert abs(fd - grad[i, j]) <= 1e-6 * (abs(grad[i, j]) + 1e-3 * np.abs(grad).max()), name
+    assert kw  # shared-point variant exercised in test_vjp_translation_invariance
+
+
+def test_dl_vjp_central_differences():
+    rng, c, f, u_ref = _vjp_case(seed=32)
+    x = c.pos[:, ::2] + 0.3                                      # off-surface targets
+    uref = u_ref[:, ::2]
+
+    def fwd(y, ff, xt):
+        return O.dl(y, ff, c.weight, c.normal, xt)
+
+    u = fwd(c.pos, f, x)
+    gp, gy, gx = O.dl_vjp(c.pos, f, c.weight, c.normal, x, u - uref)
+    h = 1e-6
+    for (arr, grad, name) in ((f, gp, "phi"), (c.pos, gy, "src"), (x, gx, "trg")):
+        for _ in range(6):
+            i, j = rng.integers(0, 3), rng.integers(0, arr.shape[1])
+            ap, am = arr.copy(), arr.copy()
+            ap[i, j] += h
+            am[i, j] -= h
+            if name == "phi":
+                up, um = fwd(c.pos, ap, x), fwd(c.pos, am, x)
+            elif name == "src":
+                up, um = fwd(ap, f, x), fwd(am, f, x)
+            else:
+                up, um = fwd(c.pos, f, ap), fwd(c.pos, f, am)
+            fd = _loss_delta(up, um, uref) / (2 * h)
+            assert abs(fd - grad[i, j]) <= 1e-6 * (abs(grad[i, j]) + 1e-3 * np.abs(grad).max()), name
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_vjp_dot_test(kernel):
+    """The sums are linear in the density: <g, A f> = <A^T g, f> exactly."""
+    rng, c, f, _ = _vjp_case(seed=33)
+    x = c.pos[:, ::3] + 0.2
+    g = rng.standard_normal((3, x.shape[1]))
+    if kernel == "sl":
+        u = O.sl(c.pos, f, c.weight, x, mu=0.9)
+        gf = O.sl_vjp(c.pos, f, c.weight, x, g, mu=0.9, want=("f",))[0]
+    else:
+        u = O.dl(c.pos, f, c.weight, c.normal, x)
+        gf = O.dl_vjp(c.pos, f, c.weight, c.normal, x, g, want=("phi",))[0]
+    lhs, rhs = (g * u).sum(), (gf * f).sum()
+    assert abs(lhs - rhs) <= 1e-13 * np.abs(g * u).sum()
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_velocity_is_divergence_free(kernel):
+    """div u = 0 off the surface, from the target gradient with unit cotangents."""
+    rng, c, f, _ = _vjp_case(seed=34)
+    x = _ball_points(rng, 12, 14.0, 18.0, c.pos.mean(1))
+    div = np.zeros(x.shape[1])
+    scale = 0.0
+    for i in range(3):
+        g = np.zeros((3, x.shape[1]))
+        g[i] = 1.0
+        if kernel == "sl":
+            gx = O.sl_vjp(c.pos, f, c.weight, x, g, want=("trg",))[2]
+        else:
+            gx = O.dl_vjp(c.pos, f, c.weight, c.normal, x, g, want=("trg",))[2]
+        div += gx[i]
+        scale = max(scale, np.abs(gx).max())
+    assert np.abs(div).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_vjp_translation_invariance(kernel):
+    """Moving sources and targets together leaves u unchanged, so the source and
+    target position gradients sum to zero (shared point set, same-group rule)."""
+    rng, c, f, u_ref = _vjp_case(seed=35)
+    kw = dict(src_group=c.group, trg_group=c.group, exclude_same_group=True)
+    if kernel == "sl":
+        u = O.sl(c.pos, f, c.weight, c.pos, **kw)
+        _, gy, gx = O.sl_vjp(c.pos, f, c.weight, c.pos, u - u_ref, **kw)
+    else:
+        u = O.dl(c.pos, f, c.weight, c.normal, c.pos, **kw)
+        _, gy, gx = O.dl_vjp(c.pos, f, c.weight, c.normal, c.pos, u - u_ref, **kw)
+    tot = gy.sum(1) + gx.sum(1)
+    assert np.abs(tot).max() < 1e-12 * np.abs(gx).sum()
