@@ -1,0 +1,21 @@
+"""MI355X-native (gfx950) Stokes kernel sums for boundary-integral red-blood-cell flow.
+
+Single-layer (Stokeslet) and double-layer (stresslet) sums from surface
+quadrature points to targets, in direct and leaf-to-leaf (FMM near-field)
+form, in float64 or mixed float32/float64, with hand-written adjoints, as
+hand-written HIP kernels behind the C ABI of ``include/stokes_mi355x.h``.
+
+``workloads`` (seeded synthetic inputs) imports without torch; the compute
+API (``sl``, ``dl``, ...) loads the HIP library on first use.
+"""
+_API = ("sl", "dl", "p2p_leaf", "P2PPlan", "context", "set_source_splits", "StokesSL", "StokesDL",
+        "StokesP2P")
+
+__all__ = list(_API) + ["workloads"]
+
+
+def __getattr__(name):
+    if name in _API:
+        from . import api
+        return getattr(api, name)
+    raise AttributeError(name)

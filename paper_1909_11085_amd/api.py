@@ -1,0 +1,147 @@
+"""PyTorch-facing API of the MI355X Stokes kernel-sum library.
+
+Thin marshalling over the C ABI: tensors supply device pointers, torch's
+current stream supplies the HIP stream and torch's caching allocator supplies
+the workspace.  All arithmetic runs in the HIP kernels; there is no CPU or
+PyTorch fallback.
+
+Layout: 3-vector fields are float64 tensors of shape (3, N), contiguous, on
+the GPU; weights (N,) float64; group ids (N,) int32.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import _capi as C
+
+_ctx_lock = threading.Lock()
+_ctxs = {}
+
+PRECISIONS = {"fp64": C.FP64, "mixed": C.MIXED}
+
+
+def context(device=None):
+    """The library context of a CUDA/HIP device (created once per device)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    with _ctx_lock:
+        if idx not in _ctxs:
+            h = ctypes.c_void_p()
+            C.check(C.lib().stokes_create(ctypes.byref(h), idx))
+            _ctxs[idx] = h
+        return _ctxs[idx]
+
+
+def set_source_splits(splits, device=None):
+    """Force the number of source splits of direct sums (0 = automatic)."""
+    C.check(C.lib().stokes_set_source_splits(context(device), int(splits)))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _vec3(t, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dim() != 2 or t.shape[0] != 3:
+        raise ValueError(f"{name} must have shape (3, N), got {tuple(t.shape)}")
+    if t.dtype != torch.float64 or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor on {device}")
+    return t
+
+
+def _vec1(t, n, name, device, dtype=torch.float64):
+    if t.shape != (n,) or t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape ({n},) on {device}")
+    return t
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class _Rule:
+    """Keeps the tensors of a stokes_exclusion alive for the duration of a call."""
+
+    def __init__(self, device, n_src, n_trg, src_group, trg_group, exclude_same_group, precision,
+                 group_h, near_frac):
+        if exclude_same_group is None:
+            exclude_same_group = src_group is not None and trg_group is not None
+        self.tensors = []
+        sg = tg = gh = None
+        if src_group is not None:
+            sg = _vec1(src_group, n_src, "src_group", device, torch.int32)
+        if trg_group is not None:
+            tg = _vec1(trg_group, n_trg, "trg_group", device, torch.int32)
+        if exclude_same_group and (sg is None or tg is None):
+            raise ValueError("exclude_same_group needs src_group and trg_group")
+        if group_h is not None:
+            gh = group_h
+            if gh.dim() != 1 or gh.dtype != torch.float64 or gh.device != device or not gh.is_contiguous():
+                raise ValueError("group_h must be a contiguous 1-D float64 tensor on the device")
+        self.tensors = [sg, tg, gh]
+        self.ex = C.Exclusion(C.EXCL_SAME_GROUP if exclude_same_group else C.EXCL_NONE,
+                              _ptr(sg).value, _ptr(tg).value, _ptr(gh).value,
+                              0 if gh is None else gh.numel(), float(near_frac))
+        self.opts = C.Opts(PRECISIONS[precision], 0)
+
+
+def _workspace(op, n_src, n_trg, n_leaves, opts, device):
+    size = ctypes.c_size_t()
+    C.check(C.lib().stokes_workspace_size(context(device), op, n_src, n_trg, n_leaves,
+                                          ctypes.byref(opts), ctypes.byref(size)))
+    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    return ws, int(size.value)
+
+
+def _out(out, n_trg, device, accumulate):
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate=True needs an out tensor")
+        return torch.empty((3, n_trg), dtype=torch.float64, device=device)
+    return _vec3(out, "out", device)
+
+
+def sl(src, f, w, trg, mu=1.0, src_group=None, trg_group=None, exclude_same_group=None,
+       precision="fp64", group_h=None, near_frac=0.5, out=None, accumulate=False):
+    """Single-layer (Stokeslet) sum at the targets; see stokes_sl_eval.
+
+    Returns ``out`` (allocated if None), shape (3, n_trg)."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    if f.shape[1] != ns:
+        raise ValueError("f must have the same number of points as src")
+    rule = _Rule(device, ns, nt, src_group, trg_group, exclude_same_group, precision, group_h, near_frac)
+    rule.opts.accumulate = int(bool(accumulate))
+    out = _out(out, nt, device, accumulate)
+    ws, size = _workspace(C.OP_SL, ns, nt, 0, rule.opts, device)
+    C.check(C.lib().stokes_sl_eval(context(device), ns, _ptr(src), _ptr(f), _ptr(w), nt, _ptr(trg),
+                                   float(mu), ctypes.byref(rule.ex), ctypes.byref(rule.opts),
+                                   _ptr(out), _ptr(ws), size, _stream(device)))
+    return out
+
+
+def dl(src, phi, w, nrm, trg, src_group=None, trg_group=None, exclude_same_group=None,
+       precision="fp64", group_h=None, near_frac=0.5, out=None, accumulate=False):
+    """Double-layer (stresslet) sum at the targets; see stokes_dl_eval."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(phi, "phi", device); _vec3(nrm, "nrm", device)
+    _vec3(trg, "trg", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    if phi.shape[1] != ns or nrm.shape[1] != ns:
+        raise ValueError("phi and nrm must have the same number of points as src")
+    rule = _Rule(device, ns, nt, src_group, trg_group, exclude_same_group, precision, group_h, near_frac)
+    rule.opts.accumulate = int(bool(accumulate))
+    out = _out(out, nt, device, accumulate)
+    ws, size = _workspace(C.OP_DL, ns, nt, 0, rule.opts, device)
+    C.check(C.lib().stokes_dl_eval(context(device), ns, _ptr(src), _ptr(phi), _ptr(w), _ptr(nrm),
+                                   nt, _ptr(trg), ctypes.byref(rule.ex), ctypes.byref(rule.opts),
+                                   _ptr(out), _ptr(ws), size, _stream(device)))
+    return out

@@ -1,0 +1,311 @@
+// Host side of the C ABI declared in include/stokes_mi355x.h: argument
+// validation, launch planning, workspace accounting and error reporting.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/stokes_mi355x.h"
+#include "common.hpp"
+#include "p2p.hpp"
+#include "vjp.hpp"
+
+struct stokes_ctx {
+    int device;
+    int n_cu;
+    int clock_khz;
+    int forced_splits;
+    char arch[64];
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+const double kPi = 3.14159265358979323846;
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Non-null (when count > 0) and naturally aligned.
+bool arr_ok(const void* p, int64_t count, size_t align) {
+    if (count <= 0) return true;
+    return p != nullptr && aligned(p, align);
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    if (!a || !b || abytes == 0 || bbytes == 0) return false;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct Parsed {
+    int precision = STOKES_FP64;
+    int accumulate = 0;
+    int excl = STOKES_EXCL_NONE;
+    const int32_t* src_group = nullptr;
+    const int32_t* trg_group = nullptr;
+    const double* group_h = nullptr;
+    int32_t n_groups = 0;
+    double near_frac = 0.0;
+};
+
+int parse_common(const stokes_exclusion* ex, const stokes_opts* op, int64_t n_src, int64_t n_trg,
+                 Parsed& p) {
+    if (op) {
+        if (op->precision != STOKES_FP64 && op->precision != STOKES_MIXED)
+            return fail(STOKES_EINVAL, "opts.precision must be STOKES_FP64 or STOKES_MIXED");
+        if (op->accumulate != 0 && op->accumulate != 1)
+            return fail(STOKES_EINVAL, "opts.accumulate must be 0 or 1");
+        p.precision = op->precision;
+        p.accumulate = op->accumulate;
+    }
+    if (ex) {
+        if (ex->mode != STOKES_EXCL_NONE && ex->mode != STOKES_EXCL_SAME_GROUP)
+            return fail(STOKES_EINVAL, "exclusion.mode must be STOKES_EXCL_NONE or STOKES_EXCL_SAME_GROUP");
+        p.excl = ex->mode;
+        p.src_group = ex->src_group;
+        p.trg_group = ex->trg_group;
+        p.group_h = ex->group_h;
+        p.n_groups = ex->n_groups;
+        p.near_frac = ex->near_frac;
+        if (p.excl == STOKES_EXCL_SAME_GROUP) {
+            if (!arr_ok(p.src_group, n_src, 4) || (n_src > 0 && !p.src_group))
+                return fail(STOKES_EINVAL, "same-group rule needs a 4-byte aligned src_group array");
+            if (!arr_ok(p.trg_group, n_trg, 4) || (n_trg > 0 && !p.trg_group))
+                return fail(STOKES_EINVAL, "same-group rule needs a 4-byte aligned trg_group array");
+        }
+        if (p.precision == STOKES_MIXED && p.group_h) {
+            if (p.n_groups <= 0) return fail(STOKES_EINVAL, "group_h given with n_groups <= 0");
+            if (!aligned(p.group_h, 8)) return fail(STOKES_EINVAL, "group_h must be 8-byte aligned");
+            if (!(isfinite(p.near_frac) && p.near_frac >= 0.0))
+                return fail(STOKES_EINVAL, "near_frac must be finite and >= 0");
+            if (n_src > 0 && (!p.src_group || !aligned(p.src_group, 4)))
+                return fail(STOKES_EINVAL, "the near rule needs a 4-byte aligned src_group array");
+        }
+        if (p.precision != STOKES_MIXED || !p.group_h) {
+            p.group_h = nullptr;
+            p.n_groups = 0;
+        }
+    }
+    return STOKES_OK;
+}
+
+int check_sizes(int64_t n_src, int64_t n_trg) {
+    if (n_src < 0 || n_trg < 0) return fail(STOKES_EINVAL, "point counts must be >= 0");
+    if (n_src > STOKES_MAX_POINTS || n_trg > STOKES_MAX_POINTS)
+        return fail(STOKES_EUNSUPPORTED, "point count above STOKES_MAX_POINTS");
+    return STOKES_OK;
+}
+
+int check_workspace(void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return STOKES_OK;
+    if (!ws) return fail(STOKES_EWORKSPACE, "workspace is NULL but " + std::to_string(need) + " bytes are needed");
+    if (!aligned(ws, 256)) return fail(STOKES_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(STOKES_EWORKSPACE, "workspace too small: " + std::to_string(ws_bytes) + " < " +
+                                           std::to_string(need));
+    return STOKES_OK;
+}
+
+int launch_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return STOKES_OK;
+    return fail(STOKES_ELAUNCH, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+stokes::SumInputs make_inputs(int kernel, const Parsed& p, int64_t n_src, const double* src_xyz,
+                              const double* density, const double* weight, const double* normal,
+                              int64_t n_trg, const double* trg_xyz, double pref) {
+    stokes::SumInputs in{};
+    in.kernel = kernel;
+    in.mixed = p.precision == STOKES_MIXED;
+    in.n_src = n_src;
+    in.n_trg = n_trg;
+    in.src_xyz = src_xyz;
+    in.density = density;
+    in.weight = weight;
+    in.normal = normal;
+    in.trg_xyz = trg_xyz;
+    in.excl = p.excl;
+    in.src_group = p.src_group;
+    in.trg_group = p.trg_group;
+    in.group_h = p.group_h;
+    in.n_groups = p.n_groups;
+    in.near_frac = p.near_frac;
+    in.pref = pref;
+    return in;
+}
+
+// Shared argument checks of the direct sums and their adjoints.
+int check_points(int kernel, int64_t n_src, const double* src_xyz, const double* density,
+                 const double* weight, const double* normal, int64_t n_trg, const double* trg_xyz) {
+    if (!arr_ok(src_xyz, 3 * n_src, 8)) return fail(STOKES_EINVAL, "src_xyz must be non-NULL and 8-byte aligned");
+    if (!arr_ok(density, 3 * n_src, 8)) return fail(STOKES_EINVAL, "density must be non-NULL and 8-byte aligned");
+    if (!arr_ok(weight, n_src, 8)) return fail(STOKES_EINVAL, "weight must be non-NULL and 8-byte aligned");
+    if (kernel == STOKES_KERNEL_DL && !arr_ok(normal, 3 * n_src, 8))
+        return fail(STOKES_EINVAL, "normal must be non-NULL and 8-byte aligned");
+    if (!arr_ok(trg_xyz, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "trg_xyz must be non-NULL and 8-byte aligned");
+    return STOKES_OK;
+}
+
+// An output must not overlap any input array.
+int check_no_alias(const void* out, size_t out_bytes, const char* name,
+                   std::initializer_list<std::pair<const void*, size_t>> inputs) {
+    for (const auto& in : inputs)
+        if (overlaps(out, out_bytes, in.first, in.second))
+            return fail(STOKES_EINVAL, std::string(name) + " overlaps an input array");
+    return STOKES_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* stokes_last_error(void) { return g_err.c_str(); }
+
+int stokes_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+int stokes_create(stokes_ctx** ctx, int device) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0)
+        return fail(STOKES_EDEVICE, std::string("no HIP device available: ") + hipGetErrorString(e));
+    if (device < 0 || device >= count)
+        return fail(STOKES_EDEVICE, "device ordinal " + std::to_string(device) + " out of range");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return fail(STOKES_EDEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(STOKES_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+    stokes_ctx* c = new (std::nothrow) stokes_ctx{};
+    if (!c) return fail(STOKES_EDEVICE, "out of host memory");
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount;
+    c->clock_khz = prop.clockRate;
+    c->forced_splits = 0;
+    strncpy(c->arch, prop.gcnArchName, sizeof(c->arch) - 1);
+    *ctx = c;
+    return STOKES_OK;
+}
+
+void stokes_destroy(stokes_ctx* ctx) { delete ctx; }
+
+int stokes_set_source_splits(stokes_ctx* ctx, int32_t splits) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (splits < 0 || splits > 65535) return fail(STOKES_EINVAL, "splits must be in [0, 65535]");
+    ctx->forced_splits = splits;
+    return STOKES_OK;
+}
+
+int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int64_t n_trg,
+                          int32_t n_leaves, const stokes_opts* opts, size_t* bytes) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!bytes) return fail(STOKES_EINVAL, "bytes is NULL");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    Parsed p;
+    rc = parse_common(nullptr, opts, n_src, n_trg, p);
+    if (rc) return rc;
+    const int mixed = p.precision == STOKES_MIXED;
+    switch (op) {
+        case STOKES_OP_SL:
+        case STOKES_OP_DL: {
+            if (n_src == 0 || n_trg == 0) { *bytes = 0; return STOKES_OK; }
+            *bytes = stokes::plan_direct(op == STOKES_OP_SL ? 0 : 1, mixed, n_src, n_trg, ctx->n_cu,
+                                         ctx->forced_splits).total;
+            return STOKES_OK;
+        }
+        case STOKES_OP_P2P_SL:
+        case STOKES_OP_P2P_DL:
+            if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
+            *bytes = stokes::p2p_workspace_bytes(op == STOKES_OP_P2P_SL ? 0 : 1, mixed, n_src, n_trg, n_leaves);
+            return STOKES_OK;
+        case STOKES_OP_SL_VJP:
+        case STOKES_OP_DL_VJP:
+            *bytes = stokes::vjp_workspace_bytes(op == STOKES_OP_SL_VJP ? 0 : 1, mixed, n_src, n_trg,
+                                                 ctx->n_cu);
+            return STOKES_OK;
+        default:
+            return fail(STOKES_EINVAL, "unknown op");
+    }
+}
+
+static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* src_xyz,
+                       const double* density, const double* weight, const double* normal,
+                       int64_t n_trg, const double* trg_xyz, double pref,
+                       const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out,
+                       void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz);
+    if (rc) return rc;
+    if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
+    Parsed p;
+    rc = parse_common(excl, opts, n_src, n_trg, p);
+    if (rc) return rc;
+    const size_t vb = (size_t)3 * n_trg * sizeof(double), sb = (size_t)3 * n_src * sizeof(double);
+    rc = check_no_alias(vel_out, vb, "vel_out",
+                        {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {normal, kernel ? sb : 0},
+                         {trg_xyz, vb}, {workspace, ws_bytes}});
+    if (rc) return rc;
+    const int mixed = p.precision == STOKES_MIXED;
+    stokes::DirectPlan plan{};
+    size_t need = 0;
+    if (n_src > 0 && n_trg > 0) {
+        plan = stokes::plan_direct(kernel, mixed, n_src, n_trg, ctx->n_cu, ctx->forced_splits);
+        need = plan.total;
+    }
+    rc = check_workspace(workspace, ws_bytes, need);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    const stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal,
+                                             n_trg, trg_xyz, pref);
+    return launch_status(stokes::launch_direct(in, plan, vel_out, p.accumulate, workspace,
+                                               static_cast<hipStream_t>(stream)),
+                         kernel ? "stokes_dl_eval" : "stokes_sl_eval");
+}
+
+int stokes_sl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                   const double* weight, int64_t n_trg, const double* trg_xyz, double mu,
+                   const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out,
+                   void* workspace, size_t ws_bytes, void* stream) {
+    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    return direct_eval(ctx, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg,
+                       trg_xyz, 1.0 / (8.0 * kPi * mu), excl, opts, vel_out, workspace, ws_bytes,
+                       stream);
+}
+
+int stokes_dl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                   const double* weight, const double* normal, int64_t n_trg,
+                   const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,
+                   double* vel_out, void* workspace, size_t ws_bytes, void* stream) {
+    return direct_eval(ctx, STOKES_KERNEL_DL, n_src, src_xyz, density, weight, normal, n_trg,
+                       trg_xyz, 6.0 / (8.0 * kPi), excl, opts, vel_out, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"
