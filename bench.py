@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark: Stokes pair-interactions/s on one MI355X.
+
+Workload: 512 Evans-Fung red blood cells (544 quadrature points each, 278,528
+points) placed by random sequential addition in a 120^3 box; single-layer
+(Stokeslet) sum from every point to every point of the other cells (same-cell
+pairs excluded), densities N(0,1) per component, unit viscosity.  One step =
+one full evaluation of that sum (prep, summation and split-reduction kernels).
+
+Reported on one JSON line (stdout):
+  value         pair-interactions/s of the headline precision (FP64 by default)
+  mixed / fp64  the other precision on the same workload, with its own rate,
+                relative L2 error and roofline
+  adjoint       single-layer VJP (dL/df and both position gradients, one fused
+                pass) time and its ratio to the forward
+  roofline      dominant kernel: algorithmic flops (29 per single-layer pair)
+                over its measured average duration (HIP events recorded by the
+                library on the stream it launches on), against the vector peak
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of targets (all
+                sources), on this host's cores
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Stokes pair-interactions/s (FP64 vs mixed FP32) at stated rel-L2 error; adjoint/forward"
+# MI355X published vector peaks (256 CUs x 2.4 GHz): FP64 128 flop/clk/CU, FP32 256 (packed).
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
+FLOPS_PER_PAIR_SL = 29
+FLOPS_PER_PAIR_SL_VJP = 95
+KERNEL_NAMES = {"fp64": "direct_f64<SL,T=4>", "mixed": "direct_mixed<SL,T=4>"}
+PROFILE_TRAFFIC = {"fp64": "direct_f64_sl_cfg2_traffic.txt", "mixed": "direct_mixed_sl_cfg2_traffic.txt"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("direct.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1909_11085_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(precision):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, or None when
+    absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", PROFILE_TRAFFIC[precision])
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="headline precision (the other one is reported alongside)")
+    ap.add_argument("--only", choices=["fp64", "mixed", "vjp"], default=None,
+                    help="time one path only (for profiler runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the CPU oracle sample")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
+              "this build has no multi-GPU path; see DESIGN.md for how it would shard.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1909_11085_amd as S
+    from paper_1909_11085_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    cfg = W.make_config(2)
+    cells, f = cfg["cells"], cfg["f"]
+    n = cells.n
+    pairs = W.pair_count_direct(cells.group, cells.group, True)
+    log(f"workload: {cells.meta['n_cells']} cells, {n} points, {pairs} pairs/step "
+        f"(generated in {time.time() - t0:.1f}s)")
+
+    def t(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    pos, ft, wt, grp, gh = t(cells.pos), t(f), t(cells.weight), t(cells.group), t(cells.group_h)
+    out = torch.empty((3, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def fwd(precision):
+        S.sl(pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=precision, group_h=gh,
+             near_frac=0.5, out=out)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        S.timing_read()                      # discard warm-up events
+        S.timing_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        S.timing_enable(False)
+        kms, launches = S.timing_read()
+        return e0.elapsed_time(e1) / steps, kms / max(launches, 1), launches
+
+    results = {}
+    outputs = {}
+    precisions = [args.precision, "mixed" if args.precision == "fp64" else "fp64"]
+    if args.only in ("fp64", "mixed"):
+        precisions = [args.only]
+    if args.only != "vjp":
+        for prec in precisions:
+            ms, kms, launches = timed(lambda: fwd(prec), args.steps, args.warmup)
+            outputs[prec] = out.cpu().numpy()
+            rate = pairs / (ms * 1e-3)
+            achieved = pairs * FLOPS_PER_PAIR_SL / (kms * 1e-3) / 1e12
+            results[prec] = dict(ms_per_step=ms, value=rate, kernel_ms=kms, launches=launches,
+                                 achieved=achieved)
+            log(f"{prec}: {ms:.3f} ms/step, {rate:.4e} pairs/s, main kernel {kms:.3f} ms "
+                f"({achieved:.2f} TFLOP/s at {FLOPS_PER_PAIR_SL} flop/pair)")
+
+    # adjoint of L = 0.5 |u - u_ref|^2 at a fixed cotangent g (FP64, fused shared-point pass)
+    adjoint = None
+    if args.only in (None, "vjp") and hasattr(S, "sl_vjp_raw"):
+        g = t(np.random.default_rng(7).standard_normal((3, n)))
+        gf = torch.empty_like(ft)
+        gs = torch.empty_like(pos)
+        gx = torch.empty_like(pos)
+
+        def bwd():
+            S.sl_vjp_raw(pos, ft, wt, pos, g, src_group=grp, trg_group=grp, precision="fp64",
+                         grad_f=gf, grad_src=gs, grad_trg=gx)
+
+        ms, kms, launches = timed(bwd, max(1, args.steps // 2), 1)
+        fwd_ms = results.get("fp64", {}).get("ms_per_step")
+        adjoint = dict(ms_per_step=ms, kernel_ms=kms, outputs=["dL/df", "dL/dsrc", "dL/dtrg"],
+                       precision="fp64",
+                       ratio_to_forward=(ms / fwd_ms) if fwd_ms else None)
+        log(f"adjoint: {ms:.3f} ms/step" + (f", {ms / fwd_ms:.2f}x forward" if fwd_ms else ""))
+
+    # CPU oracle on a bounded sample of targets; its outputs also give the error
+    cpu = None
+    rel = {}
+    if not args.no_cpu_baseline and args.only is None:
+        from oracle import oracle as O
+
+        rng = np.random.default_rng(2025)
+        pilot = W.subset(rng, n, 256)
+        tp = time.time()
+        O.sl(cells.pos, f, cells.weight, cells.pos[:, pilot], src_group=cells.group,
+             trg_group=cells.group[pilot], exclude_same_group=True)
+        rate_pilot = 256 * n / (time.time() - tp)
+        m = int(min(n, max(512, args.cpu_seconds * rate_pilot / n)))
+        idx = W.subset(rng, n, m)
+        tc = time.time()
+        ref = O.sl(cells.pos, f, cells.weight, cells.pos[:, idx], src_group=cells.group,
+                   trg_group=cells.group[idx], exclude_same_group=True)
+        dt = time.time() - tc
+        cpu_pairs = int(W.pair_count_direct(cells.group, cells.group[idx], True))
+        cpu = dict(value=cpu_pairs / dt, unit="pair-interactions/s", cores=O.num_threads(),
+                   kind="oracle",
+                   sample=f"{m} seeded targets x all {n} sources ({cpu_pairs} pairs, FP64, "
+                          f"{dt:.1f} s, compensated sums)")
+        log(f"cpu oracle: {cpu['value']:.4e} pairs/s on {cpu['cores']} threads ({dt:.1f}s)")
+        for prec, u in outputs.items():
+            rel[prec] = float(np.linalg.norm(u[:, idx] - ref) / np.linalg.norm(ref))
+            log(f"{prec}: rel-L2 vs oracle on {m} targets = {rel[prec]:.3e}")
+
+    head = args.precision if args.precision in results else (args.only or args.precision)
+    hr = results.get(head)
+
+    def roofline(prec):
+        r = results[prec]
+        return {"bound": "alu", "achieved": round(r["achieved"], 3), "peak": PEAK_TFLOPS[prec],
+                "unit": "TFLOP/s", "frac": round(r["achieved"] / PEAK_TFLOPS[prec], 4),
+                "traffic": traffic_from_profile(prec), "kernel": KERNEL_NAMES[prec],
+                "flops_per_pair": FLOPS_PER_PAIR_SL, "pairs_per_launch": pairs,
+                "kernel_ms": round(r["kernel_ms"], 4)}
+
+    line = {
+        "metric": METRIC,
+        "value": hr["value"] if hr else None,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hr["ms_per_step"] if hr else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "512 Evans-Fung RBCs (p=16, 544 pts each, 278,528 points) in a 120^3 "
+                               "box; single-layer Stokeslet direct sum, all points to all points, "
+                               "same-cell pairs excluded",
+                   "precision": head, "n_points": n, "pairs_per_step": pairs, "mu": 1.0},
+        "rel_l2": rel.get(head),
+    }
+    if hr:
+        line["roofline"] = roofline(head)
+    other = [p for p in results if p != head]
+    for p in other:
+        line[p] = {"value": results[p]["value"], "ms_per_step": results[p]["ms_per_step"],
+                   "rel_l2": rel.get(p), "roofline": roofline(p),
+                   "speedup_vs_" + head: results[head]["ms_per_step"] / results[p]["ms_per_step"]
+                   if hr else None}
+    if adjoint:
+        line["adjoint"] = adjoint
+    line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,10 +127,21 @@ const char* stokes_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int stokes_version(void);
 
-/* Tuning override for tests: number of source splits of direct sums
- * (0 = automatic).  Changes launch shape and workspace size only; results
- * stay within the same error bound.  Not thread-safe against running calls. */
-int stokes_set_source_splits(stokes_ctx* ctx, int32_t splits);
+/* Launch-shape override for tests: number of workgroups of the direct sums
+ * (0 = automatic, the number resident on the device at once; at most 2^20).
+ * Changes the work partition and the workspace size only; FP64 results stay
+ * within the same error bound.  Not thread-safe against running calls. */
+int stokes_set_grid_override(stokes_ctx* ctx, int32_t workgroups);
+
+/* Kernel timing for benchmarks.  While enabled, every evaluation records a
+ * pair of HIP events around its main summation kernel(s) (not the prep or
+ * reduction kernels) on the call's stream.  stokes_timing_read waits for
+ * those events, returns the summed milliseconds and the number of timed
+ * launches since the last read (or since enabling), and starts a new count.
+ * Enabling and reading are not thread-safe against concurrent evaluations
+ * on the same context. */
+int stokes_timing_enable(stokes_ctx* ctx, int on);
+int stokes_timing_read(stokes_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Bytes of workspace that a call of kind `op` (STOKES_OP_*) with these sizes
  * and options needs.  For P2P ops n_leaves is the plan's leaf count; for

@@ -35,9 +35,21 @@ def context(device=None):
         return _ctxs[idx]
 
 
-def set_source_splits(splits, device=None):
-    """Force the number of source splits of direct sums (0 = automatic)."""
-    C.check(C.lib().stokes_set_source_splits(context(device), int(splits)))
+def set_grid_override(workgroups, device=None):
+    """Force the workgroup count of direct sums (0 = the resident count)."""
+    C.check(C.lib().stokes_set_grid_override(context(device), int(workgroups)))
+
+
+def timing_enable(on=True, device=None):
+    """Record HIP events around each evaluation's main summation kernel."""
+    C.check(C.lib().stokes_timing_enable(context(device), int(bool(on))))
+
+
+def timing_read(device=None):
+    """(summed milliseconds, launches) of the main kernels timed since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    C.check(C.lib().stokes_timing_read(context(device), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def _ptr(t):

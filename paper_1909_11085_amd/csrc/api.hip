@@ -17,9 +17,33 @@ struct stokes_ctx {
     int device;
     int n_cu;
     int clock_khz;
-    int forced_splits;
+    int forced_grid;             // 0 = resident workgroup count
+    int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
     char arch[64];
+    // benchmark timing (see stokes_timing_enable)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // recorded, not yet read
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;    // reusable
 };
+
+namespace stokes {
+// Event pair for the next timed launch on ctx (none when timing is off).
+KernelTimer next_timer(stokes_ctx* ctx) {
+    KernelTimer t;
+    if (!ctx || !ctx->timing) return t;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (!ctx->spare.empty()) {
+        ev = ctx->spare.back();
+        ctx->spare.pop_back();
+    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+        return t;
+    }
+    ctx->events.push_back(ev);
+    t.start = ev.first;
+    t.stop = ev.second;
+    return t;
+}
+}  // namespace stokes
 
 namespace {
 
@@ -205,18 +229,63 @@ int stokes_create(stokes_ctx** ctx, int device) {
     c->device = device;
     c->n_cu = prop.multiProcessorCount;
     c->clock_khz = prop.clockRate;
-    c->forced_splits = 0;
+    c->forced_grid = 0;
     strncpy(c->arch, prop.gcnArchName, sizeof(c->arch) - 1);
+    {
+        DeviceGuard dg(device);
+        if (!dg.ok) {
+            delete c;
+            return fail(STOKES_EDEVICE, "cannot select the device");
+        }
+        for (int k = 0; k < 2; ++k)
+            for (int m = 0; m < 2; ++m) c->resident[k][m] = stokes::direct_blocks_per_cu(k, m) * c->n_cu;
+    }
     *ctx = c;
     return STOKES_OK;
 }
 
-void stokes_destroy(stokes_ctx* ctx) { delete ctx; }
+void stokes_destroy(stokes_ctx* ctx) {
+    if (!ctx) return;
+    for (auto* v : {&ctx->events, &ctx->spare})
+        for (auto& ev : *v) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+    delete ctx;
+}
 
-int stokes_set_source_splits(stokes_ctx* ctx, int32_t splits) {
+int stokes_timing_enable(stokes_ctx* ctx, int on) {
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
-    if (splits < 0 || splits > 65535) return fail(STOKES_EINVAL, "splits must be in [0, 65535]");
-    ctx->forced_splits = splits;
+    ctx->timing = on != 0;
+    return STOKES_OK;
+}
+
+int stokes_timing_read(stokes_ctx* ctx, double* total_ms, int64_t* launches) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!total_ms || !launches) return fail(STOKES_EINVAL, "output pointer is NULL");
+    double sum = 0.0;
+    int64_t n = 0;
+    for (auto& ev : ctx->events) {
+        if (hipEventSynchronize(ev.second) != hipSuccess)
+            return fail(STOKES_EDEVICE, "hipEventSynchronize failed while reading timings");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) != hipSuccess)
+            return fail(STOKES_EDEVICE, "hipEventElapsedTime failed while reading timings");
+        sum += ms;
+        ++n;
+        ctx->spare.push_back(ev);
+    }
+    ctx->events.clear();
+    *total_ms = sum;
+    *launches = n;
+    return STOKES_OK;
+}
+
+int stokes_set_grid_override(stokes_ctx* ctx, int32_t workgroups) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (workgroups < 0 || workgroups > (1 << 20))
+        return fail(STOKES_EINVAL, "workgroups must be in [0, 2^20]");
+    ctx->forced_grid = workgroups;
     return STOKES_OK;
 }
 
@@ -234,8 +303,9 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
         case STOKES_OP_SL:
         case STOKES_OP_DL: {
             if (n_src == 0 || n_trg == 0) { *bytes = 0; return STOKES_OK; }
-            *bytes = stokes::plan_direct(op == STOKES_OP_SL ? 0 : 1, mixed, n_src, n_trg, ctx->n_cu,
-                                         ctx->forced_splits).total;
+            const int k = op == STOKES_OP_SL ? 0 : 1;
+            *bytes = stokes::plan_direct(k, mixed, n_src, n_trg, ctx->resident[k][mixed],
+                                         ctx->forced_grid).total;
             return STOKES_OK;
         }
         case STOKES_OP_P2P_SL:
@@ -276,7 +346,8 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
     stokes::DirectPlan plan{};
     size_t need = 0;
     if (n_src > 0 && n_trg > 0) {
-        plan = stokes::plan_direct(kernel, mixed, n_src, n_trg, ctx->n_cu, ctx->forced_splits);
+        plan = stokes::plan_direct(kernel, mixed, n_src, n_trg, ctx->resident[kernel][mixed],
+                                   ctx->forced_grid);
         need = plan.total;
     }
     rc = check_workspace(workspace, ws_bytes, need);
@@ -286,7 +357,8 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
     const stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal,
                                              n_trg, trg_xyz, pref);
     return launch_status(stokes::launch_direct(in, plan, vel_out, p.accumulate, workspace,
-                                               static_cast<hipStream_t>(stream)),
+                                               static_cast<hipStream_t>(stream),
+                                               stokes::next_timer(ctx)),
                          kernel ? "stokes_dl_eval" : "stokes_sl_eval");
 }
 

@@ -69,18 +69,30 @@ struct DirectPlan {
     int T;                       // targets per lane
     int64_t n_src_pad;           // sources padded to kTile
     int64_t n_sub;               // n_src_pad / kSub
-    int splits;                  // source splits (grid.y)
-    int64_t subs_per_split;      // multiple of 4
-    int64_t blocks_x;            // target blocks
-    size_t off_src, off_grp, off_meta, off_part, total;
+    int64_t chunks;              // n_src_pad / kTile
+    int64_t blocks_x;            // target blocks of kBlock * T targets
+    int64_t units;               // blocks_x * chunks
+    int64_t grid;                // workgroups (resident count, at most units)
+    size_t off_src, off_grp, off_meta, off_part, off_near, off_flags, total;
 };
 
-DirectPlan plan_direct(int kernel, int mixed, int64_t n_src, int64_t n_trg, int n_cu,
-                       int forced_splits);
+// Workgroups of a direct-sum kernel that fit on one compute unit at once.
+int direct_blocks_per_cu(int kernel, int mixed);
+
+// resident_blocks: workgroups resident on the whole device; forced_grid > 0
+// overrides it (tests).
+DirectPlan plan_direct(int kernel, int mixed, int64_t n_src, int64_t n_trg, int resident_blocks,
+                       int forced_grid);
+
+// Optional event pair recorded around a call's main summation kernel(s).
+struct KernelTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool on() const { return start != nullptr; }
+};
 
 // Launches prep + sum (+ reduction) on `stream`.  Returns a hipError_t.
 hipError_t launch_direct(const SumInputs& in, const DirectPlan& p, double* out, int accumulate,
-                         void* workspace, hipStream_t stream);
+                         void* workspace, hipStream_t stream, const KernelTimer& timer);
 
 // Writes zeros into n doubles (used for empty source sets).
 hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t stream);

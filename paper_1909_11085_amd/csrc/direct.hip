@@ -14,17 +14,24 @@
 //     registers) and one split of the sources.  Sources stream through LDS
 //     in steps of 256 records (register prefetch of the next step); every
 //     lane of a wave reads the same record, a broadcast LDS read.
-//   * per 64-source sub-tile the wave decides, uniformly, between a fast loop
-//     with no per-pair tests (box far from the wave's targets and no shared
-//     group) and a masked loop.  Mixed precision evaluates pairs in float32
+//   * per 64-source sub-tile the wave decides, uniformly, whether the fast
+//     loop (no per-pair tests) is exact: box far from its targets and no
+//     shared group.  Sub-tiles that need per-pair tests are flagged and left
+//     to a separate near-pass kernel, so the main loop's register allocation
+//     and schedule carry no masked code.  Mixed precision evaluates pairs in float32
 //     on offsets from the sub-tile centre (each rounded once from float64),
 //     sums each sub-tile in float32 and adds it into float64 accumulators.
-//     In a close sub-tile (possible exclusions or near pairs, or a gap below
-//     half the boxes' extents) r is formed from float32 high parts plus
-//     float32 residues, and pairs within the near radius go through a float64
-//     branch instead.
-//   * several source splits write float64 partial sums that a second kernel
-//     adds in fixed order (deterministic; no atomics).
+//     In the near pass (possible exclusions or near pairs, or a gap below half
+//     the sub-tile's extent) r is formed from float32 high parts plus float32
+//     residues, and pairs within the near radius are evaluated in float64.
+//   * work balance (stream-K): the grid holds exactly the resident number of
+//     workgroups; the (target block x source chunk) units are cut into equal
+//     contiguous ranges, one per workgroup.  A workgroup flushes float64
+//     partial sums whenever its range moves to a new target block; segment
+//     ids (workgroup + target block) are consecutive, and a second kernel
+//     adds each target's segments in fixed order (deterministic, no atomics).
+//   * the near-pass decision tests every target of the wave against the
+//     sub-tile box, after a whole-wave box test that settles most sub-tiles.
 #include <float.h>
 #include <limits.h>
 
@@ -74,9 +81,11 @@ struct DirectArgs {
     const void* rec;          // packed source records
     const void* aux;          // FP64 path: padded int32 groups; mixed: float4 low parts
     const SubMeta* meta;
-    int64_t n_sub, subs_per_split;
-    double* out;              // final output when splits == 1, else partials
-    int splits, accumulate;
+    int64_t chunks;           // source chunks of kTile records
+    int64_t units;            // target blocks x chunks
+    double* part;             // partial sums, one segment per (block, target block) pair
+    uint8_t* flags;           // per (wave, chunk): bit s = sub-tile s left to the near pass
+    double* near_part;        // near-pass sums, (3, blocks_x * kBlock * T)
 };
 
 // ---------------------------------------------------------------------------
@@ -169,85 +178,131 @@ __global__ __launch_bounds__(kBlock) void prep_sources(SumInputs in, void* rec_o
 // ---------------------------------------------------------------------------
 // target setup shared by both precisions
 // ---------------------------------------------------------------------------
-template <int T>
-struct WaveTargets {
-    double x[T], y[T], z[T];
-    int32_t g[T];
+struct Box {
     double lo[3], hi[3];
-    int gmin, gmax;
+    int32_t gmin, gmax;
+    int32_t pad[2];
 };
 
 template <int T>
-__device__ __forceinline__ void load_targets(const SumInputs& in, int64_t tb, int lane,
-                                             WaveTargets<T>& t) {
+struct Targets {
+    double x[T], y[T], z[T];
+    int32_t g[T];
+};
+
+// Loads the wave's targets (T per lane: target tb + k*64 + lane) and returns
+// the box and group range of the whole wave.  Lanes past n_trg load the last
+// target (a real point, so the box stays conservative) and store nothing.
+template <int T>
+__device__ __forceinline__ Box load_targets(const SumInputs& in, int64_t tb, int lane,
+                                            Targets<T>& t) {
     const int64_t n = in.n_trg;
+    Box w;
     double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
     int gmn = INT_MAX, gmx = INT_MIN;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t idx = tb + (int64_t)k * kWave + lane;
-        const bool v = idx < n;
-        const int64_t ic = v ? idx : n - 1;
+        const int64_t ic = idx < n ? idx : n - 1;
         t.x[k] = in.trg_xyz[ic];
         t.y[k] = in.trg_xyz[n + ic];
         t.z[k] = in.trg_xyz[2 * n + ic];
         t.g[k] = in.trg_group ? in.trg_group[ic] : 0;
-        if (v) {
-            lo[0] = fmin(lo[0], t.x[k]); hi[0] = fmax(hi[0], t.x[k]);
-            lo[1] = fmin(lo[1], t.y[k]); hi[1] = fmax(hi[1], t.y[k]);
-            lo[2] = fmin(lo[2], t.z[k]); hi[2] = fmax(hi[2], t.z[k]);
-            gmn = min(gmn, t.g[k]); gmx = max(gmx, t.g[k]);
-        }
+        lo[0] = fmin(lo[0], t.x[k]); hi[0] = fmax(hi[0], t.x[k]);
+        lo[1] = fmin(lo[1], t.y[k]); hi[1] = fmax(hi[1], t.y[k]);
+        lo[2] = fmin(lo[2], t.z[k]); hi[2] = fmax(hi[2], t.z[k]);
+        gmn = min(gmn, t.g[k]);
+        gmx = max(gmx, t.g[k]);
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { t.lo[c] = wave_min(lo[c]); t.hi[c] = wave_max(hi[c]); }
-    t.gmin = wave_mini(gmn);
-    t.gmax = wave_maxi(gmx);
+    for (int c = 0; c < 3; ++c) { w.lo[c] = wave_min(lo[c]); w.hi[c] = wave_max(hi[c]); }
+    w.gmin = wave_mini(gmn);
+    w.gmax = wave_maxi(gmx);
+    w.pad[0] = w.pad[1] = 0;
+    return w;
 }
 
-// Squared distance between the wave's target box and a sub-tile box.
-template <int T>
-__device__ __forceinline__ double box_gap2(const WaveTargets<T>& t, const SubMeta& m) {
+__device__ __forceinline__ double box_gap2(const Box& b, const SubMeta& m) {
     double d2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double g = fmax(fmax(m.lo[c] - t.hi[c], t.lo[c] - m.hi[c]), 0.0);
+        const double g = fmax(fmax(m.lo[c] - b.hi[c], b.lo[c] - m.hi[c]), 0.0);
         d2 = __builtin_fma(g, g, d2);
     }
     return d2;
 }
 
-template <int T>
-__device__ __forceinline__ bool groups_overlap(const WaveTargets<T>& t, const SubMeta& m) {
-    return !(m.gmax < t.gmin || m.gmin > t.gmax);
+__device__ __forceinline__ bool groups_overlap(const Box& b, const SubMeta& m) {
+    return !(m.gmax < b.gmin || m.gmin > b.gmax);
+}
+
+// Squared distance from the near-pass boundary of a sub-tile.
+//   FP64: only coincident points need care, so the limit is 0 (any overlap).
+//   Mixed: pairs within the largest near radius (with slack for float32
+//   rounding of the offsets, 2^-20 of the coordinate scale) take float64, and
+//   pairs closer than half the sub-tile's extent take the high + low float32
+//   offsets; beyond that, offsets from the sub-tile centre give r to about
+//   5.5 eps32 relative.
+template <bool MIXED>
+__device__ __forceinline__ double near_limit2(const Box& w, const SubMeta& m) {
+    if constexpr (!MIXED) {
+        return 1e-200;
+    } else {
+        const double sext = fmax(fmax(m.hi[0] - m.lo[0], m.hi[1] - m.lo[1]), m.hi[2] - m.lo[2]);
+        const double wext = fmax(fmax(w.hi[0] - w.lo[0], w.hi[1] - w.lo[1]), w.hi[2] - w.lo[2]);
+        double cd = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cd += fabs(0.5 * (w.lo[c] + w.hi[c]) - m.ctr[c]);
+        const double slack = 0x1p-20 * (cd + wext + sext);
+        const double lim = fmax(__builtin_fma(1.001, m.rnear, slack), 0.5 * sext);
+        return lim * lim;
+    }
+}
+
+// Decides, uniformly for the wave, whether a sub-tile goes to the near pass:
+// some target of the wave shares a group id with the sub-tile's range, or
+// lies within the limit of its box.  The whole-wave box settles most
+// sub-tiles before the per-target test.
+template <int T, bool MIXED>
+__device__ __forceinline__ bool needs_near(const Box& w, const Targets<T>& t, const SubMeta& m,
+                                           bool excl) {
+    const double lim2 = near_limit2<MIXED>(w, m);
+    const bool wave_near = (excl && groups_overlap(w, m)) || !(box_gap2(w, m) > lim2);
+    if (!wave_near) return false;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const double p[3] = {t.x[k], t.y[k], t.z[k]};
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double g = fmax(fmax(m.lo[c] - p[c], p[c] - m.hi[c]), 0.0);
+            d2 = __builtin_fma(g, g, d2);
+        }
+        any |= (excl && t.g[k] >= m.gmin && t.g[k] <= m.gmax) || !(d2 > lim2);
+    }
+    return __ballot(any) != 0;
+}
+
+// Workgroup b of G processes units [b*U/G, (b+1)*U/G); the workgroup holding
+// unit u is floor(((u+1)*G - 1)/U).
+__device__ __forceinline__ int64_t unit_begin(int64_t b, int64_t U, int64_t G) { return b * U / G; }
+__device__ __forceinline__ int64_t unit_owner(int64_t u, int64_t U, int64_t G) {
+    return ((u + 1) * G - 1) / U;
 }
 
 template <int T>
-__device__ __forceinline__ void store_targets(const DirectArgs& a, int64_t tb, int lane,
+__device__ __forceinline__ void flush_segment(const DirectArgs& a, int64_t tbk, int wave, int lane,
                                               const double (&ax)[T], const double (&ay)[T],
                                               const double (&az)[T]) {
-    const int64_t n = a.in.n_trg;
+    constexpr int BT = kBlock * T;
+    double* seg = a.part + (int64_t)(blockIdx.x + tbk) * 3 * BT;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-        const int64_t idx = tb + (int64_t)k * kWave + lane;
-        if (idx >= n) continue;
-        if (a.splits == 1) {
-            const double p = a.in.pref;
-            if (a.accumulate) {
-                a.out[idx] += p * ax[k];
-                a.out[n + idx] += p * ay[k];
-                a.out[2 * n + idx] += p * az[k];
-            } else {
-                a.out[idx] = p * ax[k];
-                a.out[n + idx] = p * ay[k];
-                a.out[2 * n + idx] = p * az[k];
-            }
-        } else {
-            double* part = a.out + (int64_t)blockIdx.y * 3 * n;
-            part[idx] = ax[k];
-            part[n + idx] = ay[k];
-            part[2 * n + idx] = az[k];
-        }
+        const int li = wave * (kWave * T) + k * kWave + lane;
+        seg[li] = ax[k];
+        seg[BT + li] = ay[k];
+        seg[2 * BT + li] = az[k];
     }
 }
 
@@ -256,10 +311,11 @@ __device__ __forceinline__ void store_targets(const DirectArgs& a, int64_t tb, i
 // ---------------------------------------------------------------------------
 template <int KT, bool MASKED>
 __device__ __forceinline__ void pair_f64(const typename SrcRec<KT, 0>::type& s, double x, double y,
-                                         double z, bool skip, double& ax, double& ay, double& az) {
+                                         double z, bool skip_group, double& ax, double& ay,
+                                         double& az) {
     const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-    const double ri = MASKED ? rsqrt_nr_masked(r2, skip) : rsqrt_nr(r2);
+    const double ri = MASKED ? rsqrt_nr_masked(r2, skip_group || r2 == 0.0) : rsqrt_nr(r2);
     const double ri2 = ri * ri;
     const double rq = __builtin_fma(dx, s.qx, __builtin_fma(dy, s.qy, dz * s.qz));
     if constexpr (KT == 0) {
@@ -279,51 +335,107 @@ __device__ __forceinline__ void pair_f64(const typename SrcRec<KT, 0>::type& s, 
     }
 }
 
-template <int KT, int T>
-__global__ __launch_bounds__(kBlock) void direct_f64(DirectArgs a) {
-    using Rec = typename SrcRec<KT, 0>::type;
-    __shared__ Rec s_rec[kTile];
-    __shared__ int32_t s_grp[kTile];
+// Launch-shape tuning: targets per lane (T) and the minimum number of waves
+// per SIMD that the register allocation must allow, for each precision.
+#ifndef STOKES_DIRECT_T64
+#define STOKES_DIRECT_T64 4
+#endif
+#ifndef STOKES_DIRECT_W64
+#define STOKES_DIRECT_W64 3
+#endif
+#ifndef STOKES_DIRECT_T32
+#define STOKES_DIRECT_T32 2
+#endif
+#ifndef STOKES_DIRECT_W32
+#define STOKES_DIRECT_W32 4
+#endif
 
+// Copy of lane j's value of a register-resident record, for every lane
+// (v_readlane per dword; j must be wave-uniform).
+template <typename R>
+__device__ __forceinline__ R lane_bcast(const R& v, int j) {
+    static_assert(sizeof(R) % 4 == 0, "record must be whole dwords");
+    R out;
+    const int* src = reinterpret_cast<const int*>(&v);
+    int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(R) / 4); ++i) dst[i] = __builtin_amdgcn_readlane(src[i], j);
+    return out;
+}
+
+// Iterates the flagged sub-tiles of one wave's flag row: 64 flag bytes are
+// read at once (one per lane) and the nonzero ones visited in order.
+template <typename F>
+__device__ __forceinline__ void for_each_flagged(const uint8_t* fl, int64_t C, int lane, F&& fn) {
+    for (int64_t c0 = 0; c0 < C; c0 += kWave) {
+        const uint32_t mine = (c0 + lane < C) ? fl[c0 + lane] : 0u;
+        uint64_t nz = __ballot(mine != 0);
+        while (nz) {
+            const int l = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)mine, l);
+            while (f) {
+                const int s = __builtin_ctz(f);
+                f &= f - 1;
+                fn((c0 + l) * 4 + s);
+            }
+        }
+    }
+}
+
+// Main FP64 kernel: fast loop only; sub-tiles needing per-pair tests are
+// flagged for direct_near_f64.
+template <int KT, int T>
+__global__ __launch_bounds__(kBlock, STOKES_DIRECT_W64) void direct_f64(DirectArgs a) {
+    using Rec = typename SrcRec<KT, 0>::type;
+    constexpr int BT = kBlock * T;
+    __shared__ Rec s_rec[kTile];
+
+    const int64_t U = a.units, C = a.chunks, G = gridDim.x;
+    const int64_t u0 = unit_begin(blockIdx.x, U, G), u1 = unit_begin(blockIdx.x + 1, U, G);
+    if (u0 >= u1) return;                      // whole workgroup idle (uniform)
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
-    const int64_t tb = (int64_t)blockIdx.x * (kBlock * T) + (int64_t)wave * (kWave * T);
-    const bool wave_active = tb < a.in.n_trg;
+    const bool excl = a.in.excl != 0;
+    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
 
-    WaveTargets<T> t;
-    load_targets<T>(a.in, wave_active ? tb : 0, lane, t);
+    Targets<T> t;
+    Box wbox{};
+    bool wave_active = false;
+    int64_t tbk = -1;
     double ax[T], ay[T], az[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
 
-    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
-    const int64_t sb = (int64_t)blockIdx.y * a.subs_per_split;
-    const int64_t se = min(sb + a.subs_per_split, a.n_sub);
-    const bool excl = a.in.excl != 0;
-
-    Rec pre;
-    int32_t pre_g = 0;
-    if (sb < se) {
-        pre = rec[sb * kSub + threadIdx.x];
-        pre_g = reinterpret_cast<const int32_t*>(a.aux)[sb * kSub + threadIdx.x];
-    }
-    for (int64_t c = sb; c < se; c += 4) {
-        __syncthreads();
-        s_rec[threadIdx.x] = pre;
-        s_grp[threadIdx.x] = pre_g;
-        __syncthreads();
-        if (c + 4 < se) {
-            pre = rec[(c + 4) * kSub + threadIdx.x];
-            pre_g = reinterpret_cast<const int32_t*>(a.aux)[(c + 4) * kSub + threadIdx.x];
+    int64_t ub = u0 / C, c = u0 % C;           // unit position, advanced incrementally
+    Rec pre = rec[c * kTile + threadIdx.x];
+    for (int64_t u = u0; u < u1; ++u) {
+        __syncthreads();                       // previous step's readers are done
+        if (ub != tbk) {
+            if (tbk >= 0) flush_segment<T>(a, tbk, wave, lane, ax, ay, az);
+            tbk = ub;
+            const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
+            wave_active = tb < a.in.n_trg;
+            wbox = load_targets<T>(a.in, wave_active ? tb : 0, lane, t);
+#pragma unroll
+            for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
         }
-        if (!wave_active) continue;
+        s_rec[threadIdx.x] = pre;
+        __syncthreads();
+        int64_t cn = c + 1, ubn = ub;
+        if (cn == C) { cn = 0; ++ubn; }
+        if (u + 1 < u1) pre = rec[cn * kTile + threadIdx.x];
+        if (wave_active) {
+            uint32_t flags = 0;
 #pragma unroll 1
-        for (int s = 0; s < 4; ++s) {
-            const SubMeta m = a.meta[c + s];
-            if (m.count == 0) continue;
-            const bool slow = (excl && groups_overlap(t, m)) || !(box_gap2(t, m) > 0.0);
-            const Rec* base = s_rec + s * kSub;
-            if (!slow) {
+            for (int s = 0; s < 4; ++s) {
+                const SubMeta m = a.meta[c * 4 + s];
+                if (m.count == 0) continue;
+                if (needs_near<T, false>(wbox, t, m, excl)) {
+                    flags |= 1u << s;
+                    continue;
+                }
+                const Rec* base = s_rec + s * kSub;
 #pragma unroll 2
                 for (int j = 0; j < kSub; ++j) {
                     const Rec sr = base[j];
@@ -331,35 +443,68 @@ __global__ __launch_bounds__(kBlock) void direct_f64(DirectArgs a) {
                     for (int k = 0; k < T; ++k)
                         pair_f64<KT, false>(sr, t.x[k], t.y[k], t.z[k], false, ax[k], ay[k], az[k]);
                 }
-            } else {
-                const int32_t* gb = s_grp + s * kSub;
-#pragma unroll 2
-                for (int j = 0; j < kSub; ++j) {
-                    const Rec sr = base[j];
-                    const int32_t gs = gb[j];
-#pragma unroll
-                    for (int k = 0; k < T; ++k) {
-                        const double dx = t.x[k] - sr.x, dy = t.y[k] - sr.y, dz = t.z[k] - sr.z;
-                        const bool same = dx == 0.0 && dy == 0.0 && dz == 0.0;
-                        const bool skip = same || (excl && gs == t.g[k]);
-                        pair_f64<KT, true>(sr, t.x[k], t.y[k], t.z[k], skip, ax[k], ay[k], az[k]);
-                    }
-                }
             }
+            if (lane == 0) a.flags[(tbk * 4 + wave) * C + c] = (uint8_t)flags;
         }
+        c = cn;
+        ub = ubn;
     }
-    if (wave_active) store_targets<T>(a, tb, lane, ax, ay, az);
+    flush_segment<T>(a, tbk, wave, lane, ax, ay, az);
+}
+
+// Near pass (FP64): for each wave of each target block, the flagged
+// sub-tiles with the same-group and zero-distance masks.
+template <int KT, int T>
+__global__ __launch_bounds__(kBlock) void direct_near_f64(DirectArgs a) {
+    using Rec = typename SrcRec<KT, 0>::type;
+    constexpr int BT = kBlock * T;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t tbk = blockIdx.x, C = a.chunks;
+    const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
+    if (tb >= a.in.n_trg) return;              // wave has no targets (no barriers below)
+    const bool excl = a.in.excl != 0;
+    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
+    const int32_t* grp = reinterpret_cast<const int32_t*>(a.aux);
+    Targets<T> t;
+    (void)load_targets<T>(a.in, tb, lane, t);
+    double ax[T], ay[T], az[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
+    const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
+    for_each_flagged(fl, C, lane, [&](int64_t sub) {
+        // lane j holds source j of the sub-tile; the loop broadcasts it
+        const Rec mine = rec[sub * kSub + lane];
+        const int32_t mine_g = grp[sub * kSub + lane];
+#pragma unroll 2
+        for (int j = 0; j < kSub; ++j) {
+            const Rec sr = lane_bcast(mine, j);
+            const int32_t gs = __builtin_amdgcn_readlane(mine_g, j);
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+                pair_f64<KT, true>(sr, t.x[k], t.y[k], t.z[k], excl && gs == t.g[k], ax[k], ay[k],
+                                   az[k]);
+        }
+    });
+    const int64_t np = (int64_t)gridDim.x * BT;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
+        a.near_part[gi] = ax[k];
+        a.near_part[np + gi] = ay[k];
+        a.near_part[2 * np + gi] = az[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Mixed precision: float32 pairs on centred offsets, float64 near pairs & sums
 // ---------------------------------------------------------------------------
-template <int KT, bool MASKED>
-__device__ __forceinline__ void pair_f32(const typename SrcRec<KT, 1>::type& s, float x, float y,
-                                         float z, bool skip, float& ax, float& ay, float& az) {
-    const float dx = x - s.ox, dy = y - s.oy, dz = z - s.oz;
+template <int KT>
+__device__ __forceinline__ void pair_f32(const typename SrcRec<KT, 1>::type& s, float dx, float dy,
+                                         float dz, bool skip, bool masked, float& ax, float& ay,
+                                         float& az) {
     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-    const float ri = MASKED ? (skip ? 0.0f : __builtin_amdgcn_rsqf(r2)) : __builtin_amdgcn_rsqf(r2);
+    const float ri = masked ? (skip ? 0.0f : __builtin_amdgcn_rsqf(r2)) : __builtin_amdgcn_rsqf(r2);
     const float ri2 = ri * ri;
     const float rq = __builtin_fmaf(dx, s.qx, __builtin_fmaf(dy, s.qy, dz * s.qz));
     if constexpr (KT == 0) {
@@ -369,8 +514,7 @@ __device__ __forceinline__ void pair_f32(const typename SrcRec<KT, 1>::type& s, 
         az = __builtin_fmaf(__builtin_fmaf(c, dz, s.qz), ri, az);
     } else {
         const float rn = __builtin_fmaf(dx, s.nx, __builtin_fmaf(dy, s.ny, dz * s.nz));
-        const float ri5 = ri2 * ri2 * ri;
-        const float c = rn * rq * ri5;
+        const float c = rn * rq * (ri2 * ri2 * ri);
         ax = __builtin_fmaf(c, dx, ax);
         ay = __builtin_fmaf(c, dy, ay);
         az = __builtin_fmaf(c, dz, az);
@@ -379,12 +523,12 @@ __device__ __forceinline__ void pair_f32(const typename SrcRec<KT, 1>::type& s, 
 
 // One pair in float64 from the caller's arrays (near pairs of the mixed path).
 template <int KT>
-__device__ __noinline__ void near_pair_f64(const SumInputs& in, int64_t m, int64_t n_idx,
-                                           double& ax, double& ay, double& az) {
-    const int64_t ns = in.n_src, nt = in.n_trg;
-    const double dx = in.trg_xyz[n_idx] - in.src_xyz[m];
-    const double dy = in.trg_xyz[nt + n_idx] - in.src_xyz[ns + m];
-    const double dz = in.trg_xyz[2 * nt + n_idx] - in.src_xyz[2 * ns + m];
+__device__ __forceinline__ void near_pair_f64(const SumInputs& in, int64_t m, double x, double y,
+                                              double z, double& ax, double& ay, double& az) {
+    const int64_t ns = in.n_src;
+    const double dx = x - in.src_xyz[m];
+    const double dy = y - in.src_xyz[ns + m];
+    const double dz = z - in.src_xyz[2 * ns + m];
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 == 0.0) return;
     const double w = in.weight[m];
@@ -405,149 +549,193 @@ __device__ __noinline__ void near_pair_f64(const SumInputs& in, int64_t m, int64
     }
 }
 
+// Main mixed kernel: float32 fast loop only; sub-tiles needing care are
+// flagged for direct_near_mixed.
 template <int KT, int T>
-__global__ __launch_bounds__(kBlock) void direct_mixed(DirectArgs a) {
+__global__ __launch_bounds__(kBlock, STOKES_DIRECT_W32) void direct_mixed(DirectArgs a) {
     using Rec = typename SrcRec<KT, 1>::type;
+    constexpr int BT = kBlock * T;
     __shared__ Rec s_rec[kTile];
-    __shared__ float4 s_lo[kTile];
 
+    const int64_t U = a.units, C = a.chunks, G = gridDim.x;
+    const int64_t u0 = unit_begin(blockIdx.x, U, G), u1 = unit_begin(blockIdx.x + 1, U, G);
+    if (u0 >= u1) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
-    const int64_t tb = (int64_t)blockIdx.x * (kBlock * T) + (int64_t)wave * (kWave * T);
-    const bool wave_active = tb < a.in.n_trg;
+    const bool excl = a.in.excl != 0;
+    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
 
-    WaveTargets<T> t;
-    load_targets<T>(a.in, wave_active ? tb : 0, lane, t);
-    const double wext = fmax(fmax(t.hi[0] - t.lo[0], t.hi[1] - t.lo[1]), t.hi[2] - t.lo[2]);
+    Targets<T> t;
+    Box wbox{};
+    bool wave_active = false;
+    int64_t tbk = -1;
     double ax[T], ay[T], az[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
 
-    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
-    const float4* lo = reinterpret_cast<const float4*>(a.aux);
-    const int64_t sb = (int64_t)blockIdx.y * a.subs_per_split;
-    const int64_t se = min(sb + a.subs_per_split, a.n_sub);
-    const bool excl = a.in.excl != 0;
-
-    Rec pre;
-    float4 pre_lo;
-    if (sb < se) {
-        pre = rec[sb * kSub + threadIdx.x];
-        pre_lo = lo[sb * kSub + threadIdx.x];
-    }
-    for (int64_t c = sb; c < se; c += 4) {
+    int64_t ub = u0 / C, c = u0 % C;
+    Rec pre = rec[c * kTile + threadIdx.x];
+    for (int64_t u = u0; u < u1; ++u) {
         __syncthreads();
-        s_rec[threadIdx.x] = pre;
-        s_lo[threadIdx.x] = pre_lo;
-        __syncthreads();
-        if (c + 4 < se) {
-            pre = rec[(c + 4) * kSub + threadIdx.x];
-            pre_lo = lo[(c + 4) * kSub + threadIdx.x];
-        }
-        if (!wave_active) continue;
-#pragma unroll 1
-        for (int s = 0; s < 4; ++s) {
-            const SubMeta m = a.meta[c + s];
-            if (m.count == 0) continue;
-            // A sub-tile is "close" when it may hold excluded or near pairs, or
-            // when its box gap is below half the two boxes' extents: there the
-            // float32 offsets' rounding (~eps32 * extent) would be large
-            // relative to rho, so r is formed from high + low parts instead.
-            const double sext = fmax(fmax(m.hi[0] - m.lo[0], m.hi[1] - m.lo[1]), m.hi[2] - m.lo[2]);
-            const double cd0 = fabs(0.5 * (t.lo[0] + t.hi[0]) - m.ctr[0]);
-            const double cd1 = fabs(0.5 * (t.lo[1] + t.hi[1]) - m.ctr[1]);
-            const double cd2 = fabs(0.5 * (t.lo[2] + t.hi[2]) - m.ctr[2]);
-            const double slack = 0x1p-20 * (cd0 + cd1 + cd2 + wext + sext);
-            const double lim = fmax(1.001 * m.rnear + slack, 0.5 * (wext + sext));
-            const bool close = (excl && groups_overlap(t, m)) || !(box_gap2(t, m) > lim * lim);
-            // target offsets from the sub-tile centre, rounded once from float64
-            float xs[T], ys[T], zs[T], bx[T], by[T], bz[T];
+        if (ub != tbk) {
+            if (tbk >= 0) flush_segment<T>(a, tbk, wave, lane, ax, ay, az);
+            tbk = ub;
+            const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
+            wave_active = tb < a.in.n_trg;
+            wbox = load_targets<T>(a.in, wave_active ? tb : 0, lane, t);
 #pragma unroll
-            for (int k = 0; k < T; ++k) {
-                xs[k] = (float)(t.x[k] - m.ctr[0]);
-                ys[k] = (float)(t.y[k] - m.ctr[1]);
-                zs[k] = (float)(t.z[k] - m.ctr[2]);
-                bx[k] = by[k] = bz[k] = 0.0f;
-            }
-            const Rec* base = s_rec + s * kSub;
-            if (!close) {
+            for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
+        }
+        s_rec[threadIdx.x] = pre;
+        __syncthreads();
+        int64_t cn = c + 1, ubn = ub;
+        if (cn == C) { cn = 0; ++ubn; }
+        if (u + 1 < u1) pre = rec[cn * kTile + threadIdx.x];
+        if (wave_active) {
+            uint32_t flags = 0;
+#pragma unroll 1
+            for (int s = 0; s < 4; ++s) {
+                const SubMeta m = a.meta[c * 4 + s];
+                if (m.count == 0) continue;
+                if (needs_near<T, true>(wbox, t, m, excl)) {
+                    flags |= 1u << s;
+                    continue;
+                }
+                // target offsets from the sub-tile centre, rounded once from float64
+                float xs[T], ys[T], zs[T], bx[T], by[T], bz[T];
+#pragma unroll
+                for (int k = 0; k < T; ++k) {
+                    xs[k] = (float)(t.x[k] - m.ctr[0]);
+                    ys[k] = (float)(t.y[k] - m.ctr[1]);
+                    zs[k] = (float)(t.z[k] - m.ctr[2]);
+                    bx[k] = by[k] = bz[k] = 0.0f;
+                }
+                const Rec* base = s_rec + s * kSub;
 #pragma unroll 2
                 for (int j = 0; j < kSub; ++j) {
                     const Rec sr = base[j];
 #pragma unroll
                     for (int k = 0; k < T; ++k)
-                        pair_f32<KT, false>(sr, xs[k], ys[k], zs[k], false, bx[k], by[k], bz[k]);
+                        pair_f32<KT>(sr, xs[k] - sr.ox, ys[k] - sr.oy, zs[k] - sr.oz, false, false,
+                                     bx[k], by[k], bz[k]);
                 }
-            } else {
-                float xl[T], yl[T], zl[T];
 #pragma unroll
                 for (int k = 0; k < T; ++k) {
-                    xl[k] = (float)((t.x[k] - m.ctr[0]) - (double)xs[k]);
-                    yl[k] = (float)((t.y[k] - m.ctr[1]) - (double)ys[k]);
-                    zl[k] = (float)((t.z[k] - m.ctr[2]) - (double)zs[k]);
-                }
-                const float4* lb = s_lo + s * kSub;
-                const int64_t src0 = (c + s) * kSub;
-#pragma unroll 1
-                for (int j = 0; j < kSub; ++j) {
-                    const Rec sr = base[j];
-                    const float4 sl = lb[j];
-#pragma unroll
-                    for (int k = 0; k < T; ++k) {
-                        // r = (x_hi - y_hi) + (x_lo - y_lo): the high difference is
-                        // rounded relative to rho, the residues carry the rest
-                        const float dx = (xs[k] - sr.ox) + (xl[k] - sl.x);
-                        const float dy = (ys[k] - sr.oy) + (yl[k] - sl.y);
-                        const float dz = (zs[k] - sr.oz) + (zl[k] - sl.z);
-                        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                        const bool excluded = excl && sr.g == t.g[k];
-                        const bool near = r2 <= sr.t2;
-                        const bool skip = excluded || near;
-                        const float ri = skip ? 0.0f : __builtin_amdgcn_rsqf(r2);
-                        const float ri2 = ri * ri;
-                        const float rq = __builtin_fmaf(dx, sr.qx, __builtin_fmaf(dy, sr.qy, dz * sr.qz));
-                        if constexpr (KT == 0) {
-                            const float cc = rq * ri2;
-                            bx[k] = __builtin_fmaf(__builtin_fmaf(cc, dx, sr.qx), ri, bx[k]);
-                            by[k] = __builtin_fmaf(__builtin_fmaf(cc, dy, sr.qy), ri, by[k]);
-                            bz[k] = __builtin_fmaf(__builtin_fmaf(cc, dz, sr.qz), ri, bz[k]);
-                        } else {
-                            const float rn = __builtin_fmaf(dx, sr.nx, __builtin_fmaf(dy, sr.ny, dz * sr.nz));
-                            const float cc = rn * rq * (ri2 * ri2 * ri);
-                            bx[k] = __builtin_fmaf(cc, dx, bx[k]);
-                            by[k] = __builtin_fmaf(cc, dy, by[k]);
-                            bz[k] = __builtin_fmaf(cc, dz, bz[k]);
-                        }
-                        if (near && !excluded) {
-                            const int64_t idx = tb + (int64_t)k * kWave + lane;
-                            const int64_t ic = idx < a.in.n_trg ? idx : a.in.n_trg - 1;
-                            near_pair_f64<KT>(a.in, src0 + j, ic, ax[k], ay[k], az[k]);
-                        }
-                    }
+                    ax[k] += (double)bx[k];
+                    ay[k] += (double)by[k];
+                    az[k] += (double)bz[k];
                 }
             }
+            if (lane == 0) a.flags[(tbk * 4 + wave) * C + c] = (uint8_t)flags;
+        }
+        c = cn;
+        ub = ubn;
+    }
+    flush_segment<T>(a, tbk, wave, lane, ax, ay, az);
+}
+
+// Near pass (mixed): flagged sub-tiles with r from high + low float32 parts,
+// the same-group mask, and pairs inside the near radius in float64.
+template <int KT, int T>
+__global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
+    using Rec = typename SrcRec<KT, 1>::type;
+    constexpr int BT = kBlock * T;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t tbk = blockIdx.x, C = a.chunks;
+    const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
+    if (tb >= a.in.n_trg) return;
+    const bool excl = a.in.excl != 0;
+    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
+    const float4* lo = reinterpret_cast<const float4*>(a.aux);
+    Targets<T> t;
+    (void)load_targets<T>(a.in, tb, lane, t);
+    double ax[T], ay[T], az[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
+    const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
+    for_each_flagged(fl, C, lane, [&](int64_t sub) {
+        const SubMeta m = a.meta[sub];
+        float xs[T], ys[T], zs[T], xl[T], yl[T], zl[T], bx[T], by[T], bz[T];
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            const double hx = t.x[k] - m.ctr[0], hy = t.y[k] - m.ctr[1], hz = t.z[k] - m.ctr[2];
+            xs[k] = (float)hx; ys[k] = (float)hy; zs[k] = (float)hz;
+            xl[k] = (float)(hx - (double)xs[k]);
+            yl[k] = (float)(hy - (double)ys[k]);
+            zl[k] = (float)(hz - (double)zs[k]);
+            bx[k] = by[k] = bz[k] = 0.0f;
+        }
+        // lane j holds source j of the sub-tile; the loop broadcasts it
+        const Rec mine = rec[sub * kSub + lane];
+        const float4 mine_lo = lo[sub * kSub + lane];
+#pragma unroll 2
+        for (int j = 0; j < kSub; ++j) {
+            const Rec sr = lane_bcast(mine, j);
+            const float4 sl = lane_bcast(mine_lo, j);
 #pragma unroll
             for (int k = 0; k < T; ++k) {
-                ax[k] += (double)bx[k];
-                ay[k] += (double)by[k];
-                az[k] += (double)bz[k];
+                // r = (x_hi - y_hi) + (x_lo - y_lo): the high difference is
+                // rounded relative to rho, the residues carry the rest
+                const float dx = (xs[k] - sr.ox) + (xl[k] - sl.x);
+                const float dy = (ys[k] - sr.oy) + (yl[k] - sl.y);
+                const float dz = (zs[k] - sr.oz) + (zl[k] - sl.z);
+                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                const bool excluded = excl && sr.g == t.g[k];
+                const bool near = r2 <= sr.t2;
+                pair_f32<KT>(sr, dx, dy, dz, excluded || near, true, bx[k], by[k], bz[k]);
+                if (near && !excluded)
+                    near_pair_f64<KT>(a.in, sub * kSub + j, t.x[k], t.y[k], t.z[k], ax[k], ay[k],
+                                      az[k]);
             }
         }
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+            ax[k] += (double)bx[k];
+            ay[k] += (double)by[k];
+            az[k] += (double)bz[k];
+        }
+    });
+    const int64_t np = (int64_t)gridDim.x * BT;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
+        a.near_part[gi] = ax[k];
+        a.near_part[np + gi] = ay[k];
+        a.near_part[2 * np + gi] = az[k];
     }
-    if (wave_active) store_targets<T>(a, tb, lane, ax, ay, az);
 }
 
 // ---------------------------------------------------------------------------
-// split reduction and fills
+// segment reduction and fills
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void reduce_splits(const double* __restrict__ part, int splits,
-                                                        int64_t n3, double pref, double* out,
-                                                        int accumulate) {
+// out[c][i] (=|+=) pref * (sum of target i's segments in workgroup order
+//                          + its near-pass sum).
+template <int T>
+__global__ __launch_bounds__(kBlock) void reduce_segments(const double* __restrict__ part,
+                                                          const double* __restrict__ near_part,
+                                                          int64_t n_trg, int64_t units,
+                                                          int64_t chunks, int64_t grid,
+                                                          int64_t np, double pref, double* out,
+                                                          int accumulate) {
+    constexpr int BT = kBlock * T;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n3) return;
-    double s = 0.0;
-    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * n3 + i];
-    out[i] = accumulate ? out[i] + pref * s : pref * s;
+    if (i >= n_trg) return;
+    const int64_t tbk = i / BT, li = i % BT;
+    const int64_t b0 = unit_owner(tbk * chunks, units, grid);
+    const int64_t b1 = unit_owner((tbk + 1) * chunks - 1, units, grid);
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t b = b0; b <= b1; ++b) {
+        const double* seg = part + (b + tbk) * 3 * BT;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += seg[c * BT + li];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        s[c] += near_part[c * np + i];
+        const int64_t o = c * n_trg + i;
+        out[o] = accumulate ? out[o] + pref * s[c] : pref * s[c];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void fill_zero(double* out, int64_t n) {
@@ -564,42 +752,38 @@ hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t stream) {
 // ---------------------------------------------------------------------------
 // planning and launch
 // ---------------------------------------------------------------------------
-static int targets_per_lane(int kernel, int mixed) {
-    (void)kernel;
-    (void)mixed;
-    return 4;
-}
+constexpr int kT64 = STOKES_DIRECT_T64;
+constexpr int kT32 = STOKES_DIRECT_T32;
 
 static size_t rec_bytes(int kernel, int mixed) {
     if (!mixed) return kernel == 0 ? sizeof(SrcSL64) : sizeof(SrcDL64);
     return kernel == 0 ? sizeof(SrcSL32) : sizeof(SrcDL32);
 }
 
-DirectPlan plan_direct(int kernel, int mixed, int64_t n_src, int64_t n_trg, int n_cu,
-                       int forced_splits) {
+int direct_blocks_per_cu(int kernel, int mixed) {
+    int nb = 0;
+    hipError_t e;
+    if (kernel == 0)
+        e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, direct_mixed<0, kT32>, kBlock, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, direct_f64<0, kT64>, kBlock, 0);
+    else
+        e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, direct_mixed<1, kT32>, kBlock, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, direct_f64<1, kT64>, kBlock, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+DirectPlan plan_direct(int kernel, int mixed, int64_t n_src, int64_t n_trg, int resident_blocks,
+                       int forced_grid) {
     DirectPlan p{};
-    p.T = targets_per_lane(kernel, mixed);
+    p.T = mixed ? kT32 : kT64;
     p.n_src_pad = ceil_div(n_src, kTile) * kTile;
     p.n_sub = p.n_src_pad / kSub;
+    p.chunks = p.n_src_pad / kTile;
     p.blocks_x = ceil_div(n_trg, (int64_t)kBlock * p.T);
-    const int64_t chunks = p.n_sub / 4;
-    int64_t splits = 1;
-    if (chunks > 0 && p.blocks_x > 0) {
-        if (forced_splits > 0) {
-            splits = forced_splits;
-        } else {
-            // aim for ~4 waves per SIMD (16 per CU) while keeping >= 2 chunks per split
-            const int64_t want_waves = (int64_t)n_cu * 16;
-            const int64_t waves = p.blocks_x * 4;
-            splits = ceil_div(want_waves, waves);
-            splits = std::min<int64_t>(splits, std::max<int64_t>(1, chunks / 2));
-        }
-        splits = std::max<int64_t>(1, std::min<int64_t>(splits, chunks));
-    }
-    int64_t per = chunks > 0 ? ceil_div(chunks, splits) : 0;
-    if (per > 0) splits = ceil_div(chunks, per);   // drop empty splits
-    p.splits = (int)splits;
-    p.subs_per_split = per * 4;
+    p.units = p.chunks * p.blocks_x;
+    const int64_t g = forced_grid > 0 ? forced_grid : std::max(1, resident_blocks);
+    p.grid = std::max<int64_t>(1, std::min<int64_t>(g, p.units));
+    const size_t bt = (size_t)kBlock * p.T;
     size_t off = 0;
     p.off_src = off;
     off = align_up(off + (size_t)p.n_src_pad * rec_bytes(kernel, mixed), 256);
@@ -608,14 +792,19 @@ DirectPlan plan_direct(int kernel, int mixed, int64_t n_src, int64_t n_trg, int 
     p.off_meta = off;
     off = align_up(off + (size_t)p.n_sub * sizeof(SubMeta), 256);
     p.off_part = off;
-    if (p.splits > 1) off = align_up(off + (size_t)p.splits * 3 * (size_t)n_trg * sizeof(double), 256);
+    off = align_up(off + (size_t)(p.grid + p.blocks_x) * 3 * bt * sizeof(double), 256);
+    p.off_near = off;
+    off = align_up(off + (size_t)p.blocks_x * 3 * bt * sizeof(double), 256);
+    p.off_flags = off;
+    off = align_up(off + (size_t)p.blocks_x * 4 * (size_t)p.chunks, 256);
     p.total = off;
     return p;
 }
 
 template <int KT, int MIXED>
 static hipError_t launch_typed(const SumInputs& in, const DirectPlan& p, double* out, int accumulate,
-                               void* ws, hipStream_t stream) {
+                               void* ws, hipStream_t stream, const KernelTimer& timer) {
+    constexpr int T = MIXED ? kT32 : kT64;
     char* base = static_cast<char*>(ws);
     void* rec = base + p.off_src;
     void* aux = base + p.off_grp;
@@ -629,38 +818,41 @@ static hipError_t launch_typed(const SumInputs& in, const DirectPlan& p, double*
     a.rec = rec;
     a.aux = aux;
     a.meta = meta;
-    a.n_sub = p.n_sub;
-    a.subs_per_split = p.subs_per_split;
-    a.splits = p.splits;
-    a.accumulate = accumulate;
-    a.out = p.splits > 1 ? reinterpret_cast<double*>(base + p.off_part) : out;
-    const dim3 grid((unsigned)p.blocks_x, (unsigned)p.splits);
-    if (MIXED) {
-        direct_mixed<KT, 4><<<grid, dim3(kBlock), 0, stream>>>(a);
-    } else {
-        direct_f64<KT, 4><<<grid, dim3(kBlock), 0, stream>>>(a);
-    }
+    a.chunks = p.chunks;
+    a.units = p.units;
+    a.part = reinterpret_cast<double*>(base + p.off_part);
+    a.near_part = reinterpret_cast<double*>(base + p.off_near);
+    a.flags = reinterpret_cast<uint8_t*>(base + p.off_flags);
+    if (timer.on()) (void)hipEventRecord(timer.start, stream);
+    if constexpr (MIXED != 0)
+        direct_mixed<KT, T><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
+    else
+        direct_f64<KT, T><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
+    e = hipGetLastError();
+    if (timer.on()) (void)hipEventRecord(timer.stop, stream);
+    if (e != hipSuccess) return e;
+    if constexpr (MIXED != 0)
+        direct_near_mixed<KT, T><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a);
+    else
+        direct_near_f64<KT, T><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (p.splits > 1) {
-        const int64_t n3 = 3 * in.n_trg;
-        reduce_splits<<<dim3((unsigned)ceil_div(n3, kBlock)), dim3(kBlock), 0, stream>>>(
-            reinterpret_cast<const double*>(base + p.off_part), p.splits, n3, in.pref, out, accumulate);
-        e = hipGetLastError();
-    }
-    return e;
+    reduce_segments<T><<<dim3((unsigned)ceil_div(in.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(
+        a.part, a.near_part, in.n_trg, p.units, p.chunks, p.grid, p.blocks_x * (int64_t)kBlock * T,
+        in.pref, out, accumulate);
+    return hipGetLastError();
 }
 
 hipError_t launch_direct(const SumInputs& in, const DirectPlan& p, double* out, int accumulate,
-                         void* ws, hipStream_t stream) {
+                         void* ws, hipStream_t stream, const KernelTimer& timer) {
     if (in.n_trg <= 0) return hipSuccess;
     if (in.n_src <= 0) return accumulate ? hipSuccess : launch_fill_zero(out, 3 * in.n_trg, stream);
     if (in.kernel == 0) {
-        return in.mixed ? launch_typed<0, 1>(in, p, out, accumulate, ws, stream)
-                        : launch_typed<0, 0>(in, p, out, accumulate, ws, stream);
+        return in.mixed ? launch_typed<0, 1>(in, p, out, accumulate, ws, stream, timer)
+                        : launch_typed<0, 0>(in, p, out, accumulate, ws, stream, timer);
     }
-    return in.mixed ? launch_typed<1, 1>(in, p, out, accumulate, ws, stream)
-                    : launch_typed<1, 0>(in, p, out, accumulate, ws, stream);
+    return in.mixed ? launch_typed<1, 1>(in, p, out, accumulate, ws, stream, timer)
+                    : launch_typed<1, 0>(in, p, out, accumulate, ws, stream, timer);
 }
 
 }  // namespace stokes

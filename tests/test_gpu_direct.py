@@ -85,16 +85,19 @@ def test_cfg1_full(precision):
     print(f"cfg1 {precision} rel-L2 {r:.3e}")
 
 
-@pytest.mark.parametrize("splits", [1, 2, 3, 7, 64])
-def test_source_splits_agree(splits):
-    c = _cloud(99, 5000, 1300)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("grid", [1, 2, 3, 7, 64, 1000])
+def test_work_partition_agrees(grid, precision):
+    """Any workgroup count (stream-K ranges cutting target blocks anywhere)
+    gives the same sums within the bound."""
+    c = _cloud(99, 5000, 2600)
     ref = _oracle("sl", c, True)
     try:
-        S.set_source_splits(splits)
-        got = host(_run("sl", c, "fp64", True))
+        S.set_grid_override(grid)
+        got = host(_run("sl", c, precision, True))
     finally:
-        S.set_source_splits(0)
-    assert_close(got, ref, FP64_TOL, f"splits={splits}")
+        S.set_grid_override(0)
+    assert_close(got, ref, PREC_TOL[precision], f"grid={grid}/{precision}")
 
 
 def test_fp64_is_deterministic():
