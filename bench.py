@@ -150,15 +150,15 @@ def main():
 
     # adjoint of L = 0.5 |u - u_ref|^2 at a fixed cotangent g (FP64, fused shared-point pass)
     adjoint = None
-    if args.only in (None, "vjp") and hasattr(S, "sl_vjp_raw"):
+    if args.only in (None, "vjp") and hasattr(S, "sl_vjp"):
         g = t(np.random.default_rng(7).standard_normal((3, n)))
         gf = torch.empty_like(ft)
         gs = torch.empty_like(pos)
         gx = torch.empty_like(pos)
 
         def bwd():
-            S.sl_vjp_raw(pos, ft, wt, pos, g, src_group=grp, trg_group=grp, precision="fp64",
-                         grad_f=gf, grad_src=gs, grad_trg=gx)
+            S.sl_vjp(pos, ft, wt, pos, g, src_group=grp, trg_group=grp,
+                         grad_f=gf, grad_src=gs, grad_trg=gs)
 
         ms, kms, launches = timed(bwd, max(1, args.steps // 2), 1)
         fwd_ms = results.get("fp64", {}).get("ms_per_step")

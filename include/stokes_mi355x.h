@@ -218,9 +218,14 @@ int stokes_p2p_leaf_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t k
  *   K(r;a,b) = [(r.b)a + (r.a)b - (a.b)r]/rho^3 - 3 (r.a)(r.b) r/rho^5,
  * the gradient in r of a.S(r)b.  Weights and normals are constants (no
  * derivative through the surface geometry).  The pair rule is the forward's.
+ * Adjoint sums always run in float64 (opts->precision is ignored);
  * opts->accumulate adds into the outputs instead of overwriting them.
- * When src_xyz == trg_xyz, n_src == n_trg and the same-group rule (if any)
- * uses one group array, all three outputs come from a single fused pass. */
+ * Shared point set: when src_xyz == trg_xyz, n_src == n_trg, the same-group
+ * rule (if on) uses one group array, and grad_src_xyz == grad_trg_xyz (the
+ * one array allowed to receive two gradients), that array receives the total
+ * position gradient dL/dy + dL/dx and everything comes from one fused pass.
+ * Otherwise the target-side and source-side gradients are separate passes.
+ * n_src == 0 or n_trg == 0 gives zero gradients (kept when accumulating). */
 int stokes_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
                   const double* weight, int64_t n_trg, const double* trg_xyz, double mu,
                   const stokes_exclusion* excl, const stokes_opts* opts, const double* grad_vel,
@@ -231,7 +236,8 @@ int stokes_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const d
  *   grad_density (3,n_src): dL/dphi_m = d w_m sum_n' r (r.n_m)(r.g_n)/rho^5
  *   grad_src_xyz (3,n_src): dL/dy_m   = -d sum_n' G_nm
  *   grad_trg_xyz (3,n_trg): dL/dx_n   =  d sum_m' G_nm
- *   G = [(r.q)(r.g) n + (r.n)(r.g) q + (r.n)(r.q) g]/rho^5 - 5 (r.n)(r.q)(r.g) r/rho^7. */
+ *   G = [(r.q)(r.g) n + (r.n)(r.g) q + (r.n)(r.q) g]/rho^5 - 5 (r.n)(r.q)(r.g) r/rho^7.
+ * Outputs, precision and empty sets as stokes_sl_vjp (no fused pass). */
 int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
                   const double* weight, const double* normal, int64_t n_trg,
                   const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,

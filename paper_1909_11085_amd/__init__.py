@@ -8,8 +8,8 @@ hand-written HIP kernels behind the C ABI of ``include/stokes_mi355x.h``.
 ``workloads`` (seeded synthetic inputs) imports without torch; the compute
 API (``sl``, ``dl``, ...) loads the HIP library on first use.
 """
-_API = ("sl", "dl", "p2p_leaf", "P2PPlan", "context", "set_grid_override", "StokesSL", "StokesDL",
-        "StokesP2P", "timing_enable", "timing_read")
+_API = ("sl", "dl", "sl_vjp", "dl_vjp", "sl_diff", "dl_diff", "p2p_leaf", "P2PPlan", "context",
+        "set_grid_override", "StokesSL", "StokesDL", "StokesP2P", "timing_enable", "timing_read")
 
 __all__ = list(_API) + ["workloads"]
 

@@ -157,3 +157,138 @@ def dl(src, phi, w, nrm, trg, src_group=None, trg_group=None, exclude_same_group
                                    nt, _ptr(trg), ctypes.byref(rule.ex), ctypes.byref(rule.opts),
                                    _ptr(out), _ptr(ws), size, _stream(device)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# adjoints
+# ----------------------------------------------------------------------------
+def _grad_out(t, n, name, device):
+    if t is None:
+        return None
+    return _vec3(t, name, device)
+
+
+def sl_vjp(src, f, w, trg, grad_u, mu=1.0, src_group=None, trg_group=None, exclude_same_group=None,
+           grad_f=None, grad_src=None, grad_trg=None, accumulate=False):
+    """Vector-Jacobian product of the single-layer sum (see stokes_sl_vjp).
+
+    Writes into the given (3, N) float64 tensors; any may be None.  For a
+    shared point set (src is trg) grad_src and grad_trg may be the same tensor,
+    which then receives the total position gradient from one fused pass."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
+    _vec3(grad_u, "grad_u", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    rule = _Rule(device, ns, nt, src_group, trg_group, exclude_same_group, "fp64", None, 0.0)
+    rule.opts.accumulate = int(bool(accumulate))
+    gf, gs, gt = (_grad_out(grad_f, ns, "grad_f", device), _grad_out(grad_src, ns, "grad_src", device),
+                  _grad_out(grad_trg, nt, "grad_trg", device))
+    ws, size = _workspace(C.OP_SL_VJP, ns, nt, 0, rule.opts, device)
+    C.check(C.lib().stokes_sl_vjp(context(device), ns, _ptr(src), _ptr(f), _ptr(w), nt, _ptr(trg),
+                                  float(mu), ctypes.byref(rule.ex), ctypes.byref(rule.opts),
+                                  _ptr(grad_u), _ptr(gf), _ptr(gs), _ptr(gt), _ptr(ws), size,
+                                  _stream(device)))
+    return gf, gs, gt
+
+
+def dl_vjp(src, phi, w, nrm, trg, grad_u, src_group=None, trg_group=None, exclude_same_group=None,
+           grad_phi=None, grad_src=None, grad_trg=None, accumulate=False):
+    """Vector-Jacobian product of the double-layer sum (see stokes_dl_vjp)."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(phi, "phi", device); _vec3(nrm, "nrm", device)
+    _vec3(trg, "trg", device); _vec3(grad_u, "grad_u", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    rule = _Rule(device, ns, nt, src_group, trg_group, exclude_same_group, "fp64", None, 0.0)
+    rule.opts.accumulate = int(bool(accumulate))
+    gp, gs, gt = (_grad_out(grad_phi, ns, "grad_phi", device), _grad_out(grad_src, ns, "grad_src", device),
+                  _grad_out(grad_trg, nt, "grad_trg", device))
+    ws, size = _workspace(C.OP_DL_VJP, ns, nt, 0, rule.opts, device)
+    C.check(C.lib().stokes_dl_vjp(context(device), ns, _ptr(src), _ptr(phi), _ptr(w), _ptr(nrm), nt,
+                                  _ptr(trg), ctypes.byref(rule.ex), ctypes.byref(rule.opts),
+                                  _ptr(grad_u), _ptr(gp), _ptr(gs), _ptr(gt), _ptr(ws), size,
+                                  _stream(device)))
+    return gp, gs, gt
+
+
+def _empty3(n, like):
+    return torch.empty((3, n), dtype=torch.float64, device=like.device)
+
+
+class StokesSL(torch.autograd.Function):
+    """Single-layer sum differentiable in the density and in both point sets
+    (weights are constants).  The backward runs the float64 adjoint."""
+
+    @staticmethod
+    def forward(ctx, src, f, w, trg, mu, src_group, trg_group, exclude_same_group, precision, group_h,
+                near_frac):
+        u = sl(src, f, w, trg, mu=mu, src_group=src_group, trg_group=trg_group,
+               exclude_same_group=exclude_same_group, precision=precision, group_h=group_h,
+               near_frac=near_frac)
+        ctx.save_for_backward(src, f, w, trg)
+        ctx.args = (mu, src_group, trg_group, exclude_same_group)
+        ctx.shared = src is trg
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        src, f, w, trg = ctx.saved_tensors
+        mu, sg, tg, ex = ctx.args
+        need_f, need_src, need_trg = ctx.needs_input_grad[1], ctx.needs_input_grad[0], ctx.needs_input_grad[3]
+        grad_u = grad_u.contiguous()
+        gf = _empty3(src.shape[1], src) if need_f else None
+        if ctx.shared and (need_src or need_trg):
+            gpos = _empty3(src.shape[1], src)
+            sl_vjp(src, f, w, trg, grad_u, mu=mu, src_group=sg, trg_group=tg, exclude_same_group=ex,
+                   grad_f=gf, grad_src=gpos, grad_trg=gpos)
+            return gpos, gf, None, None, None, None, None, None, None, None, None
+        gs = _empty3(src.shape[1], src) if need_src else None
+        gt = _empty3(trg.shape[1], trg) if need_trg else None
+        if gf is not None or gs is not None or gt is not None:
+            sl_vjp(src, f, w, trg, grad_u, mu=mu, src_group=sg, trg_group=tg, exclude_same_group=ex,
+                   grad_f=gf, grad_src=gs, grad_trg=gt)
+        return gs, gf, None, gt, None, None, None, None, None, None, None
+
+
+class StokesDL(torch.autograd.Function):
+    """Double-layer sum differentiable in the density and in both point sets
+    (weights and normals are constants).  Float64 adjoint."""
+
+    @staticmethod
+    def forward(ctx, src, phi, w, nrm, trg, src_group, trg_group, exclude_same_group, precision,
+                group_h, near_frac):
+        u = dl(src, phi, w, nrm, trg, src_group=src_group, trg_group=trg_group,
+               exclude_same_group=exclude_same_group, precision=precision, group_h=group_h,
+               near_frac=near_frac)
+        ctx.save_for_backward(src, phi, w, nrm, trg)
+        ctx.args = (src_group, trg_group, exclude_same_group)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        src, phi, w, nrm, trg = ctx.saved_tensors
+        sg, tg, ex = ctx.args
+        need_src, need_phi, need_trg = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[4]
+        grad_u = grad_u.contiguous()
+        gp = _empty3(src.shape[1], src) if need_phi else None
+        gs = _empty3(src.shape[1], src) if need_src else None
+        gt = _empty3(trg.shape[1], trg) if need_trg else None
+        if gp is not None or gs is not None or gt is not None:
+            dl_vjp(src, phi, w, nrm, trg, grad_u, src_group=sg, trg_group=tg, exclude_same_group=ex,
+                   grad_phi=gp, grad_src=gs, grad_trg=gt)
+        return gs, gp, None, None, gt, None, None, None, None, None, None
+
+
+def sl_diff(src, f, w, trg, mu=1.0, src_group=None, trg_group=None, exclude_same_group=None,
+            precision="fp64", group_h=None, near_frac=0.5):
+    """Differentiable single-layer sum (torch.autograd)."""
+    return StokesSL.apply(src, f, w, trg, mu, src_group, trg_group, exclude_same_group, precision,
+                          group_h, near_frac)
+
+
+def dl_diff(src, phi, w, nrm, trg, src_group=None, trg_group=None, exclude_same_group=None,
+            precision="fp64", group_h=None, near_frac=0.5):
+    """Differentiable double-layer sum (torch.autograd)."""
+    return StokesDL.apply(src, phi, w, nrm, trg, src_group, trg_group, exclude_same_group, precision,
+                          group_h, near_frac)

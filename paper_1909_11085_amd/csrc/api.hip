@@ -19,6 +19,7 @@ struct stokes_ctx {
     int clock_khz;
     int forced_grid;             // 0 = resident workgroup count
     int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
+    int vjp_resident[5];         // resident workgroups of the adjoint pass kernels
     char arch[64];
     // benchmark timing (see stokes_timing_enable)
     bool timing = false;
@@ -239,6 +240,7 @@ int stokes_create(stokes_ctx** ctx, int device) {
         }
         for (int k = 0; k < 2; ++k)
             for (int m = 0; m < 2; ++m) c->resident[k][m] = stokes::direct_blocks_per_cu(k, m) * c->n_cu;
+        stokes::vjp_resident(c->n_cu, c->vjp_resident);
     }
     *ctx = c;
     return STOKES_OK;
@@ -315,8 +317,8 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
             return STOKES_OK;
         case STOKES_OP_SL_VJP:
         case STOKES_OP_DL_VJP:
-            *bytes = stokes::vjp_workspace_bytes(op == STOKES_OP_SL_VJP ? 0 : 1, mixed, n_src, n_trg,
-                                                 ctx->n_cu);
+            *bytes = stokes::vjp_workspace_bytes(op == STOKES_OP_SL_VJP ? 0 : 1, n_src, n_trg,
+                                                 ctx->vjp_resident);
             return STOKES_OK;
         default:
             return fail(STOKES_EINVAL, "unknown op");
@@ -378,6 +380,102 @@ int stokes_dl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const 
                    double* vel_out, void* workspace, size_t ws_bytes, void* stream) {
     return direct_eval(ctx, STOKES_KERNEL_DL, n_src, src_xyz, density, weight, normal, n_trg,
                        trg_xyz, 6.0 / (8.0 * kPi), excl, opts, vel_out, workspace, ws_bytes, stream);
+}
+
+static int vjp_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* src_xyz,
+                    const double* density, const double* weight, const double* normal, int64_t n_trg,
+                    const double* trg_xyz, double pref, const stokes_exclusion* excl,
+                    const stokes_opts* opts, const double* grad_vel, double* grad_density,
+                    double* grad_src_xyz, double* grad_trg_xyz, void* workspace, size_t ws_bytes,
+                    void* stream) {
+    const char* name = kernel ? "stokes_dl_vjp" : "stokes_sl_vjp";
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz);
+    if (rc) return rc;
+    if (!arr_ok(grad_vel, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "grad_vel must be non-NULL and 8-byte aligned");
+    for (const double* g : {grad_density, grad_src_xyz, grad_trg_xyz})
+        if (g && !aligned(g, 8)) return fail(STOKES_EINVAL, "gradient outputs must be 8-byte aligned");
+    Parsed p;
+    rc = parse_common(excl, opts, n_src, n_trg, p);
+    if (rc) return rc;
+    const size_t sb = (size_t)3 * n_src * 8, tb = (size_t)3 * n_trg * 8;
+    const bool shared = src_xyz == trg_xyz && n_src == n_trg &&
+                        (p.excl == STOKES_EXCL_NONE || p.src_group == p.trg_group);
+    const bool combined = grad_src_xyz && grad_src_xyz == grad_trg_xyz;
+    if (combined && !shared)
+        return fail(STOKES_EINVAL, "grad_src_xyz and grad_trg_xyz may be one array only when sources and "
+                                   "targets are the same point set (and group array)");
+    const std::initializer_list<std::pair<const void*, size_t>> inputs = {
+        {src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {normal, kernel ? sb : 0},
+        {trg_xyz, tb}, {grad_vel, tb}, {workspace, ws_bytes}};
+    if ((rc = check_no_alias(grad_density, sb, "grad_density", inputs))) return rc;
+    if ((rc = check_no_alias(grad_src_xyz, sb, "grad_src_xyz", inputs))) return rc;
+    if ((rc = check_no_alias(grad_trg_xyz, tb, "grad_trg_xyz", inputs))) return rc;
+    if (overlaps(grad_density, sb, grad_src_xyz, sb) ||
+        overlaps(grad_density, sb, grad_trg_xyz, tb) ||
+        (!combined && overlaps(grad_src_xyz, sb, grad_trg_xyz, tb)))
+        return fail(STOKES_EINVAL, "gradient outputs overlap each other");
+    const size_t need = stokes::vjp_workspace_bytes(kernel, n_src, n_trg, ctx->vjp_resident);
+    rc = check_workspace(workspace, ws_bytes, need);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n_src == 0 || n_trg == 0) {           // empty sums: zero (or keep, when accumulating)
+        if (p.accumulate) return STOKES_OK;
+        hipError_t e = hipSuccess;
+        if (grad_density) e = stokes::launch_fill_zero(grad_density, 3 * n_src, st);
+        if (e == hipSuccess && grad_src_xyz) e = stokes::launch_fill_zero(grad_src_xyz, 3 * n_src, st);
+        if (e == hipSuccess && grad_trg_xyz && !combined)
+            e = stokes::launch_fill_zero(grad_trg_xyz, 3 * n_trg, st);
+        return launch_status(e, name);
+    }
+    stokes::VjpInputs in{};
+    in.n_src = n_src;
+    in.n_trg = n_trg;
+    in.src_xyz = src_xyz;
+    in.density = density;
+    in.weight = weight;
+    in.normal = normal;
+    in.trg_xyz = trg_xyz;
+    in.grad_vel = grad_vel;
+    in.excl = p.excl;
+    in.src_group = p.src_group;
+    in.trg_group = p.trg_group;
+    in.pref = pref;
+    in.accumulate = p.accumulate;
+    in.grad_density = grad_density;
+    in.grad_src = grad_src_xyz;
+    in.grad_trg = grad_trg_xyz;
+    const stokes::KernelTimer timer = stokes::next_timer(ctx);
+    if (timer.on()) (void)hipEventRecord(timer.start, st);
+    hipError_t e = kernel ? stokes::launch_dl_vjp(in, ctx->vjp_resident, workspace, st)
+                          : stokes::launch_sl_vjp(in, ctx->vjp_resident, combined, workspace, st);
+    if (timer.on()) (void)hipEventRecord(timer.stop, st);
+    return launch_status(e, name);
+}
+
+int stokes_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                  const double* weight, int64_t n_trg, const double* trg_xyz, double mu,
+                  const stokes_exclusion* excl, const stokes_opts* opts, const double* grad_vel,
+                  double* grad_density, double* grad_src_xyz, double* grad_trg_xyz, void* workspace,
+                  size_t ws_bytes, void* stream) {
+    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    return vjp_eval(ctx, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz,
+                    1.0 / (8.0 * kPi * mu), excl, opts, grad_vel, grad_density, grad_src_xyz,
+                    grad_trg_xyz, workspace, ws_bytes, stream);
+}
+
+int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                  const double* weight, const double* normal, int64_t n_trg,
+                  const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,
+                  const double* grad_vel, double* grad_density, double* grad_src_xyz,
+                  double* grad_trg_xyz, void* workspace, size_t ws_bytes, void* stream) {
+    return vjp_eval(ctx, STOKES_KERNEL_DL, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz,
+                    6.0 / (8.0 * kPi), excl, opts, grad_vel, grad_density, grad_src_xyz, grad_trg_xyz,
+                    workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

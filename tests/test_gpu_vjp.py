@@ -1,0 +1,234 @@
+"""GPU parity of the hand-written adjoints against the FP64 oracle's gradients,
+central finite differences of the GPU forward, dot tests and torch gradcheck.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1909_11085_amd as S
+from oracle import oracle as O
+from paper_1909_11085_amd import workloads as W
+from tests.gpu_util import FP64_TOL, assert_close, dev, device, host, rel_l2
+from tests.test_gpu_direct import _cloud
+
+pytestmark = pytest.mark.gpu
+
+VJP_TOL = FP64_TOL
+
+
+def _z(n):
+    return torch.empty((3, n), dtype=torch.float64, device=device())
+
+
+@pytest.mark.parametrize("excl", [True, False])
+@pytest.mark.parametrize("sizes", [(1000, 777), (257, 1), (1, 300), (3001, 2049)])
+def test_sl_vjp_general(excl, sizes):
+    print(f"case sl_vjp excl={excl} sizes={sizes}", flush=True)
+    c = _cloud(40 + sizes[1], *sizes)
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal((3, sizes[1]))
+    ns, nt = sizes
+    gf, gs, gt = _z(ns), _z(ns), _z(nt)
+    S.sl_vjp(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["x"]), dev(g), mu=1.3,
+             src_group=dev(c["gs"]), trg_group=dev(c["gt"]), exclude_same_group=excl,
+             grad_f=gf, grad_src=gs, grad_trg=gt)
+    rf, rs, rt = O.sl_vjp(c["y"], c["f"], c["w"], c["x"], g, mu=1.3, src_group=c["gs"],
+                          trg_group=c["gt"], exclude_same_group=excl)
+    assert_close(host(gf), rf, VJP_TOL, "dL/df")
+    assert_close(host(gs), rs, VJP_TOL, "dL/dsrc")
+    assert_close(host(gt), rt, VJP_TOL, "dL/dtrg")
+
+
+@pytest.mark.parametrize("excl", [True, False])
+@pytest.mark.parametrize("sizes", [(1000, 777), (257, 1), (1, 300), (3001, 2049)])
+def test_dl_vjp_general(excl, sizes):
+    print(f"case dl_vjp excl={excl} sizes={sizes}", flush=True)
+    c = _cloud(60 + sizes[1], *sizes)
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal((3, sizes[1]))
+    ns, nt = sizes
+    gp, gs, gt = _z(ns), _z(ns), _z(nt)
+    S.dl_vjp(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["n"]), dev(c["x"]), dev(g),
+             src_group=dev(c["gs"]), trg_group=dev(c["gt"]), exclude_same_group=excl,
+             grad_phi=gp, grad_src=gs, grad_trg=gt)
+    rp, rs, rt = O.dl_vjp(c["y"], c["f"], c["w"], c["n"], c["x"], g, src_group=c["gs"],
+                          trg_group=c["gt"], exclude_same_group=excl)
+    assert_close(host(gp), rp, VJP_TOL, "dL/dphi")
+    assert_close(host(gs), rs, VJP_TOL, "dL/dsrc")
+    assert_close(host(gt), rt, VJP_TOL, "dL/dtrg")
+
+
+@pytest.mark.parametrize("excl", [True, False])
+@pytest.mark.parametrize("n", [1000, 2500])
+def test_sl_vjp_shared_fused(excl, n):
+    """Shared point set, one combined position gradient: one fused pass."""
+    c = _cloud(80 + n, n, n, dup=0)
+    c["x"], c["gt"] = c["y"], c["gs"]
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((3, n))
+    pos = dev(c["y"])
+    gf, gpos = _z(n), _z(n)
+    grp = dev(c["gs"])
+    S.sl_vjp(pos, dev(c["f"]), dev(c["w"]), pos, dev(g), src_group=grp, trg_group=grp,
+             exclude_same_group=excl, grad_f=gf, grad_src=gpos, grad_trg=gpos)
+    rf, rs, rt = O.sl_vjp(c["y"], c["f"], c["w"], c["y"], g, src_group=c["gs"], trg_group=c["gs"],
+                          exclude_same_group=excl)
+    assert_close(host(gf), rf, VJP_TOL, "fused dL/df")
+    assert_close(host(gpos), rs + rt, VJP_TOL, "fused dL/dx total")
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_vjp_accumulate_and_empty(kernel):
+    c = _cloud(7, 500, 400)
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((3, 400))
+    base = np.full((3, 400), 0.75)
+    gt = dev(base.copy())
+    args = (dev(c["y"]), dev(c["f"]), dev(c["w"]))
+    if kernel == "sl":
+        S.sl_vjp(*args, dev(c["x"]), dev(g), grad_trg=gt, accumulate=True)
+        ref = O.sl_vjp(c["y"], c["f"], c["w"], c["x"], g, want=("trg",))[2]
+    else:
+        S.dl_vjp(*args, dev(c["n"]), dev(c["x"]), dev(g), grad_trg=gt, accumulate=True)
+        ref = O.dl_vjp(c["y"], c["f"], c["w"], c["n"], c["x"], g, want=("trg",))[2]
+    assert_close(host(gt) - base, ref, VJP_TOL, "accumulate")
+    # empty target set: source-side gradients are zero
+    z3 = torch.zeros((3, 0), dtype=torch.float64, device=device())
+    gf = dev(np.ones((3, 500)))
+    if kernel == "sl":
+        S.sl_vjp(*args, z3, z3, grad_f=gf)
+    else:
+        S.dl_vjp(*args, dev(c["n"]), z3, z3, grad_phi=gf)
+    assert np.all(host(gf) == 0.0)
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_dot_test_on_gpu(kernel):
+    """Linear in the density: <g, A f> = <A^T g, f>."""
+    c = _cloud(9, 3000, 2000)
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal((3, 2000))
+    if kernel == "sl":
+        u = S.sl(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["x"]), src_group=dev(c["gs"]),
+                 trg_group=dev(c["gt"]))
+        gf = S.sl_vjp(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["x"]), dev(g),
+                      src_group=dev(c["gs"]), trg_group=dev(c["gt"]), grad_f=_z(3000))[0]
+    else:
+        u = S.dl(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["n"]), dev(c["x"]))
+        gf = S.dl_vjp(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["n"]), dev(c["x"]), dev(g),
+                      grad_phi=_z(3000))[0]
+    lhs = float((host(u) * g).sum())
+    rhs = float((host(gf) * c["f"]).sum())
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(host(u) * g).sum()
+
+
+def test_autograd_gradcheck():
+    """torch.autograd.gradcheck of both Functions on tiny inputs (float64)."""
+    rng = np.random.default_rng(6)
+    d = device()
+    y = torch.tensor(rng.standard_normal((3, 12)) * 2, device=d, requires_grad=True)
+    f = torch.tensor(rng.standard_normal((3, 12)), device=d, requires_grad=True)
+    w = torch.tensor(rng.uniform(0.5, 1.0, 12), device=d)
+    x = torch.tensor(rng.standard_normal((3, 9)) * 2 + 0.1, device=d, requires_grad=True)
+    nv = rng.standard_normal((3, 12))
+    nv = torch.tensor(nv / np.linalg.norm(nv, axis=0), device=d)
+    assert torch.autograd.gradcheck(lambda a, b, c_: S.sl_diff(a, b, w, c_, mu=0.9), (y, f, x),
+                                    eps=1e-6, atol=1e-6, rtol=1e-5)
+    assert torch.autograd.gradcheck(lambda a, b, c_: S.dl_diff(a, b, w, nv, c_), (y, f, x),
+                                    eps=1e-6, atol=1e-6, rtol=1e-5)
+    # shared tensor for sources and targets (fused pass in backward)
+    assert torch.autograd.gradcheck(lambda a, b: S.sl_diff(a, b, w, a), (y, f), eps=1e-6,
+                                    atol=1e-6, rtol=1e-5)
+
+
+# ---------------------------------------------------------------- cfg3 (128 cells, 69,632 points)
+@pytest.fixture(scope="module")
+def cfg3():
+    return W.make_config(3)
+
+
+def test_cfg3_adjoint_vs_oracle_sampled(cfg3):
+    """L = 0.5 |u - u_ref|^2 on the shared cell point set; fused GPU adjoint vs
+    the oracle's FP64 gradient at 512 seeded points."""
+    print("case cfg3 adjoint vs oracle", flush=True)
+    cells, f, u_ref = cfg3["cells"], cfg3["f"], cfg3["u_ref"]
+    pos, ft, wt, grp = dev(cells.pos), dev(f), dev(cells.weight), dev(cells.group)
+    u = S.sl(pos, ft, wt, pos, src_group=grp, trg_group=grp)
+    g = u - dev(u_ref)
+    n = cells.n
+    gf, gpos = _z(n), _z(n)
+    S.sl_vjp(pos, ft, wt, pos, g, src_group=grp, trg_group=grp, grad_f=gf, grad_src=gpos, grad_trg=gpos)
+    gh = host(g)
+    idx = W.subset(np.random.default_rng(303), n, 512)
+    _, _, rt = O.sl_vjp(cells.pos, f, cells.weight, cells.pos[:, idx], gh[:, idx],
+                        src_group=cells.group, trg_group=cells.group[idx], exclude_same_group=True,
+                        want=("trg",))
+    rf, rs, _ = O.sl_vjp(cells.pos[:, idx], f[:, idx], cells.weight[idx], cells.pos, gh,
+                         src_group=cells.group[idx], trg_group=cells.group, exclude_same_group=True,
+                         want=("f", "src"))
+    r1 = assert_close(host(gf)[:, idx], rf, VJP_TOL, "cfg3 dL/df")
+    r2 = assert_close(host(gpos)[:, idx], rs + rt, VJP_TOL, "cfg3 dL/dx")
+    print(f"cfg3 adjoint rel-L2: dL/df {r1:.3e}, dL/dx {r2:.3e}")
+
+
+def test_cfg3_central_differences(cfg3):
+    """64 seeded (point, component) coordinates, h = 1e-6, termwise difference
+    of L with the FP64 GPU forward, against the GPU adjoint."""
+    print("case cfg3 finite differences", flush=True)
+    cells, f, u_ref = cfg3["cells"], cfg3["f"], cfg3["u_ref"]
+    n = cells.n
+    pos0, ft, wt, grp, uref = dev(cells.pos), dev(f), dev(cells.weight), dev(cells.group), dev(u_ref)
+    u = S.sl(pos0, ft, wt, pos0, src_group=grp, trg_group=grp)
+    gf, gpos = _z(n), _z(n)
+    S.sl_vjp(pos0, ft, wt, pos0, u - uref, src_group=grp, trg_group=grp, grad_f=gf, grad_src=gpos,
+             grad_trg=gpos)
+    gpos_h, gf_h = host(gpos), host(gf)
+    rng = np.random.default_rng(333)
+    flat = rng.choice(3 * n, size=64, replace=False)
+    h = 1e-6
+    worst = 0.0
+    for k, fl in enumerate(flat):
+        i, j = divmod(int(fl), n)
+        which = "pos" if k % 2 == 0 else "f"
+        base = cells.pos if which == "pos" else f
+        p, m = base.copy(), base.copy()
+        p[i, j] += h
+        m[i, j] -= h
+        if which == "pos":
+            up = S.sl(dev(p), ft, wt, dev(p), src_group=grp, trg_group=grp)
+            um = S.sl(dev(m), ft, wt, dev(m), src_group=grp, trg_group=grp)
+            ad = gpos_h[i, j]
+        else:
+            up = S.sl(pos0, dev(p), wt, pos0, src_group=grp, trg_group=grp)
+            um = S.sl(pos0, dev(m), wt, pos0, src_group=grp, trg_group=grp)
+            ad = gf_h[i, j]
+        fd = float(((up - um) * (0.5 * (up + um) - uref)).sum().item()) / (2 * h)
+        scale = np.abs(gpos_h if which == "pos" else gf_h).max()
+        err = abs(fd - ad) / (abs(ad) + 1e-3 * scale)
+        worst = max(worst, err)
+        assert err < 1e-5, (which, i, j, fd, ad)
+    print(f"cfg3 FD: worst relative difference {worst:.3e} over 64 coordinates")
+
+
+# ---------------------------------------------------------------- cfg5 wall adjoint
+def test_cfg5_wall_adjoint_sampled():
+    """Double layer wall -> cells at full size: dL/dphi at 256 wall points and
+    dL/dx at 256 cell points vs the oracle."""
+    print("case cfg5 wall adjoint", flush=True)
+    cfg = W.make_config(5)
+    wall, cells, phi, u_ref = cfg["wall"], cfg["cells"], cfg["phi"], cfg["u_ref"]
+    args = (dev(wall.pos), dev(phi), dev(wall.weight), dev(wall.normal), dev(cells.pos))
+    u = S.dl(*args)
+    g = u - dev(u_ref)
+    gp, gt = _z(wall.n), _z(cells.n)
+    S.dl_vjp(*args, g, grad_phi=gp, grad_trg=gt)
+    gh = host(g)
+    it = W.subset(np.random.default_rng(505), cells.n, 256)
+    iw = W.subset(np.random.default_rng(506), wall.n, 256)
+    _, _, rt = O.dl_vjp(wall.pos, phi, wall.weight, wall.normal, cells.pos[:, it], gh[:, it],
+                        want=("trg",))
+    rp, _, _ = O.dl_vjp(wall.pos[:, iw], phi[:, iw], wall.weight[iw], wall.normal[:, iw], cells.pos,
+                        gh, want=("phi",))
+    r1 = assert_close(host(gt)[:, it], rt, VJP_TOL, "cfg5 dL/dx")
+    r2 = assert_close(host(gp)[:, iw], rp, VJP_TOL, "cfg5 dL/dphi")
+    print(f"cfg5 DL adjoint rel-L2: dL/dx {r1:.3e}, dL/dphi {r2:.3e}")
