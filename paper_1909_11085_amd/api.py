@@ -292,3 +292,72 @@ def dl_diff(src, phi, w, nrm, trg, src_group=None, trg_group=None, exclude_same_
     """Differentiable double-layer sum (torch.autograd)."""
     return StokesDL.apply(src, phi, w, nrm, trg, src_group, trg_group, exclude_same_group, precision,
                           group_h, near_frac)
+
+
+# ----------------------------------------------------------------------------
+# leaf-to-leaf (P2P) sums
+# ----------------------------------------------------------------------------
+class P2PPlan:
+    """Leaf layout on the device (see stokes_p2p_plan_create).
+
+    Host NumPy arrays: src_leaf_ofs, trg_leaf_ofs, ulist_ofs (int64,
+    n_leaves + 1 entries) and ulist (int32).  Points are in leaf order."""
+
+    def __init__(self, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, n_src, n_trg, device=None):
+        import numpy as np
+        self._so = np.ascontiguousarray(src_leaf_ofs, dtype=np.int64)
+        self._to = np.ascontiguousarray(trg_leaf_ofs, dtype=np.int64)
+        self._uo = np.ascontiguousarray(ulist_ofs, dtype=np.int64)
+        self._ul = np.ascontiguousarray(ulist, dtype=np.int32)
+        self.n_leaves = len(self._so) - 1
+        if len(self._to) != self.n_leaves + 1 or len(self._uo) != self.n_leaves + 1:
+            raise ValueError("leaf offset arrays must all have n_leaves + 1 entries")
+        self.n_src, self.n_trg = int(n_src), int(n_trg)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._lib = C.lib()
+        h = ctypes.c_void_p()
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        C.check(self._lib.stokes_p2p_plan_create(context(self.device), self.n_leaves, self.n_src, self.n_trg,
+                                                 vp(self._so), vp(self._to), vp(self._uo), vp(self._ul),
+                                                 len(self._ul), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def pairs(self):
+        """Pairs visited (before the pair rule removes any)."""
+        n = ctypes.c_int64()
+        C.check(self._lib.stokes_p2p_plan_pairs(self._h, ctypes.byref(n)))
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.stokes_p2p_plan_destroy(h)
+            self._h = None
+
+
+def p2p_leaf(plan, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=None, trg_group=None,
+             exclude_same_group=None, precision="fp64", group_h=None, near_frac=0.5, out=None,
+             accumulate=False):
+    """Leaf-to-leaf sum over the plan's interaction lists; see stokes_p2p_leaf_eval."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    k = {"sl": C.KERNEL_SL, "dl": C.KERNEL_DL}[kernel]
+    if k == C.KERNEL_DL:
+        _vec3(nrm, "nrm", device)
+    rule = _Rule(device, ns, nt, src_group, trg_group, exclude_same_group, precision, group_h, near_frac)
+    rule.opts.accumulate = int(bool(accumulate))
+    out = _out(out, nt, device, accumulate)
+    op = C.OP_P2P_SL if k == C.KERNEL_SL else C.OP_P2P_DL
+    ws, size = _workspace(op, ns, nt, plan.n_leaves, rule.opts, device)
+    C.check(C.lib().stokes_p2p_leaf_eval(context(device), plan.handle, k, ns, _ptr(src), _ptr(f), _ptr(w),
+                                         _ptr(nrm) if k == C.KERNEL_DL else ctypes.c_void_p(0), nt,
+                                         _ptr(trg), float(mu), ctypes.byref(rule.ex),
+                                         ctypes.byref(rule.opts), _ptr(out), _ptr(ws), size,
+                                         _stream(device)))
+    return out

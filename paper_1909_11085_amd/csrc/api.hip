@@ -382,6 +382,87 @@ int stokes_dl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const 
                        trg_xyz, 6.0 / (8.0 * kPi), excl, opts, vel_out, workspace, ws_bytes, stream);
 }
 
+int stokes_p2p_plan_create(stokes_ctx* ctx, int32_t n_leaves, int64_t n_src, int64_t n_trg,
+                           const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs,
+                           const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist,
+                           stokes_p2p_plan** plan) {
+    if (!plan) return fail(STOKES_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
+    if (n_ulist < 0) return fail(STOKES_EINVAL, "n_ulist must be >= 0");
+    if (!src_leaf_ofs || !trg_leaf_ofs || !ulist_ofs)
+        return fail(STOKES_EINVAL, "leaf offset arrays (n_leaves + 1 entries, host) must be non-NULL");
+    if (n_ulist > 0 && !ulist) return fail(STOKES_EINVAL, "ulist must be non-NULL when n_ulist > 0");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    std::string err;
+    rc = stokes::p2p_plan_build(ctx->device, n_leaves, n_src, n_trg, src_leaf_ofs, trg_leaf_ofs,
+                                ulist_ofs, ulist, n_ulist, plan, err);
+    if (rc) return fail(rc, "stokes_p2p_plan_create: " + err);
+    return STOKES_OK;
+}
+
+void stokes_p2p_plan_destroy(stokes_p2p_plan* plan) {
+    if (!plan) return;
+    DeviceGuard dg((int)stokes::p2p_plan_info(plan, 4));
+    stokes::p2p_plan_free(plan);
+}
+
+int stokes_p2p_plan_pairs(const stokes_p2p_plan* plan, int64_t* pairs) {
+    if (!plan || !pairs) return fail(STOKES_EINVAL, "plan and pairs must be non-NULL");
+    *pairs = stokes::p2p_plan_info(plan, 3);
+    return STOKES_OK;
+}
+
+int stokes_p2p_leaf_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t kernel,
+                         int64_t n_src, const double* src_xyz, const double* density,
+                         const double* weight, const double* normal, int64_t n_trg,
+                         const double* trg_xyz, double mu, const stokes_exclusion* excl,
+                         const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
+                         void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!plan) return fail(STOKES_EINVAL, "plan is NULL");
+    if (kernel != STOKES_KERNEL_SL && kernel != STOKES_KERNEL_DL)
+        return fail(STOKES_EINVAL, "kernel must be STOKES_KERNEL_SL or STOKES_KERNEL_DL");
+    if (kernel == STOKES_KERNEL_SL && !(isfinite(mu) && mu > 0.0))
+        return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    if (stokes::p2p_plan_info(plan, 4) != ctx->device)
+        return fail(STOKES_EINVAL, "the plan was built on another device");
+    if (n_src != stokes::p2p_plan_info(plan, 0) || n_trg != stokes::p2p_plan_info(plan, 1))
+        return fail(STOKES_EINVAL, "n_src / n_trg differ from the plan's");
+    int rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz);
+    if (rc) return rc;
+    if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
+    Parsed p;
+    rc = parse_common(excl, opts, n_src, n_trg, p);
+    if (rc) return rc;
+    const size_t vb = (size_t)3 * n_trg * sizeof(double), sb = (size_t)3 * n_src * sizeof(double);
+    rc = check_no_alias(vel_out, vb, "vel_out",
+                        {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {normal, kernel ? sb : 0},
+                         {trg_xyz, vb}, {workspace, ws_bytes}});
+    if (rc) return rc;
+    const int mixed = p.precision == STOKES_MIXED;
+    const int32_t nl = (int32_t)stokes::p2p_plan_info(plan, 2);
+    rc = check_workspace(workspace, ws_bytes, stokes::p2p_workspace_bytes(kernel, mixed, n_src, n_trg, nl));
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n_trg == 0) return STOKES_OK;
+    if (n_src == 0)
+        return p.accumulate ? STOKES_OK
+                            : launch_status(stokes::launch_fill_zero(vel_out, 3 * n_trg, st), "stokes_p2p_leaf_eval");
+    const double pref = kernel == STOKES_KERNEL_SL ? 1.0 / (8.0 * kPi * mu) : 6.0 / (8.0 * kPi);
+    const stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal, n_trg,
+                                             trg_xyz, pref);
+    return launch_status(stokes::launch_p2p(in, plan, vel_out, p.accumulate, workspace, st,
+                                            stokes::next_timer(ctx)),
+                         "stokes_p2p_leaf_eval");
+}
+
 static int vjp_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* src_xyz,
                     const double* density, const double* weight, const double* normal, int64_t n_trg,
                     const double* trg_xyz, double pref, const stokes_exclusion* excl,

@@ -1,23 +1,449 @@
-// Leaf-to-leaf (P2P) sums: not implemented yet in this revision.
+// Leaf-to-leaf (P2P) sums: the near-field part of the FMM evaluation of the
+// paper's Sec. 3.4 ("Far evaluation"), where every target leaf sums the
+// single- or double-layer kernel over the sources of the leaves in its
+// interaction list, in one launch over all the (uneven) lists.
+//
+// Design (gfx950):
+//   * plan (host, once per leaf layout): validates the leaf CSR arrays, cuts
+//     each target leaf into 64-target work items, sorts the items by pair
+//     count (largest first, for balance) and uploads layout and items.
+//   * prep (one wave per leaf, per evaluation): the leaf's box centre, then a
+//     packed record per source; mixed precision stores each source's offset
+//     from its leaf centre as a float32 high part and float32 residue.
+//   * sum: one wave per work item; each lane holds one target; the sources of
+//     each listed leaf are staged through LDS (up to 256 at a time) and read
+//     by broadcast.  Every pair goes through the same-group and
+//     zero-distance masks; in mixed precision r = (x_hi - y_hi) + (x_lo - y_lo)
+//     in float32, pairs inside the near radius are evaluated in float64, and
+//     each source leaf's float32 partial is added into float64 accumulators.
+#include <float.h>
+#include <limits.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
 #include "../../include/stokes_mi355x.h"
 #include "p2p.hpp"
 
-namespace stokes {
-size_t p2p_workspace_bytes(int, int, int64_t, int64_t, int32_t) { return 0; }
-}  // namespace stokes
+struct stokes_p2p_plan {
+    int device;
+    int32_t n_leaves;
+    int64_t n_src, n_trg, n_ulist, n_items, pairs;
+    int64_t* d_src_ofs;      // device copies
+    int64_t* d_trg_ofs;
+    int64_t* d_ulist_ofs;
+    int32_t* d_ulist;
+    int32_t* d_items;        // (leaf, chunk) pairs, largest pair count first
+};
 
-extern "C" {
-int stokes_p2p_plan_create(stokes_ctx*, int32_t, int64_t, int64_t, const int64_t*, const int64_t*,
-                           const int64_t*, const int32_t*, int64_t, stokes_p2p_plan** plan) {
-    if (plan) *plan = nullptr;
-    return STOKES_EUNSUPPORTED;
+namespace stokes {
+namespace {
+
+constexpr int kP2PTile = 256;   // sources staged per LDS step
+
+struct alignas(16) P2PSL32 { float hx, hy, hz, lx, ly, lz, qx, qy, qz, t2; int32_t g; float pad; };
+struct alignas(16) P2PDL32 {
+    float hx, hy, hz, lx, ly, lz, qx, qy, qz, nx, ny, nz, t2;
+    int32_t g;
+    float pad[2];
+};
+
+template <int KT, int MIXED> struct P2PRec;
+template <> struct P2PRec<0, 0> { using type = SrcSL64; };
+template <> struct P2PRec<1, 0> { using type = SrcDL64; };
+template <> struct P2PRec<0, 1> { using type = P2PSL32; };
+template <> struct P2PRec<1, 1> { using type = P2PDL32; };
+
+struct P2PArgs {
+    SumInputs in;
+    const int64_t* src_ofs;
+    const int64_t* trg_ofs;
+    const int64_t* ulist_ofs;
+    const int32_t* ulist;
+    const int32_t* items;
+    void* rec;
+    int32_t* grp;
+    double* leaf_ctr;        // (n_leaves, 3)
+    int32_t n_leaves;
+    double* out;
+    int accumulate;
+};
+
+__device__ __forceinline__ double wmin(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
 }
-void stokes_p2p_plan_destroy(stokes_p2p_plan*) {}
-int stokes_p2p_plan_pairs(const stokes_p2p_plan*, int64_t*) { return STOKES_EUNSUPPORTED; }
-int stokes_p2p_leaf_eval(stokes_ctx*, const stokes_p2p_plan*, int32_t, int64_t, const double*,
-                         const double*, const double*, const double*, int64_t, const double*,
-                         double, const stokes_exclusion*, const stokes_opts*, double*, void*,
-                         size_t, void*) {
-    return STOKES_EUNSUPPORTED;
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
 }
+
+// One wave per leaf: box centre of its sources, then its packed records.
+template <int KT, int MIXED>
+__global__ __launch_bounds__(kWave) void p2p_prep(P2PArgs a) {
+    using Rec = typename P2PRec<KT, MIXED>::type;
+    const int32_t L = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t s0 = a.src_ofs[L], s1 = a.src_ofs[L + 1];
+    const int64_t n = a.in.n_src;
+    const SumInputs& in = a.in;
+    double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+    for (int64_t i = s0 + lane; i < s1; i += kWave)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fmin(lo[c], in.src_xyz[c * n + i]);
+            hi[c] = fmax(hi[c], in.src_xyz[c * n + i]);
+        }
+    double ctr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double l = wmin(lo[c]), h = wmax(hi[c]);
+        ctr[c] = s1 > s0 ? 0.5 * (l + h) : 0.0;
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.leaf_ctr[3 * (int64_t)L + c] = ctr[c];
+    for (int64_t i = s0 + lane; i < s1; i += kWave) {
+        const double w = in.weight[i];
+        double y[3], q[3], nv[3] = {0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            y[c] = in.src_xyz[c * n + i];
+            q[c] = w * in.density[c * n + i];
+            if (KT == 1) nv[c] = in.normal[c * n + i];
+        }
+        int32_t g = in.src_group ? in.src_group[i] : 0;
+        double rn = 0.0;
+        if (MIXED && in.group_h) {
+            if (g >= 0 && g < in.n_groups) rn = in.near_frac * in.group_h[g];
+            else q[0] = q[1] = q[2] = __builtin_nan("");
+        }
+        Rec r;
+        if constexpr (MIXED == 0) {
+            r.x = y[0]; r.y = y[1]; r.z = y[2];
+            r.qx = q[0]; r.qy = q[1]; r.qz = q[2];
+            if constexpr (KT == 1) { r.nx = nv[0]; r.ny = nv[1]; r.nz = nv[2]; r.pad = 0.0; }
+            a.grp[i] = g;
+        } else {
+            const double o0 = y[0] - ctr[0], o1 = y[1] - ctr[1], o2 = y[2] - ctr[2];
+            r.hx = (float)o0; r.hy = (float)o1; r.hz = (float)o2;
+            r.lx = (float)(o0 - (double)r.hx);
+            r.ly = (float)(o1 - (double)r.hy);
+            r.lz = (float)(o2 - (double)r.hz);
+            r.qx = (float)q[0]; r.qy = (float)q[1]; r.qz = (float)q[2];
+            if constexpr (KT == 1) { r.nx = (float)nv[0]; r.ny = (float)nv[1]; r.nz = (float)nv[2]; }
+            r.t2 = (float)(rn * rn);
+            r.g = g;
+        }
+        reinterpret_cast<Rec*>(a.rec)[i] = r;
+    }
 }
+
+__device__ __forceinline__ double rinv(double r2, bool skip) {
+    const double y0 = skip ? 0.0 : __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-r2, y0 * y0, 1.0);
+    return __builtin_fma(0.5 * y0, e, y0);
+}
+
+template <int KT>
+__device__ __forceinline__ void pair64(const typename P2PRec<KT, 0>::type& s, double x, double y,
+                                       double z, bool skip_group, double& ax, double& ay, double& az) {
+    const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
+    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+    const double ri = rinv(r2, skip_group || r2 == 0.0);
+    const double ri2 = ri * ri;
+    const double rq = __builtin_fma(dx, s.qx, __builtin_fma(dy, s.qy, dz * s.qz));
+    if constexpr (KT == 0) {
+        const double c = rq * ri2;
+        ax = __builtin_fma(__builtin_fma(c, dx, s.qx), ri, ax);
+        ay = __builtin_fma(__builtin_fma(c, dy, s.qy), ri, ay);
+        az = __builtin_fma(__builtin_fma(c, dz, s.qz), ri, az);
+    } else {
+        const double rn = __builtin_fma(dx, s.nx, __builtin_fma(dy, s.ny, dz * s.nz));
+        const double c = rn * rq * (ri2 * ri2 * ri);
+        ax = __builtin_fma(c, dx, ax);
+        ay = __builtin_fma(c, dy, ay);
+        az = __builtin_fma(c, dz, az);
+    }
+}
+
+// float64 evaluation of one pair from the caller's arrays (near pairs, mixed)
+template <int KT>
+__device__ __noinline__ void near64(const SumInputs& in, int64_t m, double x, double y, double z,
+                                    double& ax, double& ay, double& az) {
+    const int64_t ns = in.n_src;
+    const double dx = x - in.src_xyz[m], dy = y - in.src_xyz[ns + m], dz = z - in.src_xyz[2 * ns + m];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 == 0.0) return;
+    const double w = in.weight[m];
+    const double qx = w * in.density[m], qy = w * in.density[ns + m], qz = w * in.density[2 * ns + m];
+    const double ri = 1.0 / sqrt(r2);
+    const double rq = dx * qx + dy * qy + dz * qz;
+    if constexpr (KT == 0) {
+        const double c = rq * ri * ri;
+        ax += (qx + c * dx) * ri;
+        ay += (qy + c * dy) * ri;
+        az += (qz + c * dz) * ri;
+    } else {
+        const double rn = dx * in.normal[m] + dy * in.normal[ns + m] + dz * in.normal[2 * ns + m];
+        const double c = rn * rq * (ri * ri) * (ri * ri) * ri;
+        ax += c * dx;
+        ay += c * dy;
+        az += c * dz;
+    }
+}
+
+template <int KT, int MIXED>
+__global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
+    using Rec = typename P2PRec<KT, MIXED>::type;
+    __shared__ Rec s_rec[kP2PTile];
+    __shared__ int32_t s_grp[MIXED ? 1 : kP2PTile];
+    const int lane = threadIdx.x;
+    const int32_t L = a.items[2 * blockIdx.x], ch = a.items[2 * blockIdx.x + 1];
+    const int64_t t0 = a.trg_ofs[L] + (int64_t)ch * kWave;
+    const int64_t t1 = min(a.trg_ofs[L + 1], t0 + kWave);
+    const int64_t idx = t0 + lane;
+    const bool valid = idx < t1;
+    const int64_t ic = valid ? idx : t0;
+    const int64_t nt = a.in.n_trg;
+    const double x = a.in.trg_xyz[ic], y = a.in.trg_xyz[nt + ic], z = a.in.trg_xyz[2 * nt + ic];
+    const int32_t tg = a.in.trg_group ? a.in.trg_group[ic] : 0;
+    const bool excl = a.in.excl != 0;
+    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int64_t k = a.ulist_ofs[L]; k < a.ulist_ofs[L + 1]; ++k) {
+        const int32_t Ls = a.ulist[k];
+        const int64_t s0 = a.src_ofs[Ls], ns = a.src_ofs[Ls + 1] - s0;
+        float xs = 0.f, ys = 0.f, zs = 0.f, xl = 0.f, yl = 0.f, zl = 0.f;
+        if constexpr (MIXED != 0) {
+            const double hx = x - a.leaf_ctr[3 * (int64_t)Ls], hy = y - a.leaf_ctr[3 * (int64_t)Ls + 1],
+                         hz = z - a.leaf_ctr[3 * (int64_t)Ls + 2];
+            xs = (float)hx; ys = (float)hy; zs = (float)hz;
+            xl = (float)(hx - (double)xs);
+            yl = (float)(hy - (double)ys);
+            zl = (float)(hz - (double)zs);
+        }
+        for (int64_t b = 0; b < ns; b += kP2PTile) {
+            const int nb = (int)((ns - b) < kP2PTile ? (ns - b) : kP2PTile);
+            __syncthreads();
+            for (int i = lane; i < nb; i += kWave) {
+                s_rec[i] = rec[s0 + b + i];
+                if constexpr (MIXED == 0) s_grp[i] = a.grp[s0 + b + i];
+            }
+            __syncthreads();
+            if constexpr (MIXED == 0) {
+#pragma unroll 4
+                for (int j = 0; j < nb; ++j)
+                    pair64<KT>(s_rec[j], x, y, z, excl && s_grp[j] == tg, ax, ay, az);
+            } else {
+                float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll 4
+                for (int j = 0; j < nb; ++j) {
+                    const Rec s = s_rec[j];
+                    const float dx = (xs - s.hx) + (xl - s.lx);
+                    const float dy = (ys - s.hy) + (yl - s.ly);
+                    const float dz = (zs - s.hz) + (zl - s.lz);
+                    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                    const bool excluded = excl && s.g == tg;
+                    const bool near = r2 <= s.t2;
+                    const float ri = (excluded || near) ? 0.0f : __builtin_amdgcn_rsqf(r2);
+                    const float ri2 = ri * ri;
+                    const float rq = __builtin_fmaf(dx, s.qx, __builtin_fmaf(dy, s.qy, dz * s.qz));
+                    if constexpr (KT == 0) {
+                        const float c = rq * ri2;
+                        bx = __builtin_fmaf(__builtin_fmaf(c, dx, s.qx), ri, bx);
+                        by = __builtin_fmaf(__builtin_fmaf(c, dy, s.qy), ri, by);
+                        bz = __builtin_fmaf(__builtin_fmaf(c, dz, s.qz), ri, bz);
+                    } else {
+                        const float rn = __builtin_fmaf(dx, s.nx, __builtin_fmaf(dy, s.ny, dz * s.nz));
+                        const float c = rn * rq * (ri2 * ri2 * ri);
+                        bx = __builtin_fmaf(c, dx, bx);
+                        by = __builtin_fmaf(c, dy, by);
+                        bz = __builtin_fmaf(c, dz, bz);
+                    }
+                    if (near && !excluded) near64<KT>(a.in, s0 + b + j, x, y, z, ax, ay, az);
+                }
+                ax += (double)bx;
+                ay += (double)by;
+                az += (double)bz;
+            }
+        }
+    }
+    if (valid) {
+        const double p = a.in.pref;
+        if (a.accumulate) {
+            a.out[idx] += p * ax;
+            a.out[nt + idx] += p * ay;
+            a.out[2 * nt + idx] += p * az;
+        } else {
+            a.out[idx] = p * ax;
+            a.out[nt + idx] = p * ay;
+            a.out[2 * nt + idx] = p * az;
+        }
+    }
+}
+
+size_t rec_size(int kernel, int mixed) {
+    if (!mixed) return kernel == 0 ? sizeof(SrcSL64) : sizeof(SrcDL64);
+    return kernel == 0 ? sizeof(P2PSL32) : sizeof(P2PDL32);
+}
+
+struct P2PLayout {
+    size_t off_rec, off_grp, off_ctr, total;
+};
+
+P2PLayout p2p_layout(int kernel, int mixed, int64_t n_src, int32_t n_leaves) {
+    P2PLayout l{};
+    size_t off = 0;
+    l.off_rec = off;
+    off = align_up(off + (size_t)std::max<int64_t>(n_src, 1) * rec_size(kernel, mixed), 256);
+    l.off_grp = off;
+    off = align_up(off + (size_t)std::max<int64_t>(n_src, 1) * sizeof(int32_t), 256);
+    l.off_ctr = off;
+    off = align_up(off + (size_t)std::max(n_leaves, 1) * 3 * sizeof(double), 256);
+    l.total = off;
+    return l;
+}
+
+template <int KT, int MIXED>
+hipError_t run_p2p(P2PArgs a, const stokes_p2p_plan* plan, void* ws, hipStream_t stream,
+                   const KernelTimer& timer) {
+    const P2PLayout l = p2p_layout(KT, MIXED, a.in.n_src, plan->n_leaves);
+    char* base = static_cast<char*>(ws);
+    a.rec = base + l.off_rec;
+    a.grp = reinterpret_cast<int32_t*>(base + l.off_grp);
+    a.leaf_ctr = reinterpret_cast<double*>(base + l.off_ctr);
+    if (plan->n_leaves > 0) {
+        p2p_prep<KT, MIXED><<<dim3((unsigned)plan->n_leaves), dim3(kWave), 0, stream>>>(a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (plan->n_items == 0) return hipSuccess;
+    if (timer.on()) (void)hipEventRecord(timer.start, stream);
+    p2p_sum<KT, MIXED><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+    hipError_t e = hipGetLastError();
+    if (timer.on()) (void)hipEventRecord(timer.stop, stream);
+    return e;
+}
+
+}  // namespace
+
+size_t p2p_workspace_bytes(int kernel, int mixed, int64_t n_src, int64_t n_trg, int32_t n_leaves) {
+    (void)n_trg;
+    if (n_src <= 0) return 0;
+    return p2p_layout(kernel, mixed, n_src, n_leaves).total;
+}
+
+hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* out, int accumulate,
+                      void* ws, hipStream_t stream, const KernelTimer& timer) {
+    P2PArgs a{};
+    a.in = in;
+    a.src_ofs = plan->d_src_ofs;
+    a.trg_ofs = plan->d_trg_ofs;
+    a.ulist_ofs = plan->d_ulist_ofs;
+    a.ulist = plan->d_ulist;
+    a.items = plan->d_items;
+    a.n_leaves = plan->n_leaves;
+    a.out = out;
+    a.accumulate = accumulate;
+    if (in.kernel == 0)
+        return in.mixed ? run_p2p<0, 1>(a, plan, ws, stream, timer) : run_p2p<0, 0>(a, plan, ws, stream, timer);
+    return in.mixed ? run_p2p<1, 1>(a, plan, ws, stream, timer) : run_p2p<1, 0>(a, plan, ws, stream, timer);
+}
+
+// ---------------------------------------------------------------------------
+// plan construction (host)
+// ---------------------------------------------------------------------------
+int p2p_plan_build(int device, int32_t n_leaves, int64_t n_src, int64_t n_trg,
+                   const int64_t* src_ofs, const int64_t* trg_ofs, const int64_t* ulist_ofs,
+                   const int32_t* ulist, int64_t n_ulist, stokes_p2p_plan** out, std::string& err) {
+    auto check_ofs = [&](const int64_t* o, int64_t end, const char* name) -> bool {
+        if (o[0] != 0) { err = std::string(name) + "[0] must be 0"; return false; }
+        for (int32_t L = 0; L < n_leaves; ++L)
+            if (o[L + 1] < o[L]) { err = std::string(name) + " must be non-decreasing"; return false; }
+        if (o[n_leaves] != end) {
+            err = std::string(name) + "[n_leaves] must equal " + std::to_string(end);
+            return false;
+        }
+        return true;
+    };
+    if (!check_ofs(src_ofs, n_src, "src_leaf_ofs") || !check_ofs(trg_ofs, n_trg, "trg_leaf_ofs") ||
+        !check_ofs(ulist_ofs, n_ulist, "ulist_ofs"))
+        return STOKES_EINVAL;
+    for (int64_t k = 0; k < n_ulist; ++k)
+        if (ulist[k] < 0 || ulist[k] >= n_leaves) {
+            err = "ulist entry " + std::to_string(k) + " is outside [0, n_leaves)";
+            return STOKES_EINVAL;
+        }
+    // work items: (leaf, 64-target chunk), largest pair count first
+    int64_t pairs = 0;
+    struct Item { int64_t cost; int32_t leaf, chunk; };
+    std::vector<Item> items;
+    for (int32_t L = 0; L < n_leaves; ++L) {
+        int64_t s = 0;
+        for (int64_t k = ulist_ofs[L]; k < ulist_ofs[L + 1]; ++k) s += src_ofs[ulist[k] + 1] - src_ofs[ulist[k]];
+        const int64_t nt = trg_ofs[L + 1] - trg_ofs[L];
+        pairs += nt * s;
+        for (int64_t c = 0; c * kWave < nt; ++c) {
+            if (c > INT32_MAX) { err = "leaf too large"; return STOKES_EUNSUPPORTED; }
+            items.push_back({std::min<int64_t>(kWave, nt - c * kWave) * s + 1, L, (int32_t)c});
+        }
+    }
+    if ((int64_t)items.size() > (int64_t)INT32_MAX) { err = "too many work items"; return STOKES_EUNSUPPORTED; }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    std::vector<int32_t> flat(2 * items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+        flat[2 * i] = items[i].leaf;
+        flat[2 * i + 1] = items[i].chunk;
+    }
+    stokes_p2p_plan* p = new (std::nothrow) stokes_p2p_plan{};
+    if (!p) { err = "out of host memory"; return STOKES_EDEVICE; }
+    p->device = device;
+    p->n_leaves = n_leaves;
+    p->n_src = n_src;
+    p->n_trg = n_trg;
+    p->n_ulist = n_ulist;
+    p->n_items = (int64_t)items.size();
+    p->pairs = pairs;
+    auto up = [&](void** dst, const void* src, size_t bytes) -> bool {
+        if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+        return bytes == 0 || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    const size_t ob = (size_t)(n_leaves + 1) * sizeof(int64_t);
+    if (!up((void**)&p->d_src_ofs, src_ofs, ob) || !up((void**)&p->d_trg_ofs, trg_ofs, ob) ||
+        !up((void**)&p->d_ulist_ofs, ulist_ofs, ob) ||
+        !up((void**)&p->d_ulist, ulist, (size_t)n_ulist * sizeof(int32_t)) ||
+        !up((void**)&p->d_items, flat.data(), flat.size() * sizeof(int32_t))) {
+        p2p_plan_free(p);
+        err = "device allocation or copy failed for the leaf layout";
+        return STOKES_EDEVICE;
+    }
+    *out = p;
+    return STOKES_OK;
+}
+
+void p2p_plan_free(stokes_p2p_plan* p) {
+    if (!p) return;
+    for (void* d : {(void*)p->d_src_ofs, (void*)p->d_trg_ofs, (void*)p->d_ulist_ofs, (void*)p->d_ulist,
+                    (void*)p->d_items})
+        if (d) (void)hipFree(d);
+    delete p;
+}
+
+int64_t p2p_plan_info(const stokes_p2p_plan* p, int which) {
+    switch (which) {
+        case 0: return p->n_src;
+        case 1: return p->n_trg;
+        case 2: return p->n_leaves;
+        case 3: return p->pairs;
+        case 4: return p->device;
+        default: return 0;
+    }
+}
+
+}  // namespace stokes

@@ -1,7 +1,24 @@
 // Internal declarations of the leaf-to-leaf (P2P) sums.
 #pragma once
+#include <string>
+
 #include "common.hpp"
 
+struct stokes_p2p_plan;
+
 namespace stokes {
+
 size_t p2p_workspace_bytes(int kernel, int mixed, int64_t n_src, int64_t n_trg, int32_t n_leaves);
+
+// Validates the host leaf arrays and uploads the layout to the current device.
+int p2p_plan_build(int device, int32_t n_leaves, int64_t n_src, int64_t n_trg,
+                   const int64_t* src_ofs, const int64_t* trg_ofs, const int64_t* ulist_ofs,
+                   const int32_t* ulist, int64_t n_ulist, stokes_p2p_plan** out, std::string& err);
+void p2p_plan_free(stokes_p2p_plan* p);
+// 0: n_src, 1: n_trg, 2: n_leaves, 3: pairs, 4: device
+int64_t p2p_plan_info(const stokes_p2p_plan* p, int which);
+
+hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* out, int accumulate,
+                      void* ws, hipStream_t stream, const KernelTimer& timer);
+
 }  // namespace stokes

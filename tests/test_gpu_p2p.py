@@ -1,0 +1,127 @@
+"""GPU parity of the leaf-to-leaf (FMM near-field) sums against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1909_11085_amd as S
+from oracle import oracle as O
+from paper_1909_11085_amd import _capi as C
+from paper_1909_11085_amd import workloads as W
+from tests.gpu_util import FP64_TOL, MIXED_TOL, assert_close, dev, device, host
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": FP64_TOL, "mixed": MIXED_TOL}
+
+
+def _tree(seed, n_cells=10, max_leaf=48, side=20.0):
+    rng = np.random.default_rng(seed)
+    cells = W.place_cells(rng, n_cells, ("box", side), order=8)
+    lo = cells.pos.min(1) - 1e-3
+    sd = float((cells.pos.max(1) - lo).max()) + 1e-3
+    tree = W.build_octree(cells.pos, lo, sd, max_leaf=max_leaf)
+    p = tree.perm
+    f = rng.standard_normal((3, cells.n))
+    return rng, tree, dict(pos=cells.pos[:, p].copy(), w=cells.weight[p].copy(), g=cells.group[p].copy(),
+                           n=cells.normal[:, p].copy(), f=f[:, p].copy(), h=cells.group_h)
+
+
+def _run(plan, d, kernel, precision, **kw):
+    return S.p2p_leaf(plan, dev(d["pos"]), dev(d["f"]), dev(d["w"]), dev(d["pos"]), kernel=kernel,
+                      nrm=dev(d["n"]), src_group=dev(d["g"]), trg_group=dev(d["g"]), precision=precision,
+                      group_h=dev(d["h"]), **kw)
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_p2p_random_lists(kernel, precision):
+    print(f"case p2p random lists {kernel} {precision}", flush=True)
+    rng, tree, d = _tree(11)
+    ofs, ul = W.nearest_leaf_lists(rng, tree, kmin=3, kmax=12)
+    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, ofs, ul, d["pos"].shape[1], d["pos"].shape[1])
+    got = host(_run(plan, d, kernel, precision, mu=1.4))
+    ref = O.p2p(0 if kernel == "sl" else 1, d["pos"], d["f"], d["w"], d["pos"], tree.leaf_ofs,
+                tree.leaf_ofs, ofs, ul, nrm=d["n"], mu=1.4, src_group=d["g"], trg_group=d["g"],
+                exclude_same_group=True)
+    assert_close(got, ref, TOL[precision], f"p2p {kernel}/{precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_p2p_full_lists_equal_direct(precision):
+    """Every leaf listing every leaf reproduces the direct sum."""
+    rng, tree, d = _tree(12, n_cells=6)
+    nl = len(tree.leaf_ofs) - 1
+    ofs = np.arange(nl + 1, dtype=np.int64) * nl
+    ul = np.tile(np.arange(nl, dtype=np.int32), nl)
+    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, ofs, ul, d["pos"].shape[1], d["pos"].shape[1])
+    got = host(_run(plan, d, "sl", precision))
+    ref = O.sl(d["pos"], d["f"], d["w"], d["pos"], src_group=d["g"], trg_group=d["g"],
+               exclude_same_group=True)
+    assert_close(got, ref, TOL[precision], "p2p full lists")
+    assert plan.pairs() == d["pos"].shape[1] ** 2
+
+
+def test_p2p_uneven_layout_edge_cases():
+    """Empty leaves, leaves with sources but no targets, repeated list entries,
+    accumulate into an existing velocity."""
+    rng = np.random.default_rng(13)
+    ns, nt = 300, 200
+    y = rng.standard_normal((3, ns)) * 3
+    x = rng.standard_normal((3, nt)) * 3
+    f = rng.standard_normal((3, ns))
+    w = rng.uniform(0.5, 1, ns)
+    so = np.array([0, 0, 100, 100, 250, 300], dtype=np.int64)   # leaf 0 and 2 have no sources
+    to = np.array([0, 50, 50, 120, 200, 200], dtype=np.int64)   # leaf 1 and 4 have no targets
+    uo = np.array([0, 3, 3, 5, 9, 10], dtype=np.int64)
+    ul = np.array([1, 3, 4, 1, 1, 0, 1, 1, 4, 2], dtype=np.int32)  # leaf 3 lists leaf 1 twice
+    plan = S.P2PPlan(so, to, uo, ul, ns, nt)
+    base = np.full((3, nt), 0.5)
+    out = dev(base.copy())
+    S.p2p_leaf(plan, dev(y), dev(f), dev(w), dev(x), out=out, accumulate=True)
+    ref = O.p2p(0, y, f, w, x, so, to, uo, ul)
+    assert_close(host(out) - base, ref, FP64_TOL, "uneven layout")
+
+
+def test_p2p_plan_rejects_malformed_layouts():
+    ok = dict(so=np.array([0, 5, 10]), to=np.array([0, 4, 8]), uo=np.array([0, 1, 2]), ul=np.array([0, 1]))
+    bad = [
+        dict(ok, so=np.array([1, 5, 10])),            # does not start at 0
+        dict(ok, to=np.array([0, 6, 4])),             # decreasing
+        dict(ok, so=np.array([0, 5, 9])),             # does not end at n_src
+        dict(ok, ul=np.array([0, 2])),                # leaf id out of range
+        dict(ok, ul=np.array([-1, 1])),
+    ]
+    S.P2PPlan(ok["so"], ok["to"], ok["uo"], ok["ul"], 10, 8)
+    for b in bad:
+        with pytest.raises(C.StokesError) as e:
+            S.P2PPlan(b["so"], b["to"], b["uo"], b["ul"], 10, 8)
+        assert e.value.status == C.EINVAL
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    return W.make_config(4)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_cfg4_sampled_leaves(cfg4, precision):
+    """3,840 cells (2,088,960 points) in the cylinder, octree <= 256 per leaf,
+    lists of 27..60 leaves: one launch over all lists; 48 seeded leaves checked."""
+    print(f"case cfg4 {precision}", flush=True)
+    cells, tree, f = cfg4["cells"], cfg4["tree"], cfg4["f"]
+    ofs, ul = cfg4["ulist_ofs"], cfg4["ulist"]
+    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, ofs, ul, cells.n, cells.n)
+    pos = dev(cells.pos)
+    u = host(S.p2p_leaf(plan, pos, dev(f), dev(cells.weight), pos, src_group=dev(cells.group),
+                        trg_group=dev(cells.group), precision=precision, group_h=dev(cells.group_h)))
+    rng = np.random.default_rng(404)
+    leaves = rng.choice(len(tree.leaf_ofs) - 1, size=48, replace=False)
+    got, ref = [], []
+    for L in leaves:
+        t = np.arange(tree.leaf_ofs[L], tree.leaf_ofs[L + 1])
+        src = np.concatenate([np.arange(tree.leaf_ofs[k], tree.leaf_ofs[k + 1]) for k in ul[ofs[L]:ofs[L + 1]]])
+        ref.append(O.sl(cells.pos[:, src], f[:, src], cells.weight[src], cells.pos[:, t],
+                        src_group=cells.group[src], trg_group=cells.group[t], exclude_same_group=True))
+        got.append(u[:, t])
+    r = assert_close(np.concatenate(got, 1), np.concatenate(ref, 1), TOL[precision], f"cfg4/{precision}")
+    print(f"cfg4 {precision} rel-L2 on 48 leaves {r:.3e}; plan pairs {plan.pairs()}")
