@@ -80,6 +80,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--secondary", action="store_true",
+                    help="also time the other workloads (cfg3 adjoint, cfg4 P2P, cfg5 wall + cells) "
+                         "and report them under 'secondary'")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (HBM byte-counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -96,6 +101,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": nbytes, "calibrate_copy_bytes_written": nbytes,
+                          "launches": 3}), flush=True)
+        return
     t0 = time.time()
     cfg = W.make_config(2)
     cells, f = cfg["cells"], cfg["f"]
@@ -236,7 +251,84 @@ def main():
     if adjoint:
         line["adjoint"] = adjoint
     line["cpu_baseline"] = cpu
+    if args.secondary:
+        line["secondary"] = secondary(S, W, t, timed, log)
     print(json.dumps(line), flush=True)
+
+
+def secondary(S, W, t, timed, log):
+    """Timings of the other workload shapes (not the headline)."""
+    import torch
+
+    out = {}
+    # cfg3: 128 cells, 69,632 points; forward and the fused shared-point adjoint
+    cfg = W.make_config(3)
+    c, f = cfg["cells"], cfg["f"]
+    pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
+    pairs = W.pair_count_direct(c.group, c.group, True)
+    r = {"pairs": pairs}
+    for prec in ("fp64", "mixed"):
+        ms, _, _ = timed(lambda: S.sl(pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=prec,
+                                      group_h=gh), 10, 2)
+        r[f"{prec}_ms"] = ms
+        r[f"{prec}_pairs_per_s"] = pairs / (ms * 1e-3)
+    g = t(np.random.default_rng(3).standard_normal((3, c.n)))
+    gf, gx = torch.empty_like(ft), torch.empty_like(pos)
+    ms, _, _ = timed(lambda: S.sl_vjp(pos, ft, wt, pos, g, src_group=grp, trg_group=grp, grad_f=gf,
+                                      grad_src=gx, grad_trg=gx), 5, 1)
+    r["adjoint_ms"] = ms
+    r["adjoint_over_fp64_forward"] = ms / r["fp64_ms"]
+    out["cfg3_128_cells_sl_and_adjoint"] = r
+    log(f"secondary cfg3: {r}")
+    # cfg4: leaf-to-leaf sums over 27..60-leaf lists, one launch
+    cfg = W.make_config(4)
+    c, tree, f = cfg["cells"], cfg["tree"], cfg["f"]
+    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, cfg["ulist_ofs"], cfg["ulist"], c.n, c.n)
+    pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
+    r = {"listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
+    for prec in ("mixed", "fp64"):
+        ms, kms, _ = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
+                                              precision=prec, group_h=gh), 10, 2)
+        r[f"{prec}_ms"] = ms
+        r[f"{prec}_kernel_ms"] = kms
+        r[f"{prec}_listed_pairs_per_s"] = r["listed_pairs"] / (ms * 1e-3)
+    out["cfg4_p2p_3840_cells"] = r
+    log(f"secondary cfg4: {r}")
+    # cfg5: wall double layer onto 960 cells plus the cell single layer; adjoints
+    cfg = W.make_config(5)
+    wall, c = cfg["wall"], cfg["cells"]
+    wp, wphi, ww, wn, wg, wh = (t(wall.pos), t(cfg["phi"]), t(wall.weight), t(wall.normal),
+                                t(wall.group), t(wall.group_h))
+    cp, cf, cw, cg, ch = t(c.pos), t(cfg["f"]), t(c.weight), t(c.group), t(c.group_h)
+    dl_pairs = wall.n * c.n
+    sl_pairs = W.pair_count_direct(c.group, c.group, True)
+    r = {"dl_pairs": dl_pairs, "sl_pairs": sl_pairs}
+    for prec in ("mixed", "fp64"):
+        u = torch.empty((3, c.n), dtype=torch.float64, device=cp.device)
+
+        def both():
+            S.dl(wp, wphi, ww, wn, cp, src_group=wg, precision=prec, group_h=wh,
+                 exclude_same_group=False, out=u)
+            S.sl(cp, cf, cw, cp, src_group=cg, trg_group=cg, precision=prec, group_h=ch, out=u,
+                 accumulate=True)
+
+        ms, _, _ = timed(both, 3, 1)
+        r[f"{prec}_forward_ms"] = ms
+        r[f"{prec}_pairs_per_s"] = (dl_pairs + sl_pairs) / (ms * 1e-3)
+    g = t(np.random.default_rng(5).standard_normal((3, c.n)))
+    gphi, gxd, gfc, gxc = (torch.empty_like(wphi), torch.empty_like(cp), torch.empty_like(cf),
+                           torch.empty_like(cp))
+
+    def adj():
+        S.dl_vjp(wp, wphi, ww, wn, cp, g, grad_phi=gphi, grad_trg=gxd)
+        S.sl_vjp(cp, cf, cw, cp, g, src_group=cg, trg_group=cg, grad_f=gfc, grad_src=gxc, grad_trg=gxc)
+
+    ms, _, _ = timed(adj, 2, 1)
+    r["adjoint_ms"] = ms
+    r["adjoint_over_fp64_forward"] = ms / r["fp64_forward_ms"]
+    out["cfg5_wall_and_cells"] = r
+    log(f"secondary cfg5: {r}")
+    return out
 
 
 if __name__ == "__main__":

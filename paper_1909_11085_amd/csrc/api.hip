@@ -19,7 +19,7 @@ struct stokes_ctx {
     int clock_khz;
     int forced_grid;             // 0 = resident workgroup count
     int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
-    int vjp_resident[5];         // resident workgroups of the adjoint pass kernels
+    int vjp_resident[stokes::kVjpPasses];   // resident workgroups of the adjoint pass kernels
     char arch[64];
     // benchmark timing (see stokes_timing_enable)
     bool timing = false;

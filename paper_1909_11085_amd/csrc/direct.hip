@@ -408,7 +408,6 @@ __global__ __launch_bounds__(kBlock, STOKES_DIRECT_W64) void direct_f64(DirectAr
     for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
 
     int64_t ub = u0 / C, c = u0 % C;           // unit position, advanced incrementally
-    Rec pre = rec[c * kTile + threadIdx.x];
     for (int64_t u = u0; u < u1; ++u) {
         __syncthreads();                       // previous step's readers are done
         if (ub != tbk) {
@@ -420,11 +419,10 @@ __global__ __launch_bounds__(kBlock, STOKES_DIRECT_W64) void direct_f64(DirectAr
 #pragma unroll
             for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
         }
-        s_rec[threadIdx.x] = pre;
+        s_rec[threadIdx.x] = rec[c * kTile + threadIdx.x];
         __syncthreads();
         int64_t cn = c + 1, ubn = ub;
         if (cn == C) { cn = 0; ++ubn; }
-        if (u + 1 < u1) pre = rec[cn * kTile + threadIdx.x];
         if (wave_active) {
             uint32_t flags = 0;
 #pragma unroll 1

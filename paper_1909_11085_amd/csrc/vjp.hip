@@ -15,7 +15,8 @@
 //     dL/dphi_m = d w_m sum_n r_nm (r_nm.n_m)(r_nm.g_n)/rho^5
 //     dL/dy_m   = -d sum_n G(r_nm)              (G even)
 // Source-side gradients are transposed passes: the forward's sources act as
-// targets and its targets (carrying g) as sources.  For a shared point set
+// targets and its targets (carrying g) as sources; when only the density
+// gradient is asked for, a lighter pass skips the position terms.  For a shared point set
 // with one combined position gradient, a single fused pass gives
 // dL/dx_p = c sum_m [K(r_pm; g_p, q_m) + K(r_pm; q_p, g_m)] and dL/df_p.
 #include <algorithm>
@@ -338,32 +339,95 @@ struct DlS {
     }
 };
 
+// ---- single layer, source side, density gradient only: dL/df_m ---------------
+// as SlS without the position terms
+struct SlSF {
+    using Rec = SlS::Rec;
+    static constexpr int NACC = 3, NT = 1;
+    __device__ static void make_rec(const PassArgs& a, int64_t i, Rec& r, double pos[3]) {
+        SlS::make_rec(a, i, r, pos);
+    }
+    __device__ static void pad_rec(Rec& r) { SlS::pad_rec(r); }
+    __device__ static void load_t(const PassArgs&, int64_t, double (&v)[NT]) { v[0] = 0.0; }
+    template <bool M>
+    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&)[NT],
+                                bool skip, double (&acc)[NACC]) {
+        const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
+        const double r2 = dot3(dx, dy, dz, dx, dy, dz);
+        const double ri = ri_of<M>(r2, skip);
+        const double sa = dot3(dx, dy, dz, s.gx, s.gy, s.gz) * (ri * ri * ri);
+        acc[0] = __builtin_fma(s.gx, ri, __builtin_fma(sa, dx, acc[0]));
+        acc[1] = __builtin_fma(s.gy, ri, __builtin_fma(sa, dy, acc[1]));
+        acc[2] = __builtin_fma(s.gz, ri, __builtin_fma(sa, dz, acc[2]));
+    }
+    __device__ static void store(const PassArgs& a, int64_t i, const double (&s)[NACC]) {
+        out3(a, a.out[0], a.n_trg, i, a.pref * a.tv[1][i], s[0], s[1], s[2]);
+    }
+};
+
+// ---- double layer, source side, density gradient only: dL/dphi_m -------------
+struct DlSPhi {
+    using Rec = DlS::Rec;
+    static constexpr int NACC = 3, NT = 3;   // NT: n_m
+    __device__ static void make_rec(const PassArgs& a, int64_t i, Rec& r, double pos[3]) {
+        DlS::make_rec(a, i, r, pos);
+    }
+    __device__ static void pad_rec(Rec& r) { DlS::pad_rec(r); }
+    __device__ static void load_t(const PassArgs& a, int64_t i, double (&v)[NT]) {
+        const int64_t n = a.n_trg;
+        v[0] = a.tv[2][i]; v[1] = a.tv[2][n + i]; v[2] = a.tv[2][2 * n + i];
+    }
+    template <bool M>
+    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&nv)[NT],
+                                bool skip, double (&acc)[NACC]) {
+        const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
+        const double r2 = dot3(dx, dy, dz, dx, dy, dz);
+        const double ri = ri_of<M>(r2, skip);
+        const double ri2 = ri * ri;
+        const double rn = dot3(dx, dy, dz, nv[0], nv[1], nv[2]);
+        const double rg = dot3(dx, dy, dz, s.gx, s.gy, s.gz);
+        const double c1 = rn * rg * (ri2 * ri2 * ri);
+        acc[0] = __builtin_fma(c1, dx, acc[0]);
+        acc[1] = __builtin_fma(c1, dy, acc[1]);
+        acc[2] = __builtin_fma(c1, dz, acc[2]);
+    }
+    __device__ static void store(const PassArgs& a, int64_t i, const double (&s)[NACC]) {
+        out3(a, a.out[0], a.n_trg, i, -a.pref * a.tv[1][i], s[0], s[1], s[2]);
+    }
+};
+
 // launch shapes (targets per lane, minimum waves per SIMD)
 constexpr int kTSlT = 4, kWSlT = 3;
 constexpr int kTSlS = 2, kWSlS = 4;
 constexpr int kTSym = 2, kWSym = 3;
 constexpr int kTDlT = 4, kWDlT = 3;
 constexpr int kTDlS = 2, kWDlS = 3;
+constexpr int kTSlSF = 4, kWSlSF = 4;
+constexpr int kTDlSPhi = 4, kWDlSPhi = 4;
 
 }  // namespace
 
-void vjp_resident(int n_cu, int out[5]) {
+void vjp_resident(int n_cu, int out[kVjpPasses]) {
     out[0] = ps::resident_blocks<SlT, kTSlT, kWSlT>(n_cu);
     out[1] = ps::resident_blocks<SlS, kTSlS, kWSlS>(n_cu);
     out[2] = ps::resident_blocks<SlSym, kTSym, kWSym>(n_cu);
     out[3] = ps::resident_blocks<DlT, kTDlT, kWDlT>(n_cu);
     out[4] = ps::resident_blocks<DlS, kTDlS, kWDlS>(n_cu);
+    out[5] = ps::resident_blocks<SlSF, kTSlSF, kWSlSF>(n_cu);
+    out[6] = ps::resident_blocks<DlSPhi, kTDlSPhi, kWDlSPhi>(n_cu);
 }
 
-size_t vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, const int resident[5]) {
+size_t vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, const int resident[kVjpPasses]) {
     if (n_src <= 0 || n_trg <= 0) return 0;
     if (kernel == 0) {
         size_t b = ps::plan_pass<SlT, kTSlT>(n_src, n_trg, resident[0]).total;
         b = std::max(b, ps::plan_pass<SlS, kTSlS>(n_trg, n_src, resident[1]).total);
+        b = std::max(b, ps::plan_pass<SlSF, kTSlSF>(n_trg, n_src, resident[5]).total);
         if (n_src == n_trg) b = std::max(b, ps::plan_pass<SlSym, kTSym>(n_src, n_trg, resident[2]).total);
         return b;
     }
     size_t b = ps::plan_pass<DlT, kTDlT>(n_src, n_trg, resident[3]).total;
+    b = std::max(b, ps::plan_pass<DlSPhi, kTDlSPhi>(n_trg, n_src, resident[6]).total);
     return std::max(b, ps::plan_pass<DlS, kTDlS>(n_trg, n_src, resident[4]).total);
 }
 
@@ -374,7 +438,7 @@ static PassArgs base_args(const VjpInputs& in) {
     return a;
 }
 
-hipError_t launch_sl_vjp(const VjpInputs& in, const int resident[5], bool fused, void* ws,
+hipError_t launch_sl_vjp(const VjpInputs& in, const int resident[kVjpPasses], bool fused, void* ws,
                          hipStream_t stream) {
     hipError_t e = hipSuccess;
     const KernelTimer none{};
@@ -423,13 +487,19 @@ hipError_t launch_sl_vjp(const VjpInputs& in, const int resident[5], bool fused,
         a.out[0] = in.grad_density;
         a.out[1] = in.grad_src;
         a.pref = in.pref;
-        const auto p = ps::plan_pass<SlS, kTSlS>(in.n_trg, in.n_src, resident[1]);
-        e = ps::run_pass<SlS, kTSlS, kWSlS>(a, p, ws, stream, none);
+        if (in.grad_src) {
+            const auto p = ps::plan_pass<SlS, kTSlS>(in.n_trg, in.n_src, resident[1]);
+            e = ps::run_pass<SlS, kTSlS, kWSlS>(a, p, ws, stream, none);
+        } else {
+            const auto p = ps::plan_pass<SlSF, kTSlSF>(in.n_trg, in.n_src, resident[5]);
+            e = ps::run_pass<SlSF, kTSlSF, kWSlSF>(a, p, ws, stream, none);
+        }
     }
     return e;
 }
 
-hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[5], void* ws, hipStream_t stream) {
+hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], void* ws,
+                         hipStream_t stream) {
     hipError_t e = hipSuccess;
     const KernelTimer none{};
     if (in.grad_trg) {
@@ -465,8 +535,13 @@ hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[5], void* ws, h
         a.out[0] = in.grad_density;
         a.out[1] = in.grad_src;
         a.pref = in.pref;
-        const auto p = ps::plan_pass<DlS, kTDlS>(in.n_trg, in.n_src, resident[4]);
-        e = ps::run_pass<DlS, kTDlS, kWDlS>(a, p, ws, stream, none);
+        if (in.grad_src) {
+            const auto p = ps::plan_pass<DlS, kTDlS>(in.n_trg, in.n_src, resident[4]);
+            e = ps::run_pass<DlS, kTDlS, kWDlS>(a, p, ws, stream, none);
+        } else {
+            const auto p = ps::plan_pass<DlSPhi, kTDlSPhi>(in.n_trg, in.n_src, resident[6]);
+            e = ps::run_pass<DlSPhi, kTDlSPhi, kWDlSPhi>(a, p, ws, stream, none);
+        }
     }
     return e;
 }

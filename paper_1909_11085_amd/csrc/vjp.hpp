@@ -22,18 +22,21 @@ struct VjpInputs {
     double* grad_trg;          // (3, n_trg) or null
 };
 
-// Resident workgroups of the five adjoint pass kernels on a device with
-// n_cu compute units (current device).
-void vjp_resident(int n_cu, int out[5]);
+constexpr int kVjpPasses = 7;
+
+// Resident workgroups of the adjoint pass kernels on a device with n_cu
+// compute units (current device).
+void vjp_resident(int n_cu, int out[kVjpPasses]);
 
 // Workspace bytes of an adjoint call (kernel 0 = single, 1 = double layer):
 // the largest of the passes it may run (passes run one after another).
-size_t vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, const int resident[5]);
+size_t vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, const int resident[kVjpPasses]);
 
 // fused: shared point set with one combined position gradient (grad_src ==
 // grad_trg), one pass.  Requires n_src, n_trg > 0.
-hipError_t launch_sl_vjp(const VjpInputs& in, const int resident[5], bool fused, void* ws,
+hipError_t launch_sl_vjp(const VjpInputs& in, const int resident[kVjpPasses], bool fused, void* ws,
                          hipStream_t stream);
-hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[5], void* ws, hipStream_t stream);
+hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], void* ws,
+                         hipStream_t stream);
 
 }  // namespace stokes

@@ -232,3 +232,23 @@ def test_cfg5_wall_adjoint_sampled():
     r1 = assert_close(host(gt)[:, it], rt, VJP_TOL, "cfg5 dL/dx")
     r2 = assert_close(host(gp)[:, iw], rp, VJP_TOL, "cfg5 dL/dphi")
     print(f"cfg5 DL adjoint rel-L2: dL/dx {r1:.3e}, dL/dphi {r2:.3e}")
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_density_gradient_only(kernel):
+    """Asking only for the density gradient takes the lighter source pass."""
+    c = _cloud(21, 2000, 1500)
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal((3, 1500))
+    gd = _z(2000)
+    if kernel == "sl":
+        S.sl_vjp(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["x"]), dev(g), mu=0.7,
+                 src_group=dev(c["gs"]), trg_group=dev(c["gt"]), grad_f=gd)
+        ref = O.sl_vjp(c["y"], c["f"], c["w"], c["x"], g, mu=0.7, src_group=c["gs"], trg_group=c["gt"],
+                       exclude_same_group=True, want=("f",))[0]
+    else:
+        S.dl_vjp(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["n"]), dev(c["x"]), dev(g),
+                 src_group=dev(c["gs"]), trg_group=dev(c["gt"]), grad_phi=gd)
+        ref = O.dl_vjp(c["y"], c["f"], c["w"], c["n"], c["x"], g, src_group=c["gs"], trg_group=c["gt"],
+                       exclude_same_group=True, want=("phi",))[0]
+    assert_close(host(gd), ref, VJP_TOL, f"{kernel} density-only")
