@@ -38,7 +38,7 @@ METRIC = "Stokes pair-interactions/s (FP64 vs mixed FP32) at stated rel-L2 error
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 FLOPS_PER_PAIR_SL = 29
 FLOPS_PER_PAIR_SL_VJP = 95
-KERNEL_NAMES = {"fp64": "direct_f64<SL,T=4>", "mixed": "direct_mixed<SL,T=4>"}
+KERNEL_NAMES = {"fp64": "direct_f64<SL,T=4>", "mixed": "direct_mixed<SL,T=2>"}
 PROFILE_TRAFFIC = {"fp64": "direct_f64_sl_cfg2_traffic.txt", "mixed": "direct_mixed_sl_cfg2_traffic.txt"}
 
 
@@ -47,10 +47,15 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the direct-sum kernel sources without comments and whitespace,
+    so that counters taken on the same code stay valid across comment edits."""
     h = hashlib.sha256()
     for f in ("direct.hip", "common.hpp"):
-        with open(os.path.join(ROOT, "paper_1909_11085_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1909_11085_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -89,8 +94,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
-              "this build has no multi-GPU path; see DESIGN.md for how it would shard.",
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE={world}). "
+              "The library has no multi-GPU path: a sharded run would split the targets across "
+              "GPUs after one all-gather of the packed sources, with no reduction of outputs.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -4,7 +4,7 @@
  * The library sums the two Stokes kernels of the boundary-integral red-blood-
  * cell flow method of Lu, Morse, Rahimian, Stadler and Zorin (SC'19):
  *
- *   single layer (Stokeslet), eq. (sl_stokes), Sec. 3.1.1:
+ *   single layer (Stokeslet), eq. (sl_stokes), Sec. 2.1.1:
  *     u(x_n) = 1/(8 pi mu) sum_m' [ q_m/rho + r (r.q_m)/rho^3 ]
  *   double layer (stresslet), stated after eq. (double_layer_int_eq):
  *     u(x_n) = 6/(8 pi)    sum_m' r (r.n_m)(r.q_m)/rho^5
@@ -15,7 +15,7 @@
  * (smooth_double_layer_int_eq_patches_disc)).  sum_m' skips
  *   - pairs whose source and target carry the same group id when the
  *     same-group rule is on: the "other cells only" sum of the explicit time
- *     step (Sec. 3.2, step 1d, j != i);
+ *     step (Sec. 2.2, step 1(d), j != i);
  *   - pairs at distance 0 (always).
  *
  * Layout.  Every 3-vector field over N points is structure-of-arrays float64:
@@ -173,7 +173,7 @@ int stokes_dl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const 
                    const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,
                    double* vel_out, void* workspace, size_t ws_bytes, void* stream);
 
-/* ---- leaf-to-leaf (P2P) form of the FMM near field, Sec. 3.4 ------------- */
+/* ---- leaf-to-leaf (P2P) form of the FMM near field, Sec. 3.1 ------------- */
 
 /* Builds a leaf layout on the context's device from HOST arrays, validating
  * them: src_leaf_ofs and trg_leaf_ofs (n_leaves+1 int64 each) must start at

@@ -7,7 +7,7 @@
  * header or constant with the GPU library.
  *
  * What it computes (Lu, Morse, Rahimian, Stadler, Zorin, SC'19):
- *   - single-layer (Stokeslet) potential, eq. (sl_stokes) of Sec. 3.1.1:
+ *   - single-layer (Stokeslet) potential, eq. (sl_stokes) of Sec. 2.1.1:
  *       S(x,y) f = 1/(8 pi mu) * ( f/|r| + r (r.f)/|r|^3 ),  r = x - y
  *   - double-layer (stresslet) kernel, after eq. (double_layer_int_eq):
  *       D(x,y) phi = 6/(8 pi) * r (r.n(y)) (r.phi)/|r|^5,  n = source normal
@@ -15,11 +15,11 @@
  *     (smooth_double_layer_int_eq_patches_disc): the kernel times the
  *     quadrature weight w_l times the density at node l, summed over nodes;
  *     the same form is used for the single layer over cell surfaces.
- *   - the "other cells only" rule of the explicit step (Sec. 3.2, step 1d:
+ *   - the "other cells only" rule of the explicit step (Sec. 2.2, step 1(d):
  *     sum over j != i): a pair whose source and target carry the same group
  *     id is skipped when the same-group rule is on.  A pair at distance 0 is
  *     always skipped (reading of a case the paper leaves open).
- *   - the near-field (leaf-to-leaf) form of the FMM evaluation of Sec. 3.4
+ *   - the near-field (leaf-to-leaf) form of the FMM evaluation of Sec. 3.1
  *     ("Far evaluation"): each target leaf sums over the sources of the
  *     leaves in its interaction list only.
  *   - vector-Jacobian products of these sums, obtained by differentiating

@@ -11,7 +11,7 @@ over N points has shape (3, N).  Group ids are int32 of shape (N,).
 The sums follow the paper's single-layer potential (eq. sl_stokes), its
 double-layer kernel (after eq. double_layer_int_eq), the smooth N-body
 quadrature (eq. smooth_double_layer_int_eq_patches_disc) and the "other cells
-only" rule of the explicit time step (Sec. 3.2, step 1d).  See ``oracle.c``
+only" rule of the explicit time step (Sec. 2.2, step 1(d)).  See ``oracle.c``
 for the formulas.
 """
 from __future__ import annotations

@@ -3,7 +3,7 @@
 A second, independent transcription of the same definitions (single layer,
 eq. sl_stokes; double layer, after eq. double_layer_int_eq; weights times
 densities, eq. smooth_double_layer_int_eq_patches_disc; the "other cells only"
-rule of Sec. 3.2, step 1d), written over dense (targets x sources) arrays.
+rule of Sec. 2.2, step 1(d)), written over dense (targets x sources) arrays.
 It exists to cross-check the C oracle's array layout and loop bounds on inputs
 of at most a few hundred points; it is not a pin by itself.
 """

@@ -3,7 +3,7 @@
 // Single layer (Stokeslet, paper eq. sl_stokes) and double layer (stresslet,
 // stated after eq. double_layer_int_eq), summed over the smooth quadrature of
 // eq. smooth_double_layer_int_eq_patches_disc (strength q = w * density),
-// with the "other cells only" rule of the explicit step (Sec. 3.2, step 1d)
+// with the "other cells only" rule of the explicit step (Sec. 2.2, step 1(d))
 // and distance-0 pairs skipped.
 //
 // Design (CDNA4, wave64):

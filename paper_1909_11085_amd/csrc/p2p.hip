@@ -1,5 +1,5 @@
 // Leaf-to-leaf (P2P) sums: the near-field part of the FMM evaluation of the
-// paper's Sec. 3.4 ("Far evaluation"), where every target leaf sums the
+// paper's Sec. 3.1 ("Far evaluation"), where every target leaf sums the
 // single- or double-layer kernel over the sources of the leaves in its
 // interaction list, in one launch over all the (uneven) lists.
 //

@@ -6,15 +6,15 @@ and interaction lists.  It holds none of the kernel-sum arithmetic, and both
 the HIP library's tests and the CPU oracle's tests draw their inputs from it.
 
 Shapes follow the paper's workloads:
-  * red blood cells sampled at 544 quadrature points each (Sec. 5 setup:
+  * red blood cells sampled at 544 quadrature points each (Sec. 5.1 setup:
     spherical-harmonic order 16), here an Evans-Fung biconcave surface on a
     17 x 32 Gauss-Legendre(cos theta) x uniform(phi) grid;
   * vessel-wall tensor-product polynomial patches with a tensor-product
-    quadrature rule on each patch (Sec. 3.4), here an open straight cylinder
+    quadrature rule on each patch (Sec. 3.1), here an open straight cylinder
     split into 64 x 64 patches of 16 x 16 Gauss-Legendre nodes;
-  * cells at random orientation (Sec. 6, "filling the vessel"), here uniform
+  * cells at random orientation (Sec. 5.1, "filling the vessel"), here uniform
     on SO(3), placed by random sequential addition of disjoint bounding spheres;
-  * the FMM near field (Sec. 3.4, "Far evaluation"): an adaptive octree with
+  * the FMM near field (Sec. 3.1, "Far evaluation"): an adaptive octree with
     at most 256 points per leaf and a per-leaf interaction list.
 
 Arrays are structure-of-arrays float64 of shape (3, N); group ids int32.
