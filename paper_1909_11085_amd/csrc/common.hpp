@@ -32,11 +32,14 @@ struct alignas(16) SubMeta {
 // Strength q = w * density is formed by the prep kernel.
 struct alignas(16) SrcSL64 { double x, y, z, qx, qy, qz; };                       // 48 B
 struct alignas(16) SrcDL64 { double x, y, z, qx, qy, qz, nx, ny, nz, pad; };      // 80 B
+// Direct FP64 single layer: positions stored doubled (2y, exact) and both q and
+// 4q, so that the pair needs no constant multiplies (see direct.hip).
+struct alignas(16) SrcSL64x { double x, y, z, qx, qy, qz, q4x, q4y, q4z, pad; };  // 80 B
 struct alignas(16) SrcSL32 { float ox, oy, oz, qx, qy, qz, t2; int32_t g; };      // 32 B
 struct alignas(16) SrcDL32 { float ox, oy, oz, qx, qy, qz, nx, ny, nz, t2; int32_t g; float pad; }; // 48 B
 
 template <int KT, int MIXED> struct SrcRec;
-template <> struct SrcRec<0, 0> { using type = SrcSL64; };
+template <> struct SrcRec<0, 0> { using type = SrcSL64x; };
 template <> struct SrcRec<1, 0> { using type = SrcDL64; };
 template <> struct SrcRec<0, 1> { using type = SrcSL32; };
 template <> struct SrcRec<1, 1> { using type = SrcDL32; };

@@ -63,17 +63,14 @@ __device__ __forceinline__ int wave_maxi(int v) {
     return v;
 }
 
-// 1/sqrt(r2) in float64: hardware estimate (about 24 correct bits, measured)
-// plus one Newton step y <- y + y (1 - r2 y^2)/2, leaving ~1e-15 relative.
-__device__ __forceinline__ double rsqrt_nr(double r2) {
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double e = __builtin_fma(-r2, y0 * y0, 1.0);
-    return __builtin_fma(0.5 * y0, e, y0);
-}
-__device__ __forceinline__ double rsqrt_nr_masked(double r2, bool skip) {
-    const double y0 = skip ? 0.0 : __builtin_amdgcn_rsq(r2);
-    const double e = __builtin_fma(-r2, y0 * y0, 1.0);
-    return __builtin_fma(0.5 * y0, e, y0);
+// 1/rho in float64 from A = 4 rho^2 (coordinates stored doubled, exactly):
+// hardware estimate z ~ 1/sqrt(A) = 1/(2 rho) (about 24 correct bits,
+// measured) and one Newton step, written as z (3 - A z^2) = 2 z (1.5 - A z^2/2)
+// so that the factor 2 comes for free: three operations, ~1e-15 relative.
+__device__ __forceinline__ double rinv_doubled(double A, bool skip) {
+    const double z = skip ? 0.0 : __builtin_amdgcn_rsq(A);
+    const double t = A * z;
+    return z * __builtin_fma(-t, z, 3.0);
 }
 
 struct DirectArgs {
@@ -110,6 +107,9 @@ __global__ __launch_bounds__(kBlock) void prep_sources(SumInputs in, void* rec_o
             q[c] = w * in.density[c * n + i];
             if (KT == 1) nv[c] = in.normal[c * n + i];
         }
+        if (MIXED == 0) {   // FP64 records hold doubled positions (exact)
+            y[0] *= 2.0; y[1] *= 2.0; y[2] *= 2.0;
+        }
         g = in.src_group ? in.src_group[i] : 0;
         if (MIXED && in.group_h) {
             if (g >= 0 && g < in.n_groups) {
@@ -138,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void prep_sources(SumInputs in, void* rec_o
         Rec r;
         r.x = y[0]; r.y = y[1]; r.z = y[2];
         r.qx = q[0]; r.qy = q[1]; r.qz = q[2];
+        if constexpr (KT == 0) { r.q4x = 4.0 * q[0]; r.q4y = 4.0 * q[1]; r.q4z = 4.0 * q[2]; r.pad = 0.0; }
         if constexpr (KT == 1) { r.nx = nv[0]; r.ny = nv[1]; r.nz = nv[2]; r.pad = 0.0; }
         rec[i] = r;
         reinterpret_cast<int32_t*>(aux_out)[i] = g;
@@ -309,29 +310,49 @@ __device__ __forceinline__ void flush_segment(const DirectArgs& a, int64_t tbk, 
 // ---------------------------------------------------------------------------
 // FP64 pair kernels (bare, without prefactor)
 // ---------------------------------------------------------------------------
+// Both points come in doubled, r' = 2r, and ri = 1/rho (see rinv_doubled):
+//   single layer: (4q + r' (r'.q)/rho^2)/rho = 4 [q/rho + r (r.q)/rho^3]
+//   double layer: r' (r'.n)(r'.q)/rho^5     = 8 r (r.n)(r.q)/rho^5
+// The factors 4 and 8 are divided out of the prefactor after the sum.
 template <int KT, bool MASKED>
 __device__ __forceinline__ void pair_f64(const typename SrcRec<KT, 0>::type& s, double x, double y,
                                          double z, bool skip_group, double& ax, double& ay,
                                          double& az) {
     const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
-    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-    const double ri = MASKED ? rsqrt_nr_masked(r2, skip_group || r2 == 0.0) : rsqrt_nr(r2);
+    const double A = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+    const double ri = rinv_doubled(A, MASKED && (skip_group || A == 0.0));
     const double ri2 = ri * ri;
     const double rq = __builtin_fma(dx, s.qx, __builtin_fma(dy, s.qy, dz * s.qz));
     if constexpr (KT == 0) {
-        // q/rho + r (r.q)/rho^3 = (q + r (r.q)/rho^2) / rho
         const double c = rq * ri2;
-        ax = __builtin_fma(__builtin_fma(c, dx, s.qx), ri, ax);
-        ay = __builtin_fma(__builtin_fma(c, dy, s.qy), ri, ay);
-        az = __builtin_fma(__builtin_fma(c, dz, s.qz), ri, az);
+        ax = __builtin_fma(__builtin_fma(c, dx, s.q4x), ri, ax);
+        ay = __builtin_fma(__builtin_fma(c, dy, s.q4y), ri, ay);
+        az = __builtin_fma(__builtin_fma(c, dz, s.q4z), ri, az);
     } else {
-        // r (r.n)(r.q)/rho^5
         const double rn = __builtin_fma(dx, s.nx, __builtin_fma(dy, s.ny, dz * s.nz));
-        const double ri5 = ri2 * ri2 * ri;
-        const double c = rn * rq * ri5;
+        const double c = rn * rq * (ri2 * ri2 * ri);
         ax = __builtin_fma(c, dx, ax);
         ay = __builtin_fma(c, dy, ay);
         az = __builtin_fma(c, dz, az);
+    }
+}
+
+// Doubles a wave's target coordinates and box (exact), to match the FP64
+// source records.
+template <int T>
+__device__ __forceinline__ void double_targets(Targets<T>& t, Box* w) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        t.x[k] *= 2.0;
+        t.y[k] *= 2.0;
+        t.z[k] *= 2.0;
+    }
+    if (w) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            w->lo[c] *= 2.0;
+            w->hi[c] *= 2.0;
+        }
     }
 }
 
@@ -416,6 +437,7 @@ __global__ __launch_bounds__(kBlock, STOKES_DIRECT_W64) void direct_f64(DirectAr
             const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
             wave_active = tb < a.in.n_trg;
             wbox = load_targets<T>(a.in, wave_active ? tb : 0, lane, t);
+            double_targets<T>(t, &wbox);
 #pragma unroll
             for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
         }
@@ -466,6 +488,7 @@ __global__ __launch_bounds__(kBlock) void direct_near_f64(DirectArgs a) {
     const int32_t* grp = reinterpret_cast<const int32_t*>(a.aux);
     Targets<T> t;
     (void)load_targets<T>(a.in, tb, lane, t);
+    double_targets<T>(t, nullptr);
     double ax[T], ay[T], az[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
@@ -754,7 +777,7 @@ constexpr int kT64 = STOKES_DIRECT_T64;
 constexpr int kT32 = STOKES_DIRECT_T32;
 
 static size_t rec_bytes(int kernel, int mixed) {
-    if (!mixed) return kernel == 0 ? sizeof(SrcSL64) : sizeof(SrcDL64);
+    if (!mixed) return kernel == 0 ? sizeof(SrcSL64x) : sizeof(SrcDL64);
     return kernel == 0 ? sizeof(SrcSL32) : sizeof(SrcDL32);
 }
 
@@ -835,9 +858,11 @@ static hipError_t launch_typed(const SumInputs& in, const DirectPlan& p, double*
         direct_near_f64<KT, T><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // FP64 pair sums are 4x (single layer) or 8x (double layer) the bare sums
+    const double pref = MIXED ? in.pref : (KT == 0 ? 0.25 : 0.125) * in.pref;
     reduce_segments<T><<<dim3((unsigned)ceil_div(in.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(
         a.part, a.near_part, in.n_trg, p.units, p.chunks, p.grid, p.blocks_x * (int64_t)kBlock * T,
-        in.pref, out, accumulate);
+        pref, out, accumulate);
     return hipGetLastError();
 }
 
