@@ -5,17 +5,23 @@
 //
 // Design (gfx950):
 //   * plan (host, once per leaf layout): validates the leaf CSR arrays, cuts
-//     each target leaf into 64-target work items, sorts the items by pair
-//     count (largest first, for balance) and uploads layout and items.
-//   * prep (one wave per leaf, per evaluation): the leaf's box centre, then a
-//     packed record per source; mixed precision stores each source's offset
-//     from its leaf centre as a float32 high part and float32 residue.
-//   * sum: one wave per work item; each lane holds one target; the sources of
-//     each listed leaf are staged through LDS (up to 256 at a time) and read
-//     by broadcast.  Every pair goes through the same-group and
-//     zero-distance masks; in mixed precision r = (x_hi - y_hi) + (x_lo - y_lo)
-//     in float32, pairs inside the near radius are evaluated in float64, and
-//     each source leaf's float32 partial is added into float64 accumulators.
+//     each target leaf into 64-target work items, sorts the items by their
+//     estimated cost (largest first, for balance) and uploads layout and items.
+//   * prep (one wave per leaf, per evaluation): the leaf's box centre and
+//     radius, then a packed record per source; mixed precision stores each
+//     source's offset from its leaf centre as a float32 high part and residue.
+//   * sum: one wave per work item.  An item of n <= 64 targets gives each
+//     target R = min(16, 64/n) lanes, and lane phase h takes every R-th source
+//     (so small leaves still fill the wave); the R partial sums are added in a
+//     fixed order at the end.  The sources of each listed leaf are staged
+//     through LDS, up to 128 at a time, and sorted on the way in: a source is
+//     "careful" when its group occurs among the item's targets, or when it
+//     lies within the near limit of the targets' box; all others are "clean".
+//     Clean sources run an unmasked loop (float32 offsets in mixed precision,
+//     exactly as the direct sums' fast path); careful sources go through the
+//     same-group and zero-distance masks, and in mixed precision through
+//     r = (x_hi - y_hi) + (x_lo - y_lo) with pairs inside the near radius
+//     evaluated in float64.
 #include <float.h>
 #include <limits.h>
 
@@ -42,13 +48,16 @@ struct stokes_p2p_plan {
 namespace stokes {
 namespace {
 
-constexpr int kP2PTile = 256;   // sources staged per LDS step
+constexpr int kP2PTile = 128;    // sources staged per LDS step
+constexpr int kMaxRep = 16;      // lanes per target at most
+constexpr int kMaxTGroups = 8;   // distinct target groups tracked per item
 
-struct alignas(16) P2PSL32 { float hx, hy, hz, lx, ly, lz, qx, qy, qz, t2; int32_t g; float pad; };
+// src: the source's index within its leaf (staging reorders sources)
+struct alignas(16) P2PSL32 { float hx, hy, hz, lx, ly, lz, qx, qy, qz, t2; int32_t g, src; };
 struct alignas(16) P2PDL32 {
     float hx, hy, hz, lx, ly, lz, qx, qy, qz, nx, ny, nz, t2;
-    int32_t g;
-    float pad[2];
+    int32_t g, src;
+    float pad;
 };
 
 template <int KT, int MIXED> struct P2PRec;
@@ -66,7 +75,7 @@ struct P2PArgs {
     const int32_t* items;
     void* rec;
     int32_t* grp;
-    double* leaf_ctr;        // (n_leaves, 3)
+    double* leaf_ctr;        // (n_leaves, 4): box centre and half-diagonal
     int32_t n_leaves;
     double* out;
     int accumulate;
@@ -99,15 +108,18 @@ __global__ __launch_bounds__(kWave) void p2p_prep(P2PArgs a) {
             lo[c] = fmin(lo[c], in.src_xyz[c * n + i]);
             hi[c] = fmax(hi[c], in.src_xyz[c * n + i]);
         }
-    double ctr[3];
+    double ctr[3], rad2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double l = wmin(lo[c]), h = wmax(hi[c]);
         ctr[c] = s1 > s0 ? 0.5 * (l + h) : 0.0;
+        if (s1 > s0) rad2 = __builtin_fma(0.5 * (h - l), 0.5 * (h - l), rad2);
     }
-    if (lane == 0)
+    if (lane == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.leaf_ctr[3 * (int64_t)L + c] = ctr[c];
+        for (int c = 0; c < 3; ++c) a.leaf_ctr[4 * (int64_t)L + c] = ctr[c];
+        a.leaf_ctr[4 * (int64_t)L + 3] = sqrt(rad2);
+    }
     for (int64_t i = s0 + lane; i < s1; i += kWave) {
         const double w = in.weight[i];
         double y[3], q[3], nv[3] = {0, 0, 0};
@@ -139,6 +151,7 @@ __global__ __launch_bounds__(kWave) void p2p_prep(P2PArgs a) {
             if constexpr (KT == 1) { r.nx = (float)nv[0]; r.ny = (float)nv[1]; r.nz = (float)nv[2]; }
             r.t2 = (float)(rn * rn);
             r.g = g;
+            r.src = (int32_t)(i - s0);
         }
         reinterpret_cast<Rec*>(a.rec)[i] = r;
     }
@@ -150,12 +163,12 @@ __device__ __forceinline__ double rinv(double r2, bool skip) {
     return __builtin_fma(0.5 * y0, e, y0);
 }
 
-template <int KT>
+template <int KT, bool MASKED>
 __device__ __forceinline__ void pair64(const typename P2PRec<KT, 0>::type& s, double x, double y,
                                        double z, bool skip_group, double& ax, double& ay, double& az) {
     const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-    const double ri = rinv(r2, skip_group || r2 == 0.0);
+    const double ri = rinv(r2, MASKED && (skip_group || r2 == 0.0));
     const double ri2 = ri * ri;
     const double rq = __builtin_fma(dx, s.qx, __builtin_fma(dy, s.qy, dz * s.qz));
     if constexpr (KT == 0) {
@@ -172,57 +185,125 @@ __device__ __forceinline__ void pair64(const typename P2PRec<KT, 0>::type& s, do
     }
 }
 
-// float64 evaluation of one pair from the caller's arrays (near pairs, mixed)
+// float32 pair on offsets from the source leaf's centre (clean sources only:
+// no mask, no residues)
 template <int KT>
-__device__ __noinline__ void near64(const SumInputs& in, int64_t m, double x, double y, double z,
-                                    double& ax, double& ay, double& az) {
-    const int64_t ns = in.n_src;
-    const double dx = x - in.src_xyz[m], dy = y - in.src_xyz[ns + m], dz = z - in.src_xyz[2 * ns + m];
+__device__ __forceinline__ void pair32(const typename P2PRec<KT, 1>::type& s, float xs, float ys,
+                                       float zs, float& bx, float& by, float& bz) {
+    const float dx = xs - s.hx, dy = ys - s.hy, dz = zs - s.hz;
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    const float rq = __builtin_fmaf(dx, s.qx, __builtin_fmaf(dy, s.qy, dz * s.qz));
+    if constexpr (KT == 0) {
+        const float c = rq * ri2;
+        bx = __builtin_fmaf(__builtin_fmaf(c, dx, s.qx), ri, bx);
+        by = __builtin_fmaf(__builtin_fmaf(c, dy, s.qy), ri, by);
+        bz = __builtin_fmaf(__builtin_fmaf(c, dz, s.qz), ri, bz);
+    } else {
+        const float rn = __builtin_fmaf(dx, s.nx, __builtin_fmaf(dy, s.ny, dz * s.nz));
+        const float c = rn * rq * (ri2 * ri2 * ri);
+        bx = __builtin_fmaf(c, dx, bx);
+        by = __builtin_fmaf(c, dy, by);
+        bz = __builtin_fmaf(c, dz, bz);
+    }
+}
+
+// float64 evaluation of one pair from the caller's arrays (near pairs, mixed).
+// Out of line (rarely taken) with every argument and the result in registers.
+struct Vec3 { double x, y, z; };
+template <int KT>
+__device__ __noinline__ Vec3 near64(const double* __restrict__ src_xyz, const double* __restrict__ density,
+                                    const double* __restrict__ weight, const double* __restrict__ normal,
+                                    int64_t ns, int64_t m, double x, double y, double z) {
+    const double dx = x - src_xyz[m], dy = y - src_xyz[ns + m], dz = z - src_xyz[2 * ns + m];
     const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 == 0.0) return;
-    const double w = in.weight[m];
-    const double qx = w * in.density[m], qy = w * in.density[ns + m], qz = w * in.density[2 * ns + m];
+    if (r2 == 0.0) return Vec3{0.0, 0.0, 0.0};
+    const double w = weight[m];
+    const double qx = w * density[m], qy = w * density[ns + m], qz = w * density[2 * ns + m];
     const double ri = 1.0 / sqrt(r2);
     const double rq = dx * qx + dy * qy + dz * qz;
     if constexpr (KT == 0) {
         const double c = rq * ri * ri;
-        ax += (qx + c * dx) * ri;
-        ay += (qy + c * dy) * ri;
-        az += (qz + c * dz) * ri;
+        return Vec3{(qx + c * dx) * ri, (qy + c * dy) * ri, (qz + c * dz) * ri};
     } else {
-        const double rn = dx * in.normal[m] + dy * in.normal[ns + m] + dz * in.normal[2 * ns + m];
+        const double rn = dx * normal[m] + dy * normal[ns + m] + dz * normal[2 * ns + m];
         const double c = rn * rq * (ri * ri) * (ri * ri) * ri;
-        ax += c * dx;
-        ay += c * dy;
-        az += c * dz;
+        return Vec3{c * dx, c * dy, c * dz};
     }
+}
+
+// Record written into the padding of the clean region: far away, zero strength.
+template <typename Rec>
+__device__ __forceinline__ Rec pad_record() {
+    Rec r{};
+    if constexpr (sizeof(r.qx) == 8) {
+        r.x = r.y = r.z = kPadPos;
+    } else {
+        r.hx = r.hy = r.hz = kPadOff;
+    }
+    return r;
+}
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 template <int KT, int MIXED>
 __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     using Rec = typename P2PRec<KT, MIXED>::type;
-    __shared__ Rec s_rec[kP2PTile];
-    __shared__ int32_t s_grp[MIXED ? 1 : kP2PTile];
+    constexpr int kSlots = kP2PTile + kMaxRep;
+    // staged sources: clean ones from the front (padded to a multiple of R),
+    // careful ones from the back
+    __shared__ Rec s_rec[kSlots];
+    __shared__ int32_t s_grp[MIXED ? 1 : kSlots];
+    __shared__ double s_red[3 * kWave];
     const int lane = threadIdx.x;
     const int32_t L = a.items[2 * blockIdx.x], ch = a.items[2 * blockIdx.x + 1];
     const int64_t t0 = a.trg_ofs[L] + (int64_t)ch * kWave;
-    const int64_t t1 = min(a.trg_ofs[L + 1], t0 + kWave);
-    const int64_t idx = t0 + lane;
-    const bool valid = idx < t1;
-    const int64_t ic = valid ? idx : t0;
+    const int nc = (int)min(a.trg_ofs[L + 1] - t0, (int64_t)kWave);   // 1..64 (the plan makes no empty item)
+    const int R = min(kMaxRep, kWave / nc);
+    const int ti = lane / R, h = lane - ti * R;
+    const bool valid = ti < nc;
+    const int64_t idx = t0 + (valid ? ti : 0);        // idle lanes mirror target t0
     const int64_t nt = a.in.n_trg;
-    const double x = a.in.trg_xyz[ic], y = a.in.trg_xyz[nt + ic], z = a.in.trg_xyz[2 * nt + ic];
-    const int32_t tg = a.in.trg_group ? a.in.trg_group[ic] : 0;
+    const double x = a.in.trg_xyz[idx], y = a.in.trg_xyz[nt + idx], z = a.in.trg_xyz[2 * nt + idx];
+    const int32_t tg = a.in.trg_group ? a.in.trg_group[idx] : 0;
     const bool excl = a.in.excl != 0;
+
+    // the item's target box and its distinct target groups (uniform)
+    const double blo[3] = {wmin(x), wmin(y), wmin(z)}, bhi[3] = {wmax(x), wmax(y), wmax(z)};
+    int32_t tgl[kMaxTGroups];
+#pragma unroll
+    for (int q = 0; q < kMaxTGroups; ++q) tgl[q] = 0;
+    int ntg = 0;
+    bool many_groups = false;
+    if (excl) {
+        uint64_t rem = __ballot(1);
+        while (rem) {                                  // each pass removes at least one lane
+            const int first = __builtin_ctzll(rem);
+            const int32_t g0 = __builtin_amdgcn_readlane(tg, first);
+#pragma unroll
+            for (int q = 0; q < kMaxTGroups; ++q)
+                if (q == ntg) tgl[q] = g0;
+            many_groups |= ntg >= kMaxTGroups;
+            ++ntg;
+            rem &= ~__ballot(tg == g0);
+        }
+    }
+    const double sext = fmax(fmax(bhi[0] - blo[0], bhi[1] - blo[1]), bhi[2] - blo[2]);
+
     const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int64_t k = a.ulist_ofs[L]; k < a.ulist_ofs[L + 1]; ++k) {
         const int32_t Ls = a.ulist[k];
         const int64_t s0 = a.src_ofs[Ls], ns = a.src_ofs[Ls + 1] - s0;
+        const double* lc = a.leaf_ctr + 4 * (int64_t)Ls;
+        const double cx = lc[0], cy = lc[1], cz = lc[2], crad = lc[3];
         float xs = 0.f, ys = 0.f, zs = 0.f, xl = 0.f, yl = 0.f, zl = 0.f;
         if constexpr (MIXED != 0) {
-            const double hx = x - a.leaf_ctr[3 * (int64_t)Ls], hy = y - a.leaf_ctr[3 * (int64_t)Ls + 1],
-                         hz = z - a.leaf_ctr[3 * (int64_t)Ls + 2];
+            const double hx = x - cx, hy = y - cy, hz = z - cz;
             xs = (float)hx; ys = (float)hy; zs = (float)hz;
             xl = (float)(hx - (double)xs);
             yl = (float)(hy - (double)ys);
@@ -230,26 +311,88 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
         }
         for (int64_t b = 0; b < ns; b += kP2PTile) {
             const int nb = (int)((ns - b) < kP2PTile ? (ns - b) : kP2PTile);
-            __syncthreads();
-            for (int i = lane; i < nb; i += kWave) {
-                s_rec[i] = rec[s0 + b + i];
-                if constexpr (MIXED == 0) s_grp[i] = a.grp[s0 + b + i];
+            __syncthreads();                           // previous readers are done
+            int n_clean = 0, n_care = 0;
+            for (int i0 = 0; i0 < nb; i0 += kWave) {
+                const int i = i0 + lane;
+                const bool in = i < nb;
+                const int64_t si = s0 + b + (in ? i : 0);     // nb >= 1: index 0 is a real source
+                const Rec r = rec[si];
+                double px, py, pz, lim;
+                int32_t g;
+                if constexpr (MIXED == 0) {
+                    g = a.grp[si];
+                    px = r.x; py = r.y; pz = r.z;
+                    lim = 0.0;                                 // only coincident points need the mask
+                } else {
+                    g = r.g;
+                    px = cx + ((double)r.hx + (double)r.lx);
+                    py = cy + ((double)r.hy + (double)r.ly);
+                    pz = cz + ((double)r.hz + (double)r.lz);
+                    // the near radius with margin, and an eighth of the leaf
+                    // radius, which bounds the float32 offset error on the
+                    // clean path to about 20 ulp per pair
+                    lim = fmax(__builtin_fma(1.001, (double)__builtin_amdgcn_sqrtf(r.t2), 0x1p-20 * sext), 0.125 * crad);
+                }
+                const double gx = fmax(fmax(blo[0] - px, px - bhi[0]), 0.0);
+                const double gy = fmax(fmax(blo[1] - py, py - bhi[1]), 0.0);
+                const double gz = fmax(fmax(blo[2] - pz, pz - bhi[2]), 0.0);
+                const double gap2 = __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz));
+                bool care = !(gap2 > lim * lim) || (MIXED == 0 && gap2 <= 1e-200);
+                if (excl) {
+                    bool hit = many_groups;
+#pragma unroll
+                    for (int q = 0; q < kMaxTGroups; ++q) hit |= (q < ntg) && g == tgl[q];
+                    care |= hit;
+                }
+                const uint64_t mc = __ballot(in && !care), mk = __ballot(in && care);
+                if (in) {
+                    const int pos = care ? kSlots - 1 - (n_care + lanes_below(mk)) : n_clean + lanes_below(mc);
+                    s_rec[pos] = r;
+                    if constexpr (MIXED == 0) s_grp[pos] = g;
+                }
+                n_clean += __popcll(mc);
+                n_care += __popcll(mk);
             }
+            const int n_clean_pad = (n_clean + R - 1) / R * R;
+            if (lane < n_clean_pad - n_clean) s_rec[n_clean + lane] = pad_record<Rec>();
             __syncthreads();
+
+            // clean sources, no masks: phase h takes the h-th of R equal runs
+            const int m_clean = n_clean_pad / R;
+            const Rec* pc = s_rec + h * m_clean;
             if constexpr (MIXED == 0) {
 #pragma unroll 4
-                for (int j = 0; j < nb; ++j)
-                    pair64<KT>(s_rec[j], x, y, z, excl && s_grp[j] == tg, ax, ay, az);
+                for (int j = 0; j < m_clean; ++j) pair64<KT, false>(pc[j], x, y, z, false, ax, ay, az);
             } else {
                 float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll 4
-                for (int j = 0; j < nb; ++j) {
-                    const Rec s = s_rec[j];
+                for (int j = 0; j < m_clean; ++j) pair32<KT>(pc[j], xs, ys, zs, bx, by, bz);
+                ax += (double)bx;
+                ay += (double)by;
+                az += (double)bz;
+            }
+            // careful sources: slots [kSlots - n_care, kSlots), runs of m_care
+            const int cb = kSlots - n_care;
+            const int m_care = (n_care + R - 1) / R;
+            if constexpr (MIXED == 0) {
+                for (int jr = 0; jr < m_care; ++jr) {
+                    const int j = h * m_care + jr;
+                    const bool ok = j < n_care;
+                    const int slot = ok ? cb + j : cb;
+                    pair64<KT, true>(s_rec[slot], x, y, z, !ok || (excl && s_grp[slot] == tg), ax, ay, az);
+                }
+            } else {
+                float bx = 0.f, by = 0.f, bz = 0.f;
+                for (int jr = 0; jr < m_care; ++jr) {
+                    const int j = h * m_care + jr;
+                    const bool ok = j < n_care;
+                    const Rec s = s_rec[ok ? cb + j : cb];
                     const float dx = (xs - s.hx) + (xl - s.lx);
                     const float dy = (ys - s.hy) + (yl - s.ly);
                     const float dz = (zs - s.hz) + (zl - s.lz);
                     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                    const bool excluded = excl && s.g == tg;
+                    const bool excluded = !ok || (excl && s.g == tg);
                     const bool near = r2 <= s.t2;
                     const float ri = (excluded || near) ? 0.0f : __builtin_amdgcn_rsqf(r2);
                     const float ri2 = ri * ri;
@@ -266,7 +409,13 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                         by = __builtin_fmaf(c, dy, by);
                         bz = __builtin_fmaf(c, dz, bz);
                     }
-                    if (near && !excluded) near64<KT>(a.in, s0 + b + j, x, y, z, ax, ay, az);
+                    if (near && !excluded) {
+                        const Vec3 v = near64<KT>(a.in.src_xyz, a.in.density, a.in.weight, a.in.normal,
+                                                  a.in.n_src, s0 + s.src, x, y, z);
+                        ax += v.x;
+                        ay += v.y;
+                        az += v.z;
+                    }
                 }
                 ax += (double)bx;
                 ay += (double)by;
@@ -274,7 +423,22 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
             }
         }
     }
-    if (valid) {
+    // add the R phase partials of each target in a fixed order
+    if (R > 1) {
+        __syncthreads();
+        s_red[lane] = ax;
+        s_red[kWave + lane] = ay;
+        s_red[2 * kWave + lane] = az;
+        __syncthreads();
+        if (valid && h == 0) {                         // lanes ti*R .. ti*R + R - 1 < nc*R <= 64
+            for (int q = 1; q < R; ++q) {
+                ax += s_red[lane + q];
+                ay += s_red[kWave + lane + q];
+                az += s_red[2 * kWave + lane + q];
+            }
+        }
+    }
+    if (valid && h == 0) {
         const double p = a.in.pref;
         if (a.accumulate) {
             a.out[idx] += p * ax;
@@ -305,7 +469,7 @@ P2PLayout p2p_layout(int kernel, int mixed, int64_t n_src, int32_t n_leaves) {
     l.off_grp = off;
     off = align_up(off + (size_t)std::max<int64_t>(n_src, 1) * sizeof(int32_t), 256);
     l.off_ctr = off;
-    off = align_up(off + (size_t)std::max(n_leaves, 1) * 3 * sizeof(double), 256);
+    off = align_up(off + (size_t)std::max(n_leaves, 1) * 4 * sizeof(double), 256);
     l.total = off;
     return l;
 }
@@ -391,7 +555,10 @@ int p2p_plan_build(int device, int32_t n_leaves, int64_t n_src, int64_t n_trg,
         pairs += nt * s;
         for (int64_t c = 0; c * kWave < nt; ++c) {
             if (c > INT32_MAX) { err = "leaf too large"; return STOKES_EUNSUPPORTED; }
-            items.push_back({std::min<int64_t>(kWave, nt - c * kWave) * s + 1, L, (int32_t)c});
+            // the pair loop of an n-target item runs s/R steps, R = min(16, 64/n)
+            const int64_t n_c = std::min<int64_t>(kWave, nt - c * kWave);
+            const int64_t rep = std::min<int64_t>(kMaxRep, kWave / n_c);
+            items.push_back({s * 64 / rep + s + 1, L, (int32_t)c});
         }
     }
     if ((int64_t)items.size() > (int64_t)INT32_MAX) { err = "too many work items"; return STOKES_EUNSUPPORTED; }

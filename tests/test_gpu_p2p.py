@@ -125,3 +125,35 @@ def test_cfg4_sampled_leaves(cfg4, precision):
         got.append(u[:, t])
     r = assert_close(np.concatenate(got, 1), np.concatenate(ref, 1), TOL[precision], f"cfg4/{precision}")
     print(f"cfg4 {precision} rel-L2 on 48 leaves {r:.3e}; plan pairs {plan.pairs()}")
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_p2p_leaf_size_mix(kernel, precision):
+    """Leaves of 1..300 points: every lanes-per-target factor (1..16), leaves
+    spanning several 128-source staging tiles, items with more than 8 distinct
+    target groups, and near pairs across leaves."""
+    print(f"case p2p leaf size mix {kernel} {precision}", flush=True)
+    rng = np.random.default_rng(21)
+    sizes = np.array([1, 2, 3, 4, 5, 7, 9, 13, 16, 17, 21, 31, 32, 33, 47, 63, 64, 65, 100, 127, 128,
+                      129, 200, 256, 257, 300])
+    n = int(sizes.sum())
+    pos = rng.uniform(0, 12, (3, n))
+    pos[:, ::7] = pos[:, 1::7][:, : pos[:, ::7].shape[1]] + 1e-3    # close pairs
+    g = rng.integers(0, 40, n).astype(np.int32)                     # many groups per leaf
+    h = np.full(40, 0.4)
+    f, w, nrm = rng.standard_normal((3, n)), rng.uniform(0.5, 1.5, n), rng.standard_normal((3, n))
+    nrm /= np.linalg.norm(nrm, axis=0)
+    ofs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    nl = len(sizes)
+    lists = [np.unique(np.concatenate([[L], rng.choice(nl, size=rng.integers(1, 8), replace=False)]))
+             for L in range(nl)]
+    uo = np.concatenate([[0], np.cumsum([len(l) for l in lists])]).astype(np.int64)
+    ul = np.concatenate(lists).astype(np.int32)
+    plan = S.P2PPlan(ofs, ofs, uo, ul, n, n)
+    kid = 0 if kernel == "sl" else 1
+    got = host(S.p2p_leaf(plan, dev(pos), dev(f), dev(w), dev(pos), kernel=kernel, nrm=dev(nrm),
+                          src_group=dev(g), trg_group=dev(g), precision=precision, group_h=dev(h)))
+    ref = O.p2p(kid, pos, f, w, pos, ofs, ofs, uo, ul, nrm=nrm, src_group=g, trg_group=g,
+                exclude_same_group=True)
+    assert_close(got, ref, TOL[precision], f"leaf size mix {kernel}/{precision}")
