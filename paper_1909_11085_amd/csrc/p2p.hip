@@ -14,14 +14,16 @@
 //     target R = min(16, 64/n) lanes, and lane phase h takes every R-th source
 //     (so small leaves still fill the wave); the R partial sums are added in a
 //     fixed order at the end.  The sources of each listed leaf are staged
-//     through LDS, up to 128 at a time, and sorted on the way in: a source is
-//     "careful" when its group occurs among the item's targets, or when it
-//     lies within the near limit of the targets' box; all others are "clean".
-//     Clean sources run an unmasked loop (float32 offsets in mixed precision,
-//     exactly as the direct sums' fast path); careful sources go through the
-//     same-group and zero-distance masks, and in mixed precision through
-//     r = (x_hi - y_hi) + (x_lo - y_lo) with pairs inside the near radius
-//     evaluated in float64.
+//     through LDS, up to 128 at a time, and sorted on the way in by what
+//     each needs: sources of a group that every target of the item shares
+//     are dropped (the same-group rule excludes them all); sources within
+//     the near limit of the targets' box are "careful"; sources of a group
+//     that some targets share are "masked"; the rest are "clean".  Clean
+//     sources run an unmasked loop (float32 offsets in mixed precision,
+//     exactly as the direct sums' fast path), masked ones the same loop with
+//     the same-group mask (and, in FP64, the zero-distance mask), careful
+//     ones (mixed) r = (x_hi - y_hi) + (x_lo - y_lo) with the same-group
+//     mask and the pairs inside the near radius evaluated in float64.
 #include <float.h>
 #include <limits.h>
 
@@ -48,9 +50,10 @@ struct stokes_p2p_plan {
 namespace stokes {
 namespace {
 
-constexpr int kP2PTile = 128;    // sources staged per LDS step
+constexpr int kP2PTile = 128;    // sources staged per LDS step (two batches of 64)
 constexpr int kMaxRep = 16;      // lanes per target at most
 constexpr int kMaxTGroups = 8;   // distinct target groups tracked per item
+static_assert(kP2PTile == 2 * kWave, "staging classifies a tile in two batches of one wave");
 
 // src: the source's index within its leaf (staging reorders sources)
 struct alignas(16) P2PSL32 { float hx, hy, hz, lx, ly, lz, qx, qy, qz, t2; int32_t g, src; };
@@ -185,14 +188,14 @@ __device__ __forceinline__ void pair64(const typename P2PRec<KT, 0>::type& s, do
     }
 }
 
-// float32 pair on offsets from the source leaf's centre (clean sources only:
-// no mask, no residues)
-template <int KT>
+// float32 pair on offsets from the source leaf's centre, without residues
+// (sources outside the near limit); MASKED adds the same-group mask
+template <int KT, bool MASKED>
 __device__ __forceinline__ void pair32(const typename P2PRec<KT, 1>::type& s, float xs, float ys,
-                                       float zs, float& bx, float& by, float& bz) {
+                                       float zs, bool skip, float& bx, float& by, float& bz) {
     const float dx = xs - s.hx, dy = ys - s.hy, dz = zs - s.hz;
     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float ri = (MASKED && skip) ? 0.0f : __builtin_amdgcn_rsqf(r2);
     const float ri2 = ri * ri;
     const float rq = __builtin_fmaf(dx, s.qx, __builtin_fmaf(dy, s.qy, dz * s.qz));
     if constexpr (KT == 0) {
@@ -253,9 +256,9 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 template <int KT, int MIXED>
 __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     using Rec = typename P2PRec<KT, MIXED>::type;
-    constexpr int kSlots = kP2PTile + kMaxRep;
-    // staged sources: clean ones from the front (padded to a multiple of R),
-    // careful ones from the back
+    constexpr int kSlots = kP2PTile + 2 * kMaxRep;
+    // staged sources: clean ones from the front, the others from the back;
+    // each region is padded to a multiple of R with zero-strength records
     __shared__ Rec s_rec[kSlots];
     __shared__ int32_t s_grp[MIXED ? 1 : kSlots];
     __shared__ double s_red[3 * kWave];
@@ -311,8 +314,17 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
         }
         for (int64_t b = 0; b < ns; b += kP2PTile) {
             const int nb = (int)((ns - b) < kP2PTile ? (ns - b) : kP2PTile);
+            // sort the tile's sources into LDS as they arrive (batches of 64):
+            //   clean (front): no group shared with the item's targets, outside
+            //     the near limit of their box: unmasked loop;
+            //   back: a group shared with some targets (same loop plus the
+            //     same-group mask; FP64 also masks zero distance), or (mixed)
+            //     within the near limit: residues and near test.  The back
+            //     region takes the careful loop if it holds any of the latter;
+            //   dropped: a group that every target of the item shares.
             __syncthreads();                           // previous readers are done
-            int n_clean = 0, n_care = 0;
+            int n_clean = 0, n_back = 0;
+            bool any_close = false;
             for (int i0 = 0; i0 < nb; i0 += kWave) {
                 const int i = i0 + lane;
                 const bool in = i < nb;
@@ -323,98 +335,103 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                 if constexpr (MIXED == 0) {
                     g = a.grp[si];
                     px = r.x; py = r.y; pz = r.z;
-                    lim = 0.0;                                 // only coincident points need the mask
+                    lim = 0.0;
                 } else {
                     g = r.g;
                     px = cx + ((double)r.hx + (double)r.lx);
                     py = cy + ((double)r.hy + (double)r.ly);
                     pz = cz + ((double)r.hz + (double)r.lz);
                     // the near radius with margin, and an eighth of the leaf
-                    // radius, which bounds the float32 offset error on the
-                    // clean path to about 20 ulp per pair
+                    // radius, which bounds the float32 offset error of the
+                    // unmasked formula to about 20 ulp per pair
                     lim = fmax(__builtin_fma(1.001, (double)__builtin_amdgcn_sqrtf(r.t2), 0x1p-20 * sext), 0.125 * crad);
                 }
                 const double gx = fmax(fmax(blo[0] - px, px - bhi[0]), 0.0);
                 const double gy = fmax(fmax(blo[1] - py, py - bhi[1]), 0.0);
                 const double gz = fmax(fmax(blo[2] - pz, pz - bhi[2]), 0.0);
                 const double gap2 = __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz));
-                bool care = !(gap2 > lim * lim) || (MIXED == 0 && gap2 <= 1e-200);
+                const bool close = MIXED ? !(gap2 > lim * lim) : gap2 <= 1e-200;
+                bool shared = false;
                 if (excl) {
-                    bool hit = many_groups;
+                    shared = many_groups;
 #pragma unroll
-                    for (int q = 0; q < kMaxTGroups; ++q) hit |= (q < ntg) && g == tgl[q];
-                    care |= hit;
+                    for (int q = 0; q < kMaxTGroups; ++q) shared |= (q < ntg) && g == tgl[q];
                 }
-                const uint64_t mc = __ballot(in && !care), mk = __ballot(in && care);
-                if (in) {
-                    const int pos = care ? kSlots - 1 - (n_care + lanes_below(mk)) : n_clean + lanes_below(mc);
+                const bool keep = in && !(excl && ntg == 1 && g == tgl[0]);
+                const bool back = close || shared;
+                const uint64_t mf = __ballot(keep && !back), mk = __ballot(keep && back);
+                if (MIXED && __ballot(keep && close)) any_close = true;
+                if (keep) {
+                    const int pos = back ? kSlots - 1 - (n_back + lanes_below(mk)) : n_clean + lanes_below(mf);
                     s_rec[pos] = r;
                     if constexpr (MIXED == 0) s_grp[pos] = g;
                 }
-                n_clean += __popcll(mc);
-                n_care += __popcll(mk);
+                n_clean += __popcll(mf);
+                n_back += __popcll(mk);
             }
             const int n_clean_pad = (n_clean + R - 1) / R * R;
+            const int n_back_pad = (n_back + R - 1) / R * R;
+            const int kb = kSlots - n_back_pad;        // back region [kb, kSlots), pad first
             if (lane < n_clean_pad - n_clean) s_rec[n_clean + lane] = pad_record<Rec>();
+            if (lane < n_back_pad - n_back) {
+                s_rec[kb + lane] = pad_record<Rec>();
+                if constexpr (MIXED == 0) s_grp[kb + lane] = 0;
+            }
             __syncthreads();
 
-            // clean sources, no masks: phase h takes the h-th of R equal runs
+            // clean sources: phase h takes the h-th of R equal runs
             const int m_clean = n_clean_pad / R;
             const Rec* pc = s_rec + h * m_clean;
+            const int m_back = n_back_pad / R;
+            const Rec* pb = s_rec + kb + h * m_back;
             if constexpr (MIXED == 0) {
+                const int32_t* gbk = s_grp + kb + h * m_back;
 #pragma unroll 4
                 for (int j = 0; j < m_clean; ++j) pair64<KT, false>(pc[j], x, y, z, false, ax, ay, az);
+#pragma unroll 2
+                for (int j = 0; j < m_back; ++j) pair64<KT, true>(pb[j], x, y, z, excl && gbk[j] == tg, ax, ay, az);
             } else {
                 float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll 4
-                for (int j = 0; j < m_clean; ++j) pair32<KT>(pc[j], xs, ys, zs, bx, by, bz);
-                ax += (double)bx;
-                ay += (double)by;
-                az += (double)bz;
-            }
-            // careful sources: slots [kSlots - n_care, kSlots), runs of m_care
-            const int cb = kSlots - n_care;
-            const int m_care = (n_care + R - 1) / R;
-            if constexpr (MIXED == 0) {
-                for (int jr = 0; jr < m_care; ++jr) {
-                    const int j = h * m_care + jr;
-                    const bool ok = j < n_care;
-                    const int slot = ok ? cb + j : cb;
-                    pair64<KT, true>(s_rec[slot], x, y, z, !ok || (excl && s_grp[slot] == tg), ax, ay, az);
-                }
-            } else {
-                float bx = 0.f, by = 0.f, bz = 0.f;
-                for (int jr = 0; jr < m_care; ++jr) {
-                    const int j = h * m_care + jr;
-                    const bool ok = j < n_care;
-                    const Rec s = s_rec[ok ? cb + j : cb];
-                    const float dx = (xs - s.hx) + (xl - s.lx);
-                    const float dy = (ys - s.hy) + (yl - s.ly);
-                    const float dz = (zs - s.hz) + (zl - s.lz);
-                    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                    const bool excluded = !ok || (excl && s.g == tg);
-                    const bool near = r2 <= s.t2;
-                    const float ri = (excluded || near) ? 0.0f : __builtin_amdgcn_rsqf(r2);
-                    const float ri2 = ri * ri;
-                    const float rq = __builtin_fmaf(dx, s.qx, __builtin_fmaf(dy, s.qy, dz * s.qz));
-                    if constexpr (KT == 0) {
-                        const float c = rq * ri2;
-                        bx = __builtin_fmaf(__builtin_fmaf(c, dx, s.qx), ri, bx);
-                        by = __builtin_fmaf(__builtin_fmaf(c, dy, s.qy), ri, by);
-                        bz = __builtin_fmaf(__builtin_fmaf(c, dz, s.qz), ri, bz);
-                    } else {
-                        const float rn = __builtin_fmaf(dx, s.nx, __builtin_fmaf(dy, s.ny, dz * s.nz));
-                        const float c = rn * rq * (ri2 * ri2 * ri);
-                        bx = __builtin_fmaf(c, dx, bx);
-                        by = __builtin_fmaf(c, dy, by);
-                        bz = __builtin_fmaf(c, dz, bz);
+                for (int j = 0; j < m_clean; ++j) pair32<KT, false>(pc[j], xs, ys, zs, false, bx, by, bz);
+                if (!any_close) {
+#pragma unroll 2
+                    for (int j = 0; j < m_back; ++j) {
+                        const Rec sr = pb[j];
+                        pair32<KT, true>(sr, xs, ys, zs, excl && sr.g == tg, bx, by, bz);
                     }
-                    if (near && !excluded) {
-                        const Vec3 v = near64<KT>(a.in.src_xyz, a.in.density, a.in.weight, a.in.normal,
-                                                  a.in.n_src, s0 + s.src, x, y, z);
-                        ax += v.x;
-                        ay += v.y;
-                        az += v.z;
+                } else {
+                    // residues, near test, float64 near pairs
+                    for (int j = 0; j < m_back; ++j) {
+                        const Rec sr = pb[j];
+                        const float dx = (xs - sr.hx) + (xl - sr.lx);
+                        const float dy = (ys - sr.hy) + (yl - sr.ly);
+                        const float dz = (zs - sr.hz) + (zl - sr.lz);
+                        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                        const bool excluded = excl && sr.g == tg;
+                        const bool near = r2 <= sr.t2;
+                        const float ri = (excluded || near) ? 0.0f : __builtin_amdgcn_rsqf(r2);
+                        const float ri2 = ri * ri;
+                        const float rq = __builtin_fmaf(dx, sr.qx, __builtin_fmaf(dy, sr.qy, dz * sr.qz));
+                        if constexpr (KT == 0) {
+                            const float c = rq * ri2;
+                            bx = __builtin_fmaf(__builtin_fmaf(c, dx, sr.qx), ri, bx);
+                            by = __builtin_fmaf(__builtin_fmaf(c, dy, sr.qy), ri, by);
+                            bz = __builtin_fmaf(__builtin_fmaf(c, dz, sr.qz), ri, bz);
+                        } else {
+                            const float rn = __builtin_fmaf(dx, sr.nx, __builtin_fmaf(dy, sr.ny, dz * sr.nz));
+                            const float c = rn * rq * (ri2 * ri2 * ri);
+                            bx = __builtin_fmaf(c, dx, bx);
+                            by = __builtin_fmaf(c, dy, by);
+                            bz = __builtin_fmaf(c, dz, bz);
+                        }
+                        if (near && !excluded) {
+                            const Vec3 v = near64<KT>(a.in.src_xyz, a.in.density, a.in.weight, a.in.normal,
+                                                      a.in.n_src, s0 + sr.src, x, y, z);
+                            ax += v.x;
+                            ay += v.y;
+                            az += v.z;
+                        }
                     }
                 }
                 ax += (double)bx;
