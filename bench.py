@@ -80,8 +80,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="headline precision (the other one is reported alongside)")
-    ap.add_argument("--only", choices=["fp64", "mixed", "vjp"], default=None,
-                    help="time one path only (for profiler runs)")
+    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p"], default=None,
+                    help="time one path only (for profiler runs); p2p times the leaf-to-leaf "
+                         "workload (3,840 cells in the cylinder) in both precisions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
@@ -117,24 +118,10 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": nbytes, "calibrate_copy_bytes_written": nbytes,
                           "launches": 3}), flush=True)
         return
-    t0 = time.time()
-    cfg = W.make_config(2)
-    cells, f = cfg["cells"], cfg["f"]
-    n = cells.n
-    pairs = W.pair_count_direct(cells.group, cells.group, True)
-    log(f"workload: {cells.meta['n_cells']} cells, {n} points, {pairs} pairs/step "
-        f"(generated in {time.time() - t0:.1f}s)")
+    stream = torch.cuda.current_stream(dev)
 
     def t(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-
-    pos, ft, wt, grp, gh = t(cells.pos), t(f), t(cells.weight), t(cells.group), t(cells.group_h)
-    out = torch.empty((3, n), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    def fwd(precision):
-        S.sl(pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=precision, group_h=gh,
-             near_frac=0.5, out=out)
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -152,6 +139,27 @@ def main():
         S.timing_enable(False)
         kms, launches = S.timing_read()
         return e0.elapsed_time(e1) / steps, kms / max(launches, 1), launches
+
+    if args.only == "p2p":
+        r = time_p2p(S, W, t, timed, args.steps, args.warmup)
+        log(f"p2p: {r}")
+        print(json.dumps({"p2p_3840_cells": r}), flush=True)
+        return
+
+    t0 = time.time()
+    cfg = W.make_config(2)
+    cells, f = cfg["cells"], cfg["f"]
+    n = cells.n
+    pairs = W.pair_count_direct(cells.group, cells.group, True)
+    log(f"workload: {cells.meta['n_cells']} cells, {n} points, {pairs} pairs/step "
+        f"(generated in {time.time() - t0:.1f}s)")
+
+    pos, ft, wt, grp, gh = t(cells.pos), t(f), t(cells.weight), t(cells.group), t(cells.group_h)
+    out = torch.empty((3, n), dtype=torch.float64, device=dev)
+
+    def fwd(precision):
+        S.sl(pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=precision, group_h=gh,
+             near_frac=0.5, out=out)
 
     results = {}
     outputs = {}
@@ -262,6 +270,22 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def time_p2p(S, W, t, timed, steps, warmup):
+    """Leaf-to-leaf sums of 3,840 cells in the cylinder (lists of 27..60 leaves), both precisions."""
+    cfg = W.make_config(4)
+    c, tree, f = cfg["cells"], cfg["tree"], cfg["f"]
+    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, cfg["ulist_ofs"], cfg["ulist"], c.n, c.n)
+    pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
+    r = {"listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
+    for prec in ("mixed", "fp64"):
+        ms, kms, _ = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
+                                              precision=prec, group_h=gh), steps, warmup)
+        r[f"{prec}_ms"] = ms
+        r[f"{prec}_kernel_ms"] = kms
+        r[f"{prec}_listed_pairs_per_s"] = r["listed_pairs"] / (ms * 1e-3)
+    return r
+
+
 def secondary(S, W, t, timed, log):
     """Timings of the other workload shapes (not the headline)."""
     import torch
@@ -287,17 +311,7 @@ def secondary(S, W, t, timed, log):
     out["cfg3_128_cells_sl_and_adjoint"] = r
     log(f"secondary cfg3: {r}")
     # cfg4: leaf-to-leaf sums over 27..60-leaf lists, one launch
-    cfg = W.make_config(4)
-    c, tree, f = cfg["cells"], cfg["tree"], cfg["f"]
-    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, cfg["ulist_ofs"], cfg["ulist"], c.n, c.n)
-    pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
-    r = {"listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
-    for prec in ("mixed", "fp64"):
-        ms, kms, _ = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
-                                              precision=prec, group_h=gh), 10, 2)
-        r[f"{prec}_ms"] = ms
-        r[f"{prec}_kernel_ms"] = kms
-        r[f"{prec}_listed_pairs_per_s"] = r["listed_pairs"] / (ms * 1e-3)
+    r = time_p2p(S, W, t, timed, 10, 2)
     out["cfg4_p2p_3840_cells"] = r
     log(f"secondary cfg4: {r}")
     # cfg5: wall double layer onto 960 cells plus the cell single layer; adjoints

@@ -256,12 +256,13 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 template <int KT, int MIXED>
 __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     using Rec = typename P2PRec<KT, MIXED>::type;
-    constexpr int kSlots = kP2PTile + 2 * kMaxRep;
+    constexpr int kSlots = kP2PTile + 4 * kMaxRep;
     // staged sources: clean ones from the front, the others from the back;
-    // each region is padded to a multiple of R with zero-strength records
+    // each region is padded with zero-strength records to R runs of equal
+    // length, odd when R > 1: the R lanes of a target then read records an
+    // odd number of records apart, which fall in distinct LDS banks
     __shared__ Rec s_rec[kSlots];
     __shared__ int32_t s_grp[MIXED ? 1 : kSlots];
-    __shared__ double s_red[3 * kWave];
     const int lane = threadIdx.x;
     const int32_t L = a.items[2 * blockIdx.x], ch = a.items[2 * blockIdx.x + 1];
     const int64_t t0 = a.trg_ofs[L] + (int64_t)ch * kWave;
@@ -305,12 +306,25 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
         const double* lc = a.leaf_ctr + 4 * (int64_t)Ls;
         const double cx = lc[0], cy = lc[1], cz = lc[2], crad = lc[3];
         float xs = 0.f, ys = 0.f, zs = 0.f, xl = 0.f, yl = 0.f, zl = 0.f;
+        // mixed: the targets' box relative to this leaf's centre in float32,
+        // and a slack above every rounding of the float32 gap test below
+        float flo[3] = {0.f, 0.f, 0.f}, fhi[3] = {0.f, 0.f, 0.f}, fslack = 0.f, frad8 = 0.f;
         if constexpr (MIXED != 0) {
             const double hx = x - cx, hy = y - cy, hz = z - cz;
             xs = (float)hx; ys = (float)hy; zs = (float)hz;
             xl = (float)(hx - (double)xs);
             yl = (float)(hy - (double)ys);
             zl = (float)(hz - (double)zs);
+            const double cc[3] = {cx, cy, cz};
+            double mag = crad;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                flo[q] = (float)(blo[q] - cc[q]);
+                fhi[q] = (float)(bhi[q] - cc[q]);
+                mag = fmax(mag, fmax(fabs(blo[q] - cc[q]), fabs(bhi[q] - cc[q])));
+            }
+            fslack = (float)(0x1p-18 * (mag + crad + sext));
+            frad8 = (float)(0.125 * crad);
         }
         for (int64_t b = 0; b < ns; b += kP2PTile) {
             const int nb = (int)((ns - b) < kP2PTile ? (ns - b) : kP2PTile);
@@ -330,27 +344,29 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                 const bool in = i < nb;
                 const int64_t si = s0 + b + (in ? i : 0);     // nb >= 1: index 0 is a real source
                 const Rec r = rec[si];
-                double px, py, pz, lim;
                 int32_t g;
+                bool close;
                 if constexpr (MIXED == 0) {
                     g = a.grp[si];
-                    px = r.x; py = r.y; pz = r.z;
-                    lim = 0.0;
+                    // coincident points are possible only inside the targets' box
+                    const double gx = fmax(fmax(blo[0] - r.x, r.x - bhi[0]), 0.0);
+                    const double gy = fmax(fmax(blo[1] - r.y, r.y - bhi[1]), 0.0);
+                    const double gz = fmax(fmax(blo[2] - r.z, r.z - bhi[2]), 0.0);
+                    close = __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz)) <= 1e-200;
                 } else {
                     g = r.g;
-                    px = cx + ((double)r.hx + (double)r.lx);
-                    py = cy + ((double)r.hy + (double)r.ly);
-                    pz = cz + ((double)r.hz + (double)r.lz);
-                    // the near radius with margin, and an eighth of the leaf
-                    // radius, which bounds the float32 offset error of the
-                    // unmasked formula to about 20 ulp per pair
-                    lim = fmax(__builtin_fma(1.001, (double)__builtin_amdgcn_sqrtf(r.t2), 0x1p-20 * sext), 0.125 * crad);
+                    // gap from the targets' box in float32 on leaf-centred
+                    // offsets; the limit is the near radius with margin, or an
+                    // eighth of the leaf radius (which bounds the float32 offset
+                    // error of the unmasked formula to about 20 ulp per pair),
+                    // plus the slack
+                    const float gx = fmaxf(fmaxf(flo[0] - r.hx, r.hx - fhi[0]), 0.f);
+                    const float gy = fmaxf(fmaxf(flo[1] - r.hy, r.hy - fhi[1]), 0.f);
+                    const float gz = fmaxf(fmaxf(flo[2] - r.hz, r.hz - fhi[2]), 0.f);
+                    const float gap2 = __builtin_fmaf(gx, gx, __builtin_fmaf(gy, gy, gz * gz));
+                    const float lim = fmaxf(1.001f * __builtin_amdgcn_sqrtf(r.t2), frad8) + fslack;
+                    close = !(gap2 > lim * lim);
                 }
-                const double gx = fmax(fmax(blo[0] - px, px - bhi[0]), 0.0);
-                const double gy = fmax(fmax(blo[1] - py, py - bhi[1]), 0.0);
-                const double gz = fmax(fmax(blo[2] - pz, pz - bhi[2]), 0.0);
-                const double gap2 = __builtin_fma(gx, gx, __builtin_fma(gy, gy, gz * gz));
-                const bool close = MIXED ? !(gap2 > lim * lim) : gap2 <= 1e-200;
                 bool shared = false;
                 if (excl) {
                     shared = many_groups;
@@ -369,8 +385,12 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                 n_clean += __popcll(mf);
                 n_back += __popcll(mk);
             }
-            const int n_clean_pad = (n_clean + R - 1) / R * R;
-            const int n_back_pad = (n_back + R - 1) / R * R;
+            auto run_len = [&](int n) {
+                const int m = (n + R - 1) / R;
+                return (R > 1 && m > 0) ? (m | 1) : m;
+            };
+            const int m_clean = run_len(n_clean), m_back = run_len(n_back);
+            const int n_clean_pad = m_clean * R, n_back_pad = m_back * R;
             const int kb = kSlots - n_back_pad;        // back region [kb, kSlots), pad first
             if (lane < n_clean_pad - n_clean) s_rec[n_clean + lane] = pad_record<Rec>();
             if (lane < n_back_pad - n_back) {
@@ -379,10 +399,8 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
             }
             __syncthreads();
 
-            // clean sources: phase h takes the h-th of R equal runs
-            const int m_clean = n_clean_pad / R;
+            // phase h takes the h-th of the R runs of each region
             const Rec* pc = s_rec + h * m_clean;
-            const int m_back = n_back_pad / R;
             const Rec* pb = s_rec + kb + h * m_back;
             if constexpr (MIXED == 0) {
                 const int32_t* gbk = s_grp + kb + h * m_back;
@@ -442,7 +460,9 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     }
     // add the R phase partials of each target in a fixed order
     if (R > 1) {
-        __syncthreads();
+        static_assert(sizeof(s_rec) >= 3 * kWave * sizeof(double), "reduction reuses the staging array");
+        double* s_red = reinterpret_cast<double*>(s_rec);
+        __syncthreads();                               // last tile's readers are done
         s_red[lane] = ax;
         s_red[kWave + lane] = ay;
         s_red[2 * kWave + lane] = az;
