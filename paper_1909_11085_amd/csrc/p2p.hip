@@ -53,7 +53,7 @@ namespace {
 constexpr int kP2PTile = 128;    // sources staged per LDS step (two batches of 64)
 constexpr int kMaxRep = 16;      // lanes per target at most
 constexpr int kMaxTGroups = 8;   // distinct target groups tracked per item
-static_assert(kP2PTile == 2 * kWave, "staging classifies a tile in two batches of one wave");
+static_assert(kP2PTile % kWave == 0, "staging classifies a tile in batches of one wave");
 
 // src: the source's index within its leaf (staging reorders sources)
 struct alignas(16) P2PSL32 { float hx, hy, hz, lx, ly, lz, qx, qy, qz, t2; int32_t g, src; };
@@ -256,11 +256,10 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 template <int KT, int MIXED>
 __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     using Rec = typename P2PRec<KT, MIXED>::type;
-    constexpr int kSlots = kP2PTile + 4 * kMaxRep;
+    constexpr int kSlots = kP2PTile + 2 * kMaxRep;
     // staged sources: clean ones from the front, the others from the back;
     // each region is padded with zero-strength records to R runs of equal
-    // length, odd when R > 1: the R lanes of a target then read records an
-    // odd number of records apart, which fall in distinct LDS banks
+    // length
     __shared__ Rec s_rec[kSlots];
     __shared__ int32_t s_grp[MIXED ? 1 : kSlots];
     const int lane = threadIdx.x;
@@ -385,11 +384,7 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                 n_clean += __popcll(mf);
                 n_back += __popcll(mk);
             }
-            auto run_len = [&](int n) {
-                const int m = (n + R - 1) / R;
-                return (R > 1 && m > 0) ? (m | 1) : m;
-            };
-            const int m_clean = run_len(n_clean), m_back = run_len(n_back);
+            const int m_clean = (n_clean + R - 1) / R, m_back = (n_back + R - 1) / R;
             const int n_clean_pad = m_clean * R, n_back_pad = m_back * R;
             const int kb = kSlots - n_back_pad;        // back region [kb, kSlots), pad first
             if (lane < n_clean_pad - n_clean) s_rec[n_clean + lane] = pad_record<Rec>();
