@@ -131,7 +131,7 @@ def rsa_centres(rng, n, radius, lo, hi, inside=None, batch=4096, max_tries=20_00
     cap = 8
     grid = -np.ones((dims[0] + 2, dims[1] + 2, dims[2] + 2, cap), dtype=np.int64)
     fill = np.zeros(grid.shape[:3], dtype=np.int64)
-    cent = np.empty((n, 3))
+    cent = np.zeros((n, 3))     # rows not yet placed are read only under a mask
     k = 0
     tries = 0
     offs = np.array([[i, j, l] for i in (-1, 0, 1) for j in (-1, 0, 1) for l in (-1, 0, 1)])

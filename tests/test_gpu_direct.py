@@ -210,3 +210,51 @@ def test_cfg5_wall_double_layer_sampled(cfg5, precision):
     ref = O.dl(wall.pos, phi, wall.weight, wall.normal, cells.pos[:, idx])
     r = assert_close(host(u)[:, idx], ref, PREC_TOL[precision], f"cfg5-DL/{precision}")
     print(f"cfg5 DL {precision} rel-L2 on 256 targets {r:.3e}")
+
+
+def _rotation(seed):
+    q = np.random.default_rng(seed).standard_normal(4)
+    a, b, c, d = q / np.linalg.norm(q)
+    return np.array([[a * a + b * b - c * c - d * d, 2 * (b * c - a * d), 2 * (b * d + a * c)],
+                     [2 * (b * c + a * d), a * a - b * b + c * c - d * d, 2 * (c * d - a * b)],
+                     [2 * (b * d - a * c), 2 * (c * d + a * b), a * a - b * b - c * c + d * d]])
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_rotation_equivariance_on_gpu(kernel):
+    """u(Qx; Qy, Q f, Q n) = Q u(x; y, f, n): both sums are built from r, r.q,
+    r.n and rho only, so rotating every vector rotates the result."""
+    c = _cloud(31, 900, 700, dup=0)
+    Q = _rotation(5)
+    cr = dict(c, y=Q @ c["y"], x=Q @ c["x"], f=Q @ c["f"], n=Q @ c["n"])
+    u = host(_run(kernel, c, "fp64", True))
+    ur = host(_run(kernel, cr, "fp64", True))
+    assert rel_l2(ur, Q @ u) < 1e-13
+
+
+def test_symmetry_of_weighted_single_layer_on_gpu():
+    """The Stokeslet is symmetric, S(x, y) = S(y, x) = S^T, so on a shared point
+    set with the same-group rule <w g, A f> = <w f, A g> with (A f)_n = sum_m S w_m f_m."""
+    cfg = W.make_config(1)
+    cells = cfg["cells"]
+    rng = np.random.default_rng(17)
+    f, g = rng.standard_normal((2, 3, cells.n))
+    p, w, gr = dev(cells.pos), dev(cells.weight), dev(cells.group)
+    af = host(S.sl(p, dev(f), w, p, src_group=gr, trg_group=gr))
+    ag = host(S.sl(p, dev(g), w, p, src_group=gr, trg_group=gr))
+    lhs = float(np.sum(cells.weight * g * af))
+    rhs = float(np.sum(cells.weight * f * ag))
+    assert abs(lhs - rhs) / abs(lhs) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_linearity_and_viscosity_on_gpu(precision):
+    """u(alpha f) = alpha u(f); the single layer scales as 1/mu and the double
+    layer does not depend on mu (it takes none)."""
+    c = _cloud(41, 1200, 800, dup=0)
+    u1 = host(_run("sl", c, precision, True, mu=1.0))
+    u2 = host(_run("sl", dict(c, f=-2.5 * c["f"]), precision, True, mu=4.0))
+    assert rel_l2(u2, -2.5 / 4.0 * u1) < PREC_TOL[precision]
+    d1 = host(_run("dl", c, precision, True))
+    d2 = host(_run("dl", dict(c, f=3.0 * c["f"]), precision, True))
+    assert rel_l2(d2, 3.0 * d1) < PREC_TOL[precision]
