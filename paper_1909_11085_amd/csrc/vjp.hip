@@ -80,7 +80,7 @@ struct SlT {
         v[0] = a.tv[0][i]; v[1] = a.tv[0][n + i]; v[2] = a.tv[0][2 * n + i];
     }
     template <bool M>
-    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&g)[NT],
+    __device__ __forceinline__ static void pair(const Rec& s, double x, double y, double z, const double (&g)[NT],
                                 bool skip, double (&acc)[NACC]) {
         const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
         const double r2 = dot3(dx, dy, dz, dx, dy, dz);
@@ -126,7 +126,7 @@ struct SlS {
         v[0] = w * a.tv[0][i]; v[1] = w * a.tv[0][n + i]; v[2] = w * a.tv[0][2 * n + i];
     }
     template <bool M>
-    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&q)[NT],
+    __device__ __forceinline__ static void pair(const Rec& s, double x, double y, double z, const double (&q)[NT],
                                 bool skip, double (&acc)[NACC]) {
         const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
         const double r2 = dot3(dx, dy, dz, dx, dy, dz);
@@ -184,7 +184,7 @@ struct SlSym {
         v[3] = w * a.tv[1][i]; v[4] = w * a.tv[1][n + i]; v[5] = w * a.tv[1][2 * n + i];
     }
     template <bool M>
-    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&v)[NT],
+    __device__ __forceinline__ static void pair(const Rec& s, double x, double y, double z, const double (&v)[NT],
                                 bool skip, double (&acc)[NACC]) {
         const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
         const double r2 = dot3(dx, dy, dz, dx, dy, dz);
@@ -248,9 +248,10 @@ struct DlT {
         const int64_t n = a.n_trg;
         v[0] = a.tv[0][i]; v[1] = a.tv[0][n + i]; v[2] = a.tv[0][2 * n + i];
     }
-    template <bool M>
-    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&g)[NT],
-                                bool skip, double (&acc)[NACC]) {
+    // SRC: also add the source-side term r (r.n)(r.g)/rho^5 of dL/dphi into v
+    template <bool M, bool SRC = false>
+    __device__ __forceinline__ static void pair(const Rec& s, double x, double y, double z, const double (&g)[NT],
+                                bool skip, double (&acc)[NACC], double* v = nullptr) {
         const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
         const double r2 = dot3(dx, dy, dz, dx, dy, dz);
         const double ri = ri_of<M>(r2, skip);
@@ -266,6 +267,11 @@ struct DlT {
         acc[0] = __builtin_fma(cn, s.nx, __builtin_fma(cq, s.qx, __builtin_fma(cr, dx, acc[0])));
         acc[1] = __builtin_fma(cn, s.ny, __builtin_fma(cq, s.qy, __builtin_fma(cr, dy, acc[1])));
         acc[2] = __builtin_fma(cn, s.nz, __builtin_fma(cq, s.qz, __builtin_fma(cr, dz, acc[2])));
+        if constexpr (SRC) {
+            v[0] = __builtin_fma(cq, dx, v[0]);
+            v[1] = __builtin_fma(cq, dy, v[1]);
+            v[2] = __builtin_fma(cq, dz, v[2]);
+        }
     }
     __device__ static void store(const PassArgs& a, int64_t i, const double (&s)[NACC]) {
         const int64_t n = a.n_trg;
@@ -301,7 +307,7 @@ struct DlS {
         v[3] = w * a.tv[0][i]; v[4] = w * a.tv[0][n + i]; v[5] = w * a.tv[0][2 * n + i];  // q_m
     }
     template <bool M>
-    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&v)[NT],
+    __device__ __forceinline__ static void pair(const Rec& s, double x, double y, double z, const double (&v)[NT],
                                 bool skip, double (&acc)[NACC]) {
         const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
         const double r2 = dot3(dx, dy, dz, dx, dy, dz);
@@ -350,7 +356,7 @@ struct SlSF {
     __device__ static void pad_rec(Rec& r) { SlS::pad_rec(r); }
     __device__ static void load_t(const PassArgs&, int64_t, double (&v)[NT]) { v[0] = 0.0; }
     template <bool M>
-    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&)[NT],
+    __device__ __forceinline__ static void pair(const Rec& s, double x, double y, double z, const double (&)[NT],
                                 bool skip, double (&acc)[NACC]) {
         const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
         const double r2 = dot3(dx, dy, dz, dx, dy, dz);
@@ -378,7 +384,7 @@ struct DlSPhi {
         v[0] = a.tv[2][i]; v[1] = a.tv[2][n + i]; v[2] = a.tv[2][2 * n + i];
     }
     template <bool M>
-    __device__ static void pair(const Rec& s, double x, double y, double z, const double (&nv)[NT],
+    __device__ __forceinline__ static void pair(const Rec& s, double x, double y, double z, const double (&nv)[NT],
                                 bool skip, double (&acc)[NACC]) {
         const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
         const double r2 = dot3(dx, dy, dz, dx, dy, dz);
@@ -396,6 +402,230 @@ struct DlSPhi {
     }
 };
 
+// ---- double layer, target side fused with the density gradient ---------------
+// One sweep over the (target, source) pairs of the target-side pass also gives,
+// per source, V_m = sum_n r (r.n_m)(r.g_n)/rho^5, so that dL/dphi_m = d w_m V_m
+// (its coefficient is the target side's cq).  V is summed across a wave's
+// targets by a butterfly, across the workgroup's waves in LDS in a fixed
+// order, and across target blocks by float64 atomic adds into a workspace
+// array (so dL/dphi is not bitwise reproducible from run to run; the other
+// outputs are).
+
+// v[i][c] over the 64 lanes of the wave: lane l returns the totals of source
+// i = l / 16 (two reduce-scatter steps, then a sum over 16 lanes).
+__device__ __forceinline__ void wave_sum4x3(const double (&v)[4][3], int lane, double (&out)[3]) {
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0;
+    double h[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double send = b5 ? v[i][c] : v[i + 2][c];
+            const double keep = b5 ? v[i + 2][c] : v[i][c];
+            h[i][c] = keep + __shfl_xor(send, 32);
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double send = b4 ? h[0][c] : h[1][c];
+        const double keep = b4 ? h[1][c] : h[0][c];
+        out[c] = keep + __shfl_xor(send, 16);
+    }
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] += __shfl_xor(out[c], m);
+}
+
+// Lanes past the last target hold a copy of it (the skeleton's load_tgt);
+// their target-side sums are dropped, but their source-side terms would be
+// added to V, so their cotangent is set to zero (every term then vanishes).
+template <int T>
+__device__ __forceinline__ void zero_padding_targets(const PassArgs& a, int64_t tb, int lane,
+                                                     ps::Tgt<DlT, T>& t) {
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+        if (tb + (int64_t)k * kWave + lane >= a.n_trg) t.v[k][0] = t.v[k][1] = t.v[k][2] = 0.0;
+}
+
+template <int T, int W>
+__global__ __launch_bounds__(kBlock, W) void dl_fused_main(PassArgs a, double* __restrict__ phi) {
+    using P = DlT;
+    using Rec = P::Rec;
+    constexpr int BT = kBlock * T;
+    __shared__ Rec s_rec[kTile];
+    __shared__ double s_part[4][3 * kTile];      // per wave: V of each source of the chunk
+    const int64_t U = a.units, C = a.chunks, G = gridDim.x;
+    const int64_t u0 = ps::unit_begin(blockIdx.x, U, G), u1 = ps::unit_begin(blockIdx.x + 1, U, G);
+    if (u0 >= u1) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const bool excl = a.excl != 0;
+    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
+    ps::Tgt<P, T> t;
+    bool active = false;
+    int64_t tbk = -1;
+    double acc[T][P::NACC];
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int c = 0; c < P::NACC; ++c) acc[k][c] = 0.0;
+
+    int64_t ub = u0 / C, c = u0 % C;
+    double* sp = s_part[wave];
+    for (int64_t u = u0; u < u1; ++u) {
+        __syncthreads();                           // previous readers of s_rec and s_part are done
+        if (ub != tbk) {
+            if (tbk >= 0) ps::flush<P, T>(a, tbk, wave, lane, acc);
+            tbk = ub;
+            const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
+            active = tb < a.n_trg;
+            ps::load_tgt<P, T>(a, active ? tb : 0, lane, t);
+            zero_padding_targets<T>(a, active ? tb : 0, lane, t);
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+#pragma unroll
+                for (int q = 0; q < P::NACC; ++q) acc[k][q] = 0.0;
+        }
+        s_rec[threadIdx.x] = rec[c * kTile + threadIdx.x];
+        __syncthreads();
+        int64_t cn = c + 1, ubn = ub;
+        if (cn == C) { cn = 0; ++ubn; }
+        uint32_t flags = 0;
+#pragma unroll 1
+        for (int s = 0; s < 4; ++s) {
+            const SubMeta m = a.meta[c * 4 + s];
+            bool run = active && m.count != 0;
+            if (run && ps::needs_near<P, T>(t, m, excl)) {
+                flags |= 1u << s;                  // its pairs (and V terms) go to the near pass
+                run = false;
+            }
+            if (!run) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sp[3 * (s * kSub + lane) + q] = 0.0;
+                continue;
+            }
+            const Rec* base = s_rec + s * kSub;
+#pragma unroll 1
+            for (int j0 = 0; j0 < kSub; j0 += 4) {
+                double v[4][3];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i][0] = v[i][1] = v[i][2] = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const Rec sr = base[j0 + i];
+#pragma unroll
+                    for (int k = 0; k < T; ++k)
+                        P::template pair<false, true>(sr, t.x[k], t.y[k], t.z[k], t.v[k], false, acc[k], v[i]);
+                }
+                double tot[3];
+                wave_sum4x3(v, lane, tot);
+                // the 16 lanes of a row hold the same totals: all store (no branch)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sp[3 * (s * kSub + j0 + (lane >> 4)) + q] = tot[q];
+            }
+        }
+        if (active && lane == 0) a.flags[(tbk * 4 + wave) * C + c] = (uint8_t)flags;
+        __syncthreads();
+        // this unit's V of source c * 256 + tid: the four waves in order, then one atomic add
+        const int64_t src = c * kTile + threadIdx.x;
+        if (src < a.n_src) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int i = 3 * threadIdx.x + q;
+                const double sum = ((s_part[0][i] + s_part[1][i]) + s_part[2][i]) + s_part[3][i];
+                if (sum != 0.0) unsafeAtomicAdd(phi + q * a.n_src + src, sum);
+            }
+        }
+        c = cn;
+        ub = ubn;
+    }
+    ps::flush<P, T>(a, tbk, wave, lane, acc);
+}
+
+// The flagged sub-tiles of dl_fused_main, with the same-group and
+// zero-distance masks; V goes straight to the atomic adds.
+template <int T>
+__global__ __launch_bounds__(kBlock) void dl_fused_near(PassArgs a, double* __restrict__ phi) {
+    using P = DlT;
+    using Rec = P::Rec;
+    constexpr int BT = kBlock * T;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t tbk = blockIdx.x, C = a.chunks;
+    const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
+    if (tb >= a.n_trg) return;                     // no barriers below
+    const bool excl = a.excl != 0;
+    const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
+    ps::Tgt<P, T> t;
+    ps::load_tgt<P, T>(a, tb, lane, t);
+    zero_padding_targets<T>(a, tb, lane, t);
+    double acc[T][P::NACC];
+#pragma unroll
+    for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int q = 0; q < P::NACC; ++q) acc[k][q] = 0.0;
+    const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
+    for (int64_t c0 = 0; c0 < C; c0 += kWave) {
+        const uint32_t mine = (c0 + lane < C) ? fl[c0 + lane] : 0u;
+        uint64_t nz = __ballot(mine != 0);
+        while (nz) {
+            const int l = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)mine, l);
+            while (f) {
+                const int s = __builtin_ctz(f);
+                f &= f - 1;
+                const int64_t sub = (c0 + l) * 4 + s;
+                const Rec mr = rec[sub * kSub + lane];
+                const int32_t mg = a.grp[sub * kSub + lane];
+#pragma unroll 1
+                for (int j0 = 0; j0 < kSub; j0 += 4) {
+                    double v[4][3];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i][0] = v[i][1] = v[i][2] = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const Rec sr = ps::bcast(mr, j0 + i);
+                        const int32_t gs = __builtin_amdgcn_readlane(mg, j0 + i);
+#pragma unroll
+                        for (int k = 0; k < T; ++k)
+                            P::template pair<true, true>(sr, t.x[k], t.y[k], t.z[k], t.v[k],
+                                                         excl && gs == t.g[k], acc[k], v[i]);
+                    }
+                    double tot[3];
+                    wave_sum4x3(v, lane, tot);
+                    const int64_t src = sub * kSub + j0 + (lane >> 4);
+                    if ((lane & 15) == 0 && src < a.n_src)
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+                            if (tot[q] != 0.0) unsafeAtomicAdd(phi + q * a.n_src + src, tot[q]);
+                }
+            }
+        }
+    }
+    const int64_t np = (int64_t)gridDim.x * BT;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
+#pragma unroll
+        for (int q = 0; q < P::NACC; ++q) a.near_part[q * np + gi] = acc[k][q];
+    }
+}
+
+// dL/dphi_m = d w_m V_m
+__global__ __launch_bounds__(kBlock) void dl_phi_store(const double* __restrict__ phi,
+                                                       const double* __restrict__ weight, double pref,
+                                                       double* __restrict__ out, int64_t n, int accumulate) {
+    const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (m >= n) return;
+    const double s = pref * weight[m];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double val = s * phi[q * n + m];
+        out[q * n + m] = accumulate ? out[q * n + m] + val : val;
+    }
+}
+
 // launch shapes (targets per lane, minimum waves per SIMD)
 constexpr int kTSlT = 4, kWSlT = 3;
 constexpr int kTSlS = 2, kWSlS = 4;
@@ -404,6 +634,15 @@ constexpr int kTDlT = 4, kWDlT = 3;
 constexpr int kTDlS = 2, kWDlS = 3;
 constexpr int kTSlSF = 4, kWSlSF = 4;
 constexpr int kTDlSPhi = 4, kWDlSPhi = 4;
+constexpr int kTDlF = 4, kWDlF = 2;
+
+// workspace of the fused double-layer pass: the target-side pass, then V (3, n_src)
+size_t dl_fused_bytes(int64_t n_src, int64_t n_trg, int resident, size_t* off_phi) {
+    const auto p = ps::plan_pass<DlT, kTDlF>(n_src, n_trg, resident);
+    const size_t off = align_up(p.total, 256);
+    if (off_phi) *off_phi = off;
+    return align_up(off + (size_t)3 * n_src * sizeof(double), 256);
+}
 
 }  // namespace
 
@@ -415,6 +654,11 @@ void vjp_resident(int n_cu, int out[kVjpPasses]) {
     out[4] = ps::resident_blocks<DlS, kTDlS, kWDlS>(n_cu);
     out[5] = ps::resident_blocks<SlSF, kTSlSF, kWSlSF>(n_cu);
     out[6] = ps::resident_blocks<DlSPhi, kTDlSPhi, kWDlSPhi>(n_cu);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dl_fused_main<kTDlF, kWDlF>, kBlock, 0) !=
+            hipSuccess || nb < 1)
+        nb = 1;
+    out[7] = nb * n_cu;
 }
 
 size_t vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, const int resident[kVjpPasses]) {
@@ -427,6 +671,7 @@ size_t vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, const int r
         return b;
     }
     size_t b = ps::plan_pass<DlT, kTDlT>(n_src, n_trg, resident[3]).total;
+    b = std::max(b, dl_fused_bytes(n_src, n_trg, resident[7], nullptr));
     b = std::max(b, ps::plan_pass<DlSPhi, kTDlSPhi>(n_trg, n_src, resident[6]).total);
     return std::max(b, ps::plan_pass<DlS, kTDlS>(n_trg, n_src, resident[4]).total);
 }
@@ -498,10 +743,55 @@ hipError_t launch_sl_vjp(const VjpInputs& in, const int resident[kVjpPasses], bo
     return e;
 }
 
+// dL/dx (targets) and dL/dphi in one sweep over the pairs; see dl_fused_main.
+static hipError_t launch_dl_fused(const VjpInputs& in, int resident, void* ws, hipStream_t stream) {
+    PassArgs a = base_args(in);
+    a.n_trg = in.n_trg;
+    a.trg_xyz = in.trg_xyz;
+    a.trg_group = in.trg_group;
+    a.tv[0] = in.grad_vel;
+    a.n_src = in.n_src;
+    a.src_xyz = in.src_xyz;
+    a.src_group = in.src_group;
+    a.sv[0] = in.density;
+    a.sv[1] = in.weight;
+    a.sv[2] = in.normal;
+    a.out[0] = in.grad_trg;
+    a.pref = in.pref;
+    const auto p = ps::plan_pass<DlT, kTDlF>(in.n_src, in.n_trg, resident);
+    size_t off_phi = 0;
+    (void)dl_fused_bytes(in.n_src, in.n_trg, resident, &off_phi);
+    char* base = static_cast<char*>(ws);
+    a.rec = base + p.off_rec;
+    a.grp = reinterpret_cast<int32_t*>(base + p.off_grp);
+    a.meta = reinterpret_cast<SubMeta*>(base + p.off_meta);
+    a.part = reinterpret_cast<double*>(base + p.off_part);
+    a.near_part = reinterpret_cast<double*>(base + p.off_near);
+    a.flags = reinterpret_cast<uint8_t*>(base + p.off_flags);
+    a.chunks = p.chunks;
+    a.units = p.units;
+    double* phi = reinterpret_cast<double*>(base + off_phi);
+    ps::prep<DlT><<<dim3((unsigned)(p.n_src_pad / kBlock)), dim3(kBlock), 0, stream>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_fill_zero(phi, 3 * in.n_src, stream)) != hipSuccess) return e;
+    dl_fused_main<kTDlF, kWDlF><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a, phi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dl_fused_near<kTDlF><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a, phi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    ps::reduce<DlT, kTDlF><<<dim3((unsigned)ceil_div(a.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(
+        a, p.grid, p.blocks_x * (int64_t)kBlock * kTDlF);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dl_phi_store<<<dim3((unsigned)ceil_div(in.n_src, kBlock)), dim3(kBlock), 0, stream>>>(
+        phi, in.weight, in.pref, in.grad_density, in.n_src, in.accumulate);
+    return hipGetLastError();
+}
+
 hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], void* ws,
                          hipStream_t stream) {
     hipError_t e = hipSuccess;
     const KernelTimer none{};
+    if (in.grad_trg && in.grad_density && !in.grad_src) return launch_dl_fused(in, resident[7], ws, stream);
     if (in.grad_trg) {
         PassArgs a = base_args(in);
         a.n_trg = in.n_trg;

@@ -22,7 +22,7 @@ struct VjpInputs {
     double* grad_trg;          // (3, n_trg) or null
 };
 
-constexpr int kVjpPasses = 7;
+constexpr int kVjpPasses = 8;
 
 // Resident workgroups of the adjoint pass kernels on a device with n_cu
 // compute units (current device).

@@ -59,6 +59,27 @@ def test_dl_vjp_general(excl, sizes):
 
 
 @pytest.mark.parametrize("excl", [True, False])
+@pytest.mark.parametrize("sizes", [(1000, 777), (257, 1), (1, 300), (3001, 2049)])
+def test_dl_vjp_density_and_target_fused(excl, sizes):
+    """dL/dphi with dL/dx (no dL/dy): one sweep over the pairs gives both, the
+    density gradient summed across target blocks; also accumulates."""
+    print(f"case dl_vjp fused excl={excl} sizes={sizes}", flush=True)
+    c = _cloud(90 + sizes[1], *sizes)
+    rng = np.random.default_rng(4)
+    ns, nt = sizes
+    g = rng.standard_normal((3, nt))
+    base_p, base_t = rng.standard_normal((3, ns)), rng.standard_normal((3, nt))
+    gp, gt = dev(base_p.copy()), dev(base_t.copy())
+    S.dl_vjp(dev(c["y"]), dev(c["f"]), dev(c["w"]), dev(c["n"]), dev(c["x"]), dev(g),
+             src_group=dev(c["gs"]), trg_group=dev(c["gt"]), exclude_same_group=excl,
+             grad_phi=gp, grad_trg=gt, accumulate=True)
+    rp, _, rt = O.dl_vjp(c["y"], c["f"], c["w"], c["n"], c["x"], g, src_group=c["gs"],
+                         trg_group=c["gt"], exclude_same_group=excl, want=("phi", "trg"))
+    assert_close(host(gp) - base_p, rp, VJP_TOL, "fused dL/dphi")
+    assert_close(host(gt) - base_t, rt, VJP_TOL, "fused dL/dtrg")
+
+
+@pytest.mark.parametrize("excl", [True, False])
 @pytest.mark.parametrize("n", [1000, 2500])
 def test_sl_vjp_shared_fused(excl, n):
     """Shared point set, one combined position gradient: one fused pass."""
@@ -186,28 +207,37 @@ def test_cfg3_central_differences(cfg3):
     rng = np.random.default_rng(333)
     flat = rng.choice(3 * n, size=64, replace=False)
     h = 1e-6
-    worst = 0.0
-    for k, fl in enumerate(flat):
-        i, j = divmod(int(fl), n)
-        which = "pos" if k % 2 == 0 else "f"
+
+    def central(which, i, j, step):
         base = cells.pos if which == "pos" else f
         p, m = base.copy(), base.copy()
-        p[i, j] += h
-        m[i, j] -= h
+        p[i, j] += step
+        m[i, j] -= step
         if which == "pos":
             up = S.sl(dev(p), ft, wt, dev(p), src_group=grp, trg_group=grp)
             um = S.sl(dev(m), ft, wt, dev(m), src_group=grp, trg_group=grp)
-            ad = gpos_h[i, j]
         else:
             up = S.sl(pos0, dev(p), wt, pos0, src_group=grp, trg_group=grp)
             um = S.sl(pos0, dev(m), wt, pos0, src_group=grp, trg_group=grp)
-            ad = gf_h[i, j]
-        fd = float(((up - um) * (0.5 * (up + um) - uref)).sum().item()) / (2 * h)
-        scale = np.abs(gpos_h if which == "pos" else gf_h).max()
-        err = abs(fd - ad) / (abs(ad) + 1e-3 * scale)
-        worst = max(worst, err)
-        assert err < 1e-5, (which, i, j, fd, ad)
-    print(f"cfg3 FD: worst relative difference {worst:.3e} over 64 coordinates")
+        return float(((up - um) * (0.5 * (up + um) - uref)).sum().item()) / (2 * step)
+
+    # At h = 1e-6 the quotient's error is the rounding of the forward sums
+    # (its truncation error is ~h^2 smaller); the same quotient at 2h has
+    # truncation error of the same negligible size, so their largest
+    # difference over the 64 coordinates measures that rounding noise.
+    rows = []
+    for k, fl in enumerate(flat):
+        i, j = divmod(int(fl), n)
+        which = "pos" if k % 2 == 0 else "f"
+        ad = gpos_h[i, j] if which == "pos" else gf_h[i, j]
+        rows.append((which, i, j, ad, central(which, i, j, h), central(which, i, j, 2 * h)))
+    noise = max(abs(f1 - f2) for *_, f1, f2 in rows)
+    worst = 0.0
+    for which, i, j, ad, f1, _ in rows:
+        bound = 1e-5 * abs(ad) + 4 * noise
+        worst = max(worst, abs(f1 - ad) / bound)
+        assert abs(f1 - ad) <= bound, (which, i, j, f1, ad, noise)
+    print(f"cfg3 FD: rounding noise {noise:.2e}; worst |fd - adjoint| / bound {worst:.3f} over 64 coordinates")
 
 
 # ---------------------------------------------------------------- cfg5 wall adjoint
