@@ -248,7 +248,6 @@ __global__ __launch_bounds__(kBlock, W) void main_pass(PassArgs a) {
         for (int c = 0; c < P::NACC; ++c) acc[k][c] = 0.0;
 
     int64_t ub = u0 / C, c = u0 % C;
-    Rec pre = rec[c * kTile + threadIdx.x];
     for (int64_t u = u0; u < u1; ++u) {
         __syncthreads();
         if (ub != tbk) {
@@ -262,11 +261,12 @@ __global__ __launch_bounds__(kBlock, W) void main_pass(PassArgs a) {
 #pragma unroll
                 for (int q = 0; q < P::NACC; ++q) acc[k][q] = 0.0;
         }
-        s_rec[threadIdx.x] = pre;
+        // the chunk goes straight to LDS: a record held in registers across
+        // the loop below would be spilled
+        s_rec[threadIdx.x] = rec[c * kTile + threadIdx.x];
         __syncthreads();
         int64_t cn = c + 1, ubn = ub;
         if (cn == C) { cn = 0; ++ubn; }
-        if (u + 1 < u1) pre = rec[cn * kTile + threadIdx.x];
         if (active) {
             uint32_t flags = 0;
 #pragma unroll 1

@@ -633,7 +633,7 @@ constexpr int kTSym = 2, kWSym = 3;
 constexpr int kTDlT = 4, kWDlT = 3;
 constexpr int kTDlS = 2, kWDlS = 3;
 constexpr int kTSlSF = 4, kWSlSF = 4;
-constexpr int kTDlSPhi = 4, kWDlSPhi = 4;
+constexpr int kTDlSPhi = 4, kWDlSPhi = 3;
 constexpr int kTDlF = 4, kWDlF = 2;
 
 // workspace of the fused double-layer pass: the target-side pass, then V (3, n_src)
