@@ -371,19 +371,6 @@ __device__ __forceinline__ void double_targets(Targets<T>& t, Box* w) {
 #define STOKES_DIRECT_W32 4
 #endif
 
-// Copy of lane j's value of a register-resident record, for every lane
-// (v_readlane per dword; j must be wave-uniform).
-template <typename R>
-__device__ __forceinline__ R lane_bcast(const R& v, int j) {
-    static_assert(sizeof(R) % 4 == 0, "record must be whole dwords");
-    R out;
-    const int* src = reinterpret_cast<const int*>(&v);
-    int* dst = reinterpret_cast<int*>(&out);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(R) / 4); ++i) dst[i] = __builtin_amdgcn_readlane(src[i], j);
-    return out;
-}
-
 // Iterates the flagged sub-tiles of one wave's flag row: 64 flag bytes are
 // read at once (one per lane) and the nonzero ones visited in order.
 template <typename F>
@@ -478,6 +465,9 @@ template <int KT, int T>
 __global__ __launch_bounds__(kBlock) void direct_near_f64(DirectArgs a) {
     using Rec = typename SrcRec<KT, 0>::type;
     constexpr int BT = kBlock * T;
+    // per-wave staging slice of the current sub-tile (see direct_near_mixed)
+    __shared__ Rec s_src[4][kSub];
+    __shared__ int32_t s_grp[4][kSub];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t tbk = blockIdx.x, C = a.chunks;
@@ -494,18 +484,19 @@ __global__ __launch_bounds__(kBlock) void direct_near_f64(DirectArgs a) {
     for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
     const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
     for_each_flagged(fl, C, lane, [&](int64_t sub) {
-        // lane j holds source j of the sub-tile; the loop broadcasts it
-        const Rec mine = rec[sub * kSub + lane];
-        const int32_t mine_g = grp[sub * kSub + lane];
+        s_src[wave][lane] = rec[sub * kSub + lane];
+        s_grp[wave][lane] = grp[sub * kSub + lane];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll 2
         for (int j = 0; j < kSub; ++j) {
-            const Rec sr = lane_bcast(mine, j);
-            const int32_t gs = __builtin_amdgcn_readlane(mine_g, j);
+            const Rec sr = s_src[wave][j];
+            const int32_t gs = s_grp[wave][j];
 #pragma unroll
             for (int k = 0; k < T; ++k)
                 pair_f64<KT, true>(sr, t.x[k], t.y[k], t.z[k], excl && gs == t.g[k], ax[k], ay[k],
                                    az[k]);
         }
+        __builtin_amdgcn_wave_barrier();   // reads of this sub-tile precede the next writes
     });
     const int64_t np = (int64_t)gridDim.x * BT;
 #pragma unroll
@@ -661,6 +652,11 @@ template <int KT, int T>
 __global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
     using Rec = typename SrcRec<KT, 1>::type;
     constexpr int BT = kBlock * T;
+    // each wave stages its current sub-tile in its own slice (read back by
+    // broadcast into VGPRs; only that wave touches it, and a wave's LDS
+    // operations complete in order, so no workgroup barrier is needed)
+    __shared__ Rec s_src[4][kSub];
+    __shared__ float4 s_res[4][kSub];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t tbk = blockIdx.x, C = a.chunks;
@@ -687,13 +683,13 @@ __global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
             zl[k] = (float)(hz - (double)zs[k]);
             bx[k] = by[k] = bz[k] = 0.0f;
         }
-        // lane j holds source j of the sub-tile; the loop broadcasts it
-        const Rec mine = rec[sub * kSub + lane];
-        const float4 mine_lo = lo[sub * kSub + lane];
+        s_src[wave][lane] = rec[sub * kSub + lane];
+        s_res[wave][lane] = lo[sub * kSub + lane];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll 2
         for (int j = 0; j < kSub; ++j) {
-            const Rec sr = lane_bcast(mine, j);
-            const float4 sl = lane_bcast(mine_lo, j);
+            const Rec sr = s_src[wave][j];
+            const float4 sl = s_res[wave][j];
 #pragma unroll
             for (int k = 0; k < T; ++k) {
                 // r = (x_hi - y_hi) + (x_lo - y_lo): the high difference is
@@ -716,6 +712,7 @@ __global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
             ay[k] += (double)by[k];
             az[k] += (double)bz[k];
         }
+        __builtin_amdgcn_wave_barrier();   // reads of this sub-tile precede the next writes
     });
     const int64_t np = (int64_t)gridDim.x * BT;
 #pragma unroll
