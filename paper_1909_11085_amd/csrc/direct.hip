@@ -82,7 +82,7 @@ struct DirectArgs {
     int64_t units;            // target blocks x chunks
     double* part;             // partial sums, one segment per (block, target block) pair
     uint8_t* flags;           // per (wave, chunk): bit s = sub-tile s left to the near pass
-    double* near_part;        // near-pass sums, (3, blocks_x * kBlock * T)
+    double* near_part;        // near-pass sums, (kNearSlices, 3, blocks_x * kBlock * T)
 };
 
 // ---------------------------------------------------------------------------
@@ -371,10 +371,14 @@ __device__ __forceinline__ void double_targets(Targets<T>& t, Box* w) {
 #define STOKES_DIRECT_W32 4
 #endif
 
-// Iterates the flagged sub-tiles of one wave's flag row: 64 flag bytes are
-// read at once (one per lane) and the nonzero ones visited in order.
+// Iterates the flagged sub-tiles of one wave's flag row (64 flag bytes are
+// read per step, one per lane); the near pass splits each row into
+// kNearSlices interleaved slices, one per grid row, for balance.
+constexpr int kNearSlices = 4;
 template <typename F>
-__device__ __forceinline__ void for_each_flagged(const uint8_t* fl, int64_t C, int lane, F&& fn) {
+__device__ __forceinline__ void for_each_flagged(const uint8_t* fl, int64_t C, int lane, int slice,
+                                                 F&& fn) {
+    int n = 0;                                 // flagged sub-tiles seen so far (uniform)
     for (int64_t c0 = 0; c0 < C; c0 += kWave) {
         const uint32_t mine = (c0 + lane < C) ? fl[c0 + lane] : 0u;
         uint64_t nz = __ballot(mine != 0);
@@ -385,7 +389,7 @@ __device__ __forceinline__ void for_each_flagged(const uint8_t* fl, int64_t C, i
             while (f) {
                 const int s = __builtin_ctz(f);
                 f &= f - 1;
-                fn((c0 + l) * 4 + s);
+                if (n++ % kNearSlices == slice) fn((c0 + l) * 4 + s);
             }
         }
     }
@@ -483,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void direct_near_f64(DirectArgs a) {
 #pragma unroll
     for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
     const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
-    for_each_flagged(fl, C, lane, [&](int64_t sub) {
+    for_each_flagged(fl, C, lane, (int)blockIdx.y, [&](int64_t sub) {
         s_src[wave][lane] = rec[sub * kSub + lane];
         s_grp[wave][lane] = grp[sub * kSub + lane];
         __builtin_amdgcn_wave_barrier();
@@ -499,12 +503,13 @@ __global__ __launch_bounds__(kBlock) void direct_near_f64(DirectArgs a) {
         __builtin_amdgcn_wave_barrier();   // reads of this sub-tile precede the next writes
     });
     const int64_t np = (int64_t)gridDim.x * BT;
+    double* np_slice = a.near_part + (int64_t)blockIdx.y * 3 * np;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
-        a.near_part[gi] = ax[k];
-        a.near_part[np + gi] = ay[k];
-        a.near_part[2 * np + gi] = az[k];
+        np_slice[gi] = ax[k];
+        np_slice[np + gi] = ay[k];
+        np_slice[2 * np + gi] = az[k];
     }
 }
 
@@ -671,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
 #pragma unroll
     for (int k = 0; k < T; ++k) ax[k] = ay[k] = az[k] = 0.0;
     const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
-    for_each_flagged(fl, C, lane, [&](int64_t sub) {
+    for_each_flagged(fl, C, lane, (int)blockIdx.y, [&](int64_t sub) {
         const SubMeta m = a.meta[sub];
         float xs[T], ys[T], zs[T], xl[T], yl[T], zl[T], bx[T], by[T], bz[T];
 #pragma unroll
@@ -715,12 +720,13 @@ __global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
         __builtin_amdgcn_wave_barrier();   // reads of this sub-tile precede the next writes
     });
     const int64_t np = (int64_t)gridDim.x * BT;
+    double* np_slice = a.near_part + (int64_t)blockIdx.y * 3 * np;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
-        a.near_part[gi] = ax[k];
-        a.near_part[np + gi] = ay[k];
-        a.near_part[2 * np + gi] = az[k];
+        np_slice[gi] = ax[k];
+        np_slice[np + gi] = ay[k];
+        np_slice[2 * np + gi] = az[k];
     }
 }
 
@@ -750,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void reduce_segments(const double* __restri
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        s[c] += near_part[c * np + i];
+        for (int sl = 0; sl < kNearSlices; ++sl) s[c] += near_part[(sl * 3 + c) * np + i];
         const int64_t o = c * n_trg + i;
         out[o] = accumulate ? out[o] + pref * s[c] : pref * s[c];
     }
@@ -812,7 +818,7 @@ DirectPlan plan_direct(int kernel, int mixed, int64_t n_src, int64_t n_trg, int 
     p.off_part = off;
     off = align_up(off + (size_t)(p.grid + p.blocks_x) * 3 * bt * sizeof(double), 256);
     p.off_near = off;
-    off = align_up(off + (size_t)p.blocks_x * 3 * bt * sizeof(double), 256);
+    off = align_up(off + (size_t)kNearSlices * p.blocks_x * 3 * bt * sizeof(double), 256);
     p.off_flags = off;
     off = align_up(off + (size_t)p.blocks_x * 4 * (size_t)p.chunks, 256);
     p.total = off;
@@ -850,9 +856,9 @@ static hipError_t launch_typed(const SumInputs& in, const DirectPlan& p, double*
     if (timer.on()) (void)hipEventRecord(timer.stop, stream);
     if (e != hipSuccess) return e;
     if constexpr (MIXED != 0)
-        direct_near_mixed<KT, T><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a);
+        direct_near_mixed<KT, T><<<dim3((unsigned)p.blocks_x, kNearSlices), dim3(kBlock), 0, stream>>>(a);
     else
-        direct_near_f64<KT, T><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a);
+        direct_near_f64<KT, T><<<dim3((unsigned)p.blocks_x, kNearSlices), dim3(kBlock), 0, stream>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // FP64 pair sums are 4x (single layer) or 8x (double layer) the bare sums
