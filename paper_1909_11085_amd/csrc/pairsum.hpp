@@ -10,8 +10,8 @@
 //     broadcast; per sub-tile a uniform test (a target of the wave inside the
 //     sub-tile box, or a shared group id) sends it to the near pass, every
 //     other sub-tile runs the unmasked loop;
-//   * near: the flagged sub-tiles with per-pair masks (records broadcast from
-//     registers with v_readlane);
+//   * near: the flagged sub-tiles with per-pair masks (each wave stages its
+//     sub-tile in LDS), in kNearSlices grid rows;
 //   * reduce: fixed-order sum of segments and near partials, then the
 //     policy's store (scaling, accumulate, output mapping).
 //
@@ -94,15 +94,30 @@ __device__ __forceinline__ double rinv_masked(double r2, bool skip) {
     return __builtin_fma(0.5 * y0, e, y0);
 }
 
-template <typename R>
-__device__ __forceinline__ R bcast(const R& v, int j) {
-    static_assert(sizeof(R) % 4 == 0, "record must be whole dwords");
-    R out;
-    const int* src = reinterpret_cast<const int*>(&v);
-    int* dst = reinterpret_cast<int*>(&out);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(R) / 4); ++i) dst[i] = __builtin_amdgcn_readlane(src[i], j);
-    return out;
+// The near pass takes each wave's flagged sub-tiles in kNearSlices
+// interleaved slices (one per grid row, for balance), each writing its own
+// partials; the reduction adds the slices in a fixed order.
+constexpr int kNearSlices = 4;
+
+// Visits the flagged sub-tiles of one wave's flag row that fall in `slice`.
+template <typename F>
+__device__ __forceinline__ void for_each_flagged(const uint8_t* fl, int64_t C, int lane, int slice,
+                                                 F&& fn) {
+    int n = 0;                                 // flagged sub-tiles seen so far (uniform)
+    for (int64_t c0 = 0; c0 < C; c0 += kWave) {
+        const uint32_t mine = (c0 + lane < C) ? fl[c0 + lane] : 0u;
+        uint64_t nz = __ballot(mine != 0);
+        while (nz) {
+            const int l = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)mine, l);
+            while (f) {
+                const int s = __builtin_ctz(f);
+                f &= f - 1;
+                if (n++ % kNearSlices == slice) fn((c0 + l) * 4 + s);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -298,6 +313,11 @@ template <class P, int T>
 __global__ __launch_bounds__(kBlock) void near_pass(PassArgs a) {
     using Rec = typename P::Rec;
     constexpr int BT = kBlock * T;
+    // each wave stages its current sub-tile in its own slice (read back by
+    // broadcast; only that wave touches it, and a wave's LDS operations
+    // complete in order, so no workgroup barrier is needed)
+    __shared__ Rec s_src[4][kSub];
+    __shared__ int32_t s_grp[4][kSub];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t tbk = blockIdx.x, C = a.chunks;
@@ -313,37 +333,27 @@ __global__ __launch_bounds__(kBlock) void near_pass(PassArgs a) {
 #pragma unroll
         for (int q = 0; q < P::NACC; ++q) acc[k][q] = 0.0;
     const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
-    for (int64_t c0 = 0; c0 < C; c0 += kWave) {
-        const uint32_t mine = (c0 + lane < C) ? fl[c0 + lane] : 0u;
-        uint64_t nz = __ballot(mine != 0);
-        while (nz) {
-            const int l = __builtin_ctzll(nz);
-            nz &= nz - 1;
-            uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)mine, l);
-            while (f) {
-                const int s = __builtin_ctz(f);
-                f &= f - 1;
-                const int64_t sub = (c0 + l) * 4 + s;
-                const Rec mr = rec[sub * kSub + lane];
-                const int32_t mg = a.grp[sub * kSub + lane];
+    for_each_flagged(fl, C, lane, (int)blockIdx.y, [&](int64_t sub) {
+        s_src[wave][lane] = rec[sub * kSub + lane];
+        s_grp[wave][lane] = a.grp[sub * kSub + lane];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll 2
-                for (int j = 0; j < kSub; ++j) {
-                    const Rec sr = bcast(mr, j);
-                    const int32_t gs = __builtin_amdgcn_readlane(mg, j);
+        for (int j = 0; j < kSub; ++j) {
+            const Rec sr = s_src[wave][j];
+            const int32_t gs = s_grp[wave][j];
 #pragma unroll
-                    for (int k = 0; k < T; ++k)
-                        P::template pair<true>(sr, t.x[k], t.y[k], t.z[k], t.v[k],
-                                               excl && gs == t.g[k], acc[k]);
-                }
-            }
+            for (int k = 0; k < T; ++k)
+                P::template pair<true>(sr, t.x[k], t.y[k], t.z[k], t.v[k], excl && gs == t.g[k], acc[k]);
         }
-    }
+        __builtin_amdgcn_wave_barrier();   // reads of this sub-tile precede the next writes
+    });
     const int64_t np = (int64_t)gridDim.x * BT;
+    double* part = a.near_part + (int64_t)blockIdx.y * P::NACC * np;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
 #pragma unroll
-        for (int q = 0; q < P::NACC; ++q) a.near_part[q * np + gi] = acc[k][q];
+        for (int q = 0; q < P::NACC; ++q) part[q * np + gi] = acc[k][q];
     }
 }
 
@@ -363,8 +373,9 @@ __global__ __launch_bounds__(kBlock) void reduce(PassArgs a, int64_t grid, int64
 #pragma unroll
         for (int q = 0; q < P::NACC; ++q) s[q] += seg[q * BT + li];
     }
+    for (int sl = 0; sl < kNearSlices; ++sl)
 #pragma unroll
-    for (int q = 0; q < P::NACC; ++q) s[q] += a.near_part[q * np + i];
+        for (int q = 0; q < P::NACC; ++q) s[q] += a.near_part[(sl * P::NACC + q) * np + i];
     P::store(a, i, s);
 }
 
@@ -396,7 +407,7 @@ PassPlan plan_pass(int64_t n_src, int64_t n_trg, int resident) {
     p.off_part = off;
     off = align_up(off + (size_t)(p.grid + p.blocks_x) * P::NACC * bt * sizeof(double), 256);
     p.off_near = off;
-    off = align_up(off + (size_t)p.blocks_x * P::NACC * bt * sizeof(double), 256);
+    off = align_up(off + (size_t)kNearSlices * p.blocks_x * P::NACC * bt * sizeof(double), 256);
     p.off_flags = off;
     off = align_up(off + (size_t)p.blocks_x * 4 * (size_t)p.chunks, 256);
     p.total = off;
@@ -433,7 +444,7 @@ hipError_t run_pass(PassArgs a, const PassPlan& p, void* ws, hipStream_t stream,
     e = hipGetLastError();
     if (timer.on()) (void)hipEventRecord(timer.stop, stream);
     if (e != hipSuccess) return e;
-    near_pass<P, T><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a);
+    near_pass<P, T><<<dim3((unsigned)p.blocks_x, kNearSlices), dim3(kBlock), 0, stream>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     reduce<P, T><<<dim3((unsigned)ceil_div(a.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(

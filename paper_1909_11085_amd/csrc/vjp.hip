@@ -549,6 +549,8 @@ __global__ __launch_bounds__(kBlock) void dl_fused_near(PassArgs a, double* __re
     using P = DlT;
     using Rec = P::Rec;
     constexpr int BT = kBlock * T;
+    __shared__ Rec s_src[4][kSub];                 // per-wave staging (see ps::near_pass)
+    __shared__ int32_t s_grp[4][kSub];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t tbk = blockIdx.x, C = a.chunks;
@@ -565,50 +567,41 @@ __global__ __launch_bounds__(kBlock) void dl_fused_near(PassArgs a, double* __re
 #pragma unroll
         for (int q = 0; q < P::NACC; ++q) acc[k][q] = 0.0;
     const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
-    for (int64_t c0 = 0; c0 < C; c0 += kWave) {
-        const uint32_t mine = (c0 + lane < C) ? fl[c0 + lane] : 0u;
-        uint64_t nz = __ballot(mine != 0);
-        while (nz) {
-            const int l = __builtin_ctzll(nz);
-            nz &= nz - 1;
-            uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)mine, l);
-            while (f) {
-                const int s = __builtin_ctz(f);
-                f &= f - 1;
-                const int64_t sub = (c0 + l) * 4 + s;
-                const Rec mr = rec[sub * kSub + lane];
-                const int32_t mg = a.grp[sub * kSub + lane];
+    ps::for_each_flagged(fl, C, lane, (int)blockIdx.y, [&](int64_t sub) {
+        s_src[wave][lane] = rec[sub * kSub + lane];
+        s_grp[wave][lane] = a.grp[sub * kSub + lane];
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
-                for (int j0 = 0; j0 < kSub; j0 += 4) {
-                    double v[4][3];
+        for (int j0 = 0; j0 < kSub; j0 += 4) {
+            double v[4][3];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i][0] = v[i][1] = v[i][2] = 0.0;
+            for (int i = 0; i < 4; ++i) v[i][0] = v[i][1] = v[i][2] = 0.0;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const Rec sr = ps::bcast(mr, j0 + i);
-                        const int32_t gs = __builtin_amdgcn_readlane(mg, j0 + i);
+            for (int i = 0; i < 4; ++i) {
+                const Rec sr = s_src[wave][j0 + i];
+                const int32_t gs = s_grp[wave][j0 + i];
 #pragma unroll
-                        for (int k = 0; k < T; ++k)
-                            P::template pair<true, true>(sr, t.x[k], t.y[k], t.z[k], t.v[k],
-                                                         excl && gs == t.g[k], acc[k], v[i]);
-                    }
-                    double tot[3];
-                    wave_sum4x3(v, lane, tot);
-                    const int64_t src = sub * kSub + j0 + (lane >> 4);
-                    if ((lane & 15) == 0 && src < a.n_src)
-#pragma unroll
-                        for (int q = 0; q < 3; ++q)
-                            if (tot[q] != 0.0) unsafeAtomicAdd(phi + q * a.n_src + src, tot[q]);
-                }
+                for (int k = 0; k < T; ++k)
+                    P::template pair<true, true>(sr, t.x[k], t.y[k], t.z[k], t.v[k],
+                                                 excl && gs == t.g[k], acc[k], v[i]);
             }
+            double tot[3];
+            wave_sum4x3(v, lane, tot);
+            const int64_t src = sub * kSub + j0 + (lane >> 4);
+            if ((lane & 15) == 0 && src < a.n_src)
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (tot[q] != 0.0) unsafeAtomicAdd(phi + q * a.n_src + src, tot[q]);
         }
-    }
+        __builtin_amdgcn_wave_barrier();           // reads of this sub-tile precede the next writes
+    });
     const int64_t np = (int64_t)gridDim.x * BT;
+    double* part = a.near_part + (int64_t)blockIdx.y * P::NACC * np;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
 #pragma unroll
-        for (int q = 0; q < P::NACC; ++q) a.near_part[q * np + gi] = acc[k][q];
+        for (int q = 0; q < P::NACC; ++q) part[q * np + gi] = acc[k][q];
     }
 }
 
@@ -777,7 +770,7 @@ static hipError_t launch_dl_fused(const VjpInputs& in, int resident, void* ws, h
     if ((e = launch_fill_zero(phi, 3 * in.n_src, stream)) != hipSuccess) return e;
     dl_fused_main<kTDlF, kWDlF><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a, phi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    dl_fused_near<kTDlF><<<dim3((unsigned)p.blocks_x), dim3(kBlock), 0, stream>>>(a, phi);
+    dl_fused_near<kTDlF><<<dim3((unsigned)p.blocks_x, ps::kNearSlices), dim3(kBlock), 0, stream>>>(a, phi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     ps::reduce<DlT, kTDlF><<<dim3((unsigned)ceil_div(a.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(
         a, p.grid, p.blocks_x * (int64_t)kBlock * kTDlF);
