@@ -32,7 +32,10 @@
  * Evaluations are asynchronous on it; the context is read-only after
  * creation, so calls with distinct outputs and workspaces may run
  * concurrently.  FP64 results are deterministic: fixed summation order, no
- * floating-point atomics.
+ * floating-point atomics.  One exception: grad_density of stokes_dl_vjp
+ * when it comes from the fused pass (see there) is summed across target
+ * blocks with float64 atomic adds, so it may differ in the last bits from
+ * run to run.
  *
  * Errors.  Every call returns a status code.  Arguments are validated on the
  * host before anything is launched; a failed call launches nothing and
@@ -237,7 +240,10 @@ int stokes_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const d
  *   grad_src_xyz (3,n_src): dL/dy_m   = -d sum_n' G_nm
  *   grad_trg_xyz (3,n_trg): dL/dx_n   =  d sum_m' G_nm
  *   G = [(r.q)(r.g) n + (r.n)(r.g) q + (r.n)(r.q) g]/rho^5 - 5 (r.n)(r.q)(r.g) r/rho^7.
- * Outputs, precision and empty sets as stokes_sl_vjp (no fused pass). */
+ * Outputs, precision and empty sets as stokes_sl_vjp.  When grad_density and
+ * grad_trg_xyz are asked for without grad_src_xyz, one fused pass over the
+ * pairs gives both; its grad_density is summed across target blocks with
+ * float64 atomic adds (not bitwise reproducible from run to run). */
 int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
                   const double* weight, const double* normal, int64_t n_trg,
                   const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,

@@ -1,0 +1,174 @@
+"""C-ABI contract on a GPU context: every rejected call returns the status the
+header documents, names the problem in stokes_last_error(), launches nothing
+and leaves its outputs untouched; accepted calls with the same buffers work.
+The calls go through the raw C entry points (ctypes), not the Python layer,
+so the library's own validation is what is tested."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1909_11085_amd import _capi as C
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+NS, NT = 300, 200
+SENTINEL = 7.0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    h = ctypes.c_void_p()
+    assert C.lib().stokes_create(ctypes.byref(h), 0) == C.OK, C.lib().stokes_last_error()
+    yield h
+    C.lib().stokes_destroy(h)
+
+
+def _p(t, offset=0):
+    return ctypes.c_void_p(t.data_ptr() + offset)
+
+
+def _data():
+    rng = np.random.default_rng(0)
+    d = dict(y=dev(rng.standard_normal((3, NS))), f=dev(rng.standard_normal((3, NS))),
+             w=dev(rng.uniform(0.5, 1.0, NS)), n=dev(rng.standard_normal((3, NS))),
+             x=dev(rng.standard_normal((3, NT))), g=dev(rng.integers(0, 4, NS).astype(np.int32)),
+             gt=dev(rng.integers(0, 4, NT).astype(np.int32)), h=dev(np.full(4, 0.3)),
+             gv=dev(rng.standard_normal((3, NT))))
+    d["out"] = torch.full((3, NT), SENTINEL, dtype=torch.float64, device=d["x"].device)
+    return d
+
+
+def _ws(ctx, op, ns=NS, nt=NT, precision=C.FP64, n_leaves=0):
+    size = ctypes.c_size_t()
+    opts = C.Opts(precision, 0)
+    assert C.lib().stokes_workspace_size(ctx, op, ns, nt, n_leaves, ctypes.byref(opts),
+                                         ctypes.byref(size)) == C.OK
+    ws = torch.empty(size.value + 512, dtype=torch.uint8, device="cuda")
+    assert ws.data_ptr() % 256 == 0
+    return ws, size.value
+
+
+def _sl(ctx, d, ws, ws_bytes, *, y=None, out=None, ns=NS, nt=NT, mu=1.0, excl=None, opts=None):
+    return C.lib().stokes_sl_eval(ctx, ns, y if y is not None else _p(d["y"]), _p(d["f"]), _p(d["w"]), nt,
+                                  _p(d["x"]), mu, ctypes.byref(excl) if excl else None,
+                                  ctypes.byref(opts) if opts else None,
+                                  out if out is not None else _p(d["out"]), ws, ws_bytes, None)
+
+
+def _rejected(rc, status, word, d):
+    """The call failed with `status`, its message mentions `word`, and the
+    output still holds the sentinel (nothing was launched)."""
+    assert rc == status, (rc, C.lib().stokes_last_error())
+    assert word.encode() in C.lib().stokes_last_error(), C.lib().stokes_last_error()
+    torch.cuda.synchronize()
+    assert bool((d["out"] == SENTINEL).all())
+
+
+def test_direct_sum_rejections(ctx):
+    d = _data()
+    ws, need = _ws(ctx, C.OP_SL)
+    assert need > 0
+    L = C.lib()
+    _rejected(_sl(ctx, d, _p(ws), need - 1), C.EWORKSPACE, "too small", d)
+    _rejected(_sl(ctx, d, None, 0), C.EWORKSPACE, "NULL", d)
+    _rejected(_sl(ctx, d, _p(ws, 8), need), C.EWORKSPACE, "aligned", d)
+    _rejected(_sl(ctx, d, _p(ws), need, y=_p(d["y"], 4)), C.EINVAL, "src_xyz", d)
+    _rejected(_sl(ctx, d, _p(ws), need, ns=-1), C.EINVAL, "point counts", d)
+    _rejected(_sl(ctx, d, _p(ws), need, ns=(1 << 30) + 1), C.EUNSUPPORTED, "STOKES_MAX_POINTS", d)
+    _rejected(_sl(ctx, d, _p(ws), need, out=_p(d["y"])), C.EINVAL, "overlap", d)
+    _rejected(_sl(ctx, d, _p(ws), need, opts=C.Opts(5, 0)), C.EINVAL, "precision", d)
+    _rejected(_sl(ctx, d, _p(ws), need, opts=C.Opts(C.FP64, 2)), C.EINVAL, "accumulate", d)
+    _rejected(_sl(ctx, d, _p(ws), need, excl=C.Exclusion(3, None, None, None, 0, 0.0)), C.EINVAL, "mode", d)
+    _rejected(_sl(ctx, d, _p(ws), need, excl=C.Exclusion(C.EXCL_SAME_GROUP, None, _p(d["gt"]), None, 0, 0.0)),
+              C.EINVAL, "src_group", d)
+    _rejected(_sl(ctx, d, _p(ws), need, mu=-2.0), C.EINVAL, "mu", d)
+    mixed = C.Opts(C.MIXED, 0)
+    wsm, needm = _ws(ctx, C.OP_SL, precision=C.MIXED)
+    _rejected(_sl(ctx, d, _p(wsm), needm, opts=mixed,
+                  excl=C.Exclusion(C.EXCL_NONE, _p(d["g"]), None, _p(d["h"]), 0, 0.5)), C.EINVAL, "n_groups", d)
+    _rejected(_sl(ctx, d, _p(wsm), needm, opts=mixed,
+                  excl=C.Exclusion(C.EXCL_NONE, _p(d["g"]), None, _p(d["h"]), 4, float("nan"))),
+              C.EINVAL, "near_frac", d)
+    # the same buffers in a valid call
+    assert _sl(ctx, d, _p(ws), need) == C.OK, L.stokes_last_error()
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(d["out"]).all()) and not bool((d["out"] == SENTINEL).any())
+
+
+def test_dl_needs_normals(ctx):
+    d = _data()
+    ws, need = _ws(ctx, C.OP_DL)
+    rc = C.lib().stokes_dl_eval(ctx, NS, _p(d["y"]), _p(d["f"]), _p(d["w"]), None, NT, _p(d["x"]), None,
+                                None, _p(d["out"]), _p(ws), need, None)
+    _rejected(rc, C.EINVAL, "normal", d)
+
+
+def test_p2p_rejections(ctx):
+    d = _data()
+    L = C.lib()
+    so = np.array([0, 150, NS], dtype=np.int64)
+    to = np.array([0, 120, NT], dtype=np.int64)
+    uo = np.array([0, 2, 3], dtype=np.int64)
+    ul = np.array([0, 1, 1], dtype=np.int32)
+    plan = ctypes.c_void_p()
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)   # host arrays
+    assert L.stokes_p2p_plan_create(ctx, 2, NS, NT, ptr(so), ptr(to), ptr(uo), ptr(ul), 3,
+                                    ctypes.byref(plan)) == C.OK
+    try:
+        pairs = ctypes.c_int64()
+        assert L.stokes_p2p_plan_pairs(plan, ctypes.byref(pairs)) == C.OK
+        assert pairs.value == 120 * NS + 80 * 150
+        ws, need = _ws(ctx, C.OP_P2P_SL, n_leaves=2)
+
+        def run(kernel=C.KERNEL_SL, ns=NS, normal=None, ws_bytes=need):
+            return L.stokes_p2p_leaf_eval(ctx, plan, kernel, ns, _p(d["y"]), _p(d["f"]), _p(d["w"]), normal,
+                                          NT, _p(d["x"]), 1.0, None, None, _p(d["out"]), _p(ws), ws_bytes,
+                                          None)
+
+        _rejected(run(kernel=4), C.EINVAL, "kernel", d)
+        _rejected(run(ns=NS - 1), C.EINVAL, "plan", d)
+        _rejected(run(kernel=C.KERNEL_DL), C.EINVAL, "normal", d)
+        _rejected(run(ws_bytes=need - 1), C.EWORKSPACE, "too small", d)
+        assert run() == C.OK, L.stokes_last_error()
+        torch.cuda.synchronize()
+        assert not bool((d["out"] == SENTINEL).any())
+    finally:
+        L.stokes_p2p_plan_destroy(plan)
+
+
+def test_vjp_rejections(ctx):
+    d = _data()
+    L = C.lib()
+    ws, need = _ws(ctx, C.OP_SL_VJP)
+    gf = torch.full((3, NS), SENTINEL, dtype=torch.float64, device="cuda")
+    gs = torch.full((3, NS), SENTINEL, dtype=torch.float64, device="cuda")
+
+    def run(grad_vel, grad_f, grad_src, grad_trg):
+        return L.stokes_sl_vjp(ctx, NS, _p(d["y"]), _p(d["f"]), _p(d["w"]), NT, _p(d["x"]), 1.0, None, None,
+                               grad_vel, grad_f, grad_src, grad_trg, _p(ws), need, None)
+
+    _rejected(run(None, _p(gf), None, None), C.EINVAL, "grad_vel", d)
+    # one array for both position gradients only for a shared point set
+    _rejected(run(_p(d["gv"]), None, _p(d["out"]), _p(d["out"])), C.EINVAL, "same point set", d)
+    # overlapping gradient outputs
+    _rejected(run(_p(d["gv"]), _p(gf), _p(gf), None), C.EINVAL, "overlap", d)
+    torch.cuda.synchronize()
+    assert bool((gf == SENTINEL).all()) and bool((gs == SENTINEL).all())
+    assert run(_p(d["gv"]), _p(gf), _p(gs), _p(d["out"])) == C.OK, L.stokes_last_error()
+    torch.cuda.synchronize()
+    for t in (gf, gs, d["out"]):
+        assert bool(torch.isfinite(t).all()) and not bool((t == SENTINEL).any())
+
+
+def test_context_settings(ctx):
+    L = C.lib()
+    assert L.stokes_set_grid_override(ctx, -1) == C.EINVAL
+    assert L.stokes_set_grid_override(ctx, (1 << 20) + 1) == C.EINVAL
+    assert L.stokes_set_grid_override(ctx, 0) == C.OK
+    assert L.stokes_timing_read(ctx, None, None) == C.EINVAL
+    size = ctypes.c_size_t()
+    assert L.stokes_workspace_size(ctx, 9, NS, NT, 0, None, ctypes.byref(size)) == C.EINVAL
+    assert L.stokes_workspace_size(ctx, C.OP_SL, NS, NT, 0, None, None) == C.EINVAL
