@@ -252,7 +252,59 @@ def cylinder_wall(radius=50.0, length=400.0, n_theta=64, n_z=64, q=16):
                     group=np.repeat(np.arange(npatch, dtype=np.int32), q * q),
                     group_h=np.full(npatch, math.sqrt(area_patch / (q * q))),
                     meta=dict(kind="wall", radius=radius, length=length, n_patches=npatch,
-                              points_per_patch=q * q))
+                              points_per_patch=q * q, q=q, nodes_1d=t, weights_1d=wt))
+
+
+# Cube faces as (outward axis, first tangent, second tangent) with t1 x t2 = axis,
+# so that X_u x X_v of every patch points out of the surface.
+_CUBE_FACES = (((1, 0, 0), (0, 1, 0), (0, 0, 1)), ((-1, 0, 0), (0, 0, 1), (0, 1, 0)),
+               ((0, 1, 0), (0, 0, 1), (1, 0, 0)), ((0, -1, 0), (1, 0, 0), (0, 0, 1)),
+               ((0, 0, 1), (1, 0, 0), (0, 1, 0)), ((0, 0, -1), (0, 1, 0), (1, 0, 0)))
+
+
+def cube_sphere(radius=1.0, m=2, q=16, axes=(1.0, 1.0, 1.0), centre=(0.0, 0.0, 0.0)):
+    """Closed patch surface: a sphere (or, with unequal `axes`, an ellipsoid)
+    covered by 6 m^2 tensor-product patches.
+
+    Each face of the cube [-1, 1]^3 is split into m x m squares and mapped to
+    the sphere by the equiangular gnomonic map g = e + tan(pi a/4) t1 +
+    tan(pi b/4) t2, X = centre + radius * axes * g/|g|.  Every patch carries
+    q x q Gauss-Legendre nodes in its own parameter square [-1, 1]^2 (u along
+    t1, v along t2, node k = i*q + j at (t_i, t_j)); weight w = w_i w_j
+    |X_u x X_v| and unit normal X_u x X_v / |X_u x X_v|, both from the exact
+    map, the normal outward.  Points are patch-major (q*q per patch)."""
+    t, wt = np.polynomial.legendre.leggauss(q)
+    S = np.asarray(axes, dtype=np.float64)[:, None]
+    ti, tj = [a.reshape(-1) for a in np.meshgrid(t, t, indexing="ij")]
+    wij = np.outer(wt, wt).reshape(-1)
+    pos, nrm, wts = [], [], []
+    for e, t1, t2 in _CUBE_FACES:
+        e, t1, t2 = (np.asarray(v, dtype=np.float64)[:, None] for v in (e, t1, t2))
+        for a in range(m):
+            for b in range(m):
+                al = 0.25 * np.pi * (-1.0 + (2 * a + 1 + ti) / m)
+                be = 0.25 * np.pi * (-1.0 + (2 * b + 1 + tj) / m)
+                g = e + np.tan(al) * t1 + np.tan(be) * t2
+                gn = np.linalg.norm(g, axis=0)
+                gh = g / gn
+                gu = (0.25 * np.pi / m) / np.cos(al) ** 2 * t1
+                gv = (0.25 * np.pi / m) / np.cos(be) ** 2 * t2
+                Xu = radius * S * (gu - gh * (gh * gu).sum(0)) / gn
+                Xv = radius * S * (gv - gh * (gh * gv).sum(0)) / gn
+                c = np.cross(Xu, Xv, axis=0)
+                cn = np.linalg.norm(c, axis=0)
+                pos.append(np.asarray(centre, dtype=np.float64)[:, None] + radius * S * gh)
+                nrm.append(c / cn)
+                wts.append(wij * cn)
+    npatch = 6 * m * m
+    w = np.concatenate(wts)
+    area = w.reshape(npatch, q * q).sum(1)
+    return PointSet(pos=np.ascontiguousarray(np.concatenate(pos, axis=1)), weight=w,
+                    normal=np.ascontiguousarray(np.concatenate(nrm, axis=1)),
+                    group=np.repeat(np.arange(npatch, dtype=np.int32), q * q),
+                    group_h=np.sqrt(area / (q * q)),
+                    meta=dict(kind="cube_sphere", radius=radius, axes=tuple(axes), n_patches=npatch,
+                              points_per_patch=q * q, q=q, nodes_1d=t, weights_1d=wt))
 
 
 # ----------------------------------------------------------------------------
