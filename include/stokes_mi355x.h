@@ -250,6 +250,92 @@ int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const d
                   const double* grad_vel, double* grad_density, double* grad_src_xyz,
                   double* grad_trg_xyz, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- check-point quadrature on and near a patched surface, Sec. 3.1 ------ */
+
+/* A surface made of n_patches tensor-product patches, each given by q x q
+ * nodes: node_xyz (3, n_patches*q*q), patch-major, node k = i*q + j of a patch
+ * at parameters (u, v) = (nodes_1d[i], nodes_1d[j]) of [-1, 1]^2.  The patch is
+ * the polynomial of degree q-1 in u and in v through its nodes, X_u x X_v must
+ * point out of the surface, and (nodes_1d, weights_1d) is the 1-D rule of the
+ * patch (Gauss-Legendre, Clenshaw-Curtis, ...) on [-1, 1].
+ *   q           2 .. 24.
+ *   eta         0 .. 3: the fine discretisation splits each patch into
+ *               4^eta equal sub-squares, each with the same q x q rule.
+ *   p           1 .. 15: p + 1 check points per target.
+ *   R_frac      > 0: distance of the first check point from the surface, as
+ *               a fraction of the patch size L (the square root of the area
+ *               of the target's patch).
+ *   r_frac      > 0: spacing of the check points, as a fraction of L.
+ *   nodes_1d    HOST float64[q], strictly increasing, within [-1, 1].
+ *   weights_1d  HOST float64[q], positive. */
+typedef struct {
+    int32_t       q;
+    int32_t       eta;
+    int32_t       p;
+    double        R_frac;
+    double        r_frac;
+    const double* nodes_1d;
+    const double* weights_1d;
+} stokes_patch_rule;
+
+/* The fine discretisation of Sec. 3.1 step 1 (the upsampling U), for every
+ * patch: n_fine = n_patches * (2^eta q)^2 nodes, patch-major, fine node
+ * I*(2^eta q) + J of a patch at (s_I, s_J), s_{a q + i} = -1 + (2a + 1 +
+ * nodes_1d[i]) / 2^eta, the patch evaluated there.
+ *   fine_xyz     (3, n_fine)  positions
+ *   fine_density (3, n_fine)  U phi: the density interpolated like positions
+ *   fine_weight  (n_fine)     weights_1d[i] weights_1d[j] / 4^eta |X_u x X_v|
+ *   fine_normal  (3, n_fine)  X_u x X_v / |X_u x X_v|
+ *   patch_size   (n_patches)  L = sqrt(sum of the patch's fine weights)
+ * density (3, n_patches*q*q) may be NULL, and then fine_density is not
+ * written.  R_frac, r_frac and p are not used.  Needs no workspace. */
+int stokes_patch_upsample(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                          const double* node_xyz, const double* density, double* fine_xyz,
+                          double* fine_density, double* fine_weight, double* fine_normal,
+                          double* patch_size, void* stream);
+
+/* Bytes of workspace stokes_dl_checkpoint_eval needs for these sizes. */
+int stokes_checkpoint_workspace_size(const stokes_ctx* ctx, int64_t n_patches,
+                                     const stokes_patch_rule* rule, int64_t n_trg,
+                                     const stokes_opts* opts, size_t* bytes);
+
+/* Double-layer velocity at targets on or near the surface by the check-point
+ * quadrature of Sec. 3.1 (eqs. quad_check_points and sing-quad):
+ *   1. fine discretisation and U phi, as stokes_patch_upsample;
+ *   2. target t is the point x_t = y_t - d_t n_t, y_t = P(u_t, v_t) on patch
+ *      trg_patch[t] with unit normal n_t = X_u x X_v / |X_u x X_v| there, and
+ *      d_t >= 0 its distance inside (the closest-point search is the
+ *      caller's: (u_t, v_t) is the closest point);
+ *   3. check points c_ti = y_t - (R + i r) n_t, i = 0..p, R = R_frac L,
+ *      r = r_frac L, L the size of patch trg_patch[t];
+ *   4. u(c_ti): the double-layer sum of stokes_dl_eval (no pair rule) over
+ *      the fine nodes;
+ *   5. vel_out(:, t) (=|+=) sum_i e_i u(c_ti), e_i = prod_{k != i}
+ *      (d_t - s_k)/(s_i - s_k), s_k = (R + k r) the check point distances.
+ * The result is the limit from the side the check points lie on (inside a
+ * closed surface): for a constant density it is -density, and on the
+ * surface the principal value is the result plus density / 2.
+ *   density     (3, n_patches*q*q) at the nodes.
+ *   trg_patch   int32[n_trg], trg_uvd (3, n_trg) = rows u, v, d.  Both NULL:
+ *               the targets are the n_patches*q*q nodes themselves, on the
+ *               surface (n_trg must be that count); else both non-NULL.  A
+ *               patch id outside [0, n_patches) gives NaN for that target.
+ *   opts        precision of step 4 (STOKES_FP64 or STOKES_MIXED; the
+ *               extrapolation amplifies its error by sum_i |e_i|, 511 for
+ *               p = 8, R = r, d = 0) and accumulate for vel_out.
+ *   check_xyz_out, check_vel_out  optional (3, n_trg*(p+1)) outputs, check
+ *               point t*(p+1) + i: the check points and their velocities.
+ * Every step runs on the GPU on `stream`; the workspace holds the fine
+ * discretisation, the check points and the double-layer sum's scratch.
+ * n_trg == 0 does nothing; n_patches == 0 needs n_trg == 0.  With timing on,
+ * the double-layer sum is the timed kernel. */
+int stokes_dl_checkpoint_eval(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                              const double* node_xyz, const double* density, int64_t n_trg,
+                              const int32_t* trg_patch, const double* trg_uvd,
+                              const stokes_opts* opts, double* vel_out, double* check_xyz_out,
+                              double* check_vel_out, void* workspace, size_t ws_bytes,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,14 +2,16 @@
 
 Single-layer (Stokeslet) and double-layer (stresslet) sums from surface
 quadrature points to targets, in direct and leaf-to-leaf (FMM near-field)
-form, in float64 or mixed float32/float64, with hand-written adjoints, as
+form, in float64 or mixed float32/float64, with hand-written adjoints, and the
+check-point quadrature of the double layer on and near a patched surface, as
 hand-written HIP kernels behind the C ABI of ``include/stokes_mi355x.h``.
 
 ``workloads`` (seeded synthetic inputs) imports without torch; the compute
 API (``sl``, ``dl``, ...) loads the HIP library on first use.
 """
 _API = ("sl", "dl", "sl_vjp", "dl_vjp", "sl_diff", "dl_diff", "p2p_leaf", "P2PPlan", "context",
-        "set_grid_override", "StokesSL", "StokesDL", "StokesP2P", "timing_enable", "timing_read")
+        "set_grid_override", "StokesSL", "StokesDL", "StokesP2P", "timing_enable", "timing_read",
+        "patch_upsample", "dl_checkpoint")
 
 __all__ = list(_API) + ["workloads"]
 

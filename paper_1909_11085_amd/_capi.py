@@ -40,6 +40,13 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
 
 
+class PatchRule(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("eta", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("R_frac", ctypes.c_double), ("r_frac", ctypes.c_double),
+                ("nodes_1d", ctypes.POINTER(ctypes.c_double)),
+                ("weights_1d", ctypes.POINTER(ctypes.c_double))]
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -47,6 +54,7 @@ _dbl = ctypes.c_double
 _sz = ctypes.c_size_t
 _EX = ctypes.POINTER(Exclusion)
 _OP = ctypes.POINTER(Opts)
+_PR = ctypes.POINTER(PatchRule)
 
 _SIGNATURES = {
     "stokes_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
@@ -71,6 +79,10 @@ _SIGNATURES = {
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
     "stokes_dl_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _EX, _OP, _vp,
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
+    "stokes_patch_upsample": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "stokes_checkpoint_workspace_size": (ctypes.c_int, [_vp, _i64, _PR, _i64, _OP, ctypes.POINTER(_sz)]),
+    "stokes_dl_checkpoint_eval": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _i64, _vp, _vp, _OP, _vp, _vp,
+                                                 _vp, _vp, _sz, _vp]),
 }
 
 _lib = None

@@ -13,6 +13,7 @@ from __future__ import annotations
 import ctypes
 import threading
 
+import numpy as np
 import torch
 
 from . import _capi as C
@@ -361,3 +362,95 @@ def p2p_leaf(plan, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=None
                                          ctypes.byref(rule.opts), _ptr(out), _ptr(ws), size,
                                          _stream(device)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# check-point quadrature on and near a patched surface
+# ----------------------------------------------------------------------------
+class _PatchRule:
+    """Keeps the host node / weight arrays of a stokes_patch_rule alive."""
+
+    def __init__(self, nodes_1d, weights_1d, eta, p=8, R_frac=0.15, r_frac=0.15):
+        self.t = np.ascontiguousarray(nodes_1d, dtype=np.float64)
+        self.w = np.ascontiguousarray(weights_1d, dtype=np.float64)
+        if self.t.ndim != 1 or self.t.shape != self.w.shape:
+            raise ValueError("nodes_1d and weights_1d must be 1-D arrays of the same length")
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.rule = C.PatchRule(len(self.t), int(eta), int(p), float(R_frac), float(r_frac),
+                                self.t.ctypes.data_as(dp), self.w.ctypes.data_as(dp))
+        self.q = len(self.t)
+
+
+def patch_upsample(node_xyz, nodes_1d, weights_1d, eta, density=None):
+    """Fine discretisation of a patched surface; see stokes_patch_upsample.
+
+    node_xyz (3, n_patches*q*q) and density (same shape, optional).  Returns
+    (fine_xyz, fine_density or None, fine_weight, fine_normal, patch_size)."""
+    device = node_xyz.device
+    _vec3(node_xyz, "node_xyz", device)
+    R = _PatchRule(nodes_1d, weights_1d, eta)
+    qq = R.q * R.q
+    if node_xyz.shape[1] % qq:
+        raise ValueError("node_xyz must hold n_patches * q * q points")
+    npatch = node_xyz.shape[1] // qq
+    nf = npatch * (2 ** int(eta) * R.q) ** 2
+    if density is not None:
+        _vec3(density, "density", device)
+        if density.shape != node_xyz.shape:
+            raise ValueError("density must have the shape of node_xyz")
+    fx = torch.empty((3, nf), dtype=torch.float64, device=device)
+    fphi = torch.empty((3, nf), dtype=torch.float64, device=device) if density is not None else None
+    fw = torch.empty(nf, dtype=torch.float64, device=device)
+    fn = torch.empty((3, nf), dtype=torch.float64, device=device)
+    L = torch.empty(npatch, dtype=torch.float64, device=device)
+    C.check(C.lib().stokes_patch_upsample(context(device), npatch, ctypes.byref(R.rule), _ptr(node_xyz),
+                                          _ptr(density), _ptr(fx), _ptr(fphi), _ptr(fw), _ptr(fn), _ptr(L),
+                                          _stream(device)))
+    return fx, fphi, fw, fn, L
+
+
+def dl_checkpoint(node_xyz, density, nodes_1d, weights_1d, eta=1, p=8, R_frac=0.15, r_frac=0.15,
+                  trg_patch=None, trg_uvd=None, precision="fp64", out=None, accumulate=False,
+                  return_check=False):
+    """Double-layer velocity on or near a patched surface by the check-point
+    quadrature; see stokes_dl_checkpoint_eval.
+
+    Targets: every node on the surface (trg_patch = trg_uvd = None), or
+    trg_patch (M,) int32 with trg_uvd (3, M) rows u, v, d.  Returns vel (3, M);
+    with return_check also the check points and their velocities, each
+    (3, M*(p+1))."""
+    device = node_xyz.device
+    _vec3(node_xyz, "node_xyz", device)
+    _vec3(density, "density", device)
+    if density.shape != node_xyz.shape:
+        raise ValueError("density must have the shape of node_xyz")
+    R = _PatchRule(nodes_1d, weights_1d, eta, p, R_frac, r_frac)
+    qq = R.q * R.q
+    if node_xyz.shape[1] % qq:
+        raise ValueError("node_xyz must hold n_patches * q * q points")
+    npatch = node_xyz.shape[1] // qq
+    if (trg_patch is None) != (trg_uvd is None):
+        raise ValueError("trg_patch and trg_uvd go together")
+    if trg_patch is None:
+        m = node_xyz.shape[1]
+    else:
+        m = trg_patch.shape[0]
+        _vec1(trg_patch, m, "trg_patch", device, torch.int32)
+        _vec3(trg_uvd, "trg_uvd", device)
+        if trg_uvd.shape[1] != m:
+            raise ValueError("trg_uvd must have shape (3, len(trg_patch))")
+    opts = C.Opts(PRECISIONS[precision], int(bool(accumulate)))
+    out = _out(out, m, device, accumulate)
+    cx = cv = None
+    if return_check:
+        cx = torch.empty((3, m * (p + 1)), dtype=torch.float64, device=device)
+        cv = torch.empty((3, m * (p + 1)), dtype=torch.float64, device=device)
+    size = ctypes.c_size_t()
+    C.check(C.lib().stokes_checkpoint_workspace_size(context(device), npatch, ctypes.byref(R.rule), m,
+                                                     ctypes.byref(opts), ctypes.byref(size)))
+    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    C.check(C.lib().stokes_dl_checkpoint_eval(context(device), npatch, ctypes.byref(R.rule), _ptr(node_xyz),
+                                              _ptr(density), m, _ptr(trg_patch), _ptr(trg_uvd),
+                                              ctypes.byref(opts), _ptr(out), _ptr(cx), _ptr(cv), _ptr(ws),
+                                              int(size.value), _stream(device)))
+    return (out, cx, cv) if return_check else out

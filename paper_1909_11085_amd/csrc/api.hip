@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/stokes_mi355x.h"
+#include "checkpoint.hpp"
 #include "common.hpp"
 #include "p2p.hpp"
 #include "vjp.hpp"
@@ -199,6 +200,84 @@ int check_no_alias(const void* out, size_t out_bytes, const char* name,
     for (const auto& in : inputs)
         if (overlaps(out, out_bytes, in.first, in.second))
             return fail(STOKES_EINVAL, std::string(name) + " overlaps an input array");
+    return STOKES_OK;
+}
+
+
+// Check-point quadrature: the patch rule and the workspace layout.
+int parse_patch_rule(const stokes_patch_rule* r, bool check_points, stokes::PatchRule& out) {
+    if (!r) return fail(STOKES_EINVAL, "rule is NULL");
+    if (r->q < 2 || r->q > stokes::kMaxQ)
+        return fail(STOKES_EINVAL, "rule.q must be in [2, " + std::to_string(stokes::kMaxQ) + "]");
+    if (r->eta < 0 || r->eta > stokes::kMaxEta)
+        return fail(STOKES_EINVAL, "rule.eta must be in [0, " + std::to_string(stokes::kMaxEta) + "]");
+    if (check_points) {
+        if (r->p < 1 || r->p > stokes::kMaxP)
+            return fail(STOKES_EINVAL, "rule.p must be in [1, " + std::to_string(stokes::kMaxP) + "]");
+        if (!(isfinite(r->R_frac) && r->R_frac > 0.0) || !(isfinite(r->r_frac) && r->r_frac > 0.0))
+            return fail(STOKES_EINVAL, "rule.R_frac and rule.r_frac must be finite and > 0");
+    }
+    if (!r->nodes_1d || !r->weights_1d)
+        return fail(STOKES_EINVAL, "rule.nodes_1d and rule.weights_1d (host arrays of q) must be non-NULL");
+    for (int k = 0; k < r->q; ++k) {
+        const double t = r->nodes_1d[k], w = r->weights_1d[k];
+        if (!(isfinite(t) && t >= -1.0 && t <= 1.0))
+            return fail(STOKES_EINVAL, "rule.nodes_1d must lie within [-1, 1]");
+        if (k > 0 && !(t > r->nodes_1d[k - 1]))
+            return fail(STOKES_EINVAL, "rule.nodes_1d must be strictly increasing");
+        if (!(isfinite(w) && w > 0.0)) return fail(STOKES_EINVAL, "rule.weights_1d must be finite and > 0");
+    }
+    out = stokes::PatchRule{};
+    out.q = r->q;
+    out.eta = r->eta;
+    out.p = check_points ? r->p : 1;
+    out.R = check_points ? r->R_frac : 0.0;
+    out.r = check_points ? r->r_frac : 0.0;
+    for (int k = 0; k < r->q; ++k) {
+        out.t[k] = r->nodes_1d[k];
+        out.w[k] = r->weights_1d[k];
+    }
+    return STOKES_OK;
+}
+
+struct CheckpointLayout {
+    int64_t n_nodes = 0, n_fine = 0, n_check = 0;
+    size_t off_fx = 0, off_fphi = 0, off_fw = 0, off_fn = 0, off_L = 0, off_cx = 0, off_cv = 0,
+           off_direct = 0, total = 0;
+    stokes::DirectPlan plan{};
+};
+
+// Point counts of the fine discretisation and the check points, checked
+// against STOKES_MAX_POINTS, and (with_ws) the workspace regions.
+int checkpoint_layout(const stokes_ctx* ctx, int64_t n_patches, const stokes::PatchRule& R, int64_t n_trg,
+                      int mixed, bool with_ws, CheckpointLayout& lay) {
+    if (n_patches < 0 || n_trg < 0) return fail(STOKES_EINVAL, "n_patches and n_trg must be >= 0");
+    const int64_t qq = (int64_t)R.q * R.q, per_patch = qq << (2 * R.eta);
+    if (n_patches > STOKES_MAX_POINTS / per_patch)
+        return fail(STOKES_EUNSUPPORTED, "fine node count n_patches * (2^eta q)^2 above STOKES_MAX_POINTS");
+    if (n_trg > STOKES_MAX_POINTS / (R.p + 1))
+        return fail(STOKES_EUNSUPPORTED, "check point count n_trg * (p + 1) above STOKES_MAX_POINTS");
+    lay.n_nodes = n_patches * qq;
+    lay.n_fine = n_patches * per_patch;
+    lay.n_check = n_trg * (R.p + 1);
+    if (!with_ws || n_trg == 0 || n_patches == 0) return STOKES_OK;
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off = stokes::align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t f8 = (size_t)lay.n_fine * 8, c8 = (size_t)lay.n_check * 8;
+    lay.off_fx = take(3 * f8);
+    lay.off_fphi = take(3 * f8);
+    lay.off_fw = take(f8);
+    lay.off_fn = take(3 * f8);
+    lay.off_L = take((size_t)n_patches * 8);
+    lay.off_cx = take(3 * c8);
+    lay.off_cv = take(3 * c8);
+    lay.plan = stokes::plan_direct(1, mixed, lay.n_fine, lay.n_check, ctx->resident[1][mixed], ctx->forced_grid);
+    lay.off_direct = off;
+    lay.total = off + lay.plan.total;
     return STOKES_OK;
 }
 
@@ -557,6 +636,128 @@ int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const d
     return vjp_eval(ctx, STOKES_KERNEL_DL, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz,
                     6.0 / (8.0 * kPi), excl, opts, grad_vel, grad_density, grad_src_xyz, grad_trg_xyz,
                     workspace, ws_bytes, stream);
+}
+
+int stokes_patch_upsample(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                          const double* node_xyz, const double* density, double* fine_xyz,
+                          double* fine_density, double* fine_weight, double* fine_normal,
+                          double* patch_size, void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    stokes::PatchRule R;
+    int rc = parse_patch_rule(rule, false, R);
+    if (rc) return rc;
+    CheckpointLayout lay;
+    if ((rc = checkpoint_layout(ctx, n_patches, R, 0, 0, false, lay))) return rc;
+    const int64_t nn = lay.n_nodes, nf = lay.n_fine;
+    if (!arr_ok(node_xyz, 3 * nn, 8)) return fail(STOKES_EINVAL, "node_xyz must be non-NULL and 8-byte aligned");
+    if (density && !aligned(density, 8)) return fail(STOKES_EINVAL, "density must be 8-byte aligned");
+    if (!arr_ok(fine_xyz, 3 * nf, 8) || !arr_ok(fine_weight, nf, 8) || !arr_ok(fine_normal, 3 * nf, 8) ||
+        !arr_ok(patch_size, n_patches, 8))
+        return fail(STOKES_EINVAL, "fine_xyz, fine_weight, fine_normal and patch_size must be non-NULL and "
+                                   "8-byte aligned");
+    if (density && !arr_ok(fine_density, 3 * nf, 8))
+        return fail(STOKES_EINVAL, "fine_density must be non-NULL and 8-byte aligned when density is given");
+    const size_t nb = (size_t)3 * nn * 8, fb = (size_t)3 * nf * 8;
+    const std::pair<const void*, size_t> outs[] = {{fine_xyz, fb},
+                                                   {density ? fine_density : nullptr, fb},
+                                                   {fine_weight, (size_t)nf * 8},
+                                                   {fine_normal, fb},
+                                                   {patch_size, (size_t)n_patches * 8}};
+    for (int i = 0; i < 5; ++i) {
+        if ((rc = check_no_alias(outs[i].first, outs[i].second, "an upsampling output",
+                                 {{node_xyz, nb}, {density, density ? nb : 0}})))
+            return rc;
+        for (int j = 0; j < i; ++j)
+            if (overlaps(outs[i].first, outs[i].second, outs[j].first, outs[j].second))
+                return fail(STOKES_EINVAL, "upsampling outputs overlap each other");
+    }
+    if (n_patches == 0) return STOKES_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    return launch_status(stokes::launch_upsample(R, n_patches, node_xyz, density, fine_xyz,
+                                                 density ? fine_density : nullptr, fine_weight, fine_normal,
+                                                 patch_size, static_cast<hipStream_t>(stream)),
+                         "stokes_patch_upsample");
+}
+
+int stokes_checkpoint_workspace_size(const stokes_ctx* ctx, int64_t n_patches,
+                                     const stokes_patch_rule* rule, int64_t n_trg,
+                                     const stokes_opts* opts, size_t* bytes) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!bytes) return fail(STOKES_EINVAL, "bytes is NULL");
+    stokes::PatchRule R;
+    int rc = parse_patch_rule(rule, true, R);
+    if (rc) return rc;
+    Parsed p;
+    if ((rc = parse_common(nullptr, opts, 0, 0, p))) return rc;
+    CheckpointLayout lay;
+    if ((rc = checkpoint_layout(ctx, n_patches, R, n_trg, p.precision == STOKES_MIXED, true, lay))) return rc;
+    *bytes = lay.total;
+    return STOKES_OK;
+}
+
+int stokes_dl_checkpoint_eval(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                              const double* node_xyz, const double* density, int64_t n_trg,
+                              const int32_t* trg_patch, const double* trg_uvd,
+                              const stokes_opts* opts, double* vel_out, double* check_xyz_out,
+                              double* check_vel_out, void* workspace, size_t ws_bytes,
+                              void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    stokes::PatchRule R;
+    int rc = parse_patch_rule(rule, true, R);
+    if (rc) return rc;
+    Parsed p;
+    if ((rc = parse_common(nullptr, opts, 0, 0, p))) return rc;
+    CheckpointLayout lay;
+    if ((rc = checkpoint_layout(ctx, n_patches, R, n_trg, p.precision == STOKES_MIXED, true, lay))) return rc;
+    if (n_patches == 0 && n_trg > 0) return fail(STOKES_EINVAL, "targets need at least one patch (n_patches == 0)");
+    if ((trg_patch == nullptr) != (trg_uvd == nullptr))
+        return fail(STOKES_EINVAL, "trg_patch and trg_uvd must both be given or both be NULL");
+    if (!trg_patch && n_trg != lay.n_nodes)
+        return fail(STOKES_EINVAL, "without trg_patch the targets are the n_patches*q*q nodes: n_trg must equal "
+                                   "that count");
+    const int64_t nn = lay.n_nodes;
+    if (!arr_ok(node_xyz, 3 * nn, 8)) return fail(STOKES_EINVAL, "node_xyz must be non-NULL and 8-byte aligned");
+    if (!arr_ok(density, 3 * nn, 8)) return fail(STOKES_EINVAL, "density must be non-NULL and 8-byte aligned");
+    if (trg_patch && (!arr_ok(trg_patch, n_trg, 4) || !arr_ok(trg_uvd, 3 * n_trg, 8)))
+        return fail(STOKES_EINVAL, "trg_patch must be 4-byte and trg_uvd 8-byte aligned");
+    if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
+    if ((check_xyz_out && !aligned(check_xyz_out, 8)) || (check_vel_out && !aligned(check_vel_out, 8)))
+        return fail(STOKES_EINVAL, "check_xyz_out and check_vel_out must be 8-byte aligned");
+    const size_t nb = (size_t)3 * nn * 8, tb = (size_t)3 * n_trg * 8, cb = (size_t)3 * lay.n_check * 8;
+    const std::initializer_list<std::pair<const void*, size_t>> inputs = {
+        {node_xyz, nb}, {density, nb}, {trg_patch, trg_patch ? (size_t)n_trg * 4 : 0},
+        {trg_uvd, trg_uvd ? tb : 0}, {workspace, ws_bytes}};
+    if ((rc = check_no_alias(vel_out, tb, "vel_out", inputs))) return rc;
+    if ((rc = check_no_alias(check_xyz_out, cb, "check_xyz_out", inputs))) return rc;
+    if ((rc = check_no_alias(check_vel_out, cb, "check_vel_out", inputs))) return rc;
+    if (overlaps(vel_out, tb, check_xyz_out, cb) || overlaps(vel_out, tb, check_vel_out, cb) ||
+        overlaps(check_xyz_out, cb, check_vel_out, cb))
+        return fail(STOKES_EINVAL, "outputs overlap each other");
+    if ((rc = check_workspace(workspace, ws_bytes, lay.total))) return rc;
+    if (n_trg == 0) return STOKES_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    double* fx = reinterpret_cast<double*>(ws + lay.off_fx);
+    double* fphi = reinterpret_cast<double*>(ws + lay.off_fphi);
+    double* fw = reinterpret_cast<double*>(ws + lay.off_fw);
+    double* fn = reinterpret_cast<double*>(ws + lay.off_fn);
+    double* L = reinterpret_cast<double*>(ws + lay.off_L);
+    double* cx = check_xyz_out ? check_xyz_out : reinterpret_cast<double*>(ws + lay.off_cx);
+    double* cv = check_vel_out ? check_vel_out : reinterpret_cast<double*>(ws + lay.off_cv);
+    hipError_t e = stokes::launch_upsample(R, n_patches, node_xyz, density, fx, fphi, fw, fn, L, st);
+    if (e == hipSuccess)
+        e = stokes::launch_check_points(R, n_patches, node_xyz, L, n_trg, trg_patch, trg_uvd, cx, st);
+    if (e == hipSuccess) {
+        const stokes::SumInputs in = make_inputs(STOKES_KERNEL_DL, p, lay.n_fine, fx, fphi, fw, fn, lay.n_check,
+                                                 cx, 6.0 / (8.0 * kPi));
+        e = stokes::launch_direct(in, lay.plan, cv, 0, ws + lay.off_direct, st, stokes::next_timer(ctx));
+    }
+    if (e == hipSuccess)
+        e = stokes::launch_extrapolate(R, n_patches, L, n_trg, trg_patch, trg_uvd, cv, vel_out, p.accumulate, st);
+    return launch_status(e, "stokes_dl_checkpoint_eval");
 }
 
 }  // extern "C"

@@ -262,7 +262,7 @@ _CUBE_FACES = (((1, 0, 0), (0, 1, 0), (0, 0, 1)), ((-1, 0, 0), (0, 0, 1), (0, 1,
                ((0, 0, 1), (1, 0, 0), (0, 1, 0)), ((0, 0, -1), (0, 1, 0), (1, 0, 0)))
 
 
-def cube_sphere(radius=1.0, m=2, q=16, axes=(1.0, 1.0, 1.0), centre=(0.0, 0.0, 0.0)):
+def cube_sphere(radius=1.0, m=2, q=16, axes=(1.0, 1.0, 1.0), centre=(0.0, 0.0, 0.0), rule=None):
     """Closed patch surface: a sphere (or, with unequal `axes`, an ellipsoid)
     covered by 6 m^2 tensor-product patches.
 
@@ -272,8 +272,13 @@ def cube_sphere(radius=1.0, m=2, q=16, axes=(1.0, 1.0, 1.0), centre=(0.0, 0.0, 0
     q x q Gauss-Legendre nodes in its own parameter square [-1, 1]^2 (u along
     t1, v along t2, node k = i*q + j at (t_i, t_j)); weight w = w_i w_j
     |X_u x X_v| and unit normal X_u x X_v / |X_u x X_v|, both from the exact
-    map, the normal outward.  Points are patch-major (q*q per patch)."""
-    t, wt = np.polynomial.legendre.leggauss(q)
+    map, the normal outward.  Points are patch-major (q*q per patch).  `rule`
+    = (nodes, weights) replaces the Gauss-Legendre rule (q is then its length)."""
+    if rule is None:
+        t, wt = np.polynomial.legendre.leggauss(q)
+    else:
+        t, wt = (np.asarray(a, dtype=np.float64) for a in rule)
+        q = len(t)
     S = np.asarray(axes, dtype=np.float64)[:, None]
     ti, tj = [a.reshape(-1) for a in np.meshgrid(t, t, indexing="ij")]
     wij = np.outer(wt, wt).reshape(-1)
@@ -310,6 +315,18 @@ def cube_sphere(radius=1.0, m=2, q=16, axes=(1.0, 1.0, 1.0), centre=(0.0, 0.0, 0
 # ----------------------------------------------------------------------------
 # Octree leaves and interaction lists (FMM near field)
 # ----------------------------------------------------------------------------
+def clenshaw_curtis(q):
+    """q-point Clenshaw-Curtis rule on [-1, 1]: nodes -cos(pi j / (q - 1)) in
+    increasing order, weights from the moment equations sum_j w_j t_j^k =
+    int_{-1}^{1} t^k dt, k < q."""
+    t = -np.cos(np.pi * np.arange(q) / (q - 1))
+    t[np.abs(t) < 1e-15] = 0.0
+    k = np.arange(q)
+    moments = np.where(k % 2 == 0, 2.0 / (k + 1), 0.0)
+    w = np.linalg.solve(np.vander(t, q, increasing=True).T, moments)
+    return t, w
+
+
 def _spread_bits(v):
     v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
     v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
