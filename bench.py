@@ -18,6 +18,10 @@ Reported on one JSON line (stdout):
                 library on the stream it launches on), against the vector peak
   cpu_baseline  the FP64 CPU oracle on a bounded sample of targets (all
                 sources), on this host's cores
+
+--only checkpoint times the check-point double-layer quadrature on a
+vessel-wall ring (every node an on-surface target); --secondary adds it and
+the other workload shapes to the line.
 """
 import argparse
 import hashlib
@@ -38,6 +42,7 @@ METRIC = "Stokes pair-interactions/s (FP64 vs mixed FP32) at stated rel-L2 error
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 FLOPS_PER_PAIR_SL = 29
 FLOPS_PER_PAIR_SL_VJP = 95
+FLOPS_PER_PAIR_DL = 30
 KERNEL_NAMES = {"fp64": "direct_f64<SL,T=4>", "mixed": "direct_mixed<SL,T=2>"}
 PROFILE_TRAFFIC = {"fp64": "direct_f64_sl_cfg2_traffic.txt", "mixed": "direct_mixed_sl_cfg2_traffic.txt"}
 
@@ -80,9 +85,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="headline precision (the other one is reported alongside)")
-    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p"], default=None,
+    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p", "checkpoint"], default=None,
                     help="time one path only (for profiler runs); p2p times the leaf-to-leaf "
-                         "workload (3,840 cells in the cylinder) in both precisions")
+                         "workload (3,840 cells in the cylinder) in both precisions; checkpoint "
+                         "the check-point double-layer quadrature on a vessel-wall ring")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
@@ -144,6 +150,11 @@ def main():
         r = time_p2p(S, W, t, timed, args.steps, args.warmup)
         log(f"p2p: {r}")
         print(json.dumps({"p2p_3840_cells": r}), flush=True)
+        return
+    if args.only == "checkpoint":
+        r = time_checkpoint(S, W, t, timed, args.steps, args.warmup, oracle=not args.no_cpu_baseline)
+        log(f"checkpoint: {r}")
+        print(json.dumps({"checkpoint_wall_ring": r}), flush=True)
         return
 
     t0 = time.time()
@@ -286,6 +297,55 @@ def time_p2p(S, W, t, timed, steps, warmup):
     return r
 
 
+def time_checkpoint(S, W, t, timed, steps, warmup, oracle=True):
+    """Check-point double-layer quadrature (Sec. 3.1) with every node of a
+    vessel-wall ring as an on-surface target: 64 x 4 patches of 16 x 16
+    Gauss-Legendre nodes (the 1M-node wall's patch shape), eta = 1 (4
+    sub-squares), p = 8, R = r = 0.15 L.  One step = upsampling, check points,
+    the double-layer sum over the fine nodes at every check point, and the
+    extrapolation.  The timed kernel is that sum (30 flop per pair)."""
+    wall = W.cylinder_wall(radius=50.0, length=25.0, n_theta=64, n_z=4, q=16)
+    phi = np.random.default_rng(11).standard_normal((3, wall.n))
+    tq, wq = wall.meta["nodes_1d"], wall.meta["weights_1d"]
+    eta, p, R = 1, 8, 0.15
+    n_fine = wall.n * 4 ** eta
+    n_check = wall.n * (p + 1)
+    pairs = n_fine * n_check
+    X, F = t(wall.pos), t(phi)
+    r = {"targets": wall.n, "fine_sources": n_fine, "check_points": n_check, "pairs": pairs,
+         "eta": eta, "p": p, "R_over_L": R, "r_over_L": R, "kernel": "direct_f64<DL,T=4> / direct_mixed<DL>",
+         "flops_per_pair": FLOPS_PER_PAIR_DL}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        ms, kms, _ = timed(lambda: outs.__setitem__(prec, S.dl_checkpoint(X, F, tq, wq, eta=eta, p=p, R_frac=R,
+                                                                           r_frac=R, precision=prec)),
+                           steps, warmup)
+        ach = pairs * FLOPS_PER_PAIR_DL / (kms * 1e-3) / 1e12
+        r[f"{prec}_ms"] = ms
+        r[f"{prec}_sum_kernel_ms"] = kms
+        r[f"{prec}_targets_per_s"] = wall.n / (ms * 1e-3)
+        r[f"{prec}_pairs_per_s"] = pairs / (ms * 1e-3)
+        r[f"{prec}_sum_tflops"] = ach
+        r[f"{prec}_sum_frac_of_peak"] = ach / PEAK_TFLOPS[prec]
+        r[f"{prec}_outside_sum_ms"] = ms - kms
+    if oracle:
+        from oracle import hedgehog as H
+
+        pick = W.subset(np.random.default_rng(12), wall.n, 48)
+        pt, u, v, d = H.on_surface_targets(wall.meta["n_patches"], tq)
+        tc = time.time()
+        ref = H.singular_dl(wall.pos, phi, tq, wq, eta, p, R, R, pt[pick], u[pick], v[pick], d[pick])
+        dt = time.time() - tc
+        from oracle import oracle as O
+        r["cpu_oracle"] = {"targets_per_s": len(pick) / dt, "cores": O.num_threads(), "kind": "oracle",
+                           "sample": f"{len(pick)} seeded targets, upsampling of all patches included, "
+                                     f"{dt:.1f} s"}
+        for prec, u_gpu in outs.items():
+            got = u_gpu.cpu().numpy()[:, pick]
+            r[f"{prec}_rel_l2_sample"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return r
+
+
 def secondary(S, W, t, timed, log):
     """Timings of the other workload shapes (not the headline)."""
     import torch
@@ -348,6 +408,9 @@ def secondary(S, W, t, timed, log):
     r["adjoint_over_fp64_forward"] = ms / r["fp64_forward_ms"]
     out["cfg5_wall_and_cells"] = r
     log(f"secondary cfg5: {r}")
+    r = time_checkpoint(S, W, t, timed, 5, 1, oracle=False)
+    out["checkpoint_wall_ring"] = r
+    log(f"secondary checkpoint: {r}")
     return out
 
 
