@@ -20,8 +20,9 @@ Reported on one JSON line (stdout):
                 sources), on this host's cores
 
 --only checkpoint times the check-point double-layer quadrature on a
-vessel-wall ring (every node an on-surface target); --secondary adds it and
-the other workload shapes to the line.
+vessel-wall ring (every node an on-surface target), --only bie the
+30-iteration GMRES solve of the boundary integral equation on an ellipsoid;
+--secondary adds both and the other workload shapes to the line.
 """
 import argparse
 import hashlib
@@ -85,10 +86,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="headline precision (the other one is reported alongside)")
-    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p", "checkpoint"], default=None,
+    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p", "checkpoint", "bie"], default=None,
                     help="time one path only (for profiler runs); p2p times the leaf-to-leaf "
                          "workload (3,840 cells in the cylinder) in both precisions; checkpoint "
-                         "the check-point double-layer quadrature on a vessel-wall ring")
+                         "the check-point double-layer quadrature on a vessel-wall ring; bie the "
+                         "30-iteration GMRES solve of the boundary integral equation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
@@ -150,6 +152,11 @@ def main():
         r = time_p2p(S, W, t, timed, args.steps, args.warmup)
         log(f"p2p: {r}")
         print(json.dumps({"p2p_3840_cells": r}), flush=True)
+        return
+    if args.only == "bie":
+        r = time_bie(S, W, t, args.steps, args.warmup)
+        log(f"bie: {r}")
+        print(json.dumps({"bie_solve_ellipsoid": r}), flush=True)
         return
     if args.only == "checkpoint":
         r = time_checkpoint(S, W, t, timed, args.steps, args.warmup, oracle=not args.no_cpu_baseline)
@@ -328,22 +335,71 @@ def time_checkpoint(S, W, t, timed, steps, warmup, oracle=True):
         r[f"{prec}_sum_tflops"] = ach
         r[f"{prec}_sum_frac_of_peak"] = ach / PEAK_TFLOPS[prec]
         r[f"{prec}_outside_sum_ms"] = ms - kms
-    if oracle:
+    if oracle:                           # CPU baseline leg: the oracle on a sample; it also gives the error
         from oracle import hedgehog as H
+        from oracle import oracle as O
 
         pick = W.subset(np.random.default_rng(12), wall.n, 48)
         pt, u, v, d = H.on_surface_targets(wall.meta["n_patches"], tq)
         tc = time.time()
         ref = H.singular_dl(wall.pos, phi, tq, wq, eta, p, R, R, pt[pick], u[pick], v[pick], d[pick])
         dt = time.time() - tc
-        from oracle import oracle as O
-        r["cpu_oracle"] = {"targets_per_s": len(pick) / dt, "cores": O.num_threads(), "kind": "oracle",
-                           "sample": f"{len(pick)} seeded targets, upsampling of all patches included, "
-                                     f"{dt:.1f} s"}
+        r["cpu_baseline"] = {"value": len(pick) / dt, "unit": "targets/s", "cores": O.num_threads(),
+                             "kind": "oracle",
+                             "sample": f"{len(pick)} seeded targets, upsampling of all patches included, "
+                                       f"{dt:.1f} s"}
         for prec, u_gpu in outs.items():
             got = u_gpu.cpu().numpy()[:, pick]
             r[f"{prec}_rel_l2_sample"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     return r
+
+
+def time_bie(S, W, t, steps, warmup):
+    """GMRES solve of the boundary integral equation (eq. int_eq_disc), capped
+    at 30 iterations as in the paper's scaling runs, on an ellipsoid (semi-axes
+    1, 0.9, 0.8) of 6 x 3 x 3 patches of 16 x 16 nodes (13,824 nodes), eta = 2,
+    p = 8, R = r = 0.15 L, boundary data of a point force outside.  One step =
+    one solve (30 matrix-vector products, each a check-point quadrature over
+    221,184 fine nodes at 124,416 check points, plus the Arnoldi vector work)."""
+    import torch
+
+    s = W.cube_sphere(1.0, m=3, q=16, axes=(1.0, 0.9, 0.8))
+    tq, wq = s.meta["nodes_1d"], s.meta["weights_1d"]
+    x0, F = np.array([[1.7], [0.6], [-0.5]]), np.array([[0.3], [-1.0], [0.5]])
+
+    def point_force(x):                   # its velocity, by the library's single-layer sum
+        return S.sl(t(x0), t(F), t(np.ones(1)), x)
+
+    X = t(s.pos)
+    g = point_force(X)
+    its_cap, eta, p = 30, 2, 8
+    n_fine, n_check = s.n * 4 ** eta, s.n * (p + 1)
+    pairs = n_fine * n_check
+    for _ in range(warmup):
+        S.bie_solve(X, g, tq, wq, eta=eta, p=p, max_iter=its_cap, rtol=0.0)
+    torch.cuda.synchronize()
+    S.timing_read()
+    S.timing_enable(True)
+    t0 = time.time()
+    for _ in range(steps):
+        phi, its, hist = S.bie_solve(X, g, tq, wq, eta=eta, p=p, max_iter=its_cap, rtol=0.0)
+    torch.cuda.synchronize()
+    ms = (time.time() - t0) * 1e3 / steps
+    S.timing_enable(False)
+    kms, launches = S.timing_read()
+    sum_ms = kms / max(launches, 1)
+    rng = np.random.default_rng(41)
+    xin = rng.standard_normal((3, 64))
+    xin *= 0.5 * rng.uniform(0, 1, 64) ** (1 / 3) / np.linalg.norm(xin, axis=0)
+    u = S.dl(X, phi, t(s.weight), t(s.normal), t(xin)).cpu().numpy()
+    ue = point_force(t(xin)).cpu().numpy()
+    return {"nodes": s.n, "fine_sources": n_fine, "check_points": n_check, "iterations": its,
+            "pairs_per_matvec": pairs, "solve_ms": ms, "ms_per_iteration": ms / its,
+            "dl_sum_kernel_ms": sum_ms, "dl_sum_share": sum_ms * its / ms,
+            "dl_sum_tflops": pairs * FLOPS_PER_PAIR_DL / (sum_ms * 1e-3) / 1e12,
+            "final_residual": float(hist[-1]),
+            "interior_rel_error": float(np.abs(u - ue).max() / np.abs(ue).max()),
+            "precision": "fp64", "timing": "host clock around the blocking solve"}
 
 
 def secondary(S, W, t, timed, log):
@@ -411,6 +467,9 @@ def secondary(S, W, t, timed, log):
     r = time_checkpoint(S, W, t, timed, 5, 1, oracle=False)
     out["checkpoint_wall_ring"] = r
     log(f"secondary checkpoint: {r}")
+    r = time_bie(S, W, t, 2, 1)
+    out["bie_solve_ellipsoid"] = r
+    log(f"secondary bie: {r}")
     return out
 
 

@@ -336,6 +336,55 @@ int stokes_dl_checkpoint_eval(stokes_ctx* ctx, int64_t n_patches, const stokes_p
                               double* check_vel_out, void* workspace, size_t ws_bytes,
                               void* stream);
 
+/* ---- boundary integral equation on a closed patched surface, Sec. 2.1.2 -- */
+
+/* The discretised interior Dirichlet problem of eq. (double_layer_int_eq) at
+ * the patch nodes, eq. (int_eq_disc): find the double-layer density phi whose
+ * velocity u = D phi inside the surface takes the values g on it,
+ *   A phi = g,   A = L_in - N,
+ *   L_in phi   the limit from inside of D phi at every node: the check-point
+ *              quadrature of stokes_dl_checkpoint_eval with the nodes as
+ *              on-surface targets (= (D_pv - I/2) phi for this kernel, which
+ *              gives -phi for a constant phi);
+ *   (N phi)_l  = n_l sum_m w_m n_m . phi_m, the rank-completing term, with the
+ *              node normals and weights of the patch polynomial (the fine
+ *              discretisation with eta = 0).
+ * The paper writes (I/2 + D + N); with the sign of this kernel the interior
+ * operator is D_pv - I/2, and -N keeps the eigenvalue that N moves (minus
+ * the surface area) on the side of the others (-1 .. 0).  For compatible data
+ * (sum of w g . n = 0) N phi vanishes at the solution.
+ * The surface must be closed, with X_u x X_v pointing out of it.
+ * phi, g and out are (3, N) with N = n_patches * q * q nodes in node order. */
+
+/* Workspace of stokes_bie_apply (max_iter = 0) or of stokes_bie_solve with
+ * that iteration cap. */
+int stokes_bie_workspace_size(const stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                              int32_t max_iter, const stokes_opts* opts, size_t* bytes);
+
+/* out (=|+=) A phi.  opts: precision of the double-layer sum, accumulate. */
+int stokes_bie_apply(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                     const double* node_xyz, const double* phi, const stokes_opts* opts, double* out,
+                     void* workspace, size_t ws_bytes, void* stream);
+
+/* GMRES on A phi = g (Sec. 3.1, "Discretizing the integral equation"; the
+ * paper caps it at 30 iterations): phi_0 = 0, no restart, Arnoldi with
+ * classical Gram-Schmidt applied twice, Givens rotations.  Stops when the
+ * residual estimate |g - A phi_k| / |g| is <= rtol, at max_iter (1..100)
+ * iterations, or when the Krylov space becomes invariant.
+ *   phi_out            (3, N) the solution (zeros when g == 0).
+ *   iterations         host int32: iterations done.
+ *   residual_history   host float64[max_iter + 1] or NULL: entries
+ *                      0..iterations get the residual estimates (entry 0 = 1).
+ * Every matrix-vector product and vector operation runs on the GPU on
+ * `stream`; the host reads the Arnoldi coefficients back each iteration, so
+ * the call blocks until the solve is done.  opts.accumulate must be 0.
+ * Returns STOKES_EINVAL if g holds non-finite values.  FP64 results are
+ * deterministic. */
+int stokes_bie_solve(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                     const double* node_xyz, const double* g, int32_t max_iter, double rtol,
+                     const stokes_opts* opts, double* phi_out, int32_t* iterations,
+                     double* residual_history, void* workspace, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,10 @@ _SIGNATURES = {
     "stokes_checkpoint_workspace_size": (ctypes.c_int, [_vp, _i64, _PR, _i64, _OP, ctypes.POINTER(_sz)]),
     "stokes_dl_checkpoint_eval": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _i64, _vp, _vp, _OP, _vp, _vp,
                                                  _vp, _vp, _sz, _vp]),
+    "stokes_bie_workspace_size": (ctypes.c_int, [_vp, _i64, _PR, _i32, _OP, ctypes.POINTER(_sz)]),
+    "stokes_bie_apply": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _OP, _vp, _vp, _sz, _vp]),
+    "stokes_bie_solve": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _i32, _dbl, _OP, _vp,
+                                        ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _sz, _vp]),
 }
 
 _lib = None

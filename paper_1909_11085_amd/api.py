@@ -454,3 +454,52 @@ def dl_checkpoint(node_xyz, density, nodes_1d, weights_1d, eta=1, p=8, R_frac=0.
                                               ctypes.byref(opts), _ptr(out), _ptr(cx), _ptr(cv), _ptr(ws),
                                               int(size.value), _stream(device)))
     return (out, cx, cv) if return_check else out
+
+
+def _bie_common(node_xyz, nodes_1d, weights_1d, eta, p, R_frac, r_frac, max_iter, precision, accumulate=False):
+    device = node_xyz.device
+    _vec3(node_xyz, "node_xyz", device)
+    R = _PatchRule(nodes_1d, weights_1d, eta, p, R_frac, r_frac)
+    qq = R.q * R.q
+    if node_xyz.shape[1] % qq:
+        raise ValueError("node_xyz must hold n_patches * q * q points")
+    opts = C.Opts(PRECISIONS[precision], int(bool(accumulate)))
+    size = ctypes.c_size_t()
+    npatch = node_xyz.shape[1] // qq
+    C.check(C.lib().stokes_bie_workspace_size(context(device), npatch, ctypes.byref(R.rule), int(max_iter),
+                                              ctypes.byref(opts), ctypes.byref(size)))
+    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    return device, R, npatch, opts, ws, int(size.value)
+
+
+def bie_apply(node_xyz, phi, nodes_1d, weights_1d, eta=1, p=8, R_frac=0.15, r_frac=0.15, precision="fp64",
+              out=None, accumulate=False):
+    """(L_in - N) phi at the nodes of a closed patched surface; see stokes_bie_apply."""
+    device, R, npatch, opts, ws, size = _bie_common(node_xyz, nodes_1d, weights_1d, eta, p, R_frac, r_frac, 0,
+                                                    precision, accumulate)
+    _vec3(phi, "phi", device)
+    if phi.shape != node_xyz.shape:
+        raise ValueError("phi must have the shape of node_xyz")
+    out = _out(out, node_xyz.shape[1], device, accumulate)
+    C.check(C.lib().stokes_bie_apply(context(device), npatch, ctypes.byref(R.rule), _ptr(node_xyz), _ptr(phi),
+                                     ctypes.byref(opts), _ptr(out), _ptr(ws), size, _stream(device)))
+    return out
+
+
+def bie_solve(node_xyz, g, nodes_1d, weights_1d, eta=1, p=8, R_frac=0.15, r_frac=0.15, max_iter=30, rtol=1e-10,
+              precision="fp64", out=None):
+    """GMRES on (L_in - N) phi = g; see stokes_bie_solve.  Returns (phi,
+    iterations, residual history as a NumPy array of iterations + 1 entries)."""
+    device, R, npatch, opts, ws, size = _bie_common(node_xyz, nodes_1d, weights_1d, eta, p, R_frac, r_frac,
+                                                    max_iter, precision)
+    _vec3(g, "g", device)
+    if g.shape != node_xyz.shape:
+        raise ValueError("g must have the shape of node_xyz")
+    out = _out(out, node_xyz.shape[1], device, False)
+    its = ctypes.c_int32()
+    hist = (ctypes.c_double * (int(max_iter) + 1))()
+    C.check(C.lib().stokes_bie_solve(context(device), npatch, ctypes.byref(R.rule), _ptr(node_xyz), _ptr(g),
+                                     int(max_iter), float(rtol), ctypes.byref(opts), _ptr(out), ctypes.byref(its),
+                                     hist, _ptr(ws), size, _stream(device)))
+    return out, its.value, np.array(hist[: its.value + 1])
+

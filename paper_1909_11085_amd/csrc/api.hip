@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/stokes_mi355x.h"
+#include "bie.hpp"
 #include "checkpoint.hpp"
 #include "common.hpp"
 #include "p2p.hpp"
@@ -279,6 +280,105 @@ int checkpoint_layout(const stokes_ctx* ctx, int64_t n_patches, const stokes::Pa
     lay.off_direct = off;
     lay.total = off + lay.plan.total;
     return STOKES_OK;
+}
+
+// Upsampling, check points, the double-layer sum at the check points and the
+// extrapolation, on `st`, with the workspace regions of `lay` at `ws`.
+hipError_t checkpoint_run(stokes_ctx* ctx, const stokes::PatchRule& R, const CheckpointLayout& lay,
+                          int64_t n_patches, const double* node_xyz, const double* density, int64_t n_trg,
+                          const int32_t* trg_patch, const double* trg_uvd, const Parsed& p, double* vel_out,
+                          double* check_xyz_out, double* check_vel_out, char* ws, hipStream_t st) {
+    double* fx = reinterpret_cast<double*>(ws + lay.off_fx);
+    double* fphi = reinterpret_cast<double*>(ws + lay.off_fphi);
+    double* fw = reinterpret_cast<double*>(ws + lay.off_fw);
+    double* fn = reinterpret_cast<double*>(ws + lay.off_fn);
+    double* L = reinterpret_cast<double*>(ws + lay.off_L);
+    double* cx = check_xyz_out ? check_xyz_out : reinterpret_cast<double*>(ws + lay.off_cx);
+    double* cv = check_vel_out ? check_vel_out : reinterpret_cast<double*>(ws + lay.off_cv);
+    hipError_t e = stokes::launch_upsample(R, n_patches, node_xyz, density, fx, fphi, fw, fn, L, st);
+    if (e == hipSuccess)
+        e = stokes::launch_check_points(R, n_patches, node_xyz, L, n_trg, trg_patch, trg_uvd, cx, st);
+    if (e == hipSuccess) {
+        const stokes::SumInputs in = make_inputs(STOKES_KERNEL_DL, p, lay.n_fine, fx, fphi, fw, fn, lay.n_check,
+                                                 cx, 6.0 / (8.0 * kPi));
+        e = stokes::launch_direct(in, lay.plan, cv, 0, ws + lay.off_direct, st, stokes::next_timer(ctx));
+    }
+    if (e == hipSuccess)
+        e = stokes::launch_extrapolate(R, n_patches, L, n_trg, trg_patch, trg_uvd, cv, vel_out, p.accumulate, st);
+    return e;
+}
+
+// Boundary-integral operator (L_in - N) and its GMRES solve: workspace layout.
+struct BieLayout {
+    CheckpointLayout cp;
+    int64_t n3 = 0;               // 3 * nodes
+    size_t off_cp = 0, off_nn = 0, off_nw = 0, off_wn = 0, off_gx = 0, off_gL = 0, off_part = 0, off_dots = 0,
+           off_coef = 0, off_V = 0, off_w = 0, total = 0;
+};
+
+int bie_layout(const stokes_ctx* ctx, int64_t n_patches, const stokes::PatchRule& R, int32_t max_iter, int mixed,
+               BieLayout& lay) {
+    if (max_iter < 0 || max_iter > stokes::kMaxKrylov)
+        return fail(STOKES_EINVAL, "max_iter must be in [0, " + std::to_string(stokes::kMaxKrylov) + "]");
+    if (n_patches < 0) return fail(STOKES_EINVAL, "n_patches must be >= 0");
+    const int64_t qq = (int64_t)R.q * R.q;
+    if (n_patches > STOKES_MAX_POINTS / qq) return fail(STOKES_EUNSUPPORTED, "node count above STOKES_MAX_POINTS");
+    const int64_t nn = n_patches * qq;
+    int rc = checkpoint_layout(ctx, n_patches, R, nn, mixed, true, lay.cp);
+    if (rc) return rc;
+    lay.n3 = 3 * nn;
+    if (nn == 0) return STOKES_OK;
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off = stokes::align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t v8 = (size_t)lay.n3 * 8;
+    lay.off_cp = take(lay.cp.total);
+    lay.off_nn = take(v8);
+    lay.off_nw = take((size_t)nn * 8);
+    lay.off_wn = take(v8);
+    lay.off_gx = take(v8);
+    lay.off_gL = take((size_t)n_patches * 8);
+    lay.off_part = take((size_t)(stokes::kMaxKrylov + 1) * stokes::reduce_blocks(lay.n3) * 8);
+    lay.off_dots = take((size_t)(2 * stokes::kMaxKrylov + 4) * 8);
+    lay.off_coef = take((size_t)(stokes::kMaxKrylov + 1) * 8);
+    lay.off_V = take((size_t)(max_iter + 1) * v8);
+    lay.off_w = take(v8);
+    lay.total = off;
+    return STOKES_OK;
+}
+
+// Node normals and weights of the patch polynomial (the fine discretisation
+// with eta = 0), and w*n for the rank-completing term.
+hipError_t bie_geometry(const stokes::PatchRule& R, const BieLayout& lay, int64_t n_patches, const double* node_xyz,
+                        char* ws, hipStream_t st) {
+    stokes::PatchRule R0 = R;
+    R0.eta = 0;
+    double* nn = reinterpret_cast<double*>(ws + lay.off_nn);
+    double* nw = reinterpret_cast<double*>(ws + lay.off_nw);
+    hipError_t e = stokes::launch_upsample(R0, n_patches, node_xyz, nullptr, reinterpret_cast<double*>(ws + lay.off_gx),
+                                           nullptr, nw, nn, reinterpret_cast<double*>(ws + lay.off_gL), st);
+    if (e != hipSuccess) return e;
+    return stokes::launch_weighted_normals(reinterpret_cast<double*>(ws + lay.off_wn), nn, nw, lay.n3 / 3, st);
+}
+
+// out (=|+=) (L_in - N) phi; needs bie_geometry first.  dot_slot: where in the
+// dots buffer n . phi lands.
+hipError_t bie_apply_run(stokes_ctx* ctx, const stokes::PatchRule& R, const BieLayout& lay, int64_t n_patches,
+                         const double* node_xyz, const double* phi, const Parsed& p, double* out, char* ws,
+                         int dot_slot, hipStream_t st) {
+    hipError_t e = checkpoint_run(ctx, R, lay.cp, n_patches, node_xyz, phi, lay.n3 / 3, nullptr, nullptr, p, out,
+                                  nullptr, nullptr, ws + lay.off_cp, st);
+    double* dots = reinterpret_cast<double*>(ws + lay.off_dots) + dot_slot;
+    if (e == hipSuccess)
+        e = stokes::launch_multi_dot(reinterpret_cast<const double*>(ws + lay.off_wn), lay.n3, 1, phi, lay.n3,
+                                     reinterpret_cast<double*>(ws + lay.off_part), dots, st);
+    if (e == hipSuccess)
+        e = stokes::launch_combo_sub(out, reinterpret_cast<const double*>(ws + lay.off_nn), lay.n3, 1, dots, lay.n3,
+                                     st);
+    return e;
 }
 
 }  // namespace
@@ -738,26 +838,163 @@ int stokes_dl_checkpoint_eval(stokes_ctx* ctx, int64_t n_patches, const stokes_p
     if (n_trg == 0) return STOKES_OK;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    return launch_status(checkpoint_run(ctx, R, lay, n_patches, node_xyz, density, n_trg, trg_patch, trg_uvd, p,
+                                        vel_out, check_xyz_out, check_vel_out, static_cast<char*>(workspace),
+                                        static_cast<hipStream_t>(stream)),
+                         "stokes_dl_checkpoint_eval");
+}
+
+int stokes_bie_workspace_size(const stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule,
+                              int32_t max_iter, const stokes_opts* opts, size_t* bytes) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!bytes) return fail(STOKES_EINVAL, "bytes is NULL");
+    stokes::PatchRule R;
+    int rc = parse_patch_rule(rule, true, R);
+    if (rc) return rc;
+    Parsed p;
+    if ((rc = parse_common(nullptr, opts, 0, 0, p))) return rc;
+    BieLayout lay;
+    if ((rc = bie_layout(ctx, n_patches, R, max_iter, p.precision == STOKES_MIXED, lay))) return rc;
+    *bytes = lay.total;
+    return STOKES_OK;
+}
+
+// Shared checks of the operator and the solve: rule, options, layout, node
+// array, one input and one output vector of 3 * nodes doubles, workspace.
+static int bie_prepare(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule, int32_t max_iter,
+                       const double* node_xyz, const double* in, const char* in_name, const stokes_opts* opts,
+                       const double* out, const char* out_name, void* workspace, size_t ws_bytes,
+                       stokes::PatchRule& R, Parsed& p, BieLayout& lay) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    int rc = parse_patch_rule(rule, true, R);
+    if (rc) return rc;
+    if ((rc = parse_common(nullptr, opts, 0, 0, p))) return rc;
+    if ((rc = bie_layout(ctx, n_patches, R, max_iter, p.precision == STOKES_MIXED, lay))) return rc;
+    const int64_t n3 = lay.n3;
+    if (!arr_ok(node_xyz, n3, 8)) return fail(STOKES_EINVAL, "node_xyz must be non-NULL and 8-byte aligned");
+    if (!arr_ok(in, n3, 8)) return fail(STOKES_EINVAL, std::string(in_name) + " must be non-NULL and 8-byte aligned");
+    if (!arr_ok(out, n3, 8))
+        return fail(STOKES_EINVAL, std::string(out_name) + " must be non-NULL and 8-byte aligned");
+    const size_t vb = (size_t)n3 * 8;
+    if ((rc = check_no_alias(out, vb, out_name, {{node_xyz, vb}, {in, vb}, {workspace, ws_bytes}}))) return rc;
+    return check_workspace(workspace, ws_bytes, lay.total);
+}
+
+int stokes_bie_apply(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule, const double* node_xyz,
+                     const double* phi, const stokes_opts* opts, double* out, void* workspace, size_t ws_bytes,
+                     void* stream) {
+    stokes::PatchRule R;
+    Parsed p;
+    BieLayout lay;
+    int rc = bie_prepare(ctx, n_patches, rule, 0, node_xyz, phi, "phi", opts, out, "out", workspace, ws_bytes, R, p,
+                         lay);
+    if (rc) return rc;
+    if (lay.n3 == 0) return STOKES_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* ws = static_cast<char*>(workspace);
-    double* fx = reinterpret_cast<double*>(ws + lay.off_fx);
-    double* fphi = reinterpret_cast<double*>(ws + lay.off_fphi);
-    double* fw = reinterpret_cast<double*>(ws + lay.off_fw);
-    double* fn = reinterpret_cast<double*>(ws + lay.off_fn);
-    double* L = reinterpret_cast<double*>(ws + lay.off_L);
-    double* cx = check_xyz_out ? check_xyz_out : reinterpret_cast<double*>(ws + lay.off_cx);
-    double* cv = check_vel_out ? check_vel_out : reinterpret_cast<double*>(ws + lay.off_cv);
-    hipError_t e = stokes::launch_upsample(R, n_patches, node_xyz, density, fx, fphi, fw, fn, L, st);
-    if (e == hipSuccess)
-        e = stokes::launch_check_points(R, n_patches, node_xyz, L, n_trg, trg_patch, trg_uvd, cx, st);
-    if (e == hipSuccess) {
-        const stokes::SumInputs in = make_inputs(STOKES_KERNEL_DL, p, lay.n_fine, fx, fphi, fw, fn, lay.n_check,
-                                                 cx, 6.0 / (8.0 * kPi));
-        e = stokes::launch_direct(in, lay.plan, cv, 0, ws + lay.off_direct, st, stokes::next_timer(ctx));
+    hipError_t e = bie_geometry(R, lay, n_patches, node_xyz, ws, st);
+    if (e == hipSuccess) e = bie_apply_run(ctx, R, lay, n_patches, node_xyz, phi, p, out, ws, 0, st);
+    return launch_status(e, "stokes_bie_apply");
+}
+
+int stokes_bie_solve(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule* rule, const double* node_xyz,
+                     const double* g, int32_t max_iter, double rtol, const stokes_opts* opts, double* phi_out,
+                     int32_t* iterations, double* residual_history, void* workspace, size_t ws_bytes,
+                     void* stream) {
+    if (max_iter < 1) return fail(STOKES_EINVAL, "max_iter must be in [1, " + std::to_string(stokes::kMaxKrylov) + "]");
+    if (!(rtol >= 0.0) || !isfinite(rtol)) return fail(STOKES_EINVAL, "rtol must be finite and >= 0");
+    if (!iterations) return fail(STOKES_EINVAL, "iterations is NULL");
+    if (opts && opts->accumulate) return fail(STOKES_EINVAL, "opts.accumulate must be 0 for the solve");
+    stokes::PatchRule R;
+    Parsed p;
+    BieLayout lay;
+    int rc = bie_prepare(ctx, n_patches, rule, max_iter, node_xyz, g, "g", opts, phi_out, "phi_out", workspace,
+                         ws_bytes, R, p, lay);
+    if (rc) return rc;
+    *iterations = 0;
+    if (residual_history) residual_history[0] = 1.0;
+    if (lay.n3 == 0) return STOKES_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    const int64_t n3 = lay.n3;
+    double* V = reinterpret_cast<double*>(ws + lay.off_V);
+    double* w = reinterpret_cast<double*>(ws + lay.off_w);
+    double* part = reinterpret_cast<double*>(ws + lay.off_part);
+    double* dots = reinterpret_cast<double*>(ws + lay.off_dots);
+    double* coef = reinterpret_cast<double*>(ws + lay.off_coef);
+    auto status = [](hipError_t e) { return launch_status(e, "stokes_bie_solve"); };
+    auto read = [&](double* host, int count) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(host, dots, (size_t)count * 8, hipMemcpyDeviceToHost, st);
+        return e == hipSuccess ? hipStreamSynchronize(st) : e;
+    };
+
+    // beta = |g|, v_0 = g / beta
+    hipError_t e = bie_geometry(R, lay, n_patches, node_xyz, ws, st);
+    if (e == hipSuccess) e = stokes::launch_multi_dot(g, n3, 1, g, n3, part, dots, st);
+    double beta2 = 0.0;
+    if (e == hipSuccess) e = read(&beta2, 1);
+    if (e != hipSuccess) return status(e);
+    if (!isfinite(beta2)) return fail(STOKES_EINVAL, "g holds non-finite values");
+    const double beta = sqrt(beta2);
+    if (beta == 0.0) return status(stokes::launch_fill_zero(phi_out, n3, st));
+    if ((e = stokes::launch_scale(V, g, 1.0 / beta, n3, st)) != hipSuccess) return status(e);
+
+    // Arnoldi with classical Gram-Schmidt applied twice; Givens rotations on
+    // the Hessenberg matrix on the host.
+    const int m = max_iter;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), sv(m + 1, 0.0), hd(2 * m + 2);
+    auto h = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+    sv[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+        const double* vj = V + (int64_t)j * n3;
+        const int nv = j + 1;
+        e = bie_apply_run(ctx, R, lay, n_patches, node_xyz, vj, p, w, ws, 2 * m + 2, st);
+        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+            e = stokes::launch_multi_dot(V, n3, nv, w, n3, part, dots + pass * nv, st);
+            if (e == hipSuccess) e = stokes::launch_combo_sub(w, V, n3, nv, dots + pass * nv, n3, st);
+        }
+        if (e == hipSuccess) e = stokes::launch_multi_dot(w, n3, 1, w, n3, part, dots + 2 * nv, st);
+        if (e == hipSuccess) e = read(hd.data(), 2 * nv + 1);
+        if (e != hipSuccess) return status(e);
+        for (int i = 0; i < nv; ++i) h(i, j) = hd[i] + hd[nv + i];
+        const double hnext = sqrt(fmax(hd[2 * nv], 0.0));
+        h(j + 1, j) = hnext;
+        if (!isfinite(hnext)) return fail(STOKES_EDEVICE, "stokes_bie_solve: non-finite Krylov vector");
+        for (int i = 0; i < j; ++i) {
+            const double a = h(i, j), b = h(i + 1, j);
+            h(i, j) = cs[i] * a + sn[i] * b;
+            h(i + 1, j) = -sn[i] * a + cs[i] * b;
+        }
+        const double den = hypot(h(j, j), h(j + 1, j));
+        cs[j] = den > 0.0 ? h(j, j) / den : 1.0;
+        sn[j] = den > 0.0 ? h(j + 1, j) / den : 0.0;
+        h(j, j) = den;
+        h(j + 1, j) = 0.0;
+        sv[j + 1] = -sn[j] * sv[j];
+        sv[j] = cs[j] * sv[j];
+        k = j + 1;
+        const double res = fabs(sv[j + 1]) / beta;
+        if (residual_history) residual_history[k] = res;
+        if (res <= rtol || hnext == 0.0 || k == m) break;
+        if ((e = stokes::launch_scale(V + (int64_t)k * n3, w, 1.0 / hnext, n3, st)) != hipSuccess) return status(e);
     }
-    if (e == hipSuccess)
-        e = stokes::launch_extrapolate(R, n_patches, L, n_trg, trg_patch, trg_uvd, cv, vel_out, p.accumulate, st);
-    return launch_status(e, "stokes_dl_checkpoint_eval");
+    // y = H_k^{-1} s by back substitution, phi = V_k y
+    std::vector<double> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+        double acc = sv[i];
+        for (int l = i + 1; l < k; ++l) acc -= h(i, l) * y[l];
+        y[i] = h(i, i) != 0.0 ? acc / h(i, i) : 0.0;
+    }
+    e = hipMemcpyAsync(coef, y.data(), (size_t)k * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = stokes::launch_combo_set(phi_out, V, n3, k, coef, n3, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    *iterations = k;
+    return status(e);
 }
 
 }  // extern "C"
