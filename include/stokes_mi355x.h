@@ -385,6 +385,49 @@ int stokes_bie_solve(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule
                      const stokes_opts* opts, double* phi_out, int32_t* iterations,
                      double* residual_history, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- collision candidates by spatial hashing, Sec. 4 (steps a-c of Sec. 3.3) */
+
+/* Space-time bounding boxes: for each mesh m, the smallest axis-aligned box
+ * holding its points mesh_ofs[m] .. mesh_ofs[m+1]-1 at the start (x0) and the
+ * end (x1, NULL for meshes that do not move, such as wall patches) of the
+ * time step, moved out by inflate >= 0 on every side (the near-zone margin of
+ * Sec. 3.3 step a; 0 for collision candidates).
+ *   mesh_ofs   device int64[n_meshes + 1]; entries are clamped to
+ *              [0, n_points], and a mesh with mesh_ofs[m+1] <= mesh_ofs[m] is
+ *              empty: lo = +inf, hi = -inf (it takes part in no pair).
+ *   x0, x1     (3, n_points).
+ *   box_lo, box_hi (3, n_meshes) outputs.
+ * A NaN coordinate makes the mesh's box NaN, which the search treats as
+ * empty. */
+int stokes_space_time_boxes(stokes_ctx* ctx, int32_t n_meshes, const int64_t* mesh_ofs, int64_t n_points,
+                            const double* x0, const double* x1, double inflate, double* box_lo,
+                            double* box_hi, void* stream);
+
+/* Workspace of stokes_collision_candidates for n_boxes boxes and room for
+ * max_entries (box, grid cell) entries (at most 2^31). */
+int stokes_collision_workspace_size(const stokes_ctx* ctx, int32_t n_boxes, int64_t max_entries,
+                                    size_t* bytes);
+
+/* Candidate pairs: boxes that share a cell of the grid of spacing cell_size
+ * (the paper takes the mean box diagonal) whose origin is the lowest corner of
+ * the valid boxes.  A box covers the cells floor((lo - origin) / cell_size) ..
+ * floor((hi - origin) / cell_size) on each axis (float64), which are the cells
+ * the paper's volume samples hash to; a box with lo > hi on some axis (empty,
+ * or NaN) covers none.  Every unordered pair (i, j), i < j, sharing a cell is
+ * reported once: pairs_out (2, capacity) int32, device, row 0 = i, row 1 =
+ * j, ordered by the Morton key of the pair's lowest shared cell, then i, then
+ * j.  Only the first min(*n_pairs, capacity) pairs are written; *n_pairs
+ * (host) gets the total, so a call with capacity 0 counts them.  *n_entries
+ * (host, may be NULL) gets the number of (box, cell) entries.
+ * Errors found on the GPU, after kernels have run (outputs untouched):
+ *   STOKES_EWORKSPACE    more than max_entries entries (*n_entries says how many);
+ *   STOKES_EUNSUPPORTED  a cell coordinate of 2^21 or more, or an infinite corner.
+ * The call blocks until the pairs are written. */
+int stokes_collision_candidates(stokes_ctx* ctx, int32_t n_boxes, const double* box_lo,
+                                const double* box_hi, double cell_size, int64_t max_entries,
+                                int32_t* pairs_out, int64_t capacity, int64_t* n_pairs,
+                                int64_t* n_entries, void* workspace, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

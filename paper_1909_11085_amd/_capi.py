@@ -87,6 +87,10 @@ _SIGNATURES = {
     "stokes_bie_apply": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _OP, _vp, _vp, _sz, _vp]),
     "stokes_bie_solve": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _i32, _dbl, _OP, _vp,
                                         ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _sz, _vp]),
+    "stokes_space_time_boxes": (ctypes.c_int, [_vp, _i32, _vp, _i64, _vp, _vp, _dbl, _vp, _vp, _vp]),
+    "stokes_collision_workspace_size": (ctypes.c_int, [_vp, _i32, _i64, ctypes.POINTER(_sz)]),
+    "stokes_collision_candidates": (ctypes.c_int, [_vp, _i32, _vp, _vp, _dbl, _i64, _vp, _i64,
+                                                   ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp, _sz, _vp]),
 }
 
 _lib = None

@@ -503,3 +503,57 @@ def bie_solve(node_xyz, g, nodes_1d, weights_1d, eta=1, p=8, R_frac=0.15, r_frac
                                      hist, _ptr(ws), size, _stream(device)))
     return out, its.value, np.array(hist[: its.value + 1])
 
+
+# ----------------------------------------------------------------------------
+# collision candidates by spatial hashing
+# ----------------------------------------------------------------------------
+def space_time_boxes(mesh_ofs, x0, x1=None, inflate=0.0):
+    """Space-time bounding box per mesh; see stokes_space_time_boxes.
+
+    mesh_ofs: int64 tensor (n_meshes + 1,) on the device.  Returns (lo, hi),
+    each (3, n_meshes)."""
+    device = x0.device
+    _vec3(x0, "x0", device)
+    if x1 is not None:
+        _vec3(x1, "x1", device)
+        if x1.shape != x0.shape:
+            raise ValueError("x1 must have the shape of x0")
+    nm = mesh_ofs.numel() - 1
+    _vec1(mesh_ofs, nm + 1, "mesh_ofs", device, torch.int64)
+    lo = torch.empty((3, nm), dtype=torch.float64, device=device)
+    hi = torch.empty((3, nm), dtype=torch.float64, device=device)
+    C.check(C.lib().stokes_space_time_boxes(context(device), nm, _ptr(mesh_ofs), x0.shape[1], _ptr(x0), _ptr(x1),
+                                            float(inflate), _ptr(lo), _ptr(hi), _stream(device)))
+    return lo, hi
+
+
+def collision_candidates(lo, hi, cell_size, max_entries=None, capacity=None):
+    """Pairs of boxes sharing a grid cell; see stokes_collision_candidates.
+
+    Returns an int32 tensor (2, n_pairs) on the device.  max_entries defaults
+    to 64 per box; capacity to what a first counting call reports."""
+    device = lo.device
+    _vec3(lo, "lo", device)
+    _vec3(hi, "hi", device)
+    nb = lo.shape[1]
+    if hi.shape != lo.shape:
+        raise ValueError("hi must have the shape of lo")
+    max_entries = 64 * max(nb, 1) if max_entries is None else int(max_entries)
+    size = ctypes.c_size_t()
+    C.check(C.lib().stokes_collision_workspace_size(context(device), nb, max_entries, ctypes.byref(size)))
+    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    n_pairs, n_entries = ctypes.c_int64(), ctypes.c_int64()
+
+    def call(buf, cap):
+        C.check(C.lib().stokes_collision_candidates(context(device), nb, _ptr(lo), _ptr(hi), float(cell_size),
+                                                    max_entries, _ptr(buf), cap, ctypes.byref(n_pairs),
+                                                    ctypes.byref(n_entries), _ptr(ws), int(size.value),
+                                                    _stream(device)))
+
+    if capacity is None:
+        call(None, 0)
+        capacity = n_pairs.value
+    out = torch.empty((2, max(int(capacity), 1)), dtype=torch.int32, device=device)
+    call(out, int(capacity))
+    return out[:, : min(n_pairs.value, int(capacity))]
+

@@ -13,6 +13,7 @@
 #include "checkpoint.hpp"
 #include "common.hpp"
 #include "p2p.hpp"
+#include "spatial.hpp"
 #include "vjp.hpp"
 
 struct stokes_ctx {
@@ -995,6 +996,89 @@ int stokes_bie_solve(stokes_ctx* ctx, int64_t n_patches, const stokes_patch_rule
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     *iterations = k;
     return status(e);
+}
+
+int stokes_space_time_boxes(stokes_ctx* ctx, int32_t n_meshes, const int64_t* mesh_ofs, int64_t n_points,
+                            const double* x0, const double* x1, double inflate, double* box_lo, double* box_hi,
+                            void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (n_meshes < 0) return fail(STOKES_EINVAL, "n_meshes must be >= 0");
+    int rc = check_sizes(n_points, 0);
+    if (rc) return rc;
+    if (!isfinite(inflate) || inflate < 0.0) return fail(STOKES_EINVAL, "inflate must be finite and >= 0");
+    if (n_meshes > 0 && (!mesh_ofs || !aligned(mesh_ofs, 8)))
+        return fail(STOKES_EINVAL, "mesh_ofs must be non-NULL and 8-byte aligned");
+    if (!arr_ok(x0, 3 * n_points, 8)) return fail(STOKES_EINVAL, "x0 must be non-NULL and 8-byte aligned");
+    if (x1 && !aligned(x1, 8)) return fail(STOKES_EINVAL, "x1 must be 8-byte aligned");
+    if (!arr_ok(box_lo, 3 * (int64_t)n_meshes, 8) || !arr_ok(box_hi, 3 * (int64_t)n_meshes, 8))
+        return fail(STOKES_EINVAL, "box_lo and box_hi must be non-NULL and 8-byte aligned");
+    const size_t pb = (size_t)3 * n_points * 8, bb = (size_t)3 * n_meshes * 8;
+    const std::initializer_list<std::pair<const void*, size_t>> inputs = {
+        {mesh_ofs, (size_t)(n_meshes + 1) * 8}, {x0, pb}, {x1, x1 ? pb : 0}};
+    if ((rc = check_no_alias(box_lo, bb, "box_lo", inputs))) return rc;
+    if ((rc = check_no_alias(box_hi, bb, "box_hi", inputs))) return rc;
+    if (overlaps(box_lo, bb, box_hi, bb)) return fail(STOKES_EINVAL, "box_lo and box_hi overlap");
+    if (n_meshes == 0) return STOKES_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    return launch_status(stokes::launch_space_time_boxes(n_meshes, mesh_ofs, n_points, x0, x1, inflate, box_lo,
+                                                         box_hi, static_cast<hipStream_t>(stream)),
+                         "stokes_space_time_boxes");
+}
+
+int stokes_collision_workspace_size(const stokes_ctx* ctx, int32_t n_boxes, int64_t max_entries, size_t* bytes) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!bytes) return fail(STOKES_EINVAL, "bytes is NULL");
+    if (n_boxes < 0) return fail(STOKES_EINVAL, "n_boxes must be >= 0");
+    if (max_entries < 0 || max_entries > ((int64_t)1 << 31))
+        return fail(STOKES_EINVAL, "max_entries must be in [0, 2^31]");
+    *bytes = stokes::candidate_layout(n_boxes, max_entries).total;
+    return STOKES_OK;
+}
+
+int stokes_collision_candidates(stokes_ctx* ctx, int32_t n_boxes, const double* box_lo, const double* box_hi,
+                                double cell_size, int64_t max_entries, int32_t* pairs_out, int64_t capacity,
+                                int64_t* n_pairs, int64_t* n_entries, void* workspace, size_t ws_bytes,
+                                void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (n_boxes < 0) return fail(STOKES_EINVAL, "n_boxes must be >= 0");
+    if (!(isfinite(cell_size) && cell_size > 0.0)) return fail(STOKES_EINVAL, "cell_size must be finite and > 0");
+    if (max_entries < 0 || max_entries > ((int64_t)1 << 31))
+        return fail(STOKES_EINVAL, "max_entries must be in [0, 2^31]");
+    if (capacity < 0) return fail(STOKES_EINVAL, "capacity must be >= 0");
+    if (!n_pairs) return fail(STOKES_EINVAL, "n_pairs is NULL");
+    if (!arr_ok(box_lo, 3 * (int64_t)n_boxes, 8) || !arr_ok(box_hi, 3 * (int64_t)n_boxes, 8))
+        return fail(STOKES_EINVAL, "box_lo and box_hi must be non-NULL and 8-byte aligned");
+    if (!arr_ok(pairs_out, 2 * capacity, 4))
+        return fail(STOKES_EINVAL, "pairs_out must be non-NULL and 4-byte aligned when capacity > 0");
+    const size_t bb = (size_t)3 * n_boxes * 8;
+    int rc = check_no_alias(pairs_out, (size_t)2 * capacity * 4, "pairs_out",
+                            {{box_lo, bb}, {box_hi, bb}, {workspace, ws_bytes}});
+    if (rc) return rc;
+    const stokes::CandidateLayout lay = stokes::candidate_layout(n_boxes, max_entries);
+    if ((rc = check_workspace(workspace, ws_bytes, lay.total))) return rc;
+    *n_pairs = 0;
+    if (n_entries) *n_entries = 0;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    stokes::CandidateMeta meta{};
+    hipError_t e = stokes::candidate_phase1(n_boxes, box_lo, box_hi, cell_size, ws, lay, &meta, st);
+    if (e != hipSuccess) return launch_status(e, "stokes_collision_candidates");
+    if (n_entries) *n_entries = meta.entries;
+    if (meta.overflow)
+        return fail(STOKES_EUNSUPPORTED, "a box corner is not finite or lies 2^21 or more cells from the origin "
+                                         "(cell_size too small)");
+    if (meta.entries > max_entries)
+        return fail(STOKES_EWORKSPACE, "max_entries " + std::to_string(max_entries) + " < the " +
+                                           std::to_string(meta.entries) + " (box, cell) entries needed");
+    int64_t np = 0;
+    e = stokes::candidate_phase2(n_boxes, meta, ws, lay, &np, st);
+    if (e == hipSuccess) e = stokes::candidate_phase3(n_boxes, meta, ws, lay, pairs_out, capacity, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    *n_pairs = np;
+    return launch_status(e, "stokes_collision_candidates");
 }
 
 }  // extern "C"

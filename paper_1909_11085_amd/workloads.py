@@ -312,6 +312,29 @@ def cube_sphere(radius=1.0, m=2, q=16, axes=(1.0, 1.0, 1.0), centre=(0.0, 0.0, 0
                               points_per_patch=q * q, q=q, nodes_1d=t, weights_1d=wt))
 
 
+def cells_after_step(rng, cells, max_shift=0.5, max_angle=0.05):
+    """Positions of the cells' points one time step later: each cell (a group)
+    moves rigidly by a uniform random shift of at most max_shift per axis and a
+    rotation by at most max_angle radians about its centroid.  Returns (3, N)."""
+    x1 = np.empty_like(cells.pos)
+    for g in np.unique(cells.group):
+        idx = np.nonzero(cells.group == g)[0]
+        c = cells.pos[:, idx].mean(axis=1, keepdims=True)
+        axis = rng.standard_normal(3)
+        axis /= np.linalg.norm(axis)
+        ang = rng.uniform(-max_angle, max_angle)
+        K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+        Rm = np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * K @ K
+        x1[:, idx] = c + Rm @ (cells.pos[:, idx] - c) + rng.uniform(-max_shift, max_shift, (3, 1))
+    return x1
+
+
+def group_offsets(group):
+    """CSR offsets (n_groups + 1,) of points sorted by group id."""
+    counts = np.bincount(np.asarray(group), minlength=int(np.max(group)) + 1 if len(group) else 0)
+    return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+
+
 # ----------------------------------------------------------------------------
 # Octree leaves and interaction lists (FMM near field)
 # ----------------------------------------------------------------------------
