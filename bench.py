@@ -21,8 +21,9 @@ Reported on one JSON line (stdout):
 
 --only checkpoint times the check-point double-layer quadrature on a
 vessel-wall ring (every node an on-surface target), --only bie the
-30-iteration GMRES solve of the boundary integral equation on an ellipsoid;
---secondary adds both and the other workload shapes to the line.
+30-iteration GMRES solve of the boundary integral equation on an ellipsoid,
+--only collision the collision-candidate search of the cells and the wall;
+--secondary adds them and the other workload shapes to the line.
 """
 import argparse
 import hashlib
@@ -86,11 +87,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="headline precision (the other one is reported alongside)")
-    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p", "checkpoint", "bie"], default=None,
+    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p", "checkpoint", "bie", "collision"],
+                    default=None,
                     help="time one path only (for profiler runs); p2p times the leaf-to-leaf "
                          "workload (3,840 cells in the cylinder) in both precisions; checkpoint "
                          "the check-point double-layer quadrature on a vessel-wall ring; bie the "
-                         "30-iteration GMRES solve of the boundary integral equation")
+                         "30-iteration GMRES solve of the boundary integral equation; collision the "
+                         "space-time boxes and collision candidates of 3,840 cells and the wall")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
@@ -152,6 +155,11 @@ def main():
         r = time_p2p(S, W, t, timed, args.steps, args.warmup)
         log(f"p2p: {r}")
         print(json.dumps({"p2p_3840_cells": r}), flush=True)
+        return
+    if args.only == "collision":
+        r = time_collision(S, W, t, args.steps, args.warmup, oracle=not args.no_cpu_baseline)
+        log(f"collision: {r}")
+        print(json.dumps({"collision_cells_and_wall": r}), flush=True)
         return
     if args.only == "bie":
         r = time_bie(S, W, t, args.steps, args.warmup)
@@ -402,6 +410,75 @@ def time_bie(S, W, t, steps, warmup):
             "precision": "fp64", "timing": "host clock around the blocking solve"}
 
 
+def time_collision(S, W, t, steps, warmup, oracle=True):
+    """Collision candidates (Sec. 4): space-time boxes of the 3,840 cells of
+    the cylinder workload over one time step (rigid random shifts of up to 0.5
+    and turns of up to 0.05 rad per cell) and boxes of the 4,096 static wall
+    patches, then the pairs of boxes sharing a cell of the grid whose spacing
+    is the mean box diagonal.  One step = both box kernels and one candidate
+    search.  The box kernels read every point at both time levels once."""
+    import torch
+    from types import SimpleNamespace
+
+    cfg = W.make_config(4)
+    cells = cfg["cells"]
+    order = np.argsort(cells.group, kind="stable")
+    pos = np.ascontiguousarray(cells.pos[:, order])
+    grp = cells.group[order]
+    x1 = W.cells_after_step(np.random.default_rng(66), SimpleNamespace(pos=pos, group=grp))
+    ofs = W.group_offsets(grp)
+    wall = W.cylinder_wall()
+    wofs = np.arange(0, wall.n + 1, wall.meta["points_per_patch"], dtype=np.int64)
+    P0, P1, O, WP, WO = t(pos), t(x1), t(ofs), t(wall.pos), t(wofs)
+    nc, nw = len(ofs) - 1, len(wofs) - 1
+    lo = torch.empty((3, nc + nw), dtype=torch.float64, device=P0.device)
+    hi = torch.empty_like(lo)
+    box_bytes = (2 * pos.shape[1] + wall.n) * 24 + (len(ofs) + len(wofs)) * 8 + 2 * (nc + nw) * 48
+
+    def boxes():
+        a, b = S.space_time_boxes(O, P0, P1)
+        c, d = S.space_time_boxes(WO, WP)
+        lo[:, :nc], lo[:, nc:], hi[:, :nc], hi[:, nc:] = a, c, b, d
+
+    boxes()
+    H = float((hi - lo).norm(dim=0).mean())
+    pairs = S.collision_candidates(lo, hi, H)
+    cap = pairs.shape[1]
+    for _ in range(warmup):
+        boxes()
+        S.collision_candidates(lo, hi, H, capacity=cap)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    box_ms = search_ms = 0.0
+    t0 = time.time()
+    for _ in range(steps):
+        e0.record()
+        boxes()
+        e1.record()
+        pairs = S.collision_candidates(lo, hi, H, capacity=cap)
+        e2.record()
+        torch.cuda.synchronize()
+        box_ms += e0.elapsed_time(e1)
+        search_ms += e1.elapsed_time(e2)
+    ms = (time.time() - t0) * 1e3 / steps
+    r = {"meshes": nc + nw, "cells": nc, "wall_patches": nw, "points_read": 2 * pos.shape[1] + wall.n,
+         "cell_size": H, "candidate_pairs": int(pairs.shape[1]), "step_ms": ms, "boxes_ms": box_ms / steps,
+         "boxes_GBps": box_bytes / (box_ms / steps * 1e-3) / 1e9, "boxes_bytes": box_bytes,
+         "search_ms": search_ms / steps, "note": "boxes_ms includes the slicing copies into one box array"}
+    if oracle:                           # CPU baseline leg: the oracle's search on the same boxes
+        from oracle import spatial as SP
+
+        hlo, hhi = lo.cpu().numpy(), hi.cpu().numpy()
+        tc = time.time()
+        ref = SP.collision_candidates(hlo, hhi, H)
+        dt = time.time() - tc
+        r["cpu_baseline"] = {"value": 1e3 * dt, "unit": "ms per search", "cores": 1, "kind": "oracle",
+                             "sample": f"the whole search over {nc + nw} boxes, brute force over pairs"}
+        got = {tuple(p) for p in pairs.cpu().numpy().T.tolist()}
+        r["matches_oracle"] = got == {tuple(p) for p in ref.tolist()}
+    return r
+
+
 def secondary(S, W, t, timed, log):
     """Timings of the other workload shapes (not the headline)."""
     import torch
@@ -470,6 +547,9 @@ def secondary(S, W, t, timed, log):
     r = time_bie(S, W, t, 2, 1)
     out["bie_solve_ellipsoid"] = r
     log(f"secondary bie: {r}")
+    r = time_collision(S, W, t, 5, 1, oracle=False)
+    out["collision_cells_and_wall"] = r
+    log(f"secondary collision: {r}")
     return out
 
 

@@ -1,8 +1,8 @@
 // Spatial-hash candidate search on the GPU (Sec. 4, reusing steps a-c of the
 // closest-point search of Sec. 3.3):
 //
-//   boxes        space-time bounding box per mesh: a wave per mesh, min / max
-//                over its points at both time levels (exact, any order);
+//   boxes        space-time bounding box per mesh: a workgroup per mesh, min /
+//                max over its points at both time levels (exact, any order);
 //   phase 1      grid origin (lowest valid corner), each box's integer cell
 //                range floor((corner - origin) / H), its cell count, and the
 //                exclusive prefix sum of the counts (two-level, exact);
@@ -32,11 +32,12 @@ namespace {
 constexpr int kSpBlock = 256;
 constexpr int kSpWaves = kSpBlock / kWave;
 constexpr int kRadix = 256;                      // 8-bit digits; one digit per thread of a block
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kSpBlock * kSortItems;  // keys per sort workgroup
+constexpr int kSortItems = 8;                     // most keys per thread of a sort workgroup
+constexpr int kSortTile = kSpBlock * kSortItems;  // most keys per sort workgroup
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kSpBlock * kScanItems;  // elements per scan workgroup
 constexpr int64_t kSpMaxGrid = 1 << 16;
+constexpr int kOriginBlocks = 64;                // workgroups of the origin reduction
 static_assert(kSpBlock == kRadix, "one digit per thread");
 
 unsigned sp_grid(int64_t units, int64_t per) {
@@ -52,13 +53,13 @@ __global__ __launch_bounds__(kSpBlock) void boxes_kernel(int32_t n_meshes, const
                                                          int64_t n, const double* __restrict__ x0,
                                                          const double* __restrict__ x1, double inflate,
                                                          double* __restrict__ lo, double* __restrict__ hi) {
-    const int lane = threadIdx.x % kWave;
-    for (int64_t m = (int64_t)blockIdx.x * kSpWaves + threadIdx.x / kWave; m < n_meshes;
-         m += (int64_t)gridDim.x * kSpWaves) {        // uniform over the wave
+    __shared__ double red[kSpWaves][6];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    for (int64_t m = blockIdx.x; m < n_meshes; m += gridDim.x) {      // uniform over the workgroup
         const int64_t a = std::min(std::max(ofs[m], (int64_t)0), n);
         const int64_t b = std::min(std::max(ofs[m + 1], (int64_t)0), n);
         double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int64_t i = a + lane; i < b; i += kWave) {
+        for (int64_t i = a + threadIdx.x; i < b; i += kSpBlock) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double v = x0[c * n + i];
@@ -80,9 +81,22 @@ __global__ __launch_bounds__(kSpBlock) void boxes_kernel(int32_t n_meshes, const
         if (lane == 0)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                lo[c * n_meshes + m] = b > a ? mn[c] - inflate : INFINITY;
-                hi[c * n_meshes + m] = b > a ? mx[c] + inflate : -INFINITY;
+                red[wave][c] = mn[c];
+                red[wave][3 + c] = mx[c];
             }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            const int c = threadIdx.x;
+            double l = red[0][c], h = red[0][3 + c];
+#pragma unroll
+            for (int w = 1; w < kSpWaves; ++w) {
+                l = nmin(l, red[w][c]);
+                h = nmax(h, red[w][3 + c]);
+            }
+            lo[c * (int64_t)n_meshes + m] = b > a ? l - inflate : INFINITY;
+            hi[c * (int64_t)n_meshes + m] = b > a ? h + inflate : -INFINITY;
+        }
+        __syncthreads();                          // red is reused by the next mesh
     }
 }
 
@@ -91,12 +105,15 @@ __device__ __forceinline__ bool box_valid(const double* lo, const double* hi, in
     return lo[b] <= hi[b] && lo[n + b] <= hi[n + b] && lo[2 * n + b] <= hi[2 * n + b];
 }
 
-// Single workgroup: origin = lowest corner over valid boxes; clears the flags.
+// Stage 1 of the origin: per-workgroup minima of the valid boxes' lower
+// corners (part[c * kOriginBlocks + block]); workgroup 0 also clears the
+// summary's counters.
 __global__ __launch_bounds__(kSpBlock) void origin_kernel(int32_t n, const double* __restrict__ lo,
-                                                          const double* __restrict__ hi, CandidateMeta* meta) {
+                                                          const double* __restrict__ hi, double* __restrict__ part,
+                                                          CandidateMeta* meta) {
     __shared__ double red[3][kSpBlock];
     double mn[3] = {INFINITY, INFINITY, INFINITY};
-    for (int64_t b = threadIdx.x; b < n; b += kSpBlock)
+    for (int64_t b = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; b < n; b += (int64_t)gridDim.x * kSpBlock)
         if (box_valid(lo, hi, n, b))
 #pragma unroll
             for (int c = 0; c < 3; ++c) mn[c] = fmin(mn[c], lo[c * (int64_t)n + b]);
@@ -109,9 +126,9 @@ __global__ __launch_bounds__(kSpBlock) void origin_kernel(int32_t n, const doubl
             for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = fmin(red[c][threadIdx.x], red[c][threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) meta->origin[c] = red[c][0] < INFINITY ? red[c][0] : 0.0;
+    if (threadIdx.x < 3) part[threadIdx.x * kOriginBlocks + blockIdx.x] = red[threadIdx.x][0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) meta->origin[c] = 0.0;
         meta->entries = 0;
         meta->max_cell = 0;
         meta->overflow = 0;
@@ -119,11 +136,21 @@ __global__ __launch_bounds__(kSpBlock) void origin_kernel(int32_t n, const doubl
 }
 
 // Cell range (clo in rows 0..2, chi in rows 3..5) and cell count per box.
+// Each workgroup first finishes the origin from the stage-1 minima (the
+// lowest valid corner, 0 when there is none); workgroup 0 records it.
 __global__ __launch_bounds__(kSpBlock) void cells_kernel(int32_t n, const double* __restrict__ lo,
                                                          const double* __restrict__ hi, double H,
-                                                         CandidateMeta* meta, int32_t* __restrict__ range,
-                                                         int64_t* __restrict__ count) {
-    const double o[3] = {meta->origin[0], meta->origin[1], meta->origin[2]};
+                                                         const double* __restrict__ part, CandidateMeta* meta,
+                                                         int32_t* __restrict__ range, int64_t* __restrict__ count) {
+    __shared__ double s_o[3];
+    if (threadIdx.x < 3) {
+        double v = INFINITY;
+        for (int g = 0; g < kOriginBlocks; ++g) v = fmin(v, part[threadIdx.x * kOriginBlocks + g]);
+        s_o[threadIdx.x] = v < INFINITY ? v : 0.0;
+        if (blockIdx.x == 0) meta->origin[threadIdx.x] = s_o[threadIdx.x];
+    }
+    __syncthreads();
+    const double o[3] = {s_o[0], s_o[1], s_o[2]};
     for (int64_t b = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; b < n; b += (int64_t)gridDim.x * kSpBlock) {
         int64_t cnt = 0;
         int32_t r[6] = {1, 1, 1, 0, 0, 0};
@@ -267,12 +294,13 @@ __global__ __launch_bounds__(kSpBlock) void emit_kernel(int32_t n, const int32_t
 
 // Digit counts of one sort workgroup's tile, digit-major: hist[d * nb + block].
 __global__ __launch_bounds__(kSpBlock) void rs_hist_kernel(const uint64_t* __restrict__ keys, int64_t E,
-                                                           int shift, int64_t* __restrict__ hist, int64_t nb) {
+                                                           int shift, int items, int64_t* __restrict__ hist,
+                                                           int64_t nb) {
     __shared__ int cnt[kRadix];
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int k = 0; k < kSortItems; ++k) {
+    const int64_t base = (int64_t)blockIdx.x * kSpBlock * items;
+    for (int k = 0; k < items; ++k) {
         const int64_t i = base + (int64_t)k * kSpBlock + threadIdx.x;
         if (i < E) atomicAdd(&cnt[(int)((keys[i] >> shift) & 0xff)], 1);
     }
@@ -285,7 +313,7 @@ __global__ __launch_bounds__(kSpBlock) void rs_hist_kernel(const uint64_t* __res
 // below it with the same digit) plus the counts of the waves before it.
 __global__ __launch_bounds__(kSpBlock) void rs_scatter_kernel(const uint64_t* __restrict__ keys,
                                                               const int32_t* __restrict__ vals, int64_t E,
-                                                              int shift, const int64_t* __restrict__ hoff,
+                                                              int shift, int items, const int64_t* __restrict__ hoff,
                                                               int64_t nb, uint64_t* __restrict__ keys_out,
                                                               int32_t* __restrict__ vals_out) {
     __shared__ int64_t run[kRadix];
@@ -293,8 +321,8 @@ __global__ __launch_bounds__(kSpBlock) void rs_scatter_kernel(const uint64_t* __
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     run[tid] = hoff[(int64_t)tid * nb + blockIdx.x];
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    for (int k = 0; k < kSortItems; ++k) {
+    const int64_t base = (int64_t)blockIdx.x * kSpBlock * items;
+    for (int k = 0; k < items; ++k) {
 #pragma unroll
         for (int w = 0; w < kSpWaves; ++w) wcnt[w][tid] = 0;
         __syncthreads();
@@ -372,7 +400,7 @@ __global__ __launch_bounds__(kSpBlock) void pairs_kernel(int64_t E, const uint64
 hipError_t launch_space_time_boxes(int32_t n_meshes, const int64_t* ofs, int64_t n_points, const double* x0,
                                    const double* x1, double inflate, double* lo, double* hi, hipStream_t stream) {
     if (n_meshes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(boxes_kernel, dim3(sp_grid(n_meshes, kSpWaves)), dim3(kSpBlock), 0, stream, n_meshes, ofs,
+    hipLaunchKernelGGL(boxes_kernel, dim3(sp_grid(n_meshes, 1)), dim3(kSpBlock), 0, stream, n_meshes, ofs,
                        n_points, x0, x1, inflate, lo, hi);
     return hipGetLastError();
 }
@@ -389,7 +417,7 @@ CandidateLayout candidate_layout(int32_t n_boxes, int64_t max_entries) {
         return at;
     };
     const size_t nb = (size_t)std::max<int32_t>(n_boxes, 1), ne = (size_t)std::max<int64_t>(max_entries, 1);
-    L.off_meta = take(sizeof(CandidateMeta) + 2 * sizeof(int64_t));
+    L.off_meta = take(sizeof(CandidateMeta) + 2 * sizeof(int64_t) + 3 * kOriginBlocks * sizeof(double));
     L.off_range = take(6 * nb * sizeof(int32_t));
     L.off_count = take(2 * (nb + 1) * sizeof(int64_t));                // counts, then offsets
     L.off_scan = take(((size_t)nscan / kScanTile + 2) * sizeof(int64_t));
@@ -410,11 +438,12 @@ hipError_t candidate_phase1(int32_t n_boxes, const double* lo, const double* hi,
     int64_t* count = reinterpret_cast<int64_t*>(ws + L.off_count);
     int64_t* offs = count + (n_boxes + 1);
     int64_t* tmp = reinterpret_cast<int64_t*>(ws + L.off_scan);
-    hipLaunchKernelGGL(origin_kernel, dim3(1), dim3(kSpBlock), 0, st, n_boxes, lo, hi, dmeta);
+    double* part = reinterpret_cast<double*>(ws + L.off_meta + sizeof(CandidateMeta) + 2 * sizeof(int64_t));
+    hipLaunchKernelGGL(origin_kernel, dim3(kOriginBlocks), dim3(kSpBlock), 0, st, n_boxes, lo, hi, part, dmeta);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && n_boxes > 0) {
         hipLaunchKernelGGL(cells_kernel, dim3(sp_grid(n_boxes, kSpBlock)), dim3(kSpBlock), 0, st, n_boxes, lo, hi,
-                           cell, dmeta, range, count);
+                           cell, part, dmeta, range, count);
         e = hipGetLastError();
         if (e == hipSuccess) e = exclusive_scan(count, n_boxes, offs, tmp, &dmeta->entries, st);
     }
@@ -450,15 +479,20 @@ hipError_t candidate_phase2(int32_t n_boxes, const CandidateMeta& meta, char* ws
                        keys, vals);
     hipError_t e = hipGetLastError();
     const int passes = sort_passes(meta);
-    const int64_t nb = (E + kSortTile - 1) / kSortTile;
+    // the fewest keys per thread (so the most workgroups) that the histogram
+    // space, sized for kSortTile keys per workgroup, allows
+    const int items = (int)std::min<int64_t>(
+        kSortItems, std::max<int64_t>(1, (E + (int64_t)kSpBlock * L.sort_blocks - 1) / ((int64_t)kSpBlock * L.sort_blocks)));
+    const int64_t nb = (E + (int64_t)kSpBlock * items - 1) / ((int64_t)kSpBlock * items);
     int64_t* hoff = hist + (int64_t)kRadix * nb;
     for (int p = 0; p < passes && e == hipSuccess; ++p) {
-        hipLaunchKernelGGL(rs_hist_kernel, dim3((unsigned)nb), dim3(kSpBlock), 0, st, keys, E, 8 * p, hist, nb);
+        hipLaunchKernelGGL(rs_hist_kernel, dim3((unsigned)nb), dim3(kSpBlock), 0, st, keys, E, 8 * p, items, hist,
+                           nb);
         e = hipGetLastError();
         if (e == hipSuccess) e = exclusive_scan(hist, (int64_t)kRadix * nb, hoff, tmp, total, st);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(rs_scatter_kernel, dim3((unsigned)nb), dim3(kSpBlock), 0, st, keys, vals, E, 8 * p,
-                               hoff, nb, keys2, vals2);
+                               items, hoff, nb, keys2, vals2);
             e = hipGetLastError();
         }
         std::swap(keys, keys2);
