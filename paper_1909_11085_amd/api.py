@@ -557,3 +557,47 @@ def collision_candidates(lo, hi, cell_size, max_entries=None, capacity=None):
     call(out, int(capacity))
     return out[:, : min(n_pairs.value, int(capacity))]
 
+
+# ----------------------------------------------------------------------------
+# fast multipole method (single layer)
+# ----------------------------------------------------------------------------
+class FMMPlan:
+    """Check-to-equivalent operators of one surface order, on the device; see
+    stokes_fmm_plan_create."""
+
+    def __init__(self, order=4, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._h = ctypes.c_void_p()
+        C.check(C.lib().stokes_fmm_plan_create(context(self.device), int(order), ctypes.byref(self._h)))
+        self.order = int(order)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            try:
+                C.lib().stokes_fmm_plan_destroy(self._h)
+            except Exception:
+                pass
+            self._h = ctypes.c_void_p()
+
+
+def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, accumulate=False):
+    """Single-layer sum by the FMM; see stokes_fmm_sl_eval."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    out = _out(out, nt, device, accumulate)
+    size = ctypes.c_size_t()
+    C.check(C.lib().stokes_fmm_workspace_size(context(device), plan.handle, ns, nt, int(depth), ctypes.byref(size)))
+    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    c = (ctypes.c_double * 3)(*[float(v) for v in centre])
+    opts = C.Opts(C.FP64, int(bool(accumulate)))
+    C.check(C.lib().stokes_fmm_sl_eval(context(device), plan.handle, ns, _ptr(src), _ptr(f), _ptr(w), nt, _ptr(trg),
+                                       float(mu), c, float(half_width), int(depth), ctypes.byref(opts), _ptr(out),
+                                       _ptr(ws), int(size.value), _stream(device)))
+    return out
+

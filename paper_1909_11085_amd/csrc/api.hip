@@ -12,6 +12,7 @@
 #include "bie.hpp"
 #include "checkpoint.hpp"
 #include "common.hpp"
+#include "fmm.hpp"
 #include "p2p.hpp"
 #include "spatial.hpp"
 #include "vjp.hpp"
@@ -1079,6 +1080,96 @@ int stokes_collision_candidates(stokes_ctx* ctx, int32_t n_boxes, const double* 
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     *n_pairs = np;
     return launch_status(e, "stokes_collision_candidates");
+}
+
+int stokes_fmm_plan_create(stokes_ctx* ctx, int32_t order, stokes_fmm_plan** plan) {
+    if (!plan) return fail(STOKES_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (order < stokes::kFmmMinOrder || order > stokes::kFmmMaxOrder)
+        return fail(STOKES_EINVAL, "order must be in [" + std::to_string(stokes::kFmmMinOrder) + ", " +
+                                       std::to_string(stokes::kFmmMaxOrder) + "]");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    std::string err;
+    if (stokes::fmm_plan_build(ctx->device, order, plan, err) != 0)
+        return fail(STOKES_EDEVICE, "stokes_fmm_plan_create: " + err);
+    return STOKES_OK;
+}
+
+void stokes_fmm_plan_destroy(stokes_fmm_plan* plan) {
+    if (!plan) return;
+    DeviceGuard dg(stokes::fmm_plan_device(plan));
+    stokes::fmm_plan_free(plan);
+}
+
+static int fmm_check_sizes(const stokes_fmm_plan* plan, int64_t n_src, int64_t n_trg, int32_t depth) {
+    if (!plan) return fail(STOKES_EINVAL, "plan is NULL");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    if (depth < stokes::kFmmMinDepth || depth > stokes::kFmmMaxDepth)
+        return fail(STOKES_EINVAL, "depth must be in [" + std::to_string(stokes::kFmmMinDepth) + ", " +
+                                       std::to_string(stokes::kFmmMaxDepth) + "]");
+    return STOKES_OK;
+}
+
+int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, int64_t n_trg,
+                              int32_t depth, size_t* bytes) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!bytes) return fail(STOKES_EINVAL, "bytes is NULL");
+    int rc = fmm_check_sizes(plan, n_src, n_trg, depth);
+    if (rc) return rc;
+    *bytes = stokes::fmm_workspace_bytes(stokes::fmm_plan_order(plan), n_src, n_trg, depth);
+    return STOKES_OK;
+}
+
+int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, const double* src_xyz,
+                       const double* density, const double* weight, int64_t n_trg, const double* trg_xyz,
+                       double mu, const double* centre, double half_width, int32_t depth,
+                       const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
+                       void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    int rc = fmm_check_sizes(plan, n_src, n_trg, depth);
+    if (rc) return rc;
+    if (stokes::fmm_plan_device(plan) != ctx->device) return fail(STOKES_EINVAL, "the plan was built on another device");
+    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    if (!centre) return fail(STOKES_EINVAL, "centre (host, 3 doubles) is NULL");
+    for (int c = 0; c < 3; ++c)
+        if (!isfinite(centre[c])) return fail(STOKES_EINVAL, "centre must be finite");
+    if (!(isfinite(half_width) && half_width > 0.0)) return fail(STOKES_EINVAL, "half_width must be finite and > 0");
+    Parsed p;
+    if ((rc = parse_common(nullptr, opts, n_src, n_trg, p))) return rc;
+    if (p.precision != STOKES_FP64) return fail(STOKES_EUNSUPPORTED, "the FMM runs in float64 only");
+    if ((rc = check_points(STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz))) return rc;
+    if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
+    const size_t sb = (size_t)3 * n_src * 8, tb = (size_t)3 * n_trg * 8;
+    if ((rc = check_no_alias(vel_out, tb, "vel_out",
+                             {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {trg_xyz, tb},
+                              {workspace, ws_bytes}})))
+        return rc;
+    const size_t need = stokes::fmm_workspace_bytes(stokes::fmm_plan_order(plan), n_src, n_trg, depth);
+    if ((rc = check_workspace(workspace, ws_bytes, need))) return rc;
+    if (n_trg == 0) return STOKES_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    stokes::FmmInputs in{};
+    in.n_src = n_src;
+    in.n_trg = n_trg;
+    in.src_xyz = src_xyz;
+    in.density = density;
+    in.weight = weight;
+    in.trg_xyz = trg_xyz;
+    for (int c = 0; c < 3; ++c) in.centre[c] = centre[c];
+    in.half_width = half_width;
+    in.depth = depth;
+    in.pref = 1.0 / (8.0 * kPi * mu);
+    in.accumulate = p.accumulate;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const stokes::KernelTimer timer = stokes::next_timer(ctx);
+    if (timer.on()) (void)hipEventRecord(timer.start, st);
+    hipError_t e = stokes::launch_fmm_sl(plan, in, vel_out, workspace, st);
+    if (timer.on()) (void)hipEventRecord(timer.stop, st);
+    return launch_status(e, "stokes_fmm_sl_eval");
 }
 
 }  // extern "C"

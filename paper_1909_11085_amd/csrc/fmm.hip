@@ -1,0 +1,656 @@
+// Kernel-independent fast multipole method for the single-layer (Stokeslet)
+// sum on a uniform octree (Sec. 3.1, "Far evaluation": the paper evaluates the
+// smooth quadrature for all targets at once with a kernel-independent FMM).
+//
+// Plan (host, once per surface order p): the cube-surface template with p
+// points per edge and the check-to-equivalent pseudo-inverses for a unit box,
+// upward (check 2.95, equivalent 1.05) and downward (check 1.05, equivalent
+// 2.95), from a one-sided Jacobi SVD that drops singular values below 1e-12 of
+// the largest.  The kernel is homogeneous of degree -1, so at level l the
+// operators are these times the box half-width h_l.  Everything is computed
+// with the kernel times 8 pi mu; the prefactor is applied to the output.
+//
+// Evaluation (device, one stream, no host round trip):
+//   leaf keys (Morton index of the leaf holding each point), radix sort,
+//   gathers into leaf order (sources carry q = w f), leaf offsets by binary
+//   search, per-level "has sources" / "has targets" flags;
+//   P2M, M2M (leaves up to level 2), M2L + L2L (level 2 down to the leaves),
+//   then L2P + P2P per target leaf, written back in the caller's order.
+// The surface sums give each wave of a workgroup a quarter of the source
+// boxes (or points); the four partial check vectors are added in a fixed
+// order, so results are reproducible.
+#include <math.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "fmm.hpp"
+#include "spatial.hpp"
+
+struct stokes_fmm_plan {
+    int device = 0;
+    int order = 0;
+    int ns = 0;                 // surface points
+    double* d_surf = nullptr;   // (ns, 3)
+    double* d_upT = nullptr;    // (3ns, 3ns), transposed: upT[k * 3ns + r] = UP[r][k]
+    double* d_downT = nullptr;
+};
+
+namespace stokes {
+namespace {
+
+constexpr double kAlphaUE = 1.05, kAlphaUC = 2.95, kAlphaDE = 2.95, kAlphaDC = 1.05;
+constexpr double kPinvRcond = 1e-12;
+constexpr int kFBlock = 256;
+constexpr int kFWaves = kFBlock / kWave;
+constexpr int64_t kFMaxGrid = 1 << 16;
+
+unsigned f_grid(int64_t units) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, kFMaxGrid)); }
+
+std::vector<double> surface_points(int p) {
+    std::vector<double> g(p), s;
+    const double step = 2.0 / (p - 1);
+    for (int i = 0; i < p; ++i) g[i] = -1.0 + i * step;
+    g[p - 1] = 1.0;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            for (int k = 0; k < p; ++k)
+                if (std::min({i, j, k}) == 0 || std::max({i, j, k}) == p - 1) {
+                    s.push_back(g[i]);
+                    s.push_back(g[j]);
+                    s.push_back(g[k]);
+                }
+    return s;
+}
+
+// (3 nx, 3 ny) row-major matrix of 8 pi mu times the single-layer kernel.
+std::vector<double> kernel_matrix(const std::vector<double>& x, double ax, const std::vector<double>& y, double ay) {
+    const int nx = (int)x.size() / 3, ny = (int)y.size() / 3;
+    std::vector<double> K((size_t)9 * nx * ny, 0.0);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double r[3];
+            for (int c = 0; c < 3; ++c) r[c] = ax * x[3 * i + c] - ay * y[3 * j + c];
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            if (!(r2 > 0.0)) continue;
+            const double ri = 1.0 / sqrt(r2), ri3 = ri * ri * ri;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    K[(size_t)(3 * i + a) * 3 * ny + 3 * j + b] = (a == b ? ri : 0.0) + r[a] * r[b] * ri3;
+        }
+    return K;
+}
+
+// ---------------------------------------------------------------- device
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+__device__ __forceinline__ int64_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (int64_t)v;
+}
+__device__ __forceinline__ uint64_t morton(int64_t i, int64_t j, int64_t k) {
+    return spread3((uint64_t)i) | spread3((uint64_t)j) << 1 | spread3((uint64_t)k) << 2;
+}
+
+struct FmmDev {
+    int ns, n3, D;
+    double c[3], R;
+    const double* surf;
+    const double* upT;
+    const double* downT;
+    const double* sx;          // sorted sources (3, n_src)
+    const double* sq;
+    int64_t n_src;
+    const double* tx;          // sorted targets (3, n_trg)
+    const int32_t* tperm;      // caller's index of each sorted target
+    int64_t n_trg;
+    const int64_t* sofs;       // (8^D + 1) leaf offsets
+    const int64_t* tofs;
+    uint8_t* snz;              // per box of levels 2..D: has sources
+    uint8_t* tpr;              // has targets
+    double* ue;                // per box: 3 ns upward equivalent density
+    double* de;                // downward
+    int64_t base[kFmmMaxDepth + 2];   // first box of level l in the per-box arrays
+    double pref;
+    int accumulate;
+    double* out;
+};
+
+__device__ __forceinline__ void box_centre(const FmmDev& a, int l, uint64_t b, double* ctr, double& h) {
+    h = a.R / (double)(1 << l);
+    const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ctr[c] = (a.c[c] - a.R) + (double)(2 * idx[c] + 1) * h;
+}
+
+__device__ __forceinline__ void stokeslet(double rx, double ry, double rz, double qx, double qy, double qz,
+                                          double* u) {
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 > 0.0) {
+        const double ri = 1.0 / sqrt(r2);
+        const double rq = (rx * qx + ry * qy + rz * qz) * (ri * ri * ri);
+        u[0] += qx * ri + rx * rq;
+        u[1] += qy * ri + ry * rq;
+        u[2] += qz * ri + rz * rq;
+    }
+}
+
+__global__ __launch_bounds__(kFBlock) void keys_kernel(const double* __restrict__ x, int64_t n, double c0, double c1,
+                                                       double c2, double R, int D, uint64_t* __restrict__ keys,
+                                                       int32_t* __restrict__ vals) {
+    const double lo[3] = {c0 - R, c1 - R, c2 - R};
+    const double nl = (double)(1 << D), cell = 2.0 * R / nl;
+    for (int64_t i = (int64_t)blockIdx.x * kFBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kFBlock) {
+        int64_t idx[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = floor((x[c * n + i] - lo[c]) / cell);
+            if (!(v >= 0.0)) v = 0.0;                  // also NaN
+            if (v > nl - 1.0) v = nl - 1.0;
+            idx[c] = (int64_t)v;
+        }
+        keys[i] = morton(idx[0], idx[1], idx[2]);
+        vals[i] = (int32_t)i;
+    }
+}
+
+__global__ __launch_bounds__(kFBlock) void gather_kernel(const double* __restrict__ x, const double* __restrict__ f,
+                                                         const double* __restrict__ w, int64_t n,
+                                                         const int32_t* __restrict__ perm, double* __restrict__ sx,
+                                                         double* __restrict__ sq) {
+    for (int64_t i = (int64_t)blockIdx.x * kFBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kFBlock) {
+        const int64_t m = perm[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sx[c * n + i] = x[c * n + m];
+            if (sq) sq[c * n + i] = w[m] * f[c * n + m];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFBlock) void leaf_ofs_kernel(const uint64_t* __restrict__ keys, int64_t n,
+                                                           int64_t n_leaves, int64_t* __restrict__ ofs) {
+    for (int64_t L = (int64_t)blockIdx.x * kFBlock + threadIdx.x; L <= n_leaves; L += (int64_t)gridDim.x * kFBlock) {
+        int64_t lo = 0, hi = n;                        // first key >= L
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < (uint64_t)L) lo = mid + 1; else hi = mid;
+        }
+        ofs[L] = lo;
+    }
+}
+
+__global__ __launch_bounds__(kFBlock) void flags_leaf_kernel(FmmDev a) {
+    const int64_t nl = (int64_t)1 << (3 * a.D);
+    for (int64_t L = (int64_t)blockIdx.x * kFBlock + threadIdx.x; L < nl; L += (int64_t)gridDim.x * kFBlock) {
+        a.snz[a.base[a.D] + L] = a.sofs[L + 1] > a.sofs[L];
+        a.tpr[a.base[a.D] + L] = a.tofs[L + 1] > a.tofs[L];
+    }
+}
+
+__global__ __launch_bounds__(kFBlock) void flags_up_kernel(FmmDev a, int l) {
+    const int64_t nb = (int64_t)1 << (3 * l);
+    for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock) {
+        uint8_t s = 0, t = 0;
+        for (int o = 0; o < 8; ++o) {
+            s |= a.snz[a.base[l + 1] + 8 * b + o];
+            t |= a.tpr[a.base[l + 1] + 8 * b + o];
+        }
+        a.snz[a.base[l] + b] = s;
+        a.tpr[a.base[l] + b] = t;
+    }
+}
+
+// Dynamic LDS of the surface kernels, in doubles: template, 4 partial check
+// vectors, their sum.
+size_t surface_lds(int ns) { return (size_t)(3 * ns + (kFWaves + 1) * 3 * ns) * sizeof(double); }
+
+__device__ __forceinline__ void load_surface(const FmmDev& a, double* surf) {
+    for (int r = threadIdx.x; r < 3 * a.ns; r += kFBlock) surf[r] = a.surf[r];
+    __syncthreads();
+}
+
+// Adds the four waves' partial check vectors in a fixed order, then
+// out = h * op * v, op stored transposed (column k contiguous over rows).
+__device__ __forceinline__ void finish(const FmmDev& a, const double* part, double* v, const double* opT, double h,
+                                       double* out) {
+    __syncthreads();
+    for (int r = threadIdx.x; r < a.n3; r += kFBlock)
+        v[r] = ((part[r] + part[a.n3 + r]) + part[2 * a.n3 + r]) + part[3 * a.n3 + r];
+    __syncthreads();
+    for (int r = threadIdx.x; r < a.n3; r += kFBlock) {
+        double s = 0.0;
+        for (int k = 0; k < a.n3; ++k) s = fma(opT[(int64_t)k * a.n3 + r], v[k], s);
+        out[r] = h * s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
+    extern __shared__ double sh[];
+    double* surf = sh;
+    double* part = surf + 3 * a.ns;
+    double* v = part + kFWaves * a.n3;
+    load_surface(a, surf);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int64_t nl = (int64_t)1 << (3 * a.D);
+    for (int64_t b = blockIdx.x; b < nl; b += gridDim.x) {            // uniform over the workgroup
+        double* out = a.ue + (a.base[a.D] + b) * a.n3;
+        if (!a.snz[a.base[a.D] + b]) {
+            for (int r = threadIdx.x; r < a.n3; r += kFBlock) out[r] = 0.0;
+            continue;
+        }
+        double ctr[3], h;
+        box_centre(a, a.D, b, ctr, h);
+        const int64_t m0 = a.sofs[b], m1 = a.sofs[b + 1];
+        for (int cp = lane; cp < a.ns; cp += kWave) {
+            double x[3], u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaUC * h * surf[3 * cp + c];
+            for (int64_t m = m0 + wave; m < m1; m += kFWaves)
+                stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sq[m],
+                          a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[c];
+        }
+        finish(a, part, v, a.upT, h, out);
+    }
+}
+
+__global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
+    extern __shared__ double sh[];
+    double* surf = sh;
+    double* part = surf + 3 * a.ns;
+    double* v = part + kFWaves * a.n3;
+    load_surface(a, surf);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int64_t nb = (int64_t)1 << (3 * l);
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        double* out = a.ue + (a.base[l] + b) * a.n3;
+        if (!a.snz[a.base[l] + b]) {
+            for (int r = threadIdx.x; r < a.n3; r += kFBlock) out[r] = 0.0;
+            continue;
+        }
+        double ctr[3], h;
+        box_centre(a, l, b, ctr, h);
+        for (int cp = lane; cp < a.ns; cp += kWave) {
+            double x[3], u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaUC * h * surf[3 * cp + c];
+            for (int o = wave; o < 8; o += kFWaves) {
+                const uint64_t ch = 8 * b + o;
+                if (!a.snz[a.base[l + 1] + ch]) continue;
+                double cc[3], hc;
+                box_centre(a, l + 1, ch, cc, hc);
+                const double* dens = a.ue + (a.base[l + 1] + ch) * a.n3;
+                for (int k = 0; k < a.ns; ++k)
+                    stokeslet(x[0] - (cc[0] + kAlphaUE * hc * surf[3 * k]), x[1] - (cc[1] + kAlphaUE * hc * surf[3 * k + 1]),
+                              x[2] - (cc[2] + kAlphaUE * hc * surf[3 * k + 2]), dens[3 * k], dens[3 * k + 1],
+                              dens[3 * k + 2], u);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[c];
+        }
+        finish(a, part, v, a.upT, h, out);
+    }
+}
+
+// M2L from the interaction list, plus L2L from the parent (levels > 2), then
+// the downward equivalent density.  Only boxes holding targets.
+__global__ __launch_bounds__(kFBlock) void m2l_kernel(FmmDev a, int l) {
+    extern __shared__ double sh[];
+    double* surf = sh;
+    double* part = surf + 3 * a.ns;
+    double* v = part + kFWaves * a.n3;
+    load_surface(a, surf);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int64_t nb = (int64_t)1 << (3 * l), np = (int64_t)1 << (l - 1);
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        if (!a.tpr[a.base[l] + b]) continue;
+        double ctr[3], h;
+        box_centre(a, l, b, ctr, h);
+        const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
+        const uint64_t p = b >> 3;
+        const int64_t pidx[3] = {compact3(p), compact3(p >> 1), compact3(p >> 2)};
+        for (int cp = lane; cp < a.ns; cp += kWave) {
+            double x[3], u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaDC * h * surf[3 * cp + c];
+            int item = 0;
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int64_t pn[3] = {pidx[0] + dx, pidx[1] + dy, pidx[2] + dz};
+                        if (pn[0] < 0 || pn[1] < 0 || pn[2] < 0 || pn[0] >= np || pn[1] >= np || pn[2] >= np) continue;
+                        for (int o = 0; o < 8; ++o) {
+                            const int64_t ai[3] = {2 * pn[0] + (o & 1), 2 * pn[1] + ((o >> 1) & 1), 2 * pn[2] + (o >> 2)};
+                            if (llabs(ai[0] - idx[0]) <= 1 && llabs(ai[1] - idx[1]) <= 1 && llabs(ai[2] - idx[2]) <= 1)
+                                continue;                      // a neighbour: near field
+                            const uint64_t ab = morton(ai[0], ai[1], ai[2]);
+                            if (!a.snz[a.base[l] + ab]) continue;
+                            if (item++ % kFWaves != wave) continue;
+                            double ac[3], ha;
+                            box_centre(a, l, ab, ac, ha);
+                            const double* dens = a.ue + (a.base[l] + ab) * a.n3;
+                            for (int k = 0; k < a.ns; ++k)
+                                stokeslet(x[0] - (ac[0] + kAlphaUE * ha * surf[3 * k]),
+                                          x[1] - (ac[1] + kAlphaUE * ha * surf[3 * k + 1]),
+                                          x[2] - (ac[2] + kAlphaUE * ha * surf[3 * k + 2]), dens[3 * k],
+                                          dens[3 * k + 1], dens[3 * k + 2], u);
+                        }
+                    }
+            if (l > 2 && item++ % kFWaves == wave) {
+                double pc[3], hp;
+                box_centre(a, l - 1, p, pc, hp);
+                const double* dens = a.de + (a.base[l - 1] + p) * a.n3;
+                for (int k = 0; k < a.ns; ++k)
+                    stokeslet(x[0] - (pc[0] + kAlphaDE * hp * surf[3 * k]), x[1] - (pc[1] + kAlphaDE * hp * surf[3 * k + 1]),
+                              x[2] - (pc[2] + kAlphaDE * hp * surf[3 * k + 2]), dens[3 * k], dens[3 * k + 1],
+                              dens[3 * k + 2], u);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[c];
+        }
+        finish(a, part, v, a.downT, h, a.de + (a.base[l] + b) * a.n3);
+    }
+}
+
+// L2P + P2P per target leaf; results go to the caller's target order.
+__global__ __launch_bounds__(kFBlock) void eval_kernel(FmmDev a) {
+    extern __shared__ double sh[];
+    double* surf = sh;
+    double* dens = surf + 3 * a.ns;
+    load_surface(a, surf);
+    const int64_t nlx = (int64_t)1 << a.D, nl = (int64_t)1 << (3 * a.D);
+    for (int64_t L = blockIdx.x; L < nl; L += gridDim.x) {
+        if (!a.tpr[a.base[a.D] + L]) continue;
+        const double* d = a.de + (a.base[a.D] + L) * a.n3;
+        for (int r = threadIdx.x; r < a.n3; r += kFBlock) dens[r] = d[r];
+        __syncthreads();
+        double ctr[3], h;
+        box_centre(a, a.D, L, ctr, h);
+        const int64_t idx[3] = {compact3(L), compact3(L >> 1), compact3(L >> 2)};
+        for (int64_t t = a.tofs[L] + threadIdx.x; t < a.tofs[L + 1]; t += kFBlock) {
+            const double x[3] = {a.tx[t], a.tx[a.n_trg + t], a.tx[2 * a.n_trg + t]};
+            double u[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < a.ns; ++k)
+                stokeslet(x[0] - (ctr[0] + kAlphaDE * h * surf[3 * k]), x[1] - (ctr[1] + kAlphaDE * h * surf[3 * k + 1]),
+                          x[2] - (ctr[2] + kAlphaDE * h * surf[3 * k + 2]), dens[3 * k], dens[3 * k + 1],
+                          dens[3 * k + 2], u);
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int64_t ni[3] = {idx[0] + dx, idx[1] + dy, idx[2] + dz};
+                        if (ni[0] < 0 || ni[1] < 0 || ni[2] < 0 || ni[0] >= nlx || ni[1] >= nlx || ni[2] >= nlx) continue;
+                        const uint64_t nbr = morton(ni[0], ni[1], ni[2]);
+                        for (int64_t m = a.sofs[nbr]; m < a.sofs[nbr + 1]; ++m)
+                            stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sq[m],
+                                      a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
+                    }
+            const int64_t o = a.tperm[t];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double val = a.pref * u[c];
+                a.out[c * a.n_trg + o] = a.accumulate ? a.out[c * a.n_trg + o] + val : val;
+            }
+        }
+        __syncthreads();                       // dens is reused by the next leaf
+    }
+}
+
+struct FmmLayout {
+    int64_t nbox = 0, n_leaves = 0;
+    int64_t base[kFmmMaxDepth + 2] = {};
+    SortLayout sort;
+    size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_tx, off_sofs, off_tofs, off_snz,
+        off_tpr, off_ue, off_de, total;
+};
+
+FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
+    FmmLayout L;
+    int64_t acc = 0;
+    for (int l = 2; l <= D; ++l) {
+        L.base[l] = acc;
+        acc += (int64_t)1 << (3 * l);
+    }
+    L.nbox = acc;
+    L.n_leaves = (int64_t)1 << (3 * D);
+    L.sort = sort_layout(std::max(n_src, n_trg));
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return at;
+    };
+    L.off_skeys = take((size_t)n_src * 8);
+    L.off_svals = take((size_t)n_src * 4);
+    L.off_tkeys = take((size_t)n_trg * 8);
+    L.off_tvals = take((size_t)n_trg * 4);
+    L.off_sort = take(L.sort.total);
+    L.off_sx = take((size_t)3 * n_src * 8);
+    L.off_sq = take((size_t)3 * n_src * 8);
+    L.off_tx = take((size_t)3 * n_trg * 8);
+    L.off_sofs = take((size_t)(L.n_leaves + 1) * 8);
+    L.off_tofs = take((size_t)(L.n_leaves + 1) * 8);
+    L.off_snz = take((size_t)L.nbox);
+    L.off_tpr = take((size_t)L.nbox);
+    L.off_ue = take((size_t)L.nbox * 3 * ns * 8);
+    L.off_de = take((size_t)L.nbox * 3 * ns * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host
+void pinv_jacobi(const std::vector<double>& K, int n, double rcond, std::vector<double>& P) {
+    // columns of A (a[j * n + i] = K[i][j]) are rotated until orthogonal: A V = W,
+    // W's columns are sigma_j u_j; pinv = sum_j v_j w_j^T / sigma_j^2
+    std::vector<double> a((size_t)n * n), v((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) a[(size_t)j * n + i] = K[(size_t)i * n + j];
+    for (int j = 0; j < n; ++j) v[(size_t)j * n + j] = 1.0;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double worst = 0.0;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double* ap = &a[(size_t)p * n];
+                double* aq = &a[(size_t)q * n];
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    al += ap[i] * ap[i];
+                    be += aq[i] * aq[i];
+                    ga += ap[i] * aq[i];
+                }
+                if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
+                const double rel = fabs(ga) / sqrt(al * be);
+                if (rel <= 1e-15) continue;
+                worst = std::max(worst, rel);
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int i = 0; i < n; ++i) {
+                    const double x = ap[i], y = aq[i];
+                    ap[i] = c * x - s * y;
+                    aq[i] = s * x + c * y;
+                }
+                double* vp = &v[(size_t)p * n];
+                double* vq = &v[(size_t)q * n];
+                for (int i = 0; i < n; ++i) {
+                    const double x = vp[i], y = vq[i];
+                    vp[i] = c * x - s * y;
+                    vq[i] = s * x + c * y;
+                }
+            }
+        if (worst <= 1e-14) break;
+    }
+    std::vector<double> sig2(n);
+    double smax = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += a[(size_t)j * n + i] * a[(size_t)j * n + i];
+        sig2[j] = s;
+        smax = std::max(smax, sqrt(s));
+    }
+    P.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        if (!(sqrt(sig2[j]) > rcond * smax)) continue;
+        const double inv = 1.0 / sig2[j];
+        for (int i = 0; i < n; ++i) {
+            const double vi = v[(size_t)j * n + i] * inv;
+            if (vi == 0.0) continue;
+            double* row = &P[(size_t)i * n];
+            const double* w = &a[(size_t)j * n];
+            for (int k = 0; k < n; ++k) row[k] += vi * w[k];
+        }
+    }
+}
+
+int fmm_plan_build(int device, int order, stokes_fmm_plan** out, std::string& err) {
+    const std::vector<double> s = surface_points(order);
+    const int ns = (int)s.size() / 3, n3 = 3 * ns;
+    std::vector<double> up, down;
+    pinv_jacobi(kernel_matrix(s, kAlphaUC, s, kAlphaUE), n3, kPinvRcond, up);
+    pinv_jacobi(kernel_matrix(s, kAlphaDC, s, kAlphaDE), n3, kPinvRcond, down);
+    std::vector<double> upT((size_t)n3 * n3), downT((size_t)n3 * n3);
+    for (int r = 0; r < n3; ++r)
+        for (int k = 0; k < n3; ++k) {
+            upT[(size_t)k * n3 + r] = up[(size_t)r * n3 + k];
+            downT[(size_t)k * n3 + r] = down[(size_t)r * n3 + k];
+        }
+    stokes_fmm_plan* p = new (std::nothrow) stokes_fmm_plan{};
+    if (!p) {
+        err = "out of host memory";
+        return -2;
+    }
+    p->device = device;
+    p->order = order;
+    p->ns = ns;
+    const size_t sb = s.size() * 8, ob = (size_t)n3 * n3 * 8;
+    if (hipMalloc(&p->d_surf, sb) != hipSuccess || hipMalloc(&p->d_upT, ob) != hipSuccess ||
+        hipMalloc(&p->d_downT, ob) != hipSuccess ||
+        hipMemcpy(p->d_surf, s.data(), sb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_upT, upT.data(), ob, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_downT, downT.data(), ob, hipMemcpyHostToDevice) != hipSuccess) {
+        fmm_plan_free(p);
+        err = "device allocation or copy failed";
+        return -2;
+    }
+    *out = p;
+    return 0;
+}
+
+void fmm_plan_free(stokes_fmm_plan* p) {
+    if (!p) return;
+    (void)hipFree(p->d_surf);
+    (void)hipFree(p->d_upT);
+    (void)hipFree(p->d_downT);
+    delete p;
+}
+
+int fmm_plan_order(const stokes_fmm_plan* p) { return p->order; }
+int fmm_plan_device(const stokes_fmm_plan* p) { return p->device; }
+
+size_t fmm_workspace_bytes(int order, int64_t n_src, int64_t n_trg, int depth) {
+    const int ns = 6 * (order - 1) * (order - 1) + 2;
+    return fmm_layout(ns, n_src, n_trg, depth).total;
+}
+
+hipError_t launch_fmm_sl(const stokes_fmm_plan* plan, const FmmInputs& in, double* out, void* workspace,
+                         hipStream_t st) {
+    const int D = in.depth, ns = plan->ns;
+    const FmmLayout L = fmm_layout(ns, in.n_src, in.n_trg, D);
+    char* ws = static_cast<char*>(workspace);
+    uint64_t* skeys = reinterpret_cast<uint64_t*>(ws + L.off_skeys);
+    int32_t* svals = reinterpret_cast<int32_t*>(ws + L.off_svals);
+    uint64_t* tkeys = reinterpret_cast<uint64_t*>(ws + L.off_tkeys);
+    int32_t* tvals = reinterpret_cast<int32_t*>(ws + L.off_tvals);
+    FmmDev a{};
+    a.ns = ns;
+    a.n3 = 3 * ns;
+    a.D = D;
+    for (int c = 0; c < 3; ++c) a.c[c] = in.centre[c];
+    a.R = in.half_width;
+    a.surf = plan->d_surf;
+    a.upT = plan->d_upT;
+    a.downT = plan->d_downT;
+    a.sx = reinterpret_cast<double*>(ws + L.off_sx);
+    a.sq = reinterpret_cast<double*>(ws + L.off_sq);
+    a.n_src = in.n_src;
+    a.tx = reinterpret_cast<double*>(ws + L.off_tx);
+    a.tperm = tvals;
+    a.n_trg = in.n_trg;
+    a.sofs = reinterpret_cast<int64_t*>(ws + L.off_sofs);
+    a.tofs = reinterpret_cast<int64_t*>(ws + L.off_tofs);
+    a.snz = reinterpret_cast<uint8_t*>(ws + L.off_snz);
+    a.tpr = reinterpret_cast<uint8_t*>(ws + L.off_tpr);
+    a.ue = reinterpret_cast<double*>(ws + L.off_ue);
+    a.de = reinterpret_cast<double*>(ws + L.off_de);
+    for (int l = 0; l <= kFmmMaxDepth + 1; ++l) a.base[l] = L.base[std::min(l, kFmmMaxDepth + 1)];
+    a.pref = in.pref;
+    a.accumulate = in.accumulate;
+    a.out = out;
+    char* sort_ws = ws + L.off_sort;
+    hipError_t e = hipSuccess;
+    auto chk = [&e]() {
+        if (e == hipSuccess) e = hipGetLastError();
+        return e == hipSuccess;
+    };
+    // leaf order of sources and targets
+    const unsigned gs = f_grid((in.n_src + kFBlock - 1) / kFBlock), gt = f_grid((in.n_trg + kFBlock - 1) / kFBlock);
+    if (in.n_src > 0) {
+        hipLaunchKernelGGL(keys_kernel, dim3(gs), dim3(kFBlock), 0, st, in.src_xyz, in.n_src, a.c[0], a.c[1], a.c[2],
+                           a.R, D, skeys, svals);
+        if (chk()) e = radix_sort_pairs(skeys, svals, in.n_src, 3 * D, sort_ws, L.sort, st);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(gather_kernel, dim3(gs), dim3(kFBlock), 0, st, in.src_xyz, in.density, in.weight,
+                               in.n_src, svals, const_cast<double*>(a.sx), const_cast<double*>(a.sq));
+        chk();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(keys_kernel, dim3(gt), dim3(kFBlock), 0, st, in.trg_xyz, in.n_trg, a.c[0], a.c[1], a.c[2],
+                           a.R, D, tkeys, tvals);
+        if (chk()) e = radix_sort_pairs(tkeys, tvals, in.n_trg, 3 * D, sort_ws, L.sort, st);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(gather_kernel, dim3(gt), dim3(kFBlock), 0, st, in.trg_xyz, nullptr, nullptr, in.n_trg,
+                               tvals, const_cast<double*>(a.tx), nullptr);
+        chk();
+    }
+    const unsigned gl = f_grid((L.n_leaves + 1 + kFBlock - 1) / kFBlock);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(leaf_ofs_kernel, dim3(gl), dim3(kFBlock), 0, st, skeys, in.n_src, L.n_leaves,
+                           const_cast<int64_t*>(a.sofs));
+        if (chk())
+            hipLaunchKernelGGL(leaf_ofs_kernel, dim3(gl), dim3(kFBlock), 0, st, tkeys, in.n_trg, L.n_leaves,
+                               const_cast<int64_t*>(a.tofs));
+        if (chk()) hipLaunchKernelGGL(flags_leaf_kernel, dim3(gl), dim3(kFBlock), 0, st, a);
+        for (int l = D - 1; l >= 2 && chk(); --l)
+            hipLaunchKernelGGL(flags_up_kernel, dim3(f_grid(((int64_t)1 << (3 * l)) / kFBlock + 1)), dim3(kFBlock), 0,
+                               st, a, l);
+    }
+    const size_t lds = surface_lds(ns);
+    if (chk()) hipLaunchKernelGGL(p2m_kernel, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+    for (int l = D - 1; l >= 2 && chk(); --l)
+        hipLaunchKernelGGL(m2m_kernel, dim3(f_grid((int64_t)1 << (3 * l))), dim3(kFBlock), lds, st, a, l);
+    for (int l = 2; l <= D && chk(); ++l)
+        hipLaunchKernelGGL(m2l_kernel, dim3(f_grid((int64_t)1 << (3 * l))), dim3(kFBlock), lds, st, a, l);
+    if (chk()) hipLaunchKernelGGL(eval_kernel, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+    chk();
+    return e;
+}
+
+}  // namespace stokes

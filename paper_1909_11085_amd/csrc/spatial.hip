@@ -523,4 +523,78 @@ hipError_t candidate_phase3(int32_t n_boxes, const CandidateMeta& meta, char* ws
     return hipGetLastError();
 }
 
+SortLayout sort_layout(int64_t max_n) {
+    SortLayout L;
+    L.max_n = max_n;
+    L.blocks = std::max<int64_t>(1, (max_n + kSortTile - 1) / kSortTile);
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    const size_t n = (size_t)std::max<int64_t>(max_n, 1);
+    L.off_keys2 = take(n * sizeof(uint64_t));
+    L.off_vals2 = take(n * sizeof(int32_t));
+    L.off_hist = take(2 * (size_t)kRadix * L.blocks * sizeof(int64_t));
+    L.off_scan = take(((size_t)kRadix * L.blocks / kScanTile + 2) * sizeof(int64_t));
+    L.off_total = take(sizeof(int64_t));
+    L.total = off;
+    return L;
+}
+
+namespace {
+__global__ __launch_bounds__(kSpBlock) void copy_pairs_kernel(const uint64_t* __restrict__ ks,
+                                                              const int32_t* __restrict__ vs, int64_t n,
+                                                              uint64_t* __restrict__ kd, int32_t* __restrict__ vd) {
+    for (int64_t i = (int64_t)blockIdx.x * kSpBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSpBlock) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+}  // namespace
+
+hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, char* ws, const SortLayout& L,
+                            hipStream_t st) {
+    if (n <= 1) return hipSuccess;
+    uint64_t* k2 = reinterpret_cast<uint64_t*>(ws + L.off_keys2);
+    int32_t* v2 = reinterpret_cast<int32_t*>(ws + L.off_vals2);
+    int64_t* hist = reinterpret_cast<int64_t*>(ws + L.off_hist);
+    int64_t* tmp = reinterpret_cast<int64_t*>(ws + L.off_scan);
+    int64_t* total = reinterpret_cast<int64_t*>(ws + L.off_total);
+    const int passes = std::max(1, (bits + 7) / 8);
+    const int items = (int)std::min<int64_t>(
+        kSortItems, std::max<int64_t>(1, (n + (int64_t)kSpBlock * L.blocks - 1) / ((int64_t)kSpBlock * L.blocks)));
+    const int64_t nb = (n + (int64_t)kSpBlock * items - 1) / ((int64_t)kSpBlock * items);
+    int64_t* hoff = hist + (int64_t)kRadix * nb;
+    uint64_t *ka = keys, *kb = k2;
+    int32_t *va = vals, *vb = v2;
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < passes && e == hipSuccess; ++p) {
+        hipLaunchKernelGGL(rs_hist_kernel, dim3((unsigned)nb), dim3(kSpBlock), 0, st, ka, n, 8 * p, items, hist, nb);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = exclusive_scan(hist, (int64_t)kRadix * nb, hoff, tmp, total, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(rs_scatter_kernel, dim3((unsigned)nb), dim3(kSpBlock), 0, st, ka, va, n, 8 * p, items,
+                               hoff, nb, kb, vb);
+            e = hipGetLastError();
+        }
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (e == hipSuccess && ka != keys) {          // odd pass count: the result sits in the second buffers
+        hipLaunchKernelGGL(copy_pairs_kernel, dim3(sp_grid(n, kSpBlock)), dim3(kSpBlock), 0, st, ka, va, n, keys,
+                           vals);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+int64_t scan_tmp_count(int64_t n) { return std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile) + 1; }
+
+hipError_t exclusive_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* scan_tmp, int64_t* total,
+                              hipStream_t stream) {
+    return exclusive_scan(in, n, out, scan_tmp, total, stream);
+}
+
 }  // namespace stokes

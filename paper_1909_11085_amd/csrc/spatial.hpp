@@ -47,4 +47,20 @@ hipError_t candidate_phase2(int32_t n_boxes, const CandidateMeta& meta, char* ws
 hipError_t candidate_phase3(int32_t n_boxes, const CandidateMeta& meta, char* ws, const CandidateLayout& lay,
                             int32_t* pairs, int64_t capacity, hipStream_t stream);
 
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
+// keys (8 bits per pass), in place.  Workspace from sort_layout(max_n).
+struct SortLayout {
+    int64_t max_n = 0, blocks = 0;
+    size_t off_keys2 = 0, off_vals2 = 0, off_hist = 0, off_scan = 0, off_total = 0, total = 0;
+};
+SortLayout sort_layout(int64_t max_n);
+hipError_t radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int bits, char* ws, const SortLayout& lay,
+                            hipStream_t stream);
+
+// Exclusive prefix sum of n int64 values (in may equal out); *total gets the
+// sum.  scan_tmp holds scan_tmp_count(n) int64.
+int64_t scan_tmp_count(int64_t n);
+hipError_t exclusive_scan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* scan_tmp, int64_t* total,
+                              hipStream_t stream);
+
 }  // namespace stokes

@@ -1,0 +1,134 @@
+"""GPU parity of the kernel-independent FMM for the single-layer sum (Sec. 3.1,
+"Far evaluation") against the FMM oracle, and its accuracy against the direct
+sum at sizes where only the GPU can run it.
+
+The GPU and the oracle run the same algorithm; their operators are
+pseudo-inverses from different SVD codes (one-sided Jacobi on the host here,
+LAPACK in the oracle) with the same truncation.  Singular values kept near the
+1e-12 cutoff are known only to about 1e-4 relative from either code, so the
+two pseudo-inverses differ along those directions; the effect on the velocity
+grows with the order (measured below 1e-9 at order 4 and 5.5e-8 at order 6).
+The bars are 1e-9 and 1e-6, each far below the method's own error at that
+order; against the direct sum the bar is that error.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1909_11085_amd as S
+from oracle import fmm as F
+from oracle import oracle as O
+from paper_1909_11085_amd import _capi as C
+from paper_1909_11085_amd import workloads as W
+from tests.gpu_util import dev, device, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FMM_ERR = {4: 5e-3, 6: 3e-4}          # error against the direct sum (oracle pins: 1.5e-3, 6e-5)
+ORACLE_TOL = {4: 1e-9, 6: 1e-6}
+
+
+@pytest.fixture(scope="module")
+def plans():
+    return {p: S.FMMPlan(p) for p in (4, 6)}
+
+
+def _cloud(seed, n, m):
+    rng = np.random.default_rng(seed)
+    src = rng.uniform(-1, 1, (3, n))
+    src[:, : n // 3] = 0.2 * rng.standard_normal((3, n // 3)).clip(-4.9, 4.9)
+    return src, rng.standard_normal((3, n)), rng.uniform(0.5, 1.0, n), rng.uniform(-1, 1, (3, m))
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_matches_oracle_fmm(plans, p):
+    src, f, w, trg = _cloud(71, 1200, 300)
+    got = host(S.fmm_sl(plans[p], dev(src), dev(f), dev(w), dev(trg), (0.0, 0.0, 0.0), 1.0001, 2, mu=1.3))
+    ref = F.fmm_sl(src, f, w, trg, np.zeros(3), 1.0001, 2, p, mu=1.3)
+    assert rel_l2(got, ref) < ORACLE_TOL[p], rel_l2(got, ref)
+    direct = O.sl(src, f, w, trg, mu=1.3)
+    assert rel_l2(got, direct) < FMM_ERR[p]
+
+
+@pytest.mark.parametrize("p,D", [(4, 3), (4, 4), (6, 4)])
+def test_accuracy_against_direct(plans, p, D):
+    rng = np.random.default_rng(73 + D)
+    n = 50_000
+    src = rng.uniform(-2, 2, (3, n))
+    src[:, : n // 2] = 0.4 * rng.standard_normal((3, n // 2)).clip(-4.9, 4.9)
+    f, w = rng.standard_normal((3, n)), rng.uniform(0.5, 1.0, n)
+    trg = src[:, ::7].copy()
+    trg[:, ::2] += 0.01                                  # some targets on sources, some off
+    S_, F_, W_, T_ = dev(src), dev(f), dev(w), dev(trg)
+    got = host(S.fmm_sl(plans[p], S_, F_, W_, T_, (0.0, 0.0, 0.0), 2.0001, D))
+    ref = host(S.sl(S_, F_, W_, T_))
+    assert rel_l2(got, ref) < FMM_ERR[p], rel_l2(got, ref)
+
+
+def test_cells_workload_sampled(plans):
+    """The 3,840 cells in the vessel (2,088,960 points), depth 6: all targets in
+    one launch, a seeded sample against the direct sum (no pair rule)."""
+    cfg = W.make_config(4)
+    c = cfg["cells"]
+    lo, hi = c.pos.min(axis=1), c.pos.max(axis=1)
+    ctr, R = 0.5 * (lo + hi), 0.5 * float((hi - lo).max()) * 1.0001
+    pos, f, w = dev(c.pos), dev(cfg["f"]), dev(c.weight)
+    got = S.fmm_sl(plans[4], pos, f, w, pos, tuple(ctr), R, 6)
+    pick = W.subset(np.random.default_rng(74), c.n, 2000)
+    ref = host(S.sl(pos, f, w, dev(c.pos[:, pick])))
+    err = rel_l2(host(got)[:, pick], ref)
+    assert err < FMM_ERR[4], err
+    assert bool(torch.isfinite(got).all())
+
+
+def test_edge_cases(plans):
+    src, f, w, trg = _cloud(75, 500, 100)
+    P = plans[4]
+    z = S.fmm_sl(P, dev(np.zeros((3, 0))), dev(np.zeros((3, 0))), dev(np.zeros(0)), dev(trg), (0, 0, 0), 1.0001, 2)
+    assert not bool(z.abs().max())                       # no sources: zeros
+    base = torch.full((3, 100), 0.5, dtype=torch.float64, device=device())
+    S.fmm_sl(P, dev(src), dev(f), dev(w), dev(trg), (0, 0, 0), 1.0001, 3, out=base, accumulate=True)
+    one = host(S.fmm_sl(P, dev(src), dev(f), dev(w), dev(trg), (0, 0, 0), 1.0001, 3))
+    assert np.array_equal(host(base), one + 0.5) or rel_l2(host(base), one + 0.5) < 1e-15
+    # points a little outside the cube go to the boundary leaves and stay finite
+    out = host(S.fmm_sl(P, dev(src * 1.05), dev(f), dev(w), dev(trg), (0, 0, 0), 1.0, 3))
+    assert np.all(np.isfinite(out))
+    # identical results from one run to the next
+    again = host(S.fmm_sl(P, dev(src), dev(f), dev(w), dev(trg), (0, 0, 0), 1.0001, 3))
+    assert np.array_equal(again, one)
+
+
+def test_rejections(plans):
+    L = C.lib()
+    ctx = S.context()
+    h = ctypes.c_void_p()
+    assert L.stokes_fmm_plan_create(ctx, 1, ctypes.byref(h)) == C.EINVAL
+    assert L.stokes_fmm_plan_create(ctx, 7, ctypes.byref(h)) == C.EINVAL
+    P = plans[4].handle
+    size = ctypes.c_size_t()
+    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 1, ctypes.byref(size)) == C.EINVAL
+    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 8, ctypes.byref(size)) == C.EINVAL
+    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 2, ctypes.byref(size)) == C.OK
+    ws = torch.empty(size.value, dtype=torch.uint8, device=device())
+    x = dev(np.random.default_rng(76).uniform(-1, 1, (3, 10)))
+    f, w = dev(np.ones((3, 10))), dev(np.ones(10))
+    out = torch.full((3, 10), 9.0, dtype=torch.float64, device=device())
+    c = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    def run(mu=1.0, centre=c, hw=1.0, opts=None, wsb=size.value):
+        return L.stokes_fmm_sl_eval(ctx, P, 10, vp(x), vp(f), vp(w), 10, vp(x), mu, centre, hw, 2,
+                                    ctypes.byref(opts) if opts else None, vp(out), vp(ws), wsb, None)
+
+    assert run(mu=0.0) == C.EINVAL
+    assert run(centre=None) == C.EINVAL
+    assert run(hw=-1.0) == C.EINVAL
+    assert run(opts=C.Opts(C.MIXED, 0)) == C.EUNSUPPORTED
+    assert run(wsb=size.value - 1) == C.EWORKSPACE
+    torch.cuda.synchronize()
+    assert bool((out == 9.0).all())
+    assert run() == C.OK
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
