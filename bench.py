@@ -22,7 +22,8 @@ Reported on one JSON line (stdout):
 --only checkpoint times the check-point double-layer quadrature on a
 vessel-wall ring (every node an on-surface target), --only bie the
 30-iteration GMRES solve of the boundary integral equation on an ellipsoid,
---only collision the collision-candidate search of the cells and the wall;
+--only collision the collision-candidate search of the cells and the wall,
+--only fmm the FMM single-layer sum over the cells against the direct sum;
 --secondary adds them and the other workload shapes to the line.
 """
 import argparse
@@ -87,13 +88,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="headline precision (the other one is reported alongside)")
-    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p", "checkpoint", "bie", "collision"],
+    ap.add_argument("--only", choices=["fp64", "mixed", "vjp", "p2p", "checkpoint", "bie", "collision", "fmm"],
                     default=None,
                     help="time one path only (for profiler runs); p2p times the leaf-to-leaf "
                          "workload (3,840 cells in the cylinder) in both precisions; checkpoint "
                          "the check-point double-layer quadrature on a vessel-wall ring; bie the "
                          "30-iteration GMRES solve of the boundary integral equation; collision the "
-                         "space-time boxes and collision candidates of 3,840 cells and the wall")
+                         "space-time boxes and collision candidates of 3,840 cells and the wall; fmm "
+                         "the FMM single-layer sum over those cells against the direct sum")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
@@ -155,6 +157,11 @@ def main():
         r = time_p2p(S, W, t, timed, args.steps, args.warmup)
         log(f"p2p: {r}")
         print(json.dumps({"p2p_3840_cells": r}), flush=True)
+        return
+    if args.only == "fmm":
+        r = time_fmm(S, W, t, args.steps, args.warmup)
+        log(f"fmm: {r}")
+        print(json.dumps({"fmm_3840_cells": r}), flush=True)
         return
     if args.only == "collision":
         r = time_collision(S, W, t, args.steps, args.warmup, oracle=not args.no_cpu_baseline)
@@ -479,6 +486,53 @@ def time_collision(S, W, t, steps, warmup, oracle=True):
     return r
 
 
+def time_fmm(S, W, t, steps, warmup):
+    """The single-layer sum over all 2,088,960 points of the 3,840 cells in the
+    vessel (every point a source and a target, no pair rule) by the FMM on a
+    uniform octree of depth 6, at surface orders 4 and 6, against the direct
+    sum (timed once; its 4.4e12 pairs are the O(N^2) baseline) on a seeded
+    sample of 2,000 targets for the error."""
+    import torch
+
+    cfg = W.make_config(4)
+    c = cfg["cells"]
+    lo, hi = c.pos.min(axis=1), c.pos.max(axis=1)
+    ctr, R = 0.5 * (lo + hi), 0.5 * float((hi - lo).max()) * 1.0001
+    pos, f, w = t(c.pos), t(cfg["f"]), t(c.weight)
+    depth = 6
+    r = {"points": c.n, "depth": depth, "leaves": 8 ** depth, "domain_half_width": R}
+    pick = W.subset(np.random.default_rng(74), c.n, 2000)
+    ref = S.sl(pos, f, w, t(c.pos[:, pick])).cpu().numpy()
+    out = torch.empty((3, c.n), dtype=torch.float64, device=pos.device)
+    for order in (4, 6):
+        plan = S.FMMPlan(order)
+        for _ in range(warmup):
+            S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        got = out.cpu().numpy()[:, pick]
+        r[f"order{order}_ms"] = ms
+        r[f"order{order}_points_per_s"] = c.n / (ms * 1e-3)
+        r[f"order{order}_rel_l2_vs_direct"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        del plan
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.sl(pos, f, w, pos, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    r["direct_ms"] = e0.elapsed_time(e1)
+    r["direct_pairs"] = c.n * c.n
+    r["speedup_order4_vs_direct"] = r["direct_ms"] / r["order4_ms"]
+    r["speedup_order6_vs_direct"] = r["direct_ms"] / r["order6_ms"]
+    return r
+
+
 def secondary(S, W, t, timed, log):
     """Timings of the other workload shapes (not the headline)."""
     import torch
@@ -550,6 +604,9 @@ def secondary(S, W, t, timed, log):
     r = time_collision(S, W, t, 5, 1, oracle=False)
     out["collision_cells_and_wall"] = r
     log(f"secondary collision: {r}")
+    r = time_fmm(S, W, t, 2, 1)
+    out["fmm_3840_cells"] = r
+    log(f"secondary fmm: {r}")
     return out
 
 
