@@ -26,6 +26,15 @@ octree:
   L2P/P2P  each target adds the velocity of its leaf's downward equivalent
            density and the direct sum over the sources of the 27 leaves
            around its own (zero-distance pairs skipped).
+Double-layer sources (the check points of the boundary solve are evaluated
+this way in the paper) use the double-layer kernel in P2M and P2P.  Their
+field has a net flux, sum of n . q over the sources (the flux of one stresslet
+through a sphere around it is n . q), which no single-layer density carries:
+each box therefore also carries a point source of that flux at its centre
+(velocity sigma r / (4 pi rho^3)); its upward equivalent density represents
+the flux-free rest, M2M adds the children's point sources into the parent's,
+and M2L adds the point-source velocity of each interaction-list box.  For
+single-layer sources every sigma is 0.
 
 Readings: the surface radii and the pseudo-inverse are not in the paper; the
 radii are the customary ones of the method, and pinv drops singular values
@@ -73,6 +82,27 @@ def operators(p, mu=1.0):
     return s, up, down
 
 
+def dl_matrix(x, y, nrm):
+    """(3 n_x, 3 n_y) matrix of the double-layer kernel (after eq.
+    double_layer_int_eq) from points y with normals nrm (n_y, 3) to points x:
+    6/(8 pi) r (r.n) r^T / rho^5; zero at zero distance."""
+    r = x[:, None, :] - y[None, :, :]
+    rho2 = (r ** 2).sum(-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ri5 = np.where(rho2 > 0, rho2 ** -2.5, 0.0)
+    rn = (r * nrm[None, :, :]).sum(-1)
+    K = 6.0 / (8.0 * np.pi) * (rn * ri5)[:, :, None, None] * r[:, :, :, None] * r[:, :, None, :]
+    return K.transpose(0, 2, 1, 3).reshape(3 * len(x), 3 * len(y))
+
+
+def source_velocity(x, y, sigma):
+    """Velocity (3 n_x flattened, index 3*point + component) at points x of a
+    point source of flux sigma at y: sigma r / (4 pi rho^3)."""
+    r = x - np.asarray(y, dtype=np.float64)[None, :]
+    rho = np.linalg.norm(r, axis=1)
+    return (sigma * r / (4.0 * np.pi * rho[:, None] ** 3)).reshape(-1)
+
+
 def _leaf_index(x, c, R, D):
     n = 2 ** D
     idx = np.floor((x - (np.asarray(c) - R)[:, None]) / (2.0 * R / n)).astype(np.int64)
@@ -83,9 +113,24 @@ def fmm_sl(src, f, w, trg, c, R, D, p, mu=1.0):
     """Single-layer velocity (3, n_trg) at the targets from the sources (q =
     w f), by the kernel-independent FMM on the uniform tree of depth D >= 2
     over the cube (c, R) that holds every point."""
+    return _fmm(src, f, w, None, trg, c, R, D, p, mu)
+
+
+def fmm_dl(src, phi, w, nrm, trg, c, R, D, p):
+    """Double-layer velocity (3, n_trg) from the sources (q = w phi, normals
+    nrm (3, n_src)) by the same FMM."""
+    return _fmm(src, phi, w, nrm, trg, c, R, D, p, 1.0)
+
+
+def _fmm(src, f, w, nrm, trg, c, R, D, p, mu):
     src, trg = np.asarray(src, dtype=np.float64), np.asarray(trg, dtype=np.float64)
     q = (np.asarray(w)[None, :] * np.asarray(f)).T                 # (n_src, 3)
     c = np.asarray(c, dtype=np.float64)
+    if nrm is None:
+        src_matrix = lambda x, ms: kernel_matrix(x, src[:, ms].T, mu)
+    else:
+        nrm = np.asarray(nrm, dtype=np.float64)
+        src_matrix = lambda x, ms: dl_matrix(x, src[:, ms].T, nrm[:, ms].T)
     s, up, down = operators(p, mu)
     ns = len(s)
     n_leaf = 2 ** D
@@ -98,25 +143,36 @@ def fmm_sl(src, f, w, trg, c, R, D, p, mu=1.0):
         h = R / 2 ** l
         return c - R + (2 * np.asarray(idx) + 1) * h
 
-    # upward pass: equivalent densities (ns, 3) per non-empty box, per level
+    # upward pass: equivalent densities (ns, 3) and point-source fluxes per
+    # non-empty box, per level
     ue = [dict() for _ in range(D + 1)]
+    sig = [dict() for _ in range(D + 1)]
     for idx, ms in leaf_src.items():
         h = R / 2 ** D
         ctr = centre(D, idx)
-        v = kernel_matrix(ctr + ALPHA_UC * h * s, src[:, ms].T, mu) @ q[ms].reshape(-1)
+        chk = ctr + ALPHA_UC * h * s
+        sigma = 0.0 if nrm is None else float((nrm[:, ms].T * q[ms]).sum())
+        v = src_matrix(chk, ms) @ q[ms].reshape(-1) - source_velocity(chk, ctr, sigma)
         ue[D][idx] = (h * up @ v).reshape(ns, 3)
+        sig[D][idx] = sigma
     for l in range(D - 1, 1, -1):
         h = R / 2 ** l
         parents = {tuple(np.asarray(ci) // 2) for ci in ue[l + 1]}
         for pidx in parents:
             ctr = centre(l, pidx)
+            chk = ctr + ALPHA_UC * h * s
             v = np.zeros(3 * ns)
+            sigma = 0.0
             for off in itertools.product((0, 1), repeat=3):
                 ci = tuple(2 * np.asarray(pidx) + off)
                 if ci in ue[l + 1]:
                     cc = centre(l + 1, ci)
-                    v += kernel_matrix(ctr + ALPHA_UC * h * s, cc + ALPHA_UE * (h / 2) * s, mu) @ ue[l + 1][ci].reshape(-1)
+                    v += kernel_matrix(chk, cc + ALPHA_UE * (h / 2) * s, mu) @ ue[l + 1][ci].reshape(-1)
+                    v += source_velocity(chk, cc, sig[l + 1][ci])
+                    sigma += sig[l + 1][ci]
+            v -= source_velocity(chk, ctr, sigma)
             ue[l][pidx] = (h * up @ v).reshape(ns, 3)
+            sig[l][pidx] = sigma
 
     # downward pass: equivalent densities of every box that holds targets
     need = [set() for _ in range(D + 1)]
@@ -142,6 +198,7 @@ def fmm_sl(src, f, w, trg, c, R, D, p, mu=1.0):
                     if max(abs(a[k] - idx[k]) for k in range(3)) <= 1 or a not in ue[l]:
                         continue
                     v += kernel_matrix(chk, centre(l, a) + ALPHA_UE * h * s, mu) @ ue[l][a].reshape(-1)
+                    v += source_velocity(chk, centre(l, a), sig[l][a])
             if l > 2:
                 v += kernel_matrix(chk, centre(l - 1, pidx) + ALPHA_DE * (2 * h) * s, mu) @ de[l - 1][pidx].reshape(-1)
             de[l][idx] = (h * down @ v).reshape(ns, 3)
@@ -159,6 +216,6 @@ def fmm_sl(src, f, w, trg, c, R, D, p, mu=1.0):
             if nbr in leaf_src:
                 near.extend(leaf_src[nbr])
         if near:
-            u = u + kernel_matrix(x[None, :], src[:, near].T, mu) @ q[near].reshape(-1)
+            u = u + src_matrix(x[None, :], near) @ q[near].reshape(-1)
         out[:, m] = u
     return out

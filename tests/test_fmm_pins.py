@@ -38,6 +38,21 @@ def test_fmm_matches_direct_sum():
     assert e < 3e-4, e
 
 
+def test_dl_fmm_matches_direct_sum():
+    src, f, w, trg = _cloud(74, 1000, 250)
+    rng = np.random.default_rng(75)
+    nrm = rng.standard_normal((3, 1000))
+    nrm /= np.linalg.norm(nrm, axis=0)
+    ref = O.dl(src, f, w, nrm, trg)
+    e4 = rel(F.fmm_dl(src, f, w, nrm, trg, np.zeros(3), 1.0001, 2, 4), ref)
+    e6 = rel(F.fmm_dl(src, f, w, nrm, trg, np.zeros(3), 1.0001, 2, 6), ref)
+    assert e4 < 5e-3 and e6 < 3e-4 and e6 < e4 / 10, (e4, e6)
+    # the double-layer kernel matrix itself against the direct oracle
+    K = F.dl_matrix(trg[:, :5].T, src.T, nrm.T)
+    q = (w[None, :] * f).T.reshape(-1)
+    assert rel((K @ q).reshape(5, 3).T, O.dl(src, f, w, nrm, trg[:, :5])) < 1e-13
+
+
 def test_pseudo_inverses():
     s, up, down = F.operators(4, mu=0.7)
     for a_c, a_e, X in ((F.ALPHA_UC, F.ALPHA_UE, up), (F.ALPHA_DC, F.ALPHA_DE, down)):
