@@ -530,6 +530,34 @@ def time_fmm(S, W, t, steps, warmup):
     r["direct_pairs"] = c.n * c.n
     r["speedup_order4_vs_direct"] = r["direct_ms"] / r["order4_ms"]
     r["speedup_order6_vs_direct"] = r["direct_ms"] / r["order6_ms"]
+    # the wall's double layer (1,048,576 nodes) at the 522,240 points of 960 cells, order 6
+    cfg5 = W.make_config(5)
+    wall, cells = cfg5["wall"], cfg5["cells"]
+    lo = np.minimum(wall.pos.min(axis=1), cells.pos.min(axis=1))
+    hi = np.maximum(wall.pos.max(axis=1), cells.pos.max(axis=1))
+    ctr5, R5 = 0.5 * (lo + hi), 0.5 * float((hi - lo).max()) * 1.0001
+    args = [t(wall.pos), t(cfg5["phi"]), t(wall.weight), t(wall.normal)]
+    cp = t(cells.pos)
+    pick5 = W.subset(np.random.default_rng(81), cells.n, 2000)
+    ref5 = S.dl(*args, t(cells.pos[:, pick5])).cpu().numpy()
+    u5 = torch.empty((3, cells.n), dtype=torch.float64, device=pos.device)
+    plan = S.FMMPlan(6)
+    for _ in range(warmup):
+        S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, depth, out=u5)
+    e0.record()
+    for _ in range(steps):
+        S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, depth, out=u5)
+    e1.record()
+    torch.cuda.synchronize()
+    r["dl_wall_to_cells_order6_ms"] = e0.elapsed_time(e1) / steps
+    r["dl_wall_to_cells_order6_rel_l2_vs_direct"] = float(
+        np.linalg.norm(u5.cpu().numpy()[:, pick5] - ref5) / np.linalg.norm(ref5))
+    e0.record()
+    S.dl(*args, cp, out=u5)
+    e1.record()
+    torch.cuda.synchronize()
+    r["dl_wall_to_cells_direct_ms"] = e0.elapsed_time(e1)
+    r["dl_wall_to_cells_pairs"] = wall.n * cells.n
     return r
 
 

@@ -469,6 +469,19 @@ int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_s
                        double half_width, int32_t depth, const stokes_opts* opts, double* vel_out,
                        void* workspace, size_t ws_bytes, void* stream);
 
+/* vel_out(3, n_trg) (=|+=) the double-layer sum of stokes_dl_eval (no pair
+ * rule) by the same FMM: the double-layer kernel in P2M and in the near
+ * field.  A double-layer field has a net flux (the sum of n . q over the
+ * sources) that single-layer equivalent densities cannot carry, so each box
+ * also carries a point source of that flux at its centre (velocity
+ * sigma r / (4 pi rho^3)); its equivalent density holds the flux-free rest.
+ * Other arguments as stokes_fmm_sl_eval (no mu: the kernel has none). */
+int stokes_fmm_dl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,
+                       const double* src_xyz, const double* density, const double* weight,
+                       const double* normal, int64_t n_trg, const double* trg_xyz,
+                       const double* centre, double half_width, int32_t depth, const stokes_opts* opts,
+                       double* vel_out, void* workspace, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -576,12 +576,12 @@ class FMMPlan:
         return self._h
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
-            try:
-                C.lib().stokes_fmm_plan_destroy(self._h)
-            except Exception:
-                pass
-            self._h = ctypes.c_void_p()
+        h, self._h = getattr(self, "_h", None), None
+        try:
+            if h is not None and h.value:
+                C.lib().stokes_fmm_plan_destroy(h)
+        except Exception:                 # interpreter shutdown: the library may be gone
+            pass
 
 
 def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, accumulate=False):
@@ -598,6 +598,24 @@ def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, ac
     opts = C.Opts(C.FP64, int(bool(accumulate)))
     C.check(C.lib().stokes_fmm_sl_eval(context(device), plan.handle, ns, _ptr(src), _ptr(f), _ptr(w), nt, _ptr(trg),
                                        float(mu), c, float(half_width), int(depth), ctypes.byref(opts), _ptr(out),
+                                       _ptr(ws), int(size.value), _stream(device)))
+    return out
+
+
+def fmm_dl(plan, src, phi, w, nrm, trg, centre, half_width, depth, out=None, accumulate=False):
+    """Double-layer sum by the FMM; see stokes_fmm_dl_eval."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(phi, "phi", device); _vec3(nrm, "nrm", device); _vec3(trg, "trg", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    out = _out(out, nt, device, accumulate)
+    size = ctypes.c_size_t()
+    C.check(C.lib().stokes_fmm_workspace_size(context(device), plan.handle, ns, nt, int(depth), ctypes.byref(size)))
+    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    c = (ctypes.c_double * 3)(*[float(v) for v in centre])
+    opts = C.Opts(C.FP64, int(bool(accumulate)))
+    C.check(C.lib().stokes_fmm_dl_eval(context(device), plan.handle, ns, _ptr(src), _ptr(phi), _ptr(w), _ptr(nrm), nt,
+                                       _ptr(trg), c, float(half_width), int(depth), ctypes.byref(opts), _ptr(out),
                                        _ptr(ws), int(size.value), _stream(device)))
     return out
 

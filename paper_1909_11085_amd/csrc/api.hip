@@ -1123,16 +1123,15 @@ int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan
     return STOKES_OK;
 }
 
-int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, const double* src_xyz,
-                       const double* density, const double* weight, int64_t n_trg, const double* trg_xyz,
-                       double mu, const double* centre, double half_width, int32_t depth,
-                       const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
-                       void* stream) {
+static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, int64_t n_src, const double* src_xyz,
+                    const double* density, const double* weight, const double* normal, int64_t n_trg,
+                    const double* trg_xyz, double pref, const double* centre, double half_width, int32_t depth,
+                    const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes, void* stream) {
+    const char* name = kernel ? "stokes_fmm_dl_eval" : "stokes_fmm_sl_eval";
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
     int rc = fmm_check_sizes(plan, n_src, n_trg, depth);
     if (rc) return rc;
     if (stokes::fmm_plan_device(plan) != ctx->device) return fail(STOKES_EINVAL, "the plan was built on another device");
-    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
     if (!centre) return fail(STOKES_EINVAL, "centre (host, 3 doubles) is NULL");
     for (int c = 0; c < 3; ++c)
         if (!isfinite(centre[c])) return fail(STOKES_EINVAL, "centre must be finite");
@@ -1140,12 +1139,12 @@ int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_s
     Parsed p;
     if ((rc = parse_common(nullptr, opts, n_src, n_trg, p))) return rc;
     if (p.precision != STOKES_FP64) return fail(STOKES_EUNSUPPORTED, "the FMM runs in float64 only");
-    if ((rc = check_points(STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz))) return rc;
+    if ((rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz))) return rc;
     if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
     const size_t sb = (size_t)3 * n_src * 8, tb = (size_t)3 * n_trg * 8;
     if ((rc = check_no_alias(vel_out, tb, "vel_out",
-                             {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {trg_xyz, tb},
-                              {workspace, ws_bytes}})))
+                             {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {normal, kernel ? sb : 0},
+                              {trg_xyz, tb}, {workspace, ws_bytes}})))
         return rc;
     const size_t need = stokes::fmm_workspace_bytes(stokes::fmm_plan_order(plan), n_src, n_trg, depth);
     if ((rc = check_workspace(workspace, ws_bytes, need))) return rc;
@@ -1158,18 +1157,38 @@ int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_s
     in.src_xyz = src_xyz;
     in.density = density;
     in.weight = weight;
+    in.normal = kernel ? normal : nullptr;
     in.trg_xyz = trg_xyz;
     for (int c = 0; c < 3; ++c) in.centre[c] = centre[c];
     in.half_width = half_width;
     in.depth = depth;
-    in.pref = 1.0 / (8.0 * kPi * mu);
+    in.pref = pref;
     in.accumulate = p.accumulate;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const stokes::KernelTimer timer = stokes::next_timer(ctx);
     if (timer.on()) (void)hipEventRecord(timer.start, st);
-    hipError_t e = stokes::launch_fmm_sl(plan, in, vel_out, workspace, st);
+    hipError_t e = stokes::launch_fmm(plan, in, vel_out, workspace, st);
     if (timer.on()) (void)hipEventRecord(timer.stop, st);
-    return launch_status(e, "stokes_fmm_sl_eval");
+    return launch_status(e, name);
+}
+
+int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, const double* src_xyz,
+                       const double* density, const double* weight, int64_t n_trg, const double* trg_xyz,
+                       double mu, const double* centre, double half_width, int32_t depth,
+                       const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
+                       void* stream) {
+    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    return fmm_eval(ctx, plan, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz,
+                    1.0 / (8.0 * kPi * mu), centre, half_width, depth, opts, vel_out, workspace, ws_bytes, stream);
+}
+
+int stokes_fmm_dl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, const double* src_xyz,
+                       const double* density, const double* weight, const double* normal, int64_t n_trg,
+                       const double* trg_xyz, const double* centre, double half_width, int32_t depth,
+                       const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
+                       void* stream) {
+    return fmm_eval(ctx, plan, STOKES_KERNEL_DL, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz,
+                    1.0 / (8.0 * kPi), centre, half_width, depth, opts, vel_out, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -1,5 +1,5 @@
-// Kernel-independent fast multipole method for the single-layer (Stokeslet)
-// sum on a uniform octree (Sec. 3.1, "Far evaluation": the paper evaluates the
+// Kernel-independent fast multipole method for the single- and double-layer
+// sums on a uniform octree (Sec. 3.1, "Far evaluation": the paper evaluates the
 // smooth quadrature for all targets at once with a kernel-independent FMM).
 //
 // Plan (host, once per surface order p): the cube-surface template with p
@@ -19,6 +19,13 @@
 // The surface sums give each wave of a workgroup a quarter of the source
 // boxes (or points); the four partial check vectors are added in a fixed
 // order, so results are reproducible.
+//
+// Double-layer sources use the double-layer kernel in P2M and P2P.  Their
+// field has a net flux (sum of n . q) that no single-layer density carries, so
+// every box also holds a point source of that flux at its centre (velocity
+// sigma r / (4 pi rho^3)); the upward equivalent density represents the
+// flux-free rest, M2M sums the children's fluxes, and M2L adds the point
+// source of each interaction-list box.
 #include <math.h>
 
 #include <algorithm>
@@ -114,6 +121,8 @@ struct FmmDev {
     const double* downT;
     const double* sx;          // sorted sources (3, n_src)
     const double* sq;
+    const double* sn;          // sorted source normals (double layer), else null
+    double* sig;               // per box: point-source flux (double layer), else null
     int64_t n_src;
     const double* tx;          // sorted targets (3, n_trg)
     const int32_t* tperm;      // caller's index of each sorted target
@@ -149,6 +158,31 @@ __device__ __forceinline__ void stokeslet(double rx, double ry, double rz, doubl
     }
 }
 
+// 8 pi times the double-layer kernel: 6 r (r.n)(r.q) / rho^5.
+__device__ __forceinline__ void stresslet(double rx, double ry, double rz, double nx, double ny, double nz, double qx,
+                                          double qy, double qz, double* u) {
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 > 0.0) {
+        const double ri2 = 1.0 / r2;
+        const double c = 6.0 * (rx * nx + ry * ny + rz * nz) * (rx * qx + ry * qy + rz * qz) * (ri2 * ri2) * sqrt(ri2);
+        u[0] += c * rx;
+        u[1] += c * ry;
+        u[2] += c * rz;
+    }
+}
+
+// 8 pi times the velocity of a point source of flux sigma: 2 sigma r / rho^3.
+__device__ __forceinline__ void point_source(double rx, double ry, double rz, double sigma, double* u) {
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 > 0.0 && sigma != 0.0) {
+        const double ri = 1.0 / sqrt(r2);
+        const double c = 2.0 * sigma * (ri * ri * ri);
+        u[0] += c * rx;
+        u[1] += c * ry;
+        u[2] += c * rz;
+    }
+}
+
 __global__ __launch_bounds__(kFBlock) void keys_kernel(const double* __restrict__ x, int64_t n, double c0, double c1,
                                                        double c2, double R, int D, uint64_t* __restrict__ keys,
                                                        int32_t* __restrict__ vals) {
@@ -169,15 +203,17 @@ __global__ __launch_bounds__(kFBlock) void keys_kernel(const double* __restrict_
 }
 
 __global__ __launch_bounds__(kFBlock) void gather_kernel(const double* __restrict__ x, const double* __restrict__ f,
-                                                         const double* __restrict__ w, int64_t n,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ nrm, int64_t n,
                                                          const int32_t* __restrict__ perm, double* __restrict__ sx,
-                                                         double* __restrict__ sq) {
+                                                         double* __restrict__ sq, double* __restrict__ sn) {
     for (int64_t i = (int64_t)blockIdx.x * kFBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kFBlock) {
         const int64_t m = perm[i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             sx[c * n + i] = x[c * n + m];
             if (sq) sq[c * n + i] = w[m] * f[c * n + m];
+            if (sn) sn[c * n + i] = nrm[c * n + m];
         }
     }
 }
@@ -240,11 +276,29 @@ __device__ __forceinline__ void finish(const FmmDev& a, const double* part, doub
     __syncthreads();
 }
 
+// Flux sum of n . q over a leaf's sources: per wave over a strided quarter,
+// then the four waves in order (written to sig by thread 0; read back after
+// the workgroup barrier in finish-free code below).
+__device__ __forceinline__ double leaf_flux(const FmmDev& a, int64_t m0, int64_t m1, double* red) {
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    double f = 0.0;
+    for (int64_t m = m0 + threadIdx.x; m < m1; m += kFBlock)
+        f += a.sn[m] * a.sq[m] + a.sn[a.n_src + m] * a.sq[a.n_src + m] + a.sn[2 * a.n_src + m] * a.sq[2 * a.n_src + m];
+    for (int o = kWave / 2; o >= 1; o >>= 1) f += __shfl_xor(f, o);
+    if (lane == 0) red[wave] = f;
+    __syncthreads();
+    const double total = ((red[0] + red[1]) + red[2]) + red[3];
+    __syncthreads();
+    return total;
+}
+
+template <int KT>
 __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
     extern __shared__ double sh[];
     double* surf = sh;
     double* part = surf + 3 * a.ns;
     double* v = part + kFWaves * a.n3;
+    __shared__ double red[kFWaves];
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int64_t nl = (int64_t)1 << (3 * a.D);
@@ -252,18 +306,28 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
         double* out = a.ue + (a.base[a.D] + b) * a.n3;
         if (!a.snz[a.base[a.D] + b]) {
             for (int r = threadIdx.x; r < a.n3; r += kFBlock) out[r] = 0.0;
+            if (KT == 1 && threadIdx.x == 0) a.sig[a.base[a.D] + b] = 0.0;
             continue;
         }
         double ctr[3], h;
         box_centre(a, a.D, b, ctr, h);
         const int64_t m0 = a.sofs[b], m1 = a.sofs[b + 1];
+        const double sigma = KT == 1 ? leaf_flux(a, m0, m1, red) : 0.0;
+        if (KT == 1 && threadIdx.x == 0) a.sig[a.base[a.D] + b] = sigma;
         for (int cp = lane; cp < a.ns; cp += kWave) {
             double x[3], u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaUC * h * surf[3 * cp + c];
-            for (int64_t m = m0 + wave; m < m1; m += kFWaves)
-                stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sq[m],
-                          a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
+            for (int64_t m = m0 + wave; m < m1; m += kFWaves) {
+                if (KT == 0)
+                    stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sq[m],
+                              a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
+                else
+                    stresslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sn[m],
+                              a.sn[a.n_src + m], a.sn[2 * a.n_src + m], a.sq[m], a.sq[a.n_src + m],
+                              a.sq[2 * a.n_src + m], u);
+            }
+            if (KT == 1 && wave == 0) point_source(x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2], -sigma, u);
 #pragma unroll
             for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[c];
         }
@@ -283,19 +347,26 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
         double* out = a.ue + (a.base[l] + b) * a.n3;
         if (!a.snz[a.base[l] + b]) {
             for (int r = threadIdx.x; r < a.n3; r += kFBlock) out[r] = 0.0;
+            if (a.sig && threadIdx.x == 0) a.sig[a.base[l] + b] = 0.0;
             continue;
         }
         double ctr[3], h;
         box_centre(a, l, b, ctr, h);
+        double sigma = 0.0;                       // the children's fluxes, in a fixed order
+        if (a.sig)
+            for (int o = 0; o < 8; ++o) sigma += a.sig[a.base[l + 1] + 8 * b + o];
+        if (a.sig && threadIdx.x == 0) a.sig[a.base[l] + b] = sigma;
         for (int cp = lane; cp < a.ns; cp += kWave) {
             double x[3], u[3] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaUC * h * surf[3 * cp + c];
+            if (a.sig && wave == 0) point_source(x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2], -sigma, u);
             for (int o = wave; o < 8; o += kFWaves) {
                 const uint64_t ch = 8 * b + o;
                 if (!a.snz[a.base[l + 1] + ch]) continue;
                 double cc[3], hc;
                 box_centre(a, l + 1, ch, cc, hc);
+                if (a.sig) point_source(x[0] - cc[0], x[1] - cc[1], x[2] - cc[2], a.sig[a.base[l + 1] + ch], u);
                 const double* dens = a.ue + (a.base[l + 1] + ch) * a.n3;
                 for (int k = 0; k < a.ns; ++k)
                     stokeslet(x[0] - (cc[0] + kAlphaUE * hc * surf[3 * k]), x[1] - (cc[1] + kAlphaUE * hc * surf[3 * k + 1]),
@@ -345,6 +416,7 @@ __global__ __launch_bounds__(kFBlock) void m2l_kernel(FmmDev a, int l) {
                             if (item++ % kFWaves != wave) continue;
                             double ac[3], ha;
                             box_centre(a, l, ab, ac, ha);
+                            if (a.sig) point_source(x[0] - ac[0], x[1] - ac[1], x[2] - ac[2], a.sig[a.base[l] + ab], u);
                             const double* dens = a.ue + (a.base[l] + ab) * a.n3;
                             for (int k = 0; k < a.ns; ++k)
                                 stokeslet(x[0] - (ac[0] + kAlphaUE * ha * surf[3 * k]),
@@ -370,6 +442,7 @@ __global__ __launch_bounds__(kFBlock) void m2l_kernel(FmmDev a, int l) {
 }
 
 // L2P + P2P per target leaf; results go to the caller's target order.
+template <int KT>
 __global__ __launch_bounds__(kFBlock) void eval_kernel(FmmDev a) {
     extern __shared__ double sh[];
     double* surf = sh;
@@ -397,9 +470,15 @@ __global__ __launch_bounds__(kFBlock) void eval_kernel(FmmDev a) {
                         const int64_t ni[3] = {idx[0] + dx, idx[1] + dy, idx[2] + dz};
                         if (ni[0] < 0 || ni[1] < 0 || ni[2] < 0 || ni[0] >= nlx || ni[1] >= nlx || ni[2] >= nlx) continue;
                         const uint64_t nbr = morton(ni[0], ni[1], ni[2]);
-                        for (int64_t m = a.sofs[nbr]; m < a.sofs[nbr + 1]; ++m)
-                            stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sq[m],
-                                      a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
+                        for (int64_t m = a.sofs[nbr]; m < a.sofs[nbr + 1]; ++m) {
+                            if (KT == 0)
+                                stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m],
+                                          a.sq[m], a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
+                            else
+                                stresslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m],
+                                          a.sn[m], a.sn[a.n_src + m], a.sn[2 * a.n_src + m], a.sq[m],
+                                          a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
+                        }
                     }
             const int64_t o = a.tperm[t];
 #pragma unroll
@@ -416,8 +495,8 @@ struct FmmLayout {
     int64_t nbox = 0, n_leaves = 0;
     int64_t base[kFmmMaxDepth + 2] = {};
     SortLayout sort;
-    size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_tx, off_sofs, off_tofs, off_snz,
-        off_tpr, off_ue, off_de, total;
+    size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_sn, off_tx, off_sofs, off_tofs,
+        off_snz, off_tpr, off_sig, off_ue, off_de, total;
 };
 
 FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
@@ -443,11 +522,13 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_sort = take(L.sort.total);
     L.off_sx = take((size_t)3 * n_src * 8);
     L.off_sq = take((size_t)3 * n_src * 8);
+    L.off_sn = take((size_t)3 * n_src * 8);
     L.off_tx = take((size_t)3 * n_trg * 8);
     L.off_sofs = take((size_t)(L.n_leaves + 1) * 8);
     L.off_tofs = take((size_t)(L.n_leaves + 1) * 8);
     L.off_snz = take((size_t)L.nbox);
     L.off_tpr = take((size_t)L.nbox);
+    L.off_sig = take((size_t)L.nbox * 8);
     L.off_ue = take((size_t)L.nbox * 3 * ns * 8);
     L.off_de = take((size_t)L.nbox * 3 * ns * 8);
     L.total = off;
@@ -570,8 +651,9 @@ size_t fmm_workspace_bytes(int order, int64_t n_src, int64_t n_trg, int depth) {
     return fmm_layout(ns, n_src, n_trg, depth).total;
 }
 
-hipError_t launch_fmm_sl(const stokes_fmm_plan* plan, const FmmInputs& in, double* out, void* workspace,
-                         hipStream_t st) {
+hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* out, void* workspace,
+                      hipStream_t st) {
+    const bool dl = in.normal != nullptr;
     const int D = in.depth, ns = plan->ns;
     const FmmLayout L = fmm_layout(ns, in.n_src, in.n_trg, D);
     char* ws = static_cast<char*>(workspace);
@@ -590,6 +672,8 @@ hipError_t launch_fmm_sl(const stokes_fmm_plan* plan, const FmmInputs& in, doubl
     a.downT = plan->d_downT;
     a.sx = reinterpret_cast<double*>(ws + L.off_sx);
     a.sq = reinterpret_cast<double*>(ws + L.off_sq);
+    a.sn = dl ? reinterpret_cast<double*>(ws + L.off_sn) : nullptr;
+    a.sig = dl ? reinterpret_cast<double*>(ws + L.off_sig) : nullptr;
     a.n_src = in.n_src;
     a.tx = reinterpret_cast<double*>(ws + L.off_tx);
     a.tperm = tvals;
@@ -618,7 +702,8 @@ hipError_t launch_fmm_sl(const stokes_fmm_plan* plan, const FmmInputs& in, doubl
         if (chk()) e = radix_sort_pairs(skeys, svals, in.n_src, 3 * D, sort_ws, L.sort, st);
         if (e == hipSuccess)
             hipLaunchKernelGGL(gather_kernel, dim3(gs), dim3(kFBlock), 0, st, in.src_xyz, in.density, in.weight,
-                               in.n_src, svals, const_cast<double*>(a.sx), const_cast<double*>(a.sq));
+                               in.normal, in.n_src, svals, const_cast<double*>(a.sx), const_cast<double*>(a.sq),
+                               const_cast<double*>(a.sn));
         chk();
     }
     if (e == hipSuccess) {
@@ -626,8 +711,8 @@ hipError_t launch_fmm_sl(const stokes_fmm_plan* plan, const FmmInputs& in, doubl
                            a.R, D, tkeys, tvals);
         if (chk()) e = radix_sort_pairs(tkeys, tvals, in.n_trg, 3 * D, sort_ws, L.sort, st);
         if (e == hipSuccess)
-            hipLaunchKernelGGL(gather_kernel, dim3(gt), dim3(kFBlock), 0, st, in.trg_xyz, nullptr, nullptr, in.n_trg,
-                               tvals, const_cast<double*>(a.tx), nullptr);
+            hipLaunchKernelGGL(gather_kernel, dim3(gt), dim3(kFBlock), 0, st, in.trg_xyz, nullptr, nullptr, nullptr,
+                               in.n_trg, tvals, const_cast<double*>(a.tx), nullptr, nullptr);
         chk();
     }
     const unsigned gl = f_grid((L.n_leaves + 1 + kFBlock - 1) / kFBlock);
@@ -643,12 +728,18 @@ hipError_t launch_fmm_sl(const stokes_fmm_plan* plan, const FmmInputs& in, doubl
                                st, a, l);
     }
     const size_t lds = surface_lds(ns);
-    if (chk()) hipLaunchKernelGGL(p2m_kernel, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+    if (chk()) {
+        if (dl) hipLaunchKernelGGL(p2m_kernel<1>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+        else hipLaunchKernelGGL(p2m_kernel<0>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+    }
     for (int l = D - 1; l >= 2 && chk(); --l)
         hipLaunchKernelGGL(m2m_kernel, dim3(f_grid((int64_t)1 << (3 * l))), dim3(kFBlock), lds, st, a, l);
     for (int l = 2; l <= D && chk(); ++l)
         hipLaunchKernelGGL(m2l_kernel, dim3(f_grid((int64_t)1 << (3 * l))), dim3(kFBlock), lds, st, a, l);
-    if (chk()) hipLaunchKernelGGL(eval_kernel, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+    if (chk()) {
+        if (dl) hipLaunchKernelGGL(eval_kernel<1>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+        else hipLaunchKernelGGL(eval_kernel<0>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+    }
     chk();
     return e;
 }

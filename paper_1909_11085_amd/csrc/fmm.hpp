@@ -30,16 +30,17 @@ struct FmmInputs {
     const double* src_xyz;     // (3, n_src)
     const double* density;     // (3, n_src)
     const double* weight;      // (n_src)
+    const double* normal;      // (3, n_src) for double-layer sources, else null
     const double* trg_xyz;     // (3, n_trg)
     double centre[3], half_width;
     int depth;
-    double pref;               // 1 / (8 pi mu)
+    double pref;               // 1 / (8 pi mu) (single layer) or 1 / (8 pi) (double layer)
     int accumulate;
 };
 
 size_t fmm_workspace_bytes(int order, int64_t n_src, int64_t n_trg, int depth);
 
-hipError_t launch_fmm_sl(const stokes_fmm_plan* plan, const FmmInputs& in, double* out, void* ws,
-                         hipStream_t stream);
+// Single layer when in.normal is null, double layer otherwise.
+hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* out, void* ws, hipStream_t stream);
 
 }  // namespace stokes
