@@ -429,7 +429,7 @@ int stokes_collision_candidates(stokes_ctx* ctx, int32_t n_boxes, const double* 
                                 int32_t* pairs_out, int64_t capacity, int64_t* n_pairs,
                                 int64_t* n_entries, void* workspace, size_t ws_bytes, void* stream);
 
-/* ---- fast multipole method for the single layer, Sec. 3.1 "Far evaluation" */
+/* ---- fast multipole method, single and double layer, Sec. 3.1 "Far evaluation" */
 
 /* The paper evaluates the smooth quadrature for all targets at once with a
  * kernel-independent FMM (PVFMM, not described there).  This is the published
@@ -443,8 +443,9 @@ int stokes_collision_candidates(stokes_ctx* ctx, int32_t n_boxes, const double* 
  *   passes    P2M, M2M, M2L over interaction lists, L2L, L2P, and the direct
  *             sum over the 27 leaves around each target's leaf (zero-distance
  *             pairs skipped).
- * Its error against the direct sum falls with `order` (about 1e-3 at 4, 1e-4
- * at 6 on clustered points); there is no pair rule (all pairs, as in the
+ * Its error against the direct sum falls with `order` (single layer: about
+ * 1e-3 at 4, 1e-4 at 6 on clustered points; double layer about ten times
+ * that); there is no pair rule (all pairs, as in the
  * paper, whose self-cell terms are handled by its singular quadrature).
  * The plan holds the check-to-equivalent pseudo-inverses (singular values
  * below 1e-12 of the largest dropped), computed on the host at creation

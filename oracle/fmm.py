@@ -1,5 +1,5 @@
 """CPU oracle of the kernel-independent fast multipole method for the
-single-layer sum -- test infrastructure only (imported by ``tests/``, the smoke
+single- and double-layer sums -- test infrastructure only (imported by ``tests/``, the smoke
 check and the CPU-baseline leg of the benchmark; never by the product package).
 
 Sec. 3.1, "Far evaluation": the smooth quadrature is an N-body sum, evaluated

@@ -1,5 +1,5 @@
-// Internal declarations of the kernel-independent FMM for the single-layer sum
-// (uniform octree).  Not part of the public C ABI.
+// Internal declarations of the kernel-independent FMM for the single- and
+// double-layer sums (uniform octree).  Not part of the public C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
