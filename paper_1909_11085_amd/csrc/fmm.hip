@@ -146,40 +146,58 @@ __device__ __forceinline__ void box_centre(const FmmDev& a, int l, uint64_t b, d
     for (int c = 0; c < 3; ++c) ctr[c] = (a.c[c] - a.R) + (double)(2 * idx[c] + 1) * h;
 }
 
-__device__ __forceinline__ void stokeslet(double rx, double ry, double rz, double qx, double qy, double qz,
-                                          double* u) {
-    const double r2 = rx * rx + ry * ry + rz * rz;
-    if (r2 > 0.0) {
-        const double ri = 1.0 / sqrt(r2);
-        const double rq = (rx * qx + ry * qy + rz * qz) * (ri * ri * ri);
-        u[0] += qx * ri + rx * rq;
-        u[1] += qy * ri + ry * rq;
-        u[2] += qz * ri + rz * rq;
-    }
+// 1/sqrt(r2): hardware estimate (about 24 correct bits) and one Newton step,
+// ~1e-15 relative; 0 when skip.
+__device__ __forceinline__ double rinv(double r2, bool skip = false) {
+    const double y0 = skip ? 0.0 : __builtin_amdgcn_rsq(r2);
+    return __builtin_fma(0.5 * y0, __builtin_fma(-r2, y0 * y0, 1.0), y0);
+}
+
+// 8 pi mu times the single-layer kernel applied to q: q / rho + r (r.q) / rho^3.
+// MASKED: a zero-distance pair adds nothing; otherwise rho > 0 is assumed.
+template <bool MASKED>
+__device__ __forceinline__ void sl_pair(double rx, double ry, double rz, double qx, double qy, double qz, double* u) {
+    const double r2 = __builtin_fma(rx, rx, __builtin_fma(ry, ry, rz * rz));
+    const double ri = rinv(r2, MASKED && r2 == 0.0);
+    const double c = __builtin_fma(rx, qx, __builtin_fma(ry, qy, rz * qz)) * (ri * ri);
+    u[0] = __builtin_fma(__builtin_fma(c, rx, qx), ri, u[0]);
+    u[1] = __builtin_fma(__builtin_fma(c, ry, qy), ri, u[1]);
+    u[2] = __builtin_fma(__builtin_fma(c, rz, qz), ri, u[2]);
 }
 
 // 8 pi times the double-layer kernel: 6 r (r.n)(r.q) / rho^5.
+template <bool MASKED>
+__device__ __forceinline__ void dl_pair(double rx, double ry, double rz, double nx, double ny, double nz, double qx,
+                                        double qy, double qz, double* u) {
+    const double r2 = __builtin_fma(rx, rx, __builtin_fma(ry, ry, rz * rz));
+    const double ri = rinv(r2, MASKED && r2 == 0.0);
+    const double ri2 = ri * ri;
+    const double rn = __builtin_fma(rx, nx, __builtin_fma(ry, ny, rz * nz));
+    const double rq = __builtin_fma(rx, qx, __builtin_fma(ry, qy, rz * qz));
+    const double c = 6.0 * rn * rq * (ri2 * ri2 * ri);
+    u[0] = __builtin_fma(c, rx, u[0]);
+    u[1] = __builtin_fma(c, ry, u[1]);
+    u[2] = __builtin_fma(c, rz, u[2]);
+}
+
+__device__ __forceinline__ void stokeslet(double rx, double ry, double rz, double qx, double qy, double qz,
+                                          double* u) {
+    sl_pair<true>(rx, ry, rz, qx, qy, qz, u);
+}
 __device__ __forceinline__ void stresslet(double rx, double ry, double rz, double nx, double ny, double nz, double qx,
                                           double qy, double qz, double* u) {
-    const double r2 = rx * rx + ry * ry + rz * rz;
-    if (r2 > 0.0) {
-        const double ri2 = 1.0 / r2;
-        const double c = 6.0 * (rx * nx + ry * ny + rz * nz) * (rx * qx + ry * qy + rz * qz) * (ri2 * ri2) * sqrt(ri2);
-        u[0] += c * rx;
-        u[1] += c * ry;
-        u[2] += c * rz;
-    }
+    dl_pair<true>(rx, ry, rz, nx, ny, nz, qx, qy, qz, u);
 }
 
 // 8 pi times the velocity of a point source of flux sigma: 2 sigma r / rho^3.
 __device__ __forceinline__ void point_source(double rx, double ry, double rz, double sigma, double* u) {
-    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double r2 = __builtin_fma(rx, rx, __builtin_fma(ry, ry, rz * rz));
     if (r2 > 0.0 && sigma != 0.0) {
-        const double ri = 1.0 / sqrt(r2);
+        const double ri = rinv(r2);
         const double c = 2.0 * sigma * (ri * ri * ri);
-        u[0] += c * rx;
-        u[1] += c * ry;
-        u[2] += c * rz;
+        u[0] = __builtin_fma(c, rx, u[0]);
+        u[1] = __builtin_fma(c, ry, u[1]);
+        u[2] = __builtin_fma(c, rz, u[2]);
     }
 }
 
@@ -251,10 +269,6 @@ __global__ __launch_bounds__(kFBlock) void flags_up_kernel(FmmDev a, int l) {
     }
 }
 
-// Dynamic LDS of the surface kernels, in doubles: template, 4 partial check
-// vectors, their sum.
-size_t surface_lds(int ns) { return (size_t)(3 * ns + (kFWaves + 1) * 3 * ns) * sizeof(double); }
-
 __device__ __forceinline__ void load_surface(const FmmDev& a, double* surf) {
     for (int r = threadIdx.x; r < 3 * a.ns; r += kFBlock) surf[r] = a.surf[r];
     __syncthreads();
@@ -292,11 +306,220 @@ __device__ __forceinline__ double leaf_flux(const FmmDev& a, int64_t m0, int64_t
     return total;
 }
 
-template <int KT>
-__global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
+constexpr int kMaxNs = 6 * (kFmmMaxOrder - 1) * (kFmmMaxOrder - 1) + 2;
+static_assert(kMaxNs <= 3 * kWave, "m2l_kernel holds at most three check points per lane");
+
+// Writes one box's surface sources (centre ctr, radius scale: points
+// ctr + scale * template, strengths dens) into a wave's LDS slice.
+__device__ __forceinline__ void stage_surface(const FmmDev& a, const double* surf, const double* ctr, double scale,
+                                              const double* __restrict__ dens, SrcSL64* dst, int lane) {
+    for (int j = lane; j < a.ns; j += kWave) {
+        SrcSL64 r;
+        r.x = ctr[0] + scale * surf[3 * j];
+        r.y = ctr[1] + scale * surf[3 * j + 1];
+        r.z = ctr[2] + scale * surf[3 * j + 2];
+        r.qx = dens[3 * j];
+        r.qy = dens[3 * j + 1];
+        r.qz = dens[3 * j + 2];
+        dst[j] = r;
+    }
+}
+
+// Check points of a box (centre ctr, half-width h, radius scale alpha): lane
+// j holds points j, j + 64, ... (T of them); lanes past the last point repeat
+// it and are never stored.
+template <int T>
+__device__ __forceinline__ void check_points(const FmmDev& a, const double* surf, const double* ctr, double scale,
+                                             int lane, double (&x)[T][3], double (&u)[T][3]) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int cp = min(lane + k * kWave, a.ns - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[k][c] = ctr[c] + scale * surf[3 * cp + c];
+            u[k][c] = 0.0;
+        }
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void store_partial(const FmmDev& a, double* part, int wave, int lane,
+                                              const double (&u)[T][3]) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int cp = lane + k * kWave;
+        if (cp < a.ns)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[k][c];
+    }
+}
+
+// Dynamic LDS of the M2L kernel, in doubles: the template, then one staging
+// slice of ns records per wave, which the partial check vectors and their sum
+// reuse once every wave is done with its sources.
+size_t m2l_lds(int ns) {
+    const size_t stage = (size_t)kFWaves * ns * (sizeof(SrcSL64) / sizeof(double));
+    const size_t part = (size_t)(kFWaves + 1) * 3 * ns;
+    return ((size_t)((3 * ns + 1) & ~1) + std::max(stage, part)) * sizeof(double);
+}
+
+// M2L from the interaction list, plus L2L from the parent (levels > 2), then
+// the downward equivalent density.  Only boxes holding targets.  Lane j holds
+// check points j, j + 64, ... (T of them) in registers; wave w takes every
+// fourth interaction-list box, stages its equivalent sources in its own LDS
+// slice and reads them back by broadcast.
+template <int T>
+__global__ __launch_bounds__(kFBlock) void m2l_kernel(FmmDev a, int l) {
     extern __shared__ double sh[];
     double* surf = sh;
-    double* part = surf + 3 * a.ns;
+    double* rest = surf + ((3 * a.ns + 1) & ~1);               // 16-byte aligned
+    SrcSL64* stage = reinterpret_cast<SrcSL64*>(rest);
+    double* part = rest;
+    double* v = part + kFWaves * a.n3;
+    load_surface(a, surf);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    SrcSL64* mine = stage + wave * a.ns;
+    const int64_t nb = (int64_t)1 << (3 * l), np = (int64_t)1 << (l - 1);
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        if (!a.tpr[a.base[l] + b]) continue;                      // uniform over the workgroup
+        double ctr[3], h;
+        box_centre(a, l, b, ctr, h);
+        const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
+        const uint64_t p = b >> 3;
+        const int64_t pidx[3] = {compact3(p), compact3(p >> 1), compact3(p >> 2)};
+        double x[T][3], u[T][3];
+        check_points<T>(a, surf, ctr, kAlphaDC * h, lane, x, u);
+        int item = 0;
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int64_t pn[3] = {pidx[0] + dx, pidx[1] + dy, pidx[2] + dz};
+                    if (pn[0] < 0 || pn[1] < 0 || pn[2] < 0 || pn[0] >= np || pn[1] >= np || pn[2] >= np) continue;
+                    for (int o = 0; o < 8; ++o) {
+                        const int64_t ai[3] = {2 * pn[0] + (o & 1), 2 * pn[1] + ((o >> 1) & 1), 2 * pn[2] + (o >> 2)};
+                        if (llabs(ai[0] - idx[0]) <= 1 && llabs(ai[1] - idx[1]) <= 1 && llabs(ai[2] - idx[2]) <= 1)
+                            continue;                      // a neighbour: near field
+                        const uint64_t ab = morton(ai[0], ai[1], ai[2]);
+                        if (!a.snz[a.base[l] + ab]) continue;
+                        if (item++ % kFWaves != wave) continue;
+                        double ac[3], ha;
+                        box_centre(a, l, ab, ac, ha);
+                        if (a.sig) {
+                            const double sg = a.sig[a.base[l] + ab];
+#pragma unroll
+                            for (int k = 0; k < T; ++k)
+                                point_source(x[k][0] - ac[0], x[k][1] - ac[1], x[k][2] - ac[2], sg, u[k]);
+                        }
+                        stage_surface(a, surf, ac, kAlphaUE * ha, a.ue + (a.base[l] + ab) * a.n3, mine, lane);
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+                        for (int j = 0; j < a.ns; ++j) {
+                            const SrcSL64 sr = mine[j];
+#pragma unroll
+                            for (int k = 0; k < T; ++k)
+                                sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz,
+                                               u[k]);
+                        }
+                        __builtin_amdgcn_wave_barrier();   // reads of this box precede the next writes
+                    }
+                }
+        if (l > 2 && item++ % kFWaves == wave) {
+            double pc[3], hp;
+            box_centre(a, l - 1, p, pc, hp);
+            stage_surface(a, surf, pc, kAlphaDE * hp, a.de + (a.base[l - 1] + p) * a.n3, mine, lane);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+            for (int j = 0; j < a.ns; ++j) {
+                const SrcSL64 sr = mine[j];
+#pragma unroll
+                for (int k = 0; k < T; ++k)
+                    sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz, u[k]);
+            }
+        }
+        __syncthreads();                           // the partial vectors overwrite the staging slices
+        store_partial<T>(a, part, wave, lane, u);
+        finish(a, part, v, a.downT, h, a.de + (a.base[l] + b) * a.n3);
+    }
+}
+
+// Near field (P2P) and L2P, one wave per work item: up to 64 targets of one
+// leaf (items are built per evaluation from the leaf offsets).  An item of
+// n targets gives each target R = min(16, 64 / n) lanes; lane phase hp takes
+// every R-th staged source, and the R partial sums are added in a fixed order
+// at the end.  Sources are staged in LDS, up to 128 at a time: first the
+// leaf's downward equivalent density (single-layer kernel), then the leaf's
+// own sources (the only ones that can sit at zero distance from a target, so
+// the only ones with the zero-distance mask), then the sources of the other
+// 26 neighbour leaves as one run.
+constexpr int kNearTile = 128;
+constexpr int kNearRep = 16;
+constexpr int kNearSlots = kNearTile + kNearRep;   // room for the padding of the last runs
+
+template <int KT> struct NearRec;
+template <> struct NearRec<0> { using type = SrcSL64; };
+template <> struct NearRec<1> { using type = SrcDL64; };
+
+struct NearArgs {
+    const int32_t* items;      // (leaf, chunk) pairs
+    const int64_t* n_items;    // device count
+};
+
+template <int KT>
+__device__ __forceinline__ void load_source(const FmmDev& a, int64_t m, typename NearRec<KT>::type& r) {
+    r.x = a.sx[m];
+    r.y = a.sx[a.n_src + m];
+    r.z = a.sx[2 * a.n_src + m];
+    r.qx = a.sq[m];
+    r.qy = a.sq[a.n_src + m];
+    r.qz = a.sq[2 * a.n_src + m];
+    if constexpr (KT == 1) {
+        r.nx = a.sn[m];
+        r.ny = a.sn[a.n_src + m];
+        r.nz = a.sn[2 * a.n_src + m];
+        r.pad = 0.0;
+    }
+}
+
+template <typename Rec>
+__device__ __forceinline__ Rec far_pad() {
+    Rec r{};
+    r.x = r.y = r.z = kPadPos;
+    return r;
+}
+
+template <int KT, bool MASKED>
+__device__ __forceinline__ void near_pair(const typename NearRec<KT>::type& s, double x, double y, double z,
+                                          double* u) {
+    if constexpr (KT == 0)
+        sl_pair<MASKED>(x - s.x, y - s.y, z - s.z, s.qx, s.qy, s.qz, u);
+    else
+        dl_pair<MASKED>(x - s.x, y - s.y, z - s.z, s.nx, s.ny, s.nz, s.qx, s.qy, s.qz, u);
+}
+
+// Dynamic LDS of P2M, in doubles: the template, a workgroup tile of source
+// records, the four partial check vectors and their sum.
+size_t p2m_lds(int ns, int KT) {
+    const size_t rec = KT ? sizeof(SrcDL64) : sizeof(SrcSL64);
+    return ((size_t)((3 * ns + 1) & ~1) + kFBlock * rec / sizeof(double) + (size_t)(kFWaves + 1) * 3 * ns) *
+           sizeof(double);
+}
+// ... of M2M: the template, one staging slice per wave, the partial vectors.
+size_t m2m_lds(int ns) {
+    return ((size_t)((3 * ns + 1) & ~1) + (size_t)kFWaves * ns * (sizeof(SrcSL64) / sizeof(double)) +
+            (size_t)(kFWaves + 1) * 3 * ns) *
+           sizeof(double);
+}
+
+// P2M: the leaf's sources are staged 256 at a time; wave w sums its quarter
+// of each tile at its T check points per lane (zero-distance mask: a point
+// outside the root cube is counted in a boundary leaf and may sit anywhere).
+template <int KT, int T>
+__global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
+    using Rec = typename NearRec<KT>::type;
+    extern __shared__ double sh[];
+    double* surf = sh;
+    Rec* tile = reinterpret_cast<Rec*>(surf + ((3 * a.ns + 1) & ~1));
+    double* part = reinterpret_cast<double*>(tile + kFBlock);
     double* v = part + kFWaves * a.n3;
     __shared__ double red[kFWaves];
     load_surface(a, surf);
@@ -314,34 +537,43 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
         const int64_t m0 = a.sofs[b], m1 = a.sofs[b + 1];
         const double sigma = KT == 1 ? leaf_flux(a, m0, m1, red) : 0.0;
         if (KT == 1 && threadIdx.x == 0) a.sig[a.base[a.D] + b] = sigma;
-        for (int cp = lane; cp < a.ns; cp += kWave) {
-            double x[3], u[3] = {0.0, 0.0, 0.0};
+        double x[T][3], u[T][3];
+        check_points<T>(a, surf, ctr, kAlphaUC * h, lane, x, u);
+        for (int64_t c0 = m0; c0 < m1; c0 += kFBlock) {
+            const int nb = (int)min((int64_t)kFBlock, m1 - c0);
+            __syncthreads();                                        // readers of the previous tile are done
+            Rec r = far_pad<Rec>();
+            if ((int)threadIdx.x < nb) load_source<KT>(a, c0 + threadIdx.x, r);
+            tile[threadIdx.x] = r;
+            __syncthreads();
+            const int j1 = min(kWave * (wave + 1), nb);
+            for (int j = kWave * wave; j < j1; ++j) {
+                const Rec sr = tile[j];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaUC * h * surf[3 * cp + c];
-            for (int64_t m = m0 + wave; m < m1; m += kFWaves) {
-                if (KT == 0)
-                    stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sq[m],
-                              a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
-                else
-                    stresslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m], a.sn[m],
-                              a.sn[a.n_src + m], a.sn[2 * a.n_src + m], a.sq[m], a.sq[a.n_src + m],
-                              a.sq[2 * a.n_src + m], u);
+                for (int k = 0; k < T; ++k) near_pair<KT, true>(sr, x[k][0], x[k][1], x[k][2], u[k]);
             }
-            if (KT == 1 && wave == 0) point_source(x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2], -sigma, u);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[c];
         }
+        if (KT == 1 && wave == 0)
+#pragma unroll
+            for (int k = 0; k < T; ++k)
+                point_source(x[k][0] - ctr[0], x[k][1] - ctr[1], x[k][2] - ctr[2], -sigma, u[k]);
+        store_partial<T>(a, part, wave, lane, u);
         finish(a, part, v, a.upT, h, out);
     }
 }
 
+// M2M: wave w takes children w and w + 4, stages each child's equivalent
+// sources in its own LDS slice and sums them at its T check points per lane.
+template <int T>
 __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
     extern __shared__ double sh[];
     double* surf = sh;
-    double* part = surf + 3 * a.ns;
+    SrcSL64* stage = reinterpret_cast<SrcSL64*>(surf + ((3 * a.ns + 1) & ~1));
+    double* part = reinterpret_cast<double*>(stage + kFWaves * a.ns);
     double* v = part + kFWaves * a.n3;
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    SrcSL64* mine = stage + wave * a.ns;
     const int64_t nb = (int64_t)1 << (3 * l);
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
         double* out = a.ue + (a.base[l] + b) * a.n3;
@@ -356,147 +588,194 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
         if (a.sig)
             for (int o = 0; o < 8; ++o) sigma += a.sig[a.base[l + 1] + 8 * b + o];
         if (a.sig && threadIdx.x == 0) a.sig[a.base[l] + b] = sigma;
-        for (int cp = lane; cp < a.ns; cp += kWave) {
-            double x[3], u[3] = {0.0, 0.0, 0.0};
+        double x[T][3], u[T][3];
+        check_points<T>(a, surf, ctr, kAlphaUC * h, lane, x, u);
+        if (a.sig && wave == 0)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaUC * h * surf[3 * cp + c];
-            if (a.sig && wave == 0) point_source(x[0] - ctr[0], x[1] - ctr[1], x[2] - ctr[2], -sigma, u);
-            for (int o = wave; o < 8; o += kFWaves) {
-                const uint64_t ch = 8 * b + o;
-                if (!a.snz[a.base[l + 1] + ch]) continue;
-                double cc[3], hc;
-                box_centre(a, l + 1, ch, cc, hc);
-                if (a.sig) point_source(x[0] - cc[0], x[1] - cc[1], x[2] - cc[2], a.sig[a.base[l + 1] + ch], u);
-                const double* dens = a.ue + (a.base[l + 1] + ch) * a.n3;
-                for (int k = 0; k < a.ns; ++k)
-                    stokeslet(x[0] - (cc[0] + kAlphaUE * hc * surf[3 * k]), x[1] - (cc[1] + kAlphaUE * hc * surf[3 * k + 1]),
-                              x[2] - (cc[2] + kAlphaUE * hc * surf[3 * k + 2]), dens[3 * k], dens[3 * k + 1],
-                              dens[3 * k + 2], u);
+            for (int k = 0; k < T; ++k)
+                point_source(x[k][0] - ctr[0], x[k][1] - ctr[1], x[k][2] - ctr[2], -sigma, u[k]);
+        for (int o = wave; o < 8; o += kFWaves) {
+            const uint64_t ch = 8 * b + o;
+            if (!a.snz[a.base[l + 1] + ch]) continue;
+            double cc[3], hc;
+            box_centre(a, l + 1, ch, cc, hc);
+            if (a.sig) {
+                const double sg = a.sig[a.base[l + 1] + ch];
+#pragma unroll
+                for (int k = 0; k < T; ++k) point_source(x[k][0] - cc[0], x[k][1] - cc[1], x[k][2] - cc[2], sg, u[k]);
             }
+            stage_surface(a, surf, cc, kAlphaUE * hc, a.ue + (a.base[l + 1] + ch) * a.n3, mine, lane);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+            for (int j = 0; j < a.ns; ++j) {
+                const SrcSL64 sr = mine[j];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[c];
+                for (int k = 0; k < T; ++k)
+                    sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz, u[k]);
+            }
+            __builtin_amdgcn_wave_barrier();   // reads of this child precede the next writes
         }
+        store_partial<T>(a, part, wave, lane, u);
         finish(a, part, v, a.upT, h, out);
     }
 }
 
-// M2L from the interaction list, plus L2L from the parent (levels > 2), then
-// the downward equivalent density.  Only boxes holding targets.
-__global__ __launch_bounds__(kFBlock) void m2l_kernel(FmmDev a, int l) {
-    extern __shared__ double sh[];
-    double* surf = sh;
-    double* part = surf + 3 * a.ns;
-    double* v = part + kFWaves * a.n3;
-    load_surface(a, surf);
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int64_t nb = (int64_t)1 << (3 * l), np = (int64_t)1 << (l - 1);
-    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        if (!a.tpr[a.base[l] + b]) continue;
-        double ctr[3], h;
-        box_centre(a, l, b, ctr, h);
-        const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
-        const uint64_t p = b >> 3;
-        const int64_t pidx[3] = {compact3(p), compact3(p >> 1), compact3(p >> 2)};
-        for (int cp = lane; cp < a.ns; cp += kWave) {
-            double x[3], u[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) x[c] = ctr[c] + kAlphaDC * h * surf[3 * cp + c];
-            int item = 0;
-            for (int dx = -1; dx <= 1; ++dx)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dz = -1; dz <= 1; ++dz) {
-                        const int64_t pn[3] = {pidx[0] + dx, pidx[1] + dy, pidx[2] + dz};
-                        if (pn[0] < 0 || pn[1] < 0 || pn[2] < 0 || pn[0] >= np || pn[1] >= np || pn[2] >= np) continue;
-                        for (int o = 0; o < 8; ++o) {
-                            const int64_t ai[3] = {2 * pn[0] + (o & 1), 2 * pn[1] + ((o >> 1) & 1), 2 * pn[2] + (o >> 2)};
-                            if (llabs(ai[0] - idx[0]) <= 1 && llabs(ai[1] - idx[1]) <= 1 && llabs(ai[2] - idx[2]) <= 1)
-                                continue;                      // a neighbour: near field
-                            const uint64_t ab = morton(ai[0], ai[1], ai[2]);
-                            if (!a.snz[a.base[l] + ab]) continue;
-                            if (item++ % kFWaves != wave) continue;
-                            double ac[3], ha;
-                            box_centre(a, l, ab, ac, ha);
-                            if (a.sig) point_source(x[0] - ac[0], x[1] - ac[1], x[2] - ac[2], a.sig[a.base[l] + ab], u);
-                            const double* dens = a.ue + (a.base[l] + ab) * a.n3;
-                            for (int k = 0; k < a.ns; ++k)
-                                stokeslet(x[0] - (ac[0] + kAlphaUE * ha * surf[3 * k]),
-                                          x[1] - (ac[1] + kAlphaUE * ha * surf[3 * k + 1]),
-                                          x[2] - (ac[2] + kAlphaUE * ha * surf[3 * k + 2]), dens[3 * k],
-                                          dens[3 * k + 1], dens[3 * k + 2], u);
-                        }
-                    }
-            if (l > 2 && item++ % kFWaves == wave) {
-                double pc[3], hp;
-                box_centre(a, l - 1, p, pc, hp);
-                const double* dens = a.de + (a.base[l - 1] + p) * a.n3;
-                for (int k = 0; k < a.ns; ++k)
-                    stokeslet(x[0] - (pc[0] + kAlphaDE * hp * surf[3 * k]), x[1] - (pc[1] + kAlphaDE * hp * surf[3 * k + 1]),
-                              x[2] - (pc[2] + kAlphaDE * hp * surf[3 * k + 2]), dens[3 * k], dens[3 * k + 1],
-                              dens[3 * k + 2], u);
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[c];
-        }
-        finish(a, part, v, a.downT, h, a.de + (a.base[l] + b) * a.n3);
-    }
-}
-
-// L2P + P2P per target leaf; results go to the caller's target order.
 template <int KT>
-__global__ __launch_bounds__(kFBlock) void eval_kernel(FmmDev a) {
-    extern __shared__ double sh[];
-    double* surf = sh;
-    double* dens = surf + 3 * a.ns;
-    load_surface(a, surf);
-    const int64_t nlx = (int64_t)1 << a.D, nl = (int64_t)1 << (3 * a.D);
-    for (int64_t L = blockIdx.x; L < nl; L += gridDim.x) {
-        if (!a.tpr[a.base[a.D] + L]) continue;
-        const double* d = a.de + (a.base[a.D] + L) * a.n3;
-        for (int r = threadIdx.x; r < a.n3; r += kFBlock) dens[r] = d[r];
-        __syncthreads();
+__global__ __launch_bounds__(kWave) void near_kernel(FmmDev a, NearArgs na) {
+    using Rec = typename NearRec<KT>::type;
+    __shared__ Rec s_rec[kNearSlots];
+    __shared__ int64_t s_beg[27], s_pre[28];
+    SrcSL64* s_sl = reinterpret_cast<SrcSL64*>(s_rec);
+    const int lane = threadIdx.x;
+    const int64_t count = *na.n_items;
+    const int64_t nlx = (int64_t)1 << a.D;
+    for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+        const int64_t L = na.items[2 * it];
+        const int64_t t0 = a.tofs[L] + (int64_t)na.items[2 * it + 1] * kWave;
+        const int nc = (int)min(a.tofs[L + 1] - t0, (int64_t)kWave);     // 1..64
+        const int R = min(kNearRep, kWave / nc);
+        const int ti = lane / R, hp = lane - ti * R;
+        const bool valid = ti < nc;
+        const int64_t t = t0 + (valid ? ti : 0);                           // idle lanes mirror target t0
+        const double x = a.tx[t], y = a.tx[a.n_trg + t], z = a.tx[2 * a.n_trg + t];
+        double u[3] = {0.0, 0.0, 0.0};
         double ctr[3], h;
         box_centre(a, a.D, L, ctr, h);
-        const int64_t idx[3] = {compact3(L), compact3(L >> 1), compact3(L >> 2)};
-        for (int64_t t = a.tofs[L] + threadIdx.x; t < a.tofs[L + 1]; t += kFBlock) {
-            const double x[3] = {a.tx[t], a.tx[a.n_trg + t], a.tx[2 * a.n_trg + t]};
-            double u[3] = {0.0, 0.0, 0.0};
-            for (int k = 0; k < a.ns; ++k)
-                stokeslet(x[0] - (ctr[0] + kAlphaDE * h * surf[3 * k]), x[1] - (ctr[1] + kAlphaDE * h * surf[3 * k + 1]),
-                          x[2] - (ctr[2] + kAlphaDE * h * surf[3 * k + 2]), dens[3 * k], dens[3 * k + 1],
-                          dens[3 * k + 2], u);
-            for (int dx = -1; dx <= 1; ++dx)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dz = -1; dz <= 1; ++dz) {
-                        const int64_t ni[3] = {idx[0] + dx, idx[1] + dy, idx[2] + dz};
-                        if (ni[0] < 0 || ni[1] < 0 || ni[2] < 0 || ni[0] >= nlx || ni[1] >= nlx || ni[2] >= nlx) continue;
-                        const uint64_t nbr = morton(ni[0], ni[1], ni[2]);
-                        for (int64_t m = a.sofs[nbr]; m < a.sofs[nbr + 1]; ++m) {
-                            if (KT == 0)
-                                stokeslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m],
-                                          a.sq[m], a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
-                            else
-                                stresslet(x[0] - a.sx[m], x[1] - a.sx[a.n_src + m], x[2] - a.sx[2 * a.n_src + m],
-                                          a.sn[m], a.sn[a.n_src + m], a.sn[2 * a.n_src + m], a.sq[m],
-                                          a.sq[a.n_src + m], a.sq[2 * a.n_src + m], u);
-                        }
+
+        // L2P: the leaf's downward equivalent density, single-layer kernel (with
+        // the zero-distance mask: a target outside the root cube is counted in a
+        // boundary leaf and may sit anywhere)
+        const double* de = a.de + (a.base[a.D] + L) * a.n3;
+        for (int j0 = 0; j0 < a.ns; j0 += kNearTile) {
+            const int nb = min(kNearTile, a.ns - j0);
+            for (int j = lane; j < kNearSlots; j += kWave) {
+                SrcSL64 r = far_pad<SrcSL64>();
+                if (j < nb) {
+                    const int k = j0 + j;
+                    const double sc = kAlphaDE * h;
+                    r.x = ctr[0] + sc * a.surf[3 * k];
+                    r.y = ctr[1] + sc * a.surf[3 * k + 1];
+                    r.z = ctr[2] + sc * a.surf[3 * k + 2];
+                    r.qx = de[3 * k];
+                    r.qy = de[3 * k + 1];
+                    r.qz = de[3 * k + 2];
+                }
+                s_sl[j] = r;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int steps = (nb + R - 1) / R;
+            for (int st = 0; st < steps; ++st) {
+                const SrcSL64 sr = s_sl[st * R + hp];
+                sl_pair<true>(x - sr.x, y - sr.y, z - sr.z, sr.qx, sr.qy, sr.qz, u);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+
+        // the leaf's own sources, with the zero-distance mask
+        {
+            const int64_t s0 = a.sofs[L], s1 = a.sofs[L + 1];
+            for (int64_t b0 = s0; b0 < s1; b0 += kNearTile) {
+                const int nb = (int)min((int64_t)kNearTile, s1 - b0);
+                for (int j = lane; j < kNearSlots; j += kWave) {
+                    Rec r = far_pad<Rec>();
+                    if (j < nb) load_source<KT>(a, b0 + j, r);
+                    s_rec[j] = r;
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int steps = (nb + R - 1) / R;
+                for (int st = 0; st < steps; ++st) near_pair<KT, true>(s_rec[st * R + hp], x, y, z, u);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+
+        // the other 26 neighbour leaves, as one run of sources
+        if (lane < 27) {
+            int64_t beg = 0, len = 0;
+            const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
+            const int64_t ni[3] = {compact3(L) + dx, compact3(L >> 1) + dy, compact3(L >> 2) + dz};
+            if (lane != 13 && ni[0] >= 0 && ni[1] >= 0 && ni[2] >= 0 && ni[0] < nlx && ni[1] < nlx && ni[2] < nlx) {
+                const uint64_t nbr = morton(ni[0], ni[1], ni[2]);
+                beg = a.sofs[nbr];
+                len = a.sofs[nbr + 1] - beg;
+            }
+            s_beg[lane] = beg;
+            s_pre[lane + 1] = len;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            s_pre[0] = 0;
+            for (int k = 1; k <= 27; ++k) s_pre[k] += s_pre[k - 1];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int64_t total = s_pre[27];
+        for (int64_t f0 = 0; f0 < total; f0 += kNearTile) {
+            const int nb = (int)min((int64_t)kNearTile, total - f0);
+            for (int j = lane; j < kNearSlots; j += kWave) {
+                Rec r = far_pad<Rec>();
+                if (j < nb) {
+                    const int64_t f = f0 + j;
+                    int lo = 0, hi = 27;                   // s_pre[lo] <= f < s_pre[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= f) lo = mid; else hi = mid;
                     }
+                    load_source<KT>(a, s_beg[lo] + (f - s_pre[lo]), r);
+                }
+                s_rec[j] = r;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int steps = (nb + R - 1) / R;
+#pragma unroll 2
+            for (int st = 0; st < steps; ++st) near_pair<KT, false>(s_rec[st * R + hp], x, y, z, u);
+            __builtin_amdgcn_wave_barrier();
+        }
+
+        // the R phases of each target, in order
+        double sum[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sum[c] += __shfl(u[c], ti * R + q);
+        if (valid && hp == 0) {
             const int64_t o = a.tperm[t];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double val = a.pref * u[c];
+                const double val = a.pref * sum[c];
                 a.out[c * a.n_trg + o] = a.accumulate ? a.out[c * a.n_trg + o] + val : val;
             }
         }
-        __syncthreads();                       // dens is reused by the next leaf
+        __builtin_amdgcn_wave_barrier();           // this item's reads precede the next item's writes
     }
 }
+
+__global__ __launch_bounds__(kFBlock) void chunk_count_kernel(const int64_t* __restrict__ tofs, int64_t n_leaves,
+                                                              int64_t* __restrict__ cnt) {
+    for (int64_t L = (int64_t)blockIdx.x * kFBlock + threadIdx.x; L < n_leaves; L += (int64_t)gridDim.x * kFBlock)
+        cnt[L] = (tofs[L + 1] - tofs[L] + kWave - 1) / kWave;
+}
+
+__global__ __launch_bounds__(kFBlock) void items_kernel(const int64_t* __restrict__ tofs,
+                                                        const int64_t* __restrict__ cofs, int64_t n_leaves,
+                                                        int32_t* __restrict__ items) {
+    for (int64_t L = (int64_t)blockIdx.x * kFBlock + threadIdx.x; L < n_leaves; L += (int64_t)gridDim.x * kFBlock) {
+        const int64_t n = (tofs[L + 1] - tofs[L] + kWave - 1) / kWave;
+        for (int64_t c = 0; c < n; ++c) {
+            items[2 * (cofs[L] + c)] = (int32_t)L;
+            items[2 * (cofs[L] + c) + 1] = (int32_t)c;
+        }
+    }
+}
+
+// Upper bound of the near-field work items: every leaf with targets adds at
+// most one partial chunk to the full ones.
+int64_t max_items(int64_t n_trg, int64_t n_leaves) { return (n_trg + kWave - 1) / kWave + std::min(n_trg, n_leaves); }
 
 struct FmmLayout {
     int64_t nbox = 0, n_leaves = 0;
     int64_t base[kFmmMaxDepth + 2] = {};
     SortLayout sort;
+    int64_t max_items = 0;
     size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_sn, off_tx, off_sofs, off_tofs,
-        off_snz, off_tpr, off_sig, off_ue, off_de, total;
+        off_snz, off_tpr, off_sig, off_ue, off_de, off_cofs, off_scan, off_items, off_nitems, total;
 };
 
 FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
@@ -531,6 +810,11 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_sig = take((size_t)L.nbox * 8);
     L.off_ue = take((size_t)L.nbox * 3 * ns * 8);
     L.off_de = take((size_t)L.nbox * 3 * ns * 8);
+    L.max_items = max_items(n_trg, L.n_leaves);
+    L.off_cofs = take((size_t)L.n_leaves * 8);
+    L.off_scan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
+    L.off_items = take((size_t)L.max_items * 2 * 4);
+    L.off_nitems = take(8);
     L.total = off;
     return L;
 }
@@ -727,18 +1011,49 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
             hipLaunchKernelGGL(flags_up_kernel, dim3(f_grid(((int64_t)1 << (3 * l)) / kFBlock + 1)), dim3(kFBlock), 0,
                                st, a, l);
     }
-    const size_t lds = surface_lds(ns);
+    const int T = (ns + kWave - 1) / kWave;
+    // near-field work items: (leaf, chunk of 64 targets)
+    int64_t* cofs = reinterpret_cast<int64_t*>(ws + L.off_cofs);
+    int64_t* n_items = reinterpret_cast<int64_t*>(ws + L.off_nitems);
+    int32_t* items = reinterpret_cast<int32_t*>(ws + L.off_items);
     if (chk()) {
-        if (dl) hipLaunchKernelGGL(p2m_kernel<1>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
-        else hipLaunchKernelGGL(p2m_kernel<0>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+        hipLaunchKernelGGL(chunk_count_kernel, dim3(gl), dim3(kFBlock), 0, st, a.tofs, L.n_leaves, cofs);
+        if (chk()) e = exclusive_scan_i64(cofs, L.n_leaves, cofs, reinterpret_cast<int64_t*>(ws + L.off_scan), n_items, st);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(items_kernel, dim3(gl), dim3(kFBlock), 0, st, a.tofs, cofs, L.n_leaves, items);
     }
-    for (int l = D - 1; l >= 2 && chk(); --l)
-        hipLaunchKernelGGL(m2m_kernel, dim3(f_grid((int64_t)1 << (3 * l))), dim3(kFBlock), lds, st, a, l);
-    for (int l = 2; l <= D && chk(); ++l)
-        hipLaunchKernelGGL(m2l_kernel, dim3(f_grid((int64_t)1 << (3 * l))), dim3(kFBlock), lds, st, a, l);
     if (chk()) {
-        if (dl) hipLaunchKernelGGL(eval_kernel<1>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
-        else hipLaunchKernelGGL(eval_kernel<0>, dim3(f_grid(L.n_leaves)), dim3(kFBlock), lds, st, a);
+        const dim3 g(f_grid(L.n_leaves));
+        const size_t lds = p2m_lds(ns, dl ? 1 : 0);
+        if (dl) {
+            if (T == 1) hipLaunchKernelGGL((p2m_kernel<1, 1>), g, dim3(kFBlock), lds, st, a);
+            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<1, 2>), g, dim3(kFBlock), lds, st, a);
+            else hipLaunchKernelGGL((p2m_kernel<1, 3>), g, dim3(kFBlock), lds, st, a);
+        } else {
+            if (T == 1) hipLaunchKernelGGL((p2m_kernel<0, 1>), g, dim3(kFBlock), lds, st, a);
+            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<0, 2>), g, dim3(kFBlock), lds, st, a);
+            else hipLaunchKernelGGL((p2m_kernel<0, 3>), g, dim3(kFBlock), lds, st, a);
+        }
+    }
+    for (int l = D - 1; l >= 2 && chk(); --l) {
+        const dim3 g(f_grid((int64_t)1 << (3 * l)));
+        const size_t lds = m2m_lds(ns);
+        if (T == 1) hipLaunchKernelGGL(m2m_kernel<1>, g, dim3(kFBlock), lds, st, a, l);
+        else if (T == 2) hipLaunchKernelGGL(m2m_kernel<2>, g, dim3(kFBlock), lds, st, a, l);
+        else hipLaunchKernelGGL(m2m_kernel<3>, g, dim3(kFBlock), lds, st, a, l);
+    }
+    const size_t lds2 = m2l_lds(ns);
+    for (int l = 2; l <= D && chk(); ++l) {
+        const dim3 g(f_grid((int64_t)1 << (3 * l)));
+        if (T == 1) hipLaunchKernelGGL(m2l_kernel<1>, g, dim3(kFBlock), lds2, st, a, l);
+        else if (T == 2) hipLaunchKernelGGL(m2l_kernel<2>, g, dim3(kFBlock), lds2, st, a, l);
+        else hipLaunchKernelGGL(m2l_kernel<3>, g, dim3(kFBlock), lds2, st, a, l);
+    }
+    if (chk()) {
+        const NearArgs na{items, n_items};
+        const dim3 g(f_grid(L.max_items));
+        if (dl) hipLaunchKernelGGL(near_kernel<1>, g, dim3(kWave), 0, st, a, na);
+        else hipLaunchKernelGGL(near_kernel<0>, g, dim3(kWave), 0, st, a, na);
     }
     chk();
     return e;
