@@ -43,6 +43,13 @@ struct stokes_fmm_plan {
     double* d_surf = nullptr;   // (ns, 3)
     double* d_upT = nullptr;    // (3ns, 3ns), transposed: upT[k * 3ns + r] = UP[r][k]
     double* d_downT = nullptr;
+    // M2L as GEMMs: rows padded to mp, K blocks of kb (3ns densities, the
+    // point-source flux, zero padding); see m2l_matrix_kernel
+    int mp = 0, kb = 0;
+    double* d_m2l = nullptr;    // (8 classes, kM2LBlocks, kb, mp)
+    int32_t* d_il = nullptr;    // (8 classes, kILSize, 3) interaction-list offsets
+    double* d_downA = nullptr;  // (mp, mp): downA[k * mp + r] = DOWN[r][k], zero padded
+    double* d_upA = nullptr;    // the same for UP
 };
 
 namespace stokes {
@@ -137,6 +144,9 @@ struct FmmDev {
     double pref;
     int accumulate;
     double* out;
+    double* vbuf;              // check vectors times h, one column of mp per listed box
+    const int64_t* pos;        // column of each box of the current level (upward pass)
+    int mp;
 };
 
 __device__ __forceinline__ void box_centre(const FmmDev& a, int l, uint64_t b, double* ctr, double& h) {
@@ -274,19 +284,14 @@ __device__ __forceinline__ void load_surface(const FmmDev& a, double* surf) {
     __syncthreads();
 }
 
-// Adds the four waves' partial check vectors in a fixed order, then
-// out = h * op * v, op stored transposed (column k contiguous over rows).
-__device__ __forceinline__ void finish(const FmmDev& a, const double* part, double* v, const double* opT, double h,
-                                       double* out) {
+// Adds the four waves' partial check vectors in a fixed order and stores h
+// times the sum, zero-padded to mp rows, as the box's column of the level's
+// check matrix; the pseudo-inverse is then applied to all columns at once.
+__device__ __forceinline__ void store_check(const FmmDev& a, const double* part, double h, int64_t col) {
     __syncthreads();
-    for (int r = threadIdx.x; r < a.n3; r += kFBlock)
-        v[r] = ((part[r] + part[a.n3 + r]) + part[2 * a.n3 + r]) + part[3 * a.n3 + r];
-    __syncthreads();
-    for (int r = threadIdx.x; r < a.n3; r += kFBlock) {
-        double s = 0.0;
-        for (int k = 0; k < a.n3; ++k) s = fma(opT[(int64_t)k * a.n3 + r], v[k], s);
-        out[r] = h * s;
-    }
+    double* v = a.vbuf + col * a.mp;
+    for (int r = threadIdx.x; r < a.mp; r += kFBlock)
+        v[r] = r < a.n3 ? h * (((part[r] + part[a.n3 + r]) + part[2 * a.n3 + r]) + part[3 * a.n3 + r]) : 0.0;
     __syncthreads();
 }
 
@@ -307,7 +312,7 @@ __device__ __forceinline__ double leaf_flux(const FmmDev& a, int64_t m0, int64_t
 }
 
 constexpr int kMaxNs = 6 * (kFmmMaxOrder - 1) * (kFmmMaxOrder - 1) + 2;
-static_assert(kMaxNs <= 3 * kWave, "m2l_kernel holds at most three check points per lane");
+static_assert(kMaxNs <= 3 * kWave, "the surface kernels hold at most three check points per lane");
 
 // Writes one box's surface sources (centre ctr, radius scale: points
 // ctr + scale * template, strengths dens) into a wave's LDS slice.
@@ -351,94 +356,6 @@ __device__ __forceinline__ void store_partial(const FmmDev& a, double* part, int
         if (cp < a.ns)
 #pragma unroll
             for (int c = 0; c < 3; ++c) part[wave * a.n3 + 3 * cp + c] = u[k][c];
-    }
-}
-
-// Dynamic LDS of the M2L kernel, in doubles: the template, then one staging
-// slice of ns records per wave, which the partial check vectors and their sum
-// reuse once every wave is done with its sources.
-size_t m2l_lds(int ns) {
-    const size_t stage = (size_t)kFWaves * ns * (sizeof(SrcSL64) / sizeof(double));
-    const size_t part = (size_t)(kFWaves + 1) * 3 * ns;
-    return ((size_t)((3 * ns + 1) & ~1) + std::max(stage, part)) * sizeof(double);
-}
-
-// M2L from the interaction list, plus L2L from the parent (levels > 2), then
-// the downward equivalent density.  Only boxes holding targets.  Lane j holds
-// check points j, j + 64, ... (T of them) in registers; wave w takes every
-// fourth interaction-list box, stages its equivalent sources in its own LDS
-// slice and reads them back by broadcast.
-template <int T>
-__global__ __launch_bounds__(kFBlock) void m2l_kernel(FmmDev a, int l) {
-    extern __shared__ double sh[];
-    double* surf = sh;
-    double* rest = surf + ((3 * a.ns + 1) & ~1);               // 16-byte aligned
-    SrcSL64* stage = reinterpret_cast<SrcSL64*>(rest);
-    double* part = rest;
-    double* v = part + kFWaves * a.n3;
-    load_surface(a, surf);
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    SrcSL64* mine = stage + wave * a.ns;
-    const int64_t nb = (int64_t)1 << (3 * l), np = (int64_t)1 << (l - 1);
-    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        if (!a.tpr[a.base[l] + b]) continue;                      // uniform over the workgroup
-        double ctr[3], h;
-        box_centre(a, l, b, ctr, h);
-        const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
-        const uint64_t p = b >> 3;
-        const int64_t pidx[3] = {compact3(p), compact3(p >> 1), compact3(p >> 2)};
-        double x[T][3], u[T][3];
-        check_points<T>(a, surf, ctr, kAlphaDC * h, lane, x, u);
-        int item = 0;
-        for (int dx = -1; dx <= 1; ++dx)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dz = -1; dz <= 1; ++dz) {
-                    const int64_t pn[3] = {pidx[0] + dx, pidx[1] + dy, pidx[2] + dz};
-                    if (pn[0] < 0 || pn[1] < 0 || pn[2] < 0 || pn[0] >= np || pn[1] >= np || pn[2] >= np) continue;
-                    for (int o = 0; o < 8; ++o) {
-                        const int64_t ai[3] = {2 * pn[0] + (o & 1), 2 * pn[1] + ((o >> 1) & 1), 2 * pn[2] + (o >> 2)};
-                        if (llabs(ai[0] - idx[0]) <= 1 && llabs(ai[1] - idx[1]) <= 1 && llabs(ai[2] - idx[2]) <= 1)
-                            continue;                      // a neighbour: near field
-                        const uint64_t ab = morton(ai[0], ai[1], ai[2]);
-                        if (!a.snz[a.base[l] + ab]) continue;
-                        if (item++ % kFWaves != wave) continue;
-                        double ac[3], ha;
-                        box_centre(a, l, ab, ac, ha);
-                        if (a.sig) {
-                            const double sg = a.sig[a.base[l] + ab];
-#pragma unroll
-                            for (int k = 0; k < T; ++k)
-                                point_source(x[k][0] - ac[0], x[k][1] - ac[1], x[k][2] - ac[2], sg, u[k]);
-                        }
-                        stage_surface(a, surf, ac, kAlphaUE * ha, a.ue + (a.base[l] + ab) * a.n3, mine, lane);
-                        __builtin_amdgcn_wave_barrier();
-#pragma unroll 2
-                        for (int j = 0; j < a.ns; ++j) {
-                            const SrcSL64 sr = mine[j];
-#pragma unroll
-                            for (int k = 0; k < T; ++k)
-                                sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz,
-                                               u[k]);
-                        }
-                        __builtin_amdgcn_wave_barrier();   // reads of this box precede the next writes
-                    }
-                }
-        if (l > 2 && item++ % kFWaves == wave) {
-            double pc[3], hp;
-            box_centre(a, l - 1, p, pc, hp);
-            stage_surface(a, surf, pc, kAlphaDE * hp, a.de + (a.base[l - 1] + p) * a.n3, mine, lane);
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll 2
-            for (int j = 0; j < a.ns; ++j) {
-                const SrcSL64 sr = mine[j];
-#pragma unroll
-                for (int k = 0; k < T; ++k)
-                    sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz, u[k]);
-            }
-        }
-        __syncthreads();                           // the partial vectors overwrite the staging slices
-        store_partial<T>(a, part, wave, lane, u);
-        finish(a, part, v, a.downT, h, a.de + (a.base[l] + b) * a.n3);
     }
 }
 
@@ -497,16 +414,15 @@ __device__ __forceinline__ void near_pair(const typename NearRec<KT>::type& s, d
 }
 
 // Dynamic LDS of P2M, in doubles: the template, a workgroup tile of source
-// records, the four partial check vectors and their sum.
+// records, the four partial check vectors.
 size_t p2m_lds(int ns, int KT) {
     const size_t rec = KT ? sizeof(SrcDL64) : sizeof(SrcSL64);
-    return ((size_t)((3 * ns + 1) & ~1) + kFBlock * rec / sizeof(double) + (size_t)(kFWaves + 1) * 3 * ns) *
-           sizeof(double);
+    return ((size_t)((3 * ns + 1) & ~1) + kFBlock * rec / sizeof(double) + (size_t)kFWaves * 3 * ns) * sizeof(double);
 }
 // ... of M2M: the template, one staging slice per wave, the partial vectors.
 size_t m2m_lds(int ns) {
     return ((size_t)((3 * ns + 1) & ~1) + (size_t)kFWaves * ns * (sizeof(SrcSL64) / sizeof(double)) +
-            (size_t)(kFWaves + 1) * 3 * ns) *
+            (size_t)kFWaves * 3 * ns) *
            sizeof(double);
 }
 
@@ -520,15 +436,12 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
     double* surf = sh;
     Rec* tile = reinterpret_cast<Rec*>(surf + ((3 * a.ns + 1) & ~1));
     double* part = reinterpret_cast<double*>(tile + kFBlock);
-    double* v = part + kFWaves * a.n3;
     __shared__ double red[kFWaves];
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int64_t nl = (int64_t)1 << (3 * a.D);
     for (int64_t b = blockIdx.x; b < nl; b += gridDim.x) {            // uniform over the workgroup
-        double* out = a.ue + (a.base[a.D] + b) * a.n3;
         if (!a.snz[a.base[a.D] + b]) {
-            for (int r = threadIdx.x; r < a.n3; r += kFBlock) out[r] = 0.0;
             if (KT == 1 && threadIdx.x == 0) a.sig[a.base[a.D] + b] = 0.0;
             continue;
         }
@@ -558,7 +471,7 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
             for (int k = 0; k < T; ++k)
                 point_source(x[k][0] - ctr[0], x[k][1] - ctr[1], x[k][2] - ctr[2], -sigma, u[k]);
         store_partial<T>(a, part, wave, lane, u);
-        finish(a, part, v, a.upT, h, out);
+        store_check(a, part, h, a.pos[b]);
     }
 }
 
@@ -570,15 +483,12 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
     double* surf = sh;
     SrcSL64* stage = reinterpret_cast<SrcSL64*>(surf + ((3 * a.ns + 1) & ~1));
     double* part = reinterpret_cast<double*>(stage + kFWaves * a.ns);
-    double* v = part + kFWaves * a.n3;
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     SrcSL64* mine = stage + wave * a.ns;
     const int64_t nb = (int64_t)1 << (3 * l);
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        double* out = a.ue + (a.base[l] + b) * a.n3;
         if (!a.snz[a.base[l] + b]) {
-            for (int r = threadIdx.x; r < a.n3; r += kFBlock) out[r] = 0.0;
             if (a.sig && threadIdx.x == 0) a.sig[a.base[l] + b] = 0.0;
             continue;
         }
@@ -616,7 +526,7 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
             __builtin_amdgcn_wave_barrier();   // reads of this child precede the next writes
         }
         store_partial<T>(a, part, wave, lane, u);
-        finish(a, part, v, a.upT, h, out);
+        store_check(a, part, h, a.pos[b]);
     }
 }
 
@@ -769,16 +679,386 @@ __global__ __launch_bounds__(kFBlock) void items_kernel(const int64_t* __restric
 // most one partial chunk to the full ones.
 int64_t max_items(int64_t n_trg, int64_t n_leaves) { return (n_trg + kWave - 1) / kWave + std::min(n_trg, n_leaves); }
 
+// ---------------------------------------------------------------------------
+// M2L as dense products on the FP64 matrix cores.
+//
+// A target box's position in its parent (octant class c = b & 7 of its
+// Morton index) fixes its interaction list: 189 offsets o (source box minus
+// target box, in units of the box width), the same for every box of the class
+// and level.  For a unit box (half-width 1) the velocity at the downward check
+// points of the target from the upward equivalent density e of the source box
+// at offset o is M_o e, M_o a (3ns x 3ns) kernel matrix.  The kernel is
+// homogeneous of degree -1, so at level l the check velocity is M_o e / h_l.
+// Per class the plan stores A_c = [M_o1 ... M_o189 | L2L], each block with one
+// more column, the velocity of a unit point source at the source box centre
+// (the double layer's flux term; that entry of the gathered vector is
+// sigma / h), and padded to kb columns; the last block maps the parent's
+// downward equivalent density (radius 2.95 * 2h, centre offset -(2c - 1))
+// to the check points.  Then per level and class the check vectors times h are
+// V = A_c E, E gathered from the per-box densities, and the downward density
+// is DOWN V (the h cancels).  Both products run as FP64 MFMA 16x16x4 tiles of
+// 32 boxes: A read directly from memory in the MFMA operand layout, E staged
+// through LDS in chunks of 16 K rows (double-buffered).  Workgroup w takes
+// class w & 7: consecutive workgroups are dealt round-robin to the eight
+// XCDs, so each class's A_c stays in one XCD's L2.
+constexpr int kILSize = 189;
+constexpr int kM2LBlocks = kILSize + 1;
+constexpr int kGemmNT = 64;          // boxes per tile
+constexpr int kGemmKC = 8;           // K rows per LDS chunk (2 MFMA steps)
+constexpr int kGemmThreads = 512;    // 8 waves: 4 column groups x 2 row halves
+constexpr int kM2LUnits = 4096;      // work units a level's M2L aims for (K is split to reach them)
+constexpr int kM2LMinSplits = 3;     // so that a split has at most kM2LMaxSplitBlocks blocks
+constexpr int kM2LMaxSplitBlocks = (kILSize + 1 + kM2LMinSplits - 1) / kM2LMinSplits;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+int pad16(int v) { return (v + 15) / 16 * 16; }
+
+// Interaction-list offsets of class c, in the order of the enumeration:
+// neighbours d of the parent (x slowest), then their children o.
+void il_offsets(int c, std::vector<int32_t>& out) {
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int o = 0; o < 8; ++o) {
+                    const int ox = 2 * dx + (o & 1) - cx, oy = 2 * dy + ((o >> 1) & 1) - cy,
+                              oz = 2 * dz + (o >> 2) - cz;
+                    if (std::abs(ox) <= 1 && std::abs(oy) <= 1 && std::abs(oz) <= 1) continue;
+                    out.push_back(ox);
+                    out.push_back(oy);
+                    out.push_back(oz);
+                }
+}
+
+// One thread per (class, block, check point, source point or the flux column):
+// the 3 x 3 kernel block (or 3 x 1 point-source column) of A_c.
+__global__ __launch_bounds__(kFBlock) void m2l_matrix_kernel(const double* __restrict__ surf, int ns, int mp, int kb,
+                                                             const int32_t* __restrict__ il, double* __restrict__ A) {
+    const int64_t per_block = (int64_t)ns * (ns + 1);
+    const int64_t total = 8 * kM2LBlocks * per_block;
+    for (int64_t t = (int64_t)blockIdx.x * kFBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kFBlock) {
+        const int c = (int)(t / (kM2LBlocks * per_block));
+        const int blk = (int)(t / per_block % kM2LBlocks);
+        const int cp = (int)(t % per_block / (ns + 1)), k = (int)(t % (ns + 1));
+        double ctr[3], scale;
+        if (blk < kILSize) {
+            for (int d = 0; d < 3; ++d) ctr[d] = 2.0 * il[(c * kILSize + blk) * 3 + d];
+            scale = kAlphaUE;
+        } else {
+            for (int d = 0; d < 3; ++d) ctr[d] = -(2.0 * ((c >> d) & 1) - 1.0);
+            scale = 2.0 * kAlphaDE;
+        }
+        double x[3], r[3];
+        for (int d = 0; d < 3; ++d) x[d] = kAlphaDC * surf[3 * cp + d];
+        double* col = A + ((int64_t)c * kM2LBlocks + blk) * kb * mp;   // column kk at col + kk * mp
+        if (k < ns) {
+            for (int d = 0; d < 3; ++d) r[d] = x[d] - (ctr[d] + scale * surf[3 * k + d]);
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double ri = 1.0 / sqrt(r2), ri3 = ri * ri * ri;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    col[(int64_t)(3 * k + b) * mp + 3 * cp + a] = (a == b ? ri : 0.0) + r[a] * r[b] * ri3;
+        } else if (blk < kILSize) {
+            for (int d = 0; d < 3; ++d) r[d] = x[d] - ctr[d];
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double ri = 1.0 / sqrt(r2);
+            for (int a = 0; a < 3; ++a) col[(int64_t)(3 * ns) * mp + 3 * cp + a] = 2.0 * r[a] * (ri * ri * ri);
+        }
+    }
+}
+
+// C(:, j) = A B(:, j) for the 64 columns of a tile, over the K chunks
+// chunk(0) .. chunk(n - 1) of kGemmKC rows each.  A: K x mp, k-major
+// (A[k * mp + row]), mp = 16 RB.  Each chunk of A and of B goes through LDS,
+// the next one prefetched into registers while the current one is multiplied.
+// loadb(q, j, k) gives row k of chunk q for column j; busy(t, g) is false when
+// chunk t is zero for all 16 columns of group g (that wave skips its
+// products).  Eight waves: wave w
+// owns columns 16 (w & 3) .. + 15 and row blocks (w >> 2) H .. + H - 1,
+// H = ceil(RB / 2); acc[i] holds row block (w >> 2) H + i, lane l, entry r
+// being row (l >> 4) + 4 r and column 16 (w & 3) + (l & 15).
+template <int RB> struct GemmShape {
+    static constexpr int mp = 16 * RB, H = (RB + 1) / 2, na = kGemmKC * mp;
+    static constexpr int APT = (na + kGemmThreads - 1) / kGemmThreads;
+};
+
+// C(:, j) = A B(:, j) for the 64 columns of a tile, over the K chunks
+// chunk(0) .. chunk(n - 1) of kGemmKC rows each, then store(j, row, value)
+// for the rows < nrow.  A: K x mp, k-major (A[k * mp + row]), mp = 16 RB.
+// Each chunk of A and of B goes through LDS (two buffers); chunk t + 2 is in
+// flight in registers while chunk t is multiplied.  loadb(q, j, k)
+// gives row k of chunk q for column j; busy(t, g) is false when chunk t is
+// zero for all 16 columns of group g (that wave skips its products).  Eight
+// waves: wave w owns columns 16 (w & 3) .. + 15 and the NR row blocks from
+// (w >> 2) H, H = ceil(RB / 2) (NR = H for the lower half, RB - H for the
+// upper: the caller picks the instance with a wave-uniform branch).  acc[i]
+// holds row block (w >> 2) H + i; lane l, entry r is row (l >> 4) + 4 r and
+// column 16 (w & 3) + (l & 15).
+template <int RB, int NR, typename Chunk, typename LoadB, typename Busy, typename Store>
+__device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t n, Chunk&& chunk, LoadB&& loadb,
+                                          Busy&& busy, double* As, double* Bs, int nrow, Store&& store) {
+    using G = GemmShape<RB>;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int cg = wave & 3, rb0 = (wave >> 2) * G::H;
+    const int bj = tid >> 3, bk = tid & 7;                   // one B value per thread
+    v4d acc[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+    double pa[G::APT], pb = 0.0;
+    auto fetch = [&](int64_t t) {
+        const int64_t q = chunk(t);
+        const double* Aq = A + q * G::na;
+#pragma unroll
+        for (int i = 0; i < G::APT; ++i) {
+            const int e = tid + i * kGemmThreads;
+            pa[i] = e < G::na ? Aq[e] : 0.0;
+        }
+        pb = loadb(q, bj, bk);
+    };
+    auto put = [&](int buf) {
+        double* Ab = As + buf * G::na;
+#pragma unroll
+        for (int i = 0; i < G::APT; ++i) {
+            const int e = tid + i * kGemmThreads;
+            if (e < G::na) Ab[e] = pa[i];
+        }
+        Bs[buf * (kGemmKC * kGemmNT) + bk * kGemmNT + bj] = pb;
+    };
+    auto multiply = [&](int64_t t) {
+        if (!busy(t, cg)) return;                                 // uniform over the wave
+        const double* Ab = As + (t & 1) * G::na;
+        const double* Bb = Bs + (t & 1) * (kGemmKC * kGemmNT);
+#pragma unroll
+        for (int st = 0; st < kGemmKC / 4; ++st) {
+            const int kr = 4 * st + (lane >> 4);
+            const double bv = Bb[kr * kGemmNT + 16 * cg + (lane & 15)];
+            double av[NR];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) av[i] = Ab[kr * G::mp + 16 * (rb0 + i) + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < NR; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv, acc[i], 0, 0, 0);
+        }
+    };
+    // LDS holds chunks t and t + 1 (buffers t & 1 and its pair); the registers
+    // hold chunk t + 2, fetched while chunk t is multiplied
+    if (n > 0) {
+        fetch(0);
+        put(0);
+    }
+    if (n > 1) {
+        fetch(1);
+        put(1);
+    }
+    if (n > 2) fetch(2);
+    __syncthreads();
+    for (int64_t t = 0; t < n; ++t) {
+        multiply(t);
+        __syncthreads();                                          // every wave is done with buffer t & 1
+        if (t + 2 < n) {
+            // chunk t + 2 into the freed buffer: it is read after the next
+            // iteration's barrier
+            put((int)(t & 1));
+            if (t + 3 < n) fetch(t + 3);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (rb0 + i) + (lane >> 4) + 4 * r;
+            if (row < nrow) store(16 * cg + (lane & 15), row, acc[i][r]);
+        }
+}
+
+// Runs gemm_tile with the row-block count of this wave's half (a scalar branch).
+template <int RB, typename Chunk, typename LoadB, typename Busy, typename Store>
+__device__ __forceinline__ void gemm_tile_any(const double* __restrict__ A, int64_t n, Chunk&& chunk, LoadB&& loadb,
+                                              Busy&& busy, double* As, double* Bs, int nrow, Store&& store) {
+    using G = GemmShape<RB>;
+    if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave) >> 2) != 0)
+        gemm_tile<RB, RB - G::H>(A, n, chunk, loadb, busy, As, Bs, nrow, store);
+    else
+        gemm_tile<RB, G::H>(A, n, chunk, loadb, busy, As, Bs, nrow, store);
+}
+
+struct M2LArgs {
+    const double* A;           // plan's class matrices
+    const int32_t* il;
+    const double* downA;
+    int mp, kb;
+    const int64_t* cscan;      // exclusive scan of the class-major target flags (8 * 8^(l-1))
+    const int64_t* ctotal;     // number of listed boxes
+    const int32_t* list;       // target boxes of the level, grouped by class
+    int64_t* sched;            // [0]: K splits of this level
+    double* vbuf;              // (splits, listed boxes, mp): partial check vectors times h
+};
+
+// Class-major "holds targets" flags of level l: slot (b & 7) * 8^(l-1) + (b >> 3).
+__global__ __launch_bounds__(kFBlock) void class_flags_kernel(FmmDev a, int l, int64_t* __restrict__ f) {
+    const int64_t nb = (int64_t)1 << (3 * l), P = nb >> 3;
+    for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
+        f[(b & 7) * P + (b >> 3)] = a.tpr[a.base[l] + b] ? 1 : 0;
+}
+__global__ __launch_bounds__(kFBlock) void class_list_kernel(FmmDev a, int l, const int64_t* __restrict__ scan,
+                                                             int32_t* __restrict__ list) {
+    const int64_t nb = (int64_t)1 << (3 * l), P = nb >> 3;
+    for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
+        if (a.tpr[a.base[l] + b]) list[scan[(b & 7) * P + (b >> 3)]] = (int32_t)b;
+}
+
+// K splits of a level: enough work units for the whole chip, at most one
+// K block each.
+__global__ void m2l_sched_kernel(const int64_t* __restrict__ cscan, const int64_t* __restrict__ ctotal, int l,
+                                 int64_t* __restrict__ sched) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t P = (int64_t)1 << (3 * (l - 1));
+    int64_t tiles = 0;
+    for (int c = 0; c < 8; ++c) {
+        const int64_t n = (c < 7 ? cscan[(c + 1) * P] : *ctotal) - cscan[c * P];
+        tiles += (n + kGemmNT - 1) / kGemmNT;
+    }
+    int64_t S = tiles > 0 ? (kM2LUnits + tiles - 1) / tiles : 1;
+    sched[0] = S < kM2LMinSplits ? kM2LMinSplits : (S > kM2LBlocks ? kM2LBlocks : S);
+}
+
+// Partial V = A_c E over K split `split` for one tile of 64 listed boxes of
+// class blockIdx.x & 7 (unit blockIdx.x >> 3 = split * tiles + tile).  K
+// blocks whose source box is missing for all 64 columns are skipped.
+template <int RB>
+__global__ __launch_bounds__(kGemmThreads) void m2l_gemm_kernel(FmmDev a, M2LArgs g, int l) {
+    using G = GemmShape<RB>;
+    __shared__ double As[2 * G::na];
+    __shared__ double Bs[2 * kGemmKC * kGemmNT];
+    __shared__ int32_t s_act[kM2LMaxSplitBlocks + 1];          // active blocks of this split, then the count
+    __shared__ int32_t s_src[kM2LMaxSplitBlocks][kGemmNT];     // their source boxes per column (-1: none)
+    __shared__ uint8_t s_grp[kM2LMaxSplitBlocks][kGemmNT / 16]; // any source among 16 columns
+    const int c = blockIdx.x & 7;
+    const int64_t u = blockIdx.x >> 3, P = (int64_t)1 << (3 * (l - 1));
+    const int64_t S = g.sched[0];
+    const int64_t c0 = g.cscan[c * P], c1 = c < 7 ? g.cscan[(c + 1) * P] : *g.ctotal;
+    const int64_t tiles = (c1 - c0 + kGemmNT - 1) / kGemmNT;
+    // split-major: the tiles running together on one XCD share one slice of A_c in its L2
+    const int64_t split = tiles > 0 ? u / tiles : S, tile = tiles > 0 ? u % tiles : 0;
+    if (split >= S) return;                                    // uniform over the workgroup
+    const int64_t col0 = c0 + tile * kGemmNT;
+    const int blk0 = (int)(split * kM2LBlocks / S), blk1 = (int)((split + 1) * kM2LBlocks / S);
+    const int64_t nbx = (int64_t)1 << l;
+    const int32_t* il = g.il + c * kILSize * 3;
+    // source box of block blk for column j (-1: none); the last block is the
+    // parent's L2L, present from level 3 on
+    auto source = [&](int blk, int j) -> int64_t {
+        if (col0 + j >= c1) return -1;
+        const int64_t b = g.list[col0 + j];
+        if (blk == kILSize) return l > 2 ? (b >> 3) : -1;
+        const int64_t ai[3] = {compact3(b) + il[3 * blk], compact3(b >> 1) + il[3 * blk + 1],
+                               compact3(b >> 2) + il[3 * blk + 2]};
+        if (ai[0] < 0 || ai[1] < 0 || ai[2] < 0 || ai[0] >= nbx || ai[1] >= nbx || ai[2] >= nbx) return -1;
+        const int64_t box = (int64_t)morton(ai[0], ai[1], ai[2]);
+        return a.snz[a.base[l] + box] ? box : -1;
+    };
+    {
+        const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+        for (int blk = blk0 + wave; blk < blk1; blk += kGemmThreads / kWave) {   // lane = column
+            const int64_t src = source(blk, lane);
+            s_src[blk - blk0][lane] = (int32_t)src;
+            const uint64_t m = __ballot(src >= 0);
+            if (lane == 0) {
+                s_act[blk - blk0] = m != 0 ? 1 : 0;
+                for (int gq = 0; gq < kGemmNT / 16; ++gq) s_grp[blk - blk0][gq] = ((m >> (16 * gq)) & 0xffffull) != 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {                                    // active blocks (relative to blk0), in order
+        int n = 0;
+        for (int k = 0; k < blk1 - blk0; ++k)
+            if (s_act[k]) s_act[n++] = k;
+        s_act[kM2LMaxSplitBlocks] = n;
+    }
+    __syncthreads();
+    const int nact = s_act[kM2LMaxSplitBlocks];
+    constexpr int cpb = G::mp / kGemmKC;                       // chunks per K block (the plan has kb == mp)
+    const double inv_h = (double)(1 << l) / a.R;
+    auto chunk = [&](int64_t t) {
+        const int ti = (int)t;
+        return (int64_t)(blk0 + s_act[ti / cpb]) * cpb + ti % cpb;
+    };
+    auto busy = [&](int64_t t, int gq) { return s_grp[s_act[(int)t / cpb]][gq] != 0; };
+    auto loadb = [&](int64_t q, int j, int bk) -> double {
+        const int qi = (int)q, blk = qi / cpb, kk = (qi % cpb) * kGemmKC + bk;
+        const int32_t src = s_src[blk - blk0][j];
+        if (src < 0) return 0.0;
+        if (blk == kILSize) return kk < a.n3 ? a.de[(a.base[l - 1] + src) * a.n3 + kk] : 0.0;
+        const int64_t box = a.base[l] + src;
+        if (kk < a.n3) return a.ue[box * a.n3 + kk];
+        return (kk == a.n3 && a.sig) ? a.sig[box] * inv_h : 0.0;
+    };
+    const int64_t listed = *g.ctotal;
+    double* part = g.vbuf + split * listed * G::mp;
+    gemm_tile_any<RB>(g.A + (int64_t)c * kM2LBlocks * G::mp * G::mp, (int64_t)nact * cpb, chunk, loadb, busy, As, Bs,
+                      G::mp, [&](int j, int row, double v) {
+                          if (col0 + j < c1) part[(col0 + j) * G::mp + row] = v;
+                      });
+}
+
+// Adds the K-split partials of every listed box into split 0, in split order.
+__global__ __launch_bounds__(kFBlock) void m2l_reduce_kernel(M2LArgs g) {
+    const int64_t n = *g.ctotal * g.mp, S = g.sched[0];
+    for (int64_t e = (int64_t)blockIdx.x * kFBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kFBlock) {
+        double v = g.vbuf[e];
+        for (int64_t sp = 1; sp < S; ++sp) v += g.vbuf[sp * n + e];
+        g.vbuf[e] = v;
+    }
+}
+
+// out[list[j]] = OP V(:, j) for the listed boxes (OP padded to mp x mp,
+// k-major; out rows n3 per box): the pseudo-inverse of a whole level.
+template <int RB>
+__global__ __launch_bounds__(kGemmThreads) void apply_gemm_kernel(FmmDev a, M2LArgs g, const double* __restrict__ op,
+                                                                  double* __restrict__ out) {
+    using G = GemmShape<RB>;
+    __shared__ double As[2 * G::na];
+    __shared__ double Bs[2 * kGemmKC * kGemmNT];
+    const int64_t n = *g.ctotal;
+    const int64_t col0 = (int64_t)blockIdx.x * kGemmNT;
+    if (col0 >= n) return;
+    auto chunk = [](int64_t t) { return t; };
+    auto loadb = [&](int64_t q, int j, int bk) -> double {
+        return col0 + j < n ? g.vbuf[(col0 + j) * G::mp + q * kGemmKC + bk] : 0.0;
+    };
+    auto busy = [](int64_t, int) { return true; };
+    const int32_t* list = g.list;
+    gemm_tile_any<RB>(op, G::mp / kGemmKC, chunk, loadb, busy, As, Bs, a.n3, [&](int j, int row, double v) {
+        if (col0 + j < n) out[(int64_t)list[col0 + j] * a.n3 + row] = v;
+    });
+}
+
+// Boxes of level l that hold sources, in index order: flags, then (after a
+// scan) the list.
+__global__ __launch_bounds__(kFBlock) void src_flags_kernel(FmmDev a, int l, int64_t* __restrict__ f) {
+    const int64_t nb = (int64_t)1 << (3 * l);
+    for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
+        f[b] = a.snz[a.base[l] + b] ? 1 : 0;
+}
+__global__ __launch_bounds__(kFBlock) void src_list_kernel(FmmDev a, int l, const int64_t* __restrict__ scan,
+                                                           int32_t* __restrict__ list) {
+    const int64_t nb = (int64_t)1 << (3 * l);
+    for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
+        if (a.snz[a.base[l] + b]) list[scan[b]] = (int32_t)b;
+}
+
 struct FmmLayout {
     int64_t nbox = 0, n_leaves = 0;
     int64_t base[kFmmMaxDepth + 2] = {};
     SortLayout sort;
     int64_t max_items = 0;
     size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_sn, off_tx, off_sofs, off_tofs,
-        off_snz, off_tpr, off_sig, off_ue, off_de, off_cofs, off_scan, off_items, off_nitems, total;
+        off_snz, off_tpr, off_sig, off_ue, off_de, off_cofs, off_scan, off_items, off_nitems, off_cflag, off_cscan,
+        off_ctotal, off_clist, off_sched, off_vbuf, total;
 };
 
 FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
+    const int mp = pad16(3 * ns);
     FmmLayout L;
     int64_t acc = 0;
     for (int l = 2; l <= D; ++l) {
@@ -815,6 +1095,15 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_scan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
     L.off_items = take((size_t)L.max_items * 2 * 4);
     L.off_nitems = take(8);
+    L.off_cflag = take((size_t)L.n_leaves * 8);
+    L.off_cscan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
+    L.off_ctotal = take(8);
+    L.off_clist = take((size_t)L.n_leaves * 4);
+    L.off_sched = take(8);
+    // K-split partials: splits x listed boxes <= 3 listed + 64 (units + 8)
+    L.off_vbuf = take((size_t)(kM2LMinSplits * std::min(L.n_leaves, std::max<int64_t>({n_src, n_trg, 1})) +
+                               kGemmNT * (kM2LUnits + 8)) *
+                      mp * 8);
     L.total = off;
     return L;
 }
@@ -915,6 +1204,44 @@ int fmm_plan_build(int device, int order, stokes_fmm_plan** out, std::string& er
         err = "device allocation or copy failed";
         return -2;
     }
+    // M2L class matrices (built on the device) and the padded DOWN operator
+    const int mp = pad16(n3), kb = pad16(n3 + 1);
+    p->mp = mp;
+    p->kb = kb;
+    if (kb != mp) {                    // 3 ns is never a multiple of 16 for orders 2..6
+        fmm_plan_free(p);
+        err = "internal: M2L block size";
+        return -2;
+    }
+    std::vector<int32_t> il;
+    for (int c = 0; c < 8; ++c) il_offsets(c, il);
+    std::vector<double> downA((size_t)mp * mp, 0.0), upA((size_t)mp * mp, 0.0);
+    for (int r = 0; r < n3; ++r)
+        for (int k = 0; k < n3; ++k) {
+            downA[(size_t)k * mp + r] = down[(size_t)r * n3 + k];
+            upA[(size_t)k * mp + r] = up[(size_t)r * n3 + k];
+        }
+    const size_t ab = (size_t)8 * kM2LBlocks * kb * mp * 8;
+    hipError_t e = hipMalloc(&p->d_m2l, ab);
+    if (e == hipSuccess) e = hipMalloc(&p->d_il, il.size() * 4);
+    if (e == hipSuccess) e = hipMalloc(&p->d_downA, downA.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&p->d_upA, upA.size() * 8);
+    if (e == hipSuccess) e = hipMemcpy(p->d_upA, upA.data(), upA.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_il, il.data(), il.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_downA, downA.data(), downA.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->d_m2l, 0, ab);
+    if (e == hipSuccess) {
+        const int64_t work = (int64_t)8 * kM2LBlocks * ns * (ns + 1);
+        hipLaunchKernelGGL(m2l_matrix_kernel, dim3(f_grid((work + kFBlock - 1) / kFBlock)), dim3(kFBlock), 0, 0,
+                           p->d_surf, ns, mp, kb, p->d_il, p->d_m2l);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess || (int)il.size() != 8 * kILSize * 3) {
+        fmm_plan_free(p);
+        err = "M2L operators: " + std::string(e != hipSuccess ? hipGetErrorString(e) : "interaction list size");
+        return -2;
+    }
     *out = p;
     return 0;
 }
@@ -924,6 +1251,10 @@ void fmm_plan_free(stokes_fmm_plan* p) {
     (void)hipFree(p->d_surf);
     (void)hipFree(p->d_upT);
     (void)hipFree(p->d_downT);
+    (void)hipFree(p->d_m2l);
+    (void)hipFree(p->d_il);
+    (void)hipFree(p->d_downA);
+    (void)hipFree(p->d_upA);
     delete p;
 }
 
@@ -1022,7 +1353,50 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         if (e == hipSuccess)
             hipLaunchKernelGGL(items_kernel, dim3(gl), dim3(kFBlock), 0, st, a.tofs, cofs, L.n_leaves, items);
     }
-    if (chk()) {
+    M2LArgs g2{};
+    g2.A = plan->d_m2l;
+    g2.il = plan->d_il;
+    g2.downA = plan->d_downA;
+    g2.mp = plan->mp;
+    g2.kb = plan->kb;
+    g2.cscan = reinterpret_cast<int64_t*>(ws + L.off_cflag);
+    g2.ctotal = reinterpret_cast<int64_t*>(ws + L.off_ctotal);
+    g2.list = reinterpret_cast<int32_t*>(ws + L.off_clist);
+    g2.vbuf = reinterpret_cast<double*>(ws + L.off_vbuf);
+    g2.sched = reinterpret_cast<int64_t*>(ws + L.off_sched);
+    a.vbuf = g2.vbuf;
+    a.pos = g2.cscan;
+    a.mp = plan->mp;
+    const int rb = plan->mp / 16;
+    // OP V for the listed boxes of a level, into out (rows n3 per box)
+    auto apply = [&](int l, const double* op, double* out) {
+        const dim3 g((unsigned)((std::min<int64_t>((int64_t)1 << (3 * l), std::max(in.n_src, in.n_trg)) + kGemmNT - 1) /
+                                kGemmNT));
+        switch (rb) {
+            case 2: hipLaunchKernelGGL(apply_gemm_kernel<2>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
+            case 5: hipLaunchKernelGGL(apply_gemm_kernel<5>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
+            case 11: hipLaunchKernelGGL(apply_gemm_kernel<11>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
+            case 19: hipLaunchKernelGGL(apply_gemm_kernel<19>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
+            default: hipLaunchKernelGGL(apply_gemm_kernel<29>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
+        }
+        return chk();
+    };
+    // the boxes of level l holding sources: a.pos (column of each box) and the list
+    auto list_sources = [&](int l) {
+        const int64_t nb = (int64_t)1 << (3 * l);
+        const unsigned gb = f_grid((nb + kFBlock - 1) / kFBlock);
+        int64_t* f = const_cast<int64_t*>(g2.cscan);
+        hipLaunchKernelGGL(src_flags_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, f);
+        if (!chk()) return false;
+        e = exclusive_scan_i64(f, nb, f, reinterpret_cast<int64_t*>(ws + L.off_cscan), const_cast<int64_t*>(g2.ctotal),
+                               st);
+        if (e != hipSuccess) return false;
+        hipLaunchKernelGGL(src_list_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, g2.cscan,
+                           const_cast<int32_t*>(g2.list));
+        return chk();
+    };
+    // upward pass: check vectors per level, then the pseudo-inverse as one GEMM
+    if (chk() && list_sources(D)) {
         const dim3 g(f_grid(L.n_leaves));
         const size_t lds = p2m_lds(ns, dl ? 1 : 0);
         if (dl) {
@@ -1034,20 +1408,47 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
             else if (T == 2) hipLaunchKernelGGL((p2m_kernel<0, 2>), g, dim3(kFBlock), lds, st, a);
             else hipLaunchKernelGGL((p2m_kernel<0, 3>), g, dim3(kFBlock), lds, st, a);
         }
+        if (chk()) apply(D, plan->d_upA, a.ue + L.base[D] * a.n3);
     }
     for (int l = D - 1; l >= 2 && chk(); --l) {
+        if (!list_sources(l)) break;
         const dim3 g(f_grid((int64_t)1 << (3 * l)));
         const size_t lds = m2m_lds(ns);
         if (T == 1) hipLaunchKernelGGL(m2m_kernel<1>, g, dim3(kFBlock), lds, st, a, l);
         else if (T == 2) hipLaunchKernelGGL(m2m_kernel<2>, g, dim3(kFBlock), lds, st, a, l);
         else hipLaunchKernelGGL(m2m_kernel<3>, g, dim3(kFBlock), lds, st, a, l);
+        if (chk()) apply(l, plan->d_upA, a.ue + L.base[l] * a.n3);
     }
-    const size_t lds2 = m2l_lds(ns);
     for (int l = 2; l <= D && chk(); ++l) {
-        const dim3 g(f_grid((int64_t)1 << (3 * l)));
-        if (T == 1) hipLaunchKernelGGL(m2l_kernel<1>, g, dim3(kFBlock), lds2, st, a, l);
-        else if (T == 2) hipLaunchKernelGGL(m2l_kernel<2>, g, dim3(kFBlock), lds2, st, a, l);
-        else hipLaunchKernelGGL(m2l_kernel<3>, g, dim3(kFBlock), lds2, st, a, l);
+        const int64_t nb = (int64_t)1 << (3 * l);
+        const unsigned gb = f_grid((nb + kFBlock - 1) / kFBlock);
+        int64_t* cflag = const_cast<int64_t*>(g2.cscan);
+        hipLaunchKernelGGL(class_flags_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, cflag);
+        if (!chk()) break;
+        e = exclusive_scan_i64(cflag, nb, cflag, reinterpret_cast<int64_t*>(ws + L.off_cscan),
+                               const_cast<int64_t*>(g2.ctotal), st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(class_list_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, g2.cscan,
+                           const_cast<int32_t*>(g2.list));
+        if (!chk()) break;
+        hipLaunchKernelGGL(m2l_sched_kernel, dim3(1), dim3(kWave), 0, st, g2.cscan, g2.ctotal, l, g2.sched);
+        if (!chk()) break;
+        // per class at most min(8^(l-1), n_trg) boxes in `tiles` tiles; units per
+        // class = splits x tiles <= max(kM2LUnits + tiles, kM2LMinSplits x tiles)
+        const int64_t tiles = (std::min<int64_t>(nb >> 3, in.n_trg) + kGemmNT - 1) / kGemmNT;
+        const dim3 gm((unsigned)(8 * std::max<int64_t>(kM2LUnits + tiles, kM2LMinSplits * tiles)));
+        switch (rb) {
+            case 2: hipLaunchKernelGGL(m2l_gemm_kernel<2>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
+            case 5: hipLaunchKernelGGL(m2l_gemm_kernel<5>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
+            case 11: hipLaunchKernelGGL(m2l_gemm_kernel<11>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
+            case 19: hipLaunchKernelGGL(m2l_gemm_kernel<19>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
+            default: hipLaunchKernelGGL(m2l_gemm_kernel<29>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
+        }
+        if (!chk()) break;
+        hipLaunchKernelGGL(m2l_reduce_kernel, dim3(f_grid((std::min<int64_t>(nb, in.n_trg) * plan->mp + kFBlock - 1) / kFBlock)),
+                           dim3(kFBlock), 0, st, g2);
+        if (!chk()) break;
+        if (!apply(l, plan->d_downA, a.de + L.base[l] * a.n3)) break;
     }
     if (chk()) {
         const NearArgs na{items, n_items};
