@@ -707,6 +707,7 @@ constexpr int kGemmNT = 64;          // boxes per tile
 constexpr int kGemmKC = 8;           // K rows per LDS chunk (2 MFMA steps)
 constexpr int kGemmThreads = 512;    // 8 waves: 4 column groups x 2 row halves
 constexpr int kM2LUnits = 4096;      // work units a level's M2L aims for (K is split to reach them)
+constexpr double kM2LDenseFill = 0.35;   // below this interaction-list fill, M2L runs as pair sums
 constexpr int kM2LMinSplits = 3;     // so that a split has at most kM2LMaxSplitBlocks blocks
 constexpr int kM2LMaxSplitBlocks = (kILSize + 1 + kM2LMinSplits - 1) / kM2LMinSplits;
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -889,13 +890,16 @@ struct M2LArgs {
     const int64_t* cscan;      // exclusive scan of the class-major target flags (8 * 8^(l-1))
     const int64_t* ctotal;     // number of listed boxes
     const int32_t* list;       // target boxes of the level, grouped by class
-    int64_t* sched;            // [0]: K splits of this level
+    int64_t* sched;            // [0]: K splits of this level, [1]: 1 = pair sums instead of the GEMM
+    unsigned long long* npairs; // non-empty (target box, interaction-list box) pairs of the level
     double* vbuf;              // (splits, listed boxes, mp): partial check vectors times h
 };
 
 // Class-major "holds targets" flags of level l: slot (b & 7) * 8^(l-1) + (b >> 3).
-__global__ __launch_bounds__(kFBlock) void class_flags_kernel(FmmDev a, int l, int64_t* __restrict__ f) {
+__global__ __launch_bounds__(kFBlock) void class_flags_kernel(FmmDev a, int l, int64_t* __restrict__ f,
+                                                              unsigned long long* __restrict__ npairs) {
     const int64_t nb = (int64_t)1 << (3 * l), P = nb >> 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *npairs = 0;
     for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
         f[(b & 7) * P + (b >> 3)] = a.tpr[a.base[l] + b] ? 1 : 0;
 }
@@ -909,8 +913,11 @@ __global__ __launch_bounds__(kFBlock) void class_list_kernel(FmmDev a, int l, co
 // K splits of a level: enough work units for the whole chip, at most one
 // K block each.
 __global__ void m2l_sched_kernel(const int64_t* __restrict__ cscan, const int64_t* __restrict__ ctotal, int l,
-                                 int64_t* __restrict__ sched) {
+                                 const unsigned long long* __restrict__ npairs, int64_t* __restrict__ sched) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // sparse interaction lists (few of the 189 offsets hold sources) run as
+    // pair sums: the GEMM would multiply mostly zero blocks
+    sched[1] = (double)*npairs < kM2LDenseFill * (double)*ctotal * kILSize ? 1 : 0;
     const int64_t P = (int64_t)1 << (3 * (l - 1));
     int64_t tiles = 0;
     for (int c = 0; c < 8; ++c) {
@@ -919,6 +926,23 @@ __global__ void m2l_sched_kernel(const int64_t* __restrict__ cscan, const int64_
     }
     int64_t S = tiles > 0 ? (kM2LUnits + tiles - 1) / tiles : 1;
     sched[0] = S < kM2LMinSplits ? kM2LMinSplits : (S > kM2LBlocks ? kM2LBlocks : S);
+}
+
+// Counts the non-empty interaction-list boxes of the listed target boxes.
+__global__ __launch_bounds__(kFBlock) void il_count_kernel(FmmDev a, M2LArgs g, int l) {
+    const int64_t n = *g.ctotal, nbx = (int64_t)1 << l;
+    unsigned long long cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kFBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kFBlock) {
+        const int64_t b = g.list[i];
+        const int32_t* il = g.il + (b & 7) * kILSize * 3;
+        const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
+        for (int k = 0; k < kILSize; ++k) {
+            const int64_t ai[3] = {idx[0] + il[3 * k], idx[1] + il[3 * k + 1], idx[2] + il[3 * k + 2]};
+            if (ai[0] < 0 || ai[1] < 0 || ai[2] < 0 || ai[0] >= nbx || ai[1] >= nbx || ai[2] >= nbx) continue;
+            cnt += a.snz[a.base[l] + (int64_t)morton(ai[0], ai[1], ai[2])] ? 1 : 0;
+        }
+    }
+    if (cnt) atomicAdd(g.npairs, cnt);
 }
 
 // Partial V = A_c E over K split `split` for one tile of 64 listed boxes of
@@ -935,6 +959,7 @@ __global__ __launch_bounds__(kGemmThreads) void m2l_gemm_kernel(FmmDev a, M2LArg
     const int c = blockIdx.x & 7;
     const int64_t u = blockIdx.x >> 3, P = (int64_t)1 << (3 * (l - 1));
     const int64_t S = g.sched[0];
+    if (g.sched[1]) return;                                    // this level runs as pair sums
     const int64_t c0 = g.cscan[c * P], c1 = c < 7 ? g.cscan[(c + 1) * P] : *g.ctotal;
     const int64_t tiles = (c1 - c0 + kGemmNT - 1) / kGemmNT;
     // split-major: the tiles running together on one XCD share one slice of A_c in its L2
@@ -1001,9 +1026,100 @@ __global__ __launch_bounds__(kGemmThreads) void m2l_gemm_kernel(FmmDev a, M2LArg
                       });
 }
 
+// Dynamic LDS of the pair-sum M2L kernel, in doubles: the template, then one
+// staging slice of ns records per wave, which the partial check vectors reuse
+// once every wave is done with its sources.
+size_t m2l_lds(int ns) {
+    const size_t stage = (size_t)kFWaves * ns * (sizeof(SrcSL64) / sizeof(double));
+    const size_t part = (size_t)kFWaves * 3 * ns;
+    return ((size_t)((3 * ns + 1) & ~1) + std::max(stage, part)) * sizeof(double);
+}
+
+// M2L as pair sums, for levels whose interaction lists are sparse: per target
+// box, the interaction-list boxes that hold sources (plus L2L from the parent,
+// levels > 2) summed at its check points; the check vector goes to the box's
+// column of the level's check matrix (the same column the GEMM would fill).
+// Lane j holds check points j, j + 64, ... (T of them) in registers; wave w
+// takes every fourth source box, stages its equivalent sources in its own LDS
+// slice and reads them back by broadcast.
+template <int T>
+__global__ __launch_bounds__(kFBlock) void m2l_pairs_kernel(FmmDev a, M2LArgs g, int l) {
+    extern __shared__ double sh[];
+    if (!g.sched[1]) return;                                   // this level runs as a GEMM
+    double* surf = sh;
+    double* rest = surf + ((3 * a.ns + 1) & ~1);               // 16-byte aligned
+    SrcSL64* stage = reinterpret_cast<SrcSL64*>(rest);
+    double* part = rest;
+    load_surface(a, surf);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    SrcSL64* mine = stage + wave * a.ns;
+    const int64_t nb = (int64_t)1 << (3 * l), np = (int64_t)1 << (l - 1), P = nb >> 3;
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        if (!a.tpr[a.base[l] + b]) continue;                      // uniform over the workgroup
+        double ctr[3], h;
+        box_centre(a, l, b, ctr, h);
+        const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
+        const uint64_t p = b >> 3;
+        const int64_t pidx[3] = {compact3(p), compact3(p >> 1), compact3(p >> 2)};
+        double x[T][3], u[T][3];
+        check_points<T>(a, surf, ctr, kAlphaDC * h, lane, x, u);
+        int item = 0;
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int64_t pn[3] = {pidx[0] + dx, pidx[1] + dy, pidx[2] + dz};
+                    if (pn[0] < 0 || pn[1] < 0 || pn[2] < 0 || pn[0] >= np || pn[1] >= np || pn[2] >= np) continue;
+                    for (int o = 0; o < 8; ++o) {
+                        const int64_t ai[3] = {2 * pn[0] + (o & 1), 2 * pn[1] + ((o >> 1) & 1), 2 * pn[2] + (o >> 2)};
+                        if (llabs(ai[0] - idx[0]) <= 1 && llabs(ai[1] - idx[1]) <= 1 && llabs(ai[2] - idx[2]) <= 1)
+                            continue;                      // a neighbour: near field
+                        const uint64_t ab = morton(ai[0], ai[1], ai[2]);
+                        if (!a.snz[a.base[l] + ab]) continue;
+                        if (item++ % kFWaves != wave) continue;
+                        double ac[3], ha;
+                        box_centre(a, l, ab, ac, ha);
+                        if (a.sig) {
+                            const double sg = a.sig[a.base[l] + ab];
+#pragma unroll
+                            for (int k = 0; k < T; ++k)
+                                point_source(x[k][0] - ac[0], x[k][1] - ac[1], x[k][2] - ac[2], sg, u[k]);
+                        }
+                        stage_surface(a, surf, ac, kAlphaUE * ha, a.ue + (a.base[l] + ab) * a.n3, mine, lane);
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+                        for (int j = 0; j < a.ns; ++j) {
+                            const SrcSL64 sr = mine[j];
+#pragma unroll
+                            for (int k = 0; k < T; ++k)
+                                sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz,
+                                               u[k]);
+                        }
+                        __builtin_amdgcn_wave_barrier();   // reads of this box precede the next writes
+                    }
+                }
+        if (l > 2 && item++ % kFWaves == wave) {
+            double pc[3], hp;
+            box_centre(a, l - 1, p, pc, hp);
+            stage_surface(a, surf, pc, kAlphaDE * hp, a.de + (a.base[l - 1] + p) * a.n3, mine, lane);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+            for (int j = 0; j < a.ns; ++j) {
+                const SrcSL64 sr = mine[j];
+#pragma unroll
+                for (int k = 0; k < T; ++k)
+                    sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz, u[k]);
+            }
+        }
+        __syncthreads();                           // the partial vectors overwrite the staging slices
+        store_partial<T>(a, part, wave, lane, u);
+        store_check(a, part, h, g.cscan[(b & 7) * P + (b >> 3)]);
+    }
+}
+
 // Adds the K-split partials of every listed box into split 0, in split order.
 __global__ __launch_bounds__(kFBlock) void m2l_reduce_kernel(M2LArgs g) {
     const int64_t n = *g.ctotal * g.mp, S = g.sched[0];
+    if (g.sched[1]) return;
     for (int64_t e = (int64_t)blockIdx.x * kFBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kFBlock) {
         double v = g.vbuf[e];
         for (int64_t sp = 1; sp < S; ++sp) v += g.vbuf[sp * n + e];
@@ -1099,7 +1215,7 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_cscan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
     L.off_ctotal = take(8);
     L.off_clist = take((size_t)L.n_leaves * 4);
-    L.off_sched = take(8);
+    L.off_sched = take(24);                 // splits, mode, interaction pair count
     // K-split partials: splits x listed boxes <= 3 listed + 64 (units + 8)
     L.off_vbuf = take((size_t)(kM2LMinSplits * std::min(L.n_leaves, std::max<int64_t>({n_src, n_trg, 1})) +
                                kGemmNT * (kM2LUnits + 8)) *
@@ -1364,6 +1480,7 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     g2.list = reinterpret_cast<int32_t*>(ws + L.off_clist);
     g2.vbuf = reinterpret_cast<double*>(ws + L.off_vbuf);
     g2.sched = reinterpret_cast<int64_t*>(ws + L.off_sched);
+    g2.npairs = reinterpret_cast<unsigned long long*>(ws + L.off_sched + 16);
     a.vbuf = g2.vbuf;
     a.pos = g2.cscan;
     a.mp = plan->mp;
@@ -1423,7 +1540,7 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         const int64_t nb = (int64_t)1 << (3 * l);
         const unsigned gb = f_grid((nb + kFBlock - 1) / kFBlock);
         int64_t* cflag = const_cast<int64_t*>(g2.cscan);
-        hipLaunchKernelGGL(class_flags_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, cflag);
+        hipLaunchKernelGGL(class_flags_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, cflag, g2.npairs);
         if (!chk()) break;
         e = exclusive_scan_i64(cflag, nb, cflag, reinterpret_cast<int64_t*>(ws + L.off_cscan),
                                const_cast<int64_t*>(g2.ctotal), st);
@@ -1431,7 +1548,10 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         hipLaunchKernelGGL(class_list_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, g2.cscan,
                            const_cast<int32_t*>(g2.list));
         if (!chk()) break;
-        hipLaunchKernelGGL(m2l_sched_kernel, dim3(1), dim3(kWave), 0, st, g2.cscan, g2.ctotal, l, g2.sched);
+        hipLaunchKernelGGL(il_count_kernel, dim3(f_grid((std::min<int64_t>(nb, in.n_trg) + kFBlock - 1) / kFBlock)),
+                           dim3(kFBlock), 0, st, a, g2, l);
+        if (!chk()) break;
+        hipLaunchKernelGGL(m2l_sched_kernel, dim3(1), dim3(kWave), 0, st, g2.cscan, g2.ctotal, l, g2.npairs, g2.sched);
         if (!chk()) break;
         // per class at most min(8^(l-1), n_trg) boxes in `tiles` tiles; units per
         // class = splits x tiles <= max(kM2LUnits + tiles, kM2LMinSplits x tiles)
@@ -1447,6 +1567,14 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         if (!chk()) break;
         hipLaunchKernelGGL(m2l_reduce_kernel, dim3(f_grid((std::min<int64_t>(nb, in.n_trg) * plan->mp + kFBlock - 1) / kFBlock)),
                            dim3(kFBlock), 0, st, g2);
+        if (!chk()) break;
+        {
+            const dim3 g(f_grid(nb));
+            const size_t lds = m2l_lds(ns);
+            if (T == 1) hipLaunchKernelGGL(m2l_pairs_kernel<1>, g, dim3(kFBlock), lds, st, a, g2, l);
+            else if (T == 2) hipLaunchKernelGGL(m2l_pairs_kernel<2>, g, dim3(kFBlock), lds, st, a, g2, l);
+            else hipLaunchKernelGGL(m2l_pairs_kernel<3>, g, dim3(kFBlock), lds, st, a, g2, l);
+        }
         if (!chk()) break;
         if (!apply(l, plan->d_downA, a.de + L.base[l] * a.n3)) break;
     }
