@@ -449,13 +449,19 @@ int stokes_collision_candidates(stokes_ctx* ctx, int32_t n_boxes, const double* 
  * paper, whose self-cell terms are handled by its singular quadrature).
  * The plan holds the check-to-equivalent pseudo-inverses (singular values
  * below 1e-12 of the largest dropped), computed on the host at creation
- * (about 0.1 s at order 4, a few seconds at 6), in device memory owned by the
+ * (about 0.1 s at order 4, a few seconds at 6), and the M2L operators: for
+ * each of the 8 positions of a box in its parent, its 189 interaction-list
+ * translations and the parent-to-child one at unit scale, built on the device
+ * (8 x 190 x m^2 doubles, m = 3 (6 (order-1)^2 + 2) rounded up to 16: 0.4 GB
+ * at order 4, 2.6 GB at order 6).  All of it is device memory owned by the
  * plan until stokes_fmm_plan_destroy. */
 int stokes_fmm_plan_create(stokes_ctx* ctx, int32_t order, stokes_fmm_plan** plan);   /* order 2..6 */
 void stokes_fmm_plan_destroy(stokes_fmm_plan* plan);
 
-/* Workspace for n_src sources, n_trg targets and depth (2..7); it grows as
- * 8^depth * 6 * (6 (order-1)^2 + 2) doubles for the per-box densities. */
+/* Workspace for n_src sources, n_trg targets and depth (2..7): the per-box
+ * densities grow as 8^depth * 6 * (6 (order-1)^2 + 2) doubles, the check
+ * matrix of a level as 3 min(8^depth, max(n_src, n_trg)) + 262,656 columns of
+ * m doubles (m as above). */
 int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,
                               int64_t n_trg, int32_t depth, size_t* bytes);
 

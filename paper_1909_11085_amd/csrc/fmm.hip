@@ -14,11 +14,16 @@
 //   leaf keys (Morton index of the leaf holding each point), radix sort,
 //   gathers into leaf order (sources carry q = w f), leaf offsets by binary
 //   search, per-level "has sources" / "has targets" flags;
-//   P2M, M2M (leaves up to level 2), M2L + L2L (level 2 down to the leaves),
-//   then L2P + P2P per target leaf, written back in the caller's order.
-// The surface sums give each wave of a workgroup a quarter of the source
-// boxes (or points); the four partial check vectors are added in a fixed
-// order, so results are reproducible.
+//   upward: P2M (leaves), M2M (up to level 2): per box the check velocities
+//   (LDS-staged pair sums), then per level one FP64 MFMA GEMM applies the
+//   pseudo-inverse to all boxes;
+//   downward, level 2 to the leaves: M2L + L2L as one GEMM per octant class
+//   against precomputed translation operators (or as pair sums where the
+//   interaction lists are sparse), then the pseudo-inverse GEMM;
+//   L2P + P2P per chunk of up to 64 targets of a leaf, written back in the
+//   caller's order.
+// Every sum is taken in a fixed order (no atomics on values), so results are
+// reproducible.
 //
 // Double-layer sources use the double-layer kernel in P2M and P2P.  Their
 // field has a net flux (sum of n . q) that no single-layer density carries, so
@@ -41,8 +46,6 @@ struct stokes_fmm_plan {
     int order = 0;
     int ns = 0;                 // surface points
     double* d_surf = nullptr;   // (ns, 3)
-    double* d_upT = nullptr;    // (3ns, 3ns), transposed: upT[k * 3ns + r] = UP[r][k]
-    double* d_downT = nullptr;
     // M2L as GEMMs: rows padded to mp, K blocks of kb (3ns densities, the
     // point-source flux, zero padding); see m2l_matrix_kernel
     int mp = 0, kb = 0;
@@ -124,8 +127,6 @@ struct FmmDev {
     int ns, n3, D;
     double c[3], R;
     const double* surf;
-    const double* upT;
-    const double* downT;
     const double* sx;          // sorted sources (3, n_src)
     const double* sq;
     const double* sn;          // sorted source normals (double layer), else null
@@ -1296,12 +1297,6 @@ int fmm_plan_build(int device, int order, stokes_fmm_plan** out, std::string& er
     std::vector<double> up, down;
     pinv_jacobi(kernel_matrix(s, kAlphaUC, s, kAlphaUE), n3, kPinvRcond, up);
     pinv_jacobi(kernel_matrix(s, kAlphaDC, s, kAlphaDE), n3, kPinvRcond, down);
-    std::vector<double> upT((size_t)n3 * n3), downT((size_t)n3 * n3);
-    for (int r = 0; r < n3; ++r)
-        for (int k = 0; k < n3; ++k) {
-            upT[(size_t)k * n3 + r] = up[(size_t)r * n3 + k];
-            downT[(size_t)k * n3 + r] = down[(size_t)r * n3 + k];
-        }
     stokes_fmm_plan* p = new (std::nothrow) stokes_fmm_plan{};
     if (!p) {
         err = "out of host memory";
@@ -1310,17 +1305,14 @@ int fmm_plan_build(int device, int order, stokes_fmm_plan** out, std::string& er
     p->device = device;
     p->order = order;
     p->ns = ns;
-    const size_t sb = s.size() * 8, ob = (size_t)n3 * n3 * 8;
-    if (hipMalloc(&p->d_surf, sb) != hipSuccess || hipMalloc(&p->d_upT, ob) != hipSuccess ||
-        hipMalloc(&p->d_downT, ob) != hipSuccess ||
-        hipMemcpy(p->d_surf, s.data(), sb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_upT, upT.data(), ob, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_downT, downT.data(), ob, hipMemcpyHostToDevice) != hipSuccess) {
+    const size_t sb = s.size() * 8;
+    if (hipMalloc(&p->d_surf, sb) != hipSuccess ||
+        hipMemcpy(p->d_surf, s.data(), sb, hipMemcpyHostToDevice) != hipSuccess) {
         fmm_plan_free(p);
         err = "device allocation or copy failed";
         return -2;
     }
-    // M2L class matrices (built on the device) and the padded DOWN operator
+    // the pseudo-inverses, padded and k-major, and the M2L class matrices (built on the device)
     const int mp = pad16(n3), kb = pad16(n3 + 1);
     p->mp = mp;
     p->kb = kb;
@@ -1365,8 +1357,6 @@ int fmm_plan_build(int device, int order, stokes_fmm_plan** out, std::string& er
 void fmm_plan_free(stokes_fmm_plan* p) {
     if (!p) return;
     (void)hipFree(p->d_surf);
-    (void)hipFree(p->d_upT);
-    (void)hipFree(p->d_downT);
     (void)hipFree(p->d_m2l);
     (void)hipFree(p->d_il);
     (void)hipFree(p->d_downA);
@@ -1399,8 +1389,6 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     for (int c = 0; c < 3; ++c) a.c[c] = in.centre[c];
     a.R = in.half_width;
     a.surf = plan->d_surf;
-    a.upT = plan->d_upT;
-    a.downT = plan->d_downT;
     a.sx = reinterpret_cast<double*>(ws + L.off_sx);
     a.sq = reinterpret_cast<double*>(ws + L.off_sq);
     a.sn = dl ? reinterpret_cast<double*>(ws + L.off_sn) : nullptr;
