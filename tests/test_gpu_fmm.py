@@ -1,6 +1,6 @@
-"""GPU parity of the kernel-independent FMM for the single-layer sum (Sec. 3.1,
-"Far evaluation") against the FMM oracle, and its accuracy against the direct
-sum at sizes where only the GPU can run it.
+"""GPU parity of the kernel-independent FMM for the single- and double-layer
+sums (Sec. 3.1, "Far evaluation") against the FMM oracle, and its accuracy
+against the direct sum at sizes where only the GPU can run it.
 
 The GPU and the oracle run the same algorithm; their operators are
 pseudo-inverses from different SVD codes (one-sided Jacobi on the host here,
@@ -12,6 +12,7 @@ The bars are 1e-9 and 1e-6, each far below the method's own error at that
 order; against the direct sum the bar is that error.
 """
 import ctypes
+import itertools
 
 import numpy as np
 import pytest
@@ -30,7 +31,9 @@ FMM_ERR = {4: 5e-3, 6: 3e-4}          # error against the direct sum (oracle pin
 # the double layer's far field converges more slowly (measured on the wall:
 # 1.6e-2 at order 4, 1.0e-3 at order 6, ten times the single layer's)
 FMM_ERR_DL = {4: 3e-2, 6: 2e-3}
-ORACLE_TOL = {4: 1e-9, 6: 1e-6}
+# measured: 7.6e-15 (order 2), 1.0e-13 (3), below 1e-9 (4), 5.3e-10 (5), 5.5e-8 (6)
+ORACLE_TOL = {2: 1e-12, 3: 1e-11, 4: 1e-9, 5: 1e-8, 6: 1e-6}
+M2L_DENSE_FILL = 0.35     # the library's switch between the GEMM and pair sums
 
 
 @pytest.fixture(scope="module")
@@ -130,6 +133,63 @@ def test_dl_wall_onto_cells_sampled(plans):
     ref = host(S.dl(*args, dev(cells.pos[:, pick])))
     err = rel_l2(host(got)[:, pick], ref)
     assert err < FMM_ERR_DL[6], err
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_other_orders_match_oracle(p):
+    """Orders 2, 3 and 5 (the other tile shapes of the M2L and pseudo-inverse
+    GEMMs) against the oracle FMM, single and double layer."""
+    plan = S.FMMPlan(p)
+    src, f, w, trg = _cloud(77, 900, 250)
+    got = host(S.fmm_sl(plan, dev(src), dev(f), dev(w), dev(trg), (0.0, 0.0, 0.0), 1.0001, 2, mu=1.3))
+    ref = F.fmm_sl(src, f, w, trg, np.zeros(3), 1.0001, 2, p, mu=1.3)
+    assert rel_l2(got, ref) < ORACLE_TOL[p], rel_l2(got, ref)
+    nrm = _normals(78, 900)
+    got = host(S.fmm_dl(plan, dev(src), dev(f), dev(w), dev(nrm), dev(trg), (0.0, 0.0, 0.0), 1.0001, 2))
+    ref = F.fmm_dl(src, f, w, nrm, trg, np.zeros(3), 1.0001, 2, p)
+    assert rel_l2(got, ref) < ORACLE_TOL[p], rel_l2(got, ref)
+
+
+def _il_fill(src, trg, R, l):
+    """Fraction of the 189 interaction-list offsets of the target boxes of
+    level l (cube centred at 0, half-width R) that hold sources."""
+    n = 2 ** l
+    box = lambda x: np.clip(np.floor((x + R) / (2 * R / n)).astype(int), 0, n - 1)
+    sb = set(map(tuple, box(src).T))
+    tb = set(map(tuple, box(trg).T))
+    hits = 0
+    for b in map(np.array, tb):
+        for d in itertools.product((-1, 0, 1), repeat=3):
+            pn = b // 2 + np.array(d)
+            if np.any(pn < 0) or np.any(pn >= n // 2):
+                continue
+            for o in itertools.product((0, 1), repeat=3):
+                a = 2 * pn + np.array(o)
+                if np.max(np.abs(a - b)) > 1 and tuple(a) in sb:
+                    hits += 1
+    return hits / (len(tb) * 189)
+
+
+@pytest.mark.parametrize("layout", ["filled", "separated"])
+def test_m2l_paths_match_oracle(plans, layout):
+    """Sources filling the cube give dense interaction lists (the M2L GEMM);
+    sources in one corner and targets in the opposite one give sparse lists
+    (M2L as pair sums).  Both against the oracle FMM at depth 3."""
+    rng = np.random.default_rng(91 if layout == "filled" else 92)
+    if layout == "filled":
+        src, trg = rng.uniform(-1, 1, (3, 3000)), rng.uniform(-0.3, 0.3, (3, 200))
+    else:
+        src, trg = rng.uniform(-1, -0.5, (3, 3000)), rng.uniform(0.5, 1, (3, 200))
+    # level 2 offers at most 37 of the 189 offsets, so it always runs as pair sums
+    fills = [_il_fill(src, trg, 1.0001, l) for l in (2, 3)]
+    if layout == "filled":
+        assert fills[1] >= M2L_DENSE_FILL, fills
+    else:
+        assert max(fills) < M2L_DENSE_FILL and fills[0] > 0, fills
+    f, w = rng.standard_normal((3, 3000)), rng.uniform(0.5, 1.0, 3000)
+    got = host(S.fmm_sl(plans[4], dev(src), dev(f), dev(w), dev(trg), (0.0, 0.0, 0.0), 1.0001, 3))
+    ref = F.fmm_sl(src, f, w, trg, np.zeros(3), 1.0001, 3, 4)
+    assert rel_l2(got, ref) < ORACLE_TOL[4], rel_l2(got, ref)
 
 
 def test_edge_cases(plans):
