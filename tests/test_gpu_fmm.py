@@ -73,6 +73,22 @@ def test_accuracy_against_direct(plans, p, D):
     assert rel_l2(got, ref) < FMM_ERR[p], rel_l2(got, ref)
 
 
+def test_depth_seven(plans):
+    """The deepest tree (2,097,152 leaves): 300k clustered points, order 4, a
+    seeded sample of targets against the direct sum."""
+    rng = np.random.default_rng(83)
+    n = 300_000
+    src = rng.uniform(-2, 2, (3, n))
+    src[:, : n // 2] = 0.4 * rng.standard_normal((3, n // 2)).clip(-4.9, 4.9)
+    f, w = rng.standard_normal((3, n)), rng.uniform(0.5, 1.0, n)
+    S_, F_, W_ = dev(src), dev(f), dev(w)
+    got = S.fmm_sl(plans[4], S_, F_, W_, S_, (0.0, 0.0, 0.0), 2.0001, 7)
+    pick = W.subset(np.random.default_rng(84), n, 2000)
+    ref = host(S.sl(S_, F_, W_, dev(src[:, pick])))
+    err = rel_l2(host(got)[:, pick], ref)
+    assert err < FMM_ERR[4], err
+
+
 def test_cells_workload_sampled(plans):
     """The 3,840 cells in the vessel (2,088,960 points), depth 6: all targets in
     one launch, a seeded sample against the direct sum (no pair rule)."""
