@@ -705,8 +705,9 @@ int64_t max_items(int64_t n_trg, int64_t n_leaves) { return (n_trg + kWave - 1) 
 constexpr int kILSize = 189;
 constexpr int kM2LBlocks = kILSize + 1;
 constexpr int kGemmNT = 64;          // boxes per tile
-constexpr int kGemmKC = 8;           // K rows per LDS chunk (2 MFMA steps)
+constexpr int kGemmKC = 16;          // K rows per LDS chunk (4 MFMA steps)
 constexpr int kGemmThreads = 512;    // 8 waves: 4 column groups x 2 row halves
+constexpr int kGemmBPT = kGemmKC * kGemmNT / kGemmThreads;   // B values per thread and chunk
 constexpr int kM2LUnits = 4096;      // work units a level's M2L aims for (K is split to reach them)
 constexpr double kM2LDenseFill = 0.35;   // below this interaction-list fill, M2L runs as pair sums
 constexpr int kM2LMinSplits = 3;     // so that a split has at most kM2LMaxSplitBlocks blocks
@@ -802,11 +803,11 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t 
     using G = GemmShape<RB>;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int cg = wave & 3, rb0 = (wave >> 2) * G::H;
-    const int bj = tid >> 3, bk = tid & 7;                   // one B value per thread
+    const int bj = tid >> 3, bk = tid & 7;                   // B rows bk, bk + 8, ... of column bj
     v4d acc[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-    double pa[G::APT], pb = 0.0;
+    double pa[G::APT], pb[kGemmBPT];
     auto fetch = [&](int64_t t) {
         const int64_t q = chunk(t);
         const double* Aq = A + q * G::na;
@@ -815,7 +816,8 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t 
             const int e = tid + i * kGemmThreads;
             pa[i] = e < G::na ? Aq[e] : 0.0;
         }
-        pb = loadb(q, bj, bk);
+#pragma unroll
+        for (int i = 0; i < kGemmBPT; ++i) pb[i] = loadb(q, bj, bk + 8 * i);
     };
     auto put = [&](int buf) {
         double* Ab = As + buf * G::na;
@@ -824,7 +826,8 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t 
             const int e = tid + i * kGemmThreads;
             if (e < G::na) Ab[e] = pa[i];
         }
-        Bs[buf * (kGemmKC * kGemmNT) + bk * kGemmNT + bj] = pb;
+#pragma unroll
+        for (int i = 0; i < kGemmBPT; ++i) Bs[buf * (kGemmKC * kGemmNT) + (bk + 8 * i) * kGemmNT + bj] = pb[i];
     };
     auto multiply = [&](int64_t t) {
         if (!busy(t, cg)) return;                                 // uniform over the wave
