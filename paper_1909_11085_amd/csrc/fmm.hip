@@ -710,6 +710,7 @@ constexpr int kGemmThreads = 512;    // 8 waves: 4 column groups x 2 row halves
 constexpr int kGemmBPT = kGemmKC * kGemmNT / kGemmThreads;   // B values per thread and chunk
 constexpr int kM2LUnits = 4096;      // work units a level's M2L aims for (K is split to reach them)
 constexpr double kM2LDenseFill = 0.35;   // below this interaction-list fill, M2L runs as pair sums
+constexpr int kILCountParts = 2048;      // workgroups (partial counts) of the interaction-list count
 constexpr int kM2LMinSplits = 3;     // so that a split has at most kM2LMaxSplitBlocks blocks
 constexpr int kM2LMaxSplitBlocks = (kILSize + 1 + kM2LMinSplits - 1) / kM2LMinSplits;
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -889,21 +890,20 @@ __device__ __forceinline__ void gemm_tile_any(const double* __restrict__ A, int6
 struct M2LArgs {
     const double* A;           // plan's class matrices
     const int32_t* il;
-    const double* downA;
-    int mp, kb;
-    const int64_t* cscan;      // exclusive scan of the class-major target flags (8 * 8^(l-1))
+    int mp;
+    const int64_t* cscan;      // exclusive scan of the class-major target flags (8 * 8^(l-1)); the
+                               // upward pass reuses it for the boxes holding sources
     const int64_t* ctotal;     // number of listed boxes
     const int32_t* list;       // target boxes of the level, grouped by class
     int64_t* sched;            // [0]: K splits of this level, [1]: 1 = pair sums instead of the GEMM
-    unsigned long long* npairs; // non-empty (target box, interaction-list box) pairs of the level
+    int64_t* npairs;           // per workgroup of il_count_kernel: non-empty (target box,
+                               // interaction-list box) pairs of the level
     double* vbuf;              // (splits, listed boxes, mp): partial check vectors times h
 };
 
 // Class-major "holds targets" flags of level l: slot (b & 7) * 8^(l-1) + (b >> 3).
-__global__ __launch_bounds__(kFBlock) void class_flags_kernel(FmmDev a, int l, int64_t* __restrict__ f,
-                                                              unsigned long long* __restrict__ npairs) {
+__global__ __launch_bounds__(kFBlock) void class_flags_kernel(FmmDev a, int l, int64_t* __restrict__ f) {
     const int64_t nb = (int64_t)1 << (3 * l), P = nb >> 3;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *npairs = 0;
     for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
         f[(b & 7) * P + (b >> 3)] = a.tpr[a.base[l] + b] ? 1 : 0;
 }
@@ -916,12 +916,17 @@ __global__ __launch_bounds__(kFBlock) void class_list_kernel(FmmDev a, int l, co
 
 // K splits of a level: enough work units for the whole chip, at most one
 // K block each.
-__global__ void m2l_sched_kernel(const int64_t* __restrict__ cscan, const int64_t* __restrict__ ctotal, int l,
-                                 const unsigned long long* __restrict__ npairs, int64_t* __restrict__ sched) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kWave) void m2l_sched_kernel(const int64_t* __restrict__ cscan,
+                                                          const int64_t* __restrict__ ctotal, int l,
+                                                          const int64_t* __restrict__ npairs, int n_parts,
+                                                          int64_t* __restrict__ sched) {
+    int64_t pairs = 0;                                         // the count kernel's partials
+    for (int i = threadIdx.x; i < n_parts; i += kWave) pairs += npairs[i];
+    for (int o = kWave / 2; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o);
+    if (threadIdx.x != 0) return;
     // sparse interaction lists (few of the 189 offsets hold sources) run as
     // pair sums: the GEMM would multiply mostly zero blocks
-    sched[1] = (double)*npairs < kM2LDenseFill * (double)*ctotal * kILSize ? 1 : 0;
+    sched[1] = (double)pairs < kM2LDenseFill * (double)*ctotal * kILSize ? 1 : 0;
     const int64_t P = (int64_t)1 << (3 * (l - 1));
     int64_t tiles = 0;
     for (int c = 0; c < 8; ++c) {
@@ -932,21 +937,32 @@ __global__ void m2l_sched_kernel(const int64_t* __restrict__ cscan, const int64_
     sched[0] = S < kM2LMinSplits ? kM2LMinSplits : (S > kM2LBlocks ? kM2LBlocks : S);
 }
 
-// Counts the non-empty interaction-list boxes of the listed target boxes.
+// Counts the non-empty interaction-list boxes of the listed target boxes: one
+// wave per box, lane k checking offsets k, k + 64, k + 128; one partial count
+// per workgroup.
 __global__ __launch_bounds__(kFBlock) void il_count_kernel(FmmDev a, M2LArgs g, int l) {
+    __shared__ int64_t red[kFWaves];
     const int64_t n = *g.ctotal, nbx = (int64_t)1 << l;
-    unsigned long long cnt = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kFBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kFBlock) {
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    int64_t cnt = 0;
+    for (int64_t i = ((int64_t)blockIdx.x * kFBlock + threadIdx.x) / kWave; i < n;
+         i += (int64_t)gridDim.x * (kFBlock / kWave)) {                      // uniform over the wave
         const int64_t b = g.list[i];
         const int32_t* il = g.il + (b & 7) * kILSize * 3;
         const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
-        for (int k = 0; k < kILSize; ++k) {
-            const int64_t ai[3] = {idx[0] + il[3 * k], idx[1] + il[3 * k + 1], idx[2] + il[3 * k + 2]};
-            if (ai[0] < 0 || ai[1] < 0 || ai[2] < 0 || ai[0] >= nbx || ai[1] >= nbx || ai[2] >= nbx) continue;
-            cnt += a.snz[a.base[l] + (int64_t)morton(ai[0], ai[1], ai[2])] ? 1 : 0;
+        for (int k = lane; k < kILSize + kWave - 1; k += kWave) {
+            bool hit = false;
+            if (k < kILSize) {
+                const int64_t ai[3] = {idx[0] + il[3 * k], idx[1] + il[3 * k + 1], idx[2] + il[3 * k + 2]};
+                hit = ai[0] >= 0 && ai[1] >= 0 && ai[2] >= 0 && ai[0] < nbx && ai[1] < nbx && ai[2] < nbx &&
+                      a.snz[a.base[l] + (int64_t)morton(ai[0], ai[1], ai[2])];
+            }
+            cnt += __builtin_popcountll(__ballot(hit));
         }
     }
-    if (cnt) atomicAdd(g.npairs, cnt);
+    if (lane == 0) red[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) g.npairs[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // Partial V = A_c E over K split `split` for one tile of 64 listed boxes of
@@ -1219,7 +1235,7 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_cscan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
     L.off_ctotal = take(8);
     L.off_clist = take((size_t)L.n_leaves * 4);
-    L.off_sched = take(24);                 // splits, mode, interaction pair count
+    L.off_sched = take(16 + 8 * kILCountParts);   // splits, mode, partial interaction pair counts
     // K-split partials: splits x listed boxes <= 3 listed + 64 (units + 8)
     L.off_vbuf = take((size_t)(kM2LMinSplits * std::min(L.n_leaves, std::max<int64_t>({n_src, n_trg, 1})) +
                                kGemmNT * (kM2LUnits + 8)) *
@@ -1463,15 +1479,13 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     M2LArgs g2{};
     g2.A = plan->d_m2l;
     g2.il = plan->d_il;
-    g2.downA = plan->d_downA;
     g2.mp = plan->mp;
-    g2.kb = plan->kb;
     g2.cscan = reinterpret_cast<int64_t*>(ws + L.off_cflag);
     g2.ctotal = reinterpret_cast<int64_t*>(ws + L.off_ctotal);
     g2.list = reinterpret_cast<int32_t*>(ws + L.off_clist);
     g2.vbuf = reinterpret_cast<double*>(ws + L.off_vbuf);
     g2.sched = reinterpret_cast<int64_t*>(ws + L.off_sched);
-    g2.npairs = reinterpret_cast<unsigned long long*>(ws + L.off_sched + 16);
+    g2.npairs = reinterpret_cast<int64_t*>(ws + L.off_sched + 16);
     a.vbuf = g2.vbuf;
     a.pos = g2.cscan;
     a.mp = plan->mp;
@@ -1531,7 +1545,7 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         const int64_t nb = (int64_t)1 << (3 * l);
         const unsigned gb = f_grid((nb + kFBlock - 1) / kFBlock);
         int64_t* cflag = const_cast<int64_t*>(g2.cscan);
-        hipLaunchKernelGGL(class_flags_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, cflag, g2.npairs);
+        hipLaunchKernelGGL(class_flags_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, cflag);
         if (!chk()) break;
         e = exclusive_scan_i64(cflag, nb, cflag, reinterpret_cast<int64_t*>(ws + L.off_cscan),
                                const_cast<int64_t*>(g2.ctotal), st);
@@ -1539,10 +1553,11 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         hipLaunchKernelGGL(class_list_kernel, dim3(gb), dim3(kFBlock), 0, st, a, l, g2.cscan,
                            const_cast<int32_t*>(g2.list));
         if (!chk()) break;
-        hipLaunchKernelGGL(il_count_kernel, dim3(f_grid((std::min<int64_t>(nb, in.n_trg) + kFBlock - 1) / kFBlock)),
-                           dim3(kFBlock), 0, st, a, g2, l);
+        const int n_parts = (int)std::min<int64_t>(kILCountParts, (std::min<int64_t>(nb, in.n_trg) + 3) / 4);
+        hipLaunchKernelGGL(il_count_kernel, dim3(n_parts), dim3(kFBlock), 0, st, a, g2, l);
         if (!chk()) break;
-        hipLaunchKernelGGL(m2l_sched_kernel, dim3(1), dim3(kWave), 0, st, g2.cscan, g2.ctotal, l, g2.npairs, g2.sched);
+        hipLaunchKernelGGL(m2l_sched_kernel, dim3(1), dim3(kWave), 0, st, g2.cscan, g2.ctotal, l, g2.npairs, n_parts,
+                           g2.sched);
         if (!chk()) break;
         // per class at most min(8^(l-1), n_trg) boxes in `tiles` tiles; units per
         // class = splits x tiles <= max(kM2LUnits + tiles, kM2LMinSplits x tiles)
