@@ -16,14 +16,18 @@ Reported on one JSON line (stdout):
   roofline      dominant kernel: algorithmic flops (29 per single-layer pair)
                 over its measured average duration (HIP events recorded by the
                 library on the stream it launches on), against the vector peak
+  step_ms       median and minimum of 10 single-step times, taken after the
+                timed region (one event pair per step); not part of `value`
   cpu_baseline  the FP64 CPU oracle on a bounded sample of targets (all
-                sources), on this host's cores
+                sources), on this host's cores, with the full step's time
+                extrapolated from its rate
 
 --only checkpoint times the check-point double-layer quadrature on a
 vessel-wall ring (every node an on-surface target), --only bie the
 30-iteration GMRES solve of the boundary integral equation on an ellipsoid,
 --only collision the collision-candidate search of the cells and the wall,
---only fmm the FMM single-layer sum over the cells against the direct sum;
+--only fmm the FMM single-layer sum over the cells (and the wall's double layer
+at the cells) against the direct sums;
 --secondary adds them and the other workload shapes to the line.
 """
 import argparse
@@ -97,7 +101,7 @@ def main():
                          "space-time boxes and collision candidates of 3,840 cells and the wall; fmm "
                          "the FMM single-layer sum over those cells against the direct sum")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--secondary", action="store_true",
                     help="also time the other workloads (cfg3 adjoint, cfg4 P2P, cfg5 wall + cells) "
@@ -153,6 +157,19 @@ def main():
         kms, launches = S.timing_read()
         return e0.elapsed_time(e1) / steps, kms / max(launches, 1), launches
 
+    def per_step(fn, n_steps):
+        """Median and minimum of n_steps single-step times (one event pair per
+        step), taken after the timed region; they do not enter `value`."""
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        return {"median": ms[len(ms) // 2], "min": ms[0], "steps": n_steps}
+
     if args.only == "p2p":
         r = time_p2p(S, W, t, timed, args.steps, args.warmup)
         log(f"p2p: {r}")
@@ -206,7 +223,7 @@ def main():
             rate = pairs / (ms * 1e-3)
             achieved = pairs * FLOPS_PER_PAIR_SL / (kms * 1e-3) / 1e12
             results[prec] = dict(ms_per_step=ms, value=rate, kernel_ms=kms, launches=launches,
-                                 achieved=achieved)
+                                 achieved=achieved, step_ms=per_step(lambda: fwd(prec), 10))
             log(f"{prec}: {ms:.3f} ms/step, {rate:.4e} pairs/s, main kernel {kms:.3f} ms "
                 f"({achieved:.2f} TFLOP/s at {FLOPS_PER_PAIR_SL} flop/pair)")
 
@@ -251,7 +268,8 @@ def main():
         cpu = dict(value=cpu_pairs / dt, unit="pair-interactions/s", cores=O.num_threads(),
                    kind="oracle",
                    sample=f"{m} seeded targets x all {n} sources ({cpu_pairs} pairs, FP64, "
-                          f"{dt:.1f} s, compensated sums)")
+                          f"{dt:.1f} s, compensated sums)",
+                   extrapolated_full_step_s=pairs / (cpu_pairs / dt))
         log(f"cpu oracle: {cpu['value']:.4e} pairs/s on {cpu['cores']} threads ({dt:.1f}s)")
         for prec, u in outputs.items():
             rel[prec] = float(np.linalg.norm(u[:, idx] - ref) / np.linalg.norm(ref))
@@ -286,13 +304,14 @@ def main():
                                "same-cell pairs excluded",
                    "precision": head, "n_points": n, "pairs_per_step": pairs, "mu": 1.0},
         "rel_l2": rel.get(head),
+        "step_ms": hr["step_ms"] if hr else None,
     }
     if hr:
         line["roofline"] = roofline(head)
     other = [p for p in results if p != head]
     for p in other:
         line[p] = {"value": results[p]["value"], "ms_per_step": results[p]["ms_per_step"],
-                   "rel_l2": rel.get(p), "roofline": roofline(p),
+                   "step_ms": results[p]["step_ms"], "rel_l2": rel.get(p), "roofline": roofline(p),
                    "speedup_vs_" + head: results[head]["ms_per_step"] / results[p]["ms_per_step"]
                    if hr else None}
     if adjoint:
