@@ -510,7 +510,8 @@ def time_fmm(S, W, t, steps, warmup):
     vessel (every point a source and a target, no pair rule) by the FMM on a
     uniform octree of depth 6, at surface orders 4 and 6, against the direct
     sum (timed once; its 4.4e12 pairs are the O(N^2) baseline) on a seeded
-    sample of 2,000 targets for the error."""
+    sample of 2,000 targets for the error.  Each order also runs with
+    precision="mixed" (float32 near-field pairs)."""
     import torch
 
     cfg = W.make_config(4)
@@ -539,6 +540,17 @@ def time_fmm(S, W, t, steps, warmup):
         r[f"order{order}_ms"] = ms
         r[f"order{order}_points_per_s"] = c.n / (ms * 1e-3)
         r[f"order{order}_rel_l2_vs_direct"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out, precision="mixed")
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out, precision="mixed")
+        e1.record()
+        torch.cuda.synchronize()
+        gm = out.cpu().numpy()[:, pick]
+        r[f"order{order}_mixed_ms"] = e0.elapsed_time(e1) / steps
+        r[f"order{order}_mixed_rel_l2_vs_direct"] = float(np.linalg.norm(gm - ref) / np.linalg.norm(ref))
+        r[f"order{order}_mixed_rel_l2_vs_fp64"] = float(np.linalg.norm(gm - got) / np.linalg.norm(got))
         del plan
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -570,6 +582,14 @@ def time_fmm(S, W, t, steps, warmup):
     torch.cuda.synchronize()
     r["dl_wall_to_cells_order6_ms"] = e0.elapsed_time(e1) / steps
     r["dl_wall_to_cells_order6_rel_l2_vs_direct"] = float(
+        np.linalg.norm(u5.cpu().numpy()[:, pick5] - ref5) / np.linalg.norm(ref5))
+    e0.record()
+    for _ in range(steps):
+        S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, depth, out=u5, precision="mixed")
+    e1.record()
+    torch.cuda.synchronize()
+    r["dl_wall_to_cells_order6_mixed_ms"] = e0.elapsed_time(e1) / steps
+    r["dl_wall_to_cells_order6_mixed_rel_l2_vs_direct"] = float(
         np.linalg.norm(u5.cpu().numpy()[:, pick5] - ref5) / np.linalg.norm(ref5))
     e0.record()
     S.dl(*args, cp, out=u5)

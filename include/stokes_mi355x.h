@@ -466,8 +466,11 @@ int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan
                               int64_t n_trg, int32_t depth, size_t* bytes);
 
 /* vel_out(3, n_trg) (=|+=) the single-layer sum of stokes_sl_eval (no pair
- * rule) by the FMM.  centre: HOST double[3]; half_width > 0.  opts.precision
- * must be STOKES_FP64.  Asynchronous on `stream`; the sources and targets are
+ * rule) by the FMM.  centre: HOST double[3]; half_width > 0.  opts.precision:
+ * STOKES_FP64, or STOKES_MIXED to run the near-field (leaf-to-leaf) pairs in
+ * float32 on offsets from the target leaf's centre, each staged tile's float32
+ * partial added into float64 (about 1e-7 relative, far below the FMM's own
+ * error); every other pass stays float64.  Asynchronous on `stream`; the sources and targets are
  * sorted into leaf order inside the workspace and the result is written in
  * the caller's order.  FP64 results are deterministic. */
 int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,

@@ -584,8 +584,15 @@ class FMMPlan:
             pass
 
 
-def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, accumulate=False):
-    """Single-layer sum by the FMM; see stokes_fmm_sl_eval."""
+def _fmm_precision(precision):
+    if precision not in ("fp64", "mixed"):
+        raise ValueError("precision must be 'fp64' or 'mixed'")
+    return C.MIXED if precision == "mixed" else C.FP64
+
+
+def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, accumulate=False, precision="fp64"):
+    """Single-layer sum by the FMM; see stokes_fmm_sl_eval.  precision "mixed"
+    runs the near-field pairs in float32."""
     device = src.device
     _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
     ns, nt = src.shape[1], trg.shape[1]
@@ -595,15 +602,16 @@ def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, ac
     C.check(C.lib().stokes_fmm_workspace_size(context(device), plan.handle, ns, nt, int(depth), ctypes.byref(size)))
     ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
     c = (ctypes.c_double * 3)(*[float(v) for v in centre])
-    opts = C.Opts(C.FP64, int(bool(accumulate)))
+    opts = C.Opts(_fmm_precision(precision), int(bool(accumulate)))
     C.check(C.lib().stokes_fmm_sl_eval(context(device), plan.handle, ns, _ptr(src), _ptr(f), _ptr(w), nt, _ptr(trg),
                                        float(mu), c, float(half_width), int(depth), ctypes.byref(opts), _ptr(out),
                                        _ptr(ws), int(size.value), _stream(device)))
     return out
 
 
-def fmm_dl(plan, src, phi, w, nrm, trg, centre, half_width, depth, out=None, accumulate=False):
-    """Double-layer sum by the FMM; see stokes_fmm_dl_eval."""
+def fmm_dl(plan, src, phi, w, nrm, trg, centre, half_width, depth, out=None, accumulate=False, precision="fp64"):
+    """Double-layer sum by the FMM; see stokes_fmm_dl_eval.  precision "mixed"
+    runs the near-field pairs in float32."""
     device = src.device
     _vec3(src, "src", device); _vec3(phi, "phi", device); _vec3(nrm, "nrm", device); _vec3(trg, "trg", device)
     ns, nt = src.shape[1], trg.shape[1]
@@ -613,7 +621,7 @@ def fmm_dl(plan, src, phi, w, nrm, trg, centre, half_width, depth, out=None, acc
     C.check(C.lib().stokes_fmm_workspace_size(context(device), plan.handle, ns, nt, int(depth), ctypes.byref(size)))
     ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
     c = (ctypes.c_double * 3)(*[float(v) for v in centre])
-    opts = C.Opts(C.FP64, int(bool(accumulate)))
+    opts = C.Opts(_fmm_precision(precision), int(bool(accumulate)))
     C.check(C.lib().stokes_fmm_dl_eval(context(device), plan.handle, ns, _ptr(src), _ptr(phi), _ptr(w), _ptr(nrm), nt,
                                        _ptr(trg), c, float(half_width), int(depth), ctypes.byref(opts), _ptr(out),
                                        _ptr(ws), int(size.value), _stream(device)))

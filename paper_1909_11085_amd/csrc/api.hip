@@ -1138,7 +1138,7 @@ static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, in
     if (!(isfinite(half_width) && half_width > 0.0)) return fail(STOKES_EINVAL, "half_width must be finite and > 0");
     Parsed p;
     if ((rc = parse_common(nullptr, opts, n_src, n_trg, p))) return rc;
-    if (p.precision != STOKES_FP64) return fail(STOKES_EUNSUPPORTED, "the FMM runs in float64 only");
+
     if ((rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz))) return rc;
     if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
     const size_t sb = (size_t)3 * n_src * 8, tb = (size_t)3 * n_trg * 8;
@@ -1164,6 +1164,7 @@ static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, in
     in.depth = depth;
     in.pref = pref;
     in.accumulate = p.accumulate;
+    in.mixed = p.precision == STOKES_MIXED;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const stokes::KernelTimer timer = stokes::next_timer(ctx);
     if (timer.on()) (void)hipEventRecord(timer.start, st);

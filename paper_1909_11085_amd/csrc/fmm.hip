@@ -531,10 +531,72 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
     }
 }
 
+// Mixed precision: float32 records of the sources' offsets from the item's
+// leaf centre (all sources of the 27 leaves lie within 3 leaf widths of it).
+template <int KT> struct NearRec32;
+template <> struct NearRec32<0> { using type = SrcSL32; };
+template <> struct NearRec32<1> { using type = SrcDL32; };
+
 template <int KT>
+__device__ __forceinline__ void load_source32(const FmmDev& a, int64_t m, const double* c,
+                                              typename NearRec32<KT>::type& r) {
+    r.ox = (float)(a.sx[m] - c[0]);
+    r.oy = (float)(a.sx[a.n_src + m] - c[1]);
+    r.oz = (float)(a.sx[2 * a.n_src + m] - c[2]);
+    r.qx = (float)a.sq[m];
+    r.qy = (float)a.sq[a.n_src + m];
+    r.qz = (float)a.sq[2 * a.n_src + m];
+    r.t2 = 0.0f;
+    r.g = 0;
+    if constexpr (KT == 1) {
+        r.nx = (float)a.sn[m];
+        r.ny = (float)a.sn[a.n_src + m];
+        r.nz = (float)a.sn[2 * a.n_src + m];
+        r.pad = 0.0f;
+    }
+}
+
+template <typename Rec>
+__device__ __forceinline__ Rec far_pad32() {
+    Rec r{};
+    r.ox = r.oy = r.oz = kPadOff;
+    return r;
+}
+
+// float32 pair on leaf-centred offsets (8 pi mu units); MASKED: a zero
+// distance (the same point, which rounds to the same offset) adds nothing.
+template <int KT, bool MASKED>
+__device__ __forceinline__ void near_pair32(const typename NearRec32<KT>::type& s, float x, float y, float z,
+                                            float* b) {
+    const float dx = x - s.ox, dy = y - s.oy, dz = z - s.oz;
+    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+    const float ri = (MASKED && r2 == 0.0f) ? 0.0f : __builtin_amdgcn_rsqf(r2);
+    const float ri2 = ri * ri;
+    const float rq = __builtin_fmaf(dx, s.qx, __builtin_fmaf(dy, s.qy, dz * s.qz));
+    if constexpr (KT == 0) {
+        const float c = rq * ri2;
+        b[0] = __builtin_fmaf(__builtin_fmaf(c, dx, s.qx), ri, b[0]);
+        b[1] = __builtin_fmaf(__builtin_fmaf(c, dy, s.qy), ri, b[1]);
+        b[2] = __builtin_fmaf(__builtin_fmaf(c, dz, s.qz), ri, b[2]);
+    } else {
+        const float rn = __builtin_fmaf(dx, s.nx, __builtin_fmaf(dy, s.ny, dz * s.nz));
+        const float c = 6.0f * rn * rq * (ri2 * ri2 * ri);
+        b[0] = __builtin_fmaf(c, dx, b[0]);
+        b[1] = __builtin_fmaf(c, dy, b[1]);
+        b[2] = __builtin_fmaf(c, dz, b[2]);
+    }
+}
+
+// MIXED: the P2P pairs in float32 on leaf-centred offsets, each staged tile's
+// float32 partial added into float64; L2P stays float64 (the downward density
+// comes out of a pseudo-inverse and may carry large cancelling terms).
+template <int KT, int MIXED>
 __global__ __launch_bounds__(kWave) void near_kernel(FmmDev a, NearArgs na) {
     using Rec = typename NearRec<KT>::type;
+    using Rec32 = typename NearRec32<KT>::type;
+    static_assert(sizeof(Rec32) <= sizeof(Rec), "the float32 records share the staging buffer");
     __shared__ Rec s_rec[kNearSlots];
+    Rec32* s_r32 = reinterpret_cast<Rec32*>(s_rec);
     __shared__ int64_t s_beg[27], s_pre[28];
     SrcSL64* s_sl = reinterpret_cast<SrcSL64*>(s_rec);
     const int lane = threadIdx.x;
@@ -582,19 +644,36 @@ __global__ __launch_bounds__(kWave) void near_kernel(FmmDev a, NearArgs na) {
             __builtin_amdgcn_wave_barrier();
         }
 
+        // the target's offset from the leaf centre, for the float32 pairs
+        const float xs = (float)(x - ctr[0]), ys = (float)(y - ctr[1]), zs = (float)(z - ctr[2]);
+        (void)xs; (void)ys; (void)zs;
+
         // the leaf's own sources, with the zero-distance mask
         {
             const int64_t s0 = a.sofs[L], s1 = a.sofs[L + 1];
             for (int64_t b0 = s0; b0 < s1; b0 += kNearTile) {
                 const int nb = (int)min((int64_t)kNearTile, s1 - b0);
-                for (int j = lane; j < kNearSlots; j += kWave) {
-                    Rec r = far_pad<Rec>();
-                    if (j < nb) load_source<KT>(a, b0 + j, r);
-                    s_rec[j] = r;
-                }
-                __builtin_amdgcn_wave_barrier();
                 const int steps = (nb + R - 1) / R;
-                for (int st = 0; st < steps; ++st) near_pair<KT, true>(s_rec[st * R + hp], x, y, z, u);
+                if constexpr (MIXED != 0) {
+                    for (int j = lane; j < kNearSlots; j += kWave) {
+                        Rec32 r = far_pad32<Rec32>();
+                        if (j < nb) load_source32<KT>(a, b0 + j, ctr, r);
+                        s_r32[j] = r;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    float bsum[3] = {0.0f, 0.0f, 0.0f};
+                    for (int st = 0; st < steps; ++st) near_pair32<KT, true>(s_r32[st * R + hp], xs, ys, zs, bsum);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) u[c] += (double)bsum[c];
+                } else {
+                    for (int j = lane; j < kNearSlots; j += kWave) {
+                        Rec r = far_pad<Rec>();
+                        if (j < nb) load_source<KT>(a, b0 + j, r);
+                        s_rec[j] = r;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    for (int st = 0; st < steps; ++st) near_pair<KT, true>(s_rec[st * R + hp], x, y, z, u);
+                }
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -621,8 +700,9 @@ __global__ __launch_bounds__(kWave) void near_kernel(FmmDev a, NearArgs na) {
         const int64_t total = s_pre[27];
         for (int64_t f0 = 0; f0 < total; f0 += kNearTile) {
             const int nb = (int)min((int64_t)kNearTile, total - f0);
+            const int steps = (nb + R - 1) / R;
             for (int j = lane; j < kNearSlots; j += kWave) {
-                Rec r = far_pad<Rec>();
+                int64_t m = -1;
                 if (j < nb) {
                     const int64_t f = f0 + j;
                     int lo = 0, hi = 27;                   // s_pre[lo] <= f < s_pre[hi]
@@ -630,14 +710,29 @@ __global__ __launch_bounds__(kWave) void near_kernel(FmmDev a, NearArgs na) {
                         const int mid = (lo + hi) >> 1;
                         if (s_pre[mid] <= f) lo = mid; else hi = mid;
                     }
-                    load_source<KT>(a, s_beg[lo] + (f - s_pre[lo]), r);
+                    m = s_beg[lo] + (f - s_pre[lo]);
                 }
-                s_rec[j] = r;
+                if constexpr (MIXED != 0) {
+                    Rec32 r = far_pad32<Rec32>();
+                    if (m >= 0) load_source32<KT>(a, m, ctr, r);
+                    s_r32[j] = r;
+                } else {
+                    Rec r = far_pad<Rec>();
+                    if (m >= 0) load_source<KT>(a, m, r);
+                    s_rec[j] = r;
+                }
             }
             __builtin_amdgcn_wave_barrier();
-            const int steps = (nb + R - 1) / R;
+            if constexpr (MIXED != 0) {
+                float bsum[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll 2
-            for (int st = 0; st < steps; ++st) near_pair<KT, false>(s_rec[st * R + hp], x, y, z, u);
+                for (int st = 0; st < steps; ++st) near_pair32<KT, false>(s_r32[st * R + hp], xs, ys, zs, bsum);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) u[c] += (double)bsum[c];
+            } else {
+#pragma unroll 2
+                for (int st = 0; st < steps; ++st) near_pair<KT, false>(s_rec[st * R + hp], x, y, z, u);
+            }
             __builtin_amdgcn_wave_barrier();
         }
 
@@ -1587,8 +1682,13 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     if (chk()) {
         const NearArgs na{items, n_items};
         const dim3 g(f_grid(L.max_items));
-        if (dl) hipLaunchKernelGGL(near_kernel<1>, g, dim3(kWave), 0, st, a, na);
-        else hipLaunchKernelGGL(near_kernel<0>, g, dim3(kWave), 0, st, a, na);
+        if (dl) {
+            if (in.mixed) hipLaunchKernelGGL((near_kernel<1, 1>), g, dim3(kWave), 0, st, a, na);
+            else hipLaunchKernelGGL((near_kernel<1, 0>), g, dim3(kWave), 0, st, a, na);
+        } else {
+            if (in.mixed) hipLaunchKernelGGL((near_kernel<0, 1>), g, dim3(kWave), 0, st, a, na);
+            else hipLaunchKernelGGL((near_kernel<0, 0>), g, dim3(kWave), 0, st, a, na);
+        }
     }
     chk();
     return e;

@@ -36,6 +36,7 @@ struct FmmInputs {
     int depth;
     double pref;               // 1 / (8 pi mu) (single layer) or 1 / (8 pi) (double layer)
     int accumulate;
+    int mixed;                 // near-field pairs in float32
 };
 
 size_t fmm_workspace_bytes(int order, int64_t n_src, int64_t n_trg, int depth);

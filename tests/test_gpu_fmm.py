@@ -208,6 +208,42 @@ def test_m2l_paths_match_oracle(plans, layout):
     assert rel_l2(got, ref) < ORACLE_TOL[4], rel_l2(got, ref)
 
 
+# float32 near-field pairs against the float64 FMM.  An offset of size d from
+# the leaf centre carries 2^-24 d, so a pair at distance rho errs by about
+# 6e-8 d / rho relative, times the kernel's degree (1 for the single layer, 5
+# for the double layer's r^3 / rho^5).  This cloud puts targets 0.01 from
+# sources in leaves 0.25 wide: measured 5.3e-6 for the double layer.
+MIXED_VS_FP64 = {"sl": 1e-6, "dl": 2e-5}
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_mixed_near_field(plans, kernel):
+    """precision="mixed" (float32 near-field pairs) against the float64 FMM on
+    the same tree, and against the direct sum within the FMM's error.  The
+    cloud has coincident sources and targets (the zero-distance mask in
+    float32)."""
+    rng = np.random.default_rng(85)
+    n = 60_000
+    src = rng.uniform(-2, 2, (3, n))
+    src[:, : n // 2] = 0.4 * rng.standard_normal((3, n // 2)).clip(-4.9, 4.9)
+    f, w, nrm = rng.standard_normal((3, n)), rng.uniform(0.5, 1.0, n), _normals(86, n)
+    trg = src[:, ::5].copy()
+    trg[:, ::2] += 0.01
+    S_, F_, W_, N_, T_ = dev(src), dev(f), dev(w), dev(nrm), dev(trg)
+    if kernel == "sl":
+        run = lambda prec: host(S.fmm_sl(plans[4], S_, F_, W_, T_, (0.0, 0.0, 0.0), 2.0001, 4, precision=prec))
+        ref = host(S.sl(S_, F_, W_, T_))
+        bar = FMM_ERR[4]
+    else:
+        run = lambda prec: host(S.fmm_dl(plans[4], S_, F_, W_, N_, T_, (0.0, 0.0, 0.0), 2.0001, 4, precision=prec))
+        ref = host(S.dl(S_, F_, W_, N_, T_))
+        bar = FMM_ERR_DL[4]
+    mixed, fp64 = run("mixed"), run("fp64")
+    assert np.all(np.isfinite(mixed))
+    assert rel_l2(mixed, fp64) < MIXED_VS_FP64[kernel], rel_l2(mixed, fp64)
+    assert rel_l2(mixed, ref) < bar
+
+
 def test_edge_cases(plans):
     src, f, w, trg = _cloud(75, 500, 100)
     P = plans[4]
@@ -250,7 +286,7 @@ def test_rejections(plans):
     assert run(mu=0.0) == C.EINVAL
     assert run(centre=None) == C.EINVAL
     assert run(hw=-1.0) == C.EINVAL
-    assert run(opts=C.Opts(C.MIXED, 0)) == C.EUNSUPPORTED
+    assert run(opts=C.Opts(7, 0)) == C.EINVAL
     assert run(wsb=size.value - 1) == C.EWORKSPACE
     torch.cuda.synchronize()
     assert bool((out == 9.0).all())
