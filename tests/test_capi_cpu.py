@@ -24,7 +24,7 @@ def test_version():
 def test_create_reports_device_status():
     h = ctypes.c_void_p()
     rc = C.lib().stokes_create(ctypes.byref(h), 0)
-    if rc == C.OK:           # a GPU is present (GPU machine): release it
+    if rc == C.OK:           # a GPU is present: release it
         C.lib().stokes_destroy(h)
         pytest.skip("a device is present; the no-device path is not reachable here")
     assert rc in (C.EDEVICE, C.EUNSUPPORTED)
