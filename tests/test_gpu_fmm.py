@@ -216,6 +216,30 @@ def test_m2l_paths_match_oracle(plans, layout):
 MIXED_VS_FP64 = {"sl": 1e-6, "dl": 2e-5}
 
 
+def test_fmm_minus_self_cells_is_the_excluded_sum(plans):
+    """The paper sums every pair by the FMM and replaces each cell's own terms
+    by its singular quadrature.  Without that replacement: the FMM over all
+    pairs minus each cell's sum onto itself (the leaf P2P with every cell a
+    leaf whose list is itself) equals the direct sum with the same-cell rule,
+    within the FMM's error (taken against the smaller excluded sum).  128
+    cells, 69,632 points."""
+    cfg = W.make_config(3)
+    c = cfg["cells"]
+    g = c.group
+    assert np.all(np.diff(g) >= 0)                       # points come cell by cell
+    n_cells = int(g.max()) + 1
+    ofs = np.searchsorted(g, np.arange(n_cells + 1)).astype(np.int64)
+    own = S.P2PPlan(ofs, ofs, np.arange(n_cells + 1, dtype=np.int64), np.arange(n_cells, dtype=np.int32), c.n, c.n)
+    pos, f, w = dev(c.pos), dev(cfg["f"]), dev(c.weight)
+    lo, hi = c.pos.min(axis=1), c.pos.max(axis=1)
+    ctr, R = 0.5 * (lo + hi), 0.5 * float((hi - lo).max()) * 1.0001
+    u = S.fmm_sl(plans[6], pos, f, w, pos, tuple(ctr), R, 4)
+    u -= S.p2p_leaf(own, pos, f, w, pos, kernel="sl")
+    grp = torch.as_tensor(g, dtype=torch.int32, device=device())
+    ref = host(S.sl(pos, f, w, pos, src_group=grp, trg_group=grp, exclude_same_group=True))
+    assert rel_l2(host(u), ref) < 3 * FMM_ERR[6], rel_l2(host(u), ref)
+
+
 @pytest.mark.parametrize("kernel", ["sl", "dl"])
 def test_mixed_near_field(plans, kernel):
     """precision="mixed" (float32 near-field pairs) against the float64 FMM on
