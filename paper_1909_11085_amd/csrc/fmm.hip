@@ -297,8 +297,7 @@ __device__ __forceinline__ void store_check(const FmmDev& a, const double* part,
 }
 
 // Flux sum of n . q over a leaf's sources: per wave over a strided quarter,
-// then the four waves in order (written to sig by thread 0; read back after
-// the workgroup barrier in finish-free code below).
+// then the four waves in order; every thread gets the total.
 __device__ __forceinline__ double leaf_flux(const FmmDev& a, int64_t m0, int64_t m1, double* red) {
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     double f = 0.0;
@@ -793,10 +792,10 @@ int64_t max_items(int64_t n_trg, int64_t n_leaves) { return (n_trg + kWave - 1) 
 // to the check points.  Then per level and class the check vectors times h are
 // V = A_c E, E gathered from the per-box densities, and the downward density
 // is DOWN V (the h cancels).  Both products run as FP64 MFMA 16x16x4 tiles of
-// 32 boxes: A read directly from memory in the MFMA operand layout, E staged
-// through LDS in chunks of 16 K rows (double-buffered).  Workgroup w takes
-// class w & 7: consecutive workgroups are dealt round-robin to the eight
-// XCDs, so each class's A_c stays in one XCD's L2.
+// 64 boxes, A and the gathered E staged through double-buffered LDS in chunks
+// of 16 K rows.  Workgroup w takes class w & 7: consecutive workgroups are
+// dealt round-robin to the eight XCDs, so each class's A_c stays in one XCD's
+// L2.
 constexpr int kILSize = 189;
 constexpr int kM2LBlocks = kILSize + 1;
 constexpr int kGemmNT = 64;          // boxes per tile
@@ -866,16 +865,8 @@ __global__ __launch_bounds__(kFBlock) void m2l_matrix_kernel(const double* __res
     }
 }
 
-// C(:, j) = A B(:, j) for the 64 columns of a tile, over the K chunks
-// chunk(0) .. chunk(n - 1) of kGemmKC rows each.  A: K x mp, k-major
-// (A[k * mp + row]), mp = 16 RB.  Each chunk of A and of B goes through LDS,
-// the next one prefetched into registers while the current one is multiplied.
-// loadb(q, j, k) gives row k of chunk q for column j; busy(t, g) is false when
-// chunk t is zero for all 16 columns of group g (that wave skips its
-// products).  Eight waves: wave w
-// owns columns 16 (w & 3) .. + 15 and row blocks (w >> 2) H .. + H - 1,
-// H = ceil(RB / 2); acc[i] holds row block (w >> 2) H + i, lane l, entry r
-// being row (l >> 4) + 4 r and column 16 (w & 3) + (l & 15).
+// Tile shape of the GEMMs for mp = 16 RB rows: H row blocks per wave half, na
+// doubles per A chunk, APT of them loaded per thread.
 template <int RB> struct GemmShape {
     static constexpr int mp = 16 * RB, H = (RB + 1) / 2, na = kGemmKC * mp;
     static constexpr int APT = (na + kGemmThreads - 1) / kGemmThreads;
