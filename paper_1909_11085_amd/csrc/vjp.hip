@@ -194,7 +194,9 @@ struct SlSym {
         const double rgm = dot3(dx, dy, dz, s.gx, s.gy, s.gz);
         const double rgp = dot3(dx, dy, dz, v[0], v[1], v[2]);
         const double rqp = dot3(dx, dy, dz, v[3], v[4], v[5]);
-        const double ab = dot3(v[0], v[1], v[2], s.qx, s.qy, s.qz) + dot3(v[3], v[4], v[5], s.gx, s.gy, s.gz);
+        // g_p . q_m + q_p . g_m as one chain of six products
+        const double ab = __builtin_fma(v[0], s.qx, __builtin_fma(v[1], s.qy, __builtin_fma(v[2], s.qz,
+                          __builtin_fma(v[3], s.gx, __builtin_fma(v[4], s.gy, v[5] * s.gz)))));
         const double sgm = rgm * ri3;
         // B += S(r) g_m
         acc[0] = __builtin_fma(s.gx, ri, __builtin_fma(sgm, dx, acc[0]));
@@ -622,7 +624,13 @@ __global__ __launch_bounds__(kBlock) void dl_phi_store(const double* __restrict_
 // launch shapes (targets per lane, minimum waves per SIMD)
 constexpr int kTSlT = 4, kWSlT = 3;
 constexpr int kTSlS = 2, kWSlS = 4;
-constexpr int kTSym = 2, kWSym = 3;
+#ifndef STOKES_SYM_T
+#define STOKES_SYM_T 3
+#endif
+#ifndef STOKES_SYM_W
+#define STOKES_SYM_W 2
+#endif
+constexpr int kTSym = STOKES_SYM_T, kWSym = STOKES_SYM_W;
 constexpr int kTDlT = 4, kWDlT = 3;
 constexpr int kTDlS = 2, kWDlS = 3;
 constexpr int kTSlSF = 4, kWSlSF = 4;
