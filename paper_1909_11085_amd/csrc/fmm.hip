@@ -191,15 +191,6 @@ __device__ __forceinline__ void dl_pair(double rx, double ry, double rz, double 
     u[2] = __builtin_fma(c, rz, u[2]);
 }
 
-__device__ __forceinline__ void stokeslet(double rx, double ry, double rz, double qx, double qy, double qz,
-                                          double* u) {
-    sl_pair<true>(rx, ry, rz, qx, qy, qz, u);
-}
-__device__ __forceinline__ void stresslet(double rx, double ry, double rz, double nx, double ny, double nz, double qx,
-                                          double qy, double qz, double* u) {
-    dl_pair<true>(rx, ry, rz, nx, ny, nz, qx, qy, qz, u);
-}
-
 // 8 pi times the velocity of a point source of flux sigma: 2 sigma r / rho^3.
 __device__ __forceinline__ void point_source(double rx, double ry, double rz, double sigma, double* u) {
     const double r2 = __builtin_fma(rx, rx, __builtin_fma(ry, ry, rz * rz));
@@ -1159,9 +1150,12 @@ __global__ __launch_bounds__(kFBlock) void m2l_pairs_kernel(FmmDev a, M2LArgs g,
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     SrcSL64* mine = stage + wave * a.ns;
-    const int64_t nb = (int64_t)1 << (3 * l), np = (int64_t)1 << (l - 1), P = nb >> 3;
-    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        if (!a.tpr[a.base[l] + b]) continue;                      // uniform over the workgroup
+    const int64_t np = (int64_t)1 << (l - 1), listed = *g.ctotal;
+    // the listed target boxes one after another (the list is compact, so the
+    // workgroups share the boxes evenly whatever the tree's occupancy); box i
+    // of the list owns column i of the check matrix
+    for (int64_t i = blockIdx.x; i < listed; i += gridDim.x) {
+        const int64_t b = g.list[i];
         double ctr[3], h;
         box_centre(a, l, b, ctr, h);
         const int64_t idx[3] = {compact3(b), compact3(b >> 1), compact3(b >> 2)};
@@ -1218,7 +1212,7 @@ __global__ __launch_bounds__(kFBlock) void m2l_pairs_kernel(FmmDev a, M2LArgs g,
         }
         __syncthreads();                           // the partial vectors overwrite the staging slices
         store_partial<T>(a, part, wave, lane, u);
-        store_check(a, part, h, g.cscan[(b & 7) * P + (b >> 3)]);
+        store_check(a, part, h, i);
     }
 }
 
