@@ -146,7 +146,6 @@ struct FmmDev {
     int accumulate;
     double* out;
     double* vbuf;              // check vectors times h, one column of mp per listed box
-    const int64_t* pos;        // column of each box of the current level (upward pass)
     int mp;
 };
 
@@ -421,7 +420,8 @@ size_t m2m_lds(int ns) {
 // of each tile at its T check points per lane (zero-distance mask: a point
 // outside the root cube is counted in a boundary leaf and may sit anywhere).
 template <int KT, int T>
-__global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
+__global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a, const int32_t* __restrict__ list,
+                                                      const int64_t* __restrict__ n_listed) {
     using Rec = typename NearRec<KT>::type;
     extern __shared__ double sh[];
     double* surf = sh;
@@ -430,12 +430,9 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
     __shared__ double red[kFWaves];
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int64_t nl = (int64_t)1 << (3 * a.D);
-    for (int64_t b = blockIdx.x; b < nl; b += gridDim.x) {            // uniform over the workgroup
-        if (!a.snz[a.base[a.D] + b]) {
-            if (KT == 1 && threadIdx.x == 0) a.sig[a.base[a.D] + b] = 0.0;
-            continue;
-        }
+    const int64_t listed = *n_listed;
+    for (int64_t i = blockIdx.x; i < listed; i += gridDim.x) {        // uniform over the workgroup
+        const int64_t b = list[i];                                    // the i-th leaf holding sources
         double ctr[3], h;
         box_centre(a, a.D, b, ctr, h);
         const int64_t m0 = a.sofs[b], m1 = a.sofs[b + 1];
@@ -462,14 +459,15 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a) {
             for (int k = 0; k < T; ++k)
                 point_source(x[k][0] - ctr[0], x[k][1] - ctr[1], x[k][2] - ctr[2], -sigma, u[k]);
         store_partial<T>(a, part, wave, lane, u);
-        store_check(a, part, h, a.pos[b]);
+        store_check(a, part, h, i);
     }
 }
 
 // M2M: wave w takes children w and w + 4, stages each child's equivalent
 // sources in its own LDS slice and sums them at its T check points per lane.
 template <int T>
-__global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
+__global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l, const int32_t* __restrict__ list,
+                                                      const int64_t* __restrict__ n_listed) {
     extern __shared__ double sh[];
     double* surf = sh;
     SrcSL64* stage = reinterpret_cast<SrcSL64*>(surf + ((3 * a.ns + 1) & ~1));
@@ -477,12 +475,9 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     SrcSL64* mine = stage + wave * a.ns;
-    const int64_t nb = (int64_t)1 << (3 * l);
-    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        if (!a.snz[a.base[l] + b]) {
-            if (a.sig && threadIdx.x == 0) a.sig[a.base[l] + b] = 0.0;
-            continue;
-        }
+    const int64_t listed = *n_listed;
+    for (int64_t i = blockIdx.x; i < listed; i += gridDim.x) {
+        const int64_t b = list[i];                                    // the i-th box holding sources
         double ctr[3], h;
         box_centre(a, l, b, ctr, h);
         double sigma = 0.0;                       // the children's fluxes, in a fixed order
@@ -517,7 +512,7 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l) {
             __builtin_amdgcn_wave_barrier();   // reads of this child precede the next writes
         }
         store_partial<T>(a, part, wave, lane, u);
-        store_check(a, part, h, a.pos[b]);
+        store_check(a, part, h, i);
     }
 }
 
@@ -1250,11 +1245,16 @@ __global__ __launch_bounds__(kGemmThreads) void apply_gemm_kernel(FmmDev a, M2LA
 }
 
 // Boxes of level l that hold sources, in index order: flags, then (after a
-// scan) the list.
+// scan) the list.  The flags pass also sets the flux of the boxes without
+// sources to zero (P2M and M2M visit only the listed boxes; M2M adds the flux
+// of all eight children).
 __global__ __launch_bounds__(kFBlock) void src_flags_kernel(FmmDev a, int l, int64_t* __restrict__ f) {
     const int64_t nb = (int64_t)1 << (3 * l);
-    for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
-        f[b] = a.snz[a.base[l] + b] ? 1 : 0;
+    for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock) {
+        const bool has = a.snz[a.base[l] + b] != 0;
+        f[b] = has ? 1 : 0;
+        if (!has && a.sig) a.sig[a.base[l] + b] = 0.0;
+    }
 }
 __global__ __launch_bounds__(kFBlock) void src_list_kernel(FmmDev a, int l, const int64_t* __restrict__ scan,
                                                            int32_t* __restrict__ list) {
@@ -1567,7 +1567,6 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     g2.sched = reinterpret_cast<int64_t*>(ws + L.off_sched);
     g2.npairs = reinterpret_cast<int64_t*>(ws + L.off_sched + 16);
     a.vbuf = g2.vbuf;
-    a.pos = g2.cscan;
     a.mp = plan->mp;
     const int rb = plan->mp / 16;
     // OP V for the listed boxes of a level, into out (rows n3 per box)
@@ -1583,7 +1582,7 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         }
         return chk();
     };
-    // the boxes of level l holding sources: a.pos (column of each box) and the list
+    // the boxes of level l holding sources: g2.list (box i of the list owns column i)
     auto list_sources = [&](int l) {
         const int64_t nb = (int64_t)1 << (3 * l);
         const unsigned gb = f_grid((nb + kFBlock - 1) / kFBlock);
@@ -1602,13 +1601,13 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         const dim3 g(f_grid(L.n_leaves));
         const size_t lds = p2m_lds(ns, dl ? 1 : 0);
         if (dl) {
-            if (T == 1) hipLaunchKernelGGL((p2m_kernel<1, 1>), g, dim3(kFBlock), lds, st, a);
-            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<1, 2>), g, dim3(kFBlock), lds, st, a);
-            else hipLaunchKernelGGL((p2m_kernel<1, 3>), g, dim3(kFBlock), lds, st, a);
+            if (T == 1) hipLaunchKernelGGL((p2m_kernel<1, 1>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
+            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<1, 2>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
+            else hipLaunchKernelGGL((p2m_kernel<1, 3>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
         } else {
-            if (T == 1) hipLaunchKernelGGL((p2m_kernel<0, 1>), g, dim3(kFBlock), lds, st, a);
-            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<0, 2>), g, dim3(kFBlock), lds, st, a);
-            else hipLaunchKernelGGL((p2m_kernel<0, 3>), g, dim3(kFBlock), lds, st, a);
+            if (T == 1) hipLaunchKernelGGL((p2m_kernel<0, 1>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
+            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<0, 2>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
+            else hipLaunchKernelGGL((p2m_kernel<0, 3>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
         }
         if (chk()) apply(D, plan->d_upA, a.ue + L.base[D] * a.n3);
     }
@@ -1616,9 +1615,9 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         if (!list_sources(l)) break;
         const dim3 g(f_grid((int64_t)1 << (3 * l)));
         const size_t lds = m2m_lds(ns);
-        if (T == 1) hipLaunchKernelGGL(m2m_kernel<1>, g, dim3(kFBlock), lds, st, a, l);
-        else if (T == 2) hipLaunchKernelGGL(m2m_kernel<2>, g, dim3(kFBlock), lds, st, a, l);
-        else hipLaunchKernelGGL(m2m_kernel<3>, g, dim3(kFBlock), lds, st, a, l);
+        if (T == 1) hipLaunchKernelGGL(m2m_kernel<1>, g, dim3(kFBlock), lds, st, a, l, g2.list, g2.ctotal);
+        else if (T == 2) hipLaunchKernelGGL(m2m_kernel<2>, g, dim3(kFBlock), lds, st, a, l, g2.list, g2.ctotal);
+        else hipLaunchKernelGGL(m2m_kernel<3>, g, dim3(kFBlock), lds, st, a, l, g2.list, g2.ctotal);
         if (chk()) apply(l, plan->d_upA, a.ue + L.base[l] * a.n3);
     }
     for (int l = 2; l <= D && chk(); ++l) {
