@@ -756,6 +756,53 @@ __global__ __launch_bounds__(kFBlock) void items_kernel(const int64_t* __restric
     }
 }
 
+// The items are run longest first (a wave per item, so the last items to
+// start set the end of the kernel): the key of an item is its pair-loop
+// steps, the sources of its leaf's 27 neighbours plus the downward surface
+// over the R lanes each target gets, inverted so that an ascending sort puts
+// the longest first; the unused slots of the buffer get the top key.
+constexpr int kItemKeyBits = 24;
+__global__ __launch_bounds__(kFBlock) void item_keys_kernel(FmmDev a, const int32_t* __restrict__ items,
+                                                            const int64_t* __restrict__ n_items, int64_t n_slots,
+                                                            uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    constexpr uint64_t kTop = (1ull << kItemKeyBits) - 1;
+    const int64_t count = *n_items, nlx = (int64_t)1 << a.D;
+    for (int64_t it = (int64_t)blockIdx.x * kFBlock + threadIdx.x; it < n_slots; it += (int64_t)gridDim.x * kFBlock) {
+        uint64_t key = kTop;
+        if (it < count) {
+            const int64_t L = items[2 * it];
+            const int64_t t0 = a.tofs[L] + (int64_t)items[2 * it + 1] * kWave;
+            const int nc = (int)min(a.tofs[L + 1] - t0, (int64_t)kWave);
+            const int R = min(kNearRep, kWave / nc);
+            const int64_t c0 = compact3(L), c1 = compact3(L >> 1), c2 = compact3(L >> 2);
+            int64_t n = a.ns;
+            for (int d = 0; d < 27; ++d) {
+                const int64_t n0 = c0 + d / 9 - 1, n1 = c1 + (d / 3) % 3 - 1, n2 = c2 + d % 3 - 1;
+                if (n0 < 0 || n1 < 0 || n2 < 0 || n0 >= nlx || n1 >= nlx || n2 >= nlx) continue;
+                const uint64_t nb = morton(n0, n1, n2);
+                n += a.sofs[nb + 1] - a.sofs[nb];
+            }
+            const uint64_t steps = (uint64_t)((n + R - 1) / R);
+            key = kTop - 1 - min(steps, kTop - 1);
+        }
+        keys[it] = key;
+        vals[it] = (int32_t)it;
+    }
+}
+// The items in the sorted order (the first *n_items entries of order are the
+// real items).
+__global__ __launch_bounds__(kFBlock) void item_order_kernel(const int32_t* __restrict__ items,
+                                                             const int64_t* __restrict__ n_items,
+                                                             const int32_t* __restrict__ order,
+                                                             int32_t* __restrict__ sorted) {
+    const int64_t count = *n_items;
+    for (int64_t k = (int64_t)blockIdx.x * kFBlock + threadIdx.x; k < count; k += (int64_t)gridDim.x * kFBlock) {
+        const int64_t it = order[k];
+        sorted[2 * k] = items[2 * it];
+        sorted[2 * k + 1] = items[2 * it + 1];
+    }
+}
+
 // Upper bound of the near-field work items: every leaf with targets adds at
 // most one partial chunk to the full ones.
 int64_t max_items(int64_t n_trg, int64_t n_leaves) { return (n_trg + kWave - 1) / kWave + std::min(n_trg, n_leaves); }
@@ -1269,8 +1316,8 @@ struct FmmLayout {
     SortLayout sort;
     int64_t max_items = 0;
     size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_sn, off_tx, off_sofs, off_tofs,
-        off_snz, off_tpr, off_sig, off_ue, off_de, off_cofs, off_scan, off_items, off_nitems, off_cflag, off_cscan,
-        off_ctotal, off_clist, off_sched, off_vbuf, total;
+        off_snz, off_tpr, off_sig, off_ue, off_de, off_cofs, off_scan, off_items, off_ikeys, off_ivals, off_items2,
+        off_nitems, off_cflag, off_cscan, off_ctotal, off_clist, off_sched, off_vbuf, total;
 };
 
 FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
@@ -1283,7 +1330,8 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     }
     L.nbox = acc;
     L.n_leaves = (int64_t)1 << (3 * D);
-    L.sort = sort_layout(std::max(n_src, n_trg));
+    L.max_items = max_items(n_trg, L.n_leaves);
+    L.sort = sort_layout(std::max({n_src, n_trg, L.max_items}));
     size_t off = 0;
     auto take = [&off](size_t bytes) {
         const size_t at = off;
@@ -1306,10 +1354,12 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_sig = take((size_t)L.nbox * 8);
     L.off_ue = take((size_t)L.nbox * 3 * ns * 8);
     L.off_de = take((size_t)L.nbox * 3 * ns * 8);
-    L.max_items = max_items(n_trg, L.n_leaves);
     L.off_cofs = take((size_t)L.n_leaves * 8);
     L.off_scan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
     L.off_items = take((size_t)L.max_items * 2 * 4);
+    L.off_ikeys = take((size_t)L.max_items * 8);
+    L.off_ivals = take((size_t)L.max_items * 4);
+    L.off_items2 = take((size_t)L.max_items * 2 * 4);
     L.off_nitems = take(8);
     L.off_cflag = take((size_t)L.n_leaves * 8);
     L.off_cscan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
@@ -1556,6 +1606,18 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         if (e == hipSuccess)
             hipLaunchKernelGGL(items_kernel, dim3(gl), dim3(kFBlock), 0, st, a.tofs, cofs, L.n_leaves, items);
     }
+    // the same items, longest first
+    int32_t* items_sorted = reinterpret_cast<int32_t*>(ws + L.off_items2);
+    if (chk() && L.max_items > 0) {
+        uint64_t* ikeys = reinterpret_cast<uint64_t*>(ws + L.off_ikeys);
+        int32_t* ivals = reinterpret_cast<int32_t*>(ws + L.off_ivals);
+        const unsigned gi = f_grid((L.max_items + kFBlock - 1) / kFBlock);
+        hipLaunchKernelGGL(item_keys_kernel, dim3(gi), dim3(kFBlock), 0, st, a, items, n_items, L.max_items, ikeys,
+                           ivals);
+        if (chk()) e = radix_sort_pairs(ikeys, ivals, L.max_items, kItemKeyBits, sort_ws, L.sort, st);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(item_order_kernel, dim3(gi), dim3(kFBlock), 0, st, items, n_items, ivals, items_sorted);
+    }
     M2LArgs g2{};
     g2.A = plan->d_m2l;
     g2.il = plan->d_il;
@@ -1664,7 +1726,7 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         if (!apply(l, plan->d_downA, a.de + L.base[l] * a.n3)) break;
     }
     if (chk()) {
-        const NearArgs na{items, n_items};
+        const NearArgs na{items_sorted, n_items};
         const dim3 g(f_grid(L.max_items));
         if (dl) {
             if (in.mixed) hipLaunchKernelGGL((near_kernel<1, 1>), g, dim3(kWave), 0, st, a, na);
