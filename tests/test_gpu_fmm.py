@@ -300,6 +300,8 @@ def test_edge_cases(plans):
     P = plans[4]
     z = S.fmm_sl(P, dev(np.zeros((3, 0))), dev(np.zeros((3, 0))), dev(np.zeros(0)), dev(trg), (0, 0, 0), 1.0001, 2)
     assert not bool(z.abs().max())                       # no sources: zeros
+    e = S.fmm_sl(P, dev(src), dev(f), dev(w), dev(np.zeros((3, 0))), (0, 0, 0), 1.0001, 3)
+    assert tuple(e.shape) == (3, 0)                      # no targets: nothing to do
     base = torch.full((3, 100), 0.5, dtype=torch.float64, device=device())
     S.fmm_sl(P, dev(src), dev(f), dev(w), dev(trg), (0, 0, 0), 1.0001, 3, out=base, accumulate=True)
     one = host(S.fmm_sl(P, dev(src), dev(f), dev(w), dev(trg), (0, 0, 0), 1.0001, 3))
