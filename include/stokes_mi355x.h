@@ -461,7 +461,8 @@ void stokes_fmm_plan_destroy(stokes_fmm_plan* plan);
 /* Workspace for n_src sources, n_trg targets and depth (2..7): the per-box
  * densities grow as 8^depth * 6 * (6 (order-1)^2 + 2) doubles, the check
  * matrix of a level as 3 min(8^depth, max(n_src, n_trg)) + 262,656 columns of
- * m doubles (m as above). */
+ * m doubles (m as above), plus 32,768 columns of 3 (6 (order-1)^2 + 2) doubles
+ * for the split pseudo-inverse products. */
 int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,
                               int64_t n_trg, int32_t depth, size_t* bytes);
 

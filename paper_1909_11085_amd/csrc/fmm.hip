@@ -1269,26 +1269,57 @@ __global__ __launch_bounds__(kFBlock) void m2l_reduce_kernel(M2LArgs g) {
     }
 }
 
+// K splits of a level's pseudo-inverse product: a tile's K chunks run one
+// after another on one workgroup, so a level with few tiles splits K until
+// it has about kApplyUnits work units (at most one chunk per split).
+constexpr int kApplyUnits = 512;
+constexpr int kApplyReduceGrid = 1024;
+__device__ __forceinline__ int64_t apply_splits(int64_t tiles, int64_t nk) {
+    return tiles > 0 ? min(nk, max((int64_t)1, (int64_t)kApplyUnits / tiles)) : 1;
+}
+
 // out[list[j]] = OP V(:, j) for the listed boxes (OP padded to mp x mp,
-// k-major; out rows n3 per box): the pseudo-inverse of a whole level.
+// k-major; out rows n3 per box): the pseudo-inverse of a whole level.  Unit
+// u is tile u / S, K split u % S; with one split the tile writes out, with
+// more each split writes its partial (apply_reduce_kernel adds them).
 template <int RB>
 __global__ __launch_bounds__(kGemmThreads) void apply_gemm_kernel(FmmDev a, M2LArgs g, const double* __restrict__ op,
-                                                                  double* __restrict__ out) {
+                                                                  double* __restrict__ out, double* __restrict__ part) {
     using G = GemmShape<RB>;
     __shared__ double As[2 * G::na];
     __shared__ double Bs[2 * kGemmKC * kGemmNT];
-    const int64_t n = *g.ctotal;
-    const int64_t col0 = (int64_t)blockIdx.x * kGemmNT;
-    if (col0 >= n) return;
-    auto chunk = [](int64_t t) { return t; };
+    const int64_t n = *g.ctotal, nk = G::mp / kGemmKC;
+    const int64_t tiles = (n + kGemmNT - 1) / kGemmNT, S = apply_splits(tiles, nk);
+    const int64_t u = blockIdx.x;
+    if (u >= tiles * S) return;                                   // uniform over the workgroup
+    const int64_t col0 = (u / S) * kGemmNT, sp = u % S;
+    const int64_t k0 = sp * nk / S, k1 = (sp + 1) * nk / S;
+    auto chunk = [k0](int64_t t) { return k0 + t; };
     auto loadb = [&](int64_t q, int j, int bk) -> double {
         return col0 + j < n ? g.vbuf[(col0 + j) * G::mp + q * kGemmKC + bk] : 0.0;
     };
     auto busy = [](int64_t, int) { return true; };
     const int32_t* list = g.list;
-    gemm_tile_any<RB>(op, G::mp / kGemmKC, chunk, loadb, busy, As, Bs, a.n3, [&](int j, int row, double v) {
-        if (col0 + j < n) out[(int64_t)list[col0 + j] * a.n3 + row] = v;
+    gemm_tile_any<RB>(op, k1 - k0, chunk, loadb, busy, As, Bs, a.n3, [&](int j, int row, double v) {
+        if (col0 + j >= n) return;
+        if (S == 1) out[(int64_t)list[col0 + j] * a.n3 + row] = v;
+        else part[(sp * n + col0 + j) * a.n3 + row] = v;
     });
+}
+
+// The split partials of apply_gemm_kernel added in split order.
+__global__ __launch_bounds__(kFBlock) void apply_reduce_kernel(FmmDev a, M2LArgs g, int nk,
+                                                               const double* __restrict__ part,
+                                                               double* __restrict__ out) {
+    const int64_t n = *g.ctotal;
+    const int64_t S = apply_splits((n + kGemmNT - 1) / kGemmNT, nk);
+    if (S == 1) return;
+    const int64_t m = n * a.n3;
+    for (int64_t e = (int64_t)blockIdx.x * kFBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kFBlock) {
+        double v = part[e];
+        for (int64_t sp = 1; sp < S; ++sp) v += part[sp * m + e];
+        out[(int64_t)g.list[e / a.n3] * a.n3 + e % a.n3] = v;
+    }
 }
 
 // Boxes of level l that hold sources, in index order: flags, then (after a
@@ -1317,7 +1348,7 @@ struct FmmLayout {
     int64_t max_items = 0;
     size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_sn, off_tx, off_sofs, off_tofs,
         off_snz, off_tpr, off_sig, off_ue, off_de, off_cofs, off_scan, off_items, off_ikeys, off_ivals, off_items2,
-        off_nitems, off_cflag, off_cscan, off_ctotal, off_clist, off_sched, off_vbuf, total;
+        off_nitems, off_cflag, off_cscan, off_ctotal, off_clist, off_sched, off_vbuf, off_apart, total;
 };
 
 FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
@@ -1370,6 +1401,8 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_vbuf = take((size_t)(kM2LMinSplits * std::min(L.n_leaves, std::max<int64_t>({n_src, n_trg, 1})) +
                                kGemmNT * (kM2LUnits + 8)) *
                       mp * 8);
+    // split partials of the pseudo-inverse products: S x listed <= kApplyUnits x 64 columns when S > 1
+    L.off_apart = take((size_t)kApplyUnits * kGemmNT * 3 * ns * 8);
     L.total = off;
     return L;
 }
@@ -1632,16 +1665,22 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     a.mp = plan->mp;
     const int rb = plan->mp / 16;
     // OP V for the listed boxes of a level, into out (rows n3 per box)
+    double* apart = reinterpret_cast<double*>(ws + L.off_apart);
     auto apply = [&](int l, const double* op, double* out) {
-        const dim3 g((unsigned)((std::min<int64_t>((int64_t)1 << (3 * l), std::max(in.n_src, in.n_trg)) + kGemmNT - 1) /
-                                kGemmNT));
+        // units: tiles x splits <= max(tiles, kApplyUnits), tiles at most the bound below
+        const int64_t tiles_ub =
+            (std::min<int64_t>((int64_t)1 << (3 * l), std::max(in.n_src, in.n_trg)) + kGemmNT - 1) / kGemmNT;
+        const dim3 g((unsigned)std::max<int64_t>(tiles_ub, kApplyUnits));
         switch (rb) {
-            case 2: hipLaunchKernelGGL(apply_gemm_kernel<2>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
-            case 5: hipLaunchKernelGGL(apply_gemm_kernel<5>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
-            case 11: hipLaunchKernelGGL(apply_gemm_kernel<11>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
-            case 19: hipLaunchKernelGGL(apply_gemm_kernel<19>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
-            default: hipLaunchKernelGGL(apply_gemm_kernel<29>, g, dim3(kGemmThreads), 0, st, a, g2, op, out); break;
+            case 2: hipLaunchKernelGGL(apply_gemm_kernel<2>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
+            case 5: hipLaunchKernelGGL(apply_gemm_kernel<5>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
+            case 11: hipLaunchKernelGGL(apply_gemm_kernel<11>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
+            case 19: hipLaunchKernelGGL(apply_gemm_kernel<19>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
+            default: hipLaunchKernelGGL(apply_gemm_kernel<29>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
         }
+        if (!chk()) return false;
+        // a strided pass: most levels have one split, and then every workgroup just exits
+        hipLaunchKernelGGL(apply_reduce_kernel, dim3(kApplyReduceGrid), dim3(kFBlock), 0, st, a, g2, rb, apart, out);
         return chk();
     };
     // the boxes of level l holding sources: g2.list (box i of the list owns column i)
