@@ -241,10 +241,13 @@ int stokes_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const d
  *   grad_src_xyz (3,n_src): dL/dy_m   = -d sum_n' G_nm
  *   grad_trg_xyz (3,n_trg): dL/dx_n   =  d sum_m' G_nm
  *   G = [(r.q)(r.g) n + (r.n)(r.g) q + (r.n)(r.q) g]/rho^5 - 5 (r.n)(r.q)(r.g) r/rho^7.
- * Outputs, precision and empty sets as stokes_sl_vjp.  When grad_density and
- * grad_trg_xyz are asked for without grad_src_xyz, one fused pass over the
- * pairs gives both; its grad_density is summed across target blocks with
- * float64 atomic adds (not bitwise reproducible from run to run). */
+ * Outputs, precision and empty sets as stokes_sl_vjp.  On a shared point set
+ * grad_src_xyz == grad_trg_xyz is allowed as there and receives the total
+ * position gradient dL/dy + dL/dx: the target-side pass writes (or adds, when
+ * accumulating) into it and the source-side pass adds to it.  When
+ * grad_density and grad_trg_xyz are asked for without grad_src_xyz, one fused
+ * pass over the pairs gives both; its grad_density is summed across target
+ * blocks with float64 atomic adds (not bitwise reproducible from run to run). */
 int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
                   const double* weight, const double* normal, int64_t n_trg,
                   const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,

@@ -713,7 +713,7 @@ static int vjp_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* sr
     in.grad_trg = grad_trg_xyz;
     const stokes::KernelTimer timer = stokes::next_timer(ctx);
     if (timer.on()) (void)hipEventRecord(timer.start, st);
-    hipError_t e = kernel ? stokes::launch_dl_vjp(in, ctx->vjp_resident, workspace, st)
+    hipError_t e = kernel ? stokes::launch_dl_vjp(in, ctx->vjp_resident, combined, workspace, st)
                           : stokes::launch_sl_vjp(in, ctx->vjp_resident, combined, workspace, st);
     if (timer.on()) (void)hipEventRecord(timer.stop, st);
     return launch_status(e, name);

@@ -59,6 +59,7 @@ struct PassArgs {
     double* out[3];
     double pref;
     int accumulate;
+    const double* force_acc;    // this output adds into its array whatever `accumulate` says
 };
 
 __device__ __forceinline__ double wmin(double v) {

@@ -45,7 +45,7 @@ __device__ __forceinline__ double ri_of(double r2, bool skip) {
 __device__ __forceinline__ void out3(const PassArgs& a, double* out, int64_t n, int64_t i, double s,
                                      double vx, double vy, double vz) {
     if (!out) return;
-    if (a.accumulate) {
+    if (a.accumulate || out == a.force_acc) {
         out[i] += s * vx;
         out[n + i] += s * vy;
         out[2 * n + i] += s * vz;
@@ -788,8 +788,8 @@ static hipError_t launch_dl_fused(const VjpInputs& in, int resident, void* ws, h
     return hipGetLastError();
 }
 
-hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], void* ws,
-                         hipStream_t stream) {
+hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], bool combined,
+                         void* ws, hipStream_t stream) {
     hipError_t e = hipSuccess;
     const KernelTimer none{};
     if (in.grad_trg && in.grad_density && !in.grad_src) return launch_dl_fused(in, resident[7], ws, stream);
@@ -826,6 +826,9 @@ hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], vo
         a.out[0] = in.grad_density;
         a.out[1] = in.grad_src;
         a.pref = in.pref;
+        // one array for both position gradients: the target side is already
+        // in it, so the source side adds to it
+        if (combined) a.force_acc = in.grad_src;
         if (in.grad_src) {
             const auto p = ps::plan_pass<DlS, kTDlS>(in.n_trg, in.n_src, resident[4]);
             e = ps::run_pass<DlS, kTDlS, kWDlS>(a, p, ws, stream, none);

@@ -36,7 +36,9 @@ size_t vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, const int r
 // grad_trg), one pass.  Requires n_src, n_trg > 0.
 hipError_t launch_sl_vjp(const VjpInputs& in, const int resident[kVjpPasses], bool fused, void* ws,
                          hipStream_t stream);
-hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], void* ws,
+// combined: grad_src == grad_trg on a shared point set; the array receives
+// the total position gradient (target pass, then the source pass adds).
+hipError_t launch_dl_vjp(const VjpInputs& in, const int resident[kVjpPasses], bool combined, void* ws,
                          hipStream_t stream);
 
 }  // namespace stokes

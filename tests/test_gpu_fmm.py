@@ -208,6 +208,66 @@ def test_m2l_paths_match_oracle(plans, layout):
     assert rel_l2(got, ref) < ORACLE_TOL[4], rel_l2(got, ref)
 
 
+@pytest.mark.parametrize("layout", ["filled", "separated"])
+def test_dl_m2l_paths_match_oracle(plans, layout):
+    """The double layer on both M2L paths at depth 3 against the oracle FMM:
+    the point-source flux of each box rides through M2M and both forms of
+    M2L.  Densities along the normals, so every box carries a net flux."""
+    rng = np.random.default_rng(93 if layout == "filled" else 94)
+    if layout == "filled":
+        src, trg = rng.uniform(-1, 1, (3, 3000)), rng.uniform(-0.3, 0.3, (3, 200))
+    else:
+        src, trg = rng.uniform(-1, -0.5, (3, 3000)), rng.uniform(0.5, 1, (3, 200))
+    fills = [_il_fill(src, trg, 1.0001, l) for l in (2, 3)]
+    if layout == "filled":
+        assert fills[1] >= M2L_DENSE_FILL, fills
+    else:
+        assert max(fills) < M2L_DENSE_FILL and fills[0] > 0, fills
+    nrm = _normals(95, 3000)
+    phi = nrm * rng.uniform(0.5, 1.5, 3000)
+    w = rng.uniform(0.5, 1.0, 3000)
+    got = host(S.fmm_dl(plans[4], dev(src), dev(phi), dev(w), dev(nrm), dev(trg), (0.0, 0.0, 0.0), 1.0001, 3))
+    ref = F.fmm_dl(src, phi, w, nrm, trg, np.zeros(3), 1.0001, 3, 4)
+    assert rel_l2(got, ref) < ORACLE_TOL[4], rel_l2(got, ref)
+    assert rel_l2(got, O.dl(src, phi, w, nrm, trg)) < FMM_ERR_DL[4]
+
+
+def _deep_inputs(kernel):
+    from tests.test_fmm_pins import _deep_cloud
+    src, f, w, trg = _deep_cloud(111)
+    nrm = None
+    if kernel == "dl":
+        rng = np.random.default_rng(112)
+        nrm = rng.standard_normal(src.shape)
+        nrm /= np.linalg.norm(nrm, axis=0)
+        f = nrm * rng.uniform(0.5, 1.5, src.shape[1])
+    return src, f, w, nrm, trg
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+@pytest.mark.parametrize("D", [3, 4])
+def test_deep_tree_matches_oracle(plans, kernel, D):
+    """Depths 3 and 4 against the oracle FMM (the layout of its deep-tree
+    pins: M2M, M2L and L2L at every level, targets on sources), in float64
+    and with float32 near-field pairs."""
+    src, f, w, nrm, trg = _deep_inputs(kernel)
+    if kernel == "sl":
+        ref = F.fmm_sl(src, f, w, trg, np.zeros(3), 1.0001, D, 4, mu=0.8)
+        run = lambda prec: host(S.fmm_sl(plans[4], dev(src), dev(f), dev(w), dev(trg), (0.0, 0.0, 0.0),
+                                         1.0001, D, mu=0.8, precision=prec))
+    else:
+        ref = F.fmm_dl(src, f, w, nrm, trg, np.zeros(3), 1.0001, D, 4)
+        run = lambda prec: host(S.fmm_dl(plans[4], dev(src), dev(f), dev(w), dev(nrm), dev(trg),
+                                         (0.0, 0.0, 0.0), 1.0001, D, precision=prec))
+    got = run("fp64")
+    e64 = rel_l2(got, ref)
+    assert e64 < ORACLE_TOL[4], e64
+    mixed = run("mixed")
+    e32 = rel_l2(mixed, ref)
+    assert np.all(np.isfinite(mixed)) and e32 < MIXED_VS_FP64[kernel], e32
+    print(f"deep tree {kernel} D={D}: fp64 {e64:.2e}, mixed {e32:.2e} vs the oracle FMM")
+
+
 # float32 near-field pairs against the float64 FMM.  An offset of size d from
 # the leaf centre carries 2^-24 d, so a pair at distance rho errs by about
 # 6e-8 d / rho relative, times the kernel's degree (1 for the single layer, 5

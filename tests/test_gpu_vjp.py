@@ -8,7 +8,7 @@ import torch
 import paper_1909_11085_amd as S
 from oracle import oracle as O
 from paper_1909_11085_amd import workloads as W
-from tests.gpu_util import FP64_TOL, assert_close, dev, device, host, rel_l2
+from tests.gpu_util import FP64_TOL, MIXED_TOL, assert_close, dev, device, host, rel_l2
 from tests.test_gpu_direct import _cloud
 
 pytestmark = pytest.mark.gpu
@@ -96,6 +96,26 @@ def test_sl_vjp_shared_fused(excl, n):
                           exclude_same_group=excl)
     assert_close(host(gf), rf, VJP_TOL, "fused dL/df")
     assert_close(host(gpos), rs + rt, VJP_TOL, "fused dL/dx total")
+
+
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_dl_vjp_shared_combined(accumulate):
+    """Double layer on a shared point set with one array for both position
+    gradients: it receives dL/dy + dL/dx (overwritten or added to)."""
+    n = 1500
+    c = _cloud(120, n, n, dup=0)
+    rng = np.random.default_rng(121)
+    g = rng.standard_normal((3, n))
+    base = rng.standard_normal((3, n)) if accumulate else np.zeros((3, n))
+    pos, grp = dev(c["y"]), dev(c["gs"])
+    gp, gpos = _z(n), dev(base.copy())
+    S.dl_vjp(pos, dev(c["f"]), dev(c["w"]), dev(c["n"]), pos, dev(g), src_group=grp, trg_group=grp,
+             exclude_same_group=True, grad_phi=gp, grad_src=gpos, grad_trg=gpos, accumulate=accumulate)
+    rp, rs, rt = O.dl_vjp(c["y"], c["f"], c["w"], c["n"], c["y"], g, src_group=c["gs"],
+                          trg_group=c["gs"], exclude_same_group=True)
+    if not accumulate:
+        assert_close(host(gp), rp, VJP_TOL, "dL/dphi")
+    assert_close(host(gpos) - base, rs + rt, VJP_TOL, "combined dL/dx total")
 
 
 @pytest.mark.parametrize("kernel", ["sl", "dl"])
@@ -262,6 +282,63 @@ def test_cfg5_wall_adjoint_sampled():
     r1 = assert_close(host(gt)[:, it], rt, VJP_TOL, "cfg5 dL/dx")
     r2 = assert_close(host(gp)[:, iw], rp, VJP_TOL, "cfg5 dL/dphi")
     print(f"cfg5 DL adjoint rel-L2: dL/dx {r1:.3e}, dL/dphi {r2:.3e}")
+
+
+@pytest.fixture(scope="module")
+def cfg5_oracle():
+    """The wall + cell workload and, on seeded samples, the oracle's
+    superposed velocity (eq. velocity_combined): the wall's double layer plus
+    the cells' single layer with the same-cell rule."""
+    cfg = W.make_config(5)
+    wall, cells = cfg["wall"], cfg["cells"]
+    it = W.subset(np.random.default_rng(515), cells.n, 256)
+    u = O.dl(wall.pos, cfg["phi"], wall.weight, wall.normal, cells.pos[:, it])
+    u += O.sl(cells.pos, cfg["f"], cells.weight, cells.pos[:, it], src_group=cells.group,
+              trg_group=cells.group[it], exclude_same_group=True)
+    return cfg, it, u
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg5_superposition_and_total_gradient(cfg5_oracle, precision):
+    """The whole coupling at full size (1,048,576 wall nodes, 522,240 cell
+    points): u = D[phi] + S[f] at the cell points by `accumulate` (mixed: the
+    wall's and the cells' near rules), L = 0.5 |u - u_ref|^2, and the FP64
+    adjoint: dL/dphi at the wall, dL/df at the cells, and the total dL/dx at
+    the cell points in one array (the double layer's target side, then the
+    single layer's shared-point pass added).  Seeded samples against the
+    oracle: 256 cell points and 256 wall nodes."""
+    print(f"case cfg5 coupling {precision}", flush=True)
+    cfg, it, u_ref_o = cfg5_oracle
+    wall, cells, phi, f, u_ref = cfg["wall"], cfg["cells"], cfg["phi"], cfg["f"], cfg["u_ref"]
+    wargs = (dev(wall.pos), dev(phi), dev(wall.weight), dev(wall.normal))
+    cpos, cf, cw, cg = dev(cells.pos), dev(f), dev(cells.weight), dev(cells.group)
+    u = S.dl(*wargs, cpos, src_group=dev(wall.group), exclude_same_group=False, precision=precision,
+             group_h=dev(wall.group_h))
+    S.sl(cpos, cf, cw, cpos, src_group=cg, trg_group=cg, precision=precision,
+         group_h=dev(cells.group_h), out=u, accumulate=True)
+    tol = MIXED_TOL if precision == "mixed" else FP64_TOL
+    r_u = assert_close(host(u)[:, it], u_ref_o, tol, f"cfg5 u ({precision})")
+    g = u - dev(u_ref)
+    gphi, gf, gx = _z(wall.n), dev(np.zeros((3, cells.n))), _z(cells.n)
+    S.dl_vjp(*wargs, cpos, g, grad_phi=gphi, grad_trg=gx)
+    S.sl_vjp(cpos, cf, cw, cpos, g, src_group=cg, trg_group=cg, grad_f=gf, grad_src=gx, grad_trg=gx,
+             accumulate=True)
+    gh = host(g)
+    iw = W.subset(np.random.default_rng(516), wall.n, 256)
+    rx = O.dl_vjp(wall.pos, phi, wall.weight, wall.normal, cells.pos[:, it], gh[:, it],
+                  want=("trg",))[2]
+    rx += O.sl_vjp(cells.pos, f, cells.weight, cells.pos[:, it], gh[:, it], src_group=cells.group,
+                   trg_group=cells.group[it], exclude_same_group=True, want=("trg",))[2]
+    rf, rs, _ = O.sl_vjp(cells.pos[:, it], f[:, it], cells.weight[it], cells.pos, gh,
+                         src_group=cells.group[it], trg_group=cells.group, exclude_same_group=True,
+                         want=("f", "src"))
+    rx += rs
+    rp = O.dl_vjp(wall.pos[:, iw], phi[:, iw], wall.weight[iw], wall.normal[:, iw], cells.pos, gh,
+                  want=("phi",))[0]
+    r_x = assert_close(host(gx)[:, it], rx, VJP_TOL, "cfg5 total dL/dx")
+    r_f = assert_close(host(gf)[:, it], rf, VJP_TOL, "cfg5 dL/df")
+    r_p = assert_close(host(gphi)[:, iw], rp, VJP_TOL, "cfg5 dL/dphi")
+    print(f"cfg5 {precision}: rel-L2 u {r_u:.3e}, dL/dx {r_x:.3e}, dL/df {r_f:.3e}, dL/dphi {r_p:.3e}")
 
 
 @pytest.mark.parametrize("kernel", ["sl", "dl"])
