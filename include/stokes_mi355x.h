@@ -168,6 +168,28 @@ int stokes_sl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const 
                    const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out,
                    void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): stokes_sl_eval with its scratch in a library-owned static
+ * device array of STOKES_NOALLOC_SCRATCH_BYTES (64 MiB) instead of a caller
+ * workspace.  Every GPU that the library runs on holds one such array for the
+ * life of the process.  Arguments, results and errors otherwise as
+ * stokes_sl_eval (the same kernels and launch shape, so the same values).
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine.  Sizes whose scratch (stokes_workspace_size with STOKES_OP_SL)
+ * exceeds the array are rejected with STOKES_EWORKSPACE before any launch:
+ * on a device with 256 compute units, about 230,000 sources and targets each
+ * (a shared point set) in float64 and 300,000 in mixed precision.  All calls on one GPU share its array: two calls
+ * whose executions overlap on that GPU (from other streams, threads or
+ * contexts) race and may both return wrong results; order them on one
+ * stream.  Nothing in the array needs to start at zero: every call writes all
+ * of the scratch it reads. */
+#define STOKES_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int stokes_sl_eval_noalloc(stokes_ctx* ctx, int64_t n_src, const double* src_xyz,
+                           const double* density, const double* weight, int64_t n_trg,
+                           const double* trg_xyz, double mu, const stokes_exclusion* excl,
+                           const stokes_opts* opts, double* vel_out, void* stream);
+
 /* Double-layer sum (stresslet), after eq. (double_layer_int_eq):
  *   vel_out(3, n_trg) (=|+=) 6/(8 pi) sum_m' r (r.n_m)(r.q_m)/rho^5,
  *   q_m = weight_m * density_m, n_m = normal(:, m) (unit, outward).

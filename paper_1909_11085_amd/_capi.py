@@ -19,6 +19,7 @@ FP64, MIXED = 0, 1
 EXCL_NONE, EXCL_SAME_GROUP = 0, 1
 KERNEL_SL, KERNEL_DL = 0, 1
 OP_SL, OP_DL, OP_P2P_SL, OP_P2P_DL, OP_SL_VJP, OP_DL_VJP = range(6)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_NAMES = {OK: "STOKES_OK", EINVAL: "STOKES_EINVAL", EDEVICE: "STOKES_EDEVICE",
                 ELAUNCH: "STOKES_ELAUNCH", EWORKSPACE: "STOKES_EWORKSPACE",
                 EUNSUPPORTED: "STOKES_EUNSUPPORTED"}
@@ -67,6 +68,8 @@ _SIGNATURES = {
     "stokes_workspace_size": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i32, _OP, ctypes.POINTER(_sz)]),
     "stokes_sl_eval": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _i64, _vp, _dbl, _EX, _OP, _vp,
                                       _vp, _sz, _vp]),
+    "stokes_sl_eval_noalloc": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _i64, _vp, _dbl, _EX, _OP,
+                                              _vp, _vp]),
     "stokes_dl_eval": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _EX, _OP, _vp,
                                       _vp, _sz, _vp]),
     "stokes_p2p_plan_create": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, _vp, _vp, _vp, _i64,

@@ -25,6 +25,9 @@ struct stokes_ctx {
     int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
     int vjp_resident[stokes::kVjpPasses];   // resident workgroups of the adjoint pass kernels
     char arch[64];
+    // device address of this device's copy of `scratch` (stokes_sl_eval_noalloc)
+    void* scratch = nullptr;
+    hipError_t scratch_status = hipErrorNotInitialized;
     // benchmark timing (see stokes_timing_enable)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // recorded, not yet read
@@ -49,6 +52,15 @@ KernelTimer next_timer(stokes_ctx* ctx) {
     return t;
 }
 }  // namespace stokes
+
+// Scratch of stokes_sl_eval_noalloc, for callers that cannot allocate: the
+// direct sum's workspace (packed source records, sub-tile summaries, partial
+// sums, near-pass flags) lives here instead of in caller memory.  Each GPU that
+// the library runs on holds its own copy until the process ends.  In host code
+// this name is not a device address: stokes_create takes the address of the
+// current device's copy with hipGetSymbolAddress and keeps it in the context,
+// and only that address reaches kernels.
+static __device__ __align__(256) unsigned char scratch[STOKES_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -422,6 +434,11 @@ int stokes_create(stokes_ctx** ctx, int device) {
         for (int k = 0; k < 2; ++k)
             for (int m = 0; m < 2; ++m) c->resident[k][m] = stokes::direct_blocks_per_cu(k, m) * c->n_cu;
         stokes::vjp_resident(c->n_cu, c->vjp_resident);
+        // this device's copy of the no-allocation scratch array (a failure
+        // only disables stokes_sl_eval_noalloc, which reports it)
+        void* sp = nullptr;
+        c->scratch_status = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+        c->scratch = c->scratch_status == hipSuccess ? sp : nullptr;
     }
     *ctx = c;
     return STOKES_OK;
@@ -553,6 +570,35 @@ int stokes_sl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const 
     return direct_eval(ctx, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg,
                        trg_xyz, 1.0 / (8.0 * kPi * mu), excl, opts, vel_out, workspace, ws_bytes,
                        stream);
+}
+
+int stokes_sl_eval_noalloc(stokes_ctx* ctx, int64_t n_src, const double* src_xyz,
+                           const double* density, const double* weight, int64_t n_trg,
+                           const double* trg_xyz, double mu, const stokes_exclusion* excl,
+                           const stokes_opts* opts, double* vel_out, void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    Parsed p;
+    rc = parse_common(nullptr, opts, n_src, n_trg, p);
+    if (rc) return rc;
+    const int mixed = p.precision == STOKES_MIXED;
+    size_t need = 0;
+    if (n_src > 0 && n_trg > 0)
+        need = stokes::plan_direct(STOKES_KERNEL_SL, mixed, n_src, n_trg, ctx->resident[0][mixed],
+                                   ctx->forced_grid).total;
+    if (need > (size_t)STOKES_NOALLOC_SCRATCH_BYTES)
+        return fail(STOKES_EWORKSPACE, "stokes_sl_eval_noalloc: these sizes need " + std::to_string(need) +
+                                           " bytes of scratch, more than the library's " +
+                                           std::to_string((size_t)STOKES_NOALLOC_SCRATCH_BYTES) +
+                                           "-byte array (use stokes_sl_eval with a workspace)");
+    if (!ctx->scratch)
+        return fail(STOKES_EDEVICE, std::string("stokes_sl_eval_noalloc: no device address for the scratch "
+                                                "array: ") + hipGetErrorString(ctx->scratch_status));
+    return direct_eval(ctx, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz,
+                       1.0 / (8.0 * kPi * mu), excl, opts, vel_out, ctx->scratch,
+                       (size_t)STOKES_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int stokes_dl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
