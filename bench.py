@@ -21,6 +21,16 @@ Reported on one JSON line (stdout):
   cpu_baseline  the FP64 CPU oracle on a bounded sample of targets (all
                 sources), on this host's cores, with the full step's time
                 extrapolated from its rate
+  configs       the other workload shapes, each in FP64 and mixed precision
+                with pairs/s on the pairs evaluated (same-cell pairs not
+                counted), a roofline at the stated flops per pair, rel-L2
+                against the oracle on a seeded sample, and (128 cells; wall +
+                cells) the adjoint and its ratio to the FP64 forward:
+                  128 cells (69,632 points), single layer + adjoint;
+                  3,840 cells in the vessel, leaf-to-leaf sums;
+                  the vessel wall's double layer at 960 cells plus the cells'
+                  single layer, superposed, + adjoint.
+                --headline-only skips them.
 
 --only checkpoint times the check-point double-layer quadrature on a
 vessel-wall ring (every node an on-surface target), --only bie the
@@ -28,7 +38,7 @@ vessel-wall ring (every node an on-surface target), --only bie the
 --only collision the collision-candidate search of the cells and the wall,
 --only fmm the FMM single-layer sum over the cells (and the wall's double layer
 at the cells) against the direct sums;
---secondary adds them and the other workload shapes to the line.
+--secondary adds them to the line.
 """
 import argparse
 import hashlib
@@ -103,9 +113,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the 512-cell workload (skip the 128-cell, leaf-to-leaf and wall + cell "
+                         "workloads reported under 'configs')")
     ap.add_argument("--secondary", action="store_true",
-                    help="also time the other workloads (cfg3 adjoint, cfg4 P2P, cfg5 wall + cells) "
-                         "and report them under 'secondary'")
+                    help="also time the components around the hot path (check points, boundary "
+                         "solve, collision candidates, FMM) and report them under 'secondary'")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (HBM byte-counter calibration)")
     args = ap.parse_args()
@@ -317,24 +330,210 @@ def main():
     if adjoint:
         line["adjoint"] = adjoint
     line["cpu_baseline"] = cpu
+    if not args.headline_only and args.only is None:
+        oracle = not args.no_cpu_baseline
+        line["configs"] = {}
+        for name, fn, st in (("cfg3_128_cells", bench_cfg3, 10), ("cfg4_p2p_3840_cells", bench_cfg4, 10),
+                             ("cfg5_wall_and_960_cells", bench_cfg5, 3)):
+            tc = time.time()
+            line["configs"][name] = fn(S, W, t, timed, st, oracle)
+            log(f"{name} ({time.time() - tc:.1f}s): " + json.dumps(line["configs"][name]))
     if args.secondary:
         line["secondary"] = secondary(S, W, t, timed, log)
     print(json.dumps(line), flush=True)
 
 
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _roofline(prec, flops, kernel_ms, kernel):
+    """Algorithmic flops of one step over its summation kernels' time."""
+    ach = flops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_TFLOPS[prec], 4), "kernel": kernel, "kernel_ms": round(kernel_ms, 4)}
+
+
+def bench_cfg3(S, W, t, timed, steps, oracle):
+    """128 cells (69,632 points): single layer forward in both precisions and
+    the fused adjoint of L = 0.5 |u - u_ref|^2 (dL/df and the total dL/dx)."""
+    import torch
+
+    cfg = W.make_config(3)
+    c, f, u_ref = cfg["cells"], cfg["f"], cfg["u_ref"]
+    n = c.n
+    pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
+    pairs = W.pair_count_direct(c.group, c.group, True)
+    r = {"workload": "128 Evans-Fung RBCs (69,632 points) in a 75.6^3 box; single-layer sum all points to "
+                     "all points, same-cell pairs excluded; adjoint of L = 0.5 |u - u_ref|^2",
+         "pairs": pairs}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        u = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        ms, kms, la = timed(lambda: S.sl(pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=prec,
+                                         group_h=gh, out=u), steps, 2)
+        outs[prec] = u.cpu().numpy()
+        km = kms * la / steps
+        r[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3),
+                   "roofline": _roofline(prec, pairs * FLOPS_PER_PAIR_SL, km, KERNEL_NAMES[prec])}
+    r["mixed_speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r["mixed"]["ms_per_step"]
+    g = t(outs["fp64"]) - t(u_ref)
+    gf, gx = torch.empty_like(ft), torch.empty_like(pos)
+    ms, _, _ = timed(lambda: S.sl_vjp(pos, ft, wt, pos, g, src_group=grp, trg_group=grp, grad_f=gf,
+                                      grad_src=gx, grad_trg=gx), steps, 1)
+    r["adjoint"] = {"ms_per_step": ms, "outputs": ["dL/df", "dL/dx (total)"], "precision": "fp64",
+                    "ratio_to_fp64_forward": ms / r["fp64"]["ms_per_step"]}
+    if oracle:
+        from oracle import oracle as O
+
+        idx = W.subset(np.random.default_rng(3003), n, 512)
+        ref = O.sl(c.pos, f, c.weight, c.pos[:, idx], src_group=c.group, trg_group=c.group[idx],
+                   exclude_same_group=True)
+        for prec in ("fp64", "mixed"):
+            r[prec]["rel_l2"] = _rel(outs[prec][:, idx], ref)
+        gh_ = g.cpu().numpy()
+        _, _, rt = O.sl_vjp(c.pos, f, c.weight, c.pos[:, idx], gh_[:, idx], src_group=c.group,
+                            trg_group=c.group[idx], exclude_same_group=True, want=("trg",))
+        rf, rs, _ = O.sl_vjp(c.pos[:, idx], f[:, idx], c.weight[idx], c.pos, gh_, src_group=c.group[idx],
+                             trg_group=c.group, exclude_same_group=True, want=("f", "src"))
+        r["adjoint"]["rel_l2"] = {"dL/df": _rel(gf.cpu().numpy()[:, idx], rf),
+                                  "dL/dx": _rel(gx.cpu().numpy()[:, idx], rs + rt)}
+        r["oracle_sample"] = "512 seeded points x all sources"
+    return r
+
+
+def bench_cfg4(S, W, t, timed, steps, oracle):
+    """3,840 cells (2,088,960 points) in the cylinder, octree leaves of <= 256
+    points, lists of 27..60 leaves: the leaf-to-leaf sum in one launch."""
+    cfg = W.make_config(4)
+    c, tree, f = cfg["cells"], cfg["tree"], cfg["f"]
+    ofs, ul = cfg["ulist_ofs"], cfg["ulist"]
+    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, ofs, ul, c.n, c.n)
+    pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
+    pairs = W.pair_count_p2p(tree.leaf_ofs, ofs, ul, c.group, True)
+    r = {"workload": "3,840 Evans-Fung RBCs (2,088,960 points) in a cylinder (radius 50, length 400); "
+                     "octree leaves of <= 256 points, each leaf summing over its 27..60 nearest leaves; "
+                     "single layer, same-cell pairs excluded",
+         "pairs": pairs, "listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        ms, kms, la = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
+                                               precision=prec, group_h=gh), steps, 2)
+        outs[prec] = S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=prec,
+                                group_h=gh).cpu().numpy()
+        km = kms * la / steps
+        r[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3),
+                   "roofline": _roofline(prec, pairs * FLOPS_PER_PAIR_SL, km,
+                                         "p2p_sum<SL,%s>" % ("FP64" if prec == "fp64" else "mixed"))}
+    r["mixed_speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r["mixed"]["ms_per_step"]
+    if oracle:
+        from oracle import oracle as O
+
+        leaves = np.random.default_rng(4004).choice(len(tree.leaf_ofs) - 1, size=48, replace=False)
+        tt, ref = [], []
+        for L in leaves:
+            ti = np.arange(tree.leaf_ofs[L], tree.leaf_ofs[L + 1])
+            si = np.concatenate([np.arange(tree.leaf_ofs[k], tree.leaf_ofs[k + 1]) for k in ul[ofs[L]:ofs[L + 1]]])
+            ref.append(O.sl(c.pos[:, si], f[:, si], c.weight[si], c.pos[:, ti], src_group=c.group[si],
+                            trg_group=c.group[ti], exclude_same_group=True))
+            tt.append(ti)
+        tt, ref = np.concatenate(tt), np.concatenate(ref, 1)
+        for prec in ("fp64", "mixed"):
+            r[prec]["rel_l2"] = _rel(outs[prec][:, tt], ref)
+        r["oracle_sample"] = "48 seeded leaves (%d targets) x their listed sources" % len(tt)
+    return r
+
+
+def bench_cfg5(S, W, t, timed, steps, oracle):
+    """Wall + cells: the wall's double layer (1,048,576 nodes) at the 522,240
+    points of 960 cells plus the cells' single layer (same-cell rule), added
+    into one velocity; then the adjoint of L = 0.5 |u - u_ref|^2 with respect
+    to the wall density, the cell densities and the cell positions."""
+    import torch
+
+    cfg = W.make_config(5)
+    wall, c = cfg["wall"], cfg["cells"]
+    wp, wphi, ww, wn, wg, wh = (t(wall.pos), t(cfg["phi"]), t(wall.weight), t(wall.normal),
+                                t(wall.group), t(wall.group_h))
+    cp, cf, cw, cg, ch = t(c.pos), t(cfg["f"]), t(c.weight), t(c.group), t(c.group_h)
+    dl_pairs = wall.n * c.n
+    sl_pairs = W.pair_count_direct(c.group, c.group, True)
+    r = {"workload": "vessel wall (cylinder radius 50, length 400, 4,096 patches of 16 x 16 nodes: 1,048,576 "
+                     "points) double layer at the 522,240 points of 960 Evans-Fung RBCs, plus the cells' "
+                     "single layer (same-cell pairs excluded), superposed; adjoint of L = 0.5 |u - u_ref|^2",
+         "dl_pairs": dl_pairs, "sl_pairs": sl_pairs, "pairs": dl_pairs + sl_pairs}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        u = torch.empty((3, c.n), dtype=torch.float64, device=cp.device)
+
+        def both():
+            S.dl(wp, wphi, ww, wn, cp, src_group=wg, precision=prec, group_h=wh, exclude_same_group=False,
+                 out=u)
+            S.sl(cp, cf, cw, cp, src_group=cg, trg_group=cg, precision=prec, group_h=ch, out=u,
+                 accumulate=True)
+
+        ms, kms, la = timed(both, steps, 1)
+        outs[prec] = u.cpu().numpy()
+        km = kms * la / steps
+        flops = dl_pairs * FLOPS_PER_PAIR_DL + sl_pairs * FLOPS_PER_PAIR_SL
+        r[prec] = {"ms_per_step": ms, "pairs_per_s": (dl_pairs + sl_pairs) / (ms * 1e-3),
+                   "roofline": _roofline(prec, flops, km, "direct %s DL + SL" % prec)}
+    r["mixed_speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r["mixed"]["ms_per_step"]
+    g = t(outs["fp64"]) - t(cfg["u_ref"])
+    gphi, gfc, gx = torch.empty_like(wphi), torch.zeros_like(cf), torch.empty_like(cp)
+
+    def adj():
+        S.dl_vjp(wp, wphi, ww, wn, cp, g, grad_phi=gphi, grad_trg=gx)
+        S.sl_vjp(cp, cf, cw, cp, g, src_group=cg, trg_group=cg, grad_f=gfc, grad_src=gx, grad_trg=gx,
+                 accumulate=True)
+
+    gfc.zero_()
+    ms, _, _ = timed(adj, max(1, steps // 2), 1)
+    r["adjoint"] = {"ms_per_step": ms, "outputs": ["dL/dphi (wall)", "dL/df (cells)", "dL/dx (cells, total)"],
+                    "precision": "fp64", "ratio_to_fp64_forward": ms / r["fp64"]["ms_per_step"]}
+    if oracle:
+        from oracle import oracle as O
+
+        it = W.subset(np.random.default_rng(5005), c.n, 256)
+        ref = O.dl(wall.pos, cfg["phi"], wall.weight, wall.normal, c.pos[:, it])
+        ref += O.sl(c.pos, cfg["f"], c.weight, c.pos[:, it], src_group=c.group, trg_group=c.group[it],
+                    exclude_same_group=True)
+        for prec in ("fp64", "mixed"):
+            r[prec]["rel_l2"] = _rel(outs[prec][:, it], ref)
+        # one adjoint call more, from zero (the timed calls accumulated into dL/df)
+        gfc.zero_()
+        adj()
+        gh_ = g.cpu().numpy()
+        iw = W.subset(np.random.default_rng(5006), wall.n, 256)
+        rp = O.dl_vjp(wall.pos[:, iw], cfg["phi"][:, iw], wall.weight[iw], wall.normal[:, iw], c.pos, gh_,
+                      want=("phi",))[0]
+        rx = O.dl_vjp(wall.pos, cfg["phi"], wall.weight, wall.normal, c.pos[:, it], gh_[:, it], want=("trg",))[2]
+        rx += O.sl_vjp(c.pos, cfg["f"], c.weight, c.pos[:, it], gh_[:, it], src_group=c.group,
+                       trg_group=c.group[it], exclude_same_group=True, want=("trg",))[2]
+        rf, rs, _ = O.sl_vjp(c.pos[:, it], cfg["f"][:, it], c.weight[it], c.pos, gh_, src_group=c.group[it],
+                             trg_group=c.group, exclude_same_group=True, want=("f", "src"))
+        r["adjoint"]["rel_l2"] = {"dL/dphi": _rel(gphi.cpu().numpy()[:, iw], rp),
+                                  "dL/df": _rel(gfc.cpu().numpy()[:, it], rf),
+                                  "dL/dx": _rel(gx.cpu().numpy()[:, it], rx + rs)}
+        r["oracle_sample"] = "256 seeded cell points (and 256 wall nodes for dL/dphi) x all sources"
+    return r
+
+
 def time_p2p(S, W, t, timed, steps, warmup):
-    """Leaf-to-leaf sums of 3,840 cells in the cylinder (lists of 27..60 leaves), both precisions."""
+    """Leaf-to-leaf sums of 3,840 cells in the cylinder (lists of 27..60 leaves), both precisions;
+    rates on the pairs evaluated (same-cell pairs of the lists not counted)."""
     cfg = W.make_config(4)
     c, tree, f = cfg["cells"], cfg["tree"], cfg["f"]
     plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, cfg["ulist_ofs"], cfg["ulist"], c.n, c.n)
     pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
-    r = {"listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
+    pairs = W.pair_count_p2p(tree.leaf_ofs, cfg["ulist_ofs"], cfg["ulist"], c.group, True)
+    r = {"pairs": pairs, "listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
     for prec in ("mixed", "fp64"):
         ms, kms, _ = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
                                               precision=prec, group_h=gh), steps, warmup)
         r[f"{prec}_ms"] = ms
         r[f"{prec}_kernel_ms"] = kms
-        r[f"{prec}_listed_pairs_per_s"] = r["listed_pairs"] / (ms * 1e-3)
+        r[f"{prec}_pairs_per_s"] = pairs / (ms * 1e-3)
     return r
 
 
@@ -616,67 +815,9 @@ def time_fmm(S, W, t, steps, warmup):
 
 
 def secondary(S, W, t, timed, log):
-    """Timings of the other workload shapes (not the headline)."""
-    import torch
-
+    """Timings of the components around the hot path (check points, boundary
+    solve, collision candidates, FMM)."""
     out = {}
-    # cfg3: 128 cells, 69,632 points; forward and the fused shared-point adjoint
-    cfg = W.make_config(3)
-    c, f = cfg["cells"], cfg["f"]
-    pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
-    pairs = W.pair_count_direct(c.group, c.group, True)
-    r = {"pairs": pairs}
-    for prec in ("fp64", "mixed"):
-        ms, _, _ = timed(lambda: S.sl(pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=prec,
-                                      group_h=gh), 10, 2)
-        r[f"{prec}_ms"] = ms
-        r[f"{prec}_pairs_per_s"] = pairs / (ms * 1e-3)
-    g = t(np.random.default_rng(3).standard_normal((3, c.n)))
-    gf, gx = torch.empty_like(ft), torch.empty_like(pos)
-    ms, _, _ = timed(lambda: S.sl_vjp(pos, ft, wt, pos, g, src_group=grp, trg_group=grp, grad_f=gf,
-                                      grad_src=gx, grad_trg=gx), 5, 1)
-    r["adjoint_ms"] = ms
-    r["adjoint_over_fp64_forward"] = ms / r["fp64_ms"]
-    out["cfg3_128_cells_sl_and_adjoint"] = r
-    log(f"secondary cfg3: {r}")
-    # cfg4: leaf-to-leaf sums over 27..60-leaf lists, one launch
-    r = time_p2p(S, W, t, timed, 10, 2)
-    out["cfg4_p2p_3840_cells"] = r
-    log(f"secondary cfg4: {r}")
-    # cfg5: wall double layer onto 960 cells plus the cell single layer; adjoints
-    cfg = W.make_config(5)
-    wall, c = cfg["wall"], cfg["cells"]
-    wp, wphi, ww, wn, wg, wh = (t(wall.pos), t(cfg["phi"]), t(wall.weight), t(wall.normal),
-                                t(wall.group), t(wall.group_h))
-    cp, cf, cw, cg, ch = t(c.pos), t(cfg["f"]), t(c.weight), t(c.group), t(c.group_h)
-    dl_pairs = wall.n * c.n
-    sl_pairs = W.pair_count_direct(c.group, c.group, True)
-    r = {"dl_pairs": dl_pairs, "sl_pairs": sl_pairs}
-    for prec in ("mixed", "fp64"):
-        u = torch.empty((3, c.n), dtype=torch.float64, device=cp.device)
-
-        def both():
-            S.dl(wp, wphi, ww, wn, cp, src_group=wg, precision=prec, group_h=wh,
-                 exclude_same_group=False, out=u)
-            S.sl(cp, cf, cw, cp, src_group=cg, trg_group=cg, precision=prec, group_h=ch, out=u,
-                 accumulate=True)
-
-        ms, _, _ = timed(both, 3, 1)
-        r[f"{prec}_forward_ms"] = ms
-        r[f"{prec}_pairs_per_s"] = (dl_pairs + sl_pairs) / (ms * 1e-3)
-    g = t(np.random.default_rng(5).standard_normal((3, c.n)))
-    gphi, gxd, gfc, gxc = (torch.empty_like(wphi), torch.empty_like(cp), torch.empty_like(cf),
-                           torch.empty_like(cp))
-
-    def adj():
-        S.dl_vjp(wp, wphi, ww, wn, cp, g, grad_phi=gphi, grad_trg=gxd)
-        S.sl_vjp(cp, cf, cw, cp, g, src_group=cg, trg_group=cg, grad_f=gfc, grad_src=gxc, grad_trg=gxc)
-
-    ms, _, _ = timed(adj, 2, 1)
-    r["adjoint_ms"] = ms
-    r["adjoint_over_fp64_forward"] = ms / r["fp64_forward_ms"]
-    out["cfg5_wall_and_cells"] = r
-    log(f"secondary cfg5: {r}")
     r = time_checkpoint(S, W, t, timed, 5, 1, oracle=False)
     out["checkpoint_wall_ring"] = r
     log(f"secondary checkpoint: {r}")

@@ -524,3 +524,29 @@ def pair_count_direct(group_src, group_trg, exclude_same_group=True):
     gt = np.bincount(group_trg, minlength=len(gs))
     m = min(len(gs), len(gt))
     return int(ns * nt - (gs[:m].astype(np.int64) * gt[:m]).sum())
+
+
+def pair_count_p2p(leaf_ofs, ulist_ofs, ulist, group, exclude_same_group=True):
+    """Number of (target, source) pairs a leaf-to-leaf sum evaluates when
+    sources and targets are the same points in leaf order: for every leaf, its
+    targets times the sources of its listed leaves, minus (same-group rule)
+    the pairs whose two points carry the same group id.  Coincident points are
+    not expected in these inputs."""
+    import scipy.sparse as sp
+
+    leaf_ofs = np.asarray(leaf_ofs, dtype=np.int64)
+    ulist_ofs = np.asarray(ulist_ofs, dtype=np.int64)
+    n_leaves = len(leaf_ofs) - 1
+    size = np.diff(leaf_ofs)
+    owner = np.repeat(np.arange(n_leaves), np.diff(ulist_ofs))
+    listed = size[np.asarray(ulist, dtype=np.int64)]
+    total = int((size[owner] * listed).sum())
+    if not exclude_same_group:
+        return total
+    leaf_of_point = np.repeat(np.arange(n_leaves), size)
+    g = np.asarray(group, dtype=np.int64)
+    M = sp.csr_matrix((np.ones(len(g)), (leaf_of_point, g)), shape=(n_leaves, int(g.max()) + 1))
+    A = sp.csr_matrix((np.ones(len(owner)), (owner, np.asarray(ulist, dtype=np.int64))),
+                      shape=(n_leaves, n_leaves))
+    same = M.multiply(A @ M).sum()
+    return total - int(round(float(same)))
