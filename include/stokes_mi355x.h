@@ -137,6 +137,17 @@ int stokes_version(void);
  * within the same error bound.  Not thread-safe against running calls. */
 int stokes_set_grid_override(stokes_ctx* ctx, int32_t workgroups);
 
+/* Each-pair-once evaluation of shared point sets (on by default).  When a
+ * single-layer call's sources are its targets (src_xyz == trg_xyz, n_src ==
+ * n_trg, and with the same-group rule one array for both groups) and its
+ * workspace holds what stokes_workspace_size reports for n_src == n_trg, the
+ * Stokeslet's symmetry S(x, y) = S(y, x) lets every unordered pair be
+ * evaluated once for both of its points (float64).  on = 0 makes such calls
+ * evaluate each ordered pair separately, as for distinct point sets (tests,
+ * benchmarks).  Results agree within the float64 bound either way.  Not
+ * thread-safe against running calls. */
+int stokes_set_pair_symmetry(stokes_ctx* ctx, int32_t on);
+
 /* Kernel timing for benchmarks.  While enabled, every evaluation records a
  * pair of HIP events around its main summation kernel(s) (not the prep or
  * reduction kernels) on the call's stream.  stokes_timing_read waits for
@@ -149,7 +160,10 @@ int stokes_timing_read(stokes_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Bytes of workspace that a call of kind `op` (STOKES_OP_*) with these sizes
  * and options needs.  For P2P ops n_leaves is the plan's leaf count; for
- * others it is ignored.  May be 0. */
+ * others it is ignored.  May be 0.  For STOKES_OP_SL with n_src == n_trg the
+ * size covers the each-pair-once sum of a shared point set (its column
+ * partials grow as n^2: about 0.9 GB for 278,528 points); a workspace of at
+ * least the size for distinct point sets still works, one pair at a time. */
 int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int64_t n_trg,
                           int32_t n_leaves, const stokes_opts* opts, size_t* bytes);
 

@@ -63,6 +63,7 @@ _SIGNATURES = {
     "stokes_last_error": (ctypes.c_char_p, []),
     "stokes_version": (ctypes.c_int, []),
     "stokes_set_grid_override": (ctypes.c_int, [_vp, _i32]),
+    "stokes_set_pair_symmetry": (ctypes.c_int, [_vp, _i32]),
     "stokes_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "stokes_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
     "stokes_workspace_size": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i32, _OP, ctypes.POINTER(_sz)]),

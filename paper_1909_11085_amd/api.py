@@ -41,6 +41,11 @@ def set_grid_override(workgroups, device=None):
     C.check(C.lib().stokes_set_grid_override(context(device), int(workgroups)))
 
 
+def set_pair_symmetry(on=True, device=None):
+    """Evaluate each unordered pair once on shared point sets (default on)."""
+    C.check(C.lib().stokes_set_pair_symmetry(context(device), int(bool(on))))
+
+
 def timing_enable(on=True, device=None):
     """Record HIP events around each evaluation's main summation kernel."""
     C.check(C.lib().stokes_timing_enable(context(device), int(bool(on))))

@@ -23,6 +23,8 @@ struct stokes_ctx {
     int clock_khz;
     int forced_grid;             // 0 = resident workgroup count
     int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
+    int sym_resident[2];         // [mixed]: resident workgroups of the each-pair-once sum
+    bool pair_symmetry = true;   // shared point sets take the each-pair-once sum
     int vjp_resident[stokes::kVjpPasses];   // resident workgroups of the adjoint pass kernels
     char arch[64];
     // device address of this device's copy of `scratch` (stokes_sl_eval_noalloc)
@@ -434,6 +436,7 @@ int stokes_create(stokes_ctx** ctx, int device) {
         for (int k = 0; k < 2; ++k)
             for (int m = 0; m < 2; ++m) c->resident[k][m] = stokes::direct_blocks_per_cu(k, m) * c->n_cu;
         stokes::vjp_resident(c->n_cu, c->vjp_resident);
+        for (int m = 0; m < 2; ++m) c->sym_resident[m] = stokes::sym_blocks_per_cu(m) * c->n_cu;
         // this device's copy of the no-allocation scratch array (a failure
         // only disables stokes_sl_eval_noalloc, which reports it)
         void* sp = nullptr;
@@ -489,6 +492,19 @@ int stokes_set_grid_override(stokes_ctx* ctx, int32_t workgroups) {
     return STOKES_OK;
 }
 
+int stokes_set_pair_symmetry(stokes_ctx* ctx, int32_t on) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (on != 0 && on != 1) return fail(STOKES_EINVAL, "on must be 0 or 1");
+    ctx->pair_symmetry = on != 0;
+    return STOKES_OK;
+}
+
+// Whether the single-layer sum with these sizes and precision has an
+// each-pair-once form (used only when the call's point set is shared).
+static bool sym_available(const stokes_ctx* ctx, int kernel, int mixed, int64_t n_src, int64_t n_trg) {
+    return ctx->pair_symmetry && kernel == STOKES_KERNEL_SL && !mixed && n_src == n_trg && n_src > 0;
+}
+
 int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int64_t n_trg,
                           int32_t n_leaves, const stokes_opts* opts, size_t* bytes) {
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
@@ -506,6 +522,10 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
             const int k = op == STOKES_OP_SL ? 0 : 1;
             *bytes = stokes::plan_direct(k, mixed, n_src, n_trg, ctx->resident[k][mixed],
                                          ctx->forced_grid).total;
+            // equal sizes may be a shared point set: room for the each-pair-once sum
+            if (sym_available(ctx, k, mixed, n_src, n_trg))
+                *bytes = std::max(*bytes, stokes::plan_sym(mixed, n_src, ctx->sym_resident[mixed],
+                                                           ctx->forced_grid).total);
             return STOKES_OK;
         }
         case STOKES_OP_P2P_SL:
@@ -527,7 +547,7 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
                        const double* density, const double* weight, const double* normal,
                        int64_t n_trg, const double* trg_xyz, double pref,
                        const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out,
-                       void* workspace, size_t ws_bytes, void* stream) {
+                       void* workspace, size_t ws_bytes, void* stream, bool allow_sym = true) {
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
     int rc = check_sizes(n_src, n_trg);
     if (rc) return rc;
@@ -552,12 +572,26 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
     }
     rc = check_workspace(workspace, ws_bytes, need);
     if (rc) return rc;
+    // a shared point set (one array, one group array) takes the each-pair-once
+    // sum when the workspace has room for it
+    const bool shared = src_xyz == trg_xyz && n_src == n_trg &&
+                        (p.excl == STOKES_EXCL_NONE || p.src_group == p.trg_group);
+    stokes::SymPlan splan{};
+    bool use_sym = false;
+    if (allow_sym && shared && sym_available(ctx, kernel, mixed, n_src, n_trg)) {
+        splan = stokes::plan_sym(mixed, n_src, ctx->sym_resident[mixed], ctx->forced_grid);
+        use_sym = ws_bytes >= splan.total;
+    }
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
     const stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal,
                                              n_trg, trg_xyz, pref);
-    return launch_status(stokes::launch_direct(in, plan, vel_out, p.accumulate, workspace,
-                                               static_cast<hipStream_t>(stream),
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (use_sym)
+        return launch_status(stokes::launch_sym(in, splan, vel_out, p.accumulate, workspace, st,
+                                                stokes::next_timer(ctx)),
+                             "stokes_sl_eval");
+    return launch_status(stokes::launch_direct(in, plan, vel_out, p.accumulate, workspace, st,
                                                stokes::next_timer(ctx)),
                          kernel ? "stokes_dl_eval" : "stokes_sl_eval");
 }
@@ -598,7 +632,7 @@ int stokes_sl_eval_noalloc(stokes_ctx* ctx, int64_t n_src, const double* src_xyz
                                                 "array: ") + hipGetErrorString(ctx->scratch_status));
     return direct_eval(ctx, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz,
                        1.0 / (8.0 * kPi * mu), excl, opts, vel_out, ctx->scratch,
-                       (size_t)STOKES_NOALLOC_SCRATCH_BYTES, stream);
+                       (size_t)STOKES_NOALLOC_SCRATCH_BYTES, stream, /*allow_sym=*/false);
 }
 
 int stokes_dl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
