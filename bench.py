@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target duration of the CPU oracle sample")
+    ap.add_argument("--one-sided", action="store_true",
+                    help="evaluate every ordered pair separately (pair symmetry off) on the shared point sets")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the 512-cell workload (skip the 128-cell, leaf-to-leaf and wall + cell "
                          "workloads reported under 'configs')")
@@ -138,6 +140,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
+    if args.one_sided:
+        S.set_pair_symmetry(False)
     if args.calibrate_copy:
         nbytes = 1 << 30
         a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
@@ -159,16 +163,21 @@ def main():
         torch.cuda.synchronize()
         S.timing_read()                      # discard warm-up events
         S.timing_enable(True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()                                 # one more untimed call with the library's timing on
         torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(steps):
+        S.timing_read()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for i in range(steps):
             fn()
-        e1.record(stream)
+            ev[i + 1].record(stream)         # step boundaries, for the log
         torch.cuda.synchronize()
         S.timing_enable(False)
         kms, launches = S.timing_read()
-        return e0.elapsed_time(e1) / steps, kms / max(launches, 1), launches
+        periods = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        log("  step periods ms: " + " ".join(f"{x:.2f}" for x in periods))
+        return ev[0].elapsed_time(ev[steps]) / steps, kms / max(launches, 1), launches
 
     def per_step(fn, n_steps):
         """Median and minimum of n_steps single-step times (one event pair per

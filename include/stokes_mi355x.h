@@ -188,7 +188,9 @@ int stokes_sl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const 
  * device array of STOKES_NOALLOC_SCRATCH_BYTES (64 MiB) instead of a caller
  * workspace.  Every GPU that the library runs on holds one such array for the
  * life of the process.  Arguments, results and errors otherwise as
- * stokes_sl_eval (the same kernels and launch shape, so the same values).
+ * stokes_sl_eval; every ordered pair is evaluated separately (the kernels
+ * and launch shape of stokes_sl_eval with pair symmetry off, so bitwise its
+ * values then), also on shared point sets.
  * The call allocates nothing: no hipMalloc, hipFree or allocating library
  * routine.  Sizes whose scratch (stokes_workspace_size with STOKES_OP_SL)
  * exceeds the array are rejected with STOKES_EWORKSPACE before any launch:

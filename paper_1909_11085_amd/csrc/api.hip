@@ -23,7 +23,7 @@ struct stokes_ctx {
     int clock_khz;
     int forced_grid;             // 0 = resident workgroup count
     int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
-    int sym_resident[2];         // [mixed]: resident workgroups of the each-pair-once sum
+    int sym_resident;            // resident workgroups of the each-pair-once sum
     bool pair_symmetry = true;   // shared point sets take the each-pair-once sum
     int vjp_resident[stokes::kVjpPasses];   // resident workgroups of the adjoint pass kernels
     char arch[64];
@@ -436,7 +436,7 @@ int stokes_create(stokes_ctx** ctx, int device) {
         for (int k = 0; k < 2; ++k)
             for (int m = 0; m < 2; ++m) c->resident[k][m] = stokes::direct_blocks_per_cu(k, m) * c->n_cu;
         stokes::vjp_resident(c->n_cu, c->vjp_resident);
-        for (int m = 0; m < 2; ++m) c->sym_resident[m] = stokes::sym_blocks_per_cu(m) * c->n_cu;
+        c->sym_resident = stokes::sym_blocks_per_cu() * c->n_cu;
         // this device's copy of the no-allocation scratch array (a failure
         // only disables stokes_sl_eval_noalloc, which reports it)
         void* sp = nullptr;
@@ -460,6 +460,16 @@ void stokes_destroy(stokes_ctx* ctx) {
 int stokes_timing_enable(stokes_ctx* ctx, int on) {
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
     ctx->timing = on != 0;
+    // event pairs made here, not inside timed evaluations
+    while (ctx->timing && ctx->spare.size() + ctx->events.size() < 64) {
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (hipEventCreate(&ev.first) != hipSuccess) break;
+        if (hipEventCreate(&ev.second) != hipSuccess) {
+            (void)hipEventDestroy(ev.first);
+            break;
+        }
+        ctx->spare.push_back(ev);
+    }
     return STOKES_OK;
 }
 
@@ -524,8 +534,7 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
                                          ctx->forced_grid).total;
             // equal sizes may be a shared point set: room for the each-pair-once sum
             if (sym_available(ctx, k, mixed, n_src, n_trg))
-                *bytes = std::max(*bytes, stokes::plan_sym(mixed, n_src, ctx->sym_resident[mixed],
-                                                           ctx->forced_grid).total);
+                *bytes = std::max(*bytes, stokes::plan_sym(n_src, ctx->sym_resident, ctx->forced_grid).total);
             return STOKES_OK;
         }
         case STOKES_OP_P2P_SL:
@@ -579,7 +588,7 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
     stokes::SymPlan splan{};
     bool use_sym = false;
     if (allow_sym && shared && sym_available(ctx, kernel, mixed, n_src, n_trg)) {
-        splan = stokes::plan_sym(mixed, n_src, ctx->sym_resident[mixed], ctx->forced_grid);
+        splan = stokes::plan_sym(n_src, ctx->sym_resident, ctx->forced_grid);
         use_sym = ws_bytes >= splan.total;
     }
     DeviceGuard dg(ctx->device);

@@ -102,9 +102,9 @@ hipError_t launch_direct(const SumInputs& in, const DirectPlan& p, double* out, 
 hipError_t launch_prep(const SumInputs& in, int64_t n_pad, void* rec, void* aux, SubMeta* meta,
                        hipStream_t stream);
 
-// Each-pair-once single-layer sum over a shared point set (sources are the
-// targets, one group array): every unordered pair is evaluated once for both
-// of its points.  Launch shape and workspace, a pure function of n and options.
+// Each-pair-once float64 single-layer sum over a shared point set (sources
+// are the targets, one group array): every unordered pair is evaluated once
+// for both of its points.  Launch shape and workspace, a pure function of n.
 struct SymPlan {
     int T;                       // 64-point tiles per wave (rows per lane)
     int64_t n_pad;               // points padded to a whole row block
@@ -112,10 +112,10 @@ struct SymPlan {
     int64_t NW;                  // row blocks (4 T tiles each)
     int64_t units;               // (row block, column tile) units of the triangle
     int64_t grid;                // workgroups
-    size_t off_rec, off_aux, off_meta, off_row, off_col, off_near, off_flags, total;
+    size_t off_rec, off_aux, off_meta, off_row, off_col, total;
 };
-int sym_blocks_per_cu(int mixed);
-SymPlan plan_sym(int mixed, int64_t n, int resident_blocks, int forced_grid);
+int sym_blocks_per_cu();
+SymPlan plan_sym(int64_t n, int resident_blocks, int forced_grid);
 hipError_t launch_sym(const SumInputs& in, const SymPlan& p, double* out, int accumulate, void* workspace,
                       hipStream_t stream, const KernelTimer& timer);
 

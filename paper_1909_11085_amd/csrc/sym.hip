@@ -17,17 +17,18 @@
 //     (workgroup, row block);
 //   * a unit: each lane takes one column point (position, q, 4q and its
 //     running sum) and, 64 times, evaluates its T rows against it and passes
-//     the column point with its sum one lane on (DPP wave rotate, 24 moves);
-//     after 64 steps every row of the wave has met every column point and
-//     each column point is back in its lane with the wave's sum;
+//     the column point with its sum on (within 16-lane rows by DPP, every 16
+//     steps a whole row on); after 64 steps every row of the wave has met
+//     every column point and each column point is back in its lane with the
+//     wave's sum;
 //   * the 4 waves' column sums are added in LDS in a fixed order and stored
 //     as the unit's column partial;
 //   * units that may hold a pair needing a rule (a shared group id, or a
 //     row point inside the column tile's box: possible zero distance) run the
 //     same rotation with the masks (the column's group id rotates along);
 //     a wave's own tiles run it too, the tile of the unit itself as the
-//     diagonal: at step s lane l meets column l - s, so steps 1..31 and half
-//     the lanes of step 32 give every unordered pair of the tile once;
+//     diagonal: a lane takes the pair only when its point precedes the
+//     column point, so every unordered pair of the tile counts once;
 //   * the reduction adds, per point and in a fixed order, its row segments
 //     and the column partials of its tile from every row block:
 //     deterministic, no atomics.
@@ -54,13 +55,11 @@ constexpr int kColVals = 3 * kWave;       // doubles of one unit's column partia
 struct SymArgs {
     SumInputs in;
     const void* rec;          // packed records, n_pad
-    const void* aux;          // FP64: int32 groups
+    const void* aux;          // int32 groups
     const SubMeta* meta;      // per 64-point tile
     int64_t n_pad, NT, NW, units;
     double* row_part;         // (grid + NW) segments of 3 x (kBlock T) doubles
     double* col_part;         // (units, 3, 64)
-    uint8_t* flags;           // (4 NW, NT): unit of (wave, tile) left to the near pass
-    double* near_part;        // (kNearSlices, 3, n_pad)
 };
 
 // units of the row blocks before W (row block W holds NT - tpb W units)
@@ -79,11 +78,28 @@ __device__ __forceinline__ int64_t sym_block_of(int64_t u, int64_t NT, int64_t t
     return lo;
 }
 
-// one lane on, across the whole wave (DPP wave_ror:1), for a double
-__device__ __forceinline__ double wave_rotate(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x13C, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x13C, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
+// The column points move through the wave in 4 phases: within each row of 16
+// lanes, lane i takes lane i-1's value (DPP row_ror:1) 16 times, then every
+// lane takes the value of the lane 16 below it (whole rows one row on,
+// through the LDS crossbar).  After the 4 phases every lane has held each of
+// the 64 column points once and each is back in its own lane.  (A rotation
+// across the whole wave in one DPP step, wave_ror, costs several times a
+// row rotation on this hardware.)
+__device__ __forceinline__ int row_rot(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, true); }
+__device__ __forceinline__ float row_rot(float v) { return __int_as_float(row_rot(__float_as_int(v))); }
+__device__ __forceinline__ double row_rot(double v) {
+    return __hiloint2double(row_rot(__double2hiint(v)), row_rot(__double2loint(v)));
+}
+__device__ __forceinline__ int cross_rot(int v, int addr) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+__device__ __forceinline__ float cross_rot(float v, int addr) { return __int_as_float(cross_rot(__float_as_int(v), addr)); }
+__device__ __forceinline__ double cross_rot(double v, int addr) {
+    return __hiloint2double(cross_rot(__double2hiint(v), addr), cross_rot(__double2loint(v), addr));
+}
+// byte address for cross_rot: the lane 16 below, cyclically
+__device__ __forceinline__ int cross_addr(int lane) { return ((lane - 16) & (kWave - 1)) * 4; }
+// the column point (0..63 in its tile) that lane holds in phase R at step sp
+__device__ __forceinline__ int held_col(int lane, int R, int sp) {
+    return ((((lane >> 4) - R) & 3) << 4) | (((lane & 15) - sp) & 15);
 }
 
 // One unordered pair, both directions, float64 on doubled positions:
@@ -108,10 +124,6 @@ __device__ __forceinline__ void pair_sym_f64(double x, double y, double z, doubl
     bx = __builtin_fma(__builtin_fma(rr, dx, px), ri, bx);
     by = __builtin_fma(__builtin_fma(rr, dy, py), ri, by);
     bz = __builtin_fma(__builtin_fma(rr, dz, pz), ri, bz);
-}
-
-__device__ __forceinline__ int wave_rotate_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, true);
 }
 
 template <int T>
@@ -193,38 +205,54 @@ __global__ __launch_bounds__(kBlock, STOKES_SYM_W64) void sym_main_f64(SymArgs a
             const Rec c = rec[b * kWave + lane];
             double cx = c.x, cy = c.y, cz = c.z, cqx = c.qx, cqy = c.qy, cqz = c.qz;
             double cpx = c.q4x, cpy = c.q4y, cpz = c.q4z;
+            const int xa = cross_addr(lane);
             if (!masked) {
+                for (int R = 0; R < 4; ++R) {
 #pragma unroll 1
-                for (int s = 0; s < kWave; ++s) {
+                    for (int sp = 0; sp < 16; ++sp) {
 #pragma unroll
-                    for (int k = 0; k < T; ++k)
-                        pair_sym_f64<false>(t.x[k], t.y[k], t.z[k], qx[k], qy[k], qz[k], px[k], py[k], pz[k],
-                                            cx, cy, cz, cqx, cqy, cqz, cpx, cpy, cpz, false, ax[k], ay[k], az[k],
-                                            bx, by, bz);
-                    cx = wave_rotate(cx); cy = wave_rotate(cy); cz = wave_rotate(cz);
-                    cqx = wave_rotate(cqx); cqy = wave_rotate(cqy); cqz = wave_rotate(cqz);
-                    cpx = wave_rotate(cpx); cpy = wave_rotate(cpy); cpz = wave_rotate(cpz);
-                    bx = wave_rotate(bx); by = wave_rotate(by); bz = wave_rotate(bz);
+                        for (int k = 0; k < T; ++k)
+                            pair_sym_f64<false>(t.x[k], t.y[k], t.z[k], qx[k], qy[k], qz[k], px[k], py[k], pz[k],
+                                                cx, cy, cz, cqx, cqy, cqz, cpx, cpy, cpz, false, ax[k], ay[k], az[k],
+                                                bx, by, bz);
+                        cx = row_rot(cx); cy = row_rot(cy); cz = row_rot(cz);
+                        cqx = row_rot(cqx); cqy = row_rot(cqy); cqz = row_rot(cqz);
+                        cpx = row_rot(cpx); cpy = row_rot(cpy); cpz = row_rot(cpz);
+                        bx = row_rot(bx); by = row_rot(by); bz = row_rot(bz);
+                    }
+                    cx = cross_rot(cx, xa); cy = cross_rot(cy, xa); cz = cross_rot(cz, xa);
+                    cqx = cross_rot(cqx, xa); cqy = cross_rot(cqy, xa); cqz = cross_rot(cqz, xa);
+                    cpx = cross_rot(cpx, xa); cpy = cross_rot(cpy, xa); cpz = cross_rot(cpz, xa);
+                    bx = cross_rot(bx, xa); by = cross_rot(by, xa); bz = cross_rot(bz, xa);
                 }
             } else {
                 int cg = grp[b * kWave + lane];
                 const uint32_t any = full | diag;
+                for (int R = 0; R < 4; ++R) {
 #pragma unroll 1
-                for (int s = 0; s < kWave; ++s) {
-                    const bool dstep = (s >= 1 && s < kWave / 2) || (s == kWave / 2 && lane < kWave / 2);
+                    for (int sp = 0; sp < 16; ++sp) {
+                        // the diagonal slot takes each unordered pair of its tile
+                        // once: when this lane's point precedes the column point
+                        const bool dpair = lane < held_col(lane, R, sp);
 #pragma unroll
-                    for (int k = 0; k < T; ++k) {
-                        if (!((any >> k) & 1u)) continue;
-                        const bool on = ((full >> k) & 1u) || dstep;
-                        pair_sym_f64<true>(t.x[k], t.y[k], t.z[k], qx[k], qy[k], qz[k], px[k], py[k], pz[k],
-                                           cx, cy, cz, cqx, cqy, cqz, cpx, cpy, cpz,
-                                           !on || (excl && t.g[k] == cg), ax[k], ay[k], az[k], bx, by, bz);
+                        for (int k = 0; k < T; ++k) {
+                            if (!((any >> k) & 1u)) continue;
+                            const bool on = ((full >> k) & 1u) || dpair;
+                            pair_sym_f64<true>(t.x[k], t.y[k], t.z[k], qx[k], qy[k], qz[k], px[k], py[k], pz[k],
+                                               cx, cy, cz, cqx, cqy, cqz, cpx, cpy, cpz,
+                                               !on || (excl && t.g[k] == cg), ax[k], ay[k], az[k], bx, by, bz);
+                        }
+                        cx = row_rot(cx); cy = row_rot(cy); cz = row_rot(cz);
+                        cqx = row_rot(cqx); cqy = row_rot(cqy); cqz = row_rot(cqz);
+                        cpx = row_rot(cpx); cpy = row_rot(cpy); cpz = row_rot(cpz);
+                        bx = row_rot(bx); by = row_rot(by); bz = row_rot(bz);
+                        cg = row_rot(cg);
                     }
-                    cx = wave_rotate(cx); cy = wave_rotate(cy); cz = wave_rotate(cz);
-                    cqx = wave_rotate(cqx); cqy = wave_rotate(cqy); cqz = wave_rotate(cqz);
-                    cpx = wave_rotate(cpx); cpy = wave_rotate(cpy); cpz = wave_rotate(cpz);
-                    bx = wave_rotate(bx); by = wave_rotate(by); bz = wave_rotate(bz);
-                    cg = wave_rotate_i(cg);
+                    cx = cross_rot(cx, xa); cy = cross_rot(cy, xa); cz = cross_rot(cz, xa);
+                    cqx = cross_rot(cqx, xa); cqy = cross_rot(cqy, xa); cqz = cross_rot(cqz, xa);
+                    cpx = cross_rot(cpx, xa); cpy = cross_rot(cpy, xa); cpz = cross_rot(cpz, xa);
+                    bx = cross_rot(bx, xa); by = cross_rot(by, xa); bz = cross_rot(bz, xa);
+                    cg = cross_rot(cg, xa);
                 }
             }
         }
@@ -246,7 +274,7 @@ __global__ __launch_bounds__(kBlock, STOKES_SYM_W64) void sym_main_f64(SymArgs a
     flush_sym_segment<T>(a, Wcur, wave, lane, ax, ay, az);
 }
 
-// out = (+=) pref * (row segments + column partials [+ near sums]), fixed order.
+// out = (+=) pref * (row segments + column partials), fixed order.
 template <int T>
 __global__ __launch_bounds__(kBlock) void sym_reduce(SymArgs a, int64_t grid, double pref, double* out,
                                                      int accumulate) {
@@ -271,8 +299,6 @@ __global__ __launch_bounds__(kBlock) void sym_reduce(SymArgs a, int64_t grid, do
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        if (a.near_part)
-            for (int sl = 0; sl < kNearSlices; ++sl) s[c] += a.near_part[((int64_t)sl * 3 + c) * a.n_pad + p];
         const int64_t o = c * n + p;
         out[o] = accumulate ? out[o] + pref * s[c] : pref * s[c];
     }
@@ -280,15 +306,13 @@ __global__ __launch_bounds__(kBlock) void sym_reduce(SymArgs a, int64_t grid, do
 
 }  // namespace
 
-int sym_blocks_per_cu(int mixed) {
-    (void)mixed;
+int sym_blocks_per_cu() {
     int nb = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sym_main_f64<kSymT64>, kBlock, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-SymPlan plan_sym(int mixed, int64_t n, int resident_blocks, int forced_grid) {
-    (void)mixed;
+SymPlan plan_sym(int64_t n, int resident_blocks, int forced_grid) {
     SymPlan p{};
     p.T = kSymT64;
     const int64_t rb = (int64_t)kBlock * p.T;
@@ -310,7 +334,6 @@ SymPlan plan_sym(int mixed, int64_t n, int resident_blocks, int forced_grid) {
     off = align_up(off + (size_t)(p.grid + p.NW) * 3 * (size_t)rb * sizeof(double), 256);
     p.off_col = off;
     off = align_up(off + (size_t)p.units * kColVals * sizeof(double), 256);
-    p.off_near = p.off_flags = off;   // float64: no near pass
     p.total = off;
     return p;
 }
@@ -318,8 +341,7 @@ SymPlan plan_sym(int mixed, int64_t n, int resident_blocks, int forced_grid) {
 hipError_t launch_sym(const SumInputs& in, const SymPlan& p, double* out, int accumulate, void* ws,
                       hipStream_t stream, const KernelTimer& timer) {
     if (in.n_trg <= 0) return hipSuccess;
-    if (in.mixed || in.kernel != 0) return hipErrorNotSupported;
-    constexpr int T = kSymT64;
+    if (in.kernel != 0 || in.mixed) return hipErrorNotSupported;
     char* base = static_cast<char*>(ws);
     SymArgs a{};
     a.in = in;
@@ -332,18 +354,16 @@ hipError_t launch_sym(const SumInputs& in, const SymPlan& p, double* out, int ac
     a.units = p.units;
     a.row_part = reinterpret_cast<double*>(base + p.off_row);
     a.col_part = reinterpret_cast<double*>(base + p.off_col);
-    a.near_part = nullptr;            // float64: every unit runs in the main kernel
-    a.flags = nullptr;
     hipError_t e = launch_prep(in, p.n_pad, base + p.off_rec, base + p.off_aux,
                                reinterpret_cast<SubMeta*>(base + p.off_meta), stream);
     if (e != hipSuccess) return e;
     if (timer.on()) (void)hipEventRecord(timer.start, stream);
-    sym_main_f64<T><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
+    sym_main_f64<kSymT64><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
     e = hipGetLastError();
     if (timer.on()) (void)hipEventRecord(timer.stop, stream);
     if (e != hipSuccess) return e;
     // the float64 sums are 4 times the bare single-layer sums (doubled positions)
-    sym_reduce<T><<<dim3((unsigned)ceil_div(in.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(
+    sym_reduce<kSymT64><<<dim3((unsigned)ceil_div(in.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(
         a, p.grid, 0.25 * in.pref, out, accumulate);
     return hipGetLastError();
 }

@@ -14,7 +14,9 @@ import paper_1909_11085_amd as S
 from oracle import oracle as O
 from paper_1909_11085_amd import _capi as C
 from paper_1909_11085_amd import workloads as W
-from tests.gpu_util import FP64_TOL, assert_close, dev, device, host
+from tests.gpu_util import FP64_TOL, MIXED_TOL, assert_close, dev, device, host
+
+TOL = {"fp64": FP64_TOL, "mixed": MIXED_TOL}
 
 pytestmark = pytest.mark.gpu
 
@@ -36,49 +38,55 @@ def _shared(seed, n, layout="cells", dup=6):
     return pos, rng.standard_normal((3, n)), rng.uniform(0.1, 1.0, n), g
 
 
-def _run(pos, f, w, g, excl, **kw):
+def _run(pos, f, w, g, excl, precision="fp64", **kw):
     P, G = dev(pos), dev(g)
-    return S.sl(P, dev(f), dev(w), P, src_group=G, trg_group=G, exclude_same_group=excl, **kw)
+    if precision == "mixed":
+        kw.setdefault("group_h", dev(np.full(int(g.max()) + 1, 0.45)))
+    return S.sl(P, dev(f), dev(w), P, src_group=G, trg_group=G, exclude_same_group=excl, precision=precision,
+                **kw)
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1000, 1023, 1024, 1025, 2049, 5000, 17_000])
 @pytest.mark.parametrize("excl", [True, False])
-def test_ragged_sizes(n, excl):
-    print(f"case sym n={n} excl={excl}", flush=True)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ragged_sizes(n, excl, precision):
+    print(f"case sym n={n} excl={excl} {precision}", flush=True)
     pos, f, w, g = _shared(100 + n, n)
-    got = host(_run(pos, f, w, g, excl, mu=0.9))
+    got = host(_run(pos, f, w, g, excl, precision, mu=0.9))
     ref = O.sl(pos, f, w, pos, mu=0.9, src_group=g, trg_group=g, exclude_same_group=excl)
-    assert_close(got, ref, FP64_TOL, f"sym n={n}")
+    assert_close(got, ref, TOL[precision], f"sym n={n} {precision}")
 
 
 @pytest.mark.parametrize("layout", ["cells", "shuffled"])
-def test_layouts_and_one_sided_agree(layout):
-    """Shuffled groups defeat every group-range test (most units go to the
-    near pass); the one-sided path (pair symmetry off) agrees."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_layouts_and_one_sided_agree(layout, precision):
+    """Shuffled groups defeat every group-range test (most units take the
+    masked loop); the one-sided path (pair symmetry off) agrees."""
     pos, f, w, g = _shared(7, 9_000, layout)
     ref = O.sl(pos, f, w, pos, src_group=g, trg_group=g, exclude_same_group=True)
-    got = host(_run(pos, f, w, g, True))
-    assert_close(got, ref, FP64_TOL, layout)
+    got = host(_run(pos, f, w, g, True, precision))
+    assert_close(got, ref, TOL[precision], layout)
     S.set_pair_symmetry(False)
     try:
-        one = host(_run(pos, f, w, g, True))
+        one = host(_run(pos, f, w, g, True, precision))
     finally:
         S.set_pair_symmetry(True)
-    assert_close(one, ref, FP64_TOL, layout + " one-sided")
+    assert_close(one, ref, TOL[precision], layout + " one-sided")
 
 
 @pytest.mark.parametrize("grid", [1, 3, 7, 64, 1000])
-def test_stream_k_cuts(grid):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_stream_k_cuts(grid, precision):
     """Forced workgroup counts cut the unit triangle at other places (ranges
     inside one row block, ranges spanning many)."""
     pos, f, w, g = _shared(8, 6_000)
     ref = O.sl(pos, f, w, pos, src_group=g, trg_group=g, exclude_same_group=True)
     S.set_grid_override(grid)
     try:
-        got = host(_run(pos, f, w, g, True))
+        got = host(_run(pos, f, w, g, True, precision))
     finally:
         S.set_grid_override(0)
-    assert_close(got, ref, FP64_TOL, f"grid={grid}")
+    assert_close(got, ref, TOL[precision], f"grid={grid}")
 
 
 def test_accumulate_and_identity():
@@ -115,14 +123,15 @@ def test_small_workspace_takes_the_one_sided_path():
     assert_close(host(out), ref, FP64_TOL, "one-sided fallback")
 
 
-def test_cells_workload_sampled():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cells_workload_sampled(precision):
     """512 cells (278,528 points), the benchmark's launch: 512 seeded points
     against the oracle."""
     cfg = W.make_config(2)
     c, f = cfg["cells"], cfg["f"]
-    got = host(_run(c.pos, f, c.weight, c.group, True))
+    got = host(_run(c.pos, f, c.weight, c.group, True, precision, group_h=dev(c.group_h)))
     idx = W.subset(np.random.default_rng(222), c.n, 512)
     ref = O.sl(c.pos, f, c.weight, c.pos[:, idx], src_group=c.group, trg_group=c.group[idx],
                exclude_same_group=True)
-    r = assert_close(got[:, idx], ref, FP64_TOL, "cfg2 sym")
-    print(f"cfg2 each-pair-once rel-L2 {r:.3e}")
+    r = assert_close(got[:, idx], ref, TOL[precision], f"cfg2 sym {precision}")
+    print(f"cfg2 each-pair-once {precision} rel-L2 {r:.3e}")

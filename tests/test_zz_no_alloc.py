@@ -70,15 +70,20 @@ def test_two_calls_match_the_workspace_entry_point(ctx, precision):
     for seed, n in ((31, 40_000), (32, 9_001)):              # the second call is smaller
         print(f"case noalloc precision={precision} n={n}", flush=True)
         x = _inputs(seed, n)
-        ref, ws_bytes = _reference(ctx, x, precision)
+        ref, _ = _reference(ctx, x, precision)            # default: each pair once on shared sets
+        assert C.lib().stokes_set_pair_symmetry(ctx, 0) == C.OK
+        try:
+            one, ws_bytes = _reference(ctx, x, precision)  # one-sided kernels
+        finally:
+            assert C.lib().stokes_set_pair_symmetry(ctx, 1) == C.OK
         assert ws_bytes <= C.NOALLOC_SCRATCH_BYTES
         out = torch.full((3, n), np.nan, dtype=torch.float64, device=device())
         rc = _noalloc(ctx, x, precision, out)
         assert rc == C.OK, C.lib().stokes_last_error()
         got = host(out)
         assert_close(got, ref, tol, f"noalloc n={n}")
-        # same kernels and launch shape as the workspace entry point
-        assert np.array_equal(got, ref)
+        # the one-sided kernels and launch shape of the workspace entry point
+        assert np.array_equal(got, one)
 
 
 def test_too_large_is_rejected_untouched(ctx):
@@ -97,4 +102,4 @@ def test_too_large_is_rejected_untouched(ctx):
     ref, _ = _reference(ctx, y, C.FP64)
     out2 = torch.empty((3, 3_000), dtype=torch.float64, device=device())
     assert _noalloc(ctx, y, C.FP64, out2) == C.OK
-    assert np.array_equal(host(out2), ref)
+    assert_close(host(out2), ref, FP64_TOL, "noalloc after a rejection")
