@@ -23,7 +23,7 @@ struct stokes_ctx {
     int clock_khz;
     int forced_grid;             // 0 = resident workgroup count
     int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
-    int sym_resident;            // resident workgroups of the each-pair-once sum
+    int sym_resident[2];         // resident workgroups of the each-pair-once sums [forward, adjoint]
     bool pair_symmetry = true;   // shared point sets take the each-pair-once sum
     int vjp_resident[stokes::kVjpPasses];   // resident workgroups of the adjoint pass kernels
     char arch[64];
@@ -436,7 +436,7 @@ int stokes_create(stokes_ctx** ctx, int device) {
         for (int k = 0; k < 2; ++k)
             for (int m = 0; m < 2; ++m) c->resident[k][m] = stokes::direct_blocks_per_cu(k, m) * c->n_cu;
         stokes::vjp_resident(c->n_cu, c->vjp_resident);
-        c->sym_resident = stokes::sym_blocks_per_cu() * c->n_cu;
+        for (int v = 0; v < 2; ++v) c->sym_resident[v] = stokes::sym_blocks_per_cu(v) * c->n_cu;
         // this device's copy of the no-allocation scratch array (a failure
         // only disables stokes_sl_eval_noalloc, which reports it)
         void* sp = nullptr;
@@ -534,7 +534,7 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
                                          ctx->forced_grid).total;
             // equal sizes may be a shared point set: room for the each-pair-once sum
             if (sym_available(ctx, k, mixed, n_src, n_trg))
-                *bytes = std::max(*bytes, stokes::plan_sym(n_src, ctx->sym_resident, ctx->forced_grid).total);
+                *bytes = std::max(*bytes, stokes::plan_sym(0, n_src, ctx->sym_resident[0], ctx->forced_grid).total);
             return STOKES_OK;
         }
         case STOKES_OP_P2P_SL:
@@ -546,6 +546,9 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
         case STOKES_OP_DL_VJP:
             *bytes = stokes::vjp_workspace_bytes(op == STOKES_OP_SL_VJP ? 0 : 1, n_src, n_trg,
                                                  ctx->vjp_resident);
+            // equal sizes may be a shared point set: room for the each-pair-once adjoint
+            if (op == STOKES_OP_SL_VJP && sym_available(ctx, STOKES_KERNEL_SL, 0, n_src, n_trg))
+                *bytes = std::max(*bytes, stokes::plan_sym(1, n_src, ctx->sym_resident[1], ctx->forced_grid).total);
             return STOKES_OK;
         default:
             return fail(STOKES_EINVAL, "unknown op");
@@ -588,7 +591,7 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
     stokes::SymPlan splan{};
     bool use_sym = false;
     if (allow_sym && shared && sym_available(ctx, kernel, mixed, n_src, n_trg)) {
-        splan = stokes::plan_sym(n_src, ctx->sym_resident, ctx->forced_grid);
+        splan = stokes::plan_sym(0, n_src, ctx->sym_resident[0], ctx->forced_grid);
         use_sym = ws_bytes >= splan.total;
     }
     DeviceGuard dg(ctx->device);
@@ -801,6 +804,21 @@ static int vjp_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* sr
     in.grad_src = grad_src_xyz;
     in.grad_trg = grad_trg_xyz;
     const stokes::KernelTimer timer = stokes::next_timer(ctx);
+    // a shared point set with one combined position gradient takes the
+    // each-pair-once adjoint when the workspace has room for it
+    if (kernel == STOKES_KERNEL_SL && shared && combined &&
+        sym_available(ctx, STOKES_KERNEL_SL, 0, n_src, n_trg)) {
+        const stokes::SymPlan sp = stokes::plan_sym(1, n_src, ctx->sym_resident[1], ctx->forced_grid);
+        if (ws_bytes >= sp.total) {
+            const stokes::SumInputs si = make_inputs(STOKES_KERNEL_SL, p, n_src, src_xyz, density, weight,
+                                                     nullptr, n_trg, trg_xyz, pref);
+            if (timer.on()) (void)hipEventRecord(timer.start, st);
+            hipError_t e = stokes::launch_sym_vjp(si, sp, grad_vel, grad_density, grad_src_xyz, p.accumulate,
+                                                  workspace, st, stokes::KernelTimer{});
+            if (timer.on()) (void)hipEventRecord(timer.stop, st);
+            return launch_status(e, name);
+        }
+    }
     if (timer.on()) (void)hipEventRecord(timer.start, st);
     hipError_t e = kernel ? stokes::launch_dl_vjp(in, ctx->vjp_resident, combined, workspace, st)
                           : stokes::launch_sl_vjp(in, ctx->vjp_resident, combined, workspace, st);

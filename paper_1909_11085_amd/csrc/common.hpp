@@ -102,9 +102,11 @@ hipError_t launch_direct(const SumInputs& in, const DirectPlan& p, double* out, 
 hipError_t launch_prep(const SumInputs& in, int64_t n_pad, void* rec, void* aux, SubMeta* meta,
                        hipStream_t stream);
 
-// Each-pair-once float64 single-layer sum over a shared point set (sources
+// Each-pair-once float64 single-layer sums over a shared point set (sources
 // are the targets, one group array): every unordered pair is evaluated once
-// for both of its points.  Launch shape and workspace, a pure function of n.
+// for both of its points, for the forward sum (adjoint = 0) or for the
+// adjoint's dL/df and total dL/dx (adjoint = 1).  Launch shape and
+// workspace, a pure function of n.
 struct SymPlan {
     int T;                       // 64-point tiles per wave (rows per lane)
     int64_t n_pad;               // points padded to a whole row block
@@ -114,10 +116,14 @@ struct SymPlan {
     int64_t grid;                // workgroups
     size_t off_rec, off_aux, off_meta, off_row, off_col, total;
 };
-int sym_blocks_per_cu();
-SymPlan plan_sym(int64_t n, int resident_blocks, int forced_grid);
+int sym_blocks_per_cu(int adjoint);
+SymPlan plan_sym(int adjoint, int64_t n, int resident_blocks, int forced_grid);
 hipError_t launch_sym(const SumInputs& in, const SymPlan& p, double* out, int accumulate, void* workspace,
                       hipStream_t stream, const KernelTimer& timer);
+// grad_density (dL/df) and grad_xyz (the total dL/dx) may each be null.
+hipError_t launch_sym_vjp(const SumInputs& in, const SymPlan& p, const double* grad_vel, double* grad_density,
+                          double* grad_xyz, int accumulate, void* workspace, hipStream_t stream,
+                          const KernelTimer& timer);
 
 // Writes zeros into n doubles (used for empty source sets).
 hipError_t launch_fill_zero(double* out, int64_t n, hipStream_t stream);

@@ -135,3 +135,75 @@ def test_cells_workload_sampled(precision):
                exclude_same_group=True)
     r = assert_close(got[:, idx], ref, TOL[precision], f"cfg2 sym {precision}")
     print(f"cfg2 each-pair-once {precision} rel-L2 {r:.3e}")
+
+
+# ---------------------------------------------------------------- adjoint
+def _vjp(pos, f, w, g, gu, excl, grad_f=True, grad_x=True, accumulate=False, base=None):
+    P, G, n = dev(pos), dev(g), pos.shape[1]
+    gf = dev(base[0].copy()) if base is not None else (dev(np.zeros((3, n))) if grad_f else None)
+    gx = dev(base[1].copy()) if base is not None else (dev(np.zeros((3, n))) if grad_x else None)
+    S.sl_vjp(P, dev(f), dev(w), P, dev(gu), mu=1.1, src_group=G, trg_group=G, exclude_same_group=excl,
+             grad_f=gf if grad_f else None, grad_src=gx if grad_x else None, grad_trg=gx if grad_x else None,
+             accumulate=accumulate)
+    return (host(gf) if grad_f else None), (host(gx) if grad_x else None)
+
+
+def _vjp_ref(pos, f, w, g, gu, excl):
+    rf, rs, rt = O.sl_vjp(pos, f, w, pos, gu, mu=1.1, src_group=g, trg_group=g, exclude_same_group=excl)
+    return rf, rs + rt
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 1023, 1025, 3000, 9000])
+@pytest.mark.parametrize("excl", [True, False])
+def test_adjoint_ragged_sizes(n, excl):
+    """dL/df and the total dL/dx on a shared point set (one combined position
+    gradient): the each-pair-once adjoint against the oracle."""
+    print(f"case sym adjoint n={n} excl={excl}", flush=True)
+    pos, f, w, g = _shared(300 + n, n)
+    gu = np.random.default_rng(301 + n).standard_normal((3, n))
+    gf, gx = _vjp(pos, f, w, g, gu, excl)
+    rf, rx = _vjp_ref(pos, f, w, g, gu, excl)
+    assert_close(gf, rf, FP64_TOL, f"adjoint dL/df n={n}")
+    assert_close(gx, rx, FP64_TOL, f"adjoint dL/dx n={n}")
+
+
+@pytest.mark.parametrize("layout", ["cells", "shuffled"])
+def test_adjoint_layouts_one_sided_and_outputs(layout):
+    """Shuffled groups (most units masked); the one-sided fused pass agrees;
+    either output alone; accumulation."""
+    n = 5000
+    pos, f, w, g = _shared(17, n, layout)
+    gu = np.random.default_rng(18).standard_normal((3, n))
+    rf, rx = _vjp_ref(pos, f, w, g, gu, True)
+    gf, gx = _vjp(pos, f, w, g, gu, True)
+    assert_close(gf, rf, FP64_TOL, layout + " dL/df")
+    assert_close(gx, rx, FP64_TOL, layout + " dL/dx")
+    assert_close(_vjp(pos, f, w, g, gu, True, grad_f=False)[1], rx, FP64_TOL, "dL/dx alone")
+    base = np.random.default_rng(19).standard_normal((2, 3, n))
+    af, ax = _vjp(pos, f, w, g, gu, True, accumulate=True, base=base)
+    assert_close(af - base[0], rf, FP64_TOL, "accumulated dL/df")
+    assert_close(ax - base[1], rx, FP64_TOL, "accumulated dL/dx")
+    S.set_pair_symmetry(False)
+    try:
+        of, ox = _vjp(pos, f, w, g, gu, True)
+    finally:
+        S.set_pair_symmetry(True)
+    assert_close(of, rf, FP64_TOL, "one-sided dL/df")
+    assert_close(ox, rx, FP64_TOL, "one-sided dL/dx")
+
+
+@pytest.mark.parametrize("grid", [1, 5, 333])
+def test_adjoint_stream_k_cuts(grid):
+    n = 4500
+    pos, f, w, g = _shared(21, n)
+    gu = np.random.default_rng(22).standard_normal((3, n))
+    rf, rx = _vjp_ref(pos, f, w, g, gu, True)
+    S.set_grid_override(grid)
+    try:
+        gf, gx = _vjp(pos, f, w, g, gu, True)
+    finally:
+        S.set_grid_override(0)
+    assert_close(gf, rf, FP64_TOL, f"grid={grid} dL/df")
+    assert_close(gx, rx, FP64_TOL, f"grid={grid} dL/dx")
+    a, b = _vjp(pos, f, w, g, gu, True), _vjp(pos, f, w, g, gu, True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])     # no atomics
