@@ -57,22 +57,44 @@ if ROOT not in sys.path:
 METRIC = "Stokes pair-interactions/s (FP64 vs mixed FP32) at stated rel-L2 error; adjoint/forward"
 # MI355X published vector peaks (256 CUs x 2.4 GHz): FP64 128 flop/clk/CU, FP32 256 (packed).
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
+# Algorithmic flops per pair interaction (add/sub/mul 1, fma 2, rsqrt 1; Newton
+# steps, masks and addressing not counted):
+#   single layer, one ordered pair at a time: 29;
+#   single layer, each unordered pair once for both points (float64 shared
+#   point sets): 10 shared (offset 3, rho^2 5, rsqrt 1, 1/rho^2 1) + 18 per
+#   direction (r.q 5, its scale 1, 3 x two fma 12) = 46 per pair = 23 per
+#   interaction;
+#   double layer: 30.
 FLOPS_PER_PAIR_SL = 29
-FLOPS_PER_PAIR_SL_VJP = 95
+FLOPS_PER_PAIR_SL_SYM = 23
 FLOPS_PER_PAIR_DL = 30
-KERNEL_NAMES = {"fp64": "direct_f64<SL,T=4>", "mixed": "direct_mixed<SL,T=2>"}
-PROFILE_TRAFFIC = {"fp64": "direct_f64_sl_cfg2_traffic.txt", "mixed": "direct_mixed_sl_cfg2_traffic.txt"}
+KERNEL_NAMES = {"fp64": "sym_main<FwdSL,T=6> (each pair once)", "mixed": "direct_mixed<SL,T=2>",
+                "fp64_one_sided": "direct_f64<SL,T=4>"}
+PROFILE_TRAFFIC = {"fp64": "sym_main_f64_sl_cfg2_traffic.txt", "mixed": "direct_mixed_sl_cfg2_traffic.txt",
+                   "fp64_one_sided": "direct_f64_sl_cfg2_traffic.txt"}
+PROFILE_SOURCES = {"fp64": ("sym.hip", "direct_dev.hpp", "common.hpp"),
+                   "mixed": ("direct.hip", "direct_dev.hpp", "common.hpp"),
+                   "fp64_one_sided": ("direct.hip", "direct_dev.hpp", "common.hpp")}
+
+
+def path_key(prec, one_sided):
+    """The kernel a shared-point single-layer sum of this precision takes."""
+    return "fp64_one_sided" if (prec == "fp64" and one_sided) else prec
+
+
+def flops_sl(prec, one_sided):
+    return FLOPS_PER_PAIR_SL_SYM if path_key(prec, one_sided) == "fp64" else FLOPS_PER_PAIR_SL
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the direct-sum kernel sources without comments and whitespace,
-    so that counters taken on the same code stay valid across comment edits."""
+def kernel_source_hash(key):
+    """Hash of a kernel's sources without comments and whitespace, so that
+    counters taken on the same code stay valid across comment edits."""
     h = hashlib.sha256()
-    for f in ("direct.hip", "common.hpp"):
+    for f in PROFILE_SOURCES[key]:
         with open(os.path.join(ROOT, "paper_1909_11085_amd", "csrc", f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -81,16 +103,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(precision):
+def traffic_from_profile(key):
     """HBM bytes per launch from a committed rocprofv3 PMC summary, or None when
     absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", PROFILE_TRAFFIC[precision])
+    path = os.path.join(ROOT, "profiles", PROFILE_TRAFFIC[key])
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash(key):
         return None
     return float(m_bytes.group(1))
 
@@ -243,11 +265,12 @@ def main():
             ms, kms, launches = timed(lambda: fwd(prec), args.steps, args.warmup)
             outputs[prec] = out.cpu().numpy()
             rate = pairs / (ms * 1e-3)
-            achieved = pairs * FLOPS_PER_PAIR_SL / (kms * 1e-3) / 1e12
+            fl = flops_sl(prec, args.one_sided)
+            achieved = pairs * fl / (kms * 1e-3) / 1e12
             results[prec] = dict(ms_per_step=ms, value=rate, kernel_ms=kms, launches=launches,
                                  achieved=achieved, step_ms=per_step(lambda: fwd(prec), 10))
             log(f"{prec}: {ms:.3f} ms/step, {rate:.4e} pairs/s, main kernel {kms:.3f} ms "
-                f"({achieved:.2f} TFLOP/s at {FLOPS_PER_PAIR_SL} flop/pair)")
+                f"({achieved:.2f} TFLOP/s at {fl} flop/pair)")
 
     # adjoint of L = 0.5 |u - u_ref|^2 at a fixed cotangent g (FP64, fused shared-point pass)
     adjoint = None
@@ -302,10 +325,11 @@ def main():
 
     def roofline(prec):
         r = results[prec]
+        key = path_key(prec, args.one_sided)
         return {"bound": "alu", "achieved": round(r["achieved"], 3), "peak": PEAK_TFLOPS[prec],
                 "unit": "TFLOP/s", "frac": round(r["achieved"] / PEAK_TFLOPS[prec], 4),
-                "traffic": traffic_from_profile(prec), "kernel": KERNEL_NAMES[prec],
-                "flops_per_pair": FLOPS_PER_PAIR_SL, "pairs_per_launch": pairs,
+                "traffic": traffic_from_profile(key), "kernel": KERNEL_NAMES[key],
+                "flops_per_pair": flops_sl(prec, args.one_sided), "pairs_per_launch": pairs,
                 "kernel_ms": round(r["kernel_ms"], 4)}
 
     line = {
@@ -345,7 +369,7 @@ def main():
         for name, fn, st in (("cfg3_128_cells", bench_cfg3, 10), ("cfg4_p2p_3840_cells", bench_cfg4, 10),
                              ("cfg5_wall_and_960_cells", bench_cfg5, 3)):
             tc = time.time()
-            line["configs"][name] = fn(S, W, t, timed, st, oracle)
+            line["configs"][name] = fn(S, W, t, timed, st, oracle, args.one_sided)
             log(f"{name} ({time.time() - tc:.1f}s): " + json.dumps(line["configs"][name]))
     if args.secondary:
         line["secondary"] = secondary(S, W, t, timed, log)
@@ -363,7 +387,7 @@ def _roofline(prec, flops, kernel_ms, kernel):
             "frac": round(ach / PEAK_TFLOPS[prec], 4), "kernel": kernel, "kernel_ms": round(kernel_ms, 4)}
 
 
-def bench_cfg3(S, W, t, timed, steps, oracle):
+def bench_cfg3(S, W, t, timed, steps, oracle, one_sided=False):
     """128 cells (69,632 points): single layer forward in both precisions and
     the fused adjoint of L = 0.5 |u - u_ref|^2 (dL/df and the total dL/dx)."""
     import torch
@@ -383,8 +407,10 @@ def bench_cfg3(S, W, t, timed, steps, oracle):
                                          group_h=gh, out=u), steps, 2)
         outs[prec] = u.cpu().numpy()
         km = kms * la / steps
+        key = path_key(prec, one_sided)
         r[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3),
-                   "roofline": _roofline(prec, pairs * FLOPS_PER_PAIR_SL, km, KERNEL_NAMES[prec])}
+                   "roofline": dict(_roofline(prec, pairs * flops_sl(prec, one_sided), km, KERNEL_NAMES[key]),
+                                    flops_per_pair=flops_sl(prec, one_sided))}
     r["mixed_speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r["mixed"]["ms_per_step"]
     g = t(outs["fp64"]) - t(u_ref)
     gf, gx = torch.empty_like(ft), torch.empty_like(pos)
@@ -411,7 +437,7 @@ def bench_cfg3(S, W, t, timed, steps, oracle):
     return r
 
 
-def bench_cfg4(S, W, t, timed, steps, oracle):
+def bench_cfg4(S, W, t, timed, steps, oracle, one_sided=False):
     """3,840 cells (2,088,960 points) in the cylinder, octree leaves of <= 256
     points, lists of 27..60 leaves: the leaf-to-leaf sum in one launch."""
     cfg = W.make_config(4)
@@ -432,8 +458,9 @@ def bench_cfg4(S, W, t, timed, steps, oracle):
                                 group_h=gh).cpu().numpy()
         km = kms * la / steps
         r[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3),
-                   "roofline": _roofline(prec, pairs * FLOPS_PER_PAIR_SL, km,
-                                         "p2p_sum<SL,%s>" % ("FP64" if prec == "fp64" else "mixed"))}
+                   "roofline": dict(_roofline(prec, pairs * FLOPS_PER_PAIR_SL, km,
+                                              "p2p_sum<SL,%s>" % ("FP64" if prec == "fp64" else "mixed")),
+                                    flops_per_pair=FLOPS_PER_PAIR_SL)}
     r["mixed_speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r["mixed"]["ms_per_step"]
     if oracle:
         from oracle import oracle as O
@@ -453,7 +480,7 @@ def bench_cfg4(S, W, t, timed, steps, oracle):
     return r
 
 
-def bench_cfg5(S, W, t, timed, steps, oracle):
+def bench_cfg5(S, W, t, timed, steps, oracle, one_sided=False):
     """Wall + cells: the wall's double layer (1,048,576 nodes) at the 522,240
     points of 960 cells plus the cells' single layer (same-cell rule), added
     into one velocity; then the adjoint of L = 0.5 |u - u_ref|^2 with respect
@@ -484,9 +511,11 @@ def bench_cfg5(S, W, t, timed, steps, oracle):
         ms, kms, la = timed(both, steps, 1)
         outs[prec] = u.cpu().numpy()
         km = kms * la / steps
-        flops = dl_pairs * FLOPS_PER_PAIR_DL + sl_pairs * FLOPS_PER_PAIR_SL
+        flops = dl_pairs * FLOPS_PER_PAIR_DL + sl_pairs * flops_sl(prec, one_sided)
         r[prec] = {"ms_per_step": ms, "pairs_per_s": (dl_pairs + sl_pairs) / (ms * 1e-3),
-                   "roofline": _roofline(prec, flops, km, "direct %s DL + SL" % prec)}
+                   "roofline": dict(_roofline(prec, flops, km, "direct_%s<DL> + %s" % (
+                       prec, KERNEL_NAMES[path_key(prec, one_sided)])),
+                       flops_per_pair_dl=FLOPS_PER_PAIR_DL, flops_per_pair_sl=flops_sl(prec, one_sided))}
     r["mixed_speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r["mixed"]["ms_per_step"]
     g = t(outs["fp64"]) - t(cfg["u_ref"])
     gphi, gfc, gx = torch.empty_like(wphi), torch.zeros_like(cf), torch.empty_like(cp)
