@@ -32,10 +32,7 @@
  * Evaluations are asynchronous on it; the context is read-only after
  * creation, so calls with distinct outputs and workspaces may run
  * concurrently.  FP64 results are deterministic: fixed summation order, no
- * floating-point atomics.  One exception: grad_density of stokes_dl_vjp
- * when it comes from the fused pass (see there) is summed across target
- * blocks with float64 atomic adds, so it may differ in the last bits from
- * run to run.
+ * floating-point atomics, so a repeated call gives the same bits.
  *
  * Errors.  Every call returns a status code.  Arguments are validated on the
  * host before anything is launched; a failed call launches nothing and
@@ -284,8 +281,9 @@ int stokes_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const d
  * position gradient dL/dy + dL/dx: the target-side pass writes (or adds, when
  * accumulating) into it and the source-side pass adds to it.  When
  * grad_density and grad_trg_xyz are asked for without grad_src_xyz, one fused
- * pass over the pairs gives both; its grad_density is summed across target
- * blocks with float64 atomic adds (not bitwise reproducible from run to run). */
+ * pass over the pairs gives both; its grad_density adds per-target-block
+ * partials in a fixed order (the workspace holds 3 doubles per source and
+ * 1,024 targets). */
 int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
                   const double* weight, const double* normal, int64_t n_trg,
                   const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,

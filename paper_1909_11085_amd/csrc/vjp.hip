@@ -408,10 +408,12 @@ struct DlSPhi {
 // One sweep over the (target, source) pairs of the target-side pass also gives,
 // per source, V_m = sum_n r (r.n_m)(r.g_n)/rho^5, so that dL/dphi_m = d w_m V_m
 // (its coefficient is the target side's cq).  V is summed across a wave's
-// targets by a butterfly, across the workgroup's waves in LDS in a fixed
-// order, and across target blocks by float64 atomic adds into a workspace
-// array (so dL/dphi is not bitwise reproducible from run to run; the other
-// outputs are).
+// targets by a butterfly and across the workgroup's waves in LDS in a fixed
+// order, then stored as the unit's partial: one slot per (target block,
+// source).  The near pass adds its masked pairs' V into the slots of the
+// sub-tiles it takes (each slot owned by one workgroup, after the main pass),
+// and a last kernel adds the target blocks in order: deterministic, no
+// atomics.
 
 // v[i][c] over the 64 lanes of the wave: lane l returns the totals of source
 // i = l / 16 (two reduce-scatter steps, then a sum over 16 lanes).
@@ -450,7 +452,7 @@ __device__ __forceinline__ void zero_padding_targets(const PassArgs& a, int64_t 
 }
 
 template <int T, int W>
-__global__ __launch_bounds__(kBlock, W) void dl_fused_main(PassArgs a, double* __restrict__ phi) {
+__global__ __launch_bounds__(kBlock, W) void dl_fused_main(PassArgs a, double* __restrict__ vpart) {
     using P = DlT;
     using Rec = P::Rec;
     constexpr int BT = kBlock * T;
@@ -528,14 +530,15 @@ __global__ __launch_bounds__(kBlock, W) void dl_fused_main(PassArgs a, double* _
         }
         if (active && lane == 0) a.flags[(tbk * 4 + wave) * C + c] = (uint8_t)flags;
         __syncthreads();
-        // this unit's V of source c * 256 + tid: the four waves in order, then one atomic add
-        const int64_t src = c * kTile + threadIdx.x;
-        if (src < a.n_src) {
+        // this unit's V of source c * 256 + tid: the four waves in order, stored
+        // in the slot of (target block, source); padding sources get zeros
+        {
+            const int64_t npad = C * kTile;
+            double* vp = vpart + tbk * 3 * npad + c * kTile + threadIdx.x;
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int i = 3 * threadIdx.x + q;
-                const double sum = ((s_part[0][i] + s_part[1][i]) + s_part[2][i]) + s_part[3][i];
-                if (sum != 0.0) unsafeAtomicAdd(phi + q * a.n_src + src, sum);
+                vp[q * npad] = ((s_part[0][i] + s_part[1][i]) + s_part[2][i]) + s_part[3][i];
             }
         }
         c = cn;
@@ -545,60 +548,106 @@ __global__ __launch_bounds__(kBlock, W) void dl_fused_main(PassArgs a, double* _
 }
 
 // The flagged sub-tiles of dl_fused_main, with the same-group and
-// zero-distance masks; V goes straight to the atomic adds.
+// zero-distance masks.  A workgroup takes the sub-tiles that any wave of its
+// target block flagged (every kNearSlices-th of them, for its grid row): the
+// block stages the sub-tile, each wave that flagged it runs the masked pairs
+// (the others add zeros), and the four waves' V are added in a fixed order
+// into the sub-tile's slots of the block's partial, which no other workgroup
+// touches.
 template <int T>
-__global__ __launch_bounds__(kBlock) void dl_fused_near(PassArgs a, double* __restrict__ phi) {
+__global__ __launch_bounds__(kBlock) void dl_fused_near(PassArgs a, double* __restrict__ vpart) {
     using P = DlT;
     using Rec = P::Rec;
     constexpr int BT = kBlock * T;
-    __shared__ Rec s_src[4][kSub];                 // per-wave staging (see ps::near_pass)
-    __shared__ int32_t s_grp[4][kSub];
+    __shared__ Rec s_src[kSub];
+    __shared__ int32_t s_grp[kSub];
+    __shared__ double s_v[4][3 * kSub];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
-    const int64_t tbk = blockIdx.x, C = a.chunks;
+    const int64_t tbk = blockIdx.x, C = a.chunks, npad = C * kTile;
+    const int slice = (int)blockIdx.y;
     const int64_t tb = tbk * BT + (int64_t)wave * (kWave * T);
-    if (tb >= a.n_trg) return;                     // no barriers below
+    const bool active = tb < a.n_trg;
+    // waves of the block that hold targets (the main pass writes flag rows for those only)
+    const int nw = (int)std::min<int64_t>(4, (a.n_trg - tbk * BT + kWave * T - 1) / (kWave * T));
     const bool excl = a.excl != 0;
     const Rec* rec = reinterpret_cast<const Rec*>(a.rec);
     ps::Tgt<P, T> t;
-    ps::load_tgt<P, T>(a, tb, lane, t);
-    zero_padding_targets<T>(a, tb, lane, t);
+    ps::load_tgt<P, T>(a, active ? tb : tbk * BT, lane, t);
+    zero_padding_targets<T>(a, active ? tb : tbk * BT, lane, t);
     double acc[T][P::NACC];
 #pragma unroll
     for (int k = 0; k < T; ++k)
 #pragma unroll
         for (int q = 0; q < P::NACC; ++q) acc[k][q] = 0.0;
-    const uint8_t* fl = a.flags + (tbk * 4 + wave) * C;
-    ps::for_each_flagged(fl, C, lane, (int)blockIdx.y, [&](int64_t sub) {
-        s_src[wave][lane] = rec[sub * kSub + lane];
-        s_grp[wave][lane] = a.grp[sub * kSub + lane];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll 1
-        for (int j0 = 0; j0 < kSub; j0 += 4) {
-            double v[4][3];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i][0] = v[i][1] = v[i][2] = 0.0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const Rec sr = s_src[wave][j0 + i];
-                const int32_t gs = s_grp[wave][j0 + i];
-#pragma unroll
-                for (int k = 0; k < T; ++k)
-                    P::template pair<true, true>(sr, t.x[k], t.y[k], t.z[k], t.v[k],
-                                                 excl && gs == t.g[k], acc[k], v[i]);
+    const uint8_t* fl = a.flags + tbk * 4 * C;
+    int n = 0;                                     // flagged sub-tiles seen (block-uniform)
+    for (int64_t c0 = 0; c0 < C; c0 += kWave) {
+        uint32_t any = 0, mine = 0;
+        if (c0 + lane < C)
+            for (int w = 0; w < nw; ++w) {
+                const uint32_t f = fl[w * C + c0 + lane];
+                any |= f;
+                if (w == wave) mine = f;
             }
-            double tot[3];
-            wave_sum4x3(v, lane, tot);
-            const int64_t src = sub * kSub + j0 + (lane >> 4);
-            if ((lane & 15) == 0 && src < a.n_src)
+        uint64_t nz = __ballot(any != 0);          // the same in every wave
+        while (nz) {
+            const int l = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint32_t fa = (uint32_t)__builtin_amdgcn_readlane((int)any, l);
+            const uint32_t fm = (uint32_t)__builtin_amdgcn_readlane((int)mine, l);
+            while (fa) {
+                const int sidx = __builtin_ctz(fa);
+                fa &= fa - 1;
+                if (n++ % ps::kNearSlices != slice) continue;
+                const int64_t sub = (c0 + l) * 4 + sidx;
+                __syncthreads();                   // the previous sub-tile's readers are done
+                if (threadIdx.x < kSub) {
+                    s_src[threadIdx.x] = rec[sub * kSub + threadIdx.x];
+                    s_grp[threadIdx.x] = a.grp[sub * kSub + threadIdx.x];
+                }
+                __syncthreads();
+                double* sv = s_v[wave];
+                if (active && ((fm >> sidx) & 1u)) {
+#pragma unroll 1
+                    for (int j0 = 0; j0 < kSub; j0 += 4) {
+                        double v[4][3];
 #pragma unroll
-                for (int q = 0; q < 3; ++q)
-                    if (tot[q] != 0.0) unsafeAtomicAdd(phi + q * a.n_src + src, tot[q]);
+                        for (int i = 0; i < 4; ++i) v[i][0] = v[i][1] = v[i][2] = 0.0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const Rec sr = s_src[j0 + i];
+                            const int32_t gs = s_grp[j0 + i];
+#pragma unroll
+                            for (int k = 0; k < T; ++k)
+                                P::template pair<true, true>(sr, t.x[k], t.y[k], t.z[k], t.v[k],
+                                                             excl && gs == t.g[k], acc[k], v[i]);
+                        }
+                        double tot[3];
+                        wave_sum4x3(v, lane, tot);
+                        // the 16 lanes of a row hold the same totals: all store
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) sv[3 * (j0 + (lane >> 4)) + q] = tot[q];
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) sv[3 * lane + q] = 0.0;
+                }
+                __syncthreads();
+                if (threadIdx.x < kSub) {
+                    double* vp = vpart + tbk * 3 * npad + sub * kSub + threadIdx.x;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const int i = 3 * threadIdx.x + q;
+                        vp[q * npad] += ((s_v[0][i] + s_v[1][i]) + s_v[2][i]) + s_v[3][i];
+                    }
+                }
+            }
         }
-        __builtin_amdgcn_wave_barrier();           // reads of this sub-tile precede the next writes
-    });
+    }
+    if (!active) return;                           // no barriers below
     const int64_t np = (int64_t)gridDim.x * BT;
-    double* part = a.near_part + (int64_t)blockIdx.y * P::NACC * np;
+    double* part = a.near_part + (int64_t)slice * P::NACC * np;
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int64_t gi = tbk * BT + wave * (kWave * T) + k * kWave + lane;
@@ -607,16 +656,19 @@ __global__ __launch_bounds__(kBlock) void dl_fused_near(PassArgs a, double* __re
     }
 }
 
-// dL/dphi_m = d w_m V_m
-__global__ __launch_bounds__(kBlock) void dl_phi_store(const double* __restrict__ phi,
-                                                       const double* __restrict__ weight, double pref,
-                                                       double* __restrict__ out, int64_t n, int accumulate) {
+// dL/dphi_m = d w_m V_m, V_m the target blocks' partials added in order
+__global__ __launch_bounds__(kBlock) void dl_phi_reduce(const double* __restrict__ vpart, int64_t blocks,
+                                                        int64_t npad, const double* __restrict__ weight,
+                                                        double pref, double* __restrict__ out, int64_t n,
+                                                        int accumulate) {
     const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (m >= n) return;
     const double s = pref * weight[m];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const double val = s * phi[q * n + m];
+        double v = 0.0;
+        for (int64_t b = 0; b < blocks; ++b) v += vpart[(b * 3 + q) * npad + m];
+        const double val = s * v;
         out[q * n + m] = accumulate ? out[q * n + m] + val : val;
     }
 }
@@ -637,12 +689,13 @@ constexpr int kTSlSF = 4, kWSlSF = 4;
 constexpr int kTDlSPhi = 4, kWDlSPhi = 3;
 constexpr int kTDlF = 4, kWDlF = 2;
 
-// workspace of the fused double-layer pass: the target-side pass, then V (3, n_src)
-size_t dl_fused_bytes(int64_t n_src, int64_t n_trg, int resident, size_t* off_phi) {
+// workspace of the fused double-layer pass: the target-side pass, then the
+// partials of V, (target block, 3, padded source)
+size_t dl_fused_bytes(int64_t n_src, int64_t n_trg, int resident, size_t* off_v) {
     const auto p = ps::plan_pass<DlT, kTDlF>(n_src, n_trg, resident);
     const size_t off = align_up(p.total, 256);
-    if (off_phi) *off_phi = off;
-    return align_up(off + (size_t)3 * n_src * sizeof(double), 256);
+    if (off_v) *off_v = off;
+    return align_up(off + (size_t)p.blocks_x * 3 * p.n_src_pad * sizeof(double), 256);
 }
 
 }  // namespace
@@ -760,8 +813,8 @@ static hipError_t launch_dl_fused(const VjpInputs& in, int resident, void* ws, h
     a.out[0] = in.grad_trg;
     a.pref = in.pref;
     const auto p = ps::plan_pass<DlT, kTDlF>(in.n_src, in.n_trg, resident);
-    size_t off_phi = 0;
-    (void)dl_fused_bytes(in.n_src, in.n_trg, resident, &off_phi);
+    size_t off_v = 0;
+    (void)dl_fused_bytes(in.n_src, in.n_trg, resident, &off_v);
     char* base = static_cast<char*>(ws);
     a.rec = base + p.off_rec;
     a.grp = reinterpret_cast<int32_t*>(base + p.off_grp);
@@ -771,20 +824,20 @@ static hipError_t launch_dl_fused(const VjpInputs& in, int resident, void* ws, h
     a.flags = reinterpret_cast<uint8_t*>(base + p.off_flags);
     a.chunks = p.chunks;
     a.units = p.units;
-    double* phi = reinterpret_cast<double*>(base + off_phi);
+    double* vpart = reinterpret_cast<double*>(base + off_v);
     ps::prep<DlT><<<dim3((unsigned)(p.n_src_pad / kBlock)), dim3(kBlock), 0, stream>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = launch_fill_zero(phi, 3 * in.n_src, stream)) != hipSuccess) return e;
-    dl_fused_main<kTDlF, kWDlF><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a, phi);
+    // the main pass writes every (target block, source) slot of vpart
+    dl_fused_main<kTDlF, kWDlF><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a, vpart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    dl_fused_near<kTDlF><<<dim3((unsigned)p.blocks_x, ps::kNearSlices), dim3(kBlock), 0, stream>>>(a, phi);
+    dl_fused_near<kTDlF><<<dim3((unsigned)p.blocks_x, ps::kNearSlices), dim3(kBlock), 0, stream>>>(a, vpart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     ps::reduce<DlT, kTDlF><<<dim3((unsigned)ceil_div(a.n_trg, kBlock)), dim3(kBlock), 0, stream>>>(
         a, p.grid, p.blocks_x * (int64_t)kBlock * kTDlF);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    dl_phi_store<<<dim3((unsigned)ceil_div(in.n_src, kBlock)), dim3(kBlock), 0, stream>>>(
-        phi, in.weight, in.pref, in.grad_density, in.n_src, in.accumulate);
+    dl_phi_reduce<<<dim3((unsigned)ceil_div(in.n_src, kBlock)), dim3(kBlock), 0, stream>>>(
+        vpart, p.blocks_x, p.n_src_pad, in.weight, in.pref, in.grad_density, in.n_src, in.accumulate);
     return hipGetLastError();
 }
 

@@ -62,7 +62,8 @@ def test_dl_vjp_general(excl, sizes):
 @pytest.mark.parametrize("sizes", [(1000, 777), (257, 1), (1, 300), (3001, 2049)])
 def test_dl_vjp_density_and_target_fused(excl, sizes):
     """dL/dphi with dL/dx (no dL/dy): one sweep over the pairs gives both, the
-    density gradient summed across target blocks; also accumulates."""
+    density gradient added across target blocks in a fixed order; also
+    accumulates."""
     print(f"case dl_vjp fused excl={excl} sizes={sizes}", flush=True)
     c = _cloud(90 + sizes[1], *sizes)
     rng = np.random.default_rng(4)
@@ -282,6 +283,32 @@ def test_cfg5_wall_adjoint_sampled():
     r1 = assert_close(host(gt)[:, it], rt, VJP_TOL, "cfg5 dL/dx")
     r2 = assert_close(host(gp)[:, iw], rp, VJP_TOL, "cfg5 dL/dphi")
     print(f"cfg5 DL adjoint rel-L2: dL/dx {r1:.3e}, dL/dphi {r2:.3e}")
+    # fixed summation order: a second call gives the same bits
+    gp2, gt2 = _z(wall.n), _z(cells.n)
+    S.dl_vjp(*args, g, grad_phi=gp2, grad_trg=gt2)
+    assert torch.equal(gp, gp2) and torch.equal(gt, gt2)
+
+
+@pytest.mark.parametrize("excl", [True, False])
+def test_dl_fused_repeatable_on_shared_points(excl):
+    """The fused dL/dphi + dL/dx pass on a shared point set (every target
+    block flags sub-tiles for its near pass): two calls agree bit for bit and
+    match the oracle."""
+    print(f"case dl fused repeatable excl={excl}", flush=True)
+    c = _cloud(97, 5000, 5000)
+    g = np.random.default_rng(98).standard_normal((3, 5000))
+    pos, grp = dev(c["y"]), dev(c["gs"])
+    outs = []
+    for _ in range(2):
+        gp, gt = _z(5000), _z(5000)
+        S.dl_vjp(pos, dev(c["f"]), dev(c["w"]), dev(c["n"]), pos, dev(g), src_group=grp, trg_group=grp,
+                 exclude_same_group=excl, grad_phi=gp, grad_trg=gt)
+        outs.append((gp, gt))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    rp, _, rt = O.dl_vjp(c["y"], c["f"], c["w"], c["n"], c["y"], g, src_group=c["gs"], trg_group=c["gs"],
+                         exclude_same_group=excl, want=("phi", "trg"))
+    assert_close(host(outs[0][0]), rp, VJP_TOL, "shared fused dL/dphi")
+    assert_close(host(outs[0][1]), rt, VJP_TOL, "shared fused dL/dtrg")
 
 
 @pytest.fixture(scope="module")
