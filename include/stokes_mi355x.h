@@ -145,6 +145,23 @@ int stokes_set_grid_override(stokes_ctx* ctx, int32_t workgroups);
  * thread-safe against running calls. */
 int stokes_set_pair_symmetry(stokes_ctx* ctx, int32_t on);
 
+/* Test-only record of the mixed-precision split (float32 pairs, float64 near
+ * pairs, excluded pairs; the near rule of stokes_exclusion).  While an array
+ * is registered, every STOKES_MIXED call of stokes_sl_eval, stokes_dl_eval,
+ * stokes_sl_eval_noalloc and stokes_p2p_leaf_eval with these n_trg and n_src
+ * runs instrumented copies of its kernels, which add, for each (target t,
+ * source s) pair they take, one class code into classes[t * n_src + s]
+ * (device memory, int32, zeroed by the caller): STOKES_PAIR_F32, _F64 or
+ * _SKIP (same group, or zero distance).  A pair taken once holds exactly one
+ * code; a pair a leaf-to-leaf sum does not list stays 0.  The instrumented
+ * kernels are slow (one atomic add per pair).  classes = NULL unregisters;
+ * a mixed call of other sizes fails with STOKES_EINVAL while one is
+ * registered.  FP64 calls ignore it. */
+#define STOKES_PAIR_F32 1
+#define STOKES_PAIR_F64 (1 << 8)
+#define STOKES_PAIR_SKIP (1 << 16)
+int stokes_debug_pair_classes(stokes_ctx* ctx, int32_t* classes, int64_t n_trg, int64_t n_src);
+
 /* Kernel timing for benchmarks.  While enabled, every evaluation records a
  * pair of HIP events around its main summation kernel(s) (not the prep or
  * reduction kernels) on the call's stream.  stokes_timing_read waits for

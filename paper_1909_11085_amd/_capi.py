@@ -20,6 +20,7 @@ EXCL_NONE, EXCL_SAME_GROUP = 0, 1
 KERNEL_SL, KERNEL_DL = 0, 1
 OP_SL, OP_DL, OP_P2P_SL, OP_P2P_DL, OP_SL_VJP, OP_DL_VJP = range(6)
 NOALLOC_SCRATCH_BYTES = 64 << 20
+PAIR_F32, PAIR_F64, PAIR_SKIP = 1, 1 << 8, 1 << 16
 STATUS_NAMES = {OK: "STOKES_OK", EINVAL: "STOKES_EINVAL", EDEVICE: "STOKES_EDEVICE",
                 ELAUNCH: "STOKES_ELAUNCH", EWORKSPACE: "STOKES_EWORKSPACE",
                 EUNSUPPORTED: "STOKES_EUNSUPPORTED"}
@@ -64,6 +65,7 @@ _SIGNATURES = {
     "stokes_version": (ctypes.c_int, []),
     "stokes_set_grid_override": (ctypes.c_int, [_vp, _i32]),
     "stokes_set_pair_symmetry": (ctypes.c_int, [_vp, _i32]),
+    "stokes_debug_pair_classes": (ctypes.c_int, [_vp, _vp, _i64, _i64]),
     "stokes_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "stokes_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
     "stokes_workspace_size": (ctypes.c_int, [_vp, _i32, _i64, _i64, _i32, _OP, ctypes.POINTER(_sz)]),

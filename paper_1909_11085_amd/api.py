@@ -46,6 +46,20 @@ def set_pair_symmetry(on=True, device=None):
     C.check(C.lib().stokes_set_pair_symmetry(context(device), int(bool(on))))
 
 
+def debug_pair_classes(classes, device=None):
+    """Test-only: register an int32 (n_trg, n_src) device tensor (zeroed) that
+    the mixed direct and leaf-to-leaf sums of those sizes fill with the class
+    code of every pair they take (see stokes_debug_pair_classes); None
+    unregisters."""
+    if classes is None:
+        C.check(C.lib().stokes_debug_pair_classes(context(device), None, 0, 0))
+        return
+    if classes.dtype != torch.int32 or classes.dim() != 2 or not classes.is_contiguous():
+        raise ValueError("classes must be a contiguous int32 (n_trg, n_src) tensor")
+    C.check(C.lib().stokes_debug_pair_classes(context(classes.device), _ptr(classes), classes.shape[0],
+                                              classes.shape[1]))
+
+
 def timing_enable(on=True, device=None):
     """Record HIP events around each evaluation's main summation kernel."""
     C.check(C.lib().stokes_timing_enable(context(device), int(bool(on))))

@@ -25,6 +25,10 @@ struct stokes_ctx {
     int resident[2][2];          // [kernel][mixed]: resident workgroups of the direct sums
     int sym_resident[2];         // resident workgroups of the each-pair-once sums [forward, adjoint]
     bool pair_symmetry = true;   // shared point sets take the each-pair-once sum
+    // test-only pair-class array of the mixed direct and leaf-to-leaf sums
+    // (stokes_debug_pair_classes) and the sizes it was registered for
+    int32_t* pair_class = nullptr;
+    int64_t pair_class_trg = 0, pair_class_src = 0;
     int vjp_resident[stokes::kVjpPasses];   // resident workgroups of the adjoint pass kernels
     char arch[64];
     // device address of this device's copy of `scratch` (stokes_sl_eval_noalloc)
@@ -509,6 +513,33 @@ int stokes_set_pair_symmetry(stokes_ctx* ctx, int32_t on) {
     return STOKES_OK;
 }
 
+int stokes_debug_pair_classes(stokes_ctx* ctx, int32_t* classes, int64_t n_trg, int64_t n_src) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!classes) {
+        ctx->pair_class = nullptr;
+        ctx->pair_class_trg = ctx->pair_class_src = 0;
+        return STOKES_OK;
+    }
+    if (n_trg <= 0 || n_src <= 0 || n_trg > (int64_t(1) << 40) / n_src)
+        return fail(STOKES_EINVAL, "n_trg and n_src must be > 0 with n_trg * n_src <= 2^40");
+    if (reinterpret_cast<uintptr_t>(classes) % 4 != 0) return fail(STOKES_EINVAL, "classes must be 4-byte aligned");
+    ctx->pair_class = classes;
+    ctx->pair_class_trg = n_trg;
+    ctx->pair_class_src = n_src;
+    return STOKES_OK;
+}
+
+// The pair-class array for a mixed call of these sizes (null when none is
+// registered); a registered array of other sizes is an error.
+static int pair_class_for(const stokes_ctx* ctx, int mixed, int64_t n_src, int64_t n_trg, int32_t** out) {
+    *out = nullptr;
+    if (!mixed || !ctx->pair_class) return STOKES_OK;
+    if (n_trg != ctx->pair_class_trg || n_src != ctx->pair_class_src)
+        return fail(STOKES_EINVAL, "the pair-class array was registered for other sizes");
+    *out = ctx->pair_class;
+    return STOKES_OK;
+}
+
 // Whether the single-layer sum with these sizes and precision has an
 // each-pair-once form (used only when the call's point set is shared).
 static bool sym_available(const stokes_ctx* ctx, int kernel, int mixed, int64_t n_src, int64_t n_trg) {
@@ -584,6 +615,8 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
     }
     rc = check_workspace(workspace, ws_bytes, need);
     if (rc) return rc;
+    int32_t* pair_class = nullptr;
+    if ((rc = pair_class_for(ctx, mixed, n_src, n_trg, &pair_class))) return rc;
     // a shared point set (one array, one group array) takes the each-pair-once
     // sum when the workspace has room for it
     const bool shared = src_xyz == trg_xyz && n_src == n_trg &&
@@ -596,8 +629,9 @@ static int direct_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double*
     }
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
-    const stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal,
-                                             n_trg, trg_xyz, pref);
+    stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal,
+                                       n_trg, trg_xyz, pref);
+    in.pair_class = pair_class;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     if (use_sym)
         return launch_status(stokes::launch_sym(in, splan, vel_out, p.accumulate, workspace, st,
@@ -721,6 +755,8 @@ int stokes_p2p_leaf_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t k
     const int32_t nl = (int32_t)stokes::p2p_plan_info(plan, 2);
     rc = check_workspace(workspace, ws_bytes, stokes::p2p_workspace_bytes(kernel, mixed, n_src, n_trg, nl));
     if (rc) return rc;
+    int32_t* pair_class = nullptr;
+    if ((rc = pair_class_for(ctx, mixed, n_src, n_trg, &pair_class))) return rc;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -729,8 +765,9 @@ int stokes_p2p_leaf_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t k
         return p.accumulate ? STOKES_OK
                             : launch_status(stokes::launch_fill_zero(vel_out, 3 * n_trg, st), "stokes_p2p_leaf_eval");
     const double pref = kernel == STOKES_KERNEL_SL ? 1.0 / (8.0 * kPi * mu) : 6.0 / (8.0 * kPi);
-    const stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal, n_trg,
-                                             trg_xyz, pref);
+    stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal, n_trg,
+                                       trg_xyz, pref);
+    in.pair_class = pair_class;
     return launch_status(stokes::launch_p2p(in, plan, vel_out, p.accumulate, workspace, st,
                                             stokes::next_timer(ctx)),
                          "stokes_p2p_leaf_eval");

@@ -64,7 +64,15 @@ struct SumInputs {
     int32_t n_groups;
     double near_frac;
     double pref;                 // 1/(8 pi mu) or 6/(8 pi)
+    // test-only: when set, the mixed direct and leaf-to-leaf kernels add, for
+    // every pair they take, its class code into pair_class[t * n_src + s]
+    int32_t* pair_class;
 };
+
+// class codes of pair_class (one pair taken once holds exactly one of them)
+constexpr int32_t kPairF32 = 1;        // float32 pair
+constexpr int32_t kPairF64 = 1 << 8;   // float64 near pair
+constexpr int32_t kPairSkip = 1 << 16; // excluded: same group, or zero distance
 
 // Launch shape of a direct sum; a pure function of sizes and options so that
 // the workspace query and the evaluation agree.

@@ -291,8 +291,9 @@ __global__ __launch_bounds__(kBlock) void direct_near_f64(DirectArgs a) {
 }
 
 // Main mixed kernel: float32 fast loop only; sub-tiles needing care are
-// flagged for direct_near_mixed.
-template <int KT, int T>
+// flagged for direct_near_mixed.  CNT: also record each pair's class
+// (test-only instantiation).
+template <int KT, int T, bool CNT = false>
 __global__ __launch_bounds__(kBlock, STOKES_DIRECT_W32) void direct_mixed(DirectArgs a) {
     using Rec = typename SrcRec<KT, 1>::type;
     constexpr int BT = kBlock * T;
@@ -366,6 +367,15 @@ __global__ __launch_bounds__(kBlock, STOKES_DIRECT_W32) void direct_mixed(Direct
                     ay[k] += (double)by[k];
                     az[k] += (double)bz[k];
                 }
+                if constexpr (CNT) {
+                    const int64_t s0 = c * kTile + s * kSub;
+                    for (int k = 0; k < T; ++k) {
+                        const int64_t ti = tbk * BT + (int64_t)wave * (kWave * T) + k * kWave + lane;
+                        if (ti < a.in.n_trg)
+                            for (int j = 0; j < m.count; ++j)
+                                atomicAdd(a.in.pair_class + ti * a.in.n_src + s0 + j, kPairF32);
+                    }
+                }
             }
             if (lane == 0) a.flags[(tbk * 4 + wave) * C + c] = (uint8_t)flags;
         }
@@ -376,8 +386,9 @@ __global__ __launch_bounds__(kBlock, STOKES_DIRECT_W32) void direct_mixed(Direct
 }
 
 // Near pass (mixed): flagged sub-tiles with r from high + low float32 parts,
-// the same-group mask, and pairs inside the near radius in float64.
-template <int KT, int T>
+// the same-group mask, and pairs inside the near radius in float64.  CNT:
+// also record each pair's class (test-only instantiation).
+template <int KT, int T, bool CNT = false>
 __global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
     using Rec = typename SrcRec<KT, 1>::type;
     constexpr int BT = kBlock * T;
@@ -433,6 +444,17 @@ __global__ __launch_bounds__(kBlock) void direct_near_mixed(DirectArgs a) {
                 if (near && !excluded)
                     near_pair_f64<KT>(a.in, sub * kSub + j, t.x[k], t.y[k], t.z[k], ax[k], ay[k],
                                       az[k]);
+                if constexpr (CNT) {
+                    const int64_t si = sub * kSub + j, ti = tb + k * kWave + lane;
+                    if (si < a.in.n_src && ti < a.in.n_trg) {
+                        // near_pair_f64 takes nothing at zero distance (float64)
+                        const int64_t ns = a.in.n_src;
+                        const bool zero = t.x[k] == a.in.src_xyz[si] && t.y[k] == a.in.src_xyz[ns + si] &&
+                                          t.z[k] == a.in.src_xyz[2 * ns + si];
+                        const int32_t cls = excluded ? kPairSkip : !near ? kPairF32 : zero ? kPairSkip : kPairF64;
+                        atomicAdd(a.in.pair_class + ti * ns + si, cls);
+                    }
+                }
             }
         }
 #pragma unroll
@@ -585,16 +607,22 @@ static hipError_t launch_typed(const SumInputs& in, const DirectPlan& p, double*
     a.near_part = reinterpret_cast<double*>(base + p.off_near);
     a.flags = reinterpret_cast<uint8_t*>(base + p.off_flags);
     if (timer.on()) (void)hipEventRecord(timer.start, stream);
-    if constexpr (MIXED != 0)
-        direct_mixed<KT, T><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
-    else
+    if constexpr (MIXED != 0) {
+        if (in.pair_class)
+            direct_mixed<KT, T, true><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
+        else
+            direct_mixed<KT, T><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
+    } else
         direct_f64<KT, T><<<dim3((unsigned)p.grid), dim3(kBlock), 0, stream>>>(a);
     e = hipGetLastError();
     if (timer.on()) (void)hipEventRecord(timer.stop, stream);
     if (e != hipSuccess) return e;
-    if constexpr (MIXED != 0)
-        direct_near_mixed<KT, T><<<dim3((unsigned)p.blocks_x, kNearSlices), dim3(kBlock), 0, stream>>>(a);
-    else
+    if constexpr (MIXED != 0) {
+        if (in.pair_class)
+            direct_near_mixed<KT, T, true><<<dim3((unsigned)p.blocks_x, kNearSlices), dim3(kBlock), 0, stream>>>(a);
+        else
+            direct_near_mixed<KT, T><<<dim3((unsigned)p.blocks_x, kNearSlices), dim3(kBlock), 0, stream>>>(a);
+    } else
         direct_near_f64<KT, T><<<dim3((unsigned)p.blocks_x, kNearSlices), dim3(kBlock), 0, stream>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

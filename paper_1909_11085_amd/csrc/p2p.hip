@@ -253,7 +253,8 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-template <int KT, int MIXED>
+// CNT (mixed, test-only instantiation): also record each pair's class.
+template <int KT, int MIXED, bool CNT = false>
 __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     using Rec = typename P2PRec<KT, MIXED>::type;
     constexpr int kSlots = kP2PTile + 2 * kMaxRep;
@@ -373,6 +374,11 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                     for (int q = 0; q < kMaxTGroups; ++q) shared |= (q < ntg) && g == tgl[q];
                 }
                 const bool keep = in && !(excl && ntg == 1 && g == tgl[0]);
+                if constexpr (CNT) {
+                    if (in && !keep)                   // every target of the item shares its group
+                        for (int q = 0; q < nc; ++q)
+                            atomicAdd(a.in.pair_class + (t0 + q) * a.in.n_src + si, kPairSkip);
+                }
                 const bool back = close || shared;
                 const uint64_t mf = __ballot(keep && !back), mk = __ballot(keep && back);
                 if (MIXED && __ballot(keep && close)) any_close = true;
@@ -407,11 +413,24 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                 float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll 4
                 for (int j = 0; j < m_clean; ++j) pair32<KT, false>(pc[j], xs, ys, zs, false, bx, by, bz);
+                // CNT: staged slots [0, n_clean) and [kb + back padding, kSlots) hold real sources
+                const int back_real = kb + (n_back_pad - n_back);
+                if constexpr (CNT) {
+                    if (valid)
+                        for (int j = 0; j < m_clean; ++j)
+                            if (h * m_clean + j < n_clean)
+                                atomicAdd(a.in.pair_class + idx * a.in.n_src + s0 + pc[j].src, kPairF32);
+                }
                 if (!any_close) {
 #pragma unroll 2
                     for (int j = 0; j < m_back; ++j) {
                         const Rec sr = pb[j];
                         pair32<KT, true>(sr, xs, ys, zs, excl && sr.g == tg, bx, by, bz);
+                        if constexpr (CNT) {
+                            if (valid && kb + h * m_back + j >= back_real)
+                                atomicAdd(a.in.pair_class + idx * a.in.n_src + s0 + sr.src,
+                                          (excl && sr.g == tg) ? kPairSkip : kPairF32);
+                        }
                     }
                 } else {
                     // residues, near test, float64 near pairs
@@ -444,6 +463,16 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
                             ax += v.x;
                             ay += v.y;
                             az += v.z;
+                        }
+                        if constexpr (CNT) {
+                            if (valid && kb + h * m_back + j >= back_real) {
+                                // near64 takes nothing at zero distance (float64)
+                                const int64_t nsrc = a.in.n_src, si = s0 + sr.src;
+                                const bool zero = x == a.in.src_xyz[si] && y == a.in.src_xyz[nsrc + si] &&
+                                                  z == a.in.src_xyz[2 * nsrc + si];
+                                atomicAdd(a.in.pair_class + idx * nsrc + si,
+                                          excluded ? kPairSkip : !near ? kPairF32 : zero ? kPairSkip : kPairF64);
+                            }
                         }
                     }
                 }
@@ -521,7 +550,14 @@ hipError_t run_p2p(P2PArgs a, const stokes_p2p_plan* plan, void* ws, hipStream_t
     }
     if (plan->n_items == 0) return hipSuccess;
     if (timer.on()) (void)hipEventRecord(timer.start, stream);
-    p2p_sum<KT, MIXED><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+    if constexpr (MIXED != 0) {
+        if (a.in.pair_class)
+            p2p_sum<KT, MIXED, true><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+        else
+            p2p_sum<KT, MIXED><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+    } else {
+        p2p_sum<KT, MIXED><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+    }
     hipError_t e = hipGetLastError();
     if (timer.on()) (void)hipEventRecord(timer.stop, stream);
     return e;
