@@ -450,14 +450,21 @@ def bench_cfg4(S, W, t, timed, steps, oracle, one_sided=False):
                      "octree leaves of <= 256 points, each leaf summing over its 27..60 nearest leaves; "
                      "single layer, same-cell pairs excluded",
          "pairs": pairs, "listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
+    # the leaf layout as device arrays, passed per call (the items are built,
+    # checked and sorted on the device inside the timed step)
+    lay = (t(tree.leaf_ofs.astype(np.int64)), t(tree.leaf_ofs.astype(np.int64)), t(ofs.astype(np.int64)),
+           t(ul.astype(np.int32)))
+    r["layout"] = "device leaf arrays per call (stokes_p2p_leaf_eval)"
     outs = {}
     for prec in ("fp64", "mixed"):
-        ms, kms, la = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
+        ms, kms, la = timed(lambda: S.p2p_leaf(lay, pos, ft, wt, pos, src_group=grp, trg_group=grp,
                                                precision=prec, group_h=gh), steps, 2)
-        outs[prec] = S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=prec,
+        outs[prec] = S.p2p_leaf(lay, pos, ft, wt, pos, src_group=grp, trg_group=grp, precision=prec,
                                 group_h=gh).cpu().numpy()
         km = kms * la / steps
-        r[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3),
+        ms_plan, _, _ = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
+                                                 precision=prec, group_h=gh), steps, 2)
+        r[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "plan_ms_per_step": ms_plan,
                    "roofline": dict(_roofline(prec, pairs * FLOPS_PER_PAIR_SL, km,
                                               "p2p_sum<SL,%s>" % ("FP64" if prec == "fp64" else "mixed")),
                                     flops_per_pair=FLOPS_PER_PAIR_SL)}
@@ -565,9 +572,12 @@ def time_p2p(S, W, t, timed, steps, warmup):
     plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, cfg["ulist_ofs"], cfg["ulist"], c.n, c.n)
     pos, ft, wt, grp, gh = t(c.pos), t(f), t(c.weight), t(c.group), t(c.group_h)
     pairs = W.pair_count_p2p(tree.leaf_ofs, cfg["ulist_ofs"], cfg["ulist"], c.group, True)
-    r = {"pairs": pairs, "listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1}
+    lay = (t(tree.leaf_ofs.astype(np.int64)), t(tree.leaf_ofs.astype(np.int64)),
+           t(cfg["ulist_ofs"].astype(np.int64)), t(cfg["ulist"].astype(np.int32)))
+    r = {"pairs": pairs, "listed_pairs": plan.pairs(), "leaves": len(tree.leaf_ofs) - 1,
+         "layout": "device leaf arrays per call"}
     for prec in ("mixed", "fp64"):
-        ms, kms, _ = timed(lambda: S.p2p_leaf(plan, pos, ft, wt, pos, src_group=grp, trg_group=grp,
+        ms, kms, _ = timed(lambda: S.p2p_leaf(lay, pos, ft, wt, pos, src_group=grp, trg_group=grp,
                                               precision=prec, group_h=gh), steps, warmup)
         r[f"{prec}_ms"] = ms
         r[f"{prec}_kernel_ms"] = kms

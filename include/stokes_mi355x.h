@@ -146,17 +146,17 @@ int stokes_set_grid_override(stokes_ctx* ctx, int32_t workgroups);
 int stokes_set_pair_symmetry(stokes_ctx* ctx, int32_t on);
 
 /* Test-only record of the mixed-precision split (float32 pairs, float64 near
- * pairs, excluded pairs; the near rule of stokes_exclusion).  While an array
+ * pairs, excluded pairs; the near rule of stokes_exclusion). While an array
  * is registered, every STOKES_MIXED call of stokes_sl_eval, stokes_dl_eval,
- * stokes_sl_eval_noalloc and stokes_p2p_leaf_eval with these n_trg and n_src
- * runs instrumented copies of its kernels, which add, for each (target t,
- * source s) pair they take, one class code into classes[t * n_src + s]
- * (device memory, int32, zeroed by the caller): STOKES_PAIR_F32, _F64 or
- * _SKIP (same group, or zero distance).  A pair taken once holds exactly one
- * code; a pair a leaf-to-leaf sum does not list stays 0.  The instrumented
- * kernels are slow (one atomic add per pair).  classes = NULL unregisters;
- * a mixed call of other sizes fails with STOKES_EINVAL while one is
- * registered.  FP64 calls ignore it. */
+ * stokes_sl_eval_noalloc, stokes_p2p_leaf_eval and stokes_p2p_plan_eval with
+ * these n_trg and n_src runs instrumented copies of its kernels, which add,
+ * for each (target t, source s) pair they take, one class code into
+ * classes[t * n_src + s] (device memory, int32, zeroed by the caller):
+ * STOKES_PAIR_F32, _F64 or _SKIP (same group, or zero distance). A pair
+ * taken once holds exactly one code; a pair a leaf-to-leaf sum does not list
+ * stays 0. The instrumented kernels are slow (one atomic add per pair).
+ * classes = NULL unregisters; a mixed call of other sizes fails with
+ * STOKES_EINVAL while one is registered. FP64 calls ignore it. */
 #define STOKES_PAIR_F32 1
 #define STOKES_PAIR_F64 (1 << 8)
 #define STOKES_PAIR_SKIP (1 << 16)
@@ -231,15 +231,37 @@ int stokes_dl_eval(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const 
 
 /* ---- leaf-to-leaf (P2P) form of the FMM near field, Sec. 3.1 ------------- */
 
-/* Builds a leaf layout on the context's device from HOST arrays, validating
- * them: src_leaf_ofs and trg_leaf_ofs (n_leaves+1 int64 each) must start at
- * 0, be non-decreasing and end at n_src / n_trg; ulist_ofs (n_leaves+1) must
- * start at 0, be non-decreasing and end at n_ulist; every ulist entry (int32)
- * must lie in [0, n_leaves).  Leaf L owns sources [src_leaf_ofs[L],
- * src_leaf_ofs[L+1]) and targets [trg_leaf_ofs[L], trg_leaf_ofs[L+1]); its
- * targets sum over the sources of leaves ulist[ulist_ofs[L] .. ulist_ofs[L+1]).
- * A leaf listed twice is summed twice.  The plan owns device memory until
- * stokes_p2p_plan_destroy; it is read-only afterwards. */
+/* For each leaf L and each target x_n of L:
+ *   vel_out(:, n) (=|+=) pref * sum over sources y_m of the leaves in U(L),
+ *   minus the pair rule, of K(x_n - y_m) q_m,
+ * with K the single layer (kernel = STOKES_KERNEL_SL, uses mu, normal may be
+ * NULL) or the double layer (STOKES_KERNEL_DL, needs normal, ignores mu).
+ * Leaf layout (DEVICE arrays, read during the call, caller-owned):
+ * src_leaf_ofs and trg_leaf_ofs (n_leaves+1 int64 each) start at 0, never
+ * decrease and end at n_src / n_trg; ulist_ofs (n_leaves+1 int64) starts at
+ * 0, never decreases and ends at n_ulist; every ulist entry (int32) lies in
+ * [0, n_leaves).  Leaf L owns sources [src_leaf_ofs[L], src_leaf_ofs[L+1])
+ * and targets [trg_leaf_ofs[L], trg_leaf_ofs[L+1]); its targets sum over the
+ * sources of leaves ulist[ulist_ofs[L] .. ulist_ofs[L+1]) (a leaf listed
+ * twice is summed twice).  Point arrays are in leaf order.  The layout is
+ * checked on the device, with no host round trip: if it breaks any rule
+ * above, nothing outside the arrays is read and every component of vel_out
+ * becomes NaN (also when accumulating); the call itself returns STOKES_OK.
+ * The work items (64-target pieces of the leaves, largest first) are built
+ * in the workspace on every call; stokes_workspace_size(STOKES_OP_P2P_*,
+ * n_src, n_trg, n_leaves) sizes it.  Other arguments as stokes_sl_eval. */
+int stokes_p2p_leaf_eval(stokes_ctx* ctx, int32_t kernel, int64_t n_src, const double* src_xyz,
+                         const double* density, const double* weight, const double* normal, int64_t n_trg,
+                         const double* trg_xyz, int32_t n_leaves, const int64_t* src_leaf_ofs,
+                         const int64_t* trg_leaf_ofs, const int64_t* ulist_ofs, const int32_t* ulist,
+                         int64_t n_ulist, double mu, const stokes_exclusion* excl, const stokes_opts* opts,
+                         double* vel_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* The same sum with the layout prepared once from HOST arrays: the plan
+ * validates them on the host (the rules above; a breach returns
+ * STOKES_EINVAL and creates nothing), cuts and sorts the work items once and
+ * owns their device copy until stokes_p2p_plan_destroy; it is read-only
+ * afterwards.  For a layout that is evaluated many times. */
 int stokes_p2p_plan_create(stokes_ctx* ctx, int32_t n_leaves, int64_t n_src, int64_t n_trg,
                            const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs,
                            const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist,
@@ -249,14 +271,9 @@ void stokes_p2p_plan_destroy(stokes_p2p_plan* plan);
  * the pair rule removes any. */
 int stokes_p2p_plan_pairs(const stokes_p2p_plan* plan, int64_t* pairs);
 
-/* For each leaf L and each target x_n of L:
- *   vel_out(:, n) (=|+=) pref * sum over sources y_m of the leaves in U(L),
- *   minus the pair rule, of K(x_n - y_m) q_m,
- * with K the single layer (kernel = STOKES_KERNEL_SL, uses mu, normal may be
- * NULL) or the double layer (STOKES_KERNEL_DL, needs normal, ignores mu).
- * Point arrays are in the plan's leaf order; n_src and n_trg must match the
+/* stokes_p2p_leaf_eval on a plan's layout; n_src and n_trg must match the
  * plan.  Targets of no leaf are not written. */
-int stokes_p2p_leaf_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t kernel,
+int stokes_p2p_plan_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t kernel,
                          int64_t n_src, const double* src_xyz, const double* density,
                          const double* weight, const double* normal, int64_t n_trg,
                          const double* trg_xyz, double mu, const stokes_exclusion* excl,

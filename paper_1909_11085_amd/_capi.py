@@ -79,8 +79,10 @@ _SIGNATURES = {
                                               ctypes.POINTER(_vp)]),
     "stokes_p2p_plan_destroy": (None, [_vp]),
     "stokes_p2p_plan_pairs": (ctypes.c_int, [_vp, ctypes.POINTER(_i64)]),
-    "stokes_p2p_leaf_eval": (ctypes.c_int, [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp,
+    "stokes_p2p_plan_eval": (ctypes.c_int, [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp,
                                             _dbl, _EX, _OP, _vp, _vp, _sz, _vp]),
+    "stokes_p2p_leaf_eval": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp,
+                                            _vp, _vp, _i64, _dbl, _EX, _OP, _vp, _vp, _sz, _vp]),
     "stokes_sl_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _i64, _vp, _dbl, _EX, _OP, _vp,
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
     "stokes_dl_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _EX, _OP, _vp,

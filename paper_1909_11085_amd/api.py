@@ -359,10 +359,16 @@ class P2PPlan:
             self._h = None
 
 
-def p2p_leaf(plan, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=None, trg_group=None,
+def p2p_leaf(layout, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=None, trg_group=None,
              exclude_same_group=None, precision="fp64", group_h=None, near_frac=0.5, out=None,
              accumulate=False):
-    """Leaf-to-leaf sum over the plan's interaction lists; see stokes_p2p_leaf_eval."""
+    """Leaf-to-leaf sum over interaction lists.
+
+    layout: a P2PPlan (host arrays, prepared once; stokes_p2p_plan_eval), or
+    the device arrays (src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist) as int64,
+    int64, int64 and int32 tensors on the points' device, checked and cut into
+    work items on the device at every call (stokes_p2p_leaf_eval; a malformed
+    layout gives NaN outputs)."""
     device = src.device
     _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
     ns, nt = src.shape[1], trg.shape[1]
@@ -374,11 +380,25 @@ def p2p_leaf(plan, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=None
     rule.opts.accumulate = int(bool(accumulate))
     out = _out(out, nt, device, accumulate)
     op = C.OP_P2P_SL if k == C.KERNEL_SL else C.OP_P2P_DL
-    ws, size = _workspace(op, ns, nt, plan.n_leaves, rule.opts, device)
-    C.check(C.lib().stokes_p2p_leaf_eval(context(device), plan.handle, k, ns, _ptr(src), _ptr(f), _ptr(w),
-                                         _ptr(nrm) if k == C.KERNEL_DL else ctypes.c_void_p(0), nt,
-                                         _ptr(trg), float(mu), ctypes.byref(rule.ex),
-                                         ctypes.byref(rule.opts), _ptr(out), _ptr(ws), size,
+    nrm_p = _ptr(nrm) if k == C.KERNEL_DL else ctypes.c_void_p(0)
+    if isinstance(layout, P2PPlan):
+        ws, size = _workspace(op, ns, nt, layout.n_leaves, rule.opts, device)
+        C.check(C.lib().stokes_p2p_plan_eval(context(device), layout.handle, k, ns, _ptr(src), _ptr(f), _ptr(w),
+                                             nrm_p, nt, _ptr(trg), float(mu), ctypes.byref(rule.ex),
+                                             ctypes.byref(rule.opts), _ptr(out), _ptr(ws), size, _stream(device)))
+        return out
+    so, to, uo, ul = layout
+    for t, name, dt in ((so, "src_leaf_ofs", torch.int64), (to, "trg_leaf_ofs", torch.int64),
+                        (uo, "ulist_ofs", torch.int64), (ul, "ulist", torch.int32)):
+        if t.dtype != dt or t.dim() != 1 or t.device != device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous 1-D {dt} tensor on the points' device")
+    n_leaves = so.numel() - 1
+    if n_leaves < 0 or to.numel() != n_leaves + 1 or uo.numel() != n_leaves + 1:
+        raise ValueError("the leaf offset arrays must all have n_leaves + 1 entries")
+    ws, size = _workspace(op, ns, nt, n_leaves, rule.opts, device)
+    C.check(C.lib().stokes_p2p_leaf_eval(context(device), k, ns, _ptr(src), _ptr(f), _ptr(w), nrm_p, nt, _ptr(trg),
+                                         n_leaves, _ptr(so), _ptr(to), _ptr(uo), _ptr(ul), ul.numel(), float(mu),
+                                         ctypes.byref(rule.ex), ctypes.byref(rule.opts), _ptr(out), _ptr(ws), size,
                                          _stream(device)))
     return out
 

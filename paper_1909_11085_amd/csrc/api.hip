@@ -724,7 +724,7 @@ int stokes_p2p_plan_pairs(const stokes_p2p_plan* plan, int64_t* pairs) {
     return STOKES_OK;
 }
 
-int stokes_p2p_leaf_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t kernel,
+int stokes_p2p_plan_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t kernel,
                          int64_t n_src, const double* src_xyz, const double* density,
                          const double* weight, const double* normal, int64_t n_trg,
                          const double* trg_xyz, double mu, const stokes_exclusion* excl,
@@ -763,13 +763,66 @@ int stokes_p2p_leaf_eval(stokes_ctx* ctx, const stokes_p2p_plan* plan, int32_t k
     if (n_trg == 0) return STOKES_OK;
     if (n_src == 0)
         return p.accumulate ? STOKES_OK
-                            : launch_status(stokes::launch_fill_zero(vel_out, 3 * n_trg, st), "stokes_p2p_leaf_eval");
+                            : launch_status(stokes::launch_fill_zero(vel_out, 3 * n_trg, st), "stokes_p2p_plan_eval");
     const double pref = kernel == STOKES_KERNEL_SL ? 1.0 / (8.0 * kPi * mu) : 6.0 / (8.0 * kPi);
     stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal, n_trg,
                                        trg_xyz, pref);
     in.pair_class = pair_class;
     return launch_status(stokes::launch_p2p(in, plan, vel_out, p.accumulate, workspace, st,
                                             stokes::next_timer(ctx)),
+                         "stokes_p2p_plan_eval");
+}
+
+int stokes_p2p_leaf_eval(stokes_ctx* ctx, int32_t kernel, int64_t n_src, const double* src_xyz,
+                         const double* density, const double* weight, const double* normal, int64_t n_trg,
+                         const double* trg_xyz, int32_t n_leaves, const int64_t* src_leaf_ofs,
+                         const int64_t* trg_leaf_ofs, const int64_t* ulist_ofs, const int32_t* ulist,
+                         int64_t n_ulist, double mu, const stokes_exclusion* excl, const stokes_opts* opts,
+                         double* vel_out, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (kernel != STOKES_KERNEL_SL && kernel != STOKES_KERNEL_DL)
+        return fail(STOKES_EINVAL, "kernel must be STOKES_KERNEL_SL or STOKES_KERNEL_DL");
+    if (kernel == STOKES_KERNEL_SL && !(isfinite(mu) && mu > 0.0))
+        return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
+    if (n_ulist < 0 || n_ulist > INT32_MAX) return fail(STOKES_EINVAL, "n_ulist must be in [0, 2^31)");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    if (n_src > INT32_MAX) return fail(STOKES_EUNSUPPORTED, "n_src must be below 2^31 for leaf sums");
+    rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz);
+    if (rc) return rc;
+    if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
+    if (!arr_ok(src_leaf_ofs, (int64_t)n_leaves + 1, 8) || !arr_ok(trg_leaf_ofs, (int64_t)n_leaves + 1, 8) ||
+        !arr_ok(ulist_ofs, (int64_t)n_leaves + 1, 8))
+        return fail(STOKES_EINVAL, "src_leaf_ofs, trg_leaf_ofs and ulist_ofs must be non-NULL and 8-byte aligned");
+    if (!arr_ok(ulist, n_ulist, 4)) return fail(STOKES_EINVAL, "ulist must be non-NULL and 4-byte aligned");
+    Parsed p;
+    rc = parse_common(excl, opts, n_src, n_trg, p);
+    if (rc) return rc;
+    const size_t vb = (size_t)3 * n_trg * sizeof(double), sb = (size_t)3 * n_src * sizeof(double);
+    const size_t ob = (size_t)(n_leaves + 1) * sizeof(int64_t);
+    rc = check_no_alias(vel_out, vb, "vel_out",
+                        {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {normal, kernel ? sb : 0},
+                         {trg_xyz, vb}, {workspace, ws_bytes}, {src_leaf_ofs, ob}, {trg_leaf_ofs, ob},
+                         {ulist_ofs, ob}, {ulist, (size_t)n_ulist * 4}});
+    if (rc) return rc;
+    const int mixed = p.precision == STOKES_MIXED;
+    rc = check_workspace(workspace, ws_bytes, stokes::p2p_workspace_bytes(kernel, mixed, n_src, n_trg, n_leaves));
+    if (rc) return rc;
+    int32_t* pair_class = nullptr;
+    if ((rc = pair_class_for(ctx, mixed, n_src, n_trg, &pair_class))) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n_trg == 0) return STOKES_OK;
+    if (n_src == 0)
+        return p.accumulate ? STOKES_OK
+                            : launch_status(stokes::launch_fill_zero(vel_out, 3 * n_trg, st), "stokes_p2p_leaf_eval");
+    const double pref = kernel == STOKES_KERNEL_SL ? 1.0 / (8.0 * kPi * mu) : 6.0 / (8.0 * kPi);
+    stokes::SumInputs in = make_inputs(kernel, p, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz, pref);
+    in.pair_class = pair_class;
+    return launch_status(stokes::launch_p2p_csr(in, n_leaves, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, n_ulist,
+                                                vel_out, p.accumulate, workspace, st, stokes::next_timer(ctx)),
                          "stokes_p2p_leaf_eval");
 }
 

@@ -4,9 +4,12 @@
 // interaction list, in one launch over all the (uneven) lists.
 //
 // Design (gfx950):
-//   * plan (host, once per leaf layout): validates the leaf CSR arrays, cuts
-//     each target leaf into 64-target work items, sorts the items by their
-//     estimated cost (largest first, for balance) and uploads layout and items.
+//   * work items: each target leaf cut into 64-target items, sorted by their
+//     estimated cost (largest first, for balance).  Two ways in: a plan built
+//     once from host arrays (validated and sorted on the host), or device
+//     arrays per call, validated and turned into sorted items on the device
+//     (a count, a prefix sum, cost keys, a radix sort), with no host round
+//     trip; both give the same order.
 //   * prep (one wave per leaf, per evaluation): the leaf's box centre and
 //     radius, then a packed record per source; mixed precision stores each
 //     source's offset from its leaf centre as a float32 high part and residue.
@@ -35,6 +38,7 @@
 
 #include "../../include/stokes_mi355x.h"
 #include "p2p.hpp"
+#include "spatial.hpp"
 
 struct stokes_p2p_plan {
     int device;
@@ -76,6 +80,8 @@ struct P2PArgs {
     const int64_t* ulist_ofs;
     const int32_t* ulist;
     const int32_t* items;
+    const int64_t* n_items;  // device count of items (device-built layouts), else null: one per workgroup
+    const int32_t* status;   // device-built layouts: nonzero when the leaf arrays are malformed, else null
     void* rec;
     int32_t* grp;
     double* leaf_ctr;        // (n_leaves, 4): box centre and half-diagonal
@@ -99,6 +105,7 @@ __device__ __forceinline__ double wmax(double v) {
 template <int KT, int MIXED>
 __global__ __launch_bounds__(kWave) void p2p_prep(P2PArgs a) {
     using Rec = typename P2PRec<KT, MIXED>::type;
+    if (a.status && *a.status) return;
     const int32_t L = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t s0 = a.src_ofs[L], s1 = a.src_ofs[L + 1];
@@ -263,6 +270,8 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     // length
     __shared__ Rec s_rec[kSlots];
     __shared__ int32_t s_grp[MIXED ? 1 : kSlots];
+    if (a.status && *a.status) return;
+    if (a.n_items && (int64_t)blockIdx.x >= *a.n_items) return;   // the grid covers the upper bound
     const int lane = threadIdx.x;
     const int32_t L = a.items[2 * blockIdx.x], ch = a.items[2 * blockIdx.x + 1];
     const int64_t t0 = a.trg_ofs[L] + (int64_t)ch * kWave;
@@ -519,10 +528,21 @@ size_t rec_size(int kernel, int mixed) {
 }
 
 struct P2PLayout {
-    size_t off_rec, off_grp, off_ctr, total;
+    size_t off_rec, off_grp, off_ctr;
+    // device-built items (per-call leaf arrays)
+    int64_t max_items;
+    SortLayout sort;
+    size_t off_status, off_cnt, off_listed, off_scan, off_nitems, off_items, off_keys, off_vals, off_sorted,
+        off_sort, total;
 };
 
-P2PLayout p2p_layout(int kernel, int mixed, int64_t n_src, int32_t n_leaves) {
+// Upper bound of the work items: every leaf adds at most one partial chunk to
+// the full ones.
+int64_t max_p2p_items(int64_t n_trg, int32_t n_leaves) {
+    return (n_trg + kWave - 1) / kWave + std::min<int64_t>(n_trg, n_leaves);
+}
+
+P2PLayout p2p_layout(int kernel, int mixed, int64_t n_src, int64_t n_trg, int32_t n_leaves) {
     P2PLayout l{};
     size_t off = 0;
     l.off_rec = off;
@@ -531,61 +551,270 @@ P2PLayout p2p_layout(int kernel, int mixed, int64_t n_src, int32_t n_leaves) {
     off = align_up(off + (size_t)std::max<int64_t>(n_src, 1) * sizeof(int32_t), 256);
     l.off_ctr = off;
     off = align_up(off + (size_t)std::max(n_leaves, 1) * 4 * sizeof(double), 256);
+    const int64_t nl = std::max(n_leaves, 1);
+    l.max_items = std::max<int64_t>(max_p2p_items(n_trg, n_leaves), 1);
+    l.sort = sort_layout(l.max_items);
+    l.off_status = off;
+    off = align_up(off + sizeof(int32_t), 256);
+    l.off_cnt = off;
+    off = align_up(off + (size_t)(nl + 1) * sizeof(int64_t), 256);
+    l.off_listed = off;
+    off = align_up(off + (size_t)nl * sizeof(int64_t), 256);
+    l.off_scan = off;
+    off = align_up(off + (size_t)scan_tmp_count(nl) * sizeof(int64_t), 256);
+    l.off_nitems = off;
+    off = align_up(off + sizeof(int64_t), 256);
+    l.off_items = off;
+    off = align_up(off + (size_t)l.max_items * 2 * sizeof(int32_t), 256);
+    l.off_keys = off;
+    off = align_up(off + (size_t)l.max_items * sizeof(uint64_t), 256);
+    l.off_vals = off;
+    off = align_up(off + (size_t)l.max_items * sizeof(int32_t), 256);
+    l.off_sorted = off;
+    off = align_up(off + (size_t)l.max_items * 2 * sizeof(int32_t), 256);
+    l.off_sort = off;
+    off = align_up(off + l.sort.total, 256);
     l.total = off;
     return l;
 }
 
+// What the sum kernels take from a leaf layout: its device arrays and items.
+struct P2PItems {
+    const int64_t *src_ofs, *trg_ofs, *ulist_ofs;
+    const int32_t* ulist;
+    const int32_t* items;
+    const int64_t* n_items;   // device count, or null (then grid == the item count)
+    const int32_t* status;    // or null
+    int32_t n_leaves;
+    int64_t grid;             // workgroups of the sum
+};
+
 template <int KT, int MIXED>
-hipError_t run_p2p(P2PArgs a, const stokes_p2p_plan* plan, void* ws, hipStream_t stream,
-                   const KernelTimer& timer) {
-    const P2PLayout l = p2p_layout(KT, MIXED, a.in.n_src, plan->n_leaves);
+hipError_t run_p2p(P2PArgs a, const P2PItems& it, void* ws, hipStream_t stream, const KernelTimer& timer) {
+    const P2PLayout l = p2p_layout(KT, MIXED, a.in.n_src, a.in.n_trg, it.n_leaves);
     char* base = static_cast<char*>(ws);
+    a.src_ofs = it.src_ofs;
+    a.trg_ofs = it.trg_ofs;
+    a.ulist_ofs = it.ulist_ofs;
+    a.ulist = it.ulist;
+    a.items = it.items;
+    a.n_items = it.n_items;
+    a.status = it.status;
+    a.n_leaves = it.n_leaves;
     a.rec = base + l.off_rec;
     a.grp = reinterpret_cast<int32_t*>(base + l.off_grp);
     a.leaf_ctr = reinterpret_cast<double*>(base + l.off_ctr);
-    if (plan->n_leaves > 0) {
-        p2p_prep<KT, MIXED><<<dim3((unsigned)plan->n_leaves), dim3(kWave), 0, stream>>>(a);
+    if (it.n_leaves > 0) {
+        p2p_prep<KT, MIXED><<<dim3((unsigned)it.n_leaves), dim3(kWave), 0, stream>>>(a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (plan->n_items == 0) return hipSuccess;
+    if (it.grid == 0) return hipSuccess;
     if (timer.on()) (void)hipEventRecord(timer.start, stream);
     if constexpr (MIXED != 0) {
         if (a.in.pair_class)
-            p2p_sum<KT, MIXED, true><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+            p2p_sum<KT, MIXED, true><<<dim3((unsigned)it.grid), dim3(kWave), 0, stream>>>(a);
         else
-            p2p_sum<KT, MIXED><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+            p2p_sum<KT, MIXED><<<dim3((unsigned)it.grid), dim3(kWave), 0, stream>>>(a);
     } else {
-        p2p_sum<KT, MIXED><<<dim3((unsigned)plan->n_items), dim3(kWave), 0, stream>>>(a);
+        p2p_sum<KT, MIXED><<<dim3((unsigned)it.grid), dim3(kWave), 0, stream>>>(a);
     }
     hipError_t e = hipGetLastError();
     if (timer.on()) (void)hipEventRecord(timer.stop, stream);
     return e;
 }
 
+template <int KT, int MIXED>
+hipError_t run_p2p_typed(const SumInputs& in, const P2PItems& it, double* out, int accumulate, void* ws,
+                         hipStream_t stream, const KernelTimer& timer) {
+    P2PArgs a{};
+    a.in = in;
+    a.out = out;
+    a.accumulate = accumulate;
+    return run_p2p<KT, MIXED>(a, it, ws, stream, timer);
+}
+
+hipError_t run_p2p_any(const SumInputs& in, const P2PItems& it, double* out, int accumulate, void* ws,
+                       hipStream_t stream, const KernelTimer& timer) {
+    if (in.kernel == 0)
+        return in.mixed ? run_p2p_typed<0, 1>(in, it, out, accumulate, ws, stream, timer)
+                        : run_p2p_typed<0, 0>(in, it, out, accumulate, ws, stream, timer);
+    return in.mixed ? run_p2p_typed<1, 1>(in, it, out, accumulate, ws, stream, timer)
+                    : run_p2p_typed<1, 0>(in, it, out, accumulate, ws, stream, timer);
+}
+
+// ---------------------------------------------------------------------------
+// work items from device leaf arrays
+// ---------------------------------------------------------------------------
+constexpr int kP2PThreads = 256;
+constexpr int kItemKeyBits = 40;
+constexpr uint64_t kItemKeyTop = (1ull << kItemKeyBits) - 1;
+
+__global__ __launch_bounds__(kP2PThreads) void p2p_set_i32(int32_t* p, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// The leaf arrays' contract: each offset array starts at 0, never decreases
+// and ends at its total; every list entry names a leaf.  Any breach sets
+// *status.
+__global__ __launch_bounds__(kP2PThreads) void p2p_csr_check(const int64_t* __restrict__ so,
+                                                             const int64_t* __restrict__ to,
+                                                             const int64_t* __restrict__ uo,
+                                                             const int32_t* __restrict__ ul, int32_t nl,
+                                                             int64_t ns, int64_t nt, int64_t nu,
+                                                             int32_t* __restrict__ status) {
+    const int64_t n = std::max<int64_t>((int64_t)nl + 1, nu);
+    for (int64_t i = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kP2PThreads) {
+        bool bad = false;
+        if (i <= nl) {
+            const int64_t* o[3] = {so, to, uo};
+            const int64_t tot[3] = {ns, nt, nu};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (i == 0 && o[q][0] != 0) bad = true;
+                if (i == nl && o[q][nl] != tot[q]) bad = true;
+                if (i < nl && o[q][i + 1] < o[q][i]) bad = true;
+            }
+        }
+        if (i < nu && (ul[i] < 0 || ul[i] >= nl)) bad = true;
+        if (bad) atomicOr(status, 1);
+    }
+}
+
+// Per leaf: its 64-target chunks and the sources its list holds (0 chunks
+// when the arrays are malformed).
+__global__ __launch_bounds__(kP2PThreads) void p2p_csr_count(const int64_t* __restrict__ so,
+                                                             const int64_t* __restrict__ to,
+                                                             const int64_t* __restrict__ uo,
+                                                             const int32_t* __restrict__ ul, int32_t nl,
+                                                             const int32_t* __restrict__ status,
+                                                             int64_t* __restrict__ cnt, int64_t* __restrict__ listed) {
+    const bool ok = *status == 0;
+    for (int64_t L = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; L < nl; L += (int64_t)gridDim.x * kP2PThreads) {
+        int64_t c = 0, s = 0;
+        if (ok) {
+            c = (to[L + 1] - to[L] + kWave - 1) / kWave;
+            for (int64_t k = uo[L]; k < uo[L + 1]; ++k) s += so[ul[k] + 1] - so[ul[k]];
+        }
+        cnt[L] = c;
+        listed[L] = s;
+    }
+}
+
+// Every slot gets the top key (unused slots sort last) and its own index.
+__global__ __launch_bounds__(kP2PThreads) void p2p_item_slots(int64_t max_items, uint64_t* __restrict__ keys,
+                                                              int32_t* __restrict__ vals) {
+    for (int64_t k = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; k < max_items;
+         k += (int64_t)gridDim.x * kP2PThreads) {
+        keys[k] = kItemKeyTop;
+        vals[k] = (int32_t)k;
+    }
+}
+
+// The items of each leaf, in leaf and chunk order, with their cost keys: the
+// pair loop of an n-target item runs s/R steps over the s listed sources,
+// R = min(16, 64/n); the key is inverted so that an ascending stable sort puts
+// the largest first (the order of the host-built plan).
+__global__ __launch_bounds__(kP2PThreads) void p2p_csr_items(const int64_t* __restrict__ to,
+                                                             const int64_t* __restrict__ cofs,
+                                                             const int64_t* __restrict__ listed, int32_t nl,
+                                                             int64_t max_items, int32_t* __restrict__ items,
+                                                             uint64_t* __restrict__ keys) {
+    for (int64_t L = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; L < nl; L += (int64_t)gridDim.x * kP2PThreads) {
+        const int64_t nt = to[L + 1] - to[L], s = listed[L];
+        for (int64_t c = 0; c * kWave < nt; ++c) {
+            const int64_t k = cofs[L] + c;
+            if (k >= max_items) break;
+            const int64_t n_c = std::min<int64_t>(kWave, nt - c * kWave);
+            const int64_t rep = std::min<int64_t>(kMaxRep, kWave / n_c);
+            const uint64_t cost = (uint64_t)(s * 64 / rep + s + 1);
+            items[2 * k] = (int32_t)L;
+            items[2 * k + 1] = (int32_t)c;
+            keys[k] = kItemKeyTop - 1 - std::min<uint64_t>(cost, kItemKeyTop - 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kP2PThreads) void p2p_item_order(const int32_t* __restrict__ items,
+                                                              const int32_t* __restrict__ order,
+                                                              const int64_t* __restrict__ n_items,
+                                                              int32_t* __restrict__ sorted) {
+    const int64_t count = *n_items;
+    for (int64_t k = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; k < count; k += (int64_t)gridDim.x * kP2PThreads) {
+        sorted[2 * k] = items[2 * order[k]];
+        sorted[2 * k + 1] = items[2 * order[k] + 1];
+    }
+}
+
+// Malformed leaf arrays: every output component becomes NaN.
+__global__ __launch_bounds__(kP2PThreads) void p2p_poison(const int32_t* __restrict__ status, double* __restrict__ out,
+                                                          int64_t n) {
+    if (*status == 0) return;
+    for (int64_t i = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kP2PThreads)
+        out[i] = __builtin_nan("");
+}
+
+unsigned p2p_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kP2PThreads - 1) / kP2PThreads, 4096));
+}
+
 }  // namespace
 
 size_t p2p_workspace_bytes(int kernel, int mixed, int64_t n_src, int64_t n_trg, int32_t n_leaves) {
-    (void)n_trg;
-    if (n_src <= 0) return 0;
-    return p2p_layout(kernel, mixed, n_src, n_leaves).total;
+    if (n_src <= 0 || n_trg <= 0) return 0;
+    return p2p_layout(kernel, mixed, n_src, n_trg, n_leaves).total;
 }
 
 hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* out, int accumulate,
                       void* ws, hipStream_t stream, const KernelTimer& timer) {
-    P2PArgs a{};
-    a.in = in;
-    a.src_ofs = plan->d_src_ofs;
-    a.trg_ofs = plan->d_trg_ofs;
-    a.ulist_ofs = plan->d_ulist_ofs;
-    a.ulist = plan->d_ulist;
-    a.items = plan->d_items;
-    a.n_leaves = plan->n_leaves;
-    a.out = out;
-    a.accumulate = accumulate;
-    if (in.kernel == 0)
-        return in.mixed ? run_p2p<0, 1>(a, plan, ws, stream, timer) : run_p2p<0, 0>(a, plan, ws, stream, timer);
-    return in.mixed ? run_p2p<1, 1>(a, plan, ws, stream, timer) : run_p2p<1, 0>(a, plan, ws, stream, timer);
+    const P2PItems it{plan->d_src_ofs, plan->d_trg_ofs, plan->d_ulist_ofs, plan->d_ulist, plan->d_items,
+                      nullptr, nullptr, plan->n_leaves, plan->n_items};
+    return run_p2p_any(in, it, out, accumulate, ws, stream, timer);
+}
+
+hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                          const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, double* out,
+                          int accumulate, void* ws, hipStream_t st, const KernelTimer& timer) {
+    const P2PLayout l = p2p_layout(in.kernel, in.mixed, in.n_src, in.n_trg, n_leaves);
+    char* base = static_cast<char*>(ws);
+    int32_t* status = reinterpret_cast<int32_t*>(base + l.off_status);
+    int64_t* cnt = reinterpret_cast<int64_t*>(base + l.off_cnt);
+    int64_t* listed = reinterpret_cast<int64_t*>(base + l.off_listed);
+    int64_t* n_items = reinterpret_cast<int64_t*>(base + l.off_nitems);
+    int32_t* items = reinterpret_cast<int32_t*>(base + l.off_items);
+    uint64_t* keys = reinterpret_cast<uint64_t*>(base + l.off_keys);
+    int32_t* vals = reinterpret_cast<int32_t*>(base + l.off_vals);
+    int32_t* sorted = reinterpret_cast<int32_t*>(base + l.off_sorted);
+    hipError_t e;
+    auto chk = [&]() { return (e = hipGetLastError()) == hipSuccess; };
+    p2p_set_i32<<<1, kP2PThreads, 0, st>>>(status, 0);
+    if (!chk()) return e;
+    p2p_csr_check<<<p2p_grid(std::max<int64_t>((int64_t)n_leaves + 1, n_ulist)), kP2PThreads, 0, st>>>(
+        src_ofs, trg_ofs, ulist_ofs, ulist, n_leaves, in.n_src, in.n_trg, n_ulist, status);
+    if (!chk()) return e;
+    if (n_leaves > 0) {
+        p2p_csr_count<<<p2p_grid(n_leaves), kP2PThreads, 0, st>>>(src_ofs, trg_ofs, ulist_ofs, ulist, n_leaves,
+                                                                  status, cnt, listed);
+        if (!chk()) return e;
+        if ((e = exclusive_scan_i64(cnt, n_leaves, cnt, reinterpret_cast<int64_t*>(base + l.off_scan), n_items,
+                                    st)) != hipSuccess)
+            return e;
+        p2p_item_slots<<<p2p_grid(l.max_items), kP2PThreads, 0, st>>>(l.max_items, keys, vals);
+        if (!chk()) return e;
+        p2p_csr_items<<<p2p_grid(n_leaves), kP2PThreads, 0, st>>>(trg_ofs, cnt, listed, n_leaves, l.max_items,
+                                                                  items, keys);
+        if (!chk()) return e;
+        if ((e = radix_sort_pairs(keys, vals, l.max_items, kItemKeyBits, base + l.off_sort, l.sort, st)) !=
+            hipSuccess)
+            return e;
+        p2p_item_order<<<p2p_grid(l.max_items), kP2PThreads, 0, st>>>(items, vals, n_items, sorted);
+        if (!chk()) return e;
+        const P2PItems it{src_ofs, trg_ofs, ulist_ofs, ulist, sorted, n_items, status, n_leaves, l.max_items};
+        if ((e = run_p2p_any(in, it, out, accumulate, ws, st, timer)) != hipSuccess) return e;
+    }
+    p2p_poison<<<p2p_grid(3 * in.n_trg), kP2PThreads, 0, st>>>(status, out, 3 * in.n_trg);
+    chk();
+    return e;
 }
 
 // ---------------------------------------------------------------------------

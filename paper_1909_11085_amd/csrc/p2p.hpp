@@ -21,4 +21,10 @@ int64_t p2p_plan_info(const stokes_p2p_plan* p, int which);
 hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* out, int accumulate,
                       void* ws, hipStream_t stream, const KernelTimer& timer);
 
+// The same sum from device leaf arrays, checked and cut into sorted work items
+// on the device; malformed arrays make every output component NaN.
+hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                          const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, double* out,
+                          int accumulate, void* ws, hipStream_t stream, const KernelTimer& timer);
+
 }  // namespace stokes

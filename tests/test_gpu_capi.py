@@ -124,7 +124,7 @@ def test_p2p_rejections(ctx):
         ws, need = _ws(ctx, C.OP_P2P_SL, n_leaves=2)
 
         def run(kernel=C.KERNEL_SL, ns=NS, normal=None, ws_bytes=need):
-            return L.stokes_p2p_leaf_eval(ctx, plan, kernel, ns, _p(d["y"]), _p(d["f"]), _p(d["w"]), normal,
+            return L.stokes_p2p_plan_eval(ctx, plan, kernel, ns, _p(d["y"]), _p(d["f"]), _p(d["w"]), normal,
                                           NT, _p(d["x"]), 1.0, None, None, _p(d["out"]), _p(ws), ws_bytes,
                                           None)
 
@@ -137,6 +137,58 @@ def test_p2p_rejections(ctx):
         assert not bool((d["out"] == SENTINEL).any())
     finally:
         L.stokes_p2p_plan_destroy(plan)
+
+
+def test_p2p_device_layout(ctx):
+    """stokes_p2p_leaf_eval with device leaf arrays: host-side rejections
+    launch nothing; a valid layout gives the plan path's result bit for bit;
+    a malformed one (checked on the device) turns every output into NaN."""
+    d = _data()
+    L = C.lib()
+    so = np.array([0, 150, NS], dtype=np.int64)
+    to = np.array([0, 120, NT], dtype=np.int64)
+    uo = np.array([0, 2, 3], dtype=np.int64)
+    ul = np.array([0, 1, 1], dtype=np.int32)
+    dso, dto, duo, dul = dev(so), dev(to), dev(uo), dev(ul)
+    ws, need = _ws(ctx, C.OP_P2P_SL, n_leaves=2)
+
+    def run(kernel=C.KERNEL_SL, n_leaves=2, ulp=None, n_ul=3, normal=None, ws_bytes=need, out=None, so_=None,
+            to_=None, ul_=None):
+        return L.stokes_p2p_leaf_eval(ctx, kernel, NS, _p(d["y"]), _p(d["f"]), _p(d["w"]), normal, NT, _p(d["x"]),
+                                      n_leaves, _p(so_ if so_ is not None else dso),
+                                      _p(to_ if to_ is not None else dto), _p(duo),
+                                      ulp if ulp is not None else _p(ul_ if ul_ is not None else dul), n_ul, 1.0,
+                                      None, None, _p(out if out is not None else d["out"]), _p(ws), ws_bytes, None)
+
+    _rejected(run(kernel=4), C.EINVAL, "kernel", d)
+    _rejected(run(n_leaves=-1), C.EINVAL, "n_leaves", d)
+    _rejected(run(ulp=ctypes.c_void_p(0)), C.EINVAL, "ulist", d)
+    _rejected(run(n_ul=-2), C.EINVAL, "n_ulist", d)
+    _rejected(run(kernel=C.KERNEL_DL), C.EINVAL, "normal", d)
+    _rejected(run(ws_bytes=need - 1), C.EWORKSPACE, "too small", d)
+    assert run() == C.OK, L.stokes_last_error()
+
+    plan = ctypes.c_void_p()
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert L.stokes_p2p_plan_create(ctx, 2, NS, NT, ptr(so), ptr(to), ptr(uo), ptr(ul), 3,
+                                    ctypes.byref(plan)) == C.OK
+    try:
+        ref = torch.zeros_like(d["out"])
+        assert L.stokes_p2p_plan_eval(ctx, plan, C.KERNEL_SL, NS, _p(d["y"]), _p(d["f"]), _p(d["w"]), None, NT,
+                                      _p(d["x"]), 1.0, None, None, _p(ref), _p(ws), need, None) == C.OK
+    finally:
+        L.stokes_p2p_plan_destroy(plan)
+    torch.cuda.synchronize()
+    assert torch.equal(d["out"], ref)
+
+    # malformed layouts: the call returns OK, every output component is NaN
+    for what, kw in (("list entry out of range", dict(ul_=dev(np.array([0, 2, 1], dtype=np.int32)))),
+                     ("decreasing sources", dict(so_=dev(np.array([0, NS, 150], dtype=np.int64)))),
+                     ("targets not ending at n_trg", dict(to_=dev(np.array([0, 120, NT - 1], dtype=np.int64))))):
+        out = torch.zeros_like(d["out"])
+        assert run(out=out, **kw) == C.OK, what
+        torch.cuda.synchronize()
+        assert bool(torch.isnan(out).all()), what
 
 
 def test_vjp_rejections(ctx):

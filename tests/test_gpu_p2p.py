@@ -46,6 +46,31 @@ def test_p2p_random_lists(kernel, precision):
     assert_close(got, ref, TOL[precision], f"p2p {kernel}/{precision}")
 
 
+def _device_layout(tree, ofs, ul):
+    return (dev(tree.leaf_ofs.astype(np.int64)), dev(tree.leaf_ofs.astype(np.int64)), dev(ofs.astype(np.int64)),
+            dev(ul.astype(np.int32)))
+
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_device_layout_matches_plan(kernel, precision):
+    """Leaf arrays passed on the device per call (items built, checked and
+    sorted on the device) give the host plan's result bit for bit, and the
+    oracle's within the tolerance."""
+    print(f"case p2p device layout {kernel} {precision}", flush=True)
+    rng, tree, d = _tree(13)
+    ofs, ul = W.nearest_leaf_lists(rng, tree, kmin=3, kmax=12)
+    n = d["pos"].shape[1]
+    plan = S.P2PPlan(tree.leaf_ofs, tree.leaf_ofs, ofs, ul, n, n)
+    a = _run(plan, d, kernel, precision, mu=0.7)
+    b = _run(_device_layout(tree, ofs, ul), d, kernel, precision, mu=0.7)
+    assert torch.equal(a, b)
+    ref = O.p2p(0 if kernel == "sl" else 1, d["pos"], d["f"], d["w"], d["pos"], tree.leaf_ofs,
+                tree.leaf_ofs, ofs, ul, nrm=d["n"], mu=0.7, src_group=d["g"], trg_group=d["g"],
+                exclude_same_group=True)
+    assert_close(host(b), ref, TOL[precision], f"p2p device layout {kernel}/{precision}")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_p2p_full_lists_equal_direct(precision):
     """Every leaf listing every leaf reproduces the direct sum."""
@@ -80,6 +105,34 @@ def test_p2p_uneven_layout_edge_cases():
     S.p2p_leaf(plan, dev(y), dev(f), dev(w), dev(x), out=out, accumulate=True)
     ref = O.p2p(0, y, f, w, x, so, to, uo, ul)
     assert_close(host(out) - base, ref, FP64_TOL, "uneven layout")
+    # the same layout as device arrays, per call
+    out2 = dev(base.copy())
+    S.p2p_leaf((dev(so), dev(to), dev(uo), dev(ul)), dev(y), dev(f), dev(w), dev(x), out=out2, accumulate=True)
+    assert torch.equal(out, out2)
+
+
+def test_device_layout_malformed_gives_nan():
+    """The device checks of the leaf arrays (the plan's host checks, run on
+    the device): each breach makes every output component NaN, with nothing
+    read out of range."""
+    rng = np.random.default_rng(14)
+    y, x = dev(rng.standard_normal((3, 10))), dev(rng.standard_normal((3, 8)))
+    f, w = dev(rng.standard_normal((3, 10))), dev(rng.uniform(0.5, 1, 10))
+    ok = dict(so=np.array([0, 5, 10]), to=np.array([0, 4, 8]), uo=np.array([0, 1, 2]), ul=np.array([0, 1]))
+    bad = [
+        dict(ok, so=np.array([1, 5, 10])),            # does not start at 0
+        dict(ok, to=np.array([0, 6, 4])),             # decreasing
+        dict(ok, so=np.array([0, 5, 9])),             # does not end at n_src
+        dict(ok, uo=np.array([0, 1, 3])),             # does not end at n_ulist
+        dict(ok, ul=np.array([0, 2])),                # leaf id out of range
+        dict(ok, ul=np.array([-1, 1])),
+    ]
+    lay = lambda b: (dev(b["so"].astype(np.int64)), dev(b["to"].astype(np.int64)), dev(b["uo"].astype(np.int64)),
+                     dev(b["ul"].astype(np.int32)))
+    good = host(S.p2p_leaf(lay(ok), y, f, w, x))
+    assert np.all(np.isfinite(good))
+    for b in bad:
+        assert np.all(np.isnan(host(S.p2p_leaf(lay(b), y, f, w, x, accumulate=True, out=dev(np.zeros((3, 8)))))))
 
 
 def test_p2p_plan_rejects_malformed_layouts():
