@@ -523,8 +523,8 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
 }
 
 size_t rec_size(int kernel, int mixed) {
-    if (!mixed) return kernel == 0 ? sizeof(SrcSL64) : sizeof(SrcDL64);
-    return kernel == 0 ? sizeof(P2PSL32) : sizeof(P2PDL32);
+    if (!mixed) return kernel == 0 ? sizeof(P2PRec<0, 0>::type) : sizeof(P2PRec<1, 0>::type);
+    return kernel == 0 ? sizeof(P2PRec<0, 1>::type) : sizeof(P2PRec<1, 1>::type);
 }
 
 struct P2PLayout {
