@@ -813,6 +813,24 @@ def time_fmm(S, W, t, steps, warmup):
             r["order4_graph_ms"] = e0.elapsed_time(e1) / steps
             r["order4_graph_equals_eager"] = bool(np.array_equal(out.cpu().numpy()[:, pick], got))
             del graph
+        if order == 6:
+            # the same-cell rule of Sec. 2.2: each cell's sum onto itself taken off
+            # exactly, against the direct sum with that rule on the same sample
+            grp = t(c.group.astype(np.int32))
+            ng = int(c.group.max()) + 1
+            ref_ex = S.sl(pos, f, w, t(c.pos[:, pick]), src_group=grp, trg_group=t(c.group[pick].astype(np.int32)),
+                          exclude_same_group=True).cpu().numpy()
+            S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out, src_group=grp, trg_group=grp, n_groups=ng)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out, src_group=grp, trg_group=grp,
+                         n_groups=ng)
+            e1.record()
+            torch.cuda.synchronize()
+            ge = out.cpu().numpy()[:, pick]
+            r["order6_same_cell_ms"] = e0.elapsed_time(e1) / steps
+            r["order6_same_cell_rel_l2_vs_direct"] = float(np.linalg.norm(ge - ref_ex) / np.linalg.norm(ref_ex))
         del plan
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()

@@ -535,12 +535,24 @@ void stokes_fmm_plan_destroy(stokes_fmm_plan* plan);
  * densities grow as 8^depth * 6 * (6 (order-1)^2 + 2) doubles, the check
  * matrix of a level as 3 min(8^depth, max(n_src, n_trg)) + 262,656 columns of
  * m doubles (m as above), plus 32,768 columns of 3 (6 (order-1)^2 + 2) doubles
- * for the split pseudo-inverse products. */
+ * for the split pseudo-inverse products.  excl (may be NULL) as in the
+ * evaluation: the same-group rule adds about 150 bytes per point and 32 per
+ * group. */
 int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,
-                              int64_t n_trg, int32_t depth, size_t* bytes);
+                              int64_t n_trg, int32_t depth, const stokes_exclusion* excl, size_t* bytes);
 
-/* vel_out(3, n_trg) (=|+=) the single-layer sum of stokes_sl_eval (no pair
- * rule) by the FMM.  centre: HOST double[3]; half_width > 0.  opts.precision:
+/* vel_out(3, n_trg) (=|+=) the single-layer sum of stokes_sl_eval by the
+ * FMM.  Pair rule: excl NULL or STOKES_EXCL_NONE sums every pair (rho = 0
+ * skipped), as the paper's FMM does.  STOKES_EXCL_SAME_GROUP (Sec. 2.2, the
+ * other cells only) needs n_groups > 0 and every id of src_group and
+ * trg_group in [0, n_groups): after the FMM, each group's sum onto itself
+ * (pairs of one group, rho > 0) is evaluated exactly in float64 by the
+ * leaf-to-leaf kernel (points sorted by group inside the workspace, every
+ * group a leaf listing itself) and subtracted, so the result is the sum over
+ * pairs of different groups within the FMM's error.  An id outside
+ * [0, n_groups) makes every component of vel_out NaN (checked on the device).
+ * group_h and near_frac are not used.  centre: HOST double[3]; half_width > 0.
+ * opts.precision:
  * STOKES_FP64, or STOKES_MIXED to run the near-field (leaf-to-leaf) pairs in
  * float32 on offsets from the target leaf's centre, each staged tile's float32
  * partial added into float64 (about 1e-7 relative, far below the FMM's own
@@ -550,21 +562,23 @@ int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan
 int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,
                        const double* src_xyz, const double* density, const double* weight,
                        int64_t n_trg, const double* trg_xyz, double mu, const double* centre,
-                       double half_width, int32_t depth, const stokes_opts* opts, double* vel_out,
-                       void* workspace, size_t ws_bytes, void* stream);
+                       double half_width, int32_t depth, const stokes_exclusion* excl,
+                       const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
+                       void* stream);
 
-/* vel_out(3, n_trg) (=|+=) the double-layer sum of stokes_dl_eval (no pair
- * rule) by the same FMM: the double-layer kernel in P2M and in the near
- * field.  A double-layer field has a net flux (the sum of n . q over the
+/* vel_out(3, n_trg) (=|+=) the double-layer sum of stokes_dl_eval by the
+ * same FMM: the double-layer kernel in P2M and in the near field.  A double-layer field has a net flux (the sum of n . q over the
  * sources) that single-layer equivalent densities cannot carry, so each box
  * also carries a point source of that flux at its centre (velocity
  * sigma r / (4 pi rho^3)); its equivalent density holds the flux-free rest.
- * Other arguments as stokes_fmm_sl_eval (no mu: the kernel has none). */
+ * Other arguments, the pair rule included, as stokes_fmm_sl_eval (no mu: the
+ * kernel has none). */
 int stokes_fmm_dl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,
                        const double* src_xyz, const double* density, const double* weight,
                        const double* normal, int64_t n_trg, const double* trg_xyz,
-                       const double* centre, double half_width, int32_t depth, const stokes_opts* opts,
-                       double* vel_out, void* workspace, size_t ws_bytes, void* stream);
+                       const double* centre, double half_width, int32_t depth,
+                       const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out,
+                       void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

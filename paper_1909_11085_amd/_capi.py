@@ -101,11 +101,11 @@ _SIGNATURES = {
                                                    ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp, _sz, _vp]),
     "stokes_fmm_plan_create": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_vp)]),
     "stokes_fmm_plan_destroy": (None, [_vp]),
-    "stokes_fmm_workspace_size": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i32, ctypes.POINTER(_sz)]),
-    "stokes_fmm_sl_eval": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _dbl, _vp, _dbl, _i32, _OP,
-                                          _vp, _vp, _sz, _vp]),
-    "stokes_fmm_dl_eval": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _dbl, _i32, _OP,
-                                          _vp, _vp, _sz, _vp]),
+    "stokes_fmm_workspace_size": (ctypes.c_int, [_vp, _vp, _i64, _i64, _i32, _EX, ctypes.POINTER(_sz)]),
+    "stokes_fmm_sl_eval": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp, _dbl, _vp, _dbl, _i32, _EX,
+                                          _OP, _vp, _vp, _sz, _vp]),
+    "stokes_fmm_dl_eval": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _dbl, _i32, _EX,
+                                          _OP, _vp, _vp, _sz, _vp]),
 }
 
 _lib = None

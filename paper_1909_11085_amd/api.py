@@ -629,40 +629,72 @@ def _fmm_precision(precision):
     return C.MIXED if precision == "mixed" else C.FP64
 
 
-def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, accumulate=False, precision="fp64"):
+class _FmmRule:
+    """Keeps the tensors of the FMM's pair rule alive for a call."""
+
+    def __init__(self, device, ns, nt, src_group, trg_group, exclude_same_group, n_groups):
+        if exclude_same_group is None:
+            exclude_same_group = src_group is not None and trg_group is not None
+        self.tensors = []
+        if not exclude_same_group:
+            self.ex = None
+            return
+        if src_group is None or trg_group is None:
+            raise ValueError("exclude_same_group needs src_group and trg_group")
+        sg = _vec1(src_group, ns, "src_group", device, torch.int32)
+        tg = _vec1(trg_group, nt, "trg_group", device, torch.int32)
+        if n_groups is None:   # one synchronisation: the largest id
+            n_groups = 1 + int(max(int(sg.max()) if ns else -1, int(tg.max()) if nt else -1, 0))
+        self.tensors = [sg, tg]
+        self.ex = C.Exclusion(C.EXCL_SAME_GROUP, _ptr(sg).value, _ptr(tg).value, None, int(n_groups), 0.0)
+
+    def ref(self):
+        return ctypes.byref(self.ex) if self.ex is not None else None
+
+
+def _fmm_common(plan, device, ns, nt, depth, rule):
+    size = ctypes.c_size_t()
+    C.check(C.lib().stokes_fmm_workspace_size(context(device), plan.handle, ns, nt, int(depth), rule.ref(),
+                                              ctypes.byref(size)))
+    return torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device), int(size.value)
+
+
+def fmm_sl(plan, src, f, w, trg, centre, half_width, depth, mu=1.0, out=None, accumulate=False, precision="fp64",
+           src_group=None, trg_group=None, exclude_same_group=None, n_groups=None):
     """Single-layer sum by the FMM; see stokes_fmm_sl_eval.  precision "mixed"
-    runs the near-field pairs in float32."""
+    runs the near-field pairs in float32.  With src_group and trg_group the
+    same-group rule applies (ids in [0, n_groups); n_groups defaults to the
+    largest id + 1, which costs one synchronisation)."""
     device = src.device
     _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
     ns, nt = src.shape[1], trg.shape[1]
     _vec1(w, ns, "w", device)
     out = _out(out, nt, device, accumulate)
-    size = ctypes.c_size_t()
-    C.check(C.lib().stokes_fmm_workspace_size(context(device), plan.handle, ns, nt, int(depth), ctypes.byref(size)))
-    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    rule = _FmmRule(device, ns, nt, src_group, trg_group, exclude_same_group, n_groups)
+    ws, size = _fmm_common(plan, device, ns, nt, depth, rule)
     c = (ctypes.c_double * 3)(*[float(v) for v in centre])
     opts = C.Opts(_fmm_precision(precision), int(bool(accumulate)))
     C.check(C.lib().stokes_fmm_sl_eval(context(device), plan.handle, ns, _ptr(src), _ptr(f), _ptr(w), nt, _ptr(trg),
-                                       float(mu), c, float(half_width), int(depth), ctypes.byref(opts), _ptr(out),
-                                       _ptr(ws), int(size.value), _stream(device)))
+                                       float(mu), c, float(half_width), int(depth), rule.ref(), ctypes.byref(opts),
+                                       _ptr(out), _ptr(ws), size, _stream(device)))
     return out
 
 
-def fmm_dl(plan, src, phi, w, nrm, trg, centre, half_width, depth, out=None, accumulate=False, precision="fp64"):
+def fmm_dl(plan, src, phi, w, nrm, trg, centre, half_width, depth, out=None, accumulate=False, precision="fp64",
+           src_group=None, trg_group=None, exclude_same_group=None, n_groups=None):
     """Double-layer sum by the FMM; see stokes_fmm_dl_eval.  precision "mixed"
-    runs the near-field pairs in float32."""
+    runs the near-field pairs in float32; the pair rule as in fmm_sl."""
     device = src.device
     _vec3(src, "src", device); _vec3(phi, "phi", device); _vec3(nrm, "nrm", device); _vec3(trg, "trg", device)
     ns, nt = src.shape[1], trg.shape[1]
     _vec1(w, ns, "w", device)
     out = _out(out, nt, device, accumulate)
-    size = ctypes.c_size_t()
-    C.check(C.lib().stokes_fmm_workspace_size(context(device), plan.handle, ns, nt, int(depth), ctypes.byref(size)))
-    ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
+    rule = _FmmRule(device, ns, nt, src_group, trg_group, exclude_same_group, n_groups)
+    ws, size = _fmm_common(plan, device, ns, nt, depth, rule)
     c = (ctypes.c_double * 3)(*[float(v) for v in centre])
     opts = C.Opts(_fmm_precision(precision), int(bool(accumulate)))
     C.check(C.lib().stokes_fmm_dl_eval(context(device), plan.handle, ns, _ptr(src), _ptr(phi), _ptr(w), _ptr(nrm), nt,
-                                       _ptr(trg), c, float(half_width), int(depth), ctypes.byref(opts), _ptr(out),
-                                       _ptr(ws), int(size.value), _stream(device)))
+                                       _ptr(trg), c, float(half_width), int(depth), rule.ref(), ctypes.byref(opts),
+                                       _ptr(out), _ptr(ws), size, _stream(device)))
     return out
 

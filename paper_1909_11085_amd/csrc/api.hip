@@ -13,6 +13,7 @@
 #include "checkpoint.hpp"
 #include "common.hpp"
 #include "fmm.hpp"
+#include "groups.hpp"
 #include "p2p.hpp"
 #include "spatial.hpp"
 #include "vjp.hpp"
@@ -1310,20 +1311,44 @@ static int fmm_check_sizes(const stokes_fmm_plan* plan, int64_t n_src, int64_t n
     return STOKES_OK;
 }
 
+// Groups of the FMM's same-group rule (0: no rule); the rule needs n_groups > 0.
+static int fmm_groups(const stokes_exclusion* excl, int32_t* n_groups) {
+    *n_groups = 0;
+    if (!excl || excl->mode == STOKES_EXCL_NONE) return STOKES_OK;
+    if (excl->mode != STOKES_EXCL_SAME_GROUP)
+        return fail(STOKES_EINVAL, "exclusion.mode must be STOKES_EXCL_NONE or STOKES_EXCL_SAME_GROUP");
+    if (excl->n_groups <= 0)
+        return fail(STOKES_EINVAL, "the FMM's same-group rule needs n_groups > 0 (group ids in [0, n_groups))");
+    *n_groups = excl->n_groups;
+    return STOKES_OK;
+}
+
+// Workspace of an FMM evaluation: the FMM's, then the same-group correction's.
+static size_t fmm_total_bytes(const stokes_fmm_plan* plan, int kernel, int64_t n_src, int64_t n_trg, int32_t depth,
+                              int32_t n_groups, size_t* off_groups) {
+    const size_t f = stokes::align_up(stokes::fmm_workspace_bytes(stokes::fmm_plan_order(plan), n_src, n_trg, depth), 256);
+    if (off_groups) *off_groups = f;
+    return f + stokes::same_group_workspace_bytes(kernel, n_src, n_trg, n_groups);
+}
+
 int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, int64_t n_trg,
-                              int32_t depth, size_t* bytes) {
+                              int32_t depth, const stokes_exclusion* excl, size_t* bytes) {
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
     if (!bytes) return fail(STOKES_EINVAL, "bytes is NULL");
     int rc = fmm_check_sizes(plan, n_src, n_trg, depth);
     if (rc) return rc;
-    *bytes = stokes::fmm_workspace_bytes(stokes::fmm_plan_order(plan), n_src, n_trg, depth);
+    int32_t ng = 0;
+    if ((rc = fmm_groups(excl, &ng))) return rc;
+    // sized for the double layer, whose correction also gathers the normals
+    *bytes = fmm_total_bytes(plan, STOKES_KERNEL_DL, n_src, n_trg, depth, ng, nullptr);
     return STOKES_OK;
 }
 
 static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, int64_t n_src, const double* src_xyz,
                     const double* density, const double* weight, const double* normal, int64_t n_trg,
                     const double* trg_xyz, double pref, const double* centre, double half_width, int32_t depth,
-                    const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes, void* stream) {
+                    const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out, void* workspace,
+                    size_t ws_bytes, void* stream) {
     const char* name = kernel ? "stokes_fmm_dl_eval" : "stokes_fmm_sl_eval";
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
     int rc = fmm_check_sizes(plan, n_src, n_trg, depth);
@@ -1334,7 +1359,9 @@ static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, in
         if (!isfinite(centre[c])) return fail(STOKES_EINVAL, "centre must be finite");
     if (!(isfinite(half_width) && half_width > 0.0)) return fail(STOKES_EINVAL, "half_width must be finite and > 0");
     Parsed p;
-    if ((rc = parse_common(nullptr, opts, n_src, n_trg, p))) return rc;
+    if ((rc = parse_common(excl, opts, n_src, n_trg, p))) return rc;
+    int32_t ng = 0;
+    if ((rc = fmm_groups(excl, &ng))) return rc;
 
     if ((rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz))) return rc;
     if (!arr_ok(vel_out, 3 * n_trg, 8)) return fail(STOKES_EINVAL, "vel_out must be non-NULL and 8-byte aligned");
@@ -1343,7 +1370,8 @@ static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, in
                              {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {normal, kernel ? sb : 0},
                               {trg_xyz, tb}, {workspace, ws_bytes}})))
         return rc;
-    const size_t need = stokes::fmm_workspace_bytes(stokes::fmm_plan_order(plan), n_src, n_trg, depth);
+    size_t off_groups = 0;
+    const size_t need = fmm_total_bytes(plan, kernel, n_src, n_trg, depth, ng, &off_groups);
     if ((rc = check_workspace(workspace, ws_bytes, need))) return rc;
     if (n_trg == 0) return STOKES_OK;
     DeviceGuard dg(ctx->device);
@@ -1366,6 +1394,23 @@ static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, in
     const stokes::KernelTimer timer = stokes::next_timer(ctx);
     if (timer.on()) (void)hipEventRecord(timer.start, st);
     hipError_t e = stokes::launch_fmm(plan, in, vel_out, workspace, st);
+    if (e == hipSuccess && ng > 0 && n_src > 0) {
+        // the same-group rule: take off each group's sum onto itself
+        stokes::SumInputs g{};
+        g.kernel = kernel;
+        g.n_src = n_src;
+        g.n_trg = n_trg;
+        g.src_xyz = src_xyz;
+        g.density = density;
+        g.weight = weight;
+        g.normal = kernel ? normal : nullptr;
+        g.trg_xyz = trg_xyz;
+        g.src_group = p.src_group;
+        g.trg_group = p.trg_group;
+        g.n_groups = ng;
+        g.pref = kernel ? 6.0 / (8.0 * kPi) : pref;
+        e = stokes::launch_same_group_subtract(g, vel_out, static_cast<char*>(workspace) + off_groups, st);
+    }
     if (timer.on()) (void)hipEventRecord(timer.stop, st);
     return launch_status(e, name);
 }
@@ -1373,20 +1418,21 @@ static int fmm_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int kernel, in
 int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, const double* src_xyz,
                        const double* density, const double* weight, int64_t n_trg, const double* trg_xyz,
                        double mu, const double* centre, double half_width, int32_t depth,
-                       const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
-                       void* stream) {
+                       const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out, void* workspace,
+                       size_t ws_bytes, void* stream) {
     if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
     return fmm_eval(ctx, plan, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz,
-                    1.0 / (8.0 * kPi * mu), centre, half_width, depth, opts, vel_out, workspace, ws_bytes, stream);
+                    1.0 / (8.0 * kPi * mu), centre, half_width, depth, excl, opts, vel_out, workspace, ws_bytes,
+                    stream);
 }
 
 int stokes_fmm_dl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src, const double* src_xyz,
                        const double* density, const double* weight, const double* normal, int64_t n_trg,
                        const double* trg_xyz, const double* centre, double half_width, int32_t depth,
-                       const stokes_opts* opts, double* vel_out, void* workspace, size_t ws_bytes,
-                       void* stream) {
+                       const stokes_exclusion* excl, const stokes_opts* opts, double* vel_out, void* workspace,
+                       size_t ws_bytes, void* stream) {
     return fmm_eval(ctx, plan, STOKES_KERNEL_DL, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz,
-                    1.0 / (8.0 * kPi), centre, half_width, depth, opts, vel_out, workspace, ws_bytes, stream);
+                    1.0 / (8.0 * kPi), centre, half_width, depth, excl, opts, vel_out, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -298,6 +298,37 @@ def test_fmm_minus_self_cells_is_the_excluded_sum(plans):
     grp = torch.as_tensor(g, dtype=torch.int32, device=device())
     ref = host(S.sl(pos, f, w, pos, src_group=grp, trg_group=grp, exclude_same_group=True))
     assert rel_l2(host(u), ref) < 3 * FMM_ERR[6], rel_l2(host(u), ref)
+    # the FMM's own same-group rule is that composition: the points already
+    # come group by group, so its stable sort keeps them in place
+    ruled = S.fmm_sl(plans[6], pos, f, w, pos, tuple(ctr), R, 4, src_group=grp, trg_group=grp, n_groups=n_cells)
+    assert torch.equal(ruled, u)
+
+
+def test_same_group_rule_on_shuffled_points(plans):
+    """The same-group rule with the points in random order (groups
+    interleaved), single and double layer, against the direct sums with the
+    rule; an id outside [0, n_groups) turns the output into NaN."""
+    print("case fmm same-group rule, shuffled", flush=True)
+    rng = np.random.default_rng(77)
+    cfg = W.make_config(1)
+    c = cfg["cells"]
+    perm = rng.permutation(c.n)
+    pos, f, w = dev(c.pos[:, perm]), dev(cfg["f"][:, perm]), dev(c.weight[perm])
+    nrm = dev(c.normal[:, perm])
+    grp = torch.as_tensor(c.group[perm], dtype=torch.int32, device=device())
+    lo, hi = c.pos.min(axis=1), c.pos.max(axis=1)
+    ctr, R = tuple(0.5 * (lo + hi)), 0.5 * float((hi - lo).max()) * 1.0001
+    u = host(S.fmm_sl(plans[6], pos, f, w, pos, ctr, R, 3, src_group=grp, trg_group=grp))
+    ref = host(S.sl(pos, f, w, pos, src_group=grp, trg_group=grp, exclude_same_group=True))
+    assert rel_l2(u, ref) < 3 * FMM_ERR[6], rel_l2(u, ref)
+    ud = host(S.fmm_dl(plans[6], pos, f, w, nrm, pos, ctr, R, 3, src_group=grp, trg_group=grp))
+    refd = host(S.dl(pos, f, w, nrm, pos, src_group=grp, trg_group=grp, exclude_same_group=True))
+    assert rel_l2(ud, refd) < 3 * FMM_ERR_DL[6], rel_l2(ud, refd)
+    n_groups = int(c.group.max()) + 1
+    bad = grp.clone()
+    bad[5] = n_groups
+    out = host(S.fmm_sl(plans[6], pos, f, w, pos, ctr, R, 3, src_group=bad, trg_group=grp, n_groups=n_groups))
+    assert np.all(np.isnan(out))
 
 
 @pytest.mark.parametrize("kernel", ["sl", "dl"])
@@ -382,9 +413,12 @@ def test_rejections(plans):
     assert L.stokes_fmm_plan_create(ctx, 7, ctypes.byref(h)) == C.EINVAL
     P = plans[4].handle
     size = ctypes.c_size_t()
-    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 1, ctypes.byref(size)) == C.EINVAL
-    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 8, ctypes.byref(size)) == C.EINVAL
-    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 2, ctypes.byref(size)) == C.OK
+    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 1, None, ctypes.byref(size)) == C.EINVAL
+    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 8, None, ctypes.byref(size)) == C.EINVAL
+    g = torch.zeros(10, dtype=torch.int32, device=device())
+    no_groups = C.Exclusion(C.EXCL_SAME_GROUP, g.data_ptr(), g.data_ptr(), None, 0, 0.0)
+    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 2, ctypes.byref(no_groups), ctypes.byref(size)) == C.EINVAL
+    assert L.stokes_fmm_workspace_size(ctx, P, 10, 10, 2, None, ctypes.byref(size)) == C.OK
     ws = torch.empty(size.value, dtype=torch.uint8, device=device())
     x = dev(np.random.default_rng(76).uniform(-1, 1, (3, 10)))
     f, w = dev(np.ones((3, 10))), dev(np.ones(10))
@@ -392,15 +426,19 @@ def test_rejections(plans):
     c = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
     vp = lambda t: ctypes.c_void_p(t.data_ptr())
 
-    def run(mu=1.0, centre=c, hw=1.0, opts=None, wsb=size.value):
+    def run(mu=1.0, centre=c, hw=1.0, opts=None, wsb=size.value, excl=None):
         return L.stokes_fmm_sl_eval(ctx, P, 10, vp(x), vp(f), vp(w), 10, vp(x), mu, centre, hw, 2,
-                                    ctypes.byref(opts) if opts else None, vp(out), vp(ws), wsb, None)
+                                    ctypes.byref(excl) if excl else None, ctypes.byref(opts) if opts else None,
+                                    vp(out), vp(ws), wsb, None)
 
     assert run(mu=0.0) == C.EINVAL
     assert run(centre=None) == C.EINVAL
     assert run(hw=-1.0) == C.EINVAL
     assert run(opts=C.Opts(7, 0)) == C.EINVAL
     assert run(wsb=size.value - 1) == C.EWORKSPACE
+    assert run(excl=no_groups) == C.EINVAL                              # the rule needs n_groups > 0
+    one_group = C.Exclusion(C.EXCL_SAME_GROUP, g.data_ptr(), g.data_ptr(), None, 1, 0.0)
+    assert run(excl=one_group) == C.EWORKSPACE                          # its correction needs more room
     torch.cuda.synchronize()
     assert bool((out == 9.0).all())
     assert run() == C.OK
