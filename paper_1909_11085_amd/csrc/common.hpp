@@ -67,6 +67,9 @@ struct SumInputs {
     // test-only: when set, the mixed direct and leaf-to-leaf kernels add, for
     // every pair they take, its class code into pair_class[t * n_src + s]
     int32_t* pair_class;
+    // leaf-to-leaf sums: when set, target t's result goes to output column
+    // trg_perm[t] (points sorted by an internal caller); a null weight is 1
+    const int32_t* trg_perm;
 };
 
 // class codes of pair_class (one pair taken once holds exactly one of them)

@@ -39,6 +39,7 @@
 
 #include "common.hpp"
 #include "fmm.hpp"
+#include "p2p.hpp"
 #include "spatial.hpp"
 
 struct stokes_fmm_plan {
@@ -358,18 +359,11 @@ __device__ __forceinline__ void store_partial(const FmmDev& a, double* part, int
 // own sources (the only ones that can sit at zero distance from a target, so
 // the only ones with the zero-distance mask), then the sources of the other
 // 26 neighbour leaves as one run.
-constexpr int kNearTile = 128;
-constexpr int kNearRep = 16;
-constexpr int kNearSlots = kNearTile + kNearRep;   // room for the padding of the last runs
 
 template <int KT> struct NearRec;
 template <> struct NearRec<0> { using type = SrcSL64; };
 template <> struct NearRec<1> { using type = SrcDL64; };
 
-struct NearArgs {
-    const int32_t* items;      // (leaf, chunk) pairs
-    const int64_t* n_items;    // device count
-};
 
 template <int KT>
 __device__ __forceinline__ void load_source(const FmmDev& a, int64_t m, typename NearRec<KT>::type& r) {
@@ -518,294 +512,63 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l, const int
 
 // Mixed precision: float32 records of the sources' offsets from the item's
 // leaf centre (all sources of the 27 leaves lie within 3 leaf widths of it).
-template <int KT> struct NearRec32;
-template <> struct NearRec32<0> { using type = SrcSL32; };
-template <> struct NearRec32<1> { using type = SrcDL32; };
-
-template <int KT>
-__device__ __forceinline__ void load_source32(const FmmDev& a, int64_t m, const double* c,
-                                              typename NearRec32<KT>::type& r) {
-    r.ox = (float)(a.sx[m] - c[0]);
-    r.oy = (float)(a.sx[a.n_src + m] - c[1]);
-    r.oz = (float)(a.sx[2 * a.n_src + m] - c[2]);
-    r.qx = (float)a.sq[m];
-    r.qy = (float)a.sq[a.n_src + m];
-    r.qz = (float)a.sq[2 * a.n_src + m];
-    r.t2 = 0.0f;
-    r.g = 0;
-    if constexpr (KT == 1) {
-        r.nx = (float)a.sn[m];
-        r.ny = (float)a.sn[a.n_src + m];
-        r.nz = (float)a.sn[2 * a.n_src + m];
-        r.pad = 0.0f;
-    }
-}
-
-template <typename Rec>
-__device__ __forceinline__ Rec far_pad32() {
-    Rec r{};
-    r.ox = r.oy = r.oz = kPadOff;
-    return r;
-}
-
-// float32 pair on leaf-centred offsets (8 pi mu units); MASKED: a zero
-// distance (the same point, which rounds to the same offset) adds nothing.
-template <int KT, bool MASKED>
-__device__ __forceinline__ void near_pair32(const typename NearRec32<KT>::type& s, float x, float y, float z,
-                                            float* b) {
-    const float dx = x - s.ox, dy = y - s.oy, dz = z - s.oz;
-    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-    const float ri = (MASKED && r2 == 0.0f) ? 0.0f : __builtin_amdgcn_rsqf(r2);
-    const float ri2 = ri * ri;
-    const float rq = __builtin_fmaf(dx, s.qx, __builtin_fmaf(dy, s.qy, dz * s.qz));
-    if constexpr (KT == 0) {
-        const float c = rq * ri2;
-        b[0] = __builtin_fmaf(__builtin_fmaf(c, dx, s.qx), ri, b[0]);
-        b[1] = __builtin_fmaf(__builtin_fmaf(c, dy, s.qy), ri, b[1]);
-        b[2] = __builtin_fmaf(__builtin_fmaf(c, dz, s.qz), ri, b[2]);
-    } else {
-        const float rn = __builtin_fmaf(dx, s.nx, __builtin_fmaf(dy, s.ny, dz * s.nz));
-        const float c = 6.0f * rn * rq * (ri2 * ri2 * ri);
-        b[0] = __builtin_fmaf(c, dx, b[0]);
-        b[1] = __builtin_fmaf(c, dy, b[1]);
-        b[2] = __builtin_fmaf(c, dz, b[2]);
-    }
-}
-
-// MIXED: the P2P pairs in float32 on leaf-centred offsets, each staged tile's
-// float32 partial added into float64; L2P stays float64 (the downward density
-// comes out of a pseudo-inverse and may carry large cancelling terms).
-template <int KT, int MIXED>
-__global__ __launch_bounds__(kWave) void near_kernel(FmmDev a, NearArgs na) {
-    using Rec = typename NearRec<KT>::type;
-    using Rec32 = typename NearRec32<KT>::type;
-    static_assert(sizeof(Rec32) <= sizeof(Rec), "the float32 records share the staging buffer");
-    __shared__ Rec s_rec[kNearSlots];
-    Rec32* s_r32 = reinterpret_cast<Rec32*>(s_rec);
-    __shared__ int64_t s_beg[27], s_pre[28];
-    SrcSL64* s_sl = reinterpret_cast<SrcSL64*>(s_rec);
-    const int lane = threadIdx.x;
-    const int64_t count = *na.n_items;
-    const int64_t nlx = (int64_t)1 << a.D;
-    for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-        const int64_t L = na.items[2 * it];
-        const int64_t t0 = a.tofs[L] + (int64_t)na.items[2 * it + 1] * kWave;
-        const int nc = (int)min(a.tofs[L + 1] - t0, (int64_t)kWave);     // 1..64
-        const int R = min(kNearRep, kWave / nc);
-        const int ti = lane / R, hp = lane - ti * R;
-        const bool valid = ti < nc;
-        const int64_t t = t0 + (valid ? ti : 0);                           // idle lanes mirror target t0
-        const double x = a.tx[t], y = a.tx[a.n_trg + t], z = a.tx[2 * a.n_trg + t];
-        double u[3] = {0.0, 0.0, 0.0};
-        double ctr[3], h;
-        box_centre(a, a.D, L, ctr, h);
-
-        // L2P: the leaf's downward equivalent density, single-layer kernel (with
-        // the zero-distance mask: a target outside the root cube is counted in a
-        // boundary leaf and may sit anywhere)
-        const double* de = a.de + (a.base[a.D] + L) * a.n3;
-        for (int j0 = 0; j0 < a.ns; j0 += kNearTile) {
-            const int nb = min(kNearTile, a.ns - j0);
-            for (int j = lane; j < kNearSlots; j += kWave) {
-                SrcSL64 r = far_pad<SrcSL64>();
-                if (j < nb) {
-                    const int k = j0 + j;
-                    const double sc = kAlphaDE * h;
-                    r.x = ctr[0] + sc * a.surf[3 * k];
-                    r.y = ctr[1] + sc * a.surf[3 * k + 1];
-                    r.z = ctr[2] + sc * a.surf[3 * k + 2];
-                    r.qx = de[3 * k];
-                    r.qy = de[3 * k + 1];
-                    r.qz = de[3 * k + 2];
-                }
-                s_sl[j] = r;
-            }
-            __builtin_amdgcn_wave_barrier();
-            const int steps = (nb + R - 1) / R;
-            for (int st = 0; st < steps; ++st) {
-                const SrcSL64 sr = s_sl[st * R + hp];
-                sl_pair<true>(x - sr.x, y - sr.y, z - sr.z, sr.qx, sr.qy, sr.qz, u);
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-
-        // the target's offset from the leaf centre, for the float32 pairs
-        const float xs = (float)(x - ctr[0]), ys = (float)(y - ctr[1]), zs = (float)(z - ctr[2]);
-        (void)xs; (void)ys; (void)zs;
-
-        // the leaf's own sources, with the zero-distance mask
-        {
-            const int64_t s0 = a.sofs[L], s1 = a.sofs[L + 1];
-            for (int64_t b0 = s0; b0 < s1; b0 += kNearTile) {
-                const int nb = (int)min((int64_t)kNearTile, s1 - b0);
-                const int steps = (nb + R - 1) / R;
-                if constexpr (MIXED != 0) {
-                    for (int j = lane; j < kNearSlots; j += kWave) {
-                        Rec32 r = far_pad32<Rec32>();
-                        if (j < nb) load_source32<KT>(a, b0 + j, ctr, r);
-                        s_r32[j] = r;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    float bsum[3] = {0.0f, 0.0f, 0.0f};
-                    for (int st = 0; st < steps; ++st) near_pair32<KT, true>(s_r32[st * R + hp], xs, ys, zs, bsum);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) u[c] += (double)bsum[c];
-                } else {
-                    for (int j = lane; j < kNearSlots; j += kWave) {
-                        Rec r = far_pad<Rec>();
-                        if (j < nb) load_source<KT>(a, b0 + j, r);
-                        s_rec[j] = r;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    for (int st = 0; st < steps; ++st) near_pair<KT, true>(s_rec[st * R + hp], x, y, z, u);
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-
-        // the other 26 neighbour leaves, as one run of sources
-        if (lane < 27) {
-            int64_t beg = 0, len = 0;
-            const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
-            const int64_t ni[3] = {compact3(L) + dx, compact3(L >> 1) + dy, compact3(L >> 2) + dz};
-            if (lane != 13 && ni[0] >= 0 && ni[1] >= 0 && ni[2] >= 0 && ni[0] < nlx && ni[1] < nlx && ni[2] < nlx) {
-                const uint64_t nbr = morton(ni[0], ni[1], ni[2]);
-                beg = a.sofs[nbr];
-                len = a.sofs[nbr + 1] - beg;
-            }
-            s_beg[lane] = beg;
-            s_pre[lane + 1] = len;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-            s_pre[0] = 0;
-            for (int k = 1; k <= 27; ++k) s_pre[k] += s_pre[k - 1];
-        }
-        __builtin_amdgcn_wave_barrier();
-        const int64_t total = s_pre[27];
-        for (int64_t f0 = 0; f0 < total; f0 += kNearTile) {
-            const int nb = (int)min((int64_t)kNearTile, total - f0);
-            const int steps = (nb + R - 1) / R;
-            for (int j = lane; j < kNearSlots; j += kWave) {
-                int64_t m = -1;
-                if (j < nb) {
-                    const int64_t f = f0 + j;
-                    int lo = 0, hi = 27;                   // s_pre[lo] <= f < s_pre[hi]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_pre[mid] <= f) lo = mid; else hi = mid;
-                    }
-                    m = s_beg[lo] + (f - s_pre[lo]);
-                }
-                if constexpr (MIXED != 0) {
-                    Rec32 r = far_pad32<Rec32>();
-                    if (m >= 0) load_source32<KT>(a, m, ctr, r);
-                    s_r32[j] = r;
-                } else {
-                    Rec r = far_pad<Rec>();
-                    if (m >= 0) load_source<KT>(a, m, r);
-                    s_rec[j] = r;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            if constexpr (MIXED != 0) {
-                float bsum[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll 2
-                for (int st = 0; st < steps; ++st) near_pair32<KT, false>(s_r32[st * R + hp], xs, ys, zs, bsum);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) u[c] += (double)bsum[c];
-            } else {
-#pragma unroll 2
-                for (int st = 0; st < steps; ++st) near_pair<KT, false>(s_rec[st * R + hp], x, y, z, u);
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-
-        // the R phases of each target, in order
-        double sum[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < R; ++q)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sum[c] += __shfl(u[c], ti * R + q);
-        if (valid && hp == 0) {
-            const int64_t o = a.tperm[t];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double val = a.pref * sum[c];
-                a.out[c * a.n_trg + o] = a.accumulate ? a.out[c * a.n_trg + o] + val : val;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();           // this item's reads precede the next item's writes
-    }
-}
-
-__global__ __launch_bounds__(kFBlock) void chunk_count_kernel(const int64_t* __restrict__ tofs, int64_t n_leaves,
-                                                              int64_t* __restrict__ cnt) {
-    for (int64_t L = (int64_t)blockIdx.x * kFBlock + threadIdx.x; L < n_leaves; L += (int64_t)gridDim.x * kFBlock)
-        cnt[L] = (tofs[L + 1] - tofs[L] + kWave - 1) / kWave;
-}
-
-__global__ __launch_bounds__(kFBlock) void items_kernel(const int64_t* __restrict__ tofs,
-                                                        const int64_t* __restrict__ cofs, int64_t n_leaves,
-                                                        int32_t* __restrict__ items) {
-    for (int64_t L = (int64_t)blockIdx.x * kFBlock + threadIdx.x; L < n_leaves; L += (int64_t)gridDim.x * kFBlock) {
-        const int64_t n = (tofs[L + 1] - tofs[L] + kWave - 1) / kWave;
-        for (int64_t c = 0; c < n; ++c) {
-            items[2 * (cofs[L] + c)] = (int32_t)L;
-            items[2 * (cofs[L] + c) + 1] = (int32_t)c;
-        }
-    }
-}
-
-// The items are run longest first (a wave per item, so the last items to
-// start set the end of the kernel): the key of an item is its pair-loop
-// steps, the sources of its leaf's 27 neighbours plus the downward surface
-// over the R lanes each target gets, inverted so that an ascending sort puts
-// the longest first; the unused slots of the buffer get the top key.
-constexpr int kItemKeyBits = 24;
-__global__ __launch_bounds__(kFBlock) void item_keys_kernel(FmmDev a, const int32_t* __restrict__ items,
-                                                            const int64_t* __restrict__ n_items, int64_t n_slots,
-                                                            uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
-    constexpr uint64_t kTop = (1ull << kItemKeyBits) - 1;
-    const int64_t count = *n_items, nlx = (int64_t)1 << a.D;
-    for (int64_t it = (int64_t)blockIdx.x * kFBlock + threadIdx.x; it < n_slots; it += (int64_t)gridDim.x * kFBlock) {
-        uint64_t key = kTop;
-        if (it < count) {
-            const int64_t L = items[2 * it];
-            const int64_t t0 = a.tofs[L] + (int64_t)items[2 * it + 1] * kWave;
-            const int nc = (int)min(a.tofs[L + 1] - t0, (int64_t)kWave);
-            const int R = min(kNearRep, kWave / nc);
+// ---------------------------------------------------------------------------
+// Near field.  L2P is a kernel of its own; the 27-leaf sums go to the
+// leaf-to-leaf kernel (p2p.hip) with the lists of the uniform tree built here:
+// every leaf holding targets lists its neighbours (itself included) that hold
+// sources, in a fixed order.
+// ---------------------------------------------------------------------------
+template <bool FILL>
+__global__ __launch_bounds__(kFBlock) void near_list_kernel(FmmDev a, int64_t* __restrict__ ofs,
+                                                            int32_t* __restrict__ ul) {
+    const int64_t nl = (int64_t)1 << (3 * a.D), nlx = (int64_t)1 << a.D;
+    for (int64_t L = (int64_t)blockIdx.x * kFBlock + threadIdx.x; L < nl; L += (int64_t)gridDim.x * kFBlock) {
+        int64_t n = 0;
+        if (a.tofs[L + 1] > a.tofs[L]) {
             const int64_t c0 = compact3(L), c1 = compact3(L >> 1), c2 = compact3(L >> 2);
-            int64_t n = a.ns;
             for (int d = 0; d < 27; ++d) {
                 const int64_t n0 = c0 + d / 9 - 1, n1 = c1 + (d / 3) % 3 - 1, n2 = c2 + d % 3 - 1;
                 if (n0 < 0 || n1 < 0 || n2 < 0 || n0 >= nlx || n1 >= nlx || n2 >= nlx) continue;
                 const uint64_t nb = morton(n0, n1, n2);
-                n += a.sofs[nb + 1] - a.sofs[nb];
+                if (a.sofs[nb + 1] == a.sofs[nb]) continue;
+                if constexpr (FILL) ul[ofs[L] + n] = (int32_t)nb;
+                ++n;
             }
-            const uint64_t steps = (uint64_t)((n + R - 1) / R);
-            key = kTop - 1 - min(steps, kTop - 1);
         }
-        keys[it] = key;
-        vals[it] = (int32_t)it;
-    }
-}
-// The items in the sorted order (the first *n_items entries of order are the
-// real items).
-__global__ __launch_bounds__(kFBlock) void item_order_kernel(const int32_t* __restrict__ items,
-                                                             const int64_t* __restrict__ n_items,
-                                                             const int32_t* __restrict__ order,
-                                                             int32_t* __restrict__ sorted) {
-    const int64_t count = *n_items;
-    for (int64_t k = (int64_t)blockIdx.x * kFBlock + threadIdx.x; k < count; k += (int64_t)gridDim.x * kFBlock) {
-        const int64_t it = order[k];
-        sorted[2 * k] = items[2 * it];
-        sorted[2 * k + 1] = items[2 * it + 1];
+        if constexpr (!FILL) ofs[L] = n;
     }
 }
 
-// Upper bound of the near-field work items: every leaf with targets adds at
-// most one partial chunk to the full ones.
-int64_t max_items(int64_t n_trg, int64_t n_leaves) { return (n_trg + kWave - 1) / kWave + std::min(n_trg, n_leaves); }
+// L2P: each target (leaf order) gets the single-layer field of its leaf's
+// downward equivalent density, in float64 with the zero-distance mask (a
+// target outside the root cube is counted in a boundary leaf and may sit
+// anywhere); written (or added) in the caller's order.  The near field is
+// added to it afterwards.
+__global__ __launch_bounds__(kFBlock) void l2p_kernel(FmmDev a, const uint64_t* __restrict__ tkeys) {
+    for (int64_t t = (int64_t)blockIdx.x * kFBlock + threadIdx.x; t < a.n_trg; t += (int64_t)gridDim.x * kFBlock) {
+        const int64_t L = (int64_t)tkeys[t];
+        double ctr[3], h;
+        box_centre(a, a.D, L, ctr, h);
+        const double sc = kAlphaDE * h;
+        const double* de = a.de + (a.base[a.D] + L) * a.n3;
+        const double x = a.tx[t], y = a.tx[a.n_trg + t], z = a.tx[2 * a.n_trg + t];
+        double u[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < a.ns; ++k) {
+            const double yx = ctr[0] + sc * a.surf[3 * k], yy = ctr[1] + sc * a.surf[3 * k + 1],
+                         yz = ctr[2] + sc * a.surf[3 * k + 2];
+            sl_pair<true>(x - yx, y - yy, z - yz, de[3 * k], de[3 * k + 1], de[3 * k + 2], u);
+        }
+        const int64_t o = a.tperm[t];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double val = a.pref * u[c];
+            a.out[c * a.n_trg + o] = a.accumulate ? a.out[c * a.n_trg + o] + val : val;
+        }
+    }
+}
+
+// Leaves holding targets are at most min(8^D, n_trg); each lists at most 27.
+int64_t max_list(int64_t n_trg, int64_t n_leaves) { return 27 * std::min(n_trg, n_leaves); }
 
 // ---------------------------------------------------------------------------
 // M2L as dense products on the FP64 matrix cores.
@@ -1345,10 +1108,9 @@ struct FmmLayout {
     int64_t nbox = 0, n_leaves = 0;
     int64_t base[kFmmMaxDepth + 2] = {};
     SortLayout sort;
-    int64_t max_items = 0;
     size_t off_skeys, off_svals, off_tkeys, off_tvals, off_sort, off_sx, off_sq, off_sn, off_tx, off_sofs, off_tofs,
-        off_snz, off_tpr, off_sig, off_ue, off_de, off_cofs, off_scan, off_items, off_ikeys, off_ivals, off_items2,
-        off_nitems, off_cflag, off_cscan, off_ctotal, off_clist, off_sched, off_vbuf, off_apart, total;
+        off_snz, off_tpr, off_sig, off_ue, off_de, off_uofs, off_scan, off_ul, off_p2p, off_cflag, off_cscan,
+        off_ctotal, off_clist, off_sched, off_vbuf, off_apart, total;
 };
 
 FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
@@ -1361,8 +1123,7 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     }
     L.nbox = acc;
     L.n_leaves = (int64_t)1 << (3 * D);
-    L.max_items = max_items(n_trg, L.n_leaves);
-    L.sort = sort_layout(std::max({n_src, n_trg, L.max_items}));
+    L.sort = sort_layout(std::max(n_src, n_trg));
     size_t off = 0;
     auto take = [&off](size_t bytes) {
         const size_t at = off;
@@ -1385,13 +1146,16 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
     L.off_sig = take((size_t)L.nbox * 8);
     L.off_ue = take((size_t)L.nbox * 3 * ns * 8);
     L.off_de = take((size_t)L.nbox * 3 * ns * 8);
-    L.off_cofs = take((size_t)L.n_leaves * 8);
+    // near field: the leaves' lists (offsets, entries) and the leaf-to-leaf
+    // sum's workspace (sized for the largest record of either kernel and precision)
+    L.off_uofs = take((size_t)(L.n_leaves + 1) * 8);
     L.off_scan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
-    L.off_items = take((size_t)L.max_items * 2 * 4);
-    L.off_ikeys = take((size_t)L.max_items * 8);
-    L.off_ivals = take((size_t)L.max_items * 4);
-    L.off_items2 = take((size_t)L.max_items * 2 * 4);
-    L.off_nitems = take(8);
+    L.off_ul = take((size_t)max_list(n_trg, L.n_leaves) * 4);
+    size_t p2p = 0;
+    for (int kt = 0; kt < 2; ++kt)
+        for (int mx = 0; mx < 2; ++mx)
+            p2p = std::max(p2p, p2p_workspace_bytes(kt, mx, n_src, n_trg, (int32_t)L.n_leaves));
+    L.off_p2p = take(p2p);
     L.off_cflag = take((size_t)L.n_leaves * 8);
     L.off_cscan = take((size_t)scan_tmp_count(L.n_leaves) * 8);
     L.off_ctotal = take(8);
@@ -1629,28 +1393,6 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
                                st, a, l);
     }
     const int T = (ns + kWave - 1) / kWave;
-    // near-field work items: (leaf, chunk of 64 targets)
-    int64_t* cofs = reinterpret_cast<int64_t*>(ws + L.off_cofs);
-    int64_t* n_items = reinterpret_cast<int64_t*>(ws + L.off_nitems);
-    int32_t* items = reinterpret_cast<int32_t*>(ws + L.off_items);
-    if (chk()) {
-        hipLaunchKernelGGL(chunk_count_kernel, dim3(gl), dim3(kFBlock), 0, st, a.tofs, L.n_leaves, cofs);
-        if (chk()) e = exclusive_scan_i64(cofs, L.n_leaves, cofs, reinterpret_cast<int64_t*>(ws + L.off_scan), n_items, st);
-        if (e == hipSuccess)
-            hipLaunchKernelGGL(items_kernel, dim3(gl), dim3(kFBlock), 0, st, a.tofs, cofs, L.n_leaves, items);
-    }
-    // the same items, longest first
-    int32_t* items_sorted = reinterpret_cast<int32_t*>(ws + L.off_items2);
-    if (chk() && L.max_items > 0) {
-        uint64_t* ikeys = reinterpret_cast<uint64_t*>(ws + L.off_ikeys);
-        int32_t* ivals = reinterpret_cast<int32_t*>(ws + L.off_ivals);
-        const unsigned gi = f_grid((L.max_items + kFBlock - 1) / kFBlock);
-        hipLaunchKernelGGL(item_keys_kernel, dim3(gi), dim3(kFBlock), 0, st, a, items, n_items, L.max_items, ikeys,
-                           ivals);
-        if (chk()) e = radix_sort_pairs(ikeys, ivals, L.max_items, kItemKeyBits, sort_ws, L.sort, st);
-        if (e == hipSuccess)
-            hipLaunchKernelGGL(item_order_kernel, dim3(gi), dim3(kFBlock), 0, st, items, n_items, ivals, items_sorted);
-    }
     M2LArgs g2{};
     g2.A = plan->d_m2l;
     g2.il = plan->d_il;
@@ -1765,14 +1507,35 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         if (!apply(l, plan->d_downA, a.de + L.base[l] * a.n3)) break;
     }
     if (chk()) {
-        const NearArgs na{items_sorted, n_items};
-        const dim3 g(f_grid(L.max_items));
-        if (dl) {
-            if (in.mixed) hipLaunchKernelGGL((near_kernel<1, 1>), g, dim3(kWave), 0, st, a, na);
-            else hipLaunchKernelGGL((near_kernel<1, 0>), g, dim3(kWave), 0, st, a, na);
-        } else {
-            if (in.mixed) hipLaunchKernelGGL((near_kernel<0, 1>), g, dim3(kWave), 0, st, a, na);
-            else hipLaunchKernelGGL((near_kernel<0, 0>), g, dim3(kWave), 0, st, a, na);
+        // L2P, then the near field added by the leaf-to-leaf kernel over the 27-leaf lists
+        hipLaunchKernelGGL(l2p_kernel, dim3(gt), dim3(kFBlock), 0, st, a, tkeys);
+        if (chk() && in.n_src > 0) {
+            int64_t* uofs = reinterpret_cast<int64_t*>(ws + L.off_uofs);
+            int32_t* ul = reinterpret_cast<int32_t*>(ws + L.off_ul);
+            hipLaunchKernelGGL(near_list_kernel<false>, dim3(gl), dim3(kFBlock), 0, st, a, uofs, ul);
+            if (chk())      // uofs[n_leaves] gets the total
+                e = exclusive_scan_i64(uofs, L.n_leaves, uofs, reinterpret_cast<int64_t*>(ws + L.off_scan),
+                                       uofs + L.n_leaves, st);
+            if (e == hipSuccess) hipLaunchKernelGGL(near_list_kernel<true>, dim3(gl), dim3(kFBlock), 0, st, a, uofs, ul);
+            if (chk()) {
+                SumInputs p{};
+                p.kernel = dl ? 1 : 0;
+                p.mixed = in.mixed;
+                p.n_src = in.n_src;
+                p.src_xyz = a.sx;
+                p.density = a.sq;              // q = w f, already formed: unit weights
+                p.weight = nullptr;
+                p.normal = a.sn;
+                p.n_trg = in.n_trg;
+                p.trg_xyz = a.tx;
+                p.excl = 0;
+                // the leaf-to-leaf kernel carries the double layer's factor 6 in its prefactor
+                p.pref = dl ? 6.0 * in.pref : in.pref;
+                p.trg_perm = a.tperm;
+                const KernelTimer none{};
+                e = launch_p2p_csr(p, (int32_t)L.n_leaves, a.sofs, a.tofs, uofs, ul, -1, out, 1, ws + L.off_p2p, st,
+                                   none, false);
+            }
         }
     }
     chk();

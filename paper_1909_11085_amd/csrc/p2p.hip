@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kWave) void p2p_prep(P2PArgs a) {
         a.leaf_ctr[4 * (int64_t)L + 3] = sqrt(rad2);
     }
     for (int64_t i = s0 + lane; i < s1; i += kWave) {
-        const double w = in.weight[i];
+        const double w = in.weight ? in.weight[i] : 1.0;
         double y[3], q[3], nv[3] = {0, 0, 0};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -229,7 +229,7 @@ __device__ __noinline__ Vec3 near64(const double* __restrict__ src_xyz, const do
     const double dx = x - src_xyz[m], dy = y - src_xyz[ns + m], dz = z - src_xyz[2 * ns + m];
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 == 0.0) return Vec3{0.0, 0.0, 0.0};
-    const double w = weight[m];
+    const double w = weight ? weight[m] : 1.0;
     const double qx = w * density[m], qy = w * density[ns + m], qz = w * density[2 * ns + m];
     const double ri = 1.0 / sqrt(r2);
     const double rq = dx * qx + dy * qy + dz * qz;
@@ -510,14 +510,15 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     }
     if (valid && h == 0) {
         const double p = a.in.pref;
+        const int64_t o = a.in.trg_perm ? (int64_t)a.in.trg_perm[idx] : idx;
         if (a.accumulate) {
-            a.out[idx] += p * ax;
-            a.out[nt + idx] += p * ay;
-            a.out[2 * nt + idx] += p * az;
+            a.out[o] += p * ax;
+            a.out[nt + o] += p * ay;
+            a.out[2 * nt + o] += p * az;
         } else {
-            a.out[idx] = p * ax;
-            a.out[nt + idx] = p * ay;
-            a.out[2 * nt + idx] = p * az;
+            a.out[o] = p * ax;
+            a.out[nt + o] = p * ay;
+            a.out[2 * nt + o] = p * az;
         }
     }
 }
@@ -774,7 +775,7 @@ hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* 
 
 hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
                           const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, double* out,
-                          int accumulate, void* ws, hipStream_t st, const KernelTimer& timer) {
+                          int accumulate, void* ws, hipStream_t st, const KernelTimer& timer, bool check) {
     const P2PLayout l = p2p_layout(in.kernel, in.mixed, in.n_src, in.n_trg, n_leaves);
     char* base = static_cast<char*>(ws);
     int32_t* status = reinterpret_cast<int32_t*>(base + l.off_status);
@@ -789,9 +790,11 @@ hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* 
     auto chk = [&]() { return (e = hipGetLastError()) == hipSuccess; };
     p2p_set_i32<<<1, kP2PThreads, 0, st>>>(status, 0);
     if (!chk()) return e;
-    p2p_csr_check<<<p2p_grid(std::max<int64_t>((int64_t)n_leaves + 1, n_ulist)), kP2PThreads, 0, st>>>(
-        src_ofs, trg_ofs, ulist_ofs, ulist, n_leaves, in.n_src, in.n_trg, n_ulist, status);
-    if (!chk()) return e;
+    if (check) {
+        p2p_csr_check<<<p2p_grid(std::max<int64_t>((int64_t)n_leaves + 1, n_ulist)), kP2PThreads, 0, st>>>(
+            src_ofs, trg_ofs, ulist_ofs, ulist, n_leaves, in.n_src, in.n_trg, n_ulist, status);
+        if (!chk()) return e;
+    }
     if (n_leaves > 0) {
         p2p_csr_count<<<p2p_grid(n_leaves), kP2PThreads, 0, st>>>(src_ofs, trg_ofs, ulist_ofs, ulist, n_leaves,
                                                                   status, cnt, listed);

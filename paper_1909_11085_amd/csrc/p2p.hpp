@@ -22,9 +22,12 @@ hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* 
                       void* ws, hipStream_t stream, const KernelTimer& timer);
 
 // The same sum from device leaf arrays, checked and cut into sorted work items
-// on the device; malformed arrays make every output component NaN.
+// on the device; malformed arrays make every output component NaN.  check =
+// false skips the checks (layouts built by the library itself; n_ulist is then
+// not used).
 hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
                           const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, double* out,
-                          int accumulate, void* ws, hipStream_t stream, const KernelTimer& timer);
+                          int accumulate, void* ws, hipStream_t stream, const KernelTimer& timer,
+                          bool check = true);
 
 }  // namespace stokes
