@@ -553,12 +553,13 @@ int stokes_fmm_workspace_size(const stokes_ctx* ctx, const stokes_fmm_plan* plan
  * [0, n_groups) makes every component of vel_out NaN (checked on the device).
  * group_h and near_frac are not used.  centre: HOST double[3]; half_width > 0.
  * opts.precision:
- * STOKES_FP64, or STOKES_MIXED to run the near-field (leaf-to-leaf) pairs in
- * float32 on offsets from the target leaf's centre, each staged tile's float32
- * partial added into float64 (about 1e-7 relative, far below the FMM's own
- * error); every other pass stays float64.  Asynchronous on `stream`; the sources and targets are
- * sorted into leaf order inside the workspace and the result is written in
- * the caller's order.  FP64 results are deterministic. */
+ * STOKES_FP64, or STOKES_MIXED to run the near field's pairs in float32 as
+ * the mixed leaf-to-leaf sum does (about 1e-7 relative, far below the FMM's
+ * own error); every other pass stays float64.  The near field is the
+ * leaf-to-leaf sum of stokes_p2p_leaf_eval over the uniform tree's 27-leaf
+ * lists, built in the workspace.  Asynchronous on `stream`; the sources and
+ * targets are sorted into leaf order inside the workspace and the result is
+ * written in the caller's order.  FP64 results are deterministic. */
 int stokes_fmm_sl_eval(stokes_ctx* ctx, const stokes_fmm_plan* plan, int64_t n_src,
                        const double* src_xyz, const double* density, const double* weight,
                        int64_t n_trg, const double* trg_xyz, double mu, const double* centre,
