@@ -386,6 +386,41 @@ def test_graph_capture_replays(plans):
         torch.cuda.synchronize()
 
 
+def test_graph_capture_same_cell_mixed(plans):
+    """The same-cell rule (group sort, leaf-to-leaf correction) and the mixed
+    near field inside a captured graph: three replays, each bitwise equal to
+    the eager result; the rule against the direct sum with the rule."""
+    print("case fmm graph capture, same-cell rule, mixed", flush=True)
+    cfg = W.make_config(1)
+    c = cfg["cells"]
+    pos, f, w = dev(c.pos), dev(cfg["f"]), dev(c.weight)
+    grp = torch.as_tensor(c.group, dtype=torch.int32, device=device())
+    ng = int(c.group.max()) + 1
+    lo, hi = c.pos.min(axis=1), c.pos.max(axis=1)
+    args = (plans[4], pos, f, w, pos, tuple(0.5 * (lo + hi)), 0.5 * float((hi - lo).max()) * 1.0001, 3)
+    kw = dict(src_group=grp, trg_group=grp, n_groups=ng, precision="mixed")
+    eager = host(S.fmm_sl(*args, **kw))
+    ref = host(S.sl(pos, f, w, pos, src_group=grp, trg_group=grp, exclude_same_group=True))
+    assert rel_l2(eager, ref) < 3 * FMM_ERR[4], rel_l2(eager, ref)
+    out = torch.empty_like(pos)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        S.fmm_sl(*args, out=out, **kw)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        S.fmm_sl(*args, out=out, **kw)
+    for k in range(3):
+        out.fill_(float(k + 3))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), eager), k
+        assert np.array_equal(host(S.fmm_sl(*args, **kw)), eager)
+        torch.cuda.synchronize()
+
+
 def test_edge_cases(plans):
     src, f, w, trg = _cloud(75, 500, 100)
     P = plans[4]

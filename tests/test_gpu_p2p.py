@@ -111,6 +111,40 @@ def test_p2p_uneven_layout_edge_cases():
     assert torch.equal(out, out2)
 
 
+def test_device_layout_graph_capture():
+    """The device-array layout path (checks, items, sort, sum) has no host
+    round trip and no memset: captured once and replayed three times with
+    eager work between the replays, each replay bitwise equal to the eager
+    result."""
+    print("case p2p device layout graph capture", flush=True)
+    rng, tree, d = _tree(15)
+    ofs, ul = W.nearest_leaf_lists(rng, tree, kmin=3, kmax=12)
+    lay = _device_layout(tree, ofs, ul)
+    pos, f, w, g, h = dev(d["pos"]), dev(d["f"]), dev(d["w"]), dev(d["g"]), dev(d["h"])
+
+    def run(out=None):
+        return S.p2p_leaf(lay, pos, f, w, pos, src_group=g, trg_group=g, precision="mixed", group_h=h, out=out)
+
+    eager = host(run())
+    out = torch.empty_like(pos)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run(out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run(out)
+    for k in range(3):
+        out.fill_(float(k + 5))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), eager), k
+        assert np.array_equal(host(run()), eager)
+        torch.cuda.synchronize()
+
+
 def test_device_layout_malformed_gives_nan():
     """The device checks of the leaf arrays (the plan's host checks, run on
     the device): each breach makes every output component NaN, with nothing
