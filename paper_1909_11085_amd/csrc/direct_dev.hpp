@@ -109,9 +109,10 @@ __device__ __forceinline__ bool groups_overlap(const Box& b, const SubMeta& m) {
 //   FP64: only coincident points need care, so the limit is 0 (any overlap).
 //   Mixed: pairs within the largest near radius (with slack for float32
 //   rounding of the offsets, 2^-20 of the coordinate scale) take float64, and
-//   pairs closer than half the sub-tile's extent take the high + low float32
-//   offsets; beyond that, offsets from the sub-tile centre give r to about
-//   5.5 eps32 relative.
+//   pairs closer than an eighth of the sub-tile's extent e take the high + low
+//   float32 offsets.  Beyond that, offsets from the sub-tile centre (at most
+//   rho + e sqrt(3)/2 and e sqrt(3)/2) give each component of r to within
+//   eps32 (1 + sqrt(3) e / (2 rho)) <= 8 eps32 relative.
 template <bool MIXED>
 __device__ __forceinline__ double near_limit2(const Box& w, const SubMeta& m) {
     if constexpr (!MIXED) {
@@ -123,7 +124,7 @@ __device__ __forceinline__ double near_limit2(const Box& w, const SubMeta& m) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) cd += fabs(0.5 * (w.lo[c] + w.hi[c]) - m.ctr[c]);
         const double slack = 0x1p-20 * (cd + wext + sext);
-        const double lim = fmax(__builtin_fma(1.001, m.rnear, slack), 0.5 * sext);
+        const double lim = fmax(__builtin_fma(1.001, m.rnear, slack), 0.125 * sext);
         return lim * lim;
     }
 }
