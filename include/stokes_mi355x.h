@@ -74,6 +74,7 @@ extern "C" {
 #define STOKES_OP_P2P_DL  3
 #define STOKES_OP_SL_VJP  4
 #define STOKES_OP_DL_VJP  5
+#define STOKES_OP_P2P_SL_VJP 6
 
 /* Largest point count per side accepted by any call. */
 #define STOKES_MAX_POINTS ((int64_t)1 << 30)
@@ -173,13 +174,14 @@ int stokes_timing_enable(stokes_ctx* ctx, int on);
 int stokes_timing_read(stokes_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Bytes of workspace that a call of kind `op` (STOKES_OP_*) with these sizes
- * and options needs.  For P2P ops n_leaves is the plan's leaf count; for
- * others it is ignored.  May be 0.  For STOKES_OP_SL with n_src == n_trg the
- * size covers the each-pair-once sum of a shared point set (its column
- * partials grow as n^2: about 0.9 GB for 278,528 points); a workspace of at
- * least the size for distinct point sets still works, one pair at a time. */
+ * and options needs.  For leaf-to-leaf ops n_leaves is the leaf count, and
+ * for STOKES_OP_P2P_SL_VJP n_ulist the list length; others ignore them.  May
+ * be 0.  For STOKES_OP_SL with n_src == n_trg the size covers the
+ * each-pair-once sum of a shared point set (its column partials grow as n^2:
+ * about 0.9 GB for 278,528 points); a workspace of at least the size for
+ * distinct point sets still works, one pair at a time. */
 int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int64_t n_trg,
-                          int32_t n_leaves, const stokes_opts* opts, size_t* bytes);
+                          int32_t n_leaves, int64_t n_ulist, const stokes_opts* opts, size_t* bytes);
 
 /* ---- direct sums ----------------------------------------------------------- */
 
@@ -323,6 +325,30 @@ int stokes_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const d
                   const double* trg_xyz, const stokes_exclusion* excl, const stokes_opts* opts,
                   const double* grad_vel, double* grad_density, double* grad_src_xyz,
                   double* grad_trg_xyz, void* workspace, size_t ws_bytes, void* stream);
+
+/* Single-layer adjoint of stokes_p2p_leaf_eval (same inputs and device leaf
+ * arrays, same rules for them): the sums of stokes_sl_vjp restricted to the
+ * pairs the lists name (a pair listed k times counts k times), in float64.
+ *   grad_trg_xyz: for target n of leaf L, c sum over the sources of L's list
+ *                 of K(r_nm; g_n, q_m)  (one pass on the forward lists);
+ *   grad_density, grad_src_xyz: for source m of leaf L', sums over the
+ *                 targets of every leaf whose list holds L' (one pass each on
+ *                 the transposed lists, built on the device by a stable sort
+ *                 with no host round trip).
+ * Targets of no leaf contribute nothing; sources listed by no leaf get zero.
+ * Each output is optional (NULL skips it) and no two may overlap.  Malformed
+ * leaf arrays make every component of the requested outputs NaN (also when
+ * accumulating).  Deterministic: every sum runs in a fixed order.
+ * Workspace: stokes_workspace_size(STOKES_OP_P2P_SL_VJP, n_src, n_trg,
+ * n_leaves, n_ulist).  n_src == 0 or n_trg == 0 gives zero gradients (kept
+ * when accumulating). */
+int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                      const double* weight, int64_t n_trg, const double* trg_xyz, int32_t n_leaves,
+                      const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs, const int64_t* ulist_ofs,
+                      const int32_t* ulist, int64_t n_ulist, double mu, const stokes_exclusion* excl,
+                      const stokes_opts* opts, const double* grad_vel, double* grad_density,
+                      double* grad_src_xyz, double* grad_trg_xyz, void* workspace, size_t ws_bytes,
+                      void* stream);
 
 /* ---- check-point quadrature on and near a patched surface, Sec. 3.1 ------ */
 

@@ -122,9 +122,9 @@ class _Rule:
         self.opts = C.Opts(PRECISIONS[precision], 0)
 
 
-def _workspace(op, n_src, n_trg, n_leaves, opts, device):
+def _workspace(op, n_src, n_trg, n_leaves, opts, device, n_ulist=0):
     size = ctypes.c_size_t()
-    C.check(C.lib().stokes_workspace_size(context(device), op, n_src, n_trg, n_leaves,
+    C.check(C.lib().stokes_workspace_size(context(device), op, n_src, n_trg, n_leaves, n_ulist,
                                           ctypes.byref(opts), ctypes.byref(size)))
     ws = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=device)
     return ws, int(size.value)
@@ -346,6 +346,13 @@ class P2PPlan:
     def handle(self):
         return self._h
 
+    def device_arrays(self):
+        """The layout as device tensors (src_leaf_ofs, trg_leaf_ofs, ulist_ofs,
+        ulist), uploaded on first use and kept."""
+        if getattr(self, "_dev", None) is None:
+            self._dev = tuple(torch.from_numpy(a).to(self.device) for a in (self._so, self._to, self._uo, self._ul))
+        return self._dev
+
     def pairs(self):
         """Pairs visited (before the pair rule removes any)."""
         n = ctypes.c_int64()
@@ -357,6 +364,25 @@ class P2PPlan:
         if h is not None and h.value:
             self._lib.stokes_p2p_plan_destroy(h)
             self._h = None
+
+
+def _device_layout(layout, device):
+    """(src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, n_leaves) as device
+    tensors, from a P2PPlan or a tuple of four device tensors."""
+    if isinstance(layout, P2PPlan):
+        if layout.device != device:
+            raise ValueError("the plan lives on another device than the points")
+        so, to, uo, ul = layout.device_arrays()
+    else:
+        so, to, uo, ul = layout
+    for t, name, dt in ((so, "src_leaf_ofs", torch.int64), (to, "trg_leaf_ofs", torch.int64),
+                        (uo, "ulist_ofs", torch.int64), (ul, "ulist", torch.int32)):
+        if t.dtype != dt or t.dim() != 1 or t.device != device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous 1-D {dt} tensor on the points' device")
+    n_leaves = so.numel() - 1
+    if n_leaves < 0 or to.numel() != n_leaves + 1 or uo.numel() != n_leaves + 1:
+        raise ValueError("the leaf offset arrays must all have n_leaves + 1 entries")
+    return so, to, uo, ul, n_leaves
 
 
 def p2p_leaf(layout, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=None, trg_group=None,
@@ -387,20 +413,79 @@ def p2p_leaf(layout, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=No
                                              nrm_p, nt, _ptr(trg), float(mu), ctypes.byref(rule.ex),
                                              ctypes.byref(rule.opts), _ptr(out), _ptr(ws), size, _stream(device)))
         return out
-    so, to, uo, ul = layout
-    for t, name, dt in ((so, "src_leaf_ofs", torch.int64), (to, "trg_leaf_ofs", torch.int64),
-                        (uo, "ulist_ofs", torch.int64), (ul, "ulist", torch.int32)):
-        if t.dtype != dt or t.dim() != 1 or t.device != device or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous 1-D {dt} tensor on the points' device")
-    n_leaves = so.numel() - 1
-    if n_leaves < 0 or to.numel() != n_leaves + 1 or uo.numel() != n_leaves + 1:
-        raise ValueError("the leaf offset arrays must all have n_leaves + 1 entries")
+    so, to, uo, ul, n_leaves = _device_layout(layout, device)
     ws, size = _workspace(op, ns, nt, n_leaves, rule.opts, device)
     C.check(C.lib().stokes_p2p_leaf_eval(context(device), k, ns, _ptr(src), _ptr(f), _ptr(w), nrm_p, nt, _ptr(trg),
                                          n_leaves, _ptr(so), _ptr(to), _ptr(uo), _ptr(ul), ul.numel(), float(mu),
                                          ctypes.byref(rule.ex), ctypes.byref(rule.opts), _ptr(out), _ptr(ws), size,
                                          _stream(device)))
     return out
+
+
+def p2p_sl_vjp(layout, src, f, w, trg, grad_u, mu=1.0, src_group=None, trg_group=None, exclude_same_group=None,
+               grad_f=None, grad_src=None, grad_trg=None, accumulate=False):
+    """Vector-Jacobian product of the single-layer leaf-to-leaf sum (see
+    stokes_p2p_sl_vjp): the adjoint sums over the pairs the lists name.
+
+    layout as for p2p_leaf (a P2PPlan's arrays are used on the device).  Writes
+    into the given (3, N) float64 tensors; any may be None, none may overlap."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(f, "f", device); _vec3(trg, "trg", device)
+    _vec3(grad_u, "grad_u", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    if f.shape[1] != ns or grad_u.shape[1] != nt:
+        raise ValueError("f must match src and grad_u must match trg")
+    so, to, uo, ul, n_leaves = _device_layout(layout, device)
+    rule = _Rule(device, ns, nt, src_group, trg_group, exclude_same_group, "fp64", None, 0.0)
+    rule.opts.accumulate = int(bool(accumulate))
+    gf, gs, gt = (_grad_out(grad_f, ns, "grad_f", device), _grad_out(grad_src, ns, "grad_src", device),
+                  _grad_out(grad_trg, nt, "grad_trg", device))
+    ws, size = _workspace(C.OP_P2P_SL_VJP, ns, nt, n_leaves, rule.opts, device, n_ulist=ul.numel())
+    C.check(C.lib().stokes_p2p_sl_vjp(context(device), ns, _ptr(src), _ptr(f), _ptr(w), nt, _ptr(trg), n_leaves,
+                                      _ptr(so), _ptr(to), _ptr(uo), _ptr(ul), ul.numel(), float(mu),
+                                      ctypes.byref(rule.ex), ctypes.byref(rule.opts), _ptr(grad_u), _ptr(gf),
+                                      _ptr(gs), _ptr(gt), _ptr(ws), size, _stream(device)))
+    return gf, gs, gt
+
+
+class StokesP2P(torch.autograd.Function):
+    """Single-layer leaf-to-leaf sum differentiable in the density and in both
+    point sets (weights are constants).  The backward runs the float64
+    adjoint over the same lists; on a shared point set autograd adds the
+    source-side and target-side position gradients."""
+
+    @staticmethod
+    def forward(ctx, layout, src, f, w, trg, mu, src_group, trg_group, exclude_same_group, precision, group_h,
+                near_frac):
+        u = p2p_leaf(layout, src, f, w, trg, kernel="sl", mu=mu, src_group=src_group, trg_group=trg_group,
+                     exclude_same_group=exclude_same_group, precision=precision, group_h=group_h,
+                     near_frac=near_frac)
+        ctx.save_for_backward(src, f, w, trg)
+        ctx.layout = layout
+        ctx.args = (mu, src_group, trg_group, exclude_same_group)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        src, f, w, trg = ctx.saved_tensors
+        mu, sg, tg, ex = ctx.args
+        need_src, need_f, need_trg = ctx.needs_input_grad[1], ctx.needs_input_grad[2], ctx.needs_input_grad[4]
+        grad_u = grad_u.contiguous()
+        gf = _empty3(src.shape[1], src) if need_f else None
+        gs = _empty3(src.shape[1], src) if need_src else None
+        gt = _empty3(trg.shape[1], trg) if need_trg else None
+        if gf is not None or gs is not None or gt is not None:
+            p2p_sl_vjp(ctx.layout, src, f, w, trg, grad_u, mu=mu, src_group=sg, trg_group=tg, exclude_same_group=ex,
+                       grad_f=gf, grad_src=gs, grad_trg=gt)
+        return None, gs, gf, None, gt, None, None, None, None, None, None, None
+
+
+def p2p_diff(layout, src, f, w, trg, mu=1.0, src_group=None, trg_group=None, exclude_same_group=None,
+             precision="fp64", group_h=None, near_frac=0.5):
+    """Differentiable single-layer leaf-to-leaf sum (torch.autograd)."""
+    return StokesP2P.apply(layout, src, f, w, trg, mu, src_group, trg_group, exclude_same_group, precision,
+                           group_h, near_frac)
 
 
 # ----------------------------------------------------------------------------
@@ -613,6 +698,13 @@ class FMMPlan:
     @property
     def handle(self):
         return self._h
+
+    def device_arrays(self):
+        """The layout as device tensors (src_leaf_ofs, trg_leaf_ofs, ulist_ofs,
+        ulist), uploaded on first use and kept."""
+        if getattr(self, "_dev", None) is None:
+            self._dev = tuple(torch.from_numpy(a).to(self.device) for a in (self._so, self._to, self._uo, self._ul))
+        return self._dev
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None

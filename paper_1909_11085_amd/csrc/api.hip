@@ -548,7 +548,7 @@ static bool sym_available(const stokes_ctx* ctx, int kernel, int mixed, int64_t 
 }
 
 int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int64_t n_trg,
-                          int32_t n_leaves, const stokes_opts* opts, size_t* bytes) {
+                          int32_t n_leaves, int64_t n_ulist, const stokes_opts* opts, size_t* bytes) {
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
     if (!bytes) return fail(STOKES_EINVAL, "bytes is NULL");
     int rc = check_sizes(n_src, n_trg);
@@ -573,6 +573,11 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
         case STOKES_OP_P2P_DL:
             if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
             *bytes = stokes::p2p_workspace_bytes(op == STOKES_OP_P2P_SL ? 0 : 1, mixed, n_src, n_trg, n_leaves);
+            return STOKES_OK;
+        case STOKES_OP_P2P_SL_VJP:
+            if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
+            if (n_ulist < 0) return fail(STOKES_EINVAL, "n_ulist must be >= 0");
+            *bytes = stokes::p2p_vjp_workspace_bytes(n_src, n_trg, n_leaves, n_ulist);
             return STOKES_OK;
         case STOKES_OP_SL_VJP:
         case STOKES_OP_DL_VJP:
@@ -825,6 +830,69 @@ int stokes_p2p_leaf_eval(stokes_ctx* ctx, int32_t kernel, int64_t n_src, const d
     return launch_status(stokes::launch_p2p_csr(in, n_leaves, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, n_ulist,
                                                 vel_out, p.accumulate, workspace, st, stokes::next_timer(ctx)),
                          "stokes_p2p_leaf_eval");
+}
+
+int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                      const double* weight, int64_t n_trg, const double* trg_xyz, int32_t n_leaves,
+                      const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs, const int64_t* ulist_ofs,
+                      const int32_t* ulist, int64_t n_ulist, double mu, const stokes_exclusion* excl,
+                      const stokes_opts* opts, const double* grad_vel, double* grad_density, double* grad_src_xyz,
+                      double* grad_trg_xyz, void* workspace, size_t ws_bytes, void* stream) {
+    const char* name = "stokes_p2p_sl_vjp";
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
+    if (n_ulist < 0 || n_ulist > INT32_MAX) return fail(STOKES_EINVAL, "n_ulist must be in [0, 2^31)");
+    int rc = check_sizes(n_src, n_trg);
+    if (rc) return rc;
+    rc = check_points(STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz);
+    if (rc) return rc;
+    if (!arr_ok(grad_vel, 3 * n_trg, 8) || (n_trg > 0 && !grad_vel))
+        return fail(STOKES_EINVAL, "grad_vel must be non-NULL and 8-byte aligned");
+    if (!arr_ok(src_leaf_ofs, (int64_t)n_leaves + 1, 8) || !arr_ok(trg_leaf_ofs, (int64_t)n_leaves + 1, 8) ||
+        !arr_ok(ulist_ofs, (int64_t)n_leaves + 1, 8))
+        return fail(STOKES_EINVAL, "src_leaf_ofs, trg_leaf_ofs and ulist_ofs must be non-NULL and 8-byte aligned");
+    if (!arr_ok(ulist, n_ulist, 4)) return fail(STOKES_EINVAL, "ulist must be non-NULL and 4-byte aligned");
+    for (const double* g : {(const double*)grad_density, (const double*)grad_src_xyz, (const double*)grad_trg_xyz})
+        if (g && !aligned(g, 8)) return fail(STOKES_EINVAL, "gradient outputs must be 8-byte aligned");
+    Parsed p;
+    if ((rc = parse_common(excl, opts, n_src, n_trg, p))) return rc;
+    const size_t sb = (size_t)3 * n_src * 8, tb = (size_t)3 * n_trg * 8, ob = (size_t)(n_leaves + 1) * 8;
+    struct Out { void* ptr; size_t bytes; const char* name; };
+    const Out outs[3] = {{grad_density, sb, "grad_density"}, {grad_src_xyz, sb, "grad_src_xyz"},
+                         {grad_trg_xyz, tb, "grad_trg_xyz"}};
+    for (int a = 0; a < 3; ++a) {
+        if (!outs[a].ptr) continue;
+        if ((rc = check_no_alias(outs[a].ptr, outs[a].bytes, outs[a].name,
+                                 {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {trg_xyz, tb},
+                                  {grad_vel, tb}, {workspace, ws_bytes}, {src_leaf_ofs, ob}, {trg_leaf_ofs, ob},
+                                  {ulist_ofs, ob}, {ulist, (size_t)n_ulist * 4}})))
+            return rc;
+        for (int b = a + 1; b < 3; ++b)
+            if (outs[b].ptr && overlaps(outs[a].ptr, outs[a].bytes, outs[b].ptr, outs[b].bytes))
+                return fail(STOKES_EINVAL, std::string(outs[a].name) + " overlaps " + outs[b].name);
+    }
+    rc = check_workspace(workspace, ws_bytes, stokes::p2p_vjp_workspace_bytes(n_src, n_trg, n_leaves, n_ulist));
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n_src == 0 || n_trg == 0) {            // zero gradients (kept when accumulating)
+        if (p.accumulate) return STOKES_OK;
+        hipError_t e = hipSuccess;
+        if (grad_density && e == hipSuccess) e = stokes::launch_fill_zero(grad_density, 3 * n_src, st);
+        if (grad_src_xyz && e == hipSuccess) e = stokes::launch_fill_zero(grad_src_xyz, 3 * n_src, st);
+        if (grad_trg_xyz && e == hipSuccess) e = stokes::launch_fill_zero(grad_trg_xyz, 3 * n_trg, st);
+        return launch_status(e, name);
+    }
+    Parsed pf = p;
+    pf.precision = STOKES_FP64;                // adjoints run in float64
+    stokes::SumInputs in = make_inputs(STOKES_KERNEL_SL, pf, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz,
+                                       1.0 / (8.0 * kPi * mu));
+    return launch_status(stokes::launch_p2p_sl_vjp(in, n_leaves, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist,
+                                                   n_ulist, grad_vel, grad_density, grad_src_xyz, grad_trg_xyz,
+                                                   p.accumulate, workspace, st),
+                         name);
 }
 
 static int vjp_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* src_xyz,

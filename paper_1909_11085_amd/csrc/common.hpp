@@ -70,6 +70,8 @@ struct SumInputs {
     // leaf-to-leaf sums: when set, target t's result goes to output column
     // trg_perm[t] (points sorted by an internal caller); a null weight is 1
     const int32_t* trg_perm;
+    // leaf-to-leaf kernel-gradient sums (kernel = 2): per-target vector (3, n_trg)
+    const double* trg_vec;
 };
 
 // class codes of pair_class (one pair taken once holds exactly one of them)

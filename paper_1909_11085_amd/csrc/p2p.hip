@@ -72,6 +72,8 @@ template <> struct P2PRec<0, 0> { using type = SrcSL64; };
 template <> struct P2PRec<1, 0> { using type = SrcDL64; };
 template <> struct P2PRec<0, 1> { using type = P2PSL32; };
 template <> struct P2PRec<1, 1> { using type = P2PDL32; };
+// kernel 2: the single layer's gradient sums (adjoint), float64 only
+template <> struct P2PRec<2, 0> { using type = SrcSL64; };
 
 struct P2PArgs {
     SumInputs in;
@@ -173,15 +175,28 @@ __device__ __forceinline__ double rinv(double r2, bool skip) {
     return __builtin_fma(0.5 * y0, e, y0);
 }
 
+// KT 0: q/rho + r (r.q)/rho^3; KT 1: r (r.n)(r.q)/rho^5; KT 2: the gradient in
+// r of a.S(r)b times 8 pi mu, with a = tv (the target's vector) and b = q:
+//   K(r; a, b) = [(r.b) a + (r.a) b - (a.b) r]/rho^3 - 3 (r.a)(r.b) r/rho^5.
 template <int KT, bool MASKED>
 __device__ __forceinline__ void pair64(const typename P2PRec<KT, 0>::type& s, double x, double y,
-                                       double z, bool skip_group, double& ax, double& ay, double& az) {
+                                       double z, const double (&tv)[3], bool skip_group, double& ax, double& ay,
+                                       double& az) {
     const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
     const double ri = rinv(r2, MASKED && (skip_group || r2 == 0.0));
     const double ri2 = ri * ri;
     const double rq = __builtin_fma(dx, s.qx, __builtin_fma(dy, s.qy, dz * s.qz));
-    if constexpr (KT == 0) {
+    if constexpr (KT == 2) {
+        const double ri3 = ri2 * ri;
+        const double ra = __builtin_fma(dx, tv[0], __builtin_fma(dy, tv[1], dz * tv[2]));
+        const double ab = __builtin_fma(tv[0], s.qx, __builtin_fma(tv[1], s.qy, tv[2] * s.qz));
+        const double sa = rq * ri3, sb = ra * ri3;
+        const double cr = -ri3 * __builtin_fma(3.0 * ra * rq, ri2, ab);
+        ax = __builtin_fma(sa, tv[0], __builtin_fma(sb, s.qx, __builtin_fma(cr, dx, ax)));
+        ay = __builtin_fma(sa, tv[1], __builtin_fma(sb, s.qy, __builtin_fma(cr, dy, ay)));
+        az = __builtin_fma(sa, tv[2], __builtin_fma(sb, s.qz, __builtin_fma(cr, dz, az)));
+    } else if constexpr (KT == 0) {
         const double c = rq * ri2;
         ax = __builtin_fma(__builtin_fma(c, dx, s.qx), ri, ax);
         ay = __builtin_fma(__builtin_fma(c, dy, s.qy), ri, ay);
@@ -282,6 +297,12 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     const int64_t idx = t0 + (valid ? ti : 0);        // idle lanes mirror target t0
     const int64_t nt = a.in.n_trg;
     const double x = a.in.trg_xyz[idx], y = a.in.trg_xyz[nt + idx], z = a.in.trg_xyz[2 * nt + idx];
+    double tv[3] = {0.0, 0.0, 0.0};                   // kernel 2: the target's vector
+    if constexpr (KT == 2) {
+        tv[0] = a.in.trg_vec[idx];
+        tv[1] = a.in.trg_vec[nt + idx];
+        tv[2] = a.in.trg_vec[2 * nt + idx];
+    }
     const int32_t tg = a.in.trg_group ? a.in.trg_group[idx] : 0;
     const bool excl = a.in.excl != 0;
 
@@ -415,9 +436,10 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
             if constexpr (MIXED == 0) {
                 const int32_t* gbk = s_grp + kb + h * m_back;
 #pragma unroll 4
-                for (int j = 0; j < m_clean; ++j) pair64<KT, false>(pc[j], x, y, z, false, ax, ay, az);
+                for (int j = 0; j < m_clean; ++j) pair64<KT, false>(pc[j], x, y, z, tv, false, ax, ay, az);
 #pragma unroll 2
-                for (int j = 0; j < m_back; ++j) pair64<KT, true>(pb[j], x, y, z, excl && gbk[j] == tg, ax, ay, az);
+                for (int j = 0; j < m_back; ++j)
+                    pair64<KT, true>(pb[j], x, y, z, tv, excl && gbk[j] == tg, ax, ay, az);
             } else {
                 float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll 4
@@ -524,6 +546,7 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
 }
 
 size_t rec_size(int kernel, int mixed) {
+    if (kernel == 2) return sizeof(P2PRec<2, 0>::type);
     if (!mixed) return kernel == 0 ? sizeof(P2PRec<0, 0>::type) : sizeof(P2PRec<1, 0>::type);
     return kernel == 0 ? sizeof(P2PRec<0, 1>::type) : sizeof(P2PRec<1, 1>::type);
 }
@@ -637,6 +660,7 @@ hipError_t run_p2p_typed(const SumInputs& in, const P2PItems& it, double* out, i
 
 hipError_t run_p2p_any(const SumInputs& in, const P2PItems& it, double* out, int accumulate, void* ws,
                        hipStream_t stream, const KernelTimer& timer) {
+    if (in.kernel == 2) return run_p2p_typed<2, 0>(in, it, out, accumulate, ws, stream, timer);
     if (in.kernel == 0)
         return in.mixed ? run_p2p_typed<0, 1>(in, it, out, accumulate, ws, stream, timer)
                         : run_p2p_typed<0, 0>(in, it, out, accumulate, ws, stream, timer);
@@ -653,6 +677,9 @@ constexpr uint64_t kItemKeyTop = (1ull << kItemKeyBits) - 1;
 
 __global__ __launch_bounds__(kP2PThreads) void p2p_set_i32(int32_t* p, int32_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+__global__ __launch_bounds__(kP2PThreads) void p2p_copy_i32(const int32_t* from, int32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = *from;
 }
 
 // The leaf arrays' contract: each offset array starts at 0, never decreases
@@ -775,7 +802,8 @@ hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* 
 
 hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
                           const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, double* out,
-                          int accumulate, void* ws, hipStream_t st, const KernelTimer& timer, bool check) {
+                          int accumulate, void* ws, hipStream_t st, const KernelTimer& timer, bool check,
+                          const int32_t* ext_status) {
     const P2PLayout l = p2p_layout(in.kernel, in.mixed, in.n_src, in.n_trg, n_leaves);
     char* base = static_cast<char*>(ws);
     int32_t* status = reinterpret_cast<int32_t*>(base + l.off_status);
@@ -788,7 +816,10 @@ hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* 
     int32_t* sorted = reinterpret_cast<int32_t*>(base + l.off_sorted);
     hipError_t e;
     auto chk = [&]() { return (e = hipGetLastError()) == hipSuccess; };
-    p2p_set_i32<<<1, kP2PThreads, 0, st>>>(status, 0);
+    if (ext_status)
+        p2p_copy_i32<<<1, kP2PThreads, 0, st>>>(ext_status, status);
+    else
+        p2p_set_i32<<<1, kP2PThreads, 0, st>>>(status, 0);
     if (!chk()) return e;
     if (check) {
         p2p_csr_check<<<p2p_grid(std::max<int64_t>((int64_t)n_leaves + 1, n_ulist)), kP2PThreads, 0, st>>>(
@@ -817,6 +848,225 @@ hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* 
     }
     p2p_poison<<<p2p_grid(3 * in.n_trg), kP2PThreads, 0, st>>>(status, out, 3 * in.n_trg);
     chk();
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// the layout check on its own, and the transposed lists (adjoint sums)
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ __launch_bounds__(kP2PThreads) void p2p_t_init(int64_t nu, uint64_t* __restrict__ keys,
+                                                          int32_t* __restrict__ vals) {
+    for (int64_t k = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; k < nu; k += (int64_t)gridDim.x * kP2PThreads) {
+        keys[k] = 0;
+        vals[k] = 0;
+    }
+}
+
+// entry k of leaf L's list: key = the listed leaf, value = L
+__global__ __launch_bounds__(kP2PThreads) void p2p_t_keys(const int64_t* __restrict__ uo,
+                                                          const int32_t* __restrict__ ul, int32_t nl,
+                                                          const int32_t* __restrict__ status,
+                                                          uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+    if (*status != 0) return;                          // malformed: every entry stays at leaf 0
+    for (int64_t L = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; L < nl; L += (int64_t)gridDim.x * kP2PThreads)
+        for (int64_t k = uo[L]; k < uo[L + 1]; ++k) {
+            keys[k] = (uint64_t)ul[k];
+            vals[k] = (int32_t)L;
+        }
+}
+
+// ofs[g] = first sorted position whose key is >= g, g in [0, nl]
+__global__ __launch_bounds__(kP2PThreads) void p2p_t_offsets(const uint64_t* __restrict__ keys, int64_t n, int32_t nl,
+                                                             int64_t* __restrict__ ofs) {
+    for (int64_t i = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; i <= n; i += (int64_t)gridDim.x * kP2PThreads) {
+        const int64_t kp = i == 0 ? -1 : (int64_t)keys[i - 1];
+        const int64_t kc = i == n ? (int64_t)nl : (int64_t)keys[i];
+        for (int64_t g = kp + 1; g <= kc; ++g) ofs[g] = i;
+    }
+}
+
+int p2p_key_bits(int32_t nl) {
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < nl) ++b;
+    return b;
+}
+
+struct TransposeLayout {
+    SortLayout sort;
+    size_t off_keys, off_sort, total;
+};
+TransposeLayout transpose_layout(int64_t nu) {
+    TransposeLayout l{};
+    l.sort = sort_layout(std::max<int64_t>(nu, 1));
+    size_t off = 0;
+    l.off_keys = off;
+    off = align_up(off + (size_t)std::max<int64_t>(nu, 1) * 8, 256);
+    l.off_sort = off;
+    off = align_up(off + l.sort.total, 256);
+    l.total = off;
+    return l;
+}
+
+}  // namespace
+
+hipError_t launch_p2p_check(int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                            const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_src, int64_t n_trg,
+                            int64_t n_ulist, int32_t* status, hipStream_t st) {
+    p2p_set_i32<<<1, kP2PThreads, 0, st>>>(status, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    p2p_csr_check<<<p2p_grid(std::max<int64_t>((int64_t)n_leaves + 1, n_ulist)), kP2PThreads, 0, st>>>(
+        src_ofs, trg_ofs, ulist_ofs, ulist, n_leaves, n_src, n_trg, n_ulist, status);
+    return hipGetLastError();
+}
+
+size_t p2p_transpose_bytes(int64_t n_ulist) { return transpose_layout(n_ulist).total; }
+
+hipError_t launch_p2p_transpose(int32_t n_leaves, const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist,
+                                const int32_t* status, int64_t* ulist_ofs_t, int32_t* ulist_t, void* ws,
+                                hipStream_t st) {
+    const TransposeLayout l = transpose_layout(n_ulist);
+    uint64_t* keys = reinterpret_cast<uint64_t*>(static_cast<char*>(ws) + l.off_keys);
+    hipError_t e;
+    auto chk = [&]() { return (e = hipGetLastError()) == hipSuccess; };
+    if (n_ulist > 0) {
+        p2p_t_init<<<p2p_grid(n_ulist), kP2PThreads, 0, st>>>(n_ulist, keys, ulist_t);
+        if (!chk()) return e;
+        if (n_leaves > 0) {
+            p2p_t_keys<<<p2p_grid(n_leaves), kP2PThreads, 0, st>>>(ulist_ofs, ulist, n_leaves, status, keys, ulist_t);
+            if (!chk()) return e;
+        }
+        if ((e = radix_sort_pairs(keys, ulist_t, n_ulist, p2p_key_bits(n_leaves), static_cast<char*>(ws) + l.off_sort,
+                                  l.sort, st)) != hipSuccess)
+            return e;
+    }
+    p2p_t_offsets<<<p2p_grid(n_ulist + 1), kP2PThreads, 0, st>>>(keys, n_ulist, n_leaves, ulist_ofs_t);
+    chk();
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// single-layer adjoint of the leaf-to-leaf sum (float64)
+//   dL/dx_n = c sum_m K(r_nm; g_n, q_m)          target side, the forward lists
+//   dL/df_m = c w_m sum_n S(r_nm) g_n            transposed lists (S even in r)
+//   dL/dy_m = c sum_n K(r_mn; q_m, g_n)          transposed lists (K odd in r,
+//                                                symmetric in its two vectors)
+// with r_nm = x_n - y_m, q_m = w_m f_m, g_n = dL/du_n, c the forward's prefactor;
+// the sums over n run over the targets of the leaves whose lists hold m's leaf.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct P2PVjpLayout {
+    size_t off_status, off_uot, off_ult, off_tws, off_q, off_tmp, off_p2p, total;
+};
+
+P2PVjpLayout p2p_vjp_layout(int64_t ns, int64_t nt, int32_t nl, int64_t nu) {
+    P2PVjpLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t& o, size_t bytes) {
+        o = off;
+        off = align_up(off + std::max<size_t>(bytes, 8), 256);
+    };
+    take(l.off_status, sizeof(int32_t));
+    take(l.off_uot, (size_t)(nl + 1) * 8);
+    take(l.off_ult, (size_t)nu * 4);
+    take(l.off_tws, p2p_transpose_bytes(nu));
+    take(l.off_q, (size_t)ns * 24);
+    take(l.off_tmp, (size_t)ns * 24);
+    const size_t p = std::max({p2p_workspace_bytes(2, 0, ns, nt, nl), p2p_workspace_bytes(0, 0, nt, ns, nl),
+                               p2p_workspace_bytes(2, 0, nt, ns, nl)});
+    take(l.off_p2p, p);
+    l.total = off;
+    return l;
+}
+
+// q = w f, (3, n)
+__global__ __launch_bounds__(kP2PThreads) void p2p_times_w(const double* __restrict__ w, const double* __restrict__ f,
+                                                           int64_t n, double* __restrict__ q) {
+    for (int64_t i = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kP2PThreads)
+        for (int c = 0; c < 3; ++c) q[c * n + i] = w[i] * f[c * n + i];
+}
+
+// out (=|+=) w v, (3, n)
+__global__ __launch_bounds__(kP2PThreads) void p2p_add_times_w(const double* __restrict__ w,
+                                                               const double* __restrict__ v, int64_t n,
+                                                               double* __restrict__ out, int accumulate) {
+    for (int64_t i = (int64_t)blockIdx.x * kP2PThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kP2PThreads)
+        for (int c = 0; c < 3; ++c) {
+            const double val = w[i] * v[c * n + i];
+            out[c * n + i] = accumulate ? out[c * n + i] + val : val;
+        }
+}
+
+}  // namespace
+
+size_t p2p_vjp_workspace_bytes(int64_t n_src, int64_t n_trg, int32_t n_leaves, int64_t n_ulist) {
+    if (n_src <= 0 || n_trg <= 0) return 0;
+    return p2p_vjp_layout(n_src, n_trg, n_leaves, n_ulist).total;
+}
+
+hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                             const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, const double* grad_vel,
+                             double* grad_density, double* grad_src, double* grad_trg, int accumulate, void* ws,
+                             hipStream_t st) {
+    const int64_t ns = in.n_src, nt = in.n_trg;
+    const P2PVjpLayout l = p2p_vjp_layout(ns, nt, n_leaves, n_ulist);
+    char* base = static_cast<char*>(ws);
+    int32_t* status = reinterpret_cast<int32_t*>(base + l.off_status);
+    const KernelTimer none{};
+    hipError_t e = launch_p2p_check(n_leaves, src_ofs, trg_ofs, ulist_ofs, ulist, ns, nt, n_ulist, status, st);
+    if (e != hipSuccess) return e;
+    if (grad_trg) {
+        SumInputs t = in;
+        t.kernel = 2;
+        t.mixed = 0;
+        t.trg_vec = grad_vel;
+        t.pair_class = nullptr;
+        e = launch_p2p_csr(t, n_leaves, src_ofs, trg_ofs, ulist_ofs, ulist, n_ulist, grad_trg, accumulate,
+                           base + l.off_p2p, st, none, false, status);
+        if (e != hipSuccess) return e;
+    }
+    if (!grad_density && !grad_src) return hipSuccess;
+    int64_t* uot = reinterpret_cast<int64_t*>(base + l.off_uot);
+    int32_t* ult = reinterpret_cast<int32_t*>(base + l.off_ult);
+    if ((e = launch_p2p_transpose(n_leaves, ulist_ofs, ulist, n_ulist, status, uot, ult, base + l.off_tws, st)) !=
+        hipSuccess)
+        return e;
+    // the transposed sums: the forward's sources are the targets, its targets
+    // (carrying g, unit weights) the sources; the pair rule's groups swap
+    SumInputs tr{};
+    tr.n_src = nt;
+    tr.src_xyz = in.trg_xyz;
+    tr.density = grad_vel;
+    tr.weight = nullptr;
+    tr.n_trg = ns;
+    tr.trg_xyz = in.src_xyz;
+    tr.excl = in.excl;
+    tr.src_group = in.trg_group;
+    tr.trg_group = in.src_group;
+    tr.pref = in.pref;
+    if (grad_density) {
+        double* tmp = reinterpret_cast<double*>(base + l.off_tmp);
+        SumInputs f = tr;
+        f.kernel = 0;
+        e = launch_p2p_csr(f, n_leaves, trg_ofs, src_ofs, uot, ult, n_ulist, tmp, 0, base + l.off_p2p, st, none, false,
+                           status);
+        if (e != hipSuccess) return e;
+        p2p_add_times_w<<<p2p_grid(ns), kP2PThreads, 0, st>>>(in.weight, tmp, ns, grad_density, accumulate);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (grad_src) {
+        double* q = reinterpret_cast<double*>(base + l.off_q);
+        p2p_times_w<<<p2p_grid(ns), kP2PThreads, 0, st>>>(in.weight, in.density, ns, q);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        SumInputs y = tr;
+        y.kernel = 2;
+        y.trg_vec = q;
+        e = launch_p2p_csr(y, n_leaves, trg_ofs, src_ofs, uot, ult, n_ulist, grad_src, accumulate, base + l.off_p2p,
+                           st, none, false, status);
+    }
     return e;
 }
 

@@ -28,6 +28,31 @@ hipError_t launch_p2p(const SumInputs& in, const stokes_p2p_plan* plan, double* 
 hipError_t launch_p2p_csr(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
                           const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, double* out,
                           int accumulate, void* ws, hipStream_t stream, const KernelTimer& timer,
-                          bool check = true);
+                          bool check = true, const int32_t* ext_status = nullptr);
+// (ext_status, with check = false: the verdict of an earlier launch_p2p_check.)
+
+// Clears *status and sets it when the device leaf arrays break the layout's
+// rules (the checks of launch_p2p_csr).
+hipError_t launch_p2p_check(int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                            const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_src, int64_t n_trg,
+                            int64_t n_ulist, int32_t* status, hipStream_t stream);
+
+// The transposed lists: leaf L' lists, in increasing order and with
+// multiplicity, the leaves whose lists hold L' (n_ulist entries; offsets
+// n_leaves + 1).  With *status set, every entry goes to leaf 0 (nothing
+// outside the arrays is read).  Workspace p2p_transpose_bytes(n_ulist).
+size_t p2p_transpose_bytes(int64_t n_ulist);
+
+// Single-layer adjoint of the leaf-to-leaf sum (float64): each output may be
+// null; in holds the forward's inputs (kernel 0, pref, pair rule).  The
+// device leaf arrays are checked; malformed ones make the outputs NaN.
+size_t p2p_vjp_workspace_bytes(int64_t n_src, int64_t n_trg, int32_t n_leaves, int64_t n_ulist);
+hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                             const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, const double* grad_vel,
+                             double* grad_density, double* grad_src, double* grad_trg, int accumulate, void* ws,
+                             hipStream_t stream);
+hipError_t launch_p2p_transpose(int32_t n_leaves, const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist,
+                                const int32_t* status, int64_t* ulist_ofs_t, int32_t* ulist_t, void* ws,
+                                hipStream_t stream);
 
 }  // namespace stokes

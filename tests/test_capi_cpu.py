@@ -40,7 +40,7 @@ def test_null_context_is_rejected():
     assert rc == C.EINVAL
     assert b"ctx" in L.stokes_last_error()
     size = ctypes.c_size_t()
-    assert L.stokes_workspace_size(None, C.OP_SL, 10, 10, 0, None, ctypes.byref(size)) == C.EINVAL
+    assert L.stokes_workspace_size(None, C.OP_SL, 10, 10, 0, 0, None, ctypes.byref(size)) == C.EINVAL
     assert L.stokes_set_grid_override(None, 2) == C.EINVAL
     assert L.stokes_create(None, 0) == C.EINVAL
     L.stokes_destroy(None)          # no-op

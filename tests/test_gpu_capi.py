@@ -41,10 +41,10 @@ def _data():
     return d
 
 
-def _ws(ctx, op, ns=NS, nt=NT, precision=C.FP64, n_leaves=0):
+def _ws(ctx, op, ns=NS, nt=NT, precision=C.FP64, n_leaves=0, n_ulist=0):
     size = ctypes.c_size_t()
     opts = C.Opts(precision, 0)
-    assert C.lib().stokes_workspace_size(ctx, op, ns, nt, n_leaves, ctypes.byref(opts),
+    assert C.lib().stokes_workspace_size(ctx, op, ns, nt, n_leaves, n_ulist, ctypes.byref(opts),
                                          ctypes.byref(size)) == C.OK
     ws = torch.empty(size.value + 512, dtype=torch.uint8, device="cuda")
     assert ws.data_ptr() % 256 == 0
@@ -222,5 +222,5 @@ def test_context_settings(ctx):
     assert L.stokes_set_grid_override(ctx, 0) == C.OK
     assert L.stokes_timing_read(ctx, None, None) == C.EINVAL
     size = ctypes.c_size_t()
-    assert L.stokes_workspace_size(ctx, 9, NS, NT, 0, None, ctypes.byref(size)) == C.EINVAL
-    assert L.stokes_workspace_size(ctx, C.OP_SL, NS, NT, 0, None, None) == C.EINVAL
+    assert L.stokes_workspace_size(ctx, 9, NS, NT, 0, 0, None, ctypes.byref(size)) == C.EINVAL
+    assert L.stokes_workspace_size(ctx, C.OP_SL, NS, NT, 0, 0, None, None) == C.EINVAL

@@ -1,0 +1,251 @@
+"""GPU parity of the single-layer leaf-to-leaf adjoint against the FP64 oracle.
+
+The oracle's adjoint takes every target leaf's direct adjoint over the
+sources of its list and scatters the source-side parts back; the library runs
+one pass on the forward lists (target side) and one per source-side output on
+the lists transposed on the device.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1909_11085_amd as S
+from oracle import oracle as O
+from paper_1909_11085_amd import _capi as C
+from paper_1909_11085_amd import workloads as W
+from tests.gpu_util import FP64_TOL, assert_close, dev, device, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed, n_cells=8, distinct=True, repeat=True):
+    """Cells sorted into octree leaves; random nearest-leaf lists.  With
+    distinct, the targets are every other point moved a little (their own
+    leaf offsets, some leaves without targets); with repeat, the longest list
+    names one leaf twice."""
+    rng = np.random.default_rng(seed)
+    cells = W.place_cells(rng, n_cells, ("box", 18.0), order=8)
+    lo = cells.pos.min(1) - 1e-3
+    side = float((cells.pos.max(1) - lo).max()) + 1e-3
+    tree = W.build_octree(cells.pos, lo, side, max_leaf=48)
+    p = tree.perm
+    y, w, g = cells.pos[:, p].copy(), cells.weight[p].copy(), cells.group[p].copy()
+    f = rng.standard_normal((3, cells.n))
+    ofs, ul = W.nearest_leaf_lists(rng, tree, kmin=3, kmax=12)
+    if repeat:
+        L = int(np.argmax(np.diff(ofs)))
+        ul = np.insert(ul, ofs[L], ul[ofs[L]])
+        ofs = ofs.copy()
+        ofs[L + 1:] += 1
+    so = tree.leaf_ofs.astype(np.int64)
+    if distinct:
+        sel = np.arange(0, cells.n, 3)
+        x = y[:, sel] + 0.05 * rng.standard_normal((3, sel.size))
+        to = np.searchsorted(sel, so).astype(np.int64)
+        gt = g[sel].copy()
+    else:
+        x, to, gt = y, so, g
+    gu = rng.standard_normal((3, x.shape[1]))
+    return dict(y=y, f=f, w=w, gs=g, x=x, gt=gt, so=so, to=to, ofs=ofs.astype(np.int64), ul=ul.astype(np.int32),
+                gu=gu)
+
+
+def _layout(d):
+    return dev(d["so"]), dev(d["to"]), dev(d["ofs"]), dev(d["ul"])
+
+
+def _oracle(d, mu, excl):
+    return O.p2p_sl_vjp(d["y"], d["f"], d["w"], d["x"], d["gu"], d["so"], d["to"], d["ofs"], d["ul"], mu=mu,
+                        src_group=d["gs"], trg_group=d["gt"], exclude_same_group=excl)
+
+
+def _gpu(d, mu, excl, layout=None, want=("f", "src", "trg"), accumulate=False, outs=None):
+    ns, nt = d["y"].shape[1], d["x"].shape[1]
+    if outs is None:
+        outs = [torch.zeros((3, n), dtype=torch.float64, device=device()) if k in want else None
+                for k, n in (("f", ns), ("src", ns), ("trg", nt))]
+    y = dev(d["y"])
+    x = y if d["x"] is d["y"] else dev(d["x"])
+    S.p2p_sl_vjp(layout if layout is not None else _layout(d), y, dev(d["f"]), dev(d["w"]), x, dev(d["gu"]),
+                 mu=mu, src_group=dev(d["gs"]), trg_group=dev(d["gt"]), exclude_same_group=excl,
+                 grad_f=outs[0], grad_src=outs[1], grad_trg=outs[2], accumulate=accumulate)
+    return outs
+
+
+@pytest.mark.parametrize("excl", [True, False])
+@pytest.mark.parametrize("distinct", [True, False])
+def test_p2p_sl_vjp_matches_oracle(excl, distinct):
+    print(f"case p2p sl vjp excl={excl} distinct={distinct}", flush=True)
+    d = _case(51 + 2 * int(excl) + int(distinct), distinct=distinct)
+    got = _gpu(d, 1.3, excl)
+    ref = _oracle(d, 1.3, excl)
+    for name, a, b in zip(("grad_f", "grad_src", "grad_trg"), got, ref):
+        assert_close(host(a), b, FP64_TOL, f"p2p sl vjp {name} excl={excl} distinct={distinct}")
+
+
+def test_p2p_sl_vjp_each_output_alone_and_accumulate():
+    """Each output asked for alone equals its value in the full call, bit for
+    bit; accumulate adds onto what the outputs hold."""
+    print("case p2p sl vjp single outputs", flush=True)
+    d = _case(57)
+    full = [host(t) for t in _gpu(d, 0.9, True)]
+    for k, name in enumerate(("f", "src", "trg")):
+        alone = _gpu(d, 0.9, True, want=(name,))
+        assert np.array_equal(host(alone[k]), full[k]), name
+        assert all(alone[j] is None for j in range(3) if j != k)
+    base = [np.full(a.shape, 0.25) for a in full]
+    acc = _gpu(d, 0.9, True, accumulate=True, outs=[dev(b.copy()) for b in base])
+    for a, b, ref in zip(acc, base, full):
+        assert np.allclose(host(a) - b, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+
+
+def test_p2p_sl_vjp_deterministic_and_plan_layout():
+    """Two calls agree bit for bit; a P2PPlan's arrays give the same result as
+    the device tensors."""
+    print("case p2p sl vjp determinism", flush=True)
+    d = _case(58, n_cells=10)
+    a = [host(t) for t in _gpu(d, 1.0, True)]
+    b = [host(t) for t in _gpu(d, 1.0, True)]
+    plan = S.P2PPlan(d["so"], d["to"], d["ofs"], d["ul"], d["y"].shape[1], d["x"].shape[1])
+    c = [host(t) for t in _gpu(d, 1.0, True, layout=plan)]
+    for u, v, z in zip(a, b, c):
+        assert np.array_equal(u, v) and np.array_equal(u, z)
+
+
+def test_p2p_sl_vjp_uneven_layout():
+    """Empty leaves, leaves with sources but no targets, a repeated entry,
+    sources listed by no leaf (zero source-side gradient)."""
+    print("case p2p sl vjp uneven layout", flush=True)
+    rng = np.random.default_rng(59)
+    ns, nt = 300, 200
+    d = dict(y=rng.standard_normal((3, ns)) * 3, x=rng.standard_normal((3, nt)) * 3, f=rng.standard_normal((3, ns)),
+             w=rng.uniform(0.5, 1, ns), gs=rng.integers(0, 5, ns).astype(np.int32),
+             gt=rng.integers(0, 5, nt).astype(np.int32), gu=rng.standard_normal((3, nt)),
+             so=np.array([0, 0, 100, 100, 250, 300], dtype=np.int64),
+             to=np.array([0, 50, 50, 120, 200, 200], dtype=np.int64),
+             ofs=np.array([0, 3, 3, 5, 9, 10], dtype=np.int64),
+             ul=np.array([1, 1, 4, 1, 1, 0, 1, 1, 4, 2], dtype=np.int32))   # leaf 3 (sources 100..250) unlisted
+    got = _gpu(d, 1.1, True)
+    ref = _oracle(d, 1.1, True)
+    for name, a, b in zip(("grad_f", "grad_src", "grad_trg"), got, ref):
+        assert_close(host(a), b, FP64_TOL, f"uneven {name}")
+    assert np.all(host(got[0])[:, 100:250] == 0.0) and np.all(host(got[1])[:, 100:250] == 0.0)
+
+
+def test_p2p_sl_vjp_malformed_gives_nan():
+    """The leaf arrays are checked on the device as for the forward sum: a
+    breach makes every requested output NaN, also when accumulating."""
+    print("case p2p sl vjp malformed", flush=True)
+    rng = np.random.default_rng(60)
+    y, x = dev(rng.standard_normal((3, 10))), dev(rng.standard_normal((3, 8)))
+    f, w, gu = dev(rng.standard_normal((3, 10))), dev(rng.uniform(0.5, 1, 10)), dev(rng.standard_normal((3, 8)))
+    ok = dict(so=np.array([0, 5, 10]), to=np.array([0, 4, 8]), uo=np.array([0, 1, 2]), ul=np.array([0, 1]))
+    bad = [dict(ok, so=np.array([1, 5, 10])), dict(ok, to=np.array([0, 6, 4])), dict(ok, uo=np.array([0, 1, 3])),
+           dict(ok, ul=np.array([0, 2])), dict(ok, ul=np.array([-1, 1]))]
+    lay = lambda b: (dev(b["so"].astype(np.int64)), dev(b["to"].astype(np.int64)), dev(b["uo"].astype(np.int64)),
+                     dev(b["ul"].astype(np.int32)))
+    outs = lambda: [dev(np.zeros((3, 10))), dev(np.zeros((3, 10))), dev(np.zeros((3, 8)))]
+    good = S.p2p_sl_vjp(lay(ok), y, f, w, x, gu, grad_f=outs()[0], grad_src=outs()[1], grad_trg=outs()[2])
+    assert all(np.all(np.isfinite(host(t))) for t in good)
+    for b in bad:
+        o = outs()
+        S.p2p_sl_vjp(lay(b), y, f, w, x, gu, grad_f=o[0], grad_src=o[1], grad_trg=o[2], accumulate=True)
+        assert all(np.all(np.isnan(host(t))) for t in o), b
+
+
+def test_p2p_sl_vjp_rejects_bad_arguments():
+    """Overlapping outputs, an output aliasing an input and a short workspace
+    are refused before any launch; empty sets give zeros."""
+    print("case p2p sl vjp rejections", flush=True)
+    d = _case(61, n_cells=3)
+    ns, nt = d["y"].shape[1], d["x"].shape[1]
+    y, x, f, w, gu = dev(d["y"]), dev(d["x"]), dev(d["f"]), dev(d["w"]), dev(d["gu"])
+    lay = _layout(d)
+    g3 = torch.zeros((3, ns), dtype=torch.float64, device=device())
+    with pytest.raises(C.StokesError) as e:
+        S.p2p_sl_vjp(lay, y, f, w, x, gu, grad_f=g3, grad_src=g3)
+    assert e.value.status == C.EINVAL
+    with pytest.raises(C.StokesError) as e:
+        S.p2p_sl_vjp(lay, y, f, w, x, gu, grad_f=f)
+    assert e.value.status == C.EINVAL
+    L, ctx = C.lib(), S.context(device())
+    size = ctypes.c_size_t()
+    opts = C.Opts(C.FP64, 0)
+    assert L.stokes_workspace_size(ctx, C.OP_P2P_SL_VJP, ns, nt, len(d["so"]) - 1, len(d["ul"]),
+                                   ctypes.byref(opts), ctypes.byref(size)) == C.OK
+    assert size.value > 0
+    ws = torch.empty(size.value, dtype=torch.uint8, device=device())
+    ex = C.Exclusion(C.EXCL_NONE, None, None, None, 0, 0.0)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    args = lambda nbytes: (ctx, ns, p(y), p(f), p(w), nt, p(x), len(d["so"]) - 1, p(lay[0]), p(lay[1]), p(lay[2]),
+                           p(lay[3]), len(d["ul"]), 1.0, ctypes.byref(ex), ctypes.byref(opts), p(gu), p(g3), None,
+                           None, p(ws), nbytes, None)
+    assert L.stokes_p2p_sl_vjp(*args(size.value - 1)) == C.EWORKSPACE
+    assert L.stokes_p2p_sl_vjp(*args(size.value)) == C.OK
+    torch.cuda.synchronize()
+    # no sources: zero gradients at the targets
+    empty = torch.zeros((3, 0), dtype=torch.float64, device=device())
+    gt = torch.full((3, nt), 7.0, dtype=torch.float64, device=device())
+    z = (dev(np.zeros(2, np.int64)), dev(np.array([0, nt], np.int64)), dev(np.zeros(2, np.int64)),
+         dev(np.zeros(0, np.int32)))
+    S.p2p_sl_vjp(z, empty, empty, torch.zeros(0, dtype=torch.float64, device=device()), x, gu, grad_trg=gt)
+    assert np.all(host(gt) == 0.0)
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_p2p_diff_autograd(shared):
+    """torch.autograd through p2p_diff gives the oracle's adjoint; on a shared
+    point set the position gradient is the sum of both sides."""
+    print(f"case p2p diff autograd shared={shared}", flush=True)
+    d = _case(62 + int(shared), n_cells=5, distinct=not shared)
+    lay = _layout(d)
+    y = dev(d["y"]).requires_grad_(True)
+    f = dev(d["f"]).requires_grad_(True)
+    x = y if shared else dev(d["x"]).requires_grad_(True)
+    u = S.p2p_diff(lay, y, f, dev(d["w"]), x, mu=0.7, src_group=dev(d["gs"]), trg_group=dev(d["gt"]))
+    u.backward(dev(d["gu"]))
+    gf, gy, gx = _oracle(d, 0.7, True)
+    assert_close(host(f.grad), gf, FP64_TOL, "autograd grad_f")
+    if shared:
+        assert_close(host(y.grad), gy + gx, FP64_TOL, "autograd shared position gradient")
+    else:
+        assert_close(host(y.grad), gy, FP64_TOL, "autograd grad_src")
+        assert_close(host(x.grad), gx, FP64_TOL, "autograd grad_trg")
+
+
+def test_p2p_sl_vjp_graph_capture():
+    """No host round trip and no memset: captured once, replayed three times
+    with eager work between, each replay bitwise equal to the eager result."""
+    print("case p2p sl vjp graph capture", flush=True)
+    d = _case(64)
+    lay = _layout(d)
+    y, x, f, w, gu = dev(d["y"]), dev(d["x"]), dev(d["f"]), dev(d["w"]), dev(d["gu"])
+    gs, gt = dev(d["gs"]), dev(d["gt"])
+    outs = [torch.empty_like(y), torch.empty_like(y), torch.empty_like(x)]
+
+    def run(o):
+        S.p2p_sl_vjp(lay, y, f, w, x, gu, src_group=gs, trg_group=gt, grad_f=o[0], grad_src=o[1], grad_trg=o[2])
+
+    eager = [torch.empty_like(t) for t in outs]
+    run(eager)
+    eager = [host(t) for t in eager]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run(outs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run(outs)
+    for k in range(3):
+        for t in outs:
+            t.fill_(float(k + 3))
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, eager):
+            assert np.array_equal(host(a), b), k
+        run([torch.empty_like(t) for t in outs])
+        torch.cuda.synchronize()

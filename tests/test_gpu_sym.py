@@ -108,9 +108,9 @@ def test_small_workspace_takes_the_one_sided_path():
     P, F, Wt, G = dev(pos), dev(f), dev(w), dev(g)
     L, ctx = C.lib(), S.context()
     op, size_sh = C.Opts(C.FP64, 0), ctypes.c_size_t()
-    assert L.stokes_workspace_size(ctx, C.OP_SL, n, n, 0, ctypes.byref(op), ctypes.byref(size_sh)) == C.OK
+    assert L.stokes_workspace_size(ctx, C.OP_SL, n, n, 0, 0, ctypes.byref(op), ctypes.byref(size_sh)) == C.OK
     size_1 = ctypes.c_size_t()
-    assert L.stokes_workspace_size(ctx, C.OP_SL, n, n + 1, 0, ctypes.byref(op), ctypes.byref(size_1)) == C.OK
+    assert L.stokes_workspace_size(ctx, C.OP_SL, n, n + 1, 0, 0, ctypes.byref(op), ctypes.byref(size_1)) == C.OK
     assert size_sh.value > size_1.value
     ws = torch.empty(size_1.value, dtype=torch.uint8, device=device())
     out = torch.empty((3, n), dtype=torch.float64, device=device())

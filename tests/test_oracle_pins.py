@@ -11,6 +11,9 @@ Each pin targets a plausible mistake:
   * P2P with full lists == direct          -> leaf indexing
   * central differences, dot tests, zero divergence, translation invariance of
     the loss                               -> the vector-Jacobian products
+  * P2P adjoint with full lists == direct adjoint, central differences of the
+    P2P sum (repeated list entries, distinct targets) -> the adjoint's
+    scatter over the lists
 """
 import math
 import os
@@ -431,3 +434,62 @@ def test_vjp_translation_invariance(kernel):
         _, gy, gx = O.dl_vjp(c.pos, f, c.weight, c.normal, c.pos, u - u_ref, **kw)
     tot = gy.sum(1) + gx.sum(1)
     assert np.abs(tot).max() < 1e-12 * np.abs(gx).sum()
+
+
+# ---------------------------------------------------------------- P2P adjoint
+def test_p2p_sl_vjp_full_lists_equal_direct():
+    """Every leaf listing every leaf: the leaf-by-leaf adjoint is the direct
+    adjoint (same pairs)."""
+    rng, tree, pos, f, w, g, nrm = _small_tree(seed=23)
+    nl = len(tree.leaf_ofs) - 1
+    uofs = np.arange(nl + 1, dtype=np.int64) * nl
+    ul = np.tile(np.arange(nl, dtype=np.int32), nl)
+    gu = rng.standard_normal(pos.shape)
+    kw = dict(src_group=g, trg_group=g, exclude_same_group=True)
+    a = O.p2p_sl_vjp(pos, f, w, pos, gu, tree.leaf_ofs, tree.leaf_ofs, uofs, ul, mu=1.3, **kw)
+    b = O.sl_vjp(pos, f, w, pos, gu, mu=1.3, **kw)
+    for got, ref in zip(a, b):
+        assert rel(got, ref) < 1e-13
+
+
+def _p2p_distinct_targets(seed):
+    """A shared tree; the targets are every other point, moved a little, so
+    each leaf's targets and sources differ; one list repeats an entry."""
+    rng, tree, pos, f, w, g, nrm = _small_tree(seed=seed)
+    sel = np.arange(0, pos.shape[1], 2)
+    x = pos[:, sel] + 0.05 * rng.standard_normal((3, sel.size))
+    to = np.searchsorted(sel, tree.leaf_ofs).astype(np.int64)
+    ofs, ul = W.nearest_leaf_lists(rng, tree, kmin=2, kmax=5)
+    L = int(np.argmax(np.diff(ofs)))                      # repeat an entry of the longest list
+    ul = np.insert(ul, ofs[L], ul[ofs[L]]).astype(np.int32)
+    ofs = ofs.copy()
+    ofs[L + 1:] += 1
+    k = int(ul[ofs[L]])
+    return rng, tree, pos, f, w, g, x, g[sel], to, ofs, ul, np.arange(tree.leaf_ofs[k], tree.leaf_ofs[k + 1])
+
+
+def test_p2p_sl_vjp_central_differences():
+    rng, tree, y, f, w, gs, x, gt, to, ofs, ul, dup = _p2p_distinct_targets(24)
+    so = tree.leaf_ofs
+    kw = dict(src_group=gs, trg_group=gt, exclude_same_group=True)
+    u_ref = rng.standard_normal((3, x.shape[1]))
+
+    def fwd(yy, ff, xx):
+        return O.p2p(0, yy, ff, w, xx, so, to, ofs, ul, mu=0.8, **kw)
+
+    u = fwd(y, f, x)
+    gf, gy, gx = O.p2p_sl_vjp(y, f, w, x, u - u_ref, so, to, ofs, ul, mu=0.8, **kw)
+    h = 1e-6
+    for arr, grad, name in ((f, gf, "f"), (y, gy, "src"), (x, gx, "trg")):
+        idx = rng.choice(arr.shape[1], 8, replace=False)
+        if name != "trg":                                 # and sources of the repeated entry
+            idx = np.concatenate([idx, rng.choice(dup, min(4, dup.size), replace=False)])
+        for j in idx:
+            i = int(rng.integers(0, 3))
+            ap, am = arr.copy(), arr.copy()
+            ap[i, j] += h
+            am[i, j] -= h
+            args_p = {"f": (y, ap, x), "src": (ap, f, x), "trg": (y, f, ap)}[name]
+            args_m = {"f": (y, am, x), "src": (am, f, x), "trg": (y, f, am)}[name]
+            fd = _loss_delta(fwd(*args_p), fwd(*args_m), u_ref) / (2 * h)
+            assert abs(fd - grad[i, j]) <= 1e-6 * (abs(grad[i, j]) + 1e-3 * np.abs(grad).max()), name

@@ -35,7 +35,7 @@ def _reference(ctx, x, precision):
                      x["ng"], 0.5)
     op = C.Opts(precision, 0)
     size = ctypes.c_size_t()
-    assert L.stokes_workspace_size(ctx, C.OP_SL, n, n, 0, ctypes.byref(op), ctypes.byref(size)) == C.OK
+    assert L.stokes_workspace_size(ctx, C.OP_SL, n, n, 0, 0, ctypes.byref(op), ctypes.byref(size)) == C.OK
     ws = torch.empty(max(size.value, 1), dtype=torch.uint8, device=device())
     out = torch.empty((3, n), dtype=torch.float64, device=device())
     rc = L.stokes_sl_eval(ctx, n, _vp(x["pos"]), _vp(x["f"]), _vp(x["w"]), n, _vp(x["pos"]), 1.3,
@@ -91,7 +91,7 @@ def test_too_large_is_rejected_untouched(ctx):
     x = _inputs(33, n)
     size = ctypes.c_size_t()
     op = C.Opts(C.FP64, 0)
-    assert C.lib().stokes_workspace_size(ctx, C.OP_SL, n, n, 0, ctypes.byref(op), ctypes.byref(size)) == C.OK
+    assert C.lib().stokes_workspace_size(ctx, C.OP_SL, n, n, 0, 0, ctypes.byref(op), ctypes.byref(size)) == C.OK
     assert size.value > C.NOALLOC_SCRATCH_BYTES
     out = torch.full((3, n), 7.0, dtype=torch.float64, device=device())
     assert _noalloc(ctx, x, C.FP64, out) == C.EWORKSPACE
