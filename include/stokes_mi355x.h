@@ -543,18 +543,20 @@ int stokes_collision_candidates(stokes_ctx* ctx, int32_t n_boxes, const double* 
  *             sum over the 27 leaves around each target's leaf (zero-distance
  *             pairs skipped).
  * Its error against the direct sum falls with `order` (single layer: about
- * 1e-3 at 4, 1e-4 at 6 on clustered points; double layer about ten times
- * that); there is no pair rule (all pairs, as in the
- * paper, whose self-cell terms are handled by its singular quadrature).
+ * 1e-3 at 4, 1e-4 at 6, 1e-6 at 8, 1e-7 at 10 on clustered points; double
+ * layer up to ten times that below order 10); there is no pair rule (all
+ * pairs, as in the paper, whose self-cell terms are handled by its singular
+ * quadrature).
  * The plan holds the check-to-equivalent pseudo-inverses (singular values
- * below 1e-12 of the largest dropped), computed on the host at creation
- * (about 0.1 s at order 4, a few seconds at 6), and the M2L operators: for
- * each of the 8 positions of a box in its parent, its 189 interaction-list
- * translations and the parent-to-child one at unit scale, built on the device
- * (8 x 190 x m^2 doubles, m = 3 (6 (order-1)^2 + 2) rounded up to 16: 0.4 GB
- * at order 4, 2.6 GB at order 6).  All of it is device memory owned by the
- * plan until stokes_fmm_plan_destroy. */
-int stokes_fmm_plan_create(stokes_ctx* ctx, int32_t order, stokes_fmm_plan** plan);   /* order 2..6 */
+ * below 1e-10 of the largest dropped), computed on the host at creation by a
+ * threaded Jacobi SVD (about 0.1 s at order 4, 1.5 s at 6, 8 s at 8, 30 s at
+ * 10 on 8 cores), and the M2L operators: for each of the 8 positions of a box
+ * in its parent, its 189 interaction-list translations and the
+ * parent-to-child one at unit scale, built on the device (8 x 190 x m^2
+ * doubles, m = 3 (6 (order-1)^2 + 2) rounded up to 16: 0.4 GB at order 4,
+ * 2.6 GB at 6, 9.8 GB at 8, 26 GB at 10).  All of it is device memory owned
+ * by the plan until stokes_fmm_plan_destroy. */
+int stokes_fmm_plan_create(stokes_ctx* ctx, int32_t order, stokes_fmm_plan** plan);   /* order 2..10 */
 void stokes_fmm_plan_destroy(stokes_fmm_plan* plan);
 
 /* Workspace for n_src sources, n_trg targets and depth (2..7): the per-box

@@ -38,9 +38,14 @@ single-layer sources every sigma is 0.
 
 Readings: the surface radii and the pseudo-inverse are not in the paper; the
 radii are the customary ones of the method, and pinv drops singular values
-below 1e-12 of the largest (the single layer on a closed surface annihilates
-the normal density, so the matrix is singular).  The pseudo-inverses are formed
-once for a unit box and scaled by h_l (the kernel is homogeneous of degree -1).
+below 1e-10 of the largest (the single layer on a closed surface annihilates
+the normal density, so the matrix is singular; from order 8 on its smallest
+singular values fall below 1e-12 of the largest, where float64 determines
+their singular vectors only to about 1e-4, and a lower cutoff lets that noise
+into the equivalent densities: at order 10 a 1e-12 cutoff gives an error of
+about 5e-7 to 3e-6 against the direct sum, 1e-10 about 1e-8 to 1e-7).  The
+pseudo-inverses are formed once for a unit box and scaled by h_l (the kernel
+is homogeneous of degree -1).
 """
 from __future__ import annotations
 
@@ -49,7 +54,7 @@ import itertools
 import numpy as np
 
 ALPHA_UE, ALPHA_UC, ALPHA_DE, ALPHA_DC = 1.05, 2.95, 2.95, 1.05
-PINV_RCOND = 1e-12
+PINV_RCOND = 1e-10
 
 
 def surface(p):

@@ -34,7 +34,10 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -60,7 +63,7 @@ namespace stokes {
 namespace {
 
 constexpr double kAlphaUE = 1.05, kAlphaUC = 2.95, kAlphaDE = 2.95, kAlphaDC = 1.05;
-constexpr double kPinvRcond = 1e-12;
+constexpr double kPinvRcond = 1e-10;
 constexpr int kFBlock = 256;
 constexpr int kFWaves = kFBlock / kWave;
 constexpr int64_t kFMaxGrid = 1 << 16;
@@ -302,22 +305,28 @@ __device__ __forceinline__ double leaf_flux(const FmmDev& a, int64_t m0, int64_t
     return total;
 }
 
+constexpr int kMaxT = 8;                 // check points per lane
 constexpr int kMaxNs = 6 * (kFmmMaxOrder - 1) * (kFmmMaxOrder - 1) + 2;
-static_assert(kMaxNs <= 3 * kWave, "the surface kernels hold at most three check points per lane");
+static_assert(kMaxNs <= kMaxT * kWave, "the surface kernels hold at most kMaxT check points per lane");
 
-// Writes one box's surface sources (centre ctr, radius scale: points
-// ctr + scale * template, strengths dens) into a wave's LDS slice.
-__device__ __forceinline__ void stage_surface(const FmmDev& a, const double* surf, const double* ctr, double scale,
-                                              const double* __restrict__ dens, SrcSL64* dst, int lane) {
-    for (int j = lane; j < a.ns; j += kWave) {
-        SrcSL64 r;
-        r.x = ctr[0] + scale * surf[3 * j];
-        r.y = ctr[1] + scale * surf[3 * j + 1];
-        r.z = ctr[2] + scale * surf[3 * j + 2];
-        r.qx = dens[3 * j];
-        r.qy = dens[3 * j + 1];
-        r.qz = dens[3 * j + 2];
-        dst[j] = r;
+// Copies one box's surface densities (3 per point) into a wave's LDS slice.
+__device__ __forceinline__ void stage_density(const FmmDev& a, const double* __restrict__ dens, double* dst,
+                                              int lane) {
+    for (int r = lane; r < a.n3; r += kWave) dst[r] = dens[r];
+}
+
+// Adds the single-layer velocity of a surface (points ctr + scale * template,
+// the template and the staged densities q in LDS) at a lane's T check points.
+template <int T>
+__device__ __forceinline__ void surface_sum(const FmmDev& a, const double* surf, const double* ctr, double scale,
+                                            const double* q, const double (&x)[T][3], double (&u)[T][3]) {
+#pragma unroll 2
+    for (int j = 0; j < a.ns; ++j) {
+        const double sx = ctr[0] + scale * surf[3 * j], sy = ctr[1] + scale * surf[3 * j + 1],
+                     sz = ctr[2] + scale * surf[3 * j + 2];
+        const double qx = q[3 * j], qy = q[3 * j + 1], qz = q[3 * j + 2];
+#pragma unroll
+        for (int k = 0; k < T; ++k) sl_pair<false>(x[k][0] - sx, x[k][1] - sy, x[k][2] - sz, qx, qy, qz, u[k]);
     }
 }
 
@@ -397,18 +406,16 @@ __device__ __forceinline__ void near_pair(const typename NearRec<KT>::type& s, d
         dl_pair<MASKED>(x - s.x, y - s.y, z - s.z, s.nx, s.ny, s.nz, s.qx, s.qy, s.qz, u);
 }
 
-// Dynamic LDS of P2M, in doubles: the template, a workgroup tile of source
-// records, the four partial check vectors.
+// Dynamic LDS of P2M: the template, then a workgroup tile of source records,
+// which the four partial check vectors reuse once every wave is done with it.
 size_t p2m_lds(int ns, int KT) {
     const size_t rec = KT ? sizeof(SrcDL64) : sizeof(SrcSL64);
-    return ((size_t)((3 * ns + 1) & ~1) + kFBlock * rec / sizeof(double) + (size_t)kFWaves * 3 * ns) * sizeof(double);
-}
-// ... of M2M: the template, one staging slice per wave, the partial vectors.
-size_t m2m_lds(int ns) {
-    return ((size_t)((3 * ns + 1) & ~1) + (size_t)kFWaves * ns * (sizeof(SrcSL64) / sizeof(double)) +
-            (size_t)kFWaves * 3 * ns) *
+    return ((size_t)((3 * ns + 1) & ~1) + std::max<size_t>(kFBlock * rec / sizeof(double), (size_t)kFWaves * 3 * ns)) *
            sizeof(double);
 }
+// ... of M2M: the template, then one density slice per wave (3 ns doubles),
+// which the partial vectors reuse.
+size_t m2m_lds(int ns) { return ((size_t)((3 * ns + 1) & ~1) + (size_t)kFWaves * 3 * ns) * sizeof(double); }
 
 // P2M: the leaf's sources are staged 256 at a time; wave w sums its quarter
 // of each tile at its T check points per lane (zero-distance mask: a point
@@ -420,7 +427,7 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a, const int32_t* _
     extern __shared__ double sh[];
     double* surf = sh;
     Rec* tile = reinterpret_cast<Rec*>(surf + ((3 * a.ns + 1) & ~1));
-    double* part = reinterpret_cast<double*>(tile + kFBlock);
+    double* part = reinterpret_cast<double*>(tile);            // after the last tile's reads
     __shared__ double red[kFWaves];
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -452,23 +459,24 @@ __global__ __launch_bounds__(kFBlock) void p2m_kernel(FmmDev a, const int32_t* _
 #pragma unroll
             for (int k = 0; k < T; ++k)
                 point_source(x[k][0] - ctr[0], x[k][1] - ctr[1], x[k][2] - ctr[2], -sigma, u[k]);
+        __syncthreads();                           // the partial vectors overwrite the tile
         store_partial<T>(a, part, wave, lane, u);
         store_check(a, part, h, i);
     }
 }
 
 // M2M: wave w takes children w and w + 4, stages each child's equivalent
-// sources in its own LDS slice and sums them at its T check points per lane.
+// density in its own LDS slice and sums it at its T check points per lane.
 template <int T>
 __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l, const int32_t* __restrict__ list,
                                                       const int64_t* __restrict__ n_listed) {
     extern __shared__ double sh[];
     double* surf = sh;
-    SrcSL64* stage = reinterpret_cast<SrcSL64*>(surf + ((3 * a.ns + 1) & ~1));
-    double* part = reinterpret_cast<double*>(stage + kFWaves * a.ns);
+    double* stage = surf + ((3 * a.ns + 1) & ~1);
+    double* part = stage;                                      // once every wave is done with its densities
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    SrcSL64* mine = stage + wave * a.ns;
+    double* mine = stage + wave * a.n3;
     const int64_t listed = *n_listed;
     for (int64_t i = blockIdx.x; i < listed; i += gridDim.x) {
         const int64_t b = list[i];                                    // the i-th box holding sources
@@ -494,17 +502,12 @@ __global__ __launch_bounds__(kFBlock) void m2m_kernel(FmmDev a, int l, const int
 #pragma unroll
                 for (int k = 0; k < T; ++k) point_source(x[k][0] - cc[0], x[k][1] - cc[1], x[k][2] - cc[2], sg, u[k]);
             }
-            stage_surface(a, surf, cc, kAlphaUE * hc, a.ue + (a.base[l + 1] + ch) * a.n3, mine, lane);
+            stage_density(a, a.ue + (a.base[l + 1] + ch) * a.n3, mine, lane);
             __builtin_amdgcn_wave_barrier();
-#pragma unroll 2
-            for (int j = 0; j < a.ns; ++j) {
-                const SrcSL64 sr = mine[j];
-#pragma unroll
-                for (int k = 0; k < T; ++k)
-                    sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz, u[k]);
-            }
+            surface_sum<T>(a, surf, cc, kAlphaUE * hc, mine, x, u);
             __builtin_amdgcn_wave_barrier();   // reads of this child precede the next writes
         }
+        __syncthreads();                           // the partial vectors overwrite the density slices
         store_partial<T>(a, part, wave, lane, u);
         store_check(a, part, h, i);
     }
@@ -661,16 +664,27 @@ __global__ __launch_bounds__(kFBlock) void m2l_matrix_kernel(const double* __res
     }
 }
 
-// Tile shape of the GEMMs for mp = 16 RB rows: H row blocks per wave half, na
-// doubles per A chunk, APT of them loaded per thread.
+// Tile shape of the GEMMs for mw = 16 RB rows per workgroup: H row blocks per
+// wave half, na doubles per A chunk, APT of them loaded per thread.  Up to
+// order 6 a workgroup takes all mp rows; above, the rows are cut into row
+// groups of mw (the register and LDS footprint of RB = 29 at most).
+constexpr int kGemmMaxRB = 29;
 template <int RB> struct GemmShape {
-    static constexpr int mp = 16 * RB, H = (RB + 1) / 2, na = kGemmKC * mp;
+    static_assert(RB <= kGemmMaxRB, "row blocks per workgroup");
+    static constexpr int mw = 16 * RB, H = (RB + 1) / 2, na = kGemmKC * mw;
     static constexpr int APT = (na + kGemmThreads - 1) / kGemmThreads;
 };
+// Row blocks per workgroup for mp rows, and the row groups that cover them.
+int gemm_rb(int mp) {
+    const int blocks = mp / 16, ng = (blocks + kGemmMaxRB - 1) / kGemmMaxRB;
+    return (blocks + ng - 1) / ng;
+}
+__host__ __device__ inline int gemm_groups(int mp, int rb) { return (mp / 16 + rb - 1) / rb; }
 
-// C(:, j) = A B(:, j) for the 64 columns of a tile, over the K chunks
-// chunk(0) .. chunk(n - 1) of kGemmKC rows each, then store(j, row, value)
-// for the rows < nrow.  A: K x mp, k-major (A[k * mp + row]), mp = 16 RB.
+// C(r0 + row, j) = A B(:, j) for the 64 columns of a tile and rows r0 ..
+// r0 + mw - 1, over the K chunks chunk(0) .. chunk(n - 1) of kGemmKC rows
+// each, then store(j, row, value) for the rows < nrow.  A: K x lda, k-major
+// (A[k * lda + row]); rows at or past lda read as zero.
 // Each chunk of A and of B goes through LDS (two buffers); chunk t + 2 is in
 // flight in registers while chunk t is multiplied.  loadb(q, j, k)
 // gives row k of chunk q for column j; busy(t, g) is false when chunk t is
@@ -681,8 +695,9 @@ template <int RB> struct GemmShape {
 // holds row block (w >> 2) H + i; lane l, entry r is row (l >> 4) + 4 r and
 // column 16 (w & 3) + (l & 15).
 template <int RB, int NR, typename Chunk, typename LoadB, typename Busy, typename Store>
-__device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t n, Chunk&& chunk, LoadB&& loadb,
-                                          Busy&& busy, double* As, double* Bs, int nrow, Store&& store) {
+__device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int lda, int r0, int64_t n, Chunk&& chunk,
+                                          LoadB&& loadb, Busy&& busy, double* As, double* Bs, int nrow,
+                                          Store&& store) {
     using G = GemmShape<RB>;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int cg = wave & 3, rb0 = (wave >> 2) * G::H;
@@ -693,11 +708,12 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t 
     double pa[G::APT], pb[kGemmBPT];
     auto fetch = [&](int64_t t) {
         const int64_t q = chunk(t);
-        const double* Aq = A + q * G::na;
+        const double* Aq = A + q * kGemmKC * lda + r0;
 #pragma unroll
         for (int i = 0; i < G::APT; ++i) {
             const int e = tid + i * kGemmThreads;
-            pa[i] = e < G::na ? Aq[e] : 0.0;
+            const int k = e / G::mw, r = e - k * G::mw;
+            pa[i] = (e < G::na && r0 + r < lda) ? Aq[k * lda + r] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < kGemmBPT; ++i) pb[i] = loadb(q, bj, bk + 8 * i);
@@ -722,7 +738,7 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t 
             const double bv = Bb[kr * kGemmNT + 16 * cg + (lane & 15)];
             double av[NR];
 #pragma unroll
-            for (int i = 0; i < NR; ++i) av[i] = Ab[kr * G::mp + 16 * (rb0 + i) + (lane & 15)];
+            for (int i = 0; i < NR; ++i) av[i] = Ab[kr * G::mw + 16 * (rb0 + i) + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < NR; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv, acc[i], 0, 0, 0);
         }
@@ -760,13 +776,14 @@ __device__ __forceinline__ void gemm_tile(const double* __restrict__ A, int64_t 
 
 // Runs gemm_tile with the row-block count of this wave's half (a scalar branch).
 template <int RB, typename Chunk, typename LoadB, typename Busy, typename Store>
-__device__ __forceinline__ void gemm_tile_any(const double* __restrict__ A, int64_t n, Chunk&& chunk, LoadB&& loadb,
-                                              Busy&& busy, double* As, double* Bs, int nrow, Store&& store) {
+__device__ __forceinline__ void gemm_tile_any(const double* __restrict__ A, int lda, int r0, int64_t n, Chunk&& chunk,
+                                              LoadB&& loadb, Busy&& busy, double* As, double* Bs, int nrow,
+                                              Store&& store) {
     using G = GemmShape<RB>;
     if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave) >> 2) != 0)
-        gemm_tile<RB, RB - G::H>(A, n, chunk, loadb, busy, As, Bs, nrow, store);
+        gemm_tile<RB, RB - G::H>(A, lda, r0, n, chunk, loadb, busy, As, Bs, nrow, store);
     else
-        gemm_tile<RB, G::H>(A, n, chunk, loadb, busy, As, Bs, nrow, store);
+        gemm_tile<RB, G::H>(A, lda, r0, n, chunk, loadb, busy, As, Bs, nrow, store);
 }
 
 struct M2LArgs {
@@ -848,8 +865,9 @@ __global__ __launch_bounds__(kFBlock) void il_count_kernel(FmmDev a, M2LArgs g, 
 }
 
 // Partial V = A_c E over K split `split` for one tile of 64 listed boxes of
-// class blockIdx.x & 7 (unit blockIdx.x >> 3 = split * tiles + tile).  K
-// blocks whose source box is missing for all 64 columns are skipped.
+// class blockIdx.x & 7 and one row group: blockIdx.x >> 3 = rg * units + u,
+// u = split * tiles + tile, units = gridDim.x / (8 row groups).  K blocks whose
+// source box is missing for all 64 columns are skipped.
 template <int RB>
 __global__ __launch_bounds__(kGemmThreads) void m2l_gemm_kernel(FmmDev a, M2LArgs g, int l) {
     using G = GemmShape<RB>;
@@ -859,8 +877,12 @@ __global__ __launch_bounds__(kGemmThreads) void m2l_gemm_kernel(FmmDev a, M2LArg
     __shared__ int32_t s_src[kM2LMaxSplitBlocks][kGemmNT];     // their source boxes per column (-1: none)
     __shared__ uint8_t s_grp[kM2LMaxSplitBlocks][kGemmNT / 16]; // any source among 16 columns
     const int c = blockIdx.x & 7;
-    const int64_t u = blockIdx.x >> 3, P = (int64_t)1 << (3 * (l - 1));
+    const int mp = g.mp, ng = gemm_groups(mp, RB);
+    const int64_t units = gridDim.x / (8 * ng), w = blockIdx.x >> 3, P = (int64_t)1 << (3 * (l - 1));
+    const int rg = (int)(w / units);
+    const int64_t u = w % units;
     const int64_t S = g.sched[0];
+    if (rg >= ng) return;
     if (g.sched[1]) return;                                    // this level runs as pair sums
     const int64_t c0 = g.cscan[c * P], c1 = c < 7 ? g.cscan[(c + 1) * P] : *g.ctotal;
     const int64_t tiles = (c1 - c0 + kGemmNT - 1) / kGemmNT;
@@ -904,7 +926,7 @@ __global__ __launch_bounds__(kGemmThreads) void m2l_gemm_kernel(FmmDev a, M2LArg
     }
     __syncthreads();
     const int nact = s_act[kM2LMaxSplitBlocks];
-    constexpr int cpb = G::mp / kGemmKC;                       // chunks per K block (the plan has kb == mp)
+    const int cpb = mp / kGemmKC;                              // chunks per K block (the plan has kb == mp)
     const double inv_h = (double)(1 << l) / a.R;
     auto chunk = [&](int64_t t) {
         const int ti = (int)t;
@@ -921,21 +943,18 @@ __global__ __launch_bounds__(kGemmThreads) void m2l_gemm_kernel(FmmDev a, M2LArg
         return (kk == a.n3 && a.sig) ? a.sig[box] * inv_h : 0.0;
     };
     const int64_t listed = *g.ctotal;
-    double* part = g.vbuf + split * listed * G::mp;
-    gemm_tile_any<RB>(g.A + (int64_t)c * kM2LBlocks * G::mp * G::mp, (int64_t)nact * cpb, chunk, loadb, busy, As, Bs,
-                      G::mp, [&](int j, int row, double v) {
-                          if (col0 + j < c1) part[(col0 + j) * G::mp + row] = v;
+    double* part = g.vbuf + split * listed * mp;
+    const int r0 = rg * G::mw;
+    gemm_tile_any<RB>(g.A + (int64_t)c * kM2LBlocks * mp * mp, mp, r0, (int64_t)nact * cpb, chunk, loadb, busy, As,
+                      Bs, mp - r0, [&](int j, int row, double v) {
+                          if (col0 + j < c1) part[(col0 + j) * mp + r0 + row] = v;
                       });
 }
 
 // Dynamic LDS of the pair-sum M2L kernel, in doubles: the template, then one
-// staging slice of ns records per wave, which the partial check vectors reuse
-// once every wave is done with its sources.
-size_t m2l_lds(int ns) {
-    const size_t stage = (size_t)kFWaves * ns * (sizeof(SrcSL64) / sizeof(double));
-    const size_t part = (size_t)kFWaves * 3 * ns;
-    return ((size_t)((3 * ns + 1) & ~1) + std::max(stage, part)) * sizeof(double);
-}
+// density slice of 3 ns doubles per wave, which the partial check vectors
+// reuse once every wave is done with its sources.
+size_t m2l_lds(int ns) { return ((size_t)((3 * ns + 1) & ~1) + (size_t)kFWaves * 3 * ns) * sizeof(double); }
 
 // M2L as pair sums, for levels whose interaction lists are sparse: per target
 // box, the interaction-list boxes that hold sources (plus L2L from the parent,
@@ -950,11 +969,10 @@ __global__ __launch_bounds__(kFBlock) void m2l_pairs_kernel(FmmDev a, M2LArgs g,
     if (!g.sched[1]) return;                                   // this level runs as a GEMM
     double* surf = sh;
     double* rest = surf + ((3 * a.ns + 1) & ~1);               // 16-byte aligned
-    SrcSL64* stage = reinterpret_cast<SrcSL64*>(rest);
     double* part = rest;
     load_surface(a, surf);
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    SrcSL64* mine = stage + wave * a.ns;
+    double* mine = rest + wave * a.n3;
     const int64_t np = (int64_t)1 << (l - 1), listed = *g.ctotal;
     // the listed target boxes one after another (the list is compact, so the
     // workgroups share the boxes evenly whatever the tree's occupancy); box i
@@ -989,31 +1007,18 @@ __global__ __launch_bounds__(kFBlock) void m2l_pairs_kernel(FmmDev a, M2LArgs g,
                             for (int k = 0; k < T; ++k)
                                 point_source(x[k][0] - ac[0], x[k][1] - ac[1], x[k][2] - ac[2], sg, u[k]);
                         }
-                        stage_surface(a, surf, ac, kAlphaUE * ha, a.ue + (a.base[l] + ab) * a.n3, mine, lane);
+                        stage_density(a, a.ue + (a.base[l] + ab) * a.n3, mine, lane);
                         __builtin_amdgcn_wave_barrier();
-#pragma unroll 2
-                        for (int j = 0; j < a.ns; ++j) {
-                            const SrcSL64 sr = mine[j];
-#pragma unroll
-                            for (int k = 0; k < T; ++k)
-                                sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz,
-                                               u[k]);
-                        }
+                        surface_sum<T>(a, surf, ac, kAlphaUE * ha, mine, x, u);
                         __builtin_amdgcn_wave_barrier();   // reads of this box precede the next writes
                     }
                 }
         if (l > 2 && item++ % kFWaves == wave) {
             double pc[3], hp;
             box_centre(a, l - 1, p, pc, hp);
-            stage_surface(a, surf, pc, kAlphaDE * hp, a.de + (a.base[l - 1] + p) * a.n3, mine, lane);
+            stage_density(a, a.de + (a.base[l - 1] + p) * a.n3, mine, lane);
             __builtin_amdgcn_wave_barrier();
-#pragma unroll 2
-            for (int j = 0; j < a.ns; ++j) {
-                const SrcSL64 sr = mine[j];
-#pragma unroll
-                for (int k = 0; k < T; ++k)
-                    sl_pair<false>(x[k][0] - sr.x, x[k][1] - sr.y, x[k][2] - sr.z, sr.qx, sr.qy, sr.qz, u[k]);
-            }
+            surface_sum<T>(a, surf, pc, kAlphaDE * hp, mine, x, u);
         }
         __syncthreads();                           // the partial vectors overwrite the staging slices
         store_partial<T>(a, part, wave, lane, u);
@@ -1042,8 +1047,9 @@ __device__ __forceinline__ int64_t apply_splits(int64_t tiles, int64_t nk) {
 }
 
 // out[list[j]] = OP V(:, j) for the listed boxes (OP padded to mp x mp,
-// k-major; out rows n3 per box): the pseudo-inverse of a whole level.  Unit
-// u is tile u / S, K split u % S; with one split the tile writes out, with
+// k-major; out rows n3 per box): the pseudo-inverse of a whole level.
+// Workgroup rg * units + u (units = gridDim.x / row groups) takes row group
+// rg of tile u / S, K split u % S; with one split the tile writes out, with
 // more each split writes its partial (apply_reduce_kernel adds them).
 template <int RB>
 __global__ __launch_bounds__(kGemmThreads) void apply_gemm_kernel(FmmDev a, M2LArgs g, const double* __restrict__ op,
@@ -1051,22 +1057,25 @@ __global__ __launch_bounds__(kGemmThreads) void apply_gemm_kernel(FmmDev a, M2LA
     using G = GemmShape<RB>;
     __shared__ double As[2 * G::na];
     __shared__ double Bs[2 * kGemmKC * kGemmNT];
-    const int64_t n = *g.ctotal, nk = G::mp / kGemmKC;
+    const int mp = a.mp, ng = gemm_groups(mp, RB);
+    const int64_t n = *g.ctotal, nk = mp / kGemmKC;
     const int64_t tiles = (n + kGemmNT - 1) / kGemmNT, S = apply_splits(tiles, nk);
-    const int64_t u = blockIdx.x;
-    if (u >= tiles * S) return;                                   // uniform over the workgroup
+    const int64_t units = gridDim.x / ng, u = blockIdx.x % units;
+    const int rg = (int)(blockIdx.x / units);
+    if (rg >= ng || u >= tiles * S) return;                       // uniform over the workgroup
     const int64_t col0 = (u / S) * kGemmNT, sp = u % S;
     const int64_t k0 = sp * nk / S, k1 = (sp + 1) * nk / S;
     auto chunk = [k0](int64_t t) { return k0 + t; };
     auto loadb = [&](int64_t q, int j, int bk) -> double {
-        return col0 + j < n ? g.vbuf[(col0 + j) * G::mp + q * kGemmKC + bk] : 0.0;
+        return col0 + j < n ? g.vbuf[(col0 + j) * mp + q * kGemmKC + bk] : 0.0;
     };
     auto busy = [](int64_t, int) { return true; };
     const int32_t* list = g.list;
-    gemm_tile_any<RB>(op, k1 - k0, chunk, loadb, busy, As, Bs, a.n3, [&](int j, int row, double v) {
+    const int r0 = rg * G::mw;
+    gemm_tile_any<RB>(op, mp, r0, k1 - k0, chunk, loadb, busy, As, Bs, a.n3 - r0, [&](int j, int row, double v) {
         if (col0 + j >= n) return;
-        if (S == 1) out[(int64_t)list[col0 + j] * a.n3 + row] = v;
-        else part[(sp * n + col0 + j) * a.n3 + row] = v;
+        if (S == 1) out[(int64_t)list[col0 + j] * a.n3 + r0 + row] = v;
+        else part[(sp * n + col0 + j) * a.n3 + r0 + row] = v;
     });
 }
 
@@ -1102,6 +1111,39 @@ __global__ __launch_bounds__(kFBlock) void src_list_kernel(FmmDev a, int l, cons
     const int64_t nb = (int64_t)1 << (3 * l);
     for (int64_t b = (int64_t)blockIdx.x * kFBlock + threadIdx.x; b < nb; b += (int64_t)gridDim.x * kFBlock)
         if (a.snz[a.base[l] + b]) list[scan[b]] = (int32_t)b;
+}
+
+// Calls f(std::integral_constant<int, T>) for check points per lane T
+// (1 .. kMaxT), and for the GEMM row blocks per workgroup that gemm_rb gives
+// at the orders of the plan.
+template <typename F>
+void with_T(int T, F&& f) {
+    switch (T) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 7: f(std::integral_constant<int, 7>{}); break;
+        default: f(std::integral_constant<int, 8>{}); break;
+    }
+}
+static_assert(kMaxT == 8, "with_T covers 1 .. kMaxT");
+template <typename F>
+bool with_rb(int rb, F&& f) {
+    switch (rb) {                       // orders 2 .. 10: mp / 16 = 2, 5, 11, 19, 29, 41, 56, 73, 92
+        case 2: f(std::integral_constant<int, 2>{}); return true;
+        case 5: f(std::integral_constant<int, 5>{}); return true;
+        case 11: f(std::integral_constant<int, 11>{}); return true;
+        case 19: f(std::integral_constant<int, 19>{}); return true;
+        case 21: f(std::integral_constant<int, 21>{}); return true;    // 41 in 2 groups
+        case 23: f(std::integral_constant<int, 23>{}); return true;    // 92 in 4
+        case 25: f(std::integral_constant<int, 25>{}); return true;    // 73 in 3
+        case 28: f(std::integral_constant<int, 28>{}); return true;    // 56 in 2
+        case 29: f(std::integral_constant<int, 29>{}); return true;
+        default: return false;
+    }
 }
 
 struct FmmLayout {
@@ -1174,67 +1216,217 @@ FmmLayout fmm_layout(int ns, int64_t n_src, int64_t n_trg, int D) {
 }  // namespace
 
 // ---------------------------------------------------------------- host
+namespace {
+// Sense-reversing barrier for the Jacobi rounds (threads spin, yielding).
+struct RoundBarrier {
+    explicit RoundBarrier(int n) : n_(n) {}
+    void wait() {
+        const int g = gen_.load(std::memory_order_acquire);
+        if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
+            count_.store(0, std::memory_order_relaxed);
+            gen_.fetch_add(1, std::memory_order_release);
+        } else {
+            while (gen_.load(std::memory_order_acquire) == g) std::this_thread::yield();
+        }
+    }
+    const int n_;
+    std::atomic<int> count_{0}, gen_{0};
+};
+
+// f(lo, hi) over [0, n) cut into nth contiguous ranges, one thread each.
+template <typename F>
+void parallel_ranges(int64_t n, int nth, F&& f) {
+    if (nth <= 1 || n < 2 * nth) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back([&, t] { f(n * t / nth, n * (t + 1) / nth); });
+    f((int64_t)0, n / nth);
+    for (auto& th : pool) th.join();
+}
+}  // namespace
+
 void pinv_jacobi(const std::vector<double>& K, int n, double rcond, std::vector<double>& P) {
     // columns of A (a[j * n + i] = K[i][j]) are rotated until orthogonal: A V = W,
-    // W's columns are sigma_j u_j; pinv = sum_j v_j w_j^T / sigma_j^2
+    // W's columns are sigma_j u_j; pinv = sum_j v_j w_j^T / sigma_j^2.  A sweep
+    // visits every column pair once in the round-robin order of a tournament:
+    // m - 1 rounds (m = n rounded up to even) of m / 2 disjoint pairs, split
+    // over threads.  Rotations of disjoint pairs commute, so the result does
+    // not depend on the thread count.
     std::vector<double> a((size_t)n * n), v((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) a[(size_t)j * n + i] = K[(size_t)i * n + j];
     for (int j = 0; j < n; ++j) v[(size_t)j * n + j] = 1.0;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        double worst = 0.0;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                double* ap = &a[(size_t)p * n];
-                double* aq = &a[(size_t)q * n];
-                double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = 0; i < n; ++i) {
-                    al += ap[i] * ap[i];
-                    be += aq[i] * aq[i];
-                    ga += ap[i] * aq[i];
+    const int m = n + (n & 1);
+    // A pair is left alone when its columns are orthogonal to 1e-15 or one of
+    // them is below 1e-12 of the largest column norm (sqrt(smax2)): such a
+    // column is rounding noise, two decades under the cutoff, and rotating it
+    // against the others only stirs that noise.
+    double smax2 = 0.0;
+    auto rotate = [&](int p, int q) -> double {    // returns the pair's |cos| of the angle before
+        double* ap = &a[(size_t)p * n];
+        double* aq = &a[(size_t)q * n];
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = 0; i < n; ++i) {
+            al += ap[i] * ap[i];
+            be += aq[i] * aq[i];
+            ga += ap[i] * aq[i];
+        }
+        if (ga == 0.0 || al == 0.0 || be == 0.0) return 0.0;
+        const double rel = fabs(ga) / sqrt(al * be);
+        if (rel <= 1e-15 || std::min(al, be) <= 1e-24 * smax2) return 0.0;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int i = 0; i < n; ++i) {
+            const double x = ap[i], y = aq[i];
+            ap[i] = c * x - s * y;
+            aq[i] = s * x + c * y;
+        }
+        double* vp = &v[(size_t)p * n];
+        double* vq = &v[(size_t)q * n];
+        for (int i = 0; i < n; ++i) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = c * x - s * y;
+            vq[i] = s * x + c * y;
+        }
+        return rel;
+    };
+    // position k of round r holds column (k == 0 ? 0 : 1 + (k - 1 + r) % (m - 1));
+    // the pairs of a round are positions (k, m - 1 - k)
+    auto column = [m](int k, int r) { return k == 0 ? 0 : 1 + (k - 1 + r) % (m - 1); };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, 16, (int64_t)(m / 2) / 16}));
+    std::vector<double> worst_t(nth);
+    for (int sweep = 0; sweep < 40 && m >= 2; ++sweep) {
+        std::fill(worst_t.begin(), worst_t.end(), 0.0);
+        smax2 = 0.0;
+        for (int j = 0; j < n; ++j) {
+            double c = 0.0;
+            for (int i = 0; i < n; ++i) c += a[(size_t)j * n + i] * a[(size_t)j * n + i];
+            smax2 = std::max(smax2, c);
+        }
+        RoundBarrier bar(nth);
+        auto work = [&](int tid) {
+            double worst = 0.0;
+            for (int r = 0; r < m - 1; ++r) {
+                for (int k = tid; k < m / 2; k += nth) {
+                    const int c0 = column(k, r), c1 = column(m - 1 - k, r);
+                    const int p = std::min(c0, c1), q = std::max(c0, c1);
+                    if (q >= n) continue;                  // the padding column of an odd n
+                    worst = std::max(worst, rotate(p, q));
                 }
-                if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
-                const double rel = fabs(ga) / sqrt(al * be);
-                if (rel <= 1e-15) continue;
-                worst = std::max(worst, rel);
-                const double zeta = (be - al) / (2.0 * ga);
-                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                for (int i = 0; i < n; ++i) {
-                    const double x = ap[i], y = aq[i];
-                    ap[i] = c * x - s * y;
-                    aq[i] = s * x + c * y;
-                }
-                double* vp = &v[(size_t)p * n];
-                double* vq = &v[(size_t)q * n];
-                for (int i = 0; i < n; ++i) {
-                    const double x = vp[i], y = vq[i];
-                    vp[i] = c * x - s * y;
-                    vq[i] = s * x + c * y;
-                }
+                if (nth > 1) bar.wait();                   // round r's columns are final
             }
-        if (worst <= 1e-14) break;
+            worst_t[tid] = worst;
+        };
+        if (nth == 1) {
+            work(0);
+        } else {
+            std::vector<std::thread> pool;
+            for (int t = 1; t < nth; ++t) pool.emplace_back(work, t);
+            work(0);
+            for (auto& th : pool) th.join();
+        }
+        if (*std::max_element(worst_t.begin(), worst_t.end()) <= 1e-14) break;
     }
-    std::vector<double> sig2(n);
+    // Columns near the cutoff carry rounding noise of relative size eps
+    // sigma_max / sigma_j and stay slightly non-orthogonal however many sweeps
+    // run.  The kept columns J (norm above rcond times the largest) are
+    // therefore inverted with their Gram matrix: with D their norms and
+    // C = D^-1 W_J^T W_J D^-1 (unit diagonal; the identity for orthogonal
+    // columns), pinv = V_J D^-1 C^-1 D^-1 W_J^T.  C = L L^T in order of
+    // decreasing norm; a column whose pivot falls below 1e-8 lies in the span
+    // of the larger ones and is dropped.
+    std::vector<double> nrm(n);
     double smax = 0.0;
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += a[(size_t)j * n + i] * a[(size_t)j * n + i];
-        sig2[j] = s;
-        smax = std::max(smax, sqrt(s));
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += a[(size_t)j * n + i] * a[(size_t)j * n + i];
+        nrm[j] = sqrt(c);
+        smax = std::max(smax, nrm[j]);
     }
-    P.assign((size_t)n * n, 0.0);
-    for (int j = 0; j < n; ++j) {
-        if (!(sqrt(sig2[j]) > rcond * smax)) continue;
-        const double inv = 1.0 / sig2[j];
-        for (int i = 0; i < n; ++i) {
-            const double vi = v[(size_t)j * n + i] * inv;
-            if (vi == 0.0) continue;
-            double* row = &P[(size_t)i * n];
-            const double* w = &a[(size_t)j * n];
-            for (int k = 0; k < n; ++k) row[k] += vi * w[k];
+    std::vector<int> J;
+    for (int j = 0; j < n; ++j)
+        if (nrm[j] > rcond * smax) J.push_back(j);
+    std::stable_sort(J.begin(), J.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
+    const int r = (int)J.size();
+    std::vector<double> L((size_t)r * r, 0.0), Y((size_t)r * n);
+    std::vector<char> keep(r, 1);
+    parallel_ranges(r, nth, [&](int64_t x0, int64_t x1) {
+        for (int64_t x = x0; x < x1; ++x) {
+            const double* wx = &a[(size_t)J[x] * n];
+            for (int y = 0; y <= x; ++y) {
+                const double* wy = &a[(size_t)J[y] * n];
+                double g = 0.0;
+                for (int i = 0; i < n; ++i) g += wx[i] * wy[i];
+                L[(size_t)x * r + y] = g / (nrm[J[x]] * nrm[J[y]]);
+            }
+        }
+    });
+    for (int j = 0; j < r; ++j) {                       // Cholesky, lower triangle in place
+        double d = L[(size_t)j * r + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * r + k] * L[(size_t)j * r + k];
+        if (!(d > 1e-8)) {
+            keep[j] = 0;
+            for (int i = j; i < r; ++i) L[(size_t)i * r + j] = 0.0;
+            continue;
+        }
+        const double dj = sqrt(d);
+        L[(size_t)j * r + j] = dj;
+        for (int i = j + 1; i < r; ++i) {
+            double t = L[(size_t)i * r + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * r + k] * L[(size_t)j * r + k];
+            L[(size_t)i * r + j] = t / dj;
         }
     }
+    // Y = C^-1 D^-1 W_J^T by forward and back substitution (dropped rows
+    // zero); the columns i of Y are independent, so threads take ranges of i
+    for (int x = 0; x < r; ++x)
+        for (int i = 0; i < n; ++i) Y[(size_t)x * n + i] = keep[x] ? a[(size_t)J[x] * n + i] / nrm[J[x]] : 0.0;
+    parallel_ranges(n, nth, [&](int64_t i0, int64_t i1) {
+        for (int x = 0; x < r; ++x) {
+            if (!keep[x]) continue;
+            double* yx = &Y[(size_t)x * n];
+            for (int k = 0; k < x; ++k) {
+                const double l = L[(size_t)x * r + k];
+                if (l == 0.0) continue;
+                const double* yk = &Y[(size_t)k * n];
+                for (int64_t i = i0; i < i1; ++i) yx[i] -= l * yk[i];
+            }
+            const double inv = 1.0 / L[(size_t)x * r + x];
+            for (int64_t i = i0; i < i1; ++i) yx[i] *= inv;
+        }
+        for (int x = r - 1; x >= 0; --x) {
+            if (!keep[x]) continue;
+            double* yx = &Y[(size_t)x * n];
+            for (int k = x + 1; k < r; ++k) {
+                const double l = L[(size_t)k * r + x];
+                if (l == 0.0) continue;
+                const double* yk = &Y[(size_t)k * n];
+                for (int64_t i = i0; i < i1; ++i) yx[i] -= l * yk[i];
+            }
+            const double inv = 1.0 / L[(size_t)x * r + x];
+            for (int64_t i = i0; i < i1; ++i) yx[i] *= inv;
+        }
+    });
+    // P = sum over kept x of (v_x / d_x) y_x^T; threads take ranges of rows of P
+    P.assign((size_t)n * n, 0.0);
+    parallel_ranges(n, nth, [&](int64_t i0, int64_t i1) {
+        for (int x = 0; x < r; ++x) {
+            if (!keep[x]) continue;
+            const double* vj = &v[(size_t)J[x] * n];
+            const double* yx = &Y[(size_t)x * n];
+            const double inv = 1.0 / nrm[J[x]];
+            for (int64_t i = i0; i < i1; ++i) {
+                const double vi = vj[i] * inv;
+                if (vi == 0.0) continue;
+                double* row = &P[(size_t)i * n];
+                for (int k = 0; k < n; ++k) row[k] += vi * yx[k];
+            }
+        }
+    });
 }
 
 int fmm_plan_build(int device, int order, stokes_fmm_plan** out, std::string& err) {
@@ -1262,7 +1454,7 @@ int fmm_plan_build(int device, int order, stokes_fmm_plan** out, std::string& er
     const int mp = pad16(n3), kb = pad16(n3 + 1);
     p->mp = mp;
     p->kb = kb;
-    if (kb != mp) {                    // 3 ns is never a multiple of 16 for orders 2..6
+    if (kb != mp) {                    // 3 ns = 6 (3 (p - 1)^2 + 1) is never a multiple of 16
         fmm_plan_free(p);
         err = "internal: M2L block size";
         return -2;
@@ -1405,24 +1597,22 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     g2.npairs = reinterpret_cast<int64_t*>(ws + L.off_sched + 16);
     a.vbuf = g2.vbuf;
     a.mp = plan->mp;
-    const int rb = plan->mp / 16;
+    const int rb = gemm_rb(plan->mp), ngr = gemm_groups(plan->mp, rb);
     // OP V for the listed boxes of a level, into out (rows n3 per box)
     double* apart = reinterpret_cast<double*>(ws + L.off_apart);
     auto apply = [&](int l, const double* op, double* out) {
         // units: tiles x splits <= max(tiles, kApplyUnits), tiles at most the bound below
         const int64_t tiles_ub =
             (std::min<int64_t>((int64_t)1 << (3 * l), std::max(in.n_src, in.n_trg)) + kGemmNT - 1) / kGemmNT;
-        const dim3 g((unsigned)std::max<int64_t>(tiles_ub, kApplyUnits));
-        switch (rb) {
-            case 2: hipLaunchKernelGGL(apply_gemm_kernel<2>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
-            case 5: hipLaunchKernelGGL(apply_gemm_kernel<5>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
-            case 11: hipLaunchKernelGGL(apply_gemm_kernel<11>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
-            case 19: hipLaunchKernelGGL(apply_gemm_kernel<19>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
-            default: hipLaunchKernelGGL(apply_gemm_kernel<29>, g, dim3(kGemmThreads), 0, st, a, g2, op, out, apart); break;
-        }
+        const dim3 g((unsigned)(ngr * std::max<int64_t>(tiles_ub, kApplyUnits)));
+        with_rb(rb, [&](auto r) {
+            hipLaunchKernelGGL(apply_gemm_kernel<decltype(r)::value>, g, dim3(kGemmThreads), 0, st, a, g2, op, out,
+                               apart);
+        });
         if (!chk()) return false;
         // a strided pass: most levels have one split, and then every workgroup just exits
-        hipLaunchKernelGGL(apply_reduce_kernel, dim3(kApplyReduceGrid), dim3(kFBlock), 0, st, a, g2, rb, apart, out);
+        hipLaunchKernelGGL(apply_reduce_kernel, dim3(kApplyReduceGrid), dim3(kFBlock), 0, st, a, g2,
+                           plan->mp / kGemmKC, apart, out);
         return chk();
     };
     // the boxes of level l holding sources: g2.list (box i of the list owns column i)
@@ -1443,24 +1633,20 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
     if (chk() && list_sources(D)) {
         const dim3 g(f_grid(L.n_leaves));
         const size_t lds = p2m_lds(ns, dl ? 1 : 0);
-        if (dl) {
-            if (T == 1) hipLaunchKernelGGL((p2m_kernel<1, 1>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
-            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<1, 2>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
-            else hipLaunchKernelGGL((p2m_kernel<1, 3>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
-        } else {
-            if (T == 1) hipLaunchKernelGGL((p2m_kernel<0, 1>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
-            else if (T == 2) hipLaunchKernelGGL((p2m_kernel<0, 2>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
-            else hipLaunchKernelGGL((p2m_kernel<0, 3>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
-        }
+        with_T(T, [&](auto tc) {
+            constexpr int TT = decltype(tc)::value;
+            if (dl) hipLaunchKernelGGL((p2m_kernel<1, TT>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
+            else hipLaunchKernelGGL((p2m_kernel<0, TT>), g, dim3(kFBlock), lds, st, a, g2.list, g2.ctotal);
+        });
         if (chk()) apply(D, plan->d_upA, a.ue + L.base[D] * a.n3);
     }
     for (int l = D - 1; l >= 2 && chk(); --l) {
         if (!list_sources(l)) break;
         const dim3 g(f_grid((int64_t)1 << (3 * l)));
         const size_t lds = m2m_lds(ns);
-        if (T == 1) hipLaunchKernelGGL(m2m_kernel<1>, g, dim3(kFBlock), lds, st, a, l, g2.list, g2.ctotal);
-        else if (T == 2) hipLaunchKernelGGL(m2m_kernel<2>, g, dim3(kFBlock), lds, st, a, l, g2.list, g2.ctotal);
-        else hipLaunchKernelGGL(m2m_kernel<3>, g, dim3(kFBlock), lds, st, a, l, g2.list, g2.ctotal);
+        with_T(T, [&](auto tc) {
+            hipLaunchKernelGGL(m2m_kernel<decltype(tc)::value>, g, dim3(kFBlock), lds, st, a, l, g2.list, g2.ctotal);
+        });
         if (chk()) apply(l, plan->d_upA, a.ue + L.base[l] * a.n3);
     }
     for (int l = 2; l <= D && chk(); ++l) {
@@ -1484,14 +1670,11 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         // per class at most min(8^(l-1), n_trg) boxes in `tiles` tiles; units per
         // class = splits x tiles <= max(kM2LUnits + tiles, kM2LMinSplits x tiles)
         const int64_t tiles = (std::min<int64_t>(nb >> 3, in.n_trg) + kGemmNT - 1) / kGemmNT;
-        const dim3 gm((unsigned)(8 * std::max<int64_t>(kM2LUnits + tiles, kM2LMinSplits * tiles)));
-        switch (rb) {
-            case 2: hipLaunchKernelGGL(m2l_gemm_kernel<2>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
-            case 5: hipLaunchKernelGGL(m2l_gemm_kernel<5>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
-            case 11: hipLaunchKernelGGL(m2l_gemm_kernel<11>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
-            case 19: hipLaunchKernelGGL(m2l_gemm_kernel<19>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
-            default: hipLaunchKernelGGL(m2l_gemm_kernel<29>, gm, dim3(kGemmThreads), 0, st, a, g2, l); break;
-        }
+        // row groups outermost: grid = 8 classes x row groups x units
+        const dim3 gm((unsigned)(8 * ngr * std::max<int64_t>(kM2LUnits + tiles, kM2LMinSplits * tiles)));
+        with_rb(rb, [&](auto r) {
+            hipLaunchKernelGGL(m2l_gemm_kernel<decltype(r)::value>, gm, dim3(kGemmThreads), 0, st, a, g2, l);
+        });
         if (!chk()) break;
         hipLaunchKernelGGL(m2l_reduce_kernel, dim3(f_grid((std::min<int64_t>(nb, in.n_trg) * plan->mp + kFBlock - 1) / kFBlock)),
                            dim3(kFBlock), 0, st, g2);
@@ -1499,9 +1682,9 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         {
             const dim3 g(f_grid(nb));
             const size_t lds = m2l_lds(ns);
-            if (T == 1) hipLaunchKernelGGL(m2l_pairs_kernel<1>, g, dim3(kFBlock), lds, st, a, g2, l);
-            else if (T == 2) hipLaunchKernelGGL(m2l_pairs_kernel<2>, g, dim3(kFBlock), lds, st, a, g2, l);
-            else hipLaunchKernelGGL(m2l_pairs_kernel<3>, g, dim3(kFBlock), lds, st, a, g2, l);
+            with_T(T, [&](auto tc) {
+                hipLaunchKernelGGL(m2l_pairs_kernel<decltype(tc)::value>, g, dim3(kFBlock), lds, st, a, g2, l);
+            });
         }
         if (!chk()) break;
         if (!apply(l, plan->d_downA, a.de + L.base[l] * a.n3)) break;

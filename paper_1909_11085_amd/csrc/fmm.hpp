@@ -13,7 +13,7 @@ struct stokes_fmm_plan;
 
 namespace stokes {
 
-constexpr int kFmmMinOrder = 2, kFmmMaxOrder = 6;   // points per edge of the cube surfaces
+constexpr int kFmmMinOrder = 2, kFmmMaxOrder = 10;   // points per edge of the cube surfaces
 constexpr int kFmmMinDepth = 2, kFmmMaxDepth = 7;
 
 // Pseudo-inverse of a row-major n x n matrix by one-sided Jacobi SVD,
