@@ -755,10 +755,13 @@ def time_collision(S, W, t, steps, warmup, oracle=True):
 def time_fmm(S, W, t, steps, warmup):
     """The single-layer sum over all 2,088,960 points of the 3,840 cells in the
     vessel (every point a source and a target, no pair rule) by the FMM on a
-    uniform octree of depth 6, at surface orders 4 and 6, against the direct
-    sum (timed once; its 4.4e12 pairs are the O(N^2) baseline) on a seeded
-    sample of 2,000 targets for the error.  Each order also runs with
-    precision="mixed" (float32 near-field pairs)."""
+    uniform octree (depth 6 at surface orders 4 and 6, depth 5 at orders 8 and
+    10, where the larger far-field operators favour fewer levels), against the
+    direct sum (timed once; its 4.4e12 pairs are the O(N^2) baseline) on a
+    seeded sample of 2,000 targets for the error.  Each order also runs with
+    precision="mixed" (float32 near-field pairs).  Then the wall's double
+    layer at the cells' points (cfg5) at orders 6 and 10.  Plan creation (the
+    operators; about 26 s at order 10) is outside the timings."""
     import torch
 
     cfg = W.make_config(4)
@@ -767,12 +770,19 @@ def time_fmm(S, W, t, steps, warmup):
     ctr, R = 0.5 * (lo + hi), 0.5 * float((hi - lo).max()) * 1.0001
     pos, f, w = t(c.pos), t(cfg["f"]), t(c.weight)
     depth = 6
-    r = {"points": c.n, "depth": depth, "leaves": 8 ** depth, "domain_half_width": R}
+    depths = {4: 6, 6: 6, 8: 5, 10: 5}
+    r = {"points": c.n, "depth": depth, "leaves": 8 ** depth, "domain_half_width": R,
+         "depth_by_order": {str(k): v for k, v in depths.items()}}
     pick = W.subset(np.random.default_rng(74), c.n, 2000)
     ref = S.sl(pos, f, w, t(c.pos[:, pick])).cpu().numpy()
     out = torch.empty((3, c.n), dtype=torch.float64, device=pos.device)
-    for order in (4, 6):
+    for order in (4, 6, 8, 10):
+        depth = depths[order]
+        t0 = time.perf_counter()
         plan = S.FMMPlan(order)
+        torch.cuda.synchronize()
+        r[f"order{order}_plan_s"] = time.perf_counter() - t0
+        print(f"fmm: order {order} plan ready ({r[f'order{order}_plan_s']:.1f} s)", file=sys.stderr, flush=True)
         for _ in range(warmup):
             S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out)
         torch.cuda.synchronize()
@@ -813,13 +823,14 @@ def time_fmm(S, W, t, steps, warmup):
             r["order4_graph_ms"] = e0.elapsed_time(e1) / steps
             r["order4_graph_equals_eager"] = bool(np.array_equal(out.cpu().numpy()[:, pick], got))
             del graph
-        if order == 6:
+        if order in (6, 10):
             # the same-cell rule of Sec. 2.2: each cell's sum onto itself taken off
             # exactly, against the direct sum with that rule on the same sample
             grp = t(c.group.astype(np.int32))
             ng = int(c.group.max()) + 1
-            ref_ex = S.sl(pos, f, w, t(c.pos[:, pick]), src_group=grp, trg_group=t(c.group[pick].astype(np.int32)),
-                          exclude_same_group=True).cpu().numpy()
+            if order == 6:                                 # the rule's direct reference, once
+                ref_ex = S.sl(pos, f, w, t(c.pos[:, pick]), src_group=grp,
+                              trg_group=t(c.group[pick].astype(np.int32)), exclude_same_group=True).cpu().numpy()
             S.fmm_sl(plan, pos, f, w, pos, tuple(ctr), R, depth, out=out, src_group=grp, trg_group=grp, n_groups=ng)
             torch.cuda.synchronize()
             e0.record()
@@ -829,8 +840,8 @@ def time_fmm(S, W, t, steps, warmup):
             e1.record()
             torch.cuda.synchronize()
             ge = out.cpu().numpy()[:, pick]
-            r["order6_same_cell_ms"] = e0.elapsed_time(e1) / steps
-            r["order6_same_cell_rel_l2_vs_direct"] = float(np.linalg.norm(ge - ref_ex) / np.linalg.norm(ref_ex))
+            r[f"order{order}_same_cell_ms"] = e0.elapsed_time(e1) / steps
+            r[f"order{order}_same_cell_rel_l2_vs_direct"] = float(np.linalg.norm(ge - ref_ex) / np.linalg.norm(ref_ex))
         del plan
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -839,8 +850,8 @@ def time_fmm(S, W, t, steps, warmup):
     torch.cuda.synchronize()
     r["direct_ms"] = e0.elapsed_time(e1)
     r["direct_pairs"] = c.n * c.n
-    r["speedup_order4_vs_direct"] = r["direct_ms"] / r["order4_ms"]
-    r["speedup_order6_vs_direct"] = r["direct_ms"] / r["order6_ms"]
+    for order in depths:
+        r[f"speedup_order{order}_vs_direct"] = r["direct_ms"] / r[f"order{order}_ms"]
     # the wall's double layer (1,048,576 nodes) at the 522,240 points of 960 cells, order 6
     cfg5 = W.make_config(5)
     wall, cells = cfg5["wall"], cfg5["cells"]
@@ -852,25 +863,29 @@ def time_fmm(S, W, t, steps, warmup):
     pick5 = W.subset(np.random.default_rng(81), cells.n, 2000)
     ref5 = S.dl(*args, t(cells.pos[:, pick5])).cpu().numpy()
     u5 = torch.empty((3, cells.n), dtype=torch.float64, device=pos.device)
-    plan = S.FMMPlan(6)
-    for _ in range(warmup):
-        S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, depth, out=u5)
-    e0.record()
-    for _ in range(steps):
-        S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, depth, out=u5)
-    e1.record()
-    torch.cuda.synchronize()
-    r["dl_wall_to_cells_order6_ms"] = e0.elapsed_time(e1) / steps
-    r["dl_wall_to_cells_order6_rel_l2_vs_direct"] = float(
-        np.linalg.norm(u5.cpu().numpy()[:, pick5] - ref5) / np.linalg.norm(ref5))
-    e0.record()
-    for _ in range(steps):
-        S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, depth, out=u5, precision="mixed")
-    e1.record()
-    torch.cuda.synchronize()
-    r["dl_wall_to_cells_order6_mixed_ms"] = e0.elapsed_time(e1) / steps
-    r["dl_wall_to_cells_order6_mixed_rel_l2_vs_direct"] = float(
-        np.linalg.norm(u5.cpu().numpy()[:, pick5] - ref5) / np.linalg.norm(ref5))
+    for order, d5 in ((6, 6), (10, 5)):
+        plan = S.FMMPlan(order)
+        print(f"fmm: wall double layer, order {order} plan ready", file=sys.stderr, flush=True)
+        for _ in range(warmup):
+            S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, d5, out=u5)
+        e0.record()
+        for _ in range(steps):
+            S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, d5, out=u5)
+        e1.record()
+        torch.cuda.synchronize()
+        r[f"dl_wall_to_cells_order{order}_depth"] = d5
+        r[f"dl_wall_to_cells_order{order}_ms"] = e0.elapsed_time(e1) / steps
+        r[f"dl_wall_to_cells_order{order}_rel_l2_vs_direct"] = float(
+            np.linalg.norm(u5.cpu().numpy()[:, pick5] - ref5) / np.linalg.norm(ref5))
+        e0.record()
+        for _ in range(steps):
+            S.fmm_dl(plan, *args, cp, tuple(ctr5), R5, d5, out=u5, precision="mixed")
+        e1.record()
+        torch.cuda.synchronize()
+        r[f"dl_wall_to_cells_order{order}_mixed_ms"] = e0.elapsed_time(e1) / steps
+        r[f"dl_wall_to_cells_order{order}_mixed_rel_l2_vs_direct"] = float(
+            np.linalg.norm(u5.cpu().numpy()[:, pick5] - ref5) / np.linalg.norm(ref5))
+        del plan
     e0.record()
     S.dl(*args, cp, out=u5)
     e1.record()
