@@ -75,6 +75,7 @@ extern "C" {
 #define STOKES_OP_SL_VJP  4
 #define STOKES_OP_DL_VJP  5
 #define STOKES_OP_P2P_SL_VJP 6
+#define STOKES_OP_P2P_DL_VJP 7
 
 /* Largest point count per side accepted by any call. */
 #define STOKES_MAX_POINTS ((int64_t)1 << 30)
@@ -175,7 +176,8 @@ int stokes_timing_read(stokes_ctx* ctx, double* total_ms, int64_t* launches);
 
 /* Bytes of workspace that a call of kind `op` (STOKES_OP_*) with these sizes
  * and options needs.  For leaf-to-leaf ops n_leaves is the leaf count, and
- * for STOKES_OP_P2P_SL_VJP n_ulist the list length; others ignore them.  May
+ * for STOKES_OP_P2P_SL_VJP / _DL_VJP n_ulist the list length; others ignore
+ * them.  May
  * be 0.  For STOKES_OP_SL with n_src == n_trg the size covers the
  * each-pair-once sum of a shared point set (its column partials grow as n^2:
  * about 0.9 GB for 278,528 points); a workspace of at least the size for
@@ -349,6 +351,24 @@ int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, con
                       const stokes_opts* opts, const double* grad_vel, double* grad_density,
                       double* grad_src_xyz, double* grad_trg_xyz, void* workspace, size_t ws_bytes,
                       void* stream);
+
+/* Double-layer adjoint of stokes_p2p_leaf_eval: the sums of stokes_dl_vjp
+ * restricted to the listed pairs, in float64, with d = 6/(8 pi):
+ *   grad_trg_xyz  (3,n_trg): d sum over listed m of G_nm  (forward lists);
+ *   grad_density  (3,n_src): dL/dphi_m = d w_m sum over the targets n of the
+ *                            leaves listing m's leaf of r (r.n_m)(r.g_n)/rho^5;
+ *   grad_src_xyz  (3,n_src): -d sum over the same n of G_nm
+ * (G as at stokes_dl_vjp; the source-side sums on the transposed lists).
+ * Outputs, layout checks, NaN on malformed leaf arrays, determinism and empty
+ * sets as stokes_p2p_sl_vjp.  Workspace: stokes_workspace_size(
+ * STOKES_OP_P2P_DL_VJP, n_src, n_trg, n_leaves, n_ulist). */
+int stokes_p2p_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                      const double* weight, const double* normal, int64_t n_trg, const double* trg_xyz,
+                      int32_t n_leaves, const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs,
+                      const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist,
+                      const stokes_exclusion* excl, const stokes_opts* opts, const double* grad_vel,
+                      double* grad_density, double* grad_src_xyz, double* grad_trg_xyz, void* workspace,
+                      size_t ws_bytes, void* stream);
 
 /* ---- check-point quadrature on and near a patched surface, Sec. 3.1 ------ */
 

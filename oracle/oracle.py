@@ -187,6 +187,34 @@ def p2p_sl_vjp(src, f, w, trg, g, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, 
     return gf, gy, gx
 
 
+def p2p_dl_vjp(src, phi, w, nrm, trg, g, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, src_group=None,
+               trg_group=None, exclude_same_group=False):
+    """Adjoint of the double-layer leaf-to-leaf sum, (dL/dphi, dL/dsrc,
+    dL/dtrg) for dL/du = g: as p2p_sl_vjp, leaf by leaf the adjoint (dl_vjp)
+    of the direct sum from the concatenated sources of the leaf's list."""
+    ns, nt = src.shape[1], trg.shape[1]
+    y, p, w, nv = _vec(src, ns), _vec(phi, ns), _scal(w, ns), _vec(nrm, ns)
+    x, g = _vec(trg, nt), _vec(g, nt)
+    gs, gt = _groups(src_group, ns), _groups(trg_group, nt)
+    so, to = np.asarray(src_leaf_ofs, dtype=np.int64), np.asarray(trg_leaf_ofs, dtype=np.int64)
+    uo, ul = np.asarray(ulist_ofs, dtype=np.int64), np.asarray(ulist, dtype=np.int64)
+    gp, gy, gx = np.zeros((3, ns)), np.zeros((3, ns)), np.zeros((3, nt))
+    for L in range(len(so) - 1):
+        t = np.arange(to[L], to[L + 1])
+        if t.size == 0:
+            continue
+        m = np.concatenate([np.arange(so[k], so[k + 1]) for k in ul[uo[L]:uo[L + 1]]] + [np.zeros(0, np.int64)])
+        if m.size == 0:
+            continue
+        a, b, c = dl_vjp(y[:, m], p[:, m], w[m], nv[:, m], x[:, t], g[:, t], src_group=gs[m], trg_group=gt[t],
+                         exclude_same_group=exclude_same_group)
+        for q in range(3):
+            np.add.at(gp[q], m, a[q])
+            np.add.at(gy[q], m, b[q])
+        gx[:, t] += c
+    return gp, gy, gx
+
+
 def dl_vjp(src, phi, w, nrm, trg, g, src_group=None, trg_group=None, exclude_same_group=False,
            want=("phi", "src", "trg")):
     """Returns (dL/dphi, dL/dsrc, dL/dtrg) for dL/du = g; entries not in ``want`` are None."""

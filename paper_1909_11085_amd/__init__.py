@@ -9,7 +9,7 @@ hand-written HIP kernels behind the C ABI of ``include/stokes_mi355x.h``.
 ``workloads`` (seeded synthetic inputs) imports without torch; the compute
 API (``sl``, ``dl``, ...) loads the HIP library on first use.
 """
-_API = ("sl", "dl", "sl_vjp", "dl_vjp", "sl_diff", "dl_diff", "p2p_leaf", "p2p_sl_vjp", "p2p_diff", "P2PPlan",
+_API = ("sl", "dl", "sl_vjp", "dl_vjp", "sl_diff", "dl_diff", "p2p_leaf", "p2p_sl_vjp", "p2p_dl_vjp", "p2p_diff", "P2PPlan",
         "context",
         "set_grid_override", "set_pair_symmetry", "debug_pair_classes", "StokesSL", "StokesDL", "StokesP2P",
         "timing_enable", "timing_read",

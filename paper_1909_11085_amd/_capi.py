@@ -18,7 +18,7 @@ OK, EINVAL, EDEVICE, ELAUNCH, EWORKSPACE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 EXCL_NONE, EXCL_SAME_GROUP = 0, 1
 KERNEL_SL, KERNEL_DL = 0, 1
-OP_SL, OP_DL, OP_P2P_SL, OP_P2P_DL, OP_SL_VJP, OP_DL_VJP, OP_P2P_SL_VJP = range(7)
+OP_SL, OP_DL, OP_P2P_SL, OP_P2P_DL, OP_SL_VJP, OP_DL_VJP, OP_P2P_SL_VJP, OP_P2P_DL_VJP = range(8)
 NOALLOC_SCRATCH_BYTES = 64 << 20
 PAIR_F32, PAIR_F64, PAIR_SKIP = 1, 1 << 8, 1 << 16
 STATUS_NAMES = {OK: "STOKES_OK", EINVAL: "STOKES_EINVAL", EDEVICE: "STOKES_EDEVICE",
@@ -89,6 +89,8 @@ _SIGNATURES = {
                                      _vp, _vp, _vp, _vp, _sz, _vp]),
     "stokes_p2p_sl_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _i64,
                                          _dbl, _EX, _OP, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "stokes_p2p_dl_vjp": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _i64,
+                                         _EX, _OP, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "stokes_patch_upsample": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "stokes_checkpoint_workspace_size": (ctypes.c_int, [_vp, _i64, _PR, _i64, _OP, ctypes.POINTER(_sz)]),
     "stokes_dl_checkpoint_eval": (ctypes.c_int, [_vp, _i64, _PR, _vp, _vp, _i64, _vp, _vp, _OP, _vp, _vp,

@@ -449,43 +449,76 @@ def p2p_sl_vjp(layout, src, f, w, trg, grad_u, mu=1.0, src_group=None, trg_group
     return gf, gs, gt
 
 
+def p2p_dl_vjp(layout, src, phi, w, nrm, trg, grad_u, src_group=None, trg_group=None, exclude_same_group=None,
+               grad_phi=None, grad_src=None, grad_trg=None, accumulate=False):
+    """Vector-Jacobian product of the double-layer leaf-to-leaf sum (see
+    stokes_p2p_dl_vjp); arguments as p2p_sl_vjp, plus the source normals."""
+    device = src.device
+    _vec3(src, "src", device); _vec3(phi, "phi", device); _vec3(nrm, "nrm", device); _vec3(trg, "trg", device)
+    _vec3(grad_u, "grad_u", device)
+    ns, nt = src.shape[1], trg.shape[1]
+    _vec1(w, ns, "w", device)
+    if phi.shape[1] != ns or nrm.shape[1] != ns or grad_u.shape[1] != nt:
+        raise ValueError("phi and nrm must match src and grad_u must match trg")
+    so, to, uo, ul, n_leaves = _device_layout(layout, device)
+    rule = _Rule(device, ns, nt, src_group, trg_group, exclude_same_group, "fp64", None, 0.0)
+    rule.opts.accumulate = int(bool(accumulate))
+    gp, gs, gt = (_grad_out(grad_phi, ns, "grad_phi", device), _grad_out(grad_src, ns, "grad_src", device),
+                  _grad_out(grad_trg, nt, "grad_trg", device))
+    ws, size = _workspace(C.OP_P2P_DL_VJP, ns, nt, n_leaves, rule.opts, device, n_ulist=ul.numel())
+    C.check(C.lib().stokes_p2p_dl_vjp(context(device), ns, _ptr(src), _ptr(phi), _ptr(w), _ptr(nrm), nt, _ptr(trg),
+                                      n_leaves, _ptr(so), _ptr(to), _ptr(uo), _ptr(ul), ul.numel(),
+                                      ctypes.byref(rule.ex), ctypes.byref(rule.opts), _ptr(grad_u), _ptr(gp),
+                                      _ptr(gs), _ptr(gt), _ptr(ws), size, _stream(device)))
+    return gp, gs, gt
+
+
 class StokesP2P(torch.autograd.Function):
-    """Single-layer leaf-to-leaf sum differentiable in the density and in both
-    point sets (weights are constants).  The backward runs the float64
-    adjoint over the same lists; on a shared point set autograd adds the
-    source-side and target-side position gradients."""
+    """Leaf-to-leaf sum (single or double layer) differentiable in the density
+    and in both point sets (weights and normals are constants).  The backward
+    runs the float64 adjoint over the same lists; on a shared point set
+    autograd adds the source-side and target-side position gradients."""
 
     @staticmethod
-    def forward(ctx, layout, src, f, w, trg, mu, src_group, trg_group, exclude_same_group, precision, group_h,
-                near_frac):
-        u = p2p_leaf(layout, src, f, w, trg, kernel="sl", mu=mu, src_group=src_group, trg_group=trg_group,
-                     exclude_same_group=exclude_same_group, precision=precision, group_h=group_h,
-                     near_frac=near_frac)
-        ctx.save_for_backward(src, f, w, trg)
+    def forward(ctx, layout, src, f, w, trg, kernel, nrm, mu, src_group, trg_group, exclude_same_group, precision,
+                group_h, near_frac):
+        u = p2p_leaf(layout, src, f, w, trg, kernel=kernel, nrm=nrm, mu=mu, src_group=src_group,
+                     trg_group=trg_group, exclude_same_group=exclude_same_group, precision=precision,
+                     group_h=group_h, near_frac=near_frac)
+        ctx.save_for_backward(src, f, w, trg, nrm)
         ctx.layout = layout
-        ctx.args = (mu, src_group, trg_group, exclude_same_group)
+        ctx.args = (kernel, mu, src_group, trg_group, exclude_same_group)
         return u
 
     @staticmethod
     def backward(ctx, grad_u):
-        src, f, w, trg = ctx.saved_tensors
-        mu, sg, tg, ex = ctx.args
+        src, f, w, trg, nrm = ctx.saved_tensors
+        kernel, mu, sg, tg, ex = ctx.args
         need_src, need_f, need_trg = ctx.needs_input_grad[1], ctx.needs_input_grad[2], ctx.needs_input_grad[4]
         grad_u = grad_u.contiguous()
         gf = _empty3(src.shape[1], src) if need_f else None
         gs = _empty3(src.shape[1], src) if need_src else None
         gt = _empty3(trg.shape[1], trg) if need_trg else None
         if gf is not None or gs is not None or gt is not None:
-            p2p_sl_vjp(ctx.layout, src, f, w, trg, grad_u, mu=mu, src_group=sg, trg_group=tg, exclude_same_group=ex,
-                       grad_f=gf, grad_src=gs, grad_trg=gt)
-        return None, gs, gf, None, gt, None, None, None, None, None, None, None
+            if kernel == "sl":
+                p2p_sl_vjp(ctx.layout, src, f, w, trg, grad_u, mu=mu, src_group=sg, trg_group=tg,
+                           exclude_same_group=ex, grad_f=gf, grad_src=gs, grad_trg=gt)
+            else:
+                p2p_dl_vjp(ctx.layout, src, f, w, nrm, trg, grad_u, src_group=sg, trg_group=tg,
+                           exclude_same_group=ex, grad_phi=gf, grad_src=gs, grad_trg=gt)
+        return None, gs, gf, None, gt, None, None, None, None, None, None, None, None, None
 
 
-def p2p_diff(layout, src, f, w, trg, mu=1.0, src_group=None, trg_group=None, exclude_same_group=None,
-             precision="fp64", group_h=None, near_frac=0.5):
-    """Differentiable single-layer leaf-to-leaf sum (torch.autograd)."""
-    return StokesP2P.apply(layout, src, f, w, trg, mu, src_group, trg_group, exclude_same_group, precision,
-                           group_h, near_frac)
+def p2p_diff(layout, src, f, w, trg, kernel="sl", nrm=None, mu=1.0, src_group=None, trg_group=None,
+             exclude_same_group=None, precision="fp64", group_h=None, near_frac=0.5):
+    """Differentiable leaf-to-leaf sum (torch.autograd), single layer (f is the
+    density) or double layer (f is phi, nrm the source normals)."""
+    if kernel not in ("sl", "dl"):
+        raise ValueError("kernel must be 'sl' or 'dl'")
+    if kernel == "dl" and nrm is None:
+        raise ValueError("the double layer needs nrm")
+    return StokesP2P.apply(layout, src, f, w, trg, kernel, nrm, mu, src_group, trg_group, exclude_same_group,
+                           precision, group_h, near_frac)
 
 
 # ----------------------------------------------------------------------------

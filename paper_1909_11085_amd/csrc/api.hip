@@ -575,9 +575,11 @@ int stokes_workspace_size(const stokes_ctx* ctx, int32_t op, int64_t n_src, int6
             *bytes = stokes::p2p_workspace_bytes(op == STOKES_OP_P2P_SL ? 0 : 1, mixed, n_src, n_trg, n_leaves);
             return STOKES_OK;
         case STOKES_OP_P2P_SL_VJP:
+        case STOKES_OP_P2P_DL_VJP:
             if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
             if (n_ulist < 0) return fail(STOKES_EINVAL, "n_ulist must be >= 0");
-            *bytes = stokes::p2p_vjp_workspace_bytes(n_src, n_trg, n_leaves, n_ulist);
+            *bytes = stokes::p2p_vjp_workspace_bytes(op == STOKES_OP_P2P_SL_VJP ? 0 : 1, n_src, n_trg, n_leaves,
+                                                     n_ulist);
             return STOKES_OK;
         case STOKES_OP_SL_VJP:
         case STOKES_OP_DL_VJP:
@@ -832,20 +834,19 @@ int stokes_p2p_leaf_eval(stokes_ctx* ctx, int32_t kernel, int64_t n_src, const d
                          "stokes_p2p_leaf_eval");
 }
 
-int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
-                      const double* weight, int64_t n_trg, const double* trg_xyz, int32_t n_leaves,
-                      const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs, const int64_t* ulist_ofs,
-                      const int32_t* ulist, int64_t n_ulist, double mu, const stokes_exclusion* excl,
-                      const stokes_opts* opts, const double* grad_vel, double* grad_density, double* grad_src_xyz,
-                      double* grad_trg_xyz, void* workspace, size_t ws_bytes, void* stream) {
-    const char* name = "stokes_p2p_sl_vjp";
+static int p2p_vjp_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* src_xyz, const double* density,
+                        const double* weight, const double* normal, int64_t n_trg, const double* trg_xyz,
+                        int32_t n_leaves, const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs,
+                        const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, double pref,
+                        const stokes_exclusion* excl, const stokes_opts* opts, const double* grad_vel,
+                        double* grad_density, double* grad_src_xyz, double* grad_trg_xyz, void* workspace,
+                        size_t ws_bytes, void* stream, const char* name) {
     if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
-    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
     if (n_leaves < 0) return fail(STOKES_EINVAL, "n_leaves must be >= 0");
     if (n_ulist < 0 || n_ulist > INT32_MAX) return fail(STOKES_EINVAL, "n_ulist must be in [0, 2^31)");
     int rc = check_sizes(n_src, n_trg);
     if (rc) return rc;
-    rc = check_points(STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz);
+    rc = check_points(kernel, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz);
     if (rc) return rc;
     if (!arr_ok(grad_vel, 3 * n_trg, 8) || (n_trg > 0 && !grad_vel))
         return fail(STOKES_EINVAL, "grad_vel must be non-NULL and 8-byte aligned");
@@ -864,7 +865,7 @@ int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, con
     for (int a = 0; a < 3; ++a) {
         if (!outs[a].ptr) continue;
         if ((rc = check_no_alias(outs[a].ptr, outs[a].bytes, outs[a].name,
-                                 {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {trg_xyz, tb},
+                                 {{src_xyz, sb}, {density, sb}, {weight, (size_t)n_src * 8}, {normal, sb}, {trg_xyz, tb},
                                   {grad_vel, tb}, {workspace, ws_bytes}, {src_leaf_ofs, ob}, {trg_leaf_ofs, ob},
                                   {ulist_ofs, ob}, {ulist, (size_t)n_ulist * 4}})))
             return rc;
@@ -872,7 +873,7 @@ int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, con
             if (outs[b].ptr && overlaps(outs[a].ptr, outs[a].bytes, outs[b].ptr, outs[b].bytes))
                 return fail(STOKES_EINVAL, std::string(outs[a].name) + " overlaps " + outs[b].name);
     }
-    rc = check_workspace(workspace, ws_bytes, stokes::p2p_vjp_workspace_bytes(n_src, n_trg, n_leaves, n_ulist));
+    rc = check_workspace(workspace, ws_bytes, stokes::p2p_vjp_workspace_bytes(kernel, n_src, n_trg, n_leaves, n_ulist));
     if (rc) return rc;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
@@ -887,12 +888,37 @@ int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, con
     }
     Parsed pf = p;
     pf.precision = STOKES_FP64;                // adjoints run in float64
-    stokes::SumInputs in = make_inputs(STOKES_KERNEL_SL, pf, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz,
-                                       1.0 / (8.0 * kPi * mu));
-    return launch_status(stokes::launch_p2p_sl_vjp(in, n_leaves, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist,
-                                                   n_ulist, grad_vel, grad_density, grad_src_xyz, grad_trg_xyz,
-                                                   p.accumulate, workspace, st),
+    stokes::SumInputs in = make_inputs(kernel, pf, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz, pref);
+    return launch_status(stokes::launch_p2p_vjp(in, n_leaves, src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, n_ulist,
+                                                grad_vel, grad_density, grad_src_xyz, grad_trg_xyz, p.accumulate,
+                                                workspace, st),
                          name);
+}
+
+int stokes_p2p_sl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                      const double* weight, int64_t n_trg, const double* trg_xyz, int32_t n_leaves,
+                      const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs, const int64_t* ulist_ofs,
+                      const int32_t* ulist, int64_t n_ulist, double mu, const stokes_exclusion* excl,
+                      const stokes_opts* opts, const double* grad_vel, double* grad_density, double* grad_src_xyz,
+                      double* grad_trg_xyz, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return fail(STOKES_EINVAL, "ctx is NULL");
+    if (!(isfinite(mu) && mu > 0.0)) return fail(STOKES_EINVAL, "mu must be finite and > 0");
+    return p2p_vjp_eval(ctx, STOKES_KERNEL_SL, n_src, src_xyz, density, weight, nullptr, n_trg, trg_xyz, n_leaves,
+                        src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, n_ulist, 1.0 / (8.0 * kPi * mu), excl, opts,
+                        grad_vel, grad_density, grad_src_xyz, grad_trg_xyz, workspace, ws_bytes, stream,
+                        "stokes_p2p_sl_vjp");
+}
+
+int stokes_p2p_dl_vjp(stokes_ctx* ctx, int64_t n_src, const double* src_xyz, const double* density,
+                      const double* weight, const double* normal, int64_t n_trg, const double* trg_xyz,
+                      int32_t n_leaves, const int64_t* src_leaf_ofs, const int64_t* trg_leaf_ofs,
+                      const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, const stokes_exclusion* excl,
+                      const stokes_opts* opts, const double* grad_vel, double* grad_density, double* grad_src_xyz,
+                      double* grad_trg_xyz, void* workspace, size_t ws_bytes, void* stream) {
+    return p2p_vjp_eval(ctx, STOKES_KERNEL_DL, n_src, src_xyz, density, weight, normal, n_trg, trg_xyz, n_leaves,
+                        src_leaf_ofs, trg_leaf_ofs, ulist_ofs, ulist, n_ulist, 6.0 / (8.0 * kPi), excl, opts,
+                        grad_vel, grad_density, grad_src_xyz, grad_trg_xyz, workspace, ws_bytes, stream,
+                        "stokes_p2p_dl_vjp");
 }
 
 static int vjp_eval(stokes_ctx* ctx, int kernel, int64_t n_src, const double* src_xyz,

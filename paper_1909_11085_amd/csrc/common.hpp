@@ -72,6 +72,7 @@ struct SumInputs {
     const int32_t* trg_perm;
     // leaf-to-leaf kernel-gradient sums (kernel = 2): per-target vector (3, n_trg)
     const double* trg_vec;
+    const double* trg_vec2;    // a second vector per target (leaf-to-leaf adjoint sums, kernel 5)
 };
 
 // class codes of pair_class (one pair taken once holds exactly one of them)

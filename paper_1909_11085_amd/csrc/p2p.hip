@@ -72,8 +72,13 @@ template <> struct P2PRec<0, 0> { using type = SrcSL64; };
 template <> struct P2PRec<1, 0> { using type = SrcDL64; };
 template <> struct P2PRec<0, 1> { using type = P2PSL32; };
 template <> struct P2PRec<1, 1> { using type = P2PDL32; };
-// kernel 2: the single layer's gradient sums (adjoint), float64 only
+// kernels 2 .. 5: the adjoint sums, float64 only (the pair forms at pair64)
 template <> struct P2PRec<2, 0> { using type = SrcSL64; };
+template <> struct P2PRec<3, 0> { using type = SrcDL64; };
+template <> struct P2PRec<4, 0> { using type = SrcSL64; };
+template <> struct P2PRec<5, 0> { using type = SrcSL64; };
+// kernels whose source records carry a normal
+template <int KT> constexpr bool kSrcNormal = KT == 1 || KT == 3;
 
 struct P2PArgs {
     SumInputs in;
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(kWave) void p2p_prep(P2PArgs a) {
         for (int c = 0; c < 3; ++c) {
             y[c] = in.src_xyz[c * n + i];
             q[c] = w * in.density[c * n + i];
-            if (KT == 1) nv[c] = in.normal[c * n + i];
+            if (kSrcNormal<KT>) nv[c] = in.normal[c * n + i];
         }
         int32_t g = in.src_group ? in.src_group[i] : 0;
         double rn = 0.0;
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kWave) void p2p_prep(P2PArgs a) {
         if constexpr (MIXED == 0) {
             r.x = y[0]; r.y = y[1]; r.z = y[2];
             r.qx = q[0]; r.qy = q[1]; r.qz = q[2];
-            if constexpr (KT == 1) { r.nx = nv[0]; r.ny = nv[1]; r.nz = nv[2]; r.pad = 0.0; }
+            if constexpr (kSrcNormal<KT>) { r.nx = nv[0]; r.ny = nv[1]; r.nz = nv[2]; r.pad = 0.0; }
             a.grp[i] = g;
         } else {
             const double o0 = y[0] - ctr[0], o1 = y[1] - ctr[1], o2 = y[2] - ctr[2];
@@ -175,13 +180,33 @@ __device__ __forceinline__ double rinv(double r2, bool skip) {
     return __builtin_fma(0.5 * y0, e, y0);
 }
 
+// G(r; a, b, c) = [(r.b)(r.c) a + (r.a)(r.c) b + (r.a)(r.b) c]/rho^5
+//                 - 5 (r.a)(r.b)(r.c) r/rho^7,
+// the gradient in r of (r.a)(r.b)(r.c)/rho^5 (symmetric in a, b, c; even in r),
+// added to (ax, ay, az); ri2 = 1/rho^2, ri5 = 1/rho^5.
+__device__ __forceinline__ void grad3(double dx, double dy, double dz, double ri2, double ri5, const double (&va)[3],
+                                      const double (&vb)[3], const double (&vc)[3], double& ax, double& ay,
+                                      double& az) {
+    const double ra = __builtin_fma(dx, va[0], __builtin_fma(dy, va[1], dz * va[2]));
+    const double rb = __builtin_fma(dx, vb[0], __builtin_fma(dy, vb[1], dz * vb[2]));
+    const double rc = __builtin_fma(dx, vc[0], __builtin_fma(dy, vc[1], dz * vc[2]));
+    const double bc = rb * rc * ri5, ac = ra * rc * ri5, ab = ra * rb * ri5;
+    const double cr = -5.0 * ra * bc * ri2;
+    ax = __builtin_fma(bc, va[0], __builtin_fma(ac, vb[0], __builtin_fma(ab, vc[0], __builtin_fma(cr, dx, ax))));
+    ay = __builtin_fma(bc, va[1], __builtin_fma(ac, vb[1], __builtin_fma(ab, vc[1], __builtin_fma(cr, dy, ay))));
+    az = __builtin_fma(bc, va[2], __builtin_fma(ac, vb[2], __builtin_fma(ab, vc[2], __builtin_fma(cr, dz, az))));
+}
+
 // KT 0: q/rho + r (r.q)/rho^3; KT 1: r (r.n)(r.q)/rho^5; KT 2: the gradient in
 // r of a.S(r)b times 8 pi mu, with a = tv (the target's vector) and b = q:
-//   K(r; a, b) = [(r.b) a + (r.a) b - (a.b) r]/rho^3 - 3 (r.a)(r.b) r/rho^5.
+//   K(r; a, b) = [(r.b) a + (r.a) b - (a.b) r]/rho^3 - 3 (r.a)(r.b) r/rho^5;
+// KT 3: G(r; n, q, tv) (the double layer's gradient, source normal n);
+// KT 4: r (r.tv)(r.q)/rho^5 (the double-layer form with the normal at the
+// target); KT 5: G(r; tv, tv2, q).
 template <int KT, bool MASKED>
 __device__ __forceinline__ void pair64(const typename P2PRec<KT, 0>::type& s, double x, double y,
-                                       double z, const double (&tv)[3], bool skip_group, double& ax, double& ay,
-                                       double& az) {
+                                       double z, const double (&tv)[3], const double (&tv2)[3], bool skip_group,
+                                       double& ax, double& ay, double& az) {
     const double dx = x - s.x, dy = y - s.y, dz = z - s.z;
     const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
     const double ri = rinv(r2, MASKED && (skip_group || r2 == 0.0));
@@ -201,6 +226,18 @@ __device__ __forceinline__ void pair64(const typename P2PRec<KT, 0>::type& s, do
         ax = __builtin_fma(__builtin_fma(c, dx, s.qx), ri, ax);
         ay = __builtin_fma(__builtin_fma(c, dy, s.qy), ri, ay);
         az = __builtin_fma(__builtin_fma(c, dz, s.qz), ri, az);
+    } else if constexpr (KT == 3) {
+        const double sn[3] = {s.nx, s.ny, s.nz}, sq[3] = {s.qx, s.qy, s.qz};
+        grad3(dx, dy, dz, ri2, ri2 * ri2 * ri, sn, sq, tv, ax, ay, az);
+    } else if constexpr (KT == 5) {
+        const double sq[3] = {s.qx, s.qy, s.qz};
+        grad3(dx, dy, dz, ri2, ri2 * ri2 * ri, tv, tv2, sq, ax, ay, az);
+    } else if constexpr (KT == 4) {
+        const double ra = __builtin_fma(dx, tv[0], __builtin_fma(dy, tv[1], dz * tv[2]));
+        const double c = ra * rq * (ri2 * ri2 * ri);
+        ax = __builtin_fma(c, dx, ax);
+        ay = __builtin_fma(c, dy, ay);
+        az = __builtin_fma(c, dz, az);
     } else {
         const double rn = __builtin_fma(dx, s.nx, __builtin_fma(dy, s.ny, dz * s.nz));
         const double c = rn * rq * (ri2 * ri2 * ri);
@@ -297,11 +334,16 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
     const int64_t idx = t0 + (valid ? ti : 0);        // idle lanes mirror target t0
     const int64_t nt = a.in.n_trg;
     const double x = a.in.trg_xyz[idx], y = a.in.trg_xyz[nt + idx], z = a.in.trg_xyz[2 * nt + idx];
-    double tv[3] = {0.0, 0.0, 0.0};                   // kernel 2: the target's vector
-    if constexpr (KT == 2) {
+    double tv[3] = {0.0, 0.0, 0.0}, tv2[3] = {0.0, 0.0, 0.0};   // kernels 2 .. 5: the target's vectors
+    if constexpr (KT >= 2) {
         tv[0] = a.in.trg_vec[idx];
         tv[1] = a.in.trg_vec[nt + idx];
         tv[2] = a.in.trg_vec[2 * nt + idx];
+    }
+    if constexpr (KT == 5) {
+        tv2[0] = a.in.trg_vec2[idx];
+        tv2[1] = a.in.trg_vec2[nt + idx];
+        tv2[2] = a.in.trg_vec2[2 * nt + idx];
     }
     const int32_t tg = a.in.trg_group ? a.in.trg_group[idx] : 0;
     const bool excl = a.in.excl != 0;
@@ -436,10 +478,10 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
             if constexpr (MIXED == 0) {
                 const int32_t* gbk = s_grp + kb + h * m_back;
 #pragma unroll 4
-                for (int j = 0; j < m_clean; ++j) pair64<KT, false>(pc[j], x, y, z, tv, false, ax, ay, az);
+                for (int j = 0; j < m_clean; ++j) pair64<KT, false>(pc[j], x, y, z, tv, tv2, false, ax, ay, az);
 #pragma unroll 2
                 for (int j = 0; j < m_back; ++j)
-                    pair64<KT, true>(pb[j], x, y, z, tv, excl && gbk[j] == tg, ax, ay, az);
+                    pair64<KT, true>(pb[j], x, y, z, tv, tv2, excl && gbk[j] == tg, ax, ay, az);
             } else {
                 float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll 4
@@ -546,7 +588,8 @@ __global__ __launch_bounds__(kWave) void p2p_sum(P2PArgs a) {
 }
 
 size_t rec_size(int kernel, int mixed) {
-    if (kernel == 2) return sizeof(P2PRec<2, 0>::type);
+    if (kernel == 2 || kernel == 4 || kernel == 5) return sizeof(SrcSL64);
+    if (kernel == 3) return sizeof(SrcDL64);
     if (!mixed) return kernel == 0 ? sizeof(P2PRec<0, 0>::type) : sizeof(P2PRec<1, 0>::type);
     return kernel == 0 ? sizeof(P2PRec<0, 1>::type) : sizeof(P2PRec<1, 1>::type);
 }
@@ -661,6 +704,9 @@ hipError_t run_p2p_typed(const SumInputs& in, const P2PItems& it, double* out, i
 hipError_t run_p2p_any(const SumInputs& in, const P2PItems& it, double* out, int accumulate, void* ws,
                        hipStream_t stream, const KernelTimer& timer) {
     if (in.kernel == 2) return run_p2p_typed<2, 0>(in, it, out, accumulate, ws, stream, timer);
+    if (in.kernel == 3) return run_p2p_typed<3, 0>(in, it, out, accumulate, ws, stream, timer);
+    if (in.kernel == 4) return run_p2p_typed<4, 0>(in, it, out, accumulate, ws, stream, timer);
+    if (in.kernel == 5) return run_p2p_typed<5, 0>(in, it, out, accumulate, ws, stream, timer);
     if (in.kernel == 0)
         return in.mixed ? run_p2p_typed<0, 1>(in, it, out, accumulate, ws, stream, timer)
                         : run_p2p_typed<0, 0>(in, it, out, accumulate, ws, stream, timer);
@@ -948,13 +994,21 @@ hipError_t launch_p2p_transpose(int32_t n_leaves, const int64_t* ulist_ofs, cons
 }
 
 // ---------------------------------------------------------------------------
-// single-layer adjoint of the leaf-to-leaf sum (float64)
-//   dL/dx_n = c sum_m K(r_nm; g_n, q_m)          target side, the forward lists
-//   dL/df_m = c w_m sum_n S(r_nm) g_n            transposed lists (S even in r)
-//   dL/dy_m = c sum_n K(r_mn; q_m, g_n)          transposed lists (K odd in r,
+// adjoints of the leaf-to-leaf sums (float64), with r_nm = x_n - y_m,
+// q_m = w_m f_m (phi_m for the double layer), g_n = dL/du_n, c the forward's
+// prefactor and the sums over n running over the targets of the leaves whose
+// lists hold m's leaf (the transposed lists):
+// single layer
+//   dL/dx_n = c sum_m K(r_nm; g_n, q_m)          kernel 2, forward lists
+//   dL/df_m = c w_m sum_n S(r_nm) g_n            kernel 0, transposed (S even in r)
+//   dL/dy_m = c sum_n K(r_mn; q_m, g_n)          kernel 2, transposed (K odd in r,
 //                                                symmetric in its two vectors)
-// with r_nm = x_n - y_m, q_m = w_m f_m, g_n = dL/du_n, c the forward's prefactor;
-// the sums over n run over the targets of the leaves whose lists hold m's leaf.
+// double layer
+//   dL/dx_n   = c sum_m G(r_nm; n_m, q_m, g_n)   kernel 3, forward lists
+//   dL/dphi_m = c w_m sum_n r (r.n_m)(r.g_n)/rho^5 with r = r_nm
+//             = -c w_m sum_n r' (r'.n_m)(r'.g_n)/rho^5, r' = r_mn   kernel 4, transposed
+//   dL/dy_m   = -c sum_n G(r_nm; ...) = -c sum_n G(r_mn; n_m, q_m, g_n)   kernel 5,
+//               transposed (G even in r)
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -962,7 +1016,7 @@ struct P2PVjpLayout {
     size_t off_status, off_uot, off_ult, off_tws, off_q, off_tmp, off_p2p, total;
 };
 
-P2PVjpLayout p2p_vjp_layout(int64_t ns, int64_t nt, int32_t nl, int64_t nu) {
+P2PVjpLayout p2p_vjp_layout(int kernel, int64_t ns, int64_t nt, int32_t nl, int64_t nu) {
     P2PVjpLayout l{};
     size_t off = 0;
     auto take = [&](size_t& o, size_t bytes) {
@@ -975,8 +1029,9 @@ P2PVjpLayout p2p_vjp_layout(int64_t ns, int64_t nt, int32_t nl, int64_t nu) {
     take(l.off_tws, p2p_transpose_bytes(nu));
     take(l.off_q, (size_t)ns * 24);
     take(l.off_tmp, (size_t)ns * 24);
-    const size_t p = std::max({p2p_workspace_bytes(2, 0, ns, nt, nl), p2p_workspace_bytes(0, 0, nt, ns, nl),
-                               p2p_workspace_bytes(2, 0, nt, ns, nl)});
+    const int k_trg = kernel ? 3 : 2, k_f = kernel ? 4 : 0, k_src = kernel ? 5 : 2;
+    const size_t p = std::max({p2p_workspace_bytes(k_trg, 0, ns, nt, nl), p2p_workspace_bytes(k_f, 0, nt, ns, nl),
+                               p2p_workspace_bytes(k_src, 0, nt, ns, nl)});
     take(l.off_p2p, p);
     l.total = off;
     return l;
@@ -1002,17 +1057,18 @@ __global__ __launch_bounds__(kP2PThreads) void p2p_add_times_w(const double* __r
 
 }  // namespace
 
-size_t p2p_vjp_workspace_bytes(int64_t n_src, int64_t n_trg, int32_t n_leaves, int64_t n_ulist) {
+size_t p2p_vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, int32_t n_leaves, int64_t n_ulist) {
     if (n_src <= 0 || n_trg <= 0) return 0;
-    return p2p_vjp_layout(n_src, n_trg, n_leaves, n_ulist).total;
+    return p2p_vjp_layout(kernel, n_src, n_trg, n_leaves, n_ulist).total;
 }
 
-hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
-                             const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, const double* grad_vel,
-                             double* grad_density, double* grad_src, double* grad_trg, int accumulate, void* ws,
-                             hipStream_t st) {
+hipError_t launch_p2p_vjp(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                          const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, const double* grad_vel,
+                          double* grad_density, double* grad_src, double* grad_trg, int accumulate, void* ws,
+                          hipStream_t st) {
     const int64_t ns = in.n_src, nt = in.n_trg;
-    const P2PVjpLayout l = p2p_vjp_layout(ns, nt, n_leaves, n_ulist);
+    const bool dl = in.kernel != 0;
+    const P2PVjpLayout l = p2p_vjp_layout(in.kernel, ns, nt, n_leaves, n_ulist);
     char* base = static_cast<char*>(ws);
     int32_t* status = reinterpret_cast<int32_t*>(base + l.off_status);
     const KernelTimer none{};
@@ -1020,7 +1076,7 @@ hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_
     if (e != hipSuccess) return e;
     if (grad_trg) {
         SumInputs t = in;
-        t.kernel = 2;
+        t.kernel = dl ? 3 : 2;
         t.mixed = 0;
         t.trg_vec = grad_vel;
         t.pair_class = nullptr;
@@ -1035,7 +1091,8 @@ hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_
         hipSuccess)
         return e;
     // the transposed sums: the forward's sources are the targets, its targets
-    // (carrying g, unit weights) the sources; the pair rule's groups swap
+    // (carrying g, unit weights) the sources; the pair rule's groups swap; the
+    // double layer's sums are odd in r there, hence -c
     SumInputs tr{};
     tr.n_src = nt;
     tr.src_xyz = in.trg_xyz;
@@ -1046,11 +1103,12 @@ hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_
     tr.excl = in.excl;
     tr.src_group = in.trg_group;
     tr.trg_group = in.src_group;
-    tr.pref = in.pref;
+    tr.pref = dl ? -in.pref : in.pref;
     if (grad_density) {
         double* tmp = reinterpret_cast<double*>(base + l.off_tmp);
         SumInputs f = tr;
-        f.kernel = 0;
+        f.kernel = dl ? 4 : 0;
+        f.trg_vec = dl ? in.normal : nullptr;
         e = launch_p2p_csr(f, n_leaves, trg_ofs, src_ofs, uot, ult, n_ulist, tmp, 0, base + l.off_p2p, st, none, false,
                            status);
         if (e != hipSuccess) return e;
@@ -1062,8 +1120,9 @@ hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_
         p2p_times_w<<<p2p_grid(ns), kP2PThreads, 0, st>>>(in.weight, in.density, ns, q);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         SumInputs y = tr;
-        y.kernel = 2;
-        y.trg_vec = q;
+        y.kernel = dl ? 5 : 2;
+        y.trg_vec = dl ? in.normal : q;
+        y.trg_vec2 = dl ? q : nullptr;
         e = launch_p2p_csr(y, n_leaves, trg_ofs, src_ofs, uot, ult, n_ulist, grad_src, accumulate, base + l.off_p2p,
                            st, none, false, status);
     }

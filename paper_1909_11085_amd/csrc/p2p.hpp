@@ -43,14 +43,15 @@ hipError_t launch_p2p_check(int32_t n_leaves, const int64_t* src_ofs, const int6
 // outside the arrays is read).  Workspace p2p_transpose_bytes(n_ulist).
 size_t p2p_transpose_bytes(int64_t n_ulist);
 
-// Single-layer adjoint of the leaf-to-leaf sum (float64): each output may be
-// null; in holds the forward's inputs (kernel 0, pref, pair rule).  The
-// device leaf arrays are checked; malformed ones make the outputs NaN.
-size_t p2p_vjp_workspace_bytes(int64_t n_src, int64_t n_trg, int32_t n_leaves, int64_t n_ulist);
-hipError_t launch_p2p_sl_vjp(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
-                             const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, const double* grad_vel,
-                             double* grad_density, double* grad_src, double* grad_trg, int accumulate, void* ws,
-                             hipStream_t stream);
+// Adjoint of the leaf-to-leaf sum (float64) of in.kernel (0 single layer, 1
+// double layer): each output may be null; in holds the forward's inputs
+// (density, weight, normal, pref, pair rule).  The device leaf arrays are
+// checked; malformed ones make the outputs NaN.
+size_t p2p_vjp_workspace_bytes(int kernel, int64_t n_src, int64_t n_trg, int32_t n_leaves, int64_t n_ulist);
+hipError_t launch_p2p_vjp(const SumInputs& in, int32_t n_leaves, const int64_t* src_ofs, const int64_t* trg_ofs,
+                          const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist, const double* grad_vel,
+                          double* grad_density, double* grad_src, double* grad_trg, int accumulate, void* ws,
+                          hipStream_t stream);
 hipError_t launch_p2p_transpose(int32_t n_leaves, const int64_t* ulist_ofs, const int32_t* ulist, int64_t n_ulist,
                                 const int32_t* status, int64_t* ulist_ofs_t, int32_t* ulist_t, void* ws,
                                 hipStream_t stream);

@@ -1,4 +1,4 @@
-"""GPU parity of the single-layer leaf-to-leaf adjoint against the FP64 oracle.
+"""GPU parity of the leaf-to-leaf adjoints (single and double layer) against the FP64 oracle.
 
 The oracle's adjoint takes every target leaf's direct adjoint over the
 sources of its list and scatters the source-side parts back; the library runs
@@ -32,6 +32,7 @@ def _case(seed, n_cells=8, distinct=True, repeat=True):
     tree = W.build_octree(cells.pos, lo, side, max_leaf=48)
     p = tree.perm
     y, w, g = cells.pos[:, p].copy(), cells.weight[p].copy(), cells.group[p].copy()
+    nrm = cells.normal[:, p].copy()
     f = rng.standard_normal((3, cells.n))
     ofs, ul = W.nearest_leaf_lists(rng, tree, kmin=3, kmax=12)
     if repeat:
@@ -48,55 +49,64 @@ def _case(seed, n_cells=8, distinct=True, repeat=True):
     else:
         x, to, gt = y, so, g
     gu = rng.standard_normal((3, x.shape[1]))
-    return dict(y=y, f=f, w=w, gs=g, x=x, gt=gt, so=so, to=to, ofs=ofs.astype(np.int64), ul=ul.astype(np.int32),
-                gu=gu)
+    return dict(y=y, f=f, w=w, n=nrm, gs=g, x=x, gt=gt, so=so, to=to, ofs=ofs.astype(np.int64),
+                ul=ul.astype(np.int32), gu=gu)
 
 
 def _layout(d):
     return dev(d["so"]), dev(d["to"]), dev(d["ofs"]), dev(d["ul"])
 
 
-def _oracle(d, mu, excl):
-    return O.p2p_sl_vjp(d["y"], d["f"], d["w"], d["x"], d["gu"], d["so"], d["to"], d["ofs"], d["ul"], mu=mu,
-                        src_group=d["gs"], trg_group=d["gt"], exclude_same_group=excl)
+def _oracle(d, mu, excl, kernel="sl"):
+    kw = dict(src_group=d["gs"], trg_group=d["gt"], exclude_same_group=excl)
+    lay = (d["so"], d["to"], d["ofs"], d["ul"])
+    if kernel == "sl":
+        return O.p2p_sl_vjp(d["y"], d["f"], d["w"], d["x"], d["gu"], *lay, mu=mu, **kw)
+    return O.p2p_dl_vjp(d["y"], d["f"], d["w"], d["n"], d["x"], d["gu"], *lay, **kw)
 
 
-def _gpu(d, mu, excl, layout=None, want=("f", "src", "trg"), accumulate=False, outs=None):
+def _gpu(d, mu, excl, layout=None, want=("f", "src", "trg"), accumulate=False, outs=None, kernel="sl"):
     ns, nt = d["y"].shape[1], d["x"].shape[1]
     if outs is None:
         outs = [torch.zeros((3, n), dtype=torch.float64, device=device()) if k in want else None
                 for k, n in (("f", ns), ("src", ns), ("trg", nt))]
     y = dev(d["y"])
     x = y if d["x"] is d["y"] else dev(d["x"])
-    S.p2p_sl_vjp(layout if layout is not None else _layout(d), y, dev(d["f"]), dev(d["w"]), x, dev(d["gu"]),
-                 mu=mu, src_group=dev(d["gs"]), trg_group=dev(d["gt"]), exclude_same_group=excl,
-                 grad_f=outs[0], grad_src=outs[1], grad_trg=outs[2], accumulate=accumulate)
+    lay = layout if layout is not None else _layout(d)
+    kw = dict(src_group=dev(d["gs"]), trg_group=dev(d["gt"]), exclude_same_group=excl, grad_src=outs[1],
+              grad_trg=outs[2], accumulate=accumulate)
+    if kernel == "sl":
+        S.p2p_sl_vjp(lay, y, dev(d["f"]), dev(d["w"]), x, dev(d["gu"]), mu=mu, grad_f=outs[0], **kw)
+    else:
+        S.p2p_dl_vjp(lay, y, dev(d["f"]), dev(d["w"]), dev(d["n"]), x, dev(d["gu"]), grad_phi=outs[0], **kw)
     return outs
 
 
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
 @pytest.mark.parametrize("excl", [True, False])
 @pytest.mark.parametrize("distinct", [True, False])
-def test_p2p_sl_vjp_matches_oracle(excl, distinct):
-    print(f"case p2p sl vjp excl={excl} distinct={distinct}", flush=True)
+def test_p2p_vjp_matches_oracle(kernel, excl, distinct):
+    print(f"case p2p {kernel} vjp excl={excl} distinct={distinct}", flush=True)
     d = _case(51 + 2 * int(excl) + int(distinct), distinct=distinct)
-    got = _gpu(d, 1.3, excl)
-    ref = _oracle(d, 1.3, excl)
-    for name, a, b in zip(("grad_f", "grad_src", "grad_trg"), got, ref):
-        assert_close(host(a), b, FP64_TOL, f"p2p sl vjp {name} excl={excl} distinct={distinct}")
+    got = _gpu(d, 1.3, excl, kernel=kernel)
+    ref = _oracle(d, 1.3, excl, kernel=kernel)
+    for name, a, b in zip(("grad_density", "grad_src", "grad_trg"), got, ref):
+        assert_close(host(a), b, FP64_TOL, f"p2p {kernel} vjp {name} excl={excl} distinct={distinct}")
 
 
-def test_p2p_sl_vjp_each_output_alone_and_accumulate():
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_p2p_vjp_each_output_alone_and_accumulate(kernel):
     """Each output asked for alone equals its value in the full call, bit for
     bit; accumulate adds onto what the outputs hold."""
-    print("case p2p sl vjp single outputs", flush=True)
+    print(f"case p2p {kernel} vjp single outputs", flush=True)
     d = _case(57)
-    full = [host(t) for t in _gpu(d, 0.9, True)]
+    full = [host(t) for t in _gpu(d, 0.9, True, kernel=kernel)]
     for k, name in enumerate(("f", "src", "trg")):
-        alone = _gpu(d, 0.9, True, want=(name,))
+        alone = _gpu(d, 0.9, True, want=(name,), kernel=kernel)
         assert np.array_equal(host(alone[k]), full[k]), name
         assert all(alone[j] is None for j in range(3) if j != k)
     base = [np.full(a.shape, 0.25) for a in full]
-    acc = _gpu(d, 0.9, True, accumulate=True, outs=[dev(b.copy()) for b in base])
+    acc = _gpu(d, 0.9, True, accumulate=True, outs=[dev(b.copy()) for b in base], kernel=kernel)
     for a, b, ref in zip(acc, base, full):
         assert np.allclose(host(a) - b, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
 
@@ -114,44 +124,55 @@ def test_p2p_sl_vjp_deterministic_and_plan_layout():
         assert np.array_equal(u, v) and np.array_equal(u, z)
 
 
-def test_p2p_sl_vjp_uneven_layout():
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_p2p_vjp_uneven_layout(kernel):
     """Empty leaves, leaves with sources but no targets, a repeated entry,
     sources listed by no leaf (zero source-side gradient)."""
-    print("case p2p sl vjp uneven layout", flush=True)
+    print(f"case p2p {kernel} vjp uneven layout", flush=True)
     rng = np.random.default_rng(59)
     ns, nt = 300, 200
+    nrm = rng.standard_normal((3, ns))
     d = dict(y=rng.standard_normal((3, ns)) * 3, x=rng.standard_normal((3, nt)) * 3, f=rng.standard_normal((3, ns)),
+             n=nrm / np.linalg.norm(nrm, axis=0),
              w=rng.uniform(0.5, 1, ns), gs=rng.integers(0, 5, ns).astype(np.int32),
              gt=rng.integers(0, 5, nt).astype(np.int32), gu=rng.standard_normal((3, nt)),
              so=np.array([0, 0, 100, 100, 250, 300], dtype=np.int64),
              to=np.array([0, 50, 50, 120, 200, 200], dtype=np.int64),
              ofs=np.array([0, 3, 3, 5, 9, 10], dtype=np.int64),
              ul=np.array([1, 1, 4, 1, 1, 0, 1, 1, 4, 2], dtype=np.int32))   # leaf 3 (sources 100..250) unlisted
-    got = _gpu(d, 1.1, True)
-    ref = _oracle(d, 1.1, True)
-    for name, a, b in zip(("grad_f", "grad_src", "grad_trg"), got, ref):
-        assert_close(host(a), b, FP64_TOL, f"uneven {name}")
+    got = _gpu(d, 1.1, True, kernel=kernel)
+    ref = _oracle(d, 1.1, True, kernel=kernel)
+    for name, a, b in zip(("grad_density", "grad_src", "grad_trg"), got, ref):
+        assert_close(host(a), b, FP64_TOL, f"uneven {kernel} {name}")
     assert np.all(host(got[0])[:, 100:250] == 0.0) and np.all(host(got[1])[:, 100:250] == 0.0)
 
 
-def test_p2p_sl_vjp_malformed_gives_nan():
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_p2p_vjp_malformed_gives_nan(kernel):
     """The leaf arrays are checked on the device as for the forward sum: a
     breach makes every requested output NaN, also when accumulating."""
-    print("case p2p sl vjp malformed", flush=True)
+    print(f"case p2p {kernel} vjp malformed", flush=True)
     rng = np.random.default_rng(60)
     y, x = dev(rng.standard_normal((3, 10))), dev(rng.standard_normal((3, 8)))
     f, w, gu = dev(rng.standard_normal((3, 10))), dev(rng.uniform(0.5, 1, 10)), dev(rng.standard_normal((3, 8)))
+    nv = dev(rng.standard_normal((3, 10)))
+
+    def vjp(lay, o, **kw):
+        if kernel == "sl":
+            return S.p2p_sl_vjp(lay, y, f, w, x, gu, grad_f=o[0], grad_src=o[1], grad_trg=o[2], **kw)
+        return S.p2p_dl_vjp(lay, y, f, w, nv, x, gu, grad_phi=o[0], grad_src=o[1], grad_trg=o[2], **kw)
+
     ok = dict(so=np.array([0, 5, 10]), to=np.array([0, 4, 8]), uo=np.array([0, 1, 2]), ul=np.array([0, 1]))
     bad = [dict(ok, so=np.array([1, 5, 10])), dict(ok, to=np.array([0, 6, 4])), dict(ok, uo=np.array([0, 1, 3])),
            dict(ok, ul=np.array([0, 2])), dict(ok, ul=np.array([-1, 1]))]
     lay = lambda b: (dev(b["so"].astype(np.int64)), dev(b["to"].astype(np.int64)), dev(b["uo"].astype(np.int64)),
                      dev(b["ul"].astype(np.int32)))
     outs = lambda: [dev(np.zeros((3, 10))), dev(np.zeros((3, 10))), dev(np.zeros((3, 8)))]
-    good = S.p2p_sl_vjp(lay(ok), y, f, w, x, gu, grad_f=outs()[0], grad_src=outs()[1], grad_trg=outs()[2])
+    good = vjp(lay(ok), outs())
     assert all(np.all(np.isfinite(host(t))) for t in good)
     for b in bad:
         o = outs()
-        S.p2p_sl_vjp(lay(b), y, f, w, x, gu, grad_f=o[0], grad_src=o[1], grad_trg=o[2], accumulate=True)
+        vjp(lay(b), o, accumulate=True)
         assert all(np.all(np.isnan(host(t))) for t in o), b
 
 
@@ -194,19 +215,21 @@ def test_p2p_sl_vjp_rejects_bad_arguments():
     assert np.all(host(gt) == 0.0)
 
 
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
 @pytest.mark.parametrize("shared", [False, True])
-def test_p2p_diff_autograd(shared):
+def test_p2p_diff_autograd(kernel, shared):
     """torch.autograd through p2p_diff gives the oracle's adjoint; on a shared
     point set the position gradient is the sum of both sides."""
-    print(f"case p2p diff autograd shared={shared}", flush=True)
+    print(f"case p2p diff autograd {kernel} shared={shared}", flush=True)
     d = _case(62 + int(shared), n_cells=5, distinct=not shared)
     lay = _layout(d)
     y = dev(d["y"]).requires_grad_(True)
     f = dev(d["f"]).requires_grad_(True)
     x = y if shared else dev(d["x"]).requires_grad_(True)
-    u = S.p2p_diff(lay, y, f, dev(d["w"]), x, mu=0.7, src_group=dev(d["gs"]), trg_group=dev(d["gt"]))
+    u = S.p2p_diff(lay, y, f, dev(d["w"]), x, kernel=kernel, nrm=dev(d["n"]), mu=0.7, src_group=dev(d["gs"]),
+                   trg_group=dev(d["gt"]))
     u.backward(dev(d["gu"]))
-    gf, gy, gx = _oracle(d, 0.7, True)
+    gf, gy, gx = _oracle(d, 0.7, True, kernel=kernel)
     assert_close(host(f.grad), gf, FP64_TOL, "autograd grad_f")
     if shared:
         assert_close(host(y.grad), gy + gx, FP64_TOL, "autograd shared position gradient")
@@ -215,18 +238,24 @@ def test_p2p_diff_autograd(shared):
         assert_close(host(x.grad), gx, FP64_TOL, "autograd grad_trg")
 
 
-def test_p2p_sl_vjp_graph_capture():
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_p2p_vjp_graph_capture(kernel):
     """No host round trip and no memset: captured once, replayed three times
     with eager work between, each replay bitwise equal to the eager result."""
-    print("case p2p sl vjp graph capture", flush=True)
+    print(f"case p2p {kernel} vjp graph capture", flush=True)
     d = _case(64)
     lay = _layout(d)
-    y, x, f, w, gu = dev(d["y"]), dev(d["x"]), dev(d["f"]), dev(d["w"]), dev(d["gu"])
+    y, x, f, w, gu, nv = dev(d["y"]), dev(d["x"]), dev(d["f"]), dev(d["w"]), dev(d["gu"]), dev(d["n"])
     gs, gt = dev(d["gs"]), dev(d["gt"])
     outs = [torch.empty_like(y), torch.empty_like(y), torch.empty_like(x)]
 
     def run(o):
-        S.p2p_sl_vjp(lay, y, f, w, x, gu, src_group=gs, trg_group=gt, grad_f=o[0], grad_src=o[1], grad_trg=o[2])
+        if kernel == "sl":
+            S.p2p_sl_vjp(lay, y, f, w, x, gu, src_group=gs, trg_group=gt, grad_f=o[0], grad_src=o[1],
+                         grad_trg=o[2])
+        else:
+            S.p2p_dl_vjp(lay, y, f, w, nv, x, gu, src_group=gs, trg_group=gt, grad_phi=o[0], grad_src=o[1],
+                         grad_trg=o[2])
 
     eager = [torch.empty_like(t) for t in outs]
     run(eager)

@@ -11,9 +11,9 @@ Each pin targets a plausible mistake:
   * P2P with full lists == direct          -> leaf indexing
   * central differences, dot tests, zero divergence, translation invariance of
     the loss                               -> the vector-Jacobian products
-  * P2P adjoint with full lists == direct adjoint, central differences of the
-    P2P sum (repeated list entries, distinct targets) -> the adjoint's
-    scatter over the lists
+  * P2P adjoints (single and double layer) with full lists == direct
+    adjoints, central differences of the P2P sums (repeated list entries,
+    distinct targets)                      -> the adjoints' scatter over the lists
 """
 import math
 import os
@@ -491,5 +491,47 @@ def test_p2p_sl_vjp_central_differences():
             am[i, j] -= h
             args_p = {"f": (y, ap, x), "src": (ap, f, x), "trg": (y, f, ap)}[name]
             args_m = {"f": (y, am, x), "src": (am, f, x), "trg": (y, f, am)}[name]
+            fd = _loss_delta(fwd(*args_p), fwd(*args_m), u_ref) / (2 * h)
+            assert abs(fd - grad[i, j]) <= 1e-6 * (abs(grad[i, j]) + 1e-3 * np.abs(grad).max()), name
+
+
+def test_p2p_dl_vjp_full_lists_equal_direct():
+    rng, tree, pos, f, w, g, nrm = _small_tree(seed=25)
+    nl = len(tree.leaf_ofs) - 1
+    uofs = np.arange(nl + 1, dtype=np.int64) * nl
+    ul = np.tile(np.arange(nl, dtype=np.int32), nl)
+    gu = rng.standard_normal(pos.shape)
+    kw = dict(src_group=g, trg_group=g, exclude_same_group=True)
+    a = O.p2p_dl_vjp(pos, f, w, nrm, pos, gu, tree.leaf_ofs, tree.leaf_ofs, uofs, ul, **kw)
+    b = O.dl_vjp(pos, f, w, nrm, pos, gu, **kw)
+    for got, ref in zip(a, b):
+        assert rel(got, ref) < 1e-13
+
+
+def test_p2p_dl_vjp_central_differences():
+    rng, tree, y, f, w, gs, x, gt, to, ofs, ul, dup = _p2p_distinct_targets(26)
+    nrm = rng.standard_normal(y.shape)
+    nrm /= np.linalg.norm(nrm, axis=0)
+    so = tree.leaf_ofs
+    kw = dict(src_group=gs, trg_group=gt, exclude_same_group=True)
+    u_ref = rng.standard_normal((3, x.shape[1]))
+
+    def fwd(yy, ff, xx):
+        return O.p2p(1, yy, ff, w, xx, so, to, ofs, ul, nrm=nrm, **kw)
+
+    u = fwd(y, f, x)
+    gp, gy, gx = O.p2p_dl_vjp(y, f, w, nrm, x, u - u_ref, so, to, ofs, ul, **kw)
+    h = 1e-6
+    for arr, grad, name in ((f, gp, "phi"), (y, gy, "src"), (x, gx, "trg")):
+        idx = rng.choice(arr.shape[1], 8, replace=False)
+        if name != "trg":
+            idx = np.concatenate([idx, rng.choice(dup, min(4, dup.size), replace=False)])
+        for j in idx:
+            i = int(rng.integers(0, 3))
+            ap, am = arr.copy(), arr.copy()
+            ap[i, j] += h
+            am[i, j] -= h
+            args_p = {"phi": (y, ap, x), "src": (ap, f, x), "trg": (y, f, ap)}[name]
+            args_m = {"phi": (y, am, x), "src": (am, f, x), "trg": (y, f, am)}[name]
             fd = _loss_delta(fwd(*args_p), fwd(*args_m), u_ref) / (2 * h)
             assert abs(fd - grad[i, j]) <= 1e-6 * (abs(grad[i, j]) + 1e-3 * np.abs(grad).max()), name
