@@ -1384,8 +1384,14 @@ int stokes_fmm_plan_create(stokes_ctx* ctx, int32_t order, stokes_fmm_plan** pla
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(STOKES_EDEVICE, "cannot select the context's device");
     std::string err;
-    if (stokes::fmm_plan_build(ctx->device, order, plan, err) != 0)
-        return fail(STOKES_EDEVICE, "stokes_fmm_plan_create: " + err);
+    int rc;
+    try {
+        rc = stokes::fmm_plan_build(ctx->device, order, plan, err);
+    } catch (const std::exception& ex) {           // host allocation of the operators
+        rc = -1;
+        err = ex.what();
+    }
+    if (rc != 0) return fail(STOKES_EDEVICE, "stokes_fmm_plan_create: " + err);
     return STOKES_OK;
 }
 

@@ -1229,11 +1229,12 @@ struct RoundBarrier {
             while (gen_.load(std::memory_order_acquire) == g) std::this_thread::yield();
         }
     }
-    const int n_;
+    int n_;                                    // set before any participant arrives
     std::atomic<int> count_{0}, gen_{0};
 };
 
-// f(lo, hi) over [0, n) cut into nth contiguous ranges, one thread each.
+// f(lo, hi) over [0, n) cut into nth contiguous ranges, one thread each; a
+// range whose thread cannot be started runs on the calling thread.
 template <typename F>
 void parallel_ranges(int64_t n, int nth, F&& f) {
     if (nth <= 1 || n < 2 * nth) {
@@ -1241,8 +1242,16 @@ void parallel_ranges(int64_t n, int nth, F&& f) {
         return;
     }
     std::vector<std::thread> pool;
-    for (int t = 1; t < nth; ++t) pool.emplace_back([&, t] { f(n * t / nth, n * (t + 1) / nth); });
+    std::vector<int> here;
+    for (int t = 1; t < nth; ++t) {
+        try {
+            pool.emplace_back([&, t] { f(n * t / nth, n * (t + 1) / nth); });
+        } catch (...) {
+            here.push_back(t);
+        }
+    }
     f((int64_t)0, n / nth);
+    for (int t : here) f(n * t / nth, n * (t + 1) / nth);
     for (auto& th : pool) th.join();
 }
 }  // namespace
@@ -1297,7 +1306,7 @@ void pinv_jacobi(const std::vector<double>& K, int n, double rcond, std::vector<
     // the pairs of a round are positions (k, m - 1 - k)
     auto column = [m](int k, int r) { return k == 0 ? 0 : 1 + (k - 1 + r) % (m - 1); };
     const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, 16, (int64_t)(m / 2) / 16}));
+    int nth = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, 16, (int64_t)(m / 2) / 16}));
     std::vector<double> worst_t(nth);
     for (int sweep = 0; sweep < 40 && m >= 2; ++sweep) {
         std::fill(worst_t.begin(), worst_t.end(), 0.0);
@@ -1308,7 +1317,12 @@ void pinv_jacobi(const std::vector<double>& K, int n, double rcond, std::vector<
             smax2 = std::max(smax2, c);
         }
         RoundBarrier bar(nth);
+        // the threads wait for `go`, given once the participant count is
+        // final (a thread that cannot be started lowers it for this sweep)
+        std::atomic<int> go{0};
+        const int nth_max = nth;
         auto work = [&](int tid) {
+            while (go.load(std::memory_order_acquire) == 0) std::this_thread::yield();
             double worst = 0.0;
             for (int r = 0; r < m - 1; ++r) {
                 for (int k = tid; k < m / 2; k += nth) {
@@ -1321,14 +1335,20 @@ void pinv_jacobi(const std::vector<double>& K, int n, double rcond, std::vector<
             }
             worst_t[tid] = worst;
         };
-        if (nth == 1) {
-            work(0);
-        } else {
-            std::vector<std::thread> pool;
-            for (int t = 1; t < nth; ++t) pool.emplace_back(work, t);
-            work(0);
-            for (auto& th : pool) th.join();
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nth_max; ++t) {
+            try {
+                pool.emplace_back(work, t);
+            } catch (...) {
+                break;
+            }
         }
+        nth = (int)pool.size() + 1;
+        bar.n_ = nth;
+        go.store(1, std::memory_order_release);
+        work(0);
+        for (auto& th : pool) th.join();
+        nth = nth_max;
         if (*std::max_element(worst_t.begin(), worst_t.end()) <= 1e-14) break;
     }
     // Columns near the cutoff carry rounding noise of relative size eps
@@ -1605,10 +1625,13 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         const int64_t tiles_ub =
             (std::min<int64_t>((int64_t)1 << (3 * l), std::max(in.n_src, in.n_trg)) + kGemmNT - 1) / kGemmNT;
         const dim3 g((unsigned)(ngr * std::max<int64_t>(tiles_ub, kApplyUnits)));
-        with_rb(rb, [&](auto r) {
-            hipLaunchKernelGGL(apply_gemm_kernel<decltype(r)::value>, g, dim3(kGemmThreads), 0, st, a, g2, op, out,
-                               apart);
-        });
+        if (!with_rb(rb, [&](auto r) {
+                hipLaunchKernelGGL(apply_gemm_kernel<decltype(r)::value>, g, dim3(kGemmThreads), 0, st, a, g2, op,
+                                   out, apart);
+            })) {
+            e = hipErrorInvalidValue;                   // no GEMM instance for this order (not reached for 2..10)
+            return false;
+        }
         if (!chk()) return false;
         // a strided pass: most levels have one split, and then every workgroup just exits
         hipLaunchKernelGGL(apply_reduce_kernel, dim3(kApplyReduceGrid), dim3(kFBlock), 0, st, a, g2,
@@ -1672,9 +1695,12 @@ hipError_t launch_fmm(const stokes_fmm_plan* plan, const FmmInputs& in, double* 
         const int64_t tiles = (std::min<int64_t>(nb >> 3, in.n_trg) + kGemmNT - 1) / kGemmNT;
         // row groups outermost: grid = 8 classes x row groups x units
         const dim3 gm((unsigned)(8 * ngr * std::max<int64_t>(kM2LUnits + tiles, kM2LMinSplits * tiles)));
-        with_rb(rb, [&](auto r) {
-            hipLaunchKernelGGL(m2l_gemm_kernel<decltype(r)::value>, gm, dim3(kGemmThreads), 0, st, a, g2, l);
-        });
+        if (!with_rb(rb, [&](auto r) {
+                hipLaunchKernelGGL(m2l_gemm_kernel<decltype(r)::value>, gm, dim3(kGemmThreads), 0, st, a, g2, l);
+            })) {
+            e = hipErrorInvalidValue;                   // no GEMM instance for this order (not reached for 2..10)
+            break;
+        }
         if (!chk()) break;
         hipLaunchKernelGGL(m2l_reduce_kernel, dim3(f_grid((std::min<int64_t>(nb, in.n_trg) * plan->mp + kFBlock - 1) / kFBlock)),
                            dim3(kFBlock), 0, st, g2);
