@@ -718,8 +718,16 @@ hipError_t run_p2p_any(const SumInputs& in, const P2PItems& it, double* out, int
 // work items from device leaf arrays
 // ---------------------------------------------------------------------------
 constexpr int kP2PThreads = 256;
-constexpr int kItemKeyBits = 40;
+constexpr int kItemKeyBits = 16;
 constexpr uint64_t kItemKeyTop = (1ull << kItemKeyBits) - 1;
+
+// A cost on a log scale in 16 bits (a float32's exponent and top 10 mantissa
+// bits): non-decreasing in the cost, steps of 2^-10 of it, so two radix passes
+// order the items.
+__device__ __forceinline__ uint64_t cost_code(uint64_t cost) {
+    const uint32_t b = __float_as_uint((float)cost);   // cost >= 1: exponent field >= 127
+    return (uint64_t)((b >> 13) - (127u << 10));
+}
 
 __global__ __launch_bounds__(kP2PThreads) void p2p_set_i32(int32_t* p, int32_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
@@ -787,8 +795,10 @@ __global__ __launch_bounds__(kP2PThreads) void p2p_item_slots(int64_t max_items,
 
 // The items of each leaf, in leaf and chunk order, with their cost keys: the
 // pair loop of an n-target item runs s/R steps over the s listed sources,
-// R = min(16, 64/n); the key is inverted so that an ascending stable sort puts
-// the largest first (the order of the host-built plan).
+// R = min(16, 64/n); the key is the inverted log-scale code of that cost, so
+// that an ascending stable sort puts the largest first (the host-built plan's
+// order up to costs within 2^-10 of each other, which keep leaf order).  The
+// order only schedules the items: each target's sum is one item's.
 __global__ __launch_bounds__(kP2PThreads) void p2p_csr_items(const int64_t* __restrict__ to,
                                                              const int64_t* __restrict__ cofs,
                                                              const int64_t* __restrict__ listed, int32_t nl,
@@ -804,7 +814,7 @@ __global__ __launch_bounds__(kP2PThreads) void p2p_csr_items(const int64_t* __re
             const uint64_t cost = (uint64_t)(s * 64 / rep + s + 1);
             items[2 * k] = (int32_t)L;
             items[2 * k + 1] = (int32_t)c;
-            keys[k] = kItemKeyTop - 1 - std::min<uint64_t>(cost, kItemKeyTop - 1);
+            keys[k] = kItemKeyTop - 1 - std::min<uint64_t>(cost_code(cost), kItemKeyTop - 1);
         }
     }
 }
