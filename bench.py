@@ -71,10 +71,13 @@ FLOPS_PER_PAIR_DL = 30
 KERNEL_NAMES = {"fp64": "sym_main<FwdSL,T=6> (each pair once)", "mixed": "direct_mixed<SL,T=2>",
                 "fp64_one_sided": "direct_f64<SL,T=4>"}
 PROFILE_TRAFFIC = {"fp64": "sym_main_f64_sl_cfg2_traffic.txt", "mixed": "direct_mixed_sl_cfg2_traffic.txt",
-                   "fp64_one_sided": "direct_f64_sl_cfg2_traffic.txt"}
+                   "fp64_one_sided": "direct_f64_sl_cfg2_traffic.txt",
+                   "p2p_fp64": "p2p_sum_f64_sl_cfg4_traffic.txt", "p2p_mixed": "p2p_sum_mixed_sl_cfg4_traffic.txt"}
 PROFILE_SOURCES = {"fp64": ("sym.hip", "direct_dev.hpp", "common.hpp"),
                    "mixed": ("direct.hip", "direct_dev.hpp", "common.hpp"),
-                   "fp64_one_sided": ("direct.hip", "direct_dev.hpp", "common.hpp")}
+                   "fp64_one_sided": ("direct.hip", "direct_dev.hpp", "common.hpp"),
+                   "p2p_fp64": ("p2p.hip", "p2p.hpp", "common.hpp"),
+                   "p2p_mixed": ("p2p.hip", "p2p.hpp", "common.hpp")}
 
 
 def path_key(prec, one_sided):
@@ -467,7 +470,7 @@ def bench_cfg4(S, W, t, timed, steps, oracle, one_sided=False):
         r[prec] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "plan_ms_per_step": ms_plan,
                    "roofline": dict(_roofline(prec, pairs * FLOPS_PER_PAIR_SL, km,
                                               "p2p_sum<SL,%s>" % ("FP64" if prec == "fp64" else "mixed")),
-                                    flops_per_pair=FLOPS_PER_PAIR_SL)}
+                                    flops_per_pair=FLOPS_PER_PAIR_SL, traffic=traffic_from_profile("p2p_" + prec))}
     r["mixed_speedup_vs_fp64"] = r["fp64"]["ms_per_step"] / r["mixed"]["ms_per_step"]
     if oracle:
         from oracle import oracle as O
