@@ -278,3 +278,49 @@ def test_p2p_vjp_graph_capture(kernel):
             assert np.array_equal(host(a), b), k
         run([torch.empty_like(t) for t in outs])
         torch.cuda.synchronize()
+
+
+def test_cfg4_sl_adjoint_sampled():
+    """The 3,840-cell leaf layout at full size (2,088,960 points, 30,163
+    leaves, the benchmark's lists of 27..60 leaves, same-cell rule), the
+    single-layer adjoint in the benchmark's launch: dL/dtrg of 12 seeded
+    target leaves against the oracle's adjoint over their lists, and dL/df and
+    dL/dsrc of 12 seeded source leaves against the oracle's adjoint over every
+    target of the leaves that list them (with multiplicity)."""
+    cfg = W.make_config(4)
+    c, tree, f = cfg["cells"], cfg["tree"], cfg["f"]
+    so = tree.leaf_ofs.astype(np.int64)
+    uo, ul = cfg["ulist_ofs"].astype(np.int64), cfg["ulist"].astype(np.int32)
+    nl = len(so) - 1
+    gu = np.random.default_rng(4404).standard_normal((3, c.n))
+    P = dev(c.pos)
+    G = dev(c.group)
+    outs = [torch.zeros((3, c.n), dtype=torch.float64, device=device()) for _ in range(3)]
+    S.p2p_sl_vjp((dev(so), dev(so), dev(uo), dev(ul)), P, dev(f), dev(c.weight), P, dev(gu), mu=1.0,
+                 src_group=G, trg_group=G, exclude_same_group=True, grad_f=outs[0], grad_src=outs[1],
+                 grad_trg=outs[2])
+    gf, gy, gx = (host(o) for o in outs)
+    rng = np.random.default_rng(4405)
+    pts = lambda L: np.arange(so[L], so[L + 1])
+    got, ref = [], []
+    for L in rng.choice(nl, 12, replace=False):
+        t = pts(L)
+        s = np.concatenate([pts(k) for k in ul[uo[L]:uo[L + 1]]])
+        _, _, rt = O.sl_vjp(c.pos[:, s], f[:, s], c.weight[s], c.pos[:, t], gu[:, t], src_group=c.group[s],
+                            trg_group=c.group[t], exclude_same_group=True, want=("trg",))
+        got.append(gx[:, t])
+        ref.append(rt)
+    assert_close(np.concatenate(got, 1), np.concatenate(ref, 1), FP64_TOL, "cfg4 dL/dtrg")
+    owner = np.searchsorted(uo, np.arange(len(ul)), side="right") - 1      # the leaf whose list holds entry k
+    got_f, got_y, ref_f, ref_y = [], [], [], []
+    for L in rng.choice(nl, 12, replace=False):
+        s = pts(L)
+        t = np.concatenate([pts(o) for o in owner[ul == L]])
+        rf, ry, _ = O.sl_vjp(c.pos[:, s], f[:, s], c.weight[s], c.pos[:, t], gu[:, t], src_group=c.group[s],
+                             trg_group=c.group[t], exclude_same_group=True, want=("f", "src"))
+        got_f.append(gf[:, s])
+        got_y.append(gy[:, s])
+        ref_f.append(rf)
+        ref_y.append(ry)
+    assert_close(np.concatenate(got_f, 1), np.concatenate(ref_f, 1), FP64_TOL, "cfg4 dL/df")
+    assert_close(np.concatenate(got_y, 1), np.concatenate(ref_y, 1), FP64_TOL, "cfg4 dL/dsrc")
