@@ -280,47 +280,57 @@ def test_p2p_vjp_graph_capture(kernel):
         torch.cuda.synchronize()
 
 
-def test_cfg4_sl_adjoint_sampled():
+
+@pytest.mark.parametrize("kernel", ["sl", "dl"])
+def test_cfg4_adjoint_sampled(kernel):
     """The 3,840-cell leaf layout at full size (2,088,960 points, 30,163
-    leaves, the benchmark's lists of 27..60 leaves, same-cell rule), the
-    single-layer adjoint in the benchmark's launch: dL/dtrg of 12 seeded
-    target leaves against the oracle's adjoint over their lists, and dL/df and
-    dL/dsrc of 12 seeded source leaves against the oracle's adjoint over every
-    target of the leaves that list them (with multiplicity)."""
+    leaves, the benchmark's lists of 27..60 leaves, same-cell rule; the double
+    layer takes the cells' normals), the adjoint in the benchmark's launch:
+    dL/dtrg of 12 seeded target leaves against the oracle's adjoint over their
+    lists, and the density and source-position gradients of 12 seeded source
+    leaves against the oracle's adjoint over every target of the leaves that
+    list them (with multiplicity)."""
     cfg = W.make_config(4)
     c, tree, f = cfg["cells"], cfg["tree"], cfg["f"]
     so = tree.leaf_ofs.astype(np.int64)
     uo, ul = cfg["ulist_ofs"].astype(np.int64), cfg["ulist"].astype(np.int32)
     nl = len(so) - 1
     gu = np.random.default_rng(4404).standard_normal((3, c.n))
-    P = dev(c.pos)
-    G = dev(c.group)
+    P, G = dev(c.pos), dev(c.group)
     outs = [torch.zeros((3, c.n), dtype=torch.float64, device=device()) for _ in range(3)]
-    S.p2p_sl_vjp((dev(so), dev(so), dev(uo), dev(ul)), P, dev(f), dev(c.weight), P, dev(gu), mu=1.0,
-                 src_group=G, trg_group=G, exclude_same_group=True, grad_f=outs[0], grad_src=outs[1],
-                 grad_trg=outs[2])
-    gf, gy, gx = (host(o) for o in outs)
+    lay = (dev(so), dev(so), dev(uo), dev(ul))
+    kw = dict(src_group=G, trg_group=G, exclude_same_group=True, grad_src=outs[1], grad_trg=outs[2])
+    if kernel == "sl":
+        S.p2p_sl_vjp(lay, P, dev(f), dev(c.weight), P, dev(gu), mu=1.0, grad_f=outs[0], **kw)
+    else:
+        S.p2p_dl_vjp(lay, P, dev(f), dev(c.weight), dev(c.normal), P, dev(gu), grad_phi=outs[0], **kw)
+    gd, gy, gx = (host(o) for o in outs)
+
+    def ref(s, t, want):
+        a = (c.pos[:, s], f[:, s], c.weight[s])
+        kw = dict(src_group=c.group[s], trg_group=c.group[t], exclude_same_group=True, want=want)
+        if kernel == "sl":
+            return O.sl_vjp(*a, c.pos[:, t], gu[:, t], **kw)
+        return O.dl_vjp(*a, c.normal[:, s], c.pos[:, t], gu[:, t], **kw)
+
     rng = np.random.default_rng(4405)
     pts = lambda L: np.arange(so[L], so[L + 1])
-    got, ref = [], []
+    got, exp = [], []
     for L in rng.choice(nl, 12, replace=False):
         t = pts(L)
         s = np.concatenate([pts(k) for k in ul[uo[L]:uo[L + 1]]])
-        _, _, rt = O.sl_vjp(c.pos[:, s], f[:, s], c.weight[s], c.pos[:, t], gu[:, t], src_group=c.group[s],
-                            trg_group=c.group[t], exclude_same_group=True, want=("trg",))
         got.append(gx[:, t])
-        ref.append(rt)
-    assert_close(np.concatenate(got, 1), np.concatenate(ref, 1), FP64_TOL, "cfg4 dL/dtrg")
+        exp.append(ref(s, t, ("trg",))[2])
+    assert_close(np.concatenate(got, 1), np.concatenate(exp, 1), FP64_TOL, f"cfg4 {kernel} dL/dtrg")
     owner = np.searchsorted(uo, np.arange(len(ul)), side="right") - 1      # the leaf whose list holds entry k
-    got_f, got_y, ref_f, ref_y = [], [], [], []
+    got_d, got_y, exp_d, exp_y = [], [], [], []
     for L in rng.choice(nl, 12, replace=False):
         s = pts(L)
         t = np.concatenate([pts(o) for o in owner[ul == L]])
-        rf, ry, _ = O.sl_vjp(c.pos[:, s], f[:, s], c.weight[s], c.pos[:, t], gu[:, t], src_group=c.group[s],
-                             trg_group=c.group[t], exclude_same_group=True, want=("f", "src"))
-        got_f.append(gf[:, s])
+        rd, ry, _ = ref(s, t, ("f", "src") if kernel == "sl" else ("phi", "src"))
+        got_d.append(gd[:, s])
         got_y.append(gy[:, s])
-        ref_f.append(rf)
-        ref_y.append(ry)
-    assert_close(np.concatenate(got_f, 1), np.concatenate(ref_f, 1), FP64_TOL, "cfg4 dL/df")
-    assert_close(np.concatenate(got_y, 1), np.concatenate(ref_y, 1), FP64_TOL, "cfg4 dL/dsrc")
+        exp_d.append(rd)
+        exp_y.append(ry)
+    assert_close(np.concatenate(got_d, 1), np.concatenate(exp_d, 1), FP64_TOL, f"cfg4 {kernel} density gradient")
+    assert_close(np.concatenate(got_y, 1), np.concatenate(exp_y, 1), FP64_TOL, f"cfg4 {kernel} dL/dsrc")
